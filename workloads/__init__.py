@@ -1,0 +1,388 @@
+"""Seeded synthetic inputs for the DD-DLRA step.
+
+This module builds problem descriptions: grid, subdomain layout, direction
+set, material fields, source and the initial low-rank factors of every
+subdomain.  It is shared by the HIP path's tests/bench and by the CPU oracle,
+and it holds none of the method's arithmetic: nothing here augments,
+advects, collides or truncates.  The initial factors are a weighted thin SVD
+of a prescribed initial condition, which is input preparation (the paper
+starts every run from a given low-rank representation, Algorithm 6 input).
+
+Conventions (shared by both sides, stated once here):
+  * global cells are indexed p = iy*nx + ix (x fastest), square cells of
+    width h = (x1-x0)/nx = (y1-y0)/ny;
+  * subdomain s = sy*px + sx holds lnx = nx/px by lny = ny/py cells with the
+    local index p = iy*lnx + ix;
+  * a direction set is (omega_x[q], omega_y[q], w[q]); W = sum(w);
+  * factors: U is N x r with h^2 U^T U = I, V is M x r with V^T diag(w) V = I,
+    S is r x r, and the subdomain's distribution is F = U S V^T (N x M).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional
+
+import numpy as np
+
+RANK_FIXED = 0
+RANK_ADAPTIVE = 1
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    nx: int
+    ny: int
+    px: int
+    py: int
+    x0: float
+    x1: float
+    y0: float
+    y1: float
+    omega_x: np.ndarray
+    omega_y: np.ndarray
+    w: np.ndarray
+    c_adv: float
+    sigma_s: np.ndarray          # [ny*nx]
+    sigma_a: np.ndarray          # [ny*nx]
+    Q: np.ndarray                # [ny*nx]
+    dt: float
+    rank_mode: int
+    r_fixed: int
+    r_min: int
+    r_max: int
+    r_int_max: int
+    tol: float                   # absolute L2 tolerance (adaptive mode)
+    tol_aug_rel: float           # fixed mode: augmentation tail <= tol_aug_rel * sigma_1
+    n_steps: int
+    U0: List[np.ndarray]
+    S0: List[np.ndarray]
+    V0: List[np.ndarray]
+    seed: int = 0
+    note: str = ""
+
+    @property
+    def lnx(self) -> int:
+        return self.nx // self.px
+
+    @property
+    def lny(self) -> int:
+        return self.ny // self.py
+
+    @property
+    def N(self) -> int:
+        return self.lnx * self.lny
+
+    @property
+    def M(self) -> int:
+        return int(self.w.shape[0])
+
+    @property
+    def h(self) -> float:
+        return (self.x1 - self.x0) / self.nx
+
+    @property
+    def n_sub(self) -> int:
+        return self.px * self.py
+
+    def ranks(self) -> List[int]:
+        return [int(s.shape[0]) for s in self.S0]
+
+    def local_cells(self, s: int) -> np.ndarray:
+        """Global flat cell indices of subdomain s, in local order."""
+        sx, sy = s % self.px, s // self.px
+        iy = sy * self.lny + np.arange(self.lny)
+        ix = sx * self.lnx + np.arange(self.lnx)
+        return (iy[:, None] * self.nx + ix[None, :]).ravel()
+
+    def updates_per_step(self) -> float:
+        """sum_k N_k * M * r_k at the current ranks."""
+        return float(sum(self.N * self.M * r for r in self.ranks()))
+
+    def with_factors(self, U, S, V) -> "Workload":
+        return dataclasses.replace(self, U0=list(U), S0=list(S), V0=list(V))
+
+
+# ----------------------------------------------------------------------------
+# direction sets
+# ----------------------------------------------------------------------------
+
+def paper_directions(n_phi: int):
+    """Equidistant angles phi_k = (k + 1/2) 2 pi / n_phi of the 2x1-D model,
+    v = (cos phi, sin phi), weights 2 pi / n_phi (so W = 2 pi)."""
+    phi = (np.arange(n_phi) + 0.5) * (2.0 * math.pi / n_phi)
+    w = np.full(n_phi, 2.0 * math.pi / n_phi)
+    return np.cos(phi), np.sin(phi), w
+
+
+def axis_directions():
+    """Four directions along +x, +y, -x, -y with weight pi/2 each."""
+    ox = np.array([1.0, 0.0, -1.0, 0.0])
+    oy = np.array([0.0, 1.0, 0.0, -1.0])
+    return ox, oy, np.full(4, math.pi / 2.0)
+
+
+def product_directions(n_polar: int, n_azim: int):
+    """Gauss-Legendre polar cosines mu_a on [-1,1] times equispaced azimuths
+    phi_b = (b+1/2) 2 pi / n_azim.  Omega = (sqrt(1-mu^2) cos phi,
+    sqrt(1-mu^2) sin phi), w = w_a * 2 pi / n_azim, so W = 4 pi.
+    Direction index q = a * n_azim + b."""
+    mu, wa = np.polynomial.legendre.leggauss(n_polar)
+    phi = (np.arange(n_azim) + 0.5) * (2.0 * math.pi / n_azim)
+    st = np.sqrt(1.0 - mu * mu)
+    ox = (st[:, None] * np.cos(phi)[None, :]).ravel()
+    oy = (st[:, None] * np.sin(phi)[None, :]).ravel()
+    w = (wa[:, None] * np.full(n_azim, 2.0 * math.pi / n_azim)[None, :]).ravel()
+    return ox, oy, w
+
+
+# ----------------------------------------------------------------------------
+# initial factors
+# ----------------------------------------------------------------------------
+
+def factors_from_product(A: np.ndarray, B: np.ndarray, r: int, h: float, w: np.ndarray,
+                         exact_rank: bool = False):
+    """Weighted thin SVD of F = A B^T (A: N x k, B: M x k), truncated to rank r.
+
+    Returns U (N x r, h^2 U^T U = I), S (r x r, diagonal, descending), V (M x r,
+    V^T diag(w) V = I).  If exact_rank is set, r may not exceed k."""
+    sw = np.sqrt(w)
+    qa, ra = np.linalg.qr(h * A)
+    qb, rb = np.linalg.qr(sw[:, None] * B)
+    core = ra @ rb.T
+    uc, sig, vct = np.linalg.svd(core)
+    k = core.shape[0]
+    if r > k:
+        if exact_rank:
+            raise ValueError("rank larger than the product's inner dimension")
+        # pad with orthonormal complements and zero singular values
+        rng = np.random.default_rng(12345)
+        U = np.hstack([qa @ uc, rng.standard_normal((A.shape[0], r - k))])
+        V = np.hstack([qb @ vct.T, rng.standard_normal((B.shape[0], r - k))])
+        U, _ = np.linalg.qr(U)
+        V, _ = np.linalg.qr(V)
+        s = np.concatenate([sig, np.zeros(r - k)])
+        return U / h, np.diag(s), V / sw[:, None]
+    U = (qa @ uc[:, :r]) / h
+    V = (qb @ vct.T[:, :r]) / sw[:, None]
+    return U, np.diag(sig[:r]), V
+
+
+def random_factors(N: int, M: int, r: int, h: float, w: np.ndarray, rng, sig=None):
+    """Random weighted-orthonormal U, V and S = U_s diag(sig) V_s^T with random
+    rotations (so S is a full r x r matrix)."""
+    sw = np.sqrt(w)
+    U, _ = np.linalg.qr(rng.standard_normal((N, r)))
+    V, _ = np.linalg.qr(rng.standard_normal((M, r)))
+    if sig is None:
+        sig = np.logspace(0.0, -2.0, r)
+    a, _ = np.linalg.qr(rng.standard_normal((r, r)))
+    b, _ = np.linalg.qr(rng.standard_normal((r, r)))
+    S = a @ np.diag(sig) @ b.T
+    return U / h, S, V / sw[:, None]
+
+
+# ----------------------------------------------------------------------------
+# material layouts
+# ----------------------------------------------------------------------------
+
+def _cell_centres(nx, ny, x0, x1, y0, y1):
+    h = (x1 - x0) / nx
+    xc = x0 + (np.arange(nx) + 0.5) * h
+    yc = y0 + (np.arange(ny) + 0.5) * h
+    X, Y = np.meshgrid(xc, yc)          # [ny, nx]
+    return X.ravel(), Y.ravel()
+
+
+def checkerboard(nx, ny, x0, x1, y0, y1, block, scat=(1.0, 0.0), absb=(0.0, 10.0)):
+    """Unit-block checkerboard: block (floor((x-x0)/block), floor((y-y0)/block))
+    with an even index sum is a scatterer (sigma_s, sigma_a) = scat, odd is an
+    absorber absb."""
+    X, Y = _cell_centres(nx, ny, x0, x1, y0, y1)
+    bi = np.floor((X - x0) / block).astype(int)
+    bj = np.floor((Y - y0) / block).astype(int)
+    even = ((bi + bj) % 2) == 0
+    ss = np.where(even, scat[0], absb[0]).astype(float)
+    sa = np.where(even, scat[1], absb[1]).astype(float)
+    return ss, sa
+
+
+# ----------------------------------------------------------------------------
+# named workloads
+# ----------------------------------------------------------------------------
+
+def _split_factors(nx, ny, px, py, h, A_glob, B, ranks, w):
+    lnx, lny = nx // px, ny // py
+    U, S, V = [], [], []
+    for s in range(px * py):
+        sx, sy = s % px, s // px
+        iy = sy * lny + np.arange(lny)
+        ix = sx * lnx + np.arange(lnx)
+        cells = (iy[:, None] * nx + ix[None, :]).ravel()
+        u, sg, v = factors_from_product(A_glob[cells], B, ranks[s], h, w)
+        U.append(u)
+        S.append(sg)
+        V.append(v)
+    return U, S, V
+
+
+def make_workload(name: str, seed: Optional[int] = None, **over) -> Workload:
+    """Named synthetic workloads.
+
+    C1..C5 follow the configurations of the DD-DLRA hot path (sizes, ranks,
+    material layouts, initial conditions); the paper's own lattice, Hohlraum and
+    point-source geometries exist only as figures, so these layouts are
+    stand-ins with the same structure (checkerboard absorber/scatterer blocks,
+    localized sources, thick/thin regions).  'wc-*' variants replace the
+    near-rank-one initial data by generic well-conditioned random factors
+    (singular values 1 .. 1e-2) for strict FP64 parity."""
+    idx = {"C1": 1, "C2": 2, "C3": 3, "C4": 4, "C5": 5}
+    base = name.split(":")[0]
+    cfg_i = idx.get(base.replace("wc-", ""), 0)
+    if seed is None:
+        seed = 1000 + cfg_i
+    rng = np.random.default_rng(seed)
+    wc = base.startswith("wc-")
+    key = base.replace("wc-", "")
+
+    if key == "C1":
+        nx = ny = 32; px = py = 2; x0, x1, y0, y1 = 0.0, 4.0, 0.0, 4.0
+        ox, oy, w = product_directions(8, 8)
+        r = 5; steps = 10
+        ss, sa = checkerboard(nx, ny, x0, x1, y0, y1, 1.0)
+        Q = np.zeros(nx * ny)
+        mode, r_int = RANK_FIXED, 2 * r
+        tol = 0.0
+        r_min, r_max = r, r
+    elif key == "C2":
+        nx = ny = 224; px = py = 7; x0, x1, y0, y1 = 0.0, 7.0, 0.0, 7.0
+        ox, oy, w = product_directions(16, 16)
+        r = 10; steps = 200
+        ss, sa = checkerboard(nx, ny, x0, x1, y0, y1, 1.0)
+        X, Y = _cell_centres(nx, ny, x0, x1, y0, y1)
+        Q = (((X > 3.0) & (X < 4.0) & (Y > 3.0) & (Y < 4.0))).astype(float)
+        mode, r_int = RANK_FIXED, 2 * r
+        tol = 0.0
+        r_min, r_max = r, r
+    elif key == "C3":
+        nx = ny = 448; px = py = 7; x0, x1, y0, y1 = 0.0, 7.0, 0.0, 7.0
+        ox, oy, w = product_directions(32, 32)
+        r = 20; steps = 200
+        ss, sa = checkerboard(nx, ny, x0, x1, y0, y1, 1.0)
+        X, Y = _cell_centres(nx, ny, x0, x1, y0, y1)
+        Q = (((X > 3.0) & (X < 4.0) & (Y > 3.0) & (Y < 4.0))).astype(float)
+        mode, r_int = RANK_FIXED, 2 * r
+        tol = 0.0
+        r_min, r_max = r, r
+    elif key == "C4":
+        nx = ny = 512; px = py = 8; x0, x1, y0, y1 = 0.0, 1.0, 0.0, 1.0
+        ox, oy, w = product_directions(32, 32)
+        r = 40; steps = 100
+        X, Y = _cell_centres(nx, ny, x0, x1, y0, y1)
+        ss = np.where(X < 0.5, 100.0, 0.01)
+        sa = np.zeros(nx * ny)
+        Q = np.zeros(nx * ny)
+        mode, r_int = RANK_ADAPTIVE, 80
+        tol = 1e-4
+        r_min, r_max = 2, 40
+    elif key == "C5":
+        nx = ny = 1024; px = py = 16; x0, x1, y0, y1 = -1.0, 1.0, -1.0, 1.0
+        ox, oy, w = product_directions(32, 64)
+        r = 64; steps = 500
+        ss = np.full(nx * ny, 1.0)
+        sa = np.full(nx * ny, 0.1)
+        Q = np.zeros(nx * ny)
+        mode, r_int = RANK_ADAPTIVE, 128
+        tol = 1e-4
+        r_min, r_max = 1, 64
+    else:
+        raise KeyError(name)
+
+    h = (x1 - x0) / nx
+    W = float(np.sum(w))
+    if key == "C5":
+        Q[(ny // 2) * nx + nx // 2] = 1.0 / (h * h * W)
+    M = w.shape[0]
+    n_sub = px * py
+    N = (nx // px) * (ny // py)
+    c_adv = 1.0
+    dt = 0.5 * h / c_adv
+
+    U0, S0, V0 = [], [], []
+    if wc:
+        ranks = [r] * n_sub
+        for s in range(n_sub):
+            u, sg, v = random_factors(N, M, ranks[s], h, w, rng)
+            U0.append(u); S0.append(sg); V0.append(v)
+    elif key == "C1":
+        X, Y = _cell_centres(nx, ny, x0, x1, y0, y1)
+        width = 0.1
+        g = np.exp(-((X - 2.0) ** 2 + (Y - 2.0) ** 2) / (2 * width * width)) / (2 * math.pi * width * width)
+        A = np.hstack([g[:, None], 1e-8 * rng.standard_normal((nx * ny, 5))])
+        B = np.hstack([np.full((M, 1), 1.0 / W), rng.standard_normal((M, 5))])
+        U0, S0, V0 = _split_factors(nx, ny, px, py, h, A, B, [r] * n_sub, w)
+    elif key in ("C2", "C3"):
+        A = np.hstack([np.full((nx * ny, 1), 1e-9), 1e-12 * rng.standard_normal((nx * ny, r))])
+        B = np.hstack([np.ones((M, 1)), rng.standard_normal((M, r))])
+        U0, S0, V0 = _split_factors(nx, ny, px, py, h, A, B, [r] * n_sub, w)
+    elif key == "C4":
+        for s in range(n_sub):
+            rk = int(rng.integers(2, 41))
+            sig = 10.0 ** (-4.5 * np.arange(rk) / rk)
+            u, sg, v = random_factors(N, M, rk, h, w, rng, sig=sig)
+            U0.append(u); S0.append(sg); V0.append(v)
+    elif key == "C5":
+        A = np.hstack([np.full((nx * ny, 1), 1e-9), 1e-12 * rng.standard_normal((nx * ny, 2))])
+        B = np.hstack([np.ones((M, 1)), rng.standard_normal((M, 2))])
+        U0, S0, V0 = _split_factors(nx, ny, px, py, h, A, B, [2] * n_sub, w)
+
+    wl = Workload(name=name, nx=nx, ny=ny, px=px, py=py, x0=x0, x1=x1, y0=y0, y1=y1,
+                  omega_x=ox, omega_y=oy, w=w, c_adv=c_adv, sigma_s=ss, sigma_a=sa, Q=Q,
+                  dt=dt, rank_mode=mode, r_fixed=r, r_min=r_min, r_max=r_max,
+                  r_int_max=r_int, tol=tol, tol_aug_rel=1e-12, n_steps=steps,
+                  U0=U0, S0=S0, V0=V0, seed=seed)
+    for k, v in over.items():
+        setattr(wl, k, v)
+    return wl
+
+
+def make_custom(nx, ny, px, py, dirs, ranks, seed=7, length=1.0, c_adv=1.0, cfl=0.5,
+                sigma_s=None, sigma_a=None, Q=None, rank_mode=RANK_FIXED, r_fixed=None,
+                r_int_max=None, r_min=1, r_max=None, tol=0.0, tol_aug_rel=1e-12,
+                sig=None, init=None, name="custom") -> Workload:
+    """Small hand-built problems for pins and parity cases.
+
+    dirs: (omega_x, omega_y, w).  ranks: list of per-subdomain ranks.
+    init: optional callable (N, M, r, h, w, rng, s) -> (U, S, V)."""
+    rng = np.random.default_rng(seed)
+    ox, oy, w = dirs
+    h = length / nx
+    y1 = h * ny
+    n = nx * ny
+    M = w.shape[0]
+    N = (nx // px) * (ny // py)
+    if sigma_s is None:
+        sigma_s = np.zeros(n)
+    if sigma_a is None:
+        sigma_a = np.zeros(n)
+    if Q is None:
+        Q = np.zeros(n)
+    U0, S0, V0 = [], [], []
+    for s in range(px * py):
+        if init is not None:
+            u, sg, v = init(N, M, ranks[s], h, w, rng, s)
+        else:
+            u, sg, v = random_factors(N, M, ranks[s], h, w, rng, sig=None if sig is None else sig[: ranks[s]])
+        U0.append(u); S0.append(sg); V0.append(v)
+    rf = r_fixed if r_fixed is not None else max(ranks)
+    return Workload(name=name, nx=nx, ny=ny, px=px, py=py, x0=0.0, x1=length, y0=0.0, y1=y1,
+                    omega_x=np.asarray(ox, float), omega_y=np.asarray(oy, float),
+                    w=np.asarray(w, float), c_adv=c_adv,
+                    sigma_s=np.asarray(sigma_s, float), sigma_a=np.asarray(sigma_a, float),
+                    Q=np.asarray(Q, float), dt=cfl * h / max(c_adv, 1e-300),
+                    rank_mode=rank_mode, r_fixed=rf, r_min=r_min,
+                    r_max=r_max if r_max is not None else rf,
+                    r_int_max=r_int_max if r_int_max is not None else 2 * rf,
+                    tol=tol, tol_aug_rel=tol_aug_rel, n_steps=1,
+                    U0=U0, S0=S0, V0=V0, seed=seed)
