@@ -1,0 +1,214 @@
+#!/usr/bin/env python3
+"""Throughput of the DD-DLRA time step on one MI355X.
+
+A step is one pass of Algorithm 6 over all subdomains (x stage, y stage,
+collision stage) on synthetic inputs already resident in HBM.  The default
+workload is the lattice configuration: 224 x 224 cells as 7 x 7 subdomains of
+32 x 32, 256 directions (16 Gauss-Legendre polar x 16 azimuthal), fixed
+rank 10, checkerboard absorber / scatterer blocks, source in the central
+block.  Prints one JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--config C2] [--mode graph]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+
+WORKLOAD_NAMES = {
+    "C1": "gaussian 32x32 cells, 2x2 subdomains, 64 directions, rank 5",
+    "C2": "lattice 224x224 cells, 7x7 subdomains of 32x32, 256 directions, rank 10",
+    "C3": "lattice 448x448 cells, 7x7 subdomains of 64x64, 1024 directions, rank 20",
+}
+
+
+def algorithmic_cost(wl, tmax):
+    """Algorithmic HBM bytes and flops per launch of each kernel kind for one
+    step (FP64: 8 bytes per element), from the shapes the step must touch.
+    t_s (intermediate rank) is taken as tmax[s]; r_s the stored rank."""
+    import numpy as np
+    N, M, ns = wl.N, wl.M, wl.n_sub
+    r = np.asarray(wl.ranks(), float)
+    t = np.minimum(np.asarray(tmax, float), wl.r_int_max)
+
+    def m0(axis):
+        out = []
+        for s in range(ns):
+            sx, sy = s % wl.px, s // wl.px
+            k = r[s]
+            for side in (-1, 1):
+                if axis == 0 and 0 <= sx + side < wl.px:
+                    k += r[sy * wl.px + sx + side]
+                if axis == 1 and 0 <= sy + side < wl.py:
+                    k += r[(sy + side) * wl.px + sx]
+            out.append(k)
+        return np.asarray(out)
+
+    m = (m0(0) + m0(1)) / 2.0
+    B = 8.0
+    cost = {}
+    # per advection stage, summed over subdomains; 2 stages per step -> 2 launches
+    cost["k_kstep"] = (B * N * np.sum(r + t), 2.0 * N * np.sum(3 * r * t + t * (t + 1) / 2), 2)
+    cost["k_spatial_reduce"] = (B * N * np.sum(t), 4.0 * N * np.sum(t * t), 2)
+    cost["k_aug_form"] = (B * M * np.sum(2 * m), 2.0 * M * np.sum(m * m), 2)
+    cost["k_ang_reduce"] = (B * M * np.sum(t + m), 2.0 * M * np.sum(r * t + 3 * t * t + (m - r) * t), 2)
+    cost["k_lstep"] = (B * M * np.sum(2 * t), 2.0 * M * np.sum(2 * t * t), 2)
+    # the three QR products of K1 per advection stage (t columns) and of the
+    # collision stage (r columns): 9 launches per step
+    cost["k_gemm[QR K1]"] = (B * N * (6 * np.sum(2 * t) + 3 * np.sum(2 * r)) / 9.0,
+                             2.0 * N * (6 * np.sum(t * t) + 3 * np.sum(r * r)) / 9.0, 9)
+    cost["k_gemm[QR L1]"] = (B * M * (6 * np.sum(2 * t) + 3 * np.sum(2 * r)) / 9.0,
+                             2.0 * M * (6 * np.sum(t * t) + 3 * np.sum(r * r)) / 9.0, 9)
+    cost["k_coll_kstep"] = (B * N * np.sum(2 * r + 3), 2.0 * N * np.sum(r * r + 4 * r), 1)
+    cost["k_coll_reduce"] = (B * N * np.sum(r + 3), 2.0 * N * np.sum(2 * r * r + r), 1)
+    cost["k_gemm[U=Q*Bu]"] = (B * N * np.sum(t + r), 2.0 * N * np.sum(t * r), 2)
+    return cost
+
+
+def cpu_baseline(wl, budget_s=12.0, max_steps=30):
+    """The FP64 oracle on the host cores, on the first steps of the same
+    workload until about budget_s seconds of work."""
+    from oracle import ddlra as dd
+    threads = None
+    try:
+        from threadpoolctl import threadpool_info
+        info = threadpool_info()
+        threads = max((i.get("num_threads", 1) for i in info), default=None)
+    except Exception:
+        pass
+    prob = dd.Problem(wl)
+    st = dd.initial_state(wl)
+    st = dd.dd_step(st, prob)  # warm-up step
+    n, t0 = 0, time.perf_counter()
+    upd = 0.0
+    while n < max_steps and time.perf_counter() - t0 < budget_s:
+        upd += sum(prob.N * prob.M * s.shape[0] for _, s, _ in st)
+        st = dd.dd_step(st, prob)
+        n += 1
+    el = time.perf_counter() - t0
+    return {"value": upd / el, "unit": "updates/s", "cores": threads or os.cpu_count(),
+            "kind": "oracle",
+            "sample": f"steps 2..{n + 1} of the same workload ({n} timed steps, {el:.1f} s, "
+                      f"{el / n * 1e3:.0f} ms/step), NumPy/LAPACK FP64"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", default="C2")
+    ap.add_argument("--mode", default="graph", choices=["graph", "batched", "per-subdomain"])
+    ap.add_argument("--profile-steps", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
+              "(the path would shard by blocks of subdomains with a halo exchange of low-rank traces)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads as wk
+    import paper_2602_14854_amd as pkg
+
+    torch.cuda.set_device(0)
+    wl = wk.make_workload(args.config)
+    mode = {"graph": pkg.DD_EXEC_BATCHED_GRAPH, "batched": pkg.DD_EXEC_BATCHED,
+            "per-subdomain": pkg.DD_EXEC_PER_SUBDOMAIN}[args.mode]
+    stream = torch.cuda.Stream()
+    eng = pkg.DDDLRA(wl, exec_mode=mode, stream=stream)
+    print(f"[bench] workload {args.config}: {wl.nx}x{wl.ny} cells, {wl.px}x{wl.py} subdomains, "
+          f"M={wl.M}, rank {wl.r_fixed}, mode {args.mode}", file=sys.stderr, flush=True)
+    eng.step(args.warmup)
+    eng.sync()
+    r0, _, _ = eng.ranks()
+    updates = float(np.sum(wl.N * wl.M * r0.astype(float)))
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    eng.step(args.steps)
+    ev1.record(stream)
+    stream.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    eng.sync()
+    ms_per_step = ev0.elapsed_time(ev1) / args.steps
+    r1, tmax, clamps = eng.ranks()
+    print(f"[bench] timed {args.steps} steps: {ms_per_step:.3f} ms/step (wall {wall:.3f} s)",
+          file=sys.stderr, flush=True)
+
+    # per-kernel timing: the same kernels, launched phase by phase with
+    # hipEvent pairs on the engine's stream
+    eng.profile(True)
+    for _ in range(args.profile_steps):
+        for st in (0, 1, 2):
+            eng.stage(st)
+    stats = eng.kernel_stats()
+    eng.profile(False)
+    eng.close()
+    prof_total = sum(ms for _, ms in stats.values())
+    kern = {k: {"launches": n, "avg_us": 1e3 * ms / max(n, 1), "share": ms / prof_total}
+            for k, (n, ms) in stats.items() if n > 0}
+    costs = algorithmic_cost(wl, tmax)
+    ts = {k: v for k, v in kern.items() if k in costs}
+    dom = max(ts, key=lambda k: ts[k]["share"])
+    nbytes, nflops, _ = costs[dom]
+    avg_s = ts[dom]["avg_us"] * 1e-6
+    gbs = nbytes / avg_s / 1e9
+    tfl = nflops / avg_s / 1e12
+    intensity = nflops / nbytes
+    bound = "hbm" if intensity < FP64_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9) else "alu"
+    if bound == "hbm":
+        roof = {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    else:
+        roof = {"bound": "alu", "achieved": round(tfl, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(tfl / FP64_PEAK_TFLOPS, 4)}
+    roof.update({"kernel": dom, "avg_us": round(ts[dom]["avg_us"], 3),
+                 "algorithmic_bytes_per_launch": int(nbytes), "algorithmic_flops_per_launch": int(nflops),
+                 "traffic": None})
+
+    out = {
+        "metric": "subdomain-cell·angle·rank updates/s per step",
+        "value": updates / (ms_per_step * 1e-3),
+        "unit": "updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD_NAMES.get(args.config, args.config), "name": args.config,
+                   "subdomains": wl.n_sub, "cells_per_subdomain": wl.N, "directions": wl.M,
+                   "rank": int(wl.r_fixed), "r_int_max": int(wl.r_int_max), "exec_mode": args.mode,
+                   "max_intermediate_rank": int(np.max(tmax)), "updates_per_step": updates},
+        "roofline": roof,
+        "kernels": {k: {"avg_us": round(v["avg_us"], 2), "share": round(v["share"], 4), "launches": v["launches"]}
+                    for k, v in sorted(kern.items(), key=lambda kv: -kv[1]["share"])},
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

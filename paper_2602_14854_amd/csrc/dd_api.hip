@@ -1,0 +1,826 @@
+// Host side of the DD-DLRA C ABI (include/dd_dlra.h): configuration checks,
+// device arena layout, uploads, the launch plan of one time step
+// (Algorithm 6: x stage, y stage, collision stage), hipGraph capture and the
+// query calls.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "dd_dlra.h"
+#include "dd_internal.h"
+
+using dd::Dev;
+
+struct dd_dlra_s {
+  dd_dlra_config cfg;
+  Dev d;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool own_ws = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::string err;
+  // kernel timing (dd_dlra_profile)
+  bool profiling = false;
+  bool capturing = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<std::pair<int, int>> pending;  // (kernel kind, launches) per event pair
+  std::vector<int64_t> k_launch;
+  std::vector<double> k_ms;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+enum Kind {
+  K_AUG_FORM, K_AUG_EIG1, K_GEMM_AUG_ROT, K_AUG_EIG2, K_GEMM_VHAT, K_CHOL, K_GEMM_QR_VHAT, K_ANG_REDUCE,
+  K_ADV_PREP, K_KSTEP, K_GEMM_QR_K, K_SPATIAL_REDUCE, K_ADV_SSTEP, K_LSTEP, K_GEMM_QR_L, K_TRUNC,
+  K_GEMM_FINAL_U, K_GEMM_FINAL_V, K_SET_RANK, K_COLL_PREP, K_COLL_KSTEP, K_COLL_REDUCE, K_COLL_SSTEP,
+  K_COLL_LSTEP, K_COLL_FINAL, K_COUNT
+};
+
+const char* const kKindName[K_COUNT] = {
+  "k_aug_form", "s_aug_eig1", "k_gemm[aug Z=A*Y1]", "s_aug_eig2", "k_gemm[V-hat=Z*Coef]", "s_chol",
+  "k_gemm[QR V-hat]", "k_ang_reduce", "s_adv_prep", "k_kstep", "k_gemm[QR K1]", "k_spatial_reduce",
+  "s_adv_sstep", "k_lstep", "k_gemm[QR L1]", "s_trunc", "k_gemm[U=Q*Bu]", "k_gemm[V=QL*Bv]", "s_set_rank",
+  "s_coll_prep", "k_coll_kstep", "k_coll_reduce", "s_coll_sstep", "k_coll_lstep", "s_coll_final",
+};
+
+struct Layout {
+  int R, T, MA, N, M, nsub, ntN, ntM, nwgN, nwgM, gpTile;
+  int64_t gpStride, smallStride;
+  int off[48];
+  size_t bytes;
+  // byte offsets of the arena segments
+  size_t oU, oV, oS, oA, oZ, oQh, oQh2, oK1, oK2, oAL, oAL2, oGP, oSM, oRho, oIn, oCs, oCt, oQ, oInt, oFlags;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+bool finite_all(const double* p, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+// Validate everything that does not need the initial factors.  Returns an
+// empty string on success.
+std::string validate(const dd_dlra_config* c) {
+  if (!c) return "config is NULL";
+  if (c->nx <= 0 || c->ny <= 0 || c->px <= 0 || c->py <= 0) return "grid and subdomain counts must be positive";
+  if (c->nx % c->px || c->ny % c->py) return "nx must be divisible by px and ny by py";
+  if (!(c->x1 > c->x0) || !(c->y1 > c->y0)) return "empty domain";
+  const double hx = (c->x1 - c->x0) / c->nx, hy = (c->y1 - c->y0) / c->ny;
+  if (fabs(hx - hy) > 1e-12 * hx) return "cells must be square: (x1-x0)/nx != (y1-y0)/ny";
+  if (c->n_dir <= 0) return "n_dir must be positive";
+  if (!c->omega_x || !c->omega_y || !c->w) return "direction arrays must not be NULL";
+  if (!c->sigma_s || !c->sigma_a || !c->Q) return "field arrays must not be NULL";
+  const size_t M = c->n_dir, n = (size_t)c->nx * c->ny;
+  if (!finite_all(c->omega_x, M) || !finite_all(c->omega_y, M) || !finite_all(c->w, M))
+    return "non-finite direction data";
+  for (size_t q = 0; q < M; ++q)
+    if (!(c->w[q] > 0.0)) return "quadrature weights must be positive";
+  if (!finite_all(c->sigma_s, n) || !finite_all(c->sigma_a, n) || !finite_all(c->Q, n)) return "non-finite field data";
+  for (size_t p = 0; p < n; ++p)
+    if (c->sigma_s[p] < 0.0 || c->sigma_a[p] < 0.0) return "cross sections must be non-negative";
+  if (!(c->dt > 0.0) || !std::isfinite(c->dt)) return "dt must be positive";
+  if (!(c->c_adv >= 0.0) || !std::isfinite(c->c_adv)) return "c_adv must be non-negative";
+  if (c->rank_mode != DD_RANK_FIXED && c->rank_mode != DD_RANK_ADAPTIVE) return "unknown rank_mode";
+  if (c->rank_mode == DD_RANK_FIXED && c->r_fixed < 1) return "r_fixed must be >= 1";
+  if (c->rank_mode == DD_RANK_ADAPTIVE) {
+    if (c->r_min < 1 || c->r_max < c->r_min) return "need 1 <= r_min <= r_max";
+    if (!(c->tol >= 0.0)) return "tol must be >= 0";
+  }
+  if (!(c->tol_aug_rel >= 0.0)) return "tol_aug_rel must be >= 0";
+  const int R = c->rank_mode == DD_RANK_FIXED ? c->r_fixed : c->r_max;
+  if (c->r_int_max < R) return "r_int_max must be at least the stored-rank capacity";
+  if (c->r_int_max > dd::CAP) return "r_int_max beyond the supported maximum of 64";
+  if (3 * R > dd::CAP) return "stored-rank capacity beyond the supported maximum of 21";
+  if (c->precision != DD_PREC_FP64) return "only DD_PREC_FP64 is available";
+  if (c->exec_mode < DD_EXEC_PER_SUBDOMAIN || c->exec_mode > DD_EXEC_BATCHED_GRAPH) return "unknown exec_mode";
+  for (int f = 0; f < 4; ++f)
+    if (c->bc[f] != DD_BC_VACUUM) return "only vacuum physical boundaries are available";
+  return "";
+}
+
+Layout make_layout(const dd_dlra_config* c) {
+  Layout L;
+  L.R = c->rank_mode == DD_RANK_FIXED ? c->r_fixed : c->r_max;
+  L.T = c->r_int_max;
+  L.MA = 3 * L.R;
+  L.nsub = c->px * c->py;
+  L.N = (c->nx / c->px) * (c->ny / c->py);
+  L.M = c->n_dir;
+  L.ntN = (L.N + dd::TILE - 1) / dd::TILE;
+  L.ntM = (L.M + dd::TILE - 1) / dd::TILE;
+  const int target = std::max(1, (1024 + L.nsub - 1) / L.nsub);
+  L.nwgN = std::min(std::min(L.ntN, target), 64);
+  L.nwgM = std::min(std::min(L.ntM, target), 64);
+  const int R = L.R, T = L.T, MA = L.MA;
+  L.gpTile = std::max(std::max(MA * MA, 3 * T * T + 3 * R * T), std::max(2 * T * T, 2 * R * R + R));
+  L.gpStride = (int64_t)std::max(L.nwgN, L.nwgM) * L.gpTile;
+  // small workspace
+  int o = 0;
+  int* f = L.off;
+  auto take = [&](int n) {
+    int r = o;
+    o += (n + 31) & ~31;
+    return r;
+  };
+  int k = 0;
+  f[k++] = take(MA * MA);  // Y1
+  f[k++] = take(MA * T);   // Coef
+  f[k++] = take(T);        // Fill
+  f[k++] = take(T * T);    // Rinv
+  f[k++] = take(T * T);    // Racc
+  f[k++] = take(T * T);    // Cp
+  f[k++] = take(T * T);    // Cn
+  f[k++] = take(R * T);    // Am
+  for (int i = 0; i < 7; ++i) f[k++] = take(R * T);  // M0 Mm Mp GLo GHi GLoN GHiN
+  f[k++] = take(T * T);    // Ep
+  f[k++] = take(T * T);    // En
+  f[k++] = take(R * T);    // Olo
+  f[k++] = take(R * T);    // Ohi
+  f[k++] = take(R * T);    // Tm
+  f[k++] = take(T * T);    // Gm
+  f[k++] = take(T * T);    // Gp
+  f[k++] = take(T * T);    // BKlo
+  f[k++] = take(T * T);    // BKhi
+  f[k++] = take(T * T);    // S1
+  f[k++] = take(T * T);    // S2
+  f[k++] = take(T * T);    // P0
+  f[k++] = take(T * T);    // Pm
+  f[k++] = take(T * T);    // Pp
+  f[k++] = take(T * T);    // Bu
+  f[k++] = take(T * T);    // Bv
+  f[k++] = take(MA);       // Sig
+  f[k++] = take(R);        // Mv
+  f[k++] = take(R);        // Crow
+  f[k++] = take(R * R);    // Gs
+  f[k++] = take(R * R);    // Gt
+  f[k++] = take(R);        // Qv
+  for (int i = 0; i < 6; ++i) f[k++] = take(T * T);  // W1..W6
+  L.smallStride = o;
+  // arena
+  const size_t d8 = sizeof(double);
+  const size_t ns = L.nsub;
+  size_t b = 0;
+  auto seg = [&](size_t bytes) {
+    size_t r = b;
+    b = align256(b + bytes);
+    return r;
+  };
+  L.oU = seg(ns * L.N * R * d8);
+  L.oV = seg(ns * L.M * R * d8);
+  L.oS = seg(ns * R * R * d8);
+  L.oA = seg(ns * L.M * MA * d8);
+  L.oZ = seg(ns * L.M * MA * d8);
+  L.oQh = seg(ns * L.M * T * d8);
+  L.oQh2 = seg(ns * L.M * T * d8);
+  L.oK1 = seg(ns * L.N * T * d8);
+  L.oK2 = seg(ns * L.N * T * d8);
+  L.oAL = seg(ns * L.M * T * d8);
+  L.oAL2 = seg(ns * L.M * T * d8);
+  L.oGP = seg(ns * L.gpStride * d8);
+  L.oSM = seg(ns * L.smallStride * d8);
+  L.oRho = seg((size_t)c->nx * c->ny * d8);
+  L.oIn = seg(5 * (size_t)L.M * d8);
+  L.oCs = seg(ns * L.N * d8);
+  L.oCt = seg(ns * L.N * d8);
+  L.oQ = seg(ns * L.N * d8);
+  L.oInt = seg(8 * ns * sizeof(int));
+  L.oFlags = seg(64);
+  L.bytes = b;
+  return L;
+}
+
+void fill_dev(Dev& d, const Layout& L, const dd_dlra_config* c, char* base) {
+  memset(&d, 0, sizeof(d));
+  d.px = c->px;
+  d.py = c->py;
+  d.lnx = c->nx / c->px;
+  d.lny = c->ny / c->py;
+  d.N = L.N;
+  d.M = L.M;
+  d.nsub = L.nsub;
+  d.nx = c->nx;
+  d.h = (c->x1 - c->x0) / c->nx;
+  d.dt = c->dt;
+  d.c = c->c_adv;
+  double W = 0.0;
+  for (int q = 0; q < c->n_dir; ++q) W += c->w[q];
+  d.W = W;
+  d.R = L.R;
+  d.T = L.T;
+  d.MA = L.MA;
+  d.ntN = L.ntN;
+  d.ntM = L.ntM;
+  d.nwgN = L.nwgN;
+  d.nwgM = L.nwgM;
+  d.gpTile = L.gpTile;
+  d.gpStride = L.gpStride;
+  d.smallStride = L.smallStride;
+  d.rank_mode = c->rank_mode;
+  d.r_fixed = c->r_fixed;
+  d.r_min = c->rank_mode == DD_RANK_FIXED ? c->r_fixed : c->r_min;
+  d.r_max = c->rank_mode == DD_RANK_FIXED ? c->r_fixed : c->r_max;
+  d.r_int_max = c->r_int_max;
+  d.strict = c->strict_caps;
+  d.tol = c->tol;
+  d.tol_aug_rel = c->tol_aug_rel;
+  d.U = (double*)(base + L.oU);
+  d.V = (double*)(base + L.oV);
+  d.S = (double*)(base + L.oS);
+  d.A = (double*)(base + L.oA);
+  d.Z = (double*)(base + L.oZ);
+  d.Qh = (double*)(base + L.oQh);
+  d.Qh2 = (double*)(base + L.oQh2);
+  d.K1 = (double*)(base + L.oK1);
+  d.K2 = (double*)(base + L.oK2);
+  d.AL = (double*)(base + L.oAL);
+  d.AL2 = (double*)(base + L.oAL2);
+  d.gpart = (double*)(base + L.oGP);
+  d.small = (double*)(base + L.oSM);
+  d.rho = (double*)(base + L.oRho);
+  double* in = (double*)(base + L.oIn);
+  d.omx = in;
+  d.omy = in + L.M;
+  d.w = in + 2 * L.M;
+  d.sw = in + 3 * L.M;
+  d.isw = in + 4 * L.M;
+  d.cs = (double*)(base + L.oCs);
+  d.ct = (double*)(base + L.oCt);
+  d.Qsrc = (double*)(base + L.oQ);
+  int* ip = (int*)(base + L.oInt);
+  d.rank = ip;
+  d.tdim = ip + L.nsub;
+  d.rnew = ip + 2 * L.nsub;
+  d.tmax = ip + 3 * L.nsub;
+  d.force = ip + 4 * L.nsub;
+  d.flags = (unsigned*)(base + L.oFlags);
+  d.clamps = (unsigned long long*)(base + L.oFlags + 8);
+  const int* f = L.off;
+  int k = 0;
+  d.oY1 = f[k++]; d.oCoef = f[k++]; d.oFill = f[k++]; d.oRinv = f[k++]; d.oRacc = f[k++];
+  d.oCp = f[k++]; d.oCn = f[k++]; d.oAm = f[k++];
+  d.oM0 = f[k++]; d.oMm = f[k++]; d.oMp = f[k++]; d.oGLo = f[k++]; d.oGHi = f[k++]; d.oGLoN = f[k++]; d.oGHiN = f[k++];
+  d.oEp = f[k++]; d.oEn = f[k++]; d.oOlo = f[k++]; d.oOhi = f[k++]; d.oTm = f[k++];
+  d.oGm = f[k++]; d.oGp = f[k++]; d.oBKlo = f[k++]; d.oBKhi = f[k++]; d.oS1 = f[k++]; d.oS2 = f[k++];
+  d.oP0 = f[k++]; d.oPm = f[k++]; d.oPp = f[k++]; d.oBu = f[k++]; d.oBv = f[k++];
+  d.oSig = f[k++]; d.oMv = f[k++]; d.oCrow = f[k++]; d.oGs = f[k++]; d.oGt = f[k++]; d.oQv = f[k++];
+  d.oW1 = f[k++]; d.oW2 = f[k++]; d.oW3 = f[k++]; d.oW4 = f[k++]; d.oW5 = f[k++]; d.oW6 = f[k++];
+}
+
+std::string check_factors(const dd_dlra_config* c, const Layout& L, const int32_t* rank, const double* const* U,
+                          const double* const* S, const double* const* V) {
+  if (!rank || !U || !S || !V) return "initial factor arrays must not be NULL";
+  const double h = (c->x1 - c->x0) / c->nx;
+  for (int s = 0; s < L.nsub; ++s) {
+    const int r = rank[s];
+    if (r < 1 || r > L.R) return "initial rank of subdomain " + std::to_string(s) + " outside [1, capacity]";
+    if (!U[s] || !S[s] || !V[s]) return "NULL factor of subdomain " + std::to_string(s);
+    if (!finite_all(U[s], (size_t)L.N * r) || !finite_all(S[s], (size_t)r * r) || !finite_all(V[s], (size_t)L.M * r))
+      return "non-finite initial factor in subdomain " + std::to_string(s);
+    for (int i = 0; i < r; ++i)
+      for (int j = 0; j <= i; ++j) {
+        double gu = 0.0, gv = 0.0;
+        for (int p = 0; p < L.N; ++p) gu += U[s][(size_t)i * L.N + p] * U[s][(size_t)j * L.N + p];
+        for (int q = 0; q < L.M; ++q) gv += V[s][(size_t)i * L.M + q] * c->w[q] * V[s][(size_t)j * L.M + q];
+        gu *= h * h;
+        const double e = (i == j) ? 1.0 : 0.0;
+        if (fabs(gu - e) > 1e-8 || fabs(gv - e) > 1e-8)
+          return "initial factors of subdomain " + std::to_string(s) +
+                 " are not orthonormal (need h^2 U^T U = I and V^T diag(w) V = I)";
+      }
+  }
+  return "";
+}
+
+#define HIPCHK(call)                                                                 \
+  do {                                                                               \
+    hipError_t e_ = (call);                                                          \
+    if (e_ != hipSuccess) {                                                          \
+      h->err = std::string(#call) + ": " + hipGetErrorString(e_);                    \
+      return DD_EHIP;                                                                \
+    }                                                                                \
+  } while (0)
+
+dd_status upload_factors(dd_dlra_handle h, const int32_t* rank, const double* const* U, const double* const* S,
+                         const double* const* V) {
+  const Dev& d = h->d;
+  std::vector<double> buf;
+  for (int s = 0; s < d.nsub; ++s) {
+    const int r = rank[s];
+    buf.assign((size_t)d.N * d.R, 0.0);
+    memcpy(buf.data(), U[s], sizeof(double) * (size_t)d.N * r);
+    HIPCHK(hipMemcpyAsync(d.U + (size_t)s * d.N * d.R, buf.data(), buf.size() * 8, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    buf.assign((size_t)d.M * d.R, 0.0);
+    memcpy(buf.data(), V[s], sizeof(double) * (size_t)d.M * r);
+    HIPCHK(hipMemcpyAsync(d.V + (size_t)s * d.M * d.R, buf.data(), buf.size() * 8, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    buf.assign((size_t)d.R * d.R, 0.0);
+    for (int j = 0; j < r; ++j)
+      for (int i = 0; i < r; ++i) buf[i + (size_t)j * d.R] = S[s][i + (size_t)j * r];
+    HIPCHK(hipMemcpyAsync(d.S + (size_t)s * d.R * d.R, buf.data(), buf.size() * 8, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+  }
+  std::vector<int> iv(d.nsub);
+  for (int s = 0; s < d.nsub; ++s) iv[s] = rank[s];
+  HIPCHK(hipMemcpyAsync(d.rank, iv.data(), d.nsub * sizeof(int), hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipMemcpyAsync(d.tmax, iv.data(), d.nsub * sizeof(int), hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return DD_OK;
+}
+
+// ---------------------------------------------------------------- launch plan
+
+hipEvent_t next_event(dd_dlra_handle h) {
+  if (h->ev_used == h->ev_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    h->ev_pool.push_back(e);
+  }
+  return h->ev_pool[h->ev_used++];
+}
+
+// Run one phase either for all subdomains in one launch (batched modes) or
+// once per subdomain (the plain per-subdomain mode); with profiling on (and
+// not capturing a graph) the phase is bracketed by a pair of events.
+template <class F>
+void phase(dd_dlra_handle h, int kind, F&& f) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  const bool timed = h->profiling && !h->capturing && h->ev_used + 2 <= 1u << 16;
+  if (timed) {
+    e0 = next_event(h);
+    e1 = next_event(h);
+    if (e0 && e1) (void)hipEventRecord(e0, h->stream);
+  }
+  int launches = 0;
+  if (h->cfg.exec_mode == DD_EXEC_PER_SUBDOMAIN) {
+    for (int s = 0; s < h->d.nsub; ++s) f(s, 1);
+    launches = h->d.nsub;
+  } else {
+    f(0, h->d.nsub);
+    launches = 1;
+  }
+  if (timed && e0 && e1) {
+    (void)hipEventRecord(e1, h->stream);
+    h->pending.push_back({kind, launches});
+  }
+}
+
+// Shifted Cholesky QR with three passes on X (rows x n; n = dim of kind
+// ndim) leaving Q in Y (X is used as scratch); the R factors accumulate in
+// the small workspace.  With final_dst set, the last product writes there
+// instead (stride ysd_final, optional row scale, Rinv scaled by bscale).
+void chol_qr3(dd_dlra_handle h, int axis, int ndim, double* X, double* Y, int64_t sdstride, int rows, bool cells,
+              double* final_dst, int64_t final_sd, const double* final_rowscale, double bscale, int gemm_kind) {
+  const Dev& d = h->d;
+  hipStream_t st = h->stream;
+  const int ngp = cells ? d.nwgN : d.nwgM;
+  phase(h, K_CHOL, [&](int s0, int ns) { dd::launch_chol(d, axis, s0, ns, ndim, rows, ngp, true, 1, 1.0, st); });
+  phase(h, gemm_kind, [&](int s0, int ns) {
+    dd::launch_gemm(d, axis, s0, ns, X, sdstride, rows, ndim, ndim, d.oRinv, d.T, Y, sdstride, nullptr, true, d.oFill,
+                    cells, st);
+  });
+  phase(h, K_CHOL, [&](int s0, int ns) { dd::launch_chol(d, axis, s0, ns, ndim, rows, ngp, false, 2, 1.0, st); });
+  phase(h, gemm_kind, [&](int s0, int ns) {
+    dd::launch_gemm(d, axis, s0, ns, Y, sdstride, rows, ndim, ndim, d.oRinv, d.T, X, sdstride, nullptr, true, d.oFill,
+                    cells, st);
+  });
+  phase(h, K_CHOL, [&](int s0, int ns) { dd::launch_chol(d, axis, s0, ns, ndim, rows, ngp, false, 2, bscale, st); });
+  double* dst = final_dst ? final_dst : Y;
+  const int64_t dsd = final_dst ? final_sd : sdstride;
+  phase(h, gemm_kind, [&](int s0, int ns) {
+    dd::launch_gemm(d, axis, s0, ns, X, sdstride, rows, ndim, ndim, d.oRinv, d.T, dst, dsd, final_rowscale, false,
+                    d.oFill, cells, st);
+  });
+}
+
+void enqueue_advection(dd_dlra_handle h, int axis) {
+  const Dev& d = h->d;
+  hipStream_t st = h->stream;
+  const int64_t sdMA = (int64_t)d.M * d.MA, sdMT = (int64_t)d.M * d.T, sdNT = (int64_t)d.N * d.T;
+  // Algorithm 4: augmentation, weighted SVD of L0 by two Gram/Jacobi passes
+  phase(h, K_AUG_FORM, [&](int s0, int ns) { dd::launch_aug_form(d, axis, s0, ns, st); });
+  phase(h, K_AUG_EIG1, [&](int s0, int ns) { dd::launch_aug_eig1(d, axis, s0, ns, st); });
+  phase(h, K_GEMM_AUG_ROT, [&](int s0, int ns) {
+    dd::launch_gemm(d, axis, s0, ns, d.A, sdMA, d.M, dd::DIM_M0, dd::DIM_M0, d.oY1, d.MA, d.Z, sdMA, nullptr, true, -1,
+                    false, st);
+  });
+  phase(h, K_AUG_EIG2, [&](int s0, int ns) { dd::launch_aug_eig2(d, axis, s0, ns, st); });
+  phase(h, K_GEMM_VHAT, [&](int s0, int ns) {
+    dd::launch_gemm(d, axis, s0, ns, d.Z, sdMA, d.M, dd::DIM_M0, dd::DIM_T, d.oCoef, d.MA, d.Qh, sdMT, nullptr, true,
+                    d.oFill, false, st);
+  });
+  // two Cholesky QR passes make V-hat orthonormal to working precision
+  for (int pass = 0; pass < 2; ++pass) {
+    double* src = pass == 0 ? d.Qh : d.Qh2;
+    double* dst = pass == 0 ? d.Qh2 : d.Qh;
+    phase(h, K_CHOL,
+          [&](int s0, int ns) { dd::launch_chol(d, axis, s0, ns, dd::DIM_T, d.M, d.nwgM, false, 0, 1.0, st); });
+    phase(h, K_GEMM_QR_VHAT, [&](int s0, int ns) {
+      dd::launch_gemm(d, axis, s0, ns, src, sdMT, d.M, dd::DIM_T, dd::DIM_T, d.oRinv, d.T, dst, sdMT, nullptr,
+                      pass == 0, d.oFill, false, st);
+    });
+  }
+  // angular Galerkin matrices, eigen-split of C, K-step coefficients
+  phase(h, K_ANG_REDUCE, [&](int s0, int ns) { dd::launch_ang_reduce(d, axis, s0, ns, st); });
+  phase(h, K_ADV_PREP, [&](int s0, int ns) { dd::launch_adv_prep(d, axis, s0, ns, st); });
+  // Algorithm 1/2 steps 1-2: K-step, QR
+  phase(h, K_KSTEP, [&](int s0, int ns) { dd::launch_kstep(d, axis, s0, ns, st); });
+  chol_qr3(h, axis, dd::DIM_T, d.K1, d.K2, sdNT, d.N, true, nullptr, 0, nullptr, 1.0, K_GEMM_QR_K);
+  // step 3: S-step
+  phase(h, K_SPATIAL_REDUCE, [&](int s0, int ns) { dd::launch_spatial_reduce(d, axis, s0, ns, d.K2, st); });
+  phase(h, K_ADV_SSTEP, [&](int s0, int ns) { dd::launch_adv_sstep(d, axis, s0, ns, d.K2, st); });
+  // steps 4-5: L-step, weighted QR
+  phase(h, K_LSTEP, [&](int s0, int ns) { dd::launch_lstep(d, axis, s0, ns, st); });
+  chol_qr3(h, axis, dd::DIM_T, d.AL, d.AL2, sdMT, d.M, false, nullptr, 0, nullptr, 1.0, K_GEMM_QR_L);
+  // Algorithm 5: truncation, then rotate the bases into the state
+  phase(h, K_TRUNC, [&](int s0, int ns) { dd::launch_trunc(d, axis, s0, ns, st); });
+  phase(h, K_GEMM_FINAL_U, [&](int s0, int ns) {
+    dd::launch_gemm(d, axis, s0, ns, d.K2, sdNT, d.N, dd::DIM_T, dd::DIM_RNEW, d.oBu, d.T, d.U, (int64_t)d.N * d.R,
+                    nullptr, false, -1, true, st);
+  });
+  phase(h, K_GEMM_FINAL_V, [&](int s0, int ns) {
+    dd::launch_gemm(d, axis, s0, ns, d.AL2, sdMT, d.M, dd::DIM_T, dd::DIM_RNEW, d.oBv, d.T, d.V, (int64_t)d.M * d.R,
+                    d.isw, false, -1, false, st);
+  });
+  phase(h, K_SET_RANK, [&](int s0, int ns) { dd::launch_set_rank(d, s0, ns, st); });
+}
+
+void enqueue_collision(dd_dlra_handle h) {
+  const Dev& d = h->d;
+  hipStream_t st = h->stream;
+  const int64_t sdMT = (int64_t)d.M * d.T, sdNT = (int64_t)d.N * d.T;
+  phase(h, K_COLL_PREP, [&](int s0, int ns) { dd::launch_coll_prep(d, s0, ns, st); });
+  phase(h, K_COLL_KSTEP, [&](int s0, int ns) { dd::launch_coll_kstep(d, s0, ns, st); });
+  // QR of K1; the last product writes U^1 = Q / h straight into the state
+  chol_qr3(h, 0, dd::DIM_R, d.K1, d.K2, sdNT, d.N, true, d.U, (int64_t)d.N * d.R, nullptr, 1.0 / d.h, K_GEMM_QR_K);
+  phase(h, K_COLL_REDUCE, [&](int s0, int ns) { dd::launch_coll_reduce(d, s0, ns, st); });
+  phase(h, K_COLL_SSTEP, [&](int s0, int ns) { dd::launch_coll_sstep(d, s0, ns, st); });
+  phase(h, K_COLL_LSTEP, [&](int s0, int ns) { dd::launch_coll_lstep(d, s0, ns, st); });
+  // weighted QR of L1; V^1 = Q / sqrt(w) straight into the state
+  chol_qr3(h, 0, dd::DIM_R, d.AL, d.AL2, sdMT, d.M, false, d.V, (int64_t)d.M * d.R, d.isw, 1.0, K_GEMM_QR_L);
+  phase(h, K_COLL_FINAL, [&](int s0, int ns) { dd::launch_coll_final(d, s0, ns, st); });
+}
+
+void enqueue_step(dd_dlra_handle h) {
+  enqueue_advection(h, 0);
+  enqueue_advection(h, 1);
+  enqueue_collision(h);
+}
+
+dd_status check_flags(dd_dlra_handle h) {
+  unsigned flags = 0;
+  HIPCHK(hipMemcpy(&flags, h->d.flags, sizeof(unsigned), hipMemcpyDeviceToHost));
+  if (flags & (dd::FLAG_NONFINITE | dd::FLAG_JACOBI_NOCONV)) {
+    h->err = "device reported:";
+    if (flags & dd::FLAG_NONFINITE) h->err += " non-finite factors;";
+    if (flags & dd::FLAG_JACOBI_NOCONV) h->err += " Jacobi did not converge;";
+    return DD_ENUMERIC;
+  }
+  if (flags & dd::FLAG_RANK_CLAMP) {
+    h->err = "a rank rule exceeded its capacity (strict_caps)";
+    return DD_ERANK;
+  }
+  return DD_OK;
+}
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+
+extern "C" {
+
+dd_status dd_dlra_workspace_size(const dd_dlra_config* cfg, size_t* bytes) {
+  std::string e = validate(cfg);
+  if (!e.empty()) {
+    g_err = e;
+    return DD_EINVAL;
+  }
+  if (!bytes) {
+    g_err = "bytes is NULL";
+    return DD_EINVAL;
+  }
+  *bytes = make_layout(cfg).bytes;
+  return DD_OK;
+}
+
+dd_status dd_dlra_create(const dd_dlra_config* cfg, const int32_t* rank0, const double* const* U0,
+                         const double* const* S0, const double* const* V0, void* d_workspace, size_t ws_bytes,
+                         void* hip_stream, dd_dlra_handle* out) {
+  if (!out) {
+    g_err = "out is NULL";
+    return DD_EINVAL;
+  }
+  *out = nullptr;
+  std::string e = validate(cfg);
+  if (!e.empty()) {
+    g_err = e;
+    return DD_EINVAL;
+  }
+  Layout L = make_layout(cfg);
+  e = check_factors(cfg, L, rank0, U0, S0, V0);
+  if (!e.empty()) {
+    g_err = e;
+    return DD_EINVAL;
+  }
+  if (d_workspace && ws_bytes < L.bytes) {
+    g_err = "workspace too small: need " + std::to_string(L.bytes) + " bytes";
+    return DD_EINVAL;
+  }
+  dd_dlra_handle h = new dd_dlra_s();
+  h->cfg = *cfg;
+  h->cfg.omega_x = h->cfg.omega_y = h->cfg.w = nullptr;
+  h->cfg.sigma_s = h->cfg.sigma_a = h->cfg.Q = nullptr;
+  auto fail = [&](dd_status st) {
+    g_err = h->err;
+    dd_dlra_destroy(h);
+    return st;
+  };
+  if (hip_stream) {
+    h->stream = (hipStream_t)hip_stream;
+  } else {
+    if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess) {
+      h->err = "hipStreamCreate failed";
+      return fail(DD_EHIP);
+    }
+    h->own_stream = true;
+  }
+  if (d_workspace) {
+    h->ws = d_workspace;
+    h->ws_bytes = ws_bytes;
+  } else {
+    if (hipMalloc(&h->ws, L.bytes) != hipSuccess) {
+      h->ws = nullptr;
+      h->err = "hipMalloc of " + std::to_string(L.bytes) + " bytes failed";
+      return fail(DD_ENOMEM);
+    }
+    h->own_ws = true;
+    h->ws_bytes = L.bytes;
+  }
+  fill_dev(h->d, L, cfg, (char*)h->ws);
+  Dev& d = h->d;
+  if (hipMemsetAsync(h->ws, 0, L.bytes, h->stream) != hipSuccess) {
+    h->err = "hipMemsetAsync failed";
+    return fail(DD_EHIP);
+  }
+  // directions
+  {
+    std::vector<double> in(5 * (size_t)d.M);
+    for (int q = 0; q < d.M; ++q) {
+      in[q] = cfg->omega_x[q];
+      in[d.M + q] = cfg->omega_y[q];
+      in[2 * d.M + q] = cfg->w[q];
+      in[3 * d.M + q] = sqrt(cfg->w[q]);
+      in[4 * d.M + q] = 1.0 / sqrt(cfg->w[q]);
+    }
+    if (hipMemcpyAsync(d.omx, in.data(), in.size() * 8, hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+        hipStreamSynchronize(h->stream) != hipSuccess) {
+      h->err = "upload of directions failed";
+      return fail(DD_EHIP);
+    }
+  }
+  // fields in subdomain-local order
+  {
+    std::vector<double> cs((size_t)d.nsub * d.N), ct(cs.size()), qq(cs.size());
+    for (int s = 0; s < d.nsub; ++s) {
+      const int sx = s % d.px, sy = s / d.px;
+      for (int iy = 0; iy < d.lny; ++iy)
+        for (int ix = 0; ix < d.lnx; ++ix) {
+          const size_t g = (size_t)(sy * d.lny + iy) * cfg->nx + sx * d.lnx + ix;
+          const size_t l = (size_t)s * d.N + iy * d.lnx + ix;
+          cs[l] = cfg->sigma_s[g];
+          ct[l] = cfg->sigma_s[g] + cfg->sigma_a[g];
+          qq[l] = cfg->Q[g];
+        }
+    }
+    if (hipMemcpyAsync(d.cs, cs.data(), cs.size() * 8, hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+        hipMemcpyAsync(d.ct, ct.data(), ct.size() * 8, hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+        hipMemcpyAsync(d.Qsrc, qq.data(), qq.size() * 8, hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+        hipStreamSynchronize(h->stream) != hipSuccess) {
+      h->err = "upload of fields failed";
+      return fail(DD_EHIP);
+    }
+  }
+  dd_status st = upload_factors(h, rank0, U0, S0, V0);
+  if (st != DD_OK) return fail(st);
+  *out = h;
+  return DD_OK;
+}
+
+dd_status dd_dlra_step(dd_dlra_handle h, int32_t n_steps) {
+  if (!h) return DD_EINVAL;
+  if (n_steps < 0) {
+    h->err = "n_steps must be >= 0";
+    return DD_EINVAL;
+  }
+  if (h->cfg.exec_mode == DD_EXEC_BATCHED_GRAPH) {
+    if (!h->gexec) {
+      HIPCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+      h->capturing = true;
+      enqueue_step(h);
+      h->capturing = false;
+      hipError_t ce = hipStreamEndCapture(h->stream, &h->graph);
+      if (ce != hipSuccess) {
+        h->err = std::string("hipStreamEndCapture: ") + hipGetErrorString(ce);
+        return DD_EHIP;
+      }
+      HIPCHK(hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0));
+    }
+    for (int i = 0; i < n_steps; ++i) HIPCHK(hipGraphLaunch(h->gexec, h->stream));
+  } else {
+    for (int i = 0; i < n_steps; ++i) enqueue_step(h);
+  }
+  HIPCHK(hipGetLastError());
+  return DD_OK;
+}
+
+dd_status dd_dlra_stage(dd_dlra_handle h, int32_t stage) {
+  if (!h) return DD_EINVAL;
+  if (stage < 0 || stage > 2) {
+    h->err = "stage must be 0, 1 or 2";
+    return DD_EINVAL;
+  }
+  if (stage < 2) enqueue_advection(h, stage);
+  else enqueue_collision(h);
+  HIPCHK(hipGetLastError());
+  return DD_OK;
+}
+
+dd_status dd_dlra_profile(dd_dlra_handle h, int32_t enable) {
+  if (!h) return DD_EINVAL;
+  h->profiling = enable != 0;
+  return DD_OK;
+}
+
+dd_status dd_dlra_kernel_stats(dd_dlra_handle h, int32_t n, int64_t* launches, double* total_ms, int32_t* n_kernels) {
+  if (!h) return DD_EINVAL;
+  HIPCHK(hipStreamSynchronize(h->stream));
+  if (h->k_ms.empty()) {
+    h->k_ms.assign(K_COUNT, 0.0);
+    h->k_launch.assign(K_COUNT, 0);
+  }
+  for (size_t i = 0; i < h->pending.size(); ++i) {
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, h->ev_pool[2 * i], h->ev_pool[2 * i + 1]));
+    h->k_ms[h->pending[i].first] += ms;
+    h->k_launch[h->pending[i].first] += h->pending[i].second;
+  }
+  h->pending.clear();
+  h->ev_used = 0;
+  if (n_kernels) *n_kernels = K_COUNT;
+  for (int k = 0; k < n && k < K_COUNT; ++k) {
+    if (launches) launches[k] = h->k_launch[k];
+    if (total_ms) total_ms[k] = h->k_ms[k];
+  }
+  return DD_OK;
+}
+
+const char* dd_dlra_kernel_name(int32_t k) {
+  if (k < 0 || k >= K_COUNT) return nullptr;
+  return kKindName[k];
+}
+
+dd_status dd_dlra_sync(dd_dlra_handle h) {
+  if (!h) return DD_EINVAL;
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return check_flags(h);
+}
+
+dd_status dd_dlra_get_ranks(dd_dlra_handle h, int32_t* r, int32_t* t_max, int64_t* clamp_events) {
+  if (!h) return DD_EINVAL;
+  HIPCHK(hipStreamSynchronize(h->stream));
+  const int ns = h->d.nsub;
+  std::vector<int> buf(ns);
+  if (r) {
+    HIPCHK(hipMemcpy(buf.data(), h->d.rank, ns * sizeof(int), hipMemcpyDeviceToHost));
+    for (int s = 0; s < ns; ++s) r[s] = buf[s];
+  }
+  if (t_max) {
+    HIPCHK(hipMemcpy(buf.data(), h->d.tmax, ns * sizeof(int), hipMemcpyDeviceToHost));
+    for (int s = 0; s < ns; ++s) t_max[s] = buf[s];
+  }
+  if (clamp_events) {
+    unsigned long long c = 0;
+    HIPCHK(hipMemcpy(&c, h->d.clamps, sizeof(c), hipMemcpyDeviceToHost));
+    *clamp_events = (int64_t)c;
+  }
+  return check_flags(h);
+}
+
+dd_status dd_dlra_get_factors(dd_dlra_handle h, int32_t sd, int32_t cap, int32_t* r, double* U, double* S, double* V) {
+  if (!h) return DD_EINVAL;
+  const Dev& d = h->d;
+  if (sd < 0 || sd >= d.nsub || !r) {
+    h->err = "bad subdomain index or NULL r";
+    return DD_EINVAL;
+  }
+  HIPCHK(hipStreamSynchronize(h->stream));
+  int rr = 0;
+  HIPCHK(hipMemcpy(&rr, d.rank + sd, sizeof(int), hipMemcpyDeviceToHost));
+  *r = rr;
+  if (cap < rr) {
+    h->err = "cap smaller than the rank";
+    return DD_EINVAL;
+  }
+  if (U) HIPCHK(hipMemcpy(U, d.U + (size_t)sd * d.N * d.R, (size_t)d.N * rr * 8, hipMemcpyDeviceToHost));
+  if (V) HIPCHK(hipMemcpy(V, d.V + (size_t)sd * d.M * d.R, (size_t)d.M * rr * 8, hipMemcpyDeviceToHost));
+  if (S) {
+    std::vector<double> buf((size_t)d.R * d.R);
+    HIPCHK(hipMemcpy(buf.data(), d.S + (size_t)sd * d.R * d.R, buf.size() * 8, hipMemcpyDeviceToHost));
+    for (int j = 0; j < rr; ++j)
+      for (int i = 0; i < rr; ++i) S[i + (size_t)j * rr] = buf[i + (size_t)j * d.R];
+  }
+  return check_flags(h);
+}
+
+dd_status dd_dlra_moments(dd_dlra_handle h, double* rho, int32_t dst_is_device) {
+  if (!h || !rho) return DD_EINVAL;
+  const Dev& d = h->d;
+  dd::launch_moments(d, h->stream);
+  const size_t n = (size_t)h->cfg.nx * h->cfg.ny;
+  if (dst_is_device) {
+    HIPCHK(hipMemcpyAsync(rho, d.rho, n * 8, hipMemcpyDeviceToDevice, h->stream));
+    return DD_OK;
+  }
+  HIPCHK(hipMemcpyAsync(rho, d.rho, n * 8, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return check_flags(h);
+}
+
+dd_status dd_dlra_set_factors(dd_dlra_handle h, const int32_t* rank, const double* const* U, const double* const* S,
+                              const double* const* V) {
+  if (!h) return DD_EINVAL;
+  dd_dlra_config c = h->cfg;
+  Layout L;
+  L.R = h->d.R;
+  L.N = h->d.N;
+  L.M = h->d.M;
+  L.nsub = h->d.nsub;
+  // orthonormality check needs the weights: read them back from the device
+  std::vector<double> w(h->d.M);
+  HIPCHK(hipStreamSynchronize(h->stream));
+  HIPCHK(hipMemcpy(w.data(), h->d.w, w.size() * 8, hipMemcpyDeviceToHost));
+  c.w = w.data();
+  std::string e = check_factors(&c, L, rank, U, S, V);
+  if (!e.empty()) {
+    h->err = e;
+    return DD_EINVAL;
+  }
+  return upload_factors(h, rank, U, S, V);
+}
+
+dd_status dd_dlra_force_ranks(dd_dlra_handle h, const int32_t* t, const int32_t* r_out) {
+  if (!h) return DD_EINVAL;
+  const int ns = h->d.nsub;
+  std::vector<int> f(4 * ns, -1);
+  for (int i = 0; i < 2 * ns; ++i) {
+    if (t) f[i] = t[i];
+    if (r_out) f[2 * ns + i] = r_out[i];
+  }
+  HIPCHK(hipStreamSynchronize(h->stream));
+  HIPCHK(hipMemcpy(h->d.force, f.data(), f.size() * sizeof(int), hipMemcpyHostToDevice));
+  h->d.forced = (t || r_out) ? 1 : 0;
+  // a captured graph holds the old kernel arguments
+  if (h->gexec) {
+    (void)hipGraphExecDestroy(h->gexec);
+    h->gexec = nullptr;
+  }
+  if (h->graph) {
+    (void)hipGraphDestroy(h->graph);
+    h->graph = nullptr;
+  }
+  return DD_OK;
+}
+
+dd_status dd_dlra_destroy(dd_dlra_handle h) {
+  if (!h) return DD_OK;
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+  if (h->graph) (void)hipGraphDestroy(h->graph);
+  for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+  if (h->own_ws && h->ws) (void)hipFree(h->ws);
+  if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+  delete h;
+  return DD_OK;
+}
+
+const char* dd_dlra_last_error(dd_dlra_handle h) {
+  if (!h) return g_err.c_str();
+  return h->err.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,206 @@
+// Internal definitions shared by the HIP translation units of the DD-DLRA
+// engine.  Nothing here is part of the public C ABI (include/dd_dlra.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dd {
+
+constexpr int NTHR = 256;        // threads per workgroup (4 wavefronts of 64)
+constexpr int TILE = 64;         // rows per tall-skinny tile
+constexpr int LDT = TILE + 1;    // padded leading dimension of LDS tiles
+constexpr int CAP = 64;          // largest T (intermediate rank) and MA (= r + r_lo + r_hi)
+constexpr int GPAIRS = (CAP * (CAP + 1) / 2 + NTHR - 1) / NTHR;  // Gram pairs per thread
+
+// error bits latched in Dev::flags
+enum : unsigned {
+  FLAG_NONFINITE = 1u,
+  FLAG_JACOBI_NOCONV = 4u,
+  FLAG_RANK_CLAMP = 8u,
+};
+
+// which per-subdomain dimension a generic kernel uses
+enum Dim : int { DIM_M0 = 0, DIM_T = 1, DIM_R = 2, DIM_RNEW = 3 };
+
+// Everything a kernel needs, passed by value.  Pointers are device memory.
+struct Dev {
+  // geometry and physics
+  int px, py, lnx, lny, N, M, nsub;
+  double h, dt, c, W;
+  // capacities and launch shapes
+  int R, T, MA;
+  int ntN, ntM;            // tiles over cells / over directions
+  int nwgN, nwgM;          // workgroups per subdomain for cell / direction kernels
+  int gpTile;              // doubles per workgroup partial
+  int64_t gpStride;        // doubles of partials per subdomain
+  int64_t smallStride;     // doubles of small workspace per subdomain
+  // rank rules
+  int rank_mode, r_fixed, r_min, r_max, r_int_max, strict;
+  double tol, tol_aug_rel;
+  // state
+  double* U;               // [nsub][R][N]
+  double* V;               // [nsub][R][M]
+  double* S;               // [nsub][R][R]
+  int* rank;               // [nsub]
+  int* tdim;               // [nsub] intermediate rank of the current stage
+  int* rnew;               // [nsub] rank after truncation
+  int* tmax;               // [nsub] largest t seen
+  int* force;              // [2*nsub] t per advection stage, [2*nsub] r' ; -1 = rule
+  int forced;
+  unsigned* flags;         // [1]
+  unsigned long long* clamps;  // [1]
+  // scratch
+  double* A;               // [nsub][MA][M]   weighted augmentation matrix
+  double* Z;               // [nsub][MA][M]
+  double* Qh;              // [nsub][T][M]    sqrt(w) * V-hat
+  double* Qh2;             // [nsub][T][M]
+  double* K1;              // [nsub][T][N]
+  double* K2;              // [nsub][T][N]
+  double* AL;              // [nsub][T][M]
+  double* AL2;             // [nsub][T][M]
+  double* gpart;           // [nsub][gpStride]
+  double* small;           // [nsub][smallStride]
+  double* rho;             // [ny*nx]
+  // inputs
+  double* omx;             // [M]
+  double* omy;             // [M]
+  double* w;               // [M]
+  double* sw;              // [M] sqrt(w)
+  double* isw;             // [M] 1/sqrt(w)
+  double* cs;              // [nsub][N] sigma_s in local order
+  double* ct;              // [nsub][N] sigma_s + sigma_a
+  double* Qsrc;            // [nsub][N]
+  int nx;                  // global cells along x (moments)
+  // small workspace offsets (doubles)
+  int oY1, oCoef, oFill, oRinv, oRacc, oCp, oCn, oAm, oM0, oMm, oMp, oGLo, oGHi, oGLoN, oGHiN;
+  int oEp, oEn, oOlo, oOhi, oTm, oGm, oGp, oBKlo, oBKhi, oS1, oS2, oP0, oPm, oPp, oBu, oBv;
+  int oSig, oMv, oCrow, oGs, oGt, oQv, oW1, oW2, oW3, oW4, oW5, oW6;
+};
+
+__host__ __device__ inline int neighbour(const Dev& d, int s, int axis, int side) {
+  int sx = s % d.px, sy = s / d.px;
+  if (axis == 0) {
+    sx += side;
+    if (sx < 0 || sx >= d.px) return -1;
+  } else {
+    sy += side;
+    if (sy < 0 || sy >= d.py) return -1;
+  }
+  return sy * d.px + sx;
+}
+
+// local cell index of face entry f on a subdomain face
+__device__ inline int face_cell(const Dev& d, int axis, bool high, int f) {
+  if (axis == 0) return f * d.lnx + (high ? d.lnx - 1 : 0);
+  return (high ? d.lny - 1 : 0) * d.lnx + f;
+}
+
+__device__ inline int face_len(const Dev& d, int axis) { return axis == 0 ? d.lny : d.lnx; }
+
+__device__ inline int m0_of(const Dev& d, int s, int axis) {
+  int lo = neighbour(d, s, axis, -1), hi = neighbour(d, s, axis, +1);
+  return d.rank[s] + (lo >= 0 ? d.rank[lo] : 0) + (hi >= 0 ? d.rank[hi] : 0);
+}
+
+__device__ inline int dim_of(const Dev& d, int s, int axis, int which) {
+  switch (which) {
+    case DIM_M0: return m0_of(d, s, axis);
+    case DIM_T: return d.tdim[s];
+    case DIM_R: return d.rank[s];
+    default: return d.rnew[s];
+  }
+}
+
+__device__ inline double* small_of(const Dev& d, int s) { return d.small + (int64_t)s * d.smallStride; }
+__device__ inline double* gpart_of(const Dev& d, int s) { return d.gpart + (int64_t)s * d.gpStride; }
+
+// (i, j) with i <= j from the packed upper-triangle index k = j(j+1)/2 + i
+__device__ inline void unpack_pair(int k, int& i, int& j) {
+  int jj = (int)((sqrt(8.0 * k + 1.0) - 1.0) * 0.5);
+  while (jj * (jj + 1) / 2 > k) --jj;
+  while ((jj + 1) * (jj + 2) / 2 <= k) ++jj;
+  j = jj;
+  i = k - jj * (jj + 1) / 2;
+}
+
+// Gram accumulator: each thread owns up to GPAIRS entries (i <= j) of an
+// n x n Gram matrix and sums rows of LDS tiles into them.
+struct GramAcc {
+  double a[GPAIRS];
+  __device__ void zero() {
+#pragma unroll
+    for (int m = 0; m < GPAIRS; ++m) a[m] = 0.0;
+  }
+  // buf: column-major tile with leading dimension ld, nrows valid rows
+  __device__ void add(const double* buf, int ld, int nrows, int n) {
+    const int npair = n * (n + 1) / 2;
+#pragma unroll
+    for (int m = 0; m < GPAIRS; ++m) {
+      int k = threadIdx.x + m * NTHR;
+      if (k < npair) {
+        int i, j;
+        unpack_pair(k, i, j);
+        const double* ci = buf + i * ld;
+        const double* cj = buf + j * ld;
+        double s = 0.0;
+        for (int r = 0; r < nrows; ++r) s = fma(ci[r], cj[r], s);
+        a[m] += s;
+      }
+    }
+  }
+  // full symmetric n x n into out (leading dimension n)
+  __device__ void store(double* out, int n) const {
+    const int npair = n * (n + 1) / 2;
+#pragma unroll
+    for (int m = 0; m < GPAIRS; ++m) {
+      int k = threadIdx.x + m * NTHR;
+      if (k < npair) {
+        int i, j;
+        unpack_pair(k, i, j);
+        out[i + j * n] = a[m];
+        out[j + i * n] = a[m];
+      }
+    }
+  }
+};
+
+// deterministic pseudo-random value in [-1, 1) (splitmix64 finaliser)
+__device__ inline double hash_unit(uint64_t x) {
+  x += 0x9e3779b97f4a7c15ull;
+  x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
+  x = (x ^ (x >> 27)) * 0x94d049bb133111ebull;
+  x ^= x >> 31;
+  return (double)(x >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
+}  // namespace dd
+
+// Launchers (host functions) implemented in the kernel translation units.
+namespace dd {
+// tall-skinny kernels
+void launch_aug_form(const Dev& d, int axis, int sd0, int nsd, hipStream_t st);
+void launch_gemm(const Dev& d, int axis, int sd0, int nsd, const double* X, int64_t xsd, int rows,
+                 int kdim, int ndim, int boff, int bld, double* Y, int64_t ysd, const double* rowscale,
+                 bool gram, int fill_off, bool rows_are_cells, hipStream_t st);
+void launch_ang_reduce(const Dev& d, int axis, int sd0, int nsd, hipStream_t st);
+void launch_kstep(const Dev& d, int axis, int sd0, int nsd, hipStream_t st);
+void launch_spatial_reduce(const Dev& d, int axis, int sd0, int nsd, const double* Q, hipStream_t st);
+void launch_lstep(const Dev& d, int axis, int sd0, int nsd, hipStream_t st);
+void launch_coll_kstep(const Dev& d, int sd0, int nsd, hipStream_t st);
+void launch_coll_reduce(const Dev& d, int sd0, int nsd, hipStream_t st);
+void launch_coll_lstep(const Dev& d, int sd0, int nsd, hipStream_t st);
+void launch_moments(const Dev& d, hipStream_t st);
+// small (one workgroup per subdomain) kernels
+void launch_aug_eig1(const Dev& d, int axis, int sd0, int nsd, hipStream_t st);
+void launch_aug_eig2(const Dev& d, int axis, int sd0, int nsd, hipStream_t st);
+void launch_chol(const Dev& d, int axis, int sd0, int nsd, int ndim, int rows, int ngp, bool shift,
+                 int acc_mode, double bscale, hipStream_t st);
+void launch_adv_prep(const Dev& d, int axis, int sd0, int nsd, hipStream_t st);
+void launch_adv_sstep(const Dev& d, int axis, int sd0, int nsd, const double* Q, hipStream_t st);
+void launch_trunc(const Dev& d, int axis, int sd0, int nsd, hipStream_t st);
+void launch_set_rank(const Dev& d, int sd0, int nsd, hipStream_t st);
+void launch_coll_prep(const Dev& d, int sd0, int nsd, hipStream_t st);
+void launch_coll_sstep(const Dev& d, int sd0, int nsd, hipStream_t st);
+void launch_coll_final(const Dev& d, int sd0, int nsd, hipStream_t st);
+}  // namespace dd

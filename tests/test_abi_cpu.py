@@ -1,0 +1,131 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every symbol the header declares, and rejects bad configurations before any
+device call."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as wk
+import paper_2602_14854_amd as pkg
+from paper_2602_14854_amd import _native as nat
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dd_dlra.h")
+
+needs_lib = pytest.mark.skipif(not os.path.exists(pkg.library_path()), reason="HIP library not built")
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(dd_dlra_[a-z_]+)\s*\(", txt)))
+
+
+def test_header_and_binding_agree():
+    assert declared_functions() == sorted(nat.EXPORTS)
+
+
+@needs_lib
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(pkg.library_path())
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_config_struct_layout_matches_header(tmp_path):
+    """Compile a host-only C probe against the header and compare the size
+    and field offsets of dd_dlra_config with the ctypes mirror."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    fields = [f[0] for f in nat.Config._fields_]
+    src = tmp_path / "probe.c"
+    body = "\n".join(f'  printf("%s %zu\\n", "{f}", offsetof(dd_dlra_config, {f}));' for f in fields)
+    src.write_text("#include <stdio.h>\n#include <stddef.h>\n#include \"dd_dlra.h\"\nint main(void){\n"
+                   f'  printf("sizeof %zu\\n", sizeof(dd_dlra_config));\n{body}\n  return 0;\n}}\n')
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = dict(line.split() for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                      check=True).stdout.splitlines())
+    assert int(out["sizeof"]) == ctypes.sizeof(nat.Config)
+    for f in fields:
+        assert int(out[f]) == getattr(nat.Config, f).offset, f
+
+
+def _cfg(**over):
+    wl = wk.make_workload("wc-C1")
+    for k, v in over.items():
+        setattr(wl, k, v)
+    return wl
+
+
+@needs_lib
+def test_workspace_size_scales_with_problem():
+    dirs = wk.product_directions(4, 4)
+    a = pkg.workspace_size(wk.make_custom(8, 8, 2, 2, dirs, [3] * 4))
+    b = pkg.workspace_size(wk.make_custom(16, 16, 2, 2, dirs, [3] * 4))
+    c = pkg.workspace_size(wk.make_custom(16, 16, 4, 4, dirs, [3] * 16))
+    assert 0 < a < b < c
+
+
+@needs_lib
+@pytest.mark.parametrize("over,needle", [
+    (dict(nx=33), "divisible"),
+    (dict(x1=5.0), "square"),
+    (dict(dt=0.0), "dt"),
+    (dict(r_int_max=3), "r_int_max"),
+    (dict(r_int_max=80), "64"),
+    (dict(r_fixed=30, r_int_max=60), "21"),
+    (dict(rank_mode=7), "rank_mode"),
+])
+def test_invalid_configs_rejected(over, needle):
+    with pytest.raises(nat.DDError) as ei:
+        pkg.workspace_size(_cfg(**over))
+    assert ei.value.status == nat.DD_EINVAL
+    assert needle in str(ei.value)
+
+
+@needs_lib
+def test_negative_cross_section_rejected():
+    wl = _cfg()
+    wl.sigma_s = wl.sigma_s.copy()
+    wl.sigma_s[3] = -1.0
+    with pytest.raises(nat.DDError) as ei:
+        pkg.workspace_size(wl)
+    assert "non-negative" in str(ei.value)
+
+
+@needs_lib
+def test_nonorthonormal_factors_rejected_before_device_use():
+    wl = _cfg()
+    wl.U0 = [2.0 * u for u in wl.U0]
+    with pytest.raises(nat.DDError) as ei:
+        pkg.DDDLRA(wl)
+    assert ei.value.status == nat.DD_EINVAL and "orthonormal" in str(ei.value)
+
+
+@needs_lib
+def test_nan_factors_rejected_before_device_use():
+    wl = _cfg()
+    S = [s.copy() for s in wl.S0]
+    S[1][0, 0] = np.nan
+    wl.S0 = S
+    with pytest.raises(nat.DDError) as ei:
+        pkg.DDDLRA(wl)
+    assert "non-finite" in str(ei.value)
+
+
+@needs_lib
+def test_rank_above_capacity_rejected():
+    wl = _cfg()
+    rng = np.random.default_rng(0)
+    u, s, v = wk.random_factors(wl.N, wl.M, 6, wl.h, wl.w, rng)
+    wl.U0 = [u] + wl.U0[1:]
+    wl.S0 = [s] + wl.S0[1:]
+    wl.V0 = [v] + wl.V0[1:]
+    with pytest.raises(nat.DDError) as ei:
+        pkg.DDDLRA(wl)
+    assert "capacity" in str(ei.value)
