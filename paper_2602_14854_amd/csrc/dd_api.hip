@@ -541,6 +541,11 @@ dd_status dd_dlra_create(const dd_dlra_config* cfg, const int32_t* rank0, const 
     g_err = "workspace too small: need " + std::to_string(L.bytes) + " bytes";
     return DD_EINVAL;
   }
+  static bool kernels_ready = false;
+  if (!kernels_ready) {
+    dd::init_kernels();
+    kernels_ready = true;
+  }
   dd_dlra_handle h = new dd_dlra_s();
   h->cfg = *cfg;
   h->cfg.omega_x = h->cfg.omega_y = h->cfg.w = nullptr;

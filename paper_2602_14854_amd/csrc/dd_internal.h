@@ -179,6 +179,7 @@ __device__ inline double hash_unit(uint64_t x) {
 // Launchers (host functions) implemented in the kernel translation units.
 namespace dd {
 // tall-skinny kernels
+void init_kernels();
 void launch_aug_form(const Dev& d, int axis, int sd0, int nsd, hipStream_t st);
 void launch_gemm(const Dev& d, int axis, int sd0, int nsd, const double* X, int64_t xsd, int rows,
                  int kdim, int ndim, int boff, int bld, double* Y, int64_t ysd, const double* rowscale,

@@ -4,245 +4,11 @@
 // a fixed order, run the serial linear algebra (two-sided Jacobi
 // eigensolver, Cholesky, triangular inverse) and form the coefficient
 // matrices of the next tall-skinny pass.
-#include "dd_internal.h"
+#include "dd_dense.h"
 
 namespace dd {
 
-constexpr int LDA = CAP + 1;        // padded leading dimension of LDS matrices
 constexpr int CAPR = 21;
-constexpr double U_ROUND = 1.1102230246251565e-16;  // 2^-53
-
-// ---------------------------------------------------------------- helpers
-
-// C (m x n) = alpha * op(A) op(B) (+ beta C); generic pointers, no aliasing.
-__device__ void mm(double* C, int ldc, const double* A, int lda, bool ta, const double* B, int ldb,
-                   bool tb, int m, int n, int k, double alpha, double beta) {
-  for (int idx = threadIdx.x; idx < m * n; idx += NTHR) {
-    const int i = idx % m, j = idx / m;
-    double acc = 0.0;
-    for (int l = 0; l < k; ++l) {
-      const double a = ta ? A[l + i * lda] : A[i + l * lda];
-      const double b = tb ? B[j + l * ldb] : B[l + j * ldb];
-      acc = fma(a, b, acc);
-    }
-    C[i + j * ldc] = (beta == 0.0) ? alpha * acc : alpha * acc + beta * C[i + j * ldc];
-  }
-  __syncthreads();
-}
-
-// dst (rows x cols, ldd) = sum over ngp workgroup partials of the block at
-// offset off (leading dimension lds) -- fixed order, deterministic.
-__device__ void sum_partials(const Dev& d, int s, int ngp, int off, int lds, int rows, int cols, double* dst,
-                             int ldd, double scale) {
-  const double* gp = gpart_of(d, s);
-  for (int idx = threadIdx.x; idx < rows * cols; idx += NTHR) {
-    const int i = idx % rows, j = idx / rows;
-    double acc = 0.0;
-    for (int w = 0; w < ngp; ++w) acc += gp[(int64_t)w * d.gpTile + off + i + j * lds];
-    dst[i + j * ldd] = scale * acc;
-  }
-  __syncthreads();
-}
-
-// Cyclic two-sided Jacobi on the symmetric n x n matrix A (LDS, ld LDA),
-// parallel over disjoint pairs with the round-robin ordering.  On exit the
-// diagonal of A holds the eigenvalues and Y (ld LDA) the eigenvectors.
-// rel = true: a rotation is skipped when |a_pq| <= 1e-15 sqrt(|a_pp a_qq|),
-// which gives eigenvalues of positive definite graded matrices to high
-// relative accuracy; rel = false uses 1e-15 ||A||_F.
-__device__ void jacobi_eig(const Dev& d, double* A, double* Y, int n, bool rel) {
-  __shared__ double cs[CAP];
-  __shared__ int pq[CAP];
-  __shared__ int rotated;
-  __shared__ double fro;
-  for (int idx = threadIdx.x; idx < n * n; idx += NTHR) {
-    const int i = idx % n, j = idx / n;
-    Y[i + j * LDA] = (i == j) ? 1.0 : 0.0;
-  }
-  if (threadIdx.x == 0) {
-    double f = 0.0;
-    for (int j = 0; j < n; ++j)
-      for (int i = 0; i < n; ++i) f += A[i + j * LDA] * A[i + j * LDA];
-    fro = sqrt(f);
-  }
-  __syncthreads();
-  if (n <= 1) return;
-  const int n2 = n + (n & 1);
-  const int npair = n2 / 2;
-  const double atol = 1e-15 * fro;
-  bool converged = false;
-  for (int sweep = 0; sweep < 60; ++sweep) {
-    if (threadIdx.x == 0) rotated = 0;
-    __syncthreads();
-    for (int round = 0; round < n2 - 1; ++round) {
-      if (threadIdx.x < npair) {
-        const int k = threadIdx.x;
-        const int pa = k, pb = n2 - 1 - k;
-        const int a = pa == 0 ? 0 : ((pa - 1 + round) % (n2 - 1)) + 1;
-        const int b = ((pb - 1 + round) % (n2 - 1)) + 1;
-        const int p = a < b ? a : b, q = a < b ? b : a;
-        double c = 1.0, sn = 0.0;
-        if (q < n) {
-          const double app = A[p + p * LDA], aqq = A[q + q * LDA], apq = A[p + q * LDA];
-          const double thr = rel ? 1e-15 * sqrt(fabs(app * aqq)) : atol;
-          if (fabs(apq) > thr && apq != 0.0) {
-            const double tau = (aqq - app) / (2.0 * apq);
-            const double at = fabs(tau);
-            const double tt = (at > 1e150) ? 0.5 / tau : copysign(1.0, tau) / (at + sqrt(1.0 + at * at));
-            c = 1.0 / sqrt(1.0 + tt * tt);
-            sn = tt * c;
-            rotated = 1;
-          }
-        }
-        cs[2 * k] = c;
-        cs[2 * k + 1] = sn;
-        pq[2 * k] = p;
-        pq[2 * k + 1] = q;
-      }
-      __syncthreads();
-      for (int idx = threadIdx.x; idx < npair * n; idx += NTHR) {
-        const int k = idx / n, j = idx % n;
-        const double sn = cs[2 * k + 1];
-        if (sn == 0.0) continue;
-        const double c = cs[2 * k];
-        const int p = pq[2 * k], q = pq[2 * k + 1];
-        const double ap = A[p + j * LDA], aq = A[q + j * LDA];
-        A[p + j * LDA] = c * ap - sn * aq;
-        A[q + j * LDA] = sn * ap + c * aq;
-      }
-      __syncthreads();
-      for (int idx = threadIdx.x; idx < npair * n; idx += NTHR) {
-        const int k = idx / n, i = idx % n;
-        const double sn = cs[2 * k + 1];
-        if (sn == 0.0) continue;
-        const double c = cs[2 * k];
-        const int p = pq[2 * k], q = pq[2 * k + 1];
-        const double ap = A[i + p * LDA], aq = A[i + q * LDA];
-        A[i + p * LDA] = c * ap - sn * aq;
-        A[i + q * LDA] = sn * ap + c * aq;
-        const double yp = Y[i + p * LDA], yq = Y[i + q * LDA];
-        Y[i + p * LDA] = c * yp - sn * yq;
-        Y[i + q * LDA] = sn * yp + c * yq;
-      }
-      __syncthreads();
-      if (threadIdx.x < npair && cs[2 * threadIdx.x + 1] != 0.0) {
-        const int p = pq[2 * threadIdx.x], q = pq[2 * threadIdx.x + 1];
-        A[p + q * LDA] = 0.0;
-        A[q + p * LDA] = 0.0;
-      }
-      __syncthreads();
-    }
-    const int any = rotated;
-    __syncthreads();
-    if (!any) {
-      converged = true;
-      break;
-    }
-  }
-  if (!converged && threadIdx.x == 0) atomicOr(d.flags, FLAG_JACOBI_NOCONV);
-  __syncthreads();
-}
-
-// descending order of the diagonal of A: perm[j] = index of the j-th largest
-__device__ void sort_desc(const double* A, int n, int* perm) {
-  if (threadIdx.x == 0) {
-    for (int j = 0; j < n; ++j) perm[j] = j;
-    for (int j = 0; j < n; ++j) {
-      int best = j;
-      for (int k = j + 1; k < n; ++k)
-        if (A[perm[k] + perm[k] * LDA] > A[perm[best] + perm[best] * LDA]) best = k;
-      const int tmp = perm[j];
-      perm[j] = perm[best];
-      perm[best] = tmp;
-    }
-  }
-  __syncthreads();
-}
-
-// In-place upper Cholesky of the n x n matrix G (LDS, ld LDA): G = R^T R.
-// A pivot that is not larger than 1e-20 times the column's own diagonal
-// entry means the column is numerically dependent on the earlier ones (the
-// matrix being factored is rank-deficient).  Such a pivot is set to 1 so the
-// factorisation continues as if the column were a fresh unit direction, and
-// dep[k] is set: the caller replaces that column by a pseudo-random vector
-// and zeroes the row in the accumulated R, which keeps A = Q R exact up to
-// the dependent column's residual.  A non-finite pivot latches
-// FLAG_NONFINITE.
-__device__ void chol_upper(const Dev& d, double* G, int n, int* dep) {
-  __shared__ double diag0[CAP];
-  for (int i = threadIdx.x; i < n; i += NTHR) {
-    diag0[i] = G[i + i * LDA];
-    dep[i] = 0;
-  }
-  __syncthreads();
-  for (int k = 0; k < n; ++k) {
-    if (threadIdx.x == 0) {
-      double dk = G[k + k * LDA];
-      if (!isfinite(dk)) {
-        atomicOr(d.flags, FLAG_NONFINITE);
-        dk = 1.0;
-        dep[k] = 1;
-      } else if (!(dk > 1e-20 * diag0[k])) {
-        dk = 1.0;
-        dep[k] = 1;
-      }
-      G[k + k * LDA] = sqrt(dk);
-    }
-    __syncthreads();
-    const double rkk = G[k + k * LDA];
-    for (int j = k + 1 + threadIdx.x; j < n; j += NTHR) G[k + j * LDA] /= rkk;
-    for (int i = k + 1 + threadIdx.x; i < n; i += NTHR) G[i + k * LDA] = 0.0;
-    __syncthreads();
-    const int m = n - k - 1;
-    for (int idx = threadIdx.x; idx < m * m; idx += NTHR) {
-      const int i = k + 1 + idx % m, j = k + 1 + idx / m;
-      if (i <= j) G[i + j * LDA] -= G[k + i * LDA] * G[k + j * LDA];
-    }
-    __syncthreads();
-  }
-}
-
-// X = R^{-1} for upper triangular R (both LDS, ld LDA)
-__device__ void tri_inv_upper(const double* R, double* X, int n) {
-  for (int j = threadIdx.x; j < n; j += NTHR) {
-    for (int i = n - 1; i > j; --i) X[i + j * LDA] = 0.0;
-    X[j + j * LDA] = 1.0 / R[j + j * LDA];
-    for (int i = j - 1; i >= 0; --i) {
-      double acc = 0.0;
-      for (int k = i + 1; k <= j; ++k) acc = fma(R[i + k * LDA], X[k + j * LDA], acc);
-      X[i + j * LDA] = -acc / R[i + i * LDA];
-    }
-  }
-  __syncthreads();
-}
-
-// smallest k with (sum_{j >= k} sig_j^2)^(1/2) <= tol (Algorithms 4, 5)
-__device__ int tail_rank(const double* sig, int n, double tol) {
-  double tail2 = 0.0;
-  int k = n;
-  for (int j = n - 1; j >= 0; --j) {
-    tail2 += sig[j] * sig[j];
-    if (sqrt(tail2) <= tol) k = j;
-    else break;
-  }
-  return k;
-}
-
-__device__ void copy_to_lds(double* dst, const double* src, int lds, int rows, int cols) {
-  for (int idx = threadIdx.x; idx < rows * cols; idx += NTHR) {
-    const int i = idx % rows, j = idx / rows;
-    dst[i + j * LDA] = src[i + j * lds];
-  }
-  __syncthreads();
-}
-
-__device__ void copy_from_lds(double* dst, int ldd, const double* src, int rows, int cols, double scale) {
-  for (int idx = threadIdx.x; idx < rows * cols; idx += NTHR) {
-    const int i = idx % rows, j = idx / rows;
-    dst[i + j * ldd] = scale * src[i + j * LDA];
-  }
-  __syncthreads();
-}
 
 // ---------------------------------------------------------------- augmentation
 
@@ -254,7 +20,9 @@ __global__ __launch_bounds__(NTHR) void s_aug_eig1(Dev d, int axis, int sd0) {
   __shared__ double G[LDA * CAP];
   __shared__ double Y[LDA * CAP];
   sum_partials(d, s, d.nwgM, 0, m0, m0, m0, G, LDA, 1.0);
-  jacobi_eig(d, G, Y, m0, true);
+  // a loose pass suffices: it only has to make the columns of Z = A Y1
+  // nearly orthogonal; the second pass resolves the small singular values
+  jacobi_1s(d, G, m0, m0, Y, 1e-8, 1e-14, 40);
   copy_from_lds(small_of(d, s) + d.oY1, d.MA, Y, m0, m0, 1.0);
 }
 
@@ -272,12 +40,17 @@ __global__ __launch_bounds__(NTHR) void s_aug_eig2(Dev d, int axis, int sd0) {
   __shared__ double G[LDA * CAP];
   __shared__ double Y[LDA * CAP];
   __shared__ double sig[CAP];
+  __shared__ double lam[CAP];
   __shared__ int perm[CAP];
   __shared__ int tsh;
   sum_partials(d, s, d.nwgM, 0, m0, m0, m0, G, LDA, 1.0);
-  jacobi_eig(d, G, Y, m0, true);
-  sort_desc(G, m0, perm);
-  for (int j = threadIdx.x; j < m0; j += NTHR) sig[j] = sqrt(fmax(G[perm[j] + perm[j] * LDA], 0.0));
+  // G2 is nearly diagonal: the eigenvalues are the column norms of G2 Y2;
+  // its entries scale like sigma_i sigma_j, so the noise floor of a null
+  // direction is (u sigma_1)^2
+  jacobi_1s(d, G, m0, m0, Y, 1e-15, 1e-28, 40);
+  col_norms(G, m0, m0, lam);
+  sort_desc(lam, m0, perm);
+  for (int j = threadIdx.x; j < m0; j += NTHR) sig[j] = sqrt(fmax(lam[perm[j]], 0.0));
   __syncthreads();
   if (threadIdx.x == 0) {
     int t;
@@ -332,12 +105,11 @@ __global__ __launch_bounds__(NTHR) void s_chol(Dev d, int axis, int sd0, int ndi
   __shared__ int dep[CAP];
   sum_partials(d, s, ngp, 0, n, n, n, G, LDA, 1.0);
   if (shift) {
-    if (threadIdx.x == 0) {
-      double tr = 0.0;
-      for (int i = 0; i < n; ++i) tr += G[i + i * LDA];
-      const double sh = 11.0 * ((double)rows * n + (double)n * (n + 1)) * U_ROUND * tr;
-      for (int i = 0; i < n; ++i) G[i + i * LDA] += sh;
-    }
+    __shared__ double red[NTHR];
+    double part = 0.0;
+    for (int i = threadIdx.x; i < n; i += NTHR) part += G[i + i * LDA];
+    const double sh = 11.0 * ((double)rows * n + (double)n * (n + 1)) * U_ROUND * block_sum(part, red);
+    for (int i = threadIdx.x; i < n; i += NTHR) G[i + i * LDA] += sh;
     __syncthreads();
   }
   chol_upper(d, G, n, dep);
@@ -408,8 +180,20 @@ __global__ __launch_bounds__(NTHR) void s_adv_prep(Dev d, int axis, int sd0) {
     }
   }
   __syncthreads();
-  jacobi_eig(d, A, P, t, false);
-  for (int j = threadIdx.x; j < t; j += NTHR) lam[j] = A[j + j * LDA];
+  // eigenvectors of C from the one-sided Jacobi of the positive definite
+  // C + shift I; eigenvalue = column norm - shift
+  __shared__ double red[NTHR];
+  double part = 0.0;
+  for (int idx = threadIdx.x; idx < t * t; idx += NTHR) {
+    const double x = A[idx % t + (idx / t) * LDA];
+    part = fma(x, x, part);
+  }
+  const double shift = 1.5 * sqrt(block_sum(part, red)) + 1e-300;
+  for (int i = threadIdx.x; i < t; i += NTHR) A[i + i * LDA] += shift;
+  __syncthreads();
+  jacobi_1s(d, A, t, t, P, 1e-15, 0.0, 40);
+  col_norms(A, t, t, lam);
+  for (int j = threadIdx.x; j < t; j += NTHR) lam[j] -= shift;
   __syncthreads();
   double* Cp = sm + d.oCp;
   double* Cn = sm + d.oCn;
@@ -583,38 +367,20 @@ __global__ __launch_bounds__(NTHR) void s_trunc(Dev d, int axis, int sd0) {
   __shared__ int perm[CAP];
   __shared__ int rsh;
   __shared__ double red[NTHR];
+  __shared__ double sv[CAP];
+  __shared__ int anyfill;
   const double* RL = sm + d.oRacc;
-  double* S3 = sm + d.oW1;   // t x t
-  double* Z = sm + d.oW2;    // t x t
-  double* Y1 = sm + d.oW3;   // t x t
   double* Ut = sm + d.oW4;   // t x r'
+  // B = S3 = RL^T; one-sided Jacobi: S3 V = U Sigma
   for (int idx = threadIdx.x; idx < t * t; idx += NTHR) {
     const int i = idx % t, j = idx / t;
-    S3[i + j * T] = RL[j + i * T];
+    G[i + j * LDA] = RL[j + i * T];
   }
   __syncthreads();
-  // pass 1: G = S3^T S3
-  for (int idx = threadIdx.x; idx < t * t; idx += NTHR) {
-    const int i = idx % t, j = idx / t;
-    double acc = 0.0;
-    for (int k = 0; k < t; ++k) acc = fma(S3[k + i * T], S3[k + j * T], acc);
-    G[i + j * LDA] = acc;
-  }
-  __syncthreads();
-  jacobi_eig(d, G, Y, t, true);
-  copy_from_lds(Y1, T, Y, t, t, 1.0);
-  mm(Z, T, S3, T, false, Y1, T, false, t, t, t, 1.0, 0.0);
-  // pass 2: G = Z^T Z
-  for (int idx = threadIdx.x; idx < t * t; idx += NTHR) {
-    const int i = idx % t, j = idx / t;
-    double acc = 0.0;
-    for (int k = 0; k < t; ++k) acc = fma(Z[k + i * T], Z[k + j * T], acc);
-    G[i + j * LDA] = acc;
-  }
-  __syncthreads();
-  jacobi_eig(d, G, Y, t, true);
-  sort_desc(G, t, perm);
-  for (int j = threadIdx.x; j < t; j += NTHR) sig[j] = sqrt(fmax(G[perm[j] + perm[j] * LDA], 0.0));
+  jacobi_1s(d, G, t, t, Y, 1e-15, 1e-15, 40);
+  col_norms(G, t, t, sv);
+  sort_desc(sv, t, perm);
+  for (int j = threadIdx.x; j < t; j += NTHR) sig[j] = sv[perm[j]];
   __syncthreads();
   if (threadIdx.x == 0) {
     int rp;
@@ -634,61 +400,61 @@ __global__ __launch_bounds__(NTHR) void s_trunc(Dev d, int axis, int sd0) {
     if (rp < 1) rp = 1;
     rsh = rp;
     d.rnew[s] = rp;
+    anyfill = 0;
   }
   __syncthreads();
   const int rp = rsh;
-  // Bv = Y1 Y2[:, perm[:r']]
   for (int idx = threadIdx.x; idx < t * rp; idx += NTHR) {
     const int i = idx % t, j = idx / t;
-    double acc = 0.0;
-    for (int k = 0; k < t; ++k) acc = fma(Y1[i + k * T], Y[k + perm[j] * LDA], acc);
-    sm[d.oBv + i + j * T] = acc;
+    sm[d.oBv + i + j * T] = Y[i + perm[j] * LDA];
   }
-  // U~ = Z Y2[:, perm[:r']] / sigma (pseudo-random where sigma vanishes)
+  // U~ = S3 V / sigma (pseudo-random where sigma vanishes)
   const double s0 = sig[0];
   for (int idx = threadIdx.x; idx < t * rp; idx += NTHR) {
     const int i = idx % t, j = idx / t;
     double v;
     if (s0 > 0.0 && sig[j] > 1e-13 * s0) {
-      double acc = 0.0;
-      for (int k = 0; k < t; ++k) acc = fma(Z[i + k * T], Y[k + perm[j] * LDA], acc);
-      v = acc / sig[j];
+      v = G[i + perm[j] * LDA] / sig[j];
     } else {
       v = hash_unit(((uint64_t)s << 40) ^ ((uint64_t)(j + 1000) << 24) ^ (uint64_t)i);
+      anyfill = 1;
     }
     Ut[i + j * T] = v;
   }
   __syncthreads();
-  // two passes of modified Gram-Schmidt on U~ (t x r')
-  for (int pass = 0; pass < 2; ++pass) {
-    for (int j = 0; j < rp; ++j) {
-      for (int k = 0; k < j; ++k) {
+  // completed columns are made orthonormal to the others (two passes of
+  // modified Gram-Schmidt); the Jacobi columns already are
+  if (anyfill) {
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int j = 0; j < rp; ++j) {
+        for (int k = 0; k < j; ++k) {
+          double part = 0.0;
+          for (int i = threadIdx.x; i < t; i += NTHR) part = fma(Ut[i + k * T], Ut[i + j * T], part);
+          red[threadIdx.x] = part;
+          __syncthreads();
+          for (int off = NTHR / 2; off > 0; off >>= 1) {
+            if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+            __syncthreads();
+          }
+          const double dot = red[0];
+          __syncthreads();
+          for (int i = threadIdx.x; i < t; i += NTHR) Ut[i + j * T] -= dot * Ut[i + k * T];
+          __syncthreads();
+        }
         double part = 0.0;
-        for (int i = threadIdx.x; i < t; i += NTHR) part = fma(Ut[i + k * T], Ut[i + j * T], part);
+        for (int i = threadIdx.x; i < t; i += NTHR) part = fma(Ut[i + j * T], Ut[i + j * T], part);
         red[threadIdx.x] = part;
         __syncthreads();
         for (int off = NTHR / 2; off > 0; off >>= 1) {
           if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
           __syncthreads();
         }
-        const double dot = red[0];
+        const double nrm = sqrt(red[0]);
         __syncthreads();
-        for (int i = threadIdx.x; i < t; i += NTHR) Ut[i + j * T] -= dot * Ut[i + k * T];
-        __syncthreads();
-      }
-      double part = 0.0;
-      for (int i = threadIdx.x; i < t; i += NTHR) part = fma(Ut[i + j * T], Ut[i + j * T], part);
-      red[threadIdx.x] = part;
-      __syncthreads();
-      for (int off = NTHR / 2; off > 0; off >>= 1) {
-        if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+        for (int i = threadIdx.x; i < t; i += NTHR) Ut[i + j * T] *= inv;
         __syncthreads();
       }
-      const double nrm = sqrt(red[0]);
-      __syncthreads();
-      const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
-      for (int i = threadIdx.x; i < t; i += NTHR) Ut[i + j * T] *= inv;
-      __syncthreads();
     }
   }
   const double ih = 1.0 / d.h;

@@ -32,14 +32,15 @@ __global__ __launch_bounds__(NTHR) void k_aug_form(Dev d, int axis, int sd0) {
   const int m0 = rb[0] + rb[1] + rb[2];
   const int M = d.M, R = d.R;
 
-  __shared__ double Ss[3 * CAPR * CAPR];
-  __shared__ double Ys[LDT * CAP];
+  extern __shared__ double lds[];
+  double* Ss = lds;                 // 3 blocks of R x R
+  double* Ys = lds + 3 * R * R;     // LDT x MA
   for (int b = 0; b < 3; ++b) {
     if (nb[b] < 0) continue;
     const double* Sb = d.S + (int64_t)nb[b] * R * R;
     for (int idx = threadIdx.x; idx < rb[b] * rb[b]; idx += NTHR) {
       int i = idx % rb[b], k = idx / rb[b];
-      Ss[b * CAPR * CAPR + i + k * CAPR] = Sb[i + k * R];
+      Ss[b * R * R + i + k * R] = Sb[i + k * R];
     }
   }
   __syncthreads();
@@ -58,8 +59,8 @@ __global__ __launch_bounds__(NTHR) void k_aug_form(Dev d, int axis, int sd0) {
       double acc = 0.0;
       if (i < nr) {
         const double* Vb = d.V + (int64_t)nb[b] * M * R;
-        const double* Sb = Ss + b * CAPR * CAPR;
-        for (int k = 0; k < rb[b]; ++k) acc = fma(Vb[(int64_t)k * M + q], Sb[jl + k * CAPR], acc);
+        const double* Sb = Ss + b * R * R;
+        for (int k = 0; k < rb[b]; ++k) acc = fma(Vb[(int64_t)k * M + q], Sb[jl + k * R], acc);
         acc *= d.sw[q];
         As[(int64_t)j * M + q] = acc;
       }
@@ -73,7 +74,8 @@ __global__ __launch_bounds__(NTHR) void k_aug_form(Dev d, int axis, int sd0) {
 }
 
 void launch_aug_form(const Dev& d, int axis, int sd0, int nsd, hipStream_t st) {
-  hipLaunchKernelGGL(k_aug_form, dim3(d.nwgM, nsd), dim3(NTHR), 0, st, d, axis, sd0);
+  const size_t lds = sizeof(double) * (3 * d.R * d.R + LDT * d.MA);
+  hipLaunchKernelGGL(k_aug_form, dim3(d.nwgM, nsd), dim3(NTHR), lds, st, d, axis, sd0);
 }
 
 // ----------------------------------------------------------------------------
@@ -86,17 +88,18 @@ void launch_aug_form(const Dev& d, int axis, int sd0, int nsd, hipStream_t st) {
 __global__ __launch_bounds__(NTHR) void k_gemm(Dev d, int axis, int sd0, const double* X, int64_t xsd,
                                                int rows, int kdim, int ndim, int boff, int bld,
                                                double* Y, int64_t ysd, const double* rowscale, int gram,
-                                               int fill_off, int ntiles) {
+                                               int fill_off, int ntiles, int kc) {
   const int s = sd0 + blockIdx.y;
   const int k = dim_of(d, s, axis, kdim);
   const int n = dim_of(d, s, axis, ndim);
-  __shared__ double Bs[CAP * CAP];
-  __shared__ double Xs[LDT * CAP];
+  extern __shared__ double lds[];
+  double* Bs = lds;                   // kc x n (leading dimension kc)
+  double* Xs = lds + kc * CAP;        // LDT x max(kc, n)
   __shared__ int fillm[CAP];
   const double* sm = small_of(d, s);
   for (int idx = threadIdx.x; idx < k * n; idx += NTHR) {
     int c = idx % k, j = idx / k;
-    Bs[c + j * CAP] = sm[boff + c + j * bld];
+    Bs[c + j * kc] = sm[boff + c + j * bld];
   }
   for (int j = threadIdx.x; j < CAP; j += NTHR) fillm[j] = (fill_off >= 0 && j < n) ? (sm[fill_off + j] != 0.0) : 0;
   __syncthreads();
@@ -123,7 +126,7 @@ __global__ __launch_bounds__(NTHR) void k_gemm(Dev d, int axis, int sd0, const d
 #pragma unroll
       for (int jj = 0; jj < NJ; ++jj) {
         const int j = cg + jj * (NTHR / TILE);
-        if (j < n) acc[jj] = fma(x, Bs[c + j * CAP], acc[jj]);
+        if (j < n) acc[jj] = fma(x, Bs[c + j * kc], acc[jj]);
       }
     }
     __syncthreads();
@@ -151,8 +154,11 @@ void launch_gemm(const Dev& d, int axis, int sd0, int nsd, const double* X, int6
                  bool gram, int fill_off, bool rows_are_cells, hipStream_t st) {
   const int nwg = rows_are_cells ? d.nwgN : d.nwgM;
   const int nt = rows_are_cells ? d.ntN : d.ntM;
-  hipLaunchKernelGGL(k_gemm, dim3(nwg, nsd), dim3(NTHR), 0, st, d, axis, sd0, X, xsd, rows, kdim, ndim,
-                     boff, bld, Y, ysd, rowscale, gram ? 1 : 0, fill_off, nt);
+  auto cap = [&](int which) { return which == DIM_M0 ? d.MA : (which == DIM_T ? d.T : d.R); };
+  const int kc = cap(kdim), nc = cap(ndim);
+  const size_t lds = sizeof(double) * ((size_t)kc * CAP + (size_t)LDT * (kc > nc ? kc : nc));
+  hipLaunchKernelGGL(k_gemm, dim3(nwg, nsd), dim3(NTHR), lds, st, d, axis, sd0, X, xsd, rows, kdim, ndim,
+                     boff, bld, Y, ysd, rowscale, gram ? 1 : 0, fill_off, nt, kc);
 }
 
 // ----------------------------------------------------------------------------
@@ -173,9 +179,10 @@ __global__ __launch_bounds__(NTHR) void k_ang_reduce(Dev d, int axis, int sd0) {
   const int t = d.tdim[s];
   const int M = d.M, R = d.R, T = d.T;
   const double* om = axis == 0 ? d.omx : d.omy;
-  __shared__ double Qs[LDT * CAP];
-  __shared__ double Vs[LDT * 3 * CAPR];
-  __shared__ double oms[TILE];
+  extern __shared__ double lds[];
+  double* Qs = lds;                       // LDT x T
+  double* Vs = lds + LDT * T;             // LDT x 3R
+  double* oms = Vs + LDT * 3 * R;         // TILE
 
   double* out = gpart_of(d, s) + (int64_t)blockIdx.x * d.gpTile;
   const int oT = 0, oC = R * T, oEp = oC + T * T, oEn = oEp + T * T, oOlo = oEn + T * T, oOhi = oOlo + R * T;
@@ -261,7 +268,8 @@ __global__ __launch_bounds__(NTHR) void k_ang_reduce(Dev d, int axis, int sd0) {
 }
 
 void launch_ang_reduce(const Dev& d, int axis, int sd0, int nsd, hipStream_t st) {
-  hipLaunchKernelGGL(k_ang_reduce, dim3(d.nwgM, nsd), dim3(NTHR), 0, st, d, axis, sd0);
+  const size_t lds = sizeof(double) * ((size_t)LDT * (d.T + 3 * d.R) + TILE);
+  hipLaunchKernelGGL(k_ang_reduce, dim3(d.nwgM, nsd), dim3(NTHR), lds, st, d, axis, sd0);
 }
 
 // ----------------------------------------------------------------------------
@@ -280,30 +288,32 @@ __global__ __launch_bounds__(NTHR) void k_kstep(Dev d, int axis, int sd0) {
   const int r = d.rank[s], rl = lo >= 0 ? d.rank[lo] : 0, rh = hi >= 0 ? d.rank[hi] : 0;
   const int t = d.tdim[s];
   const int N = d.N, R = d.R;
-  __shared__ double Cf[7 * CAPR * CAP];
-  __shared__ double Ks[LDT * CAP];
+  const int T = d.T;
+  extern __shared__ double lds[];
+  double* Cf = lds;                 // 7 blocks of R x T (leading dimension R)
+  double* Ks = lds + 7 * R * T;     // LDT x T
   const double* sm = small_of(d, s);
   const int offs[7] = {d.oM0, d.oMm, d.oMp, d.oGLo, d.oGHi, d.oGLoN, d.oGHiN};
   const int rows[7] = {r, r, r, r, r, rl, rh};
   for (int m = 0; m < 7; ++m) {
     for (int idx = threadIdx.x; idx < rows[m] * t; idx += NTHR) {
       int c = idx % rows[m], j = idx / rows[m];
-      Cf[m * CAPR * CAP + c + j * CAPR] = sm[offs[m] + c + j * R];
+      Cf[m * R * T + c + j * R] = sm[offs[m] + c + j * R];
     }
   }
   __syncthreads();
   const double* M0 = Cf;
-  const double* Mm = Cf + 1 * CAPR * CAP;
-  const double* Mp = Cf + 2 * CAPR * CAP;
-  const double* GLo = Cf + 3 * CAPR * CAP;
-  const double* GHi = Cf + 4 * CAPR * CAP;
-  const double* GLoN = Cf + 5 * CAPR * CAP;
-  const double* GHiN = Cf + 6 * CAPR * CAP;
+  const double* Mm = Cf + 1 * R * T;
+  const double* Mp = Cf + 2 * R * T;
+  const double* GLo = Cf + 3 * R * T;
+  const double* GHi = Cf + 4 * R * T;
+  const double* GLoN = Cf + 5 * R * T;
+  const double* GHiN = Cf + 6 * R * T;
 
   const double* Us = d.U + (int64_t)s * N * R;
   const double* Ul = lo >= 0 ? d.U + (int64_t)lo * N * R : nullptr;
   const double* Uh = hi >= 0 ? d.U + (int64_t)hi * N * R : nullptr;
-  double* K1 = d.K1 + (int64_t)s * N * d.T;
+  double* K1 = d.K1 + (int64_t)s * N * T;
   const int e = axis == 0 ? 1 : d.lnx;
   const int na = axis == 0 ? d.lnx : d.lny;
   GramAcc g;
@@ -326,7 +336,7 @@ __global__ __launch_bounds__(NTHR) void k_kstep(Dev d, int axis, int sd0) {
 #pragma unroll
         for (int jj = 0; jj < NJ; ++jj) {
           const int j = cg + jj * (NTHR / TILE);
-          if (j < t) acc[jj] = fma(u, M0[c + j * CAPR], acc[jj]);
+          if (j < t) acc[jj] = fma(u, M0[c + j * R], acc[jj]);
         }
       }
       if (ia > 0) {
@@ -335,7 +345,7 @@ __global__ __launch_bounds__(NTHR) void k_kstep(Dev d, int axis, int sd0) {
 #pragma unroll
           for (int jj = 0; jj < NJ; ++jj) {
             const int j = cg + jj * (NTHR / TILE);
-            if (j < t) acc[jj] = fma(u, Mm[c + j * CAPR], acc[jj]);
+            if (j < t) acc[jj] = fma(u, Mm[c + j * R], acc[jj]);
           }
         }
       } else {
@@ -344,7 +354,7 @@ __global__ __launch_bounds__(NTHR) void k_kstep(Dev d, int axis, int sd0) {
 #pragma unroll
           for (int jj = 0; jj < NJ; ++jj) {
             const int j = cg + jj * (NTHR / TILE);
-            if (j < t) acc[jj] = fma(u, GLo[c + j * CAPR], acc[jj]);
+            if (j < t) acc[jj] = fma(u, GLo[c + j * R], acc[jj]);
           }
         }
         if (lo >= 0) {
@@ -354,7 +364,7 @@ __global__ __launch_bounds__(NTHR) void k_kstep(Dev d, int axis, int sd0) {
 #pragma unroll
             for (int jj = 0; jj < NJ; ++jj) {
               const int j = cg + jj * (NTHR / TILE);
-              if (j < t) acc[jj] = fma(u, GLoN[c + j * CAPR], acc[jj]);
+              if (j < t) acc[jj] = fma(u, GLoN[c + j * R], acc[jj]);
             }
           }
         }
@@ -365,7 +375,7 @@ __global__ __launch_bounds__(NTHR) void k_kstep(Dev d, int axis, int sd0) {
 #pragma unroll
           for (int jj = 0; jj < NJ; ++jj) {
             const int j = cg + jj * (NTHR / TILE);
-            if (j < t) acc[jj] = fma(u, Mp[c + j * CAPR], acc[jj]);
+            if (j < t) acc[jj] = fma(u, Mp[c + j * R], acc[jj]);
           }
         }
       } else {
@@ -374,7 +384,7 @@ __global__ __launch_bounds__(NTHR) void k_kstep(Dev d, int axis, int sd0) {
 #pragma unroll
           for (int jj = 0; jj < NJ; ++jj) {
             const int j = cg + jj * (NTHR / TILE);
-            if (j < t) acc[jj] = fma(u, GHi[c + j * CAPR], acc[jj]);
+            if (j < t) acc[jj] = fma(u, GHi[c + j * R], acc[jj]);
           }
         }
         if (hi >= 0) {
@@ -384,7 +394,7 @@ __global__ __launch_bounds__(NTHR) void k_kstep(Dev d, int axis, int sd0) {
 #pragma unroll
             for (int jj = 0; jj < NJ; ++jj) {
               const int j = cg + jj * (NTHR / TILE);
-              if (j < t) acc[jj] = fma(u, GHiN[c + j * CAPR], acc[jj]);
+              if (j < t) acc[jj] = fma(u, GHiN[c + j * R], acc[jj]);
             }
           }
         }
@@ -406,7 +416,8 @@ __global__ __launch_bounds__(NTHR) void k_kstep(Dev d, int axis, int sd0) {
 }
 
 void launch_kstep(const Dev& d, int axis, int sd0, int nsd, hipStream_t st) {
-  hipLaunchKernelGGL(k_kstep, dim3(d.nwgN, nsd), dim3(NTHR), 0, st, d, axis, sd0);
+  const size_t lds = sizeof(double) * ((size_t)7 * d.R * d.T + (size_t)LDT * d.T);
+  hipLaunchKernelGGL(k_kstep, dim3(d.nwgN, nsd), dim3(NTHR), lds, st, d, axis, sd0);
 }
 
 // ----------------------------------------------------------------------------
@@ -420,9 +431,10 @@ __global__ __launch_bounds__(NTHR) void k_spatial_reduce(Dev d, int axis, int sd
   const int s = sd0 + blockIdx.y;
   const int t = d.tdim[s];
   const int N = d.N, T = d.T;
-  __shared__ double Qs[LDT * CAP];
-  __shared__ double Dm[LDT * CAP];
-  __shared__ double Dp[LDT * CAP];
+  extern __shared__ double lds[];
+  double* Qs = lds;                 // LDT x T each
+  double* Dm = lds + LDT * T;
+  double* Dp = lds + 2 * LDT * T;
   const double* Qsd = Q + (int64_t)s * N * T;
   double* out = gpart_of(d, s) + (int64_t)blockIdx.x * d.gpTile;
   for (int e2 = threadIdx.x; e2 < 2 * t * t; e2 += NTHR) out[(e2 < t * t) ? e2 : (T * T + e2 - t * t)] = 0.0;
@@ -459,7 +471,8 @@ __global__ __launch_bounds__(NTHR) void k_spatial_reduce(Dev d, int axis, int sd
 }
 
 void launch_spatial_reduce(const Dev& d, int axis, int sd0, int nsd, const double* Q, hipStream_t st) {
-  hipLaunchKernelGGL(k_spatial_reduce, dim3(d.nwgN, nsd), dim3(NTHR), 0, st, d, axis, sd0, Q);
+  const size_t lds = sizeof(double) * 3 * (size_t)LDT * d.T;
+  hipLaunchKernelGGL(k_spatial_reduce, dim3(d.nwgN, nsd), dim3(NTHR), lds, st, d, axis, sd0, Q);
 }
 
 // ----------------------------------------------------------------------------
@@ -473,14 +486,15 @@ __global__ __launch_bounds__(NTHR) void k_lstep(Dev d, int axis, int sd0) {
   const int t = d.tdim[s];
   const int M = d.M, T = d.T;
   const double* om = axis == 0 ? d.omx : d.omy;
-  __shared__ double P[3 * CAP * CAP];
-  __shared__ double Xs[LDT * CAP];
+  extern __shared__ double lds[];
+  double* P = lds;                  // 3 blocks of T x T (leading dimension T)
+  double* Xs = lds + 3 * T * T;     // LDT x T
   const double* sm = small_of(d, s);
   for (int idx = threadIdx.x; idx < t * t; idx += NTHR) {
     const int c = idx % t, j = idx / t;
-    P[c + j * CAP] = sm[d.oP0 + c + j * T];
-    P[CAP * CAP + c + j * CAP] = sm[d.oPm + c + j * T];
-    P[2 * CAP * CAP + c + j * CAP] = sm[d.oPp + c + j * T];
+    P[c + j * T] = sm[d.oP0 + c + j * T];
+    P[T * T + c + j * T] = sm[d.oPm + c + j * T];
+    P[2 * T * T + c + j * T] = sm[d.oPp + c + j * T];
   }
   __syncthreads();
   const double* Qsd = d.Qh + (int64_t)s * M * T;
@@ -499,7 +513,7 @@ __global__ __launch_bounds__(NTHR) void k_lstep(Dev d, int axis, int sd0) {
     __syncthreads();
     const int q = q0 + i;
     const double o = (i < nr) ? om[q] : 0.0;
-    const double* Ps = (o >= 0.0) ? P + CAP * CAP : P + 2 * CAP * CAP;
+    const double* Ps = (o >= 0.0) ? P + T * T : P + 2 * T * T;
     double acc[NJ];
 #pragma unroll
     for (int jj = 0; jj < NJ; ++jj) acc[jj] = 0.0;
@@ -508,7 +522,7 @@ __global__ __launch_bounds__(NTHR) void k_lstep(Dev d, int axis, int sd0) {
 #pragma unroll
       for (int jj = 0; jj < NJ; ++jj) {
         const int j = cg + jj * (NTHR / TILE);
-        if (j < t) acc[jj] = fma(x, fma(o, Ps[c + j * CAP], P[c + j * CAP]), acc[jj]);
+        if (j < t) acc[jj] = fma(x, fma(o, Ps[c + j * T], P[c + j * T]), acc[jj]);
       }
     }
     __syncthreads();
@@ -528,7 +542,8 @@ __global__ __launch_bounds__(NTHR) void k_lstep(Dev d, int axis, int sd0) {
 }
 
 void launch_lstep(const Dev& d, int axis, int sd0, int nsd, hipStream_t st) {
-  hipLaunchKernelGGL(k_lstep, dim3(d.nwgM, nsd), dim3(NTHR), 0, st, d, axis, sd0);
+  const size_t lds = sizeof(double) * ((size_t)3 * d.T * d.T + (size_t)LDT * d.T);
+  hipLaunchKernelGGL(k_lstep, dim3(d.nwgM, nsd), dim3(NTHR), lds, st, d, axis, sd0);
 }
 
 // ----------------------------------------------------------------------------
@@ -542,7 +557,7 @@ __global__ __launch_bounds__(NTHR) void k_coll_kstep(Dev d, int sd0) {
   const int N = d.N, R = d.R;
   __shared__ double Ss[CAPR * CAPR];
   __shared__ double mv[CAPR];
-  __shared__ double Ks[LDT * CAP];
+  __shared__ double Ks[LDT * CAPR];
   const double* sm = small_of(d, s);
   const double* Sg = d.S + (int64_t)s * R * R;
   for (int idx = threadIdx.x; idx < r * r; idx += NTHR) {
@@ -672,7 +687,7 @@ __global__ __launch_bounds__(NTHR) void k_coll_lstep(Dev d, int sd0) {
   const int M = d.M, R = d.R;
   __shared__ double Ps[CAPR * CAPR];
   __shared__ double cr[CAPR];
-  __shared__ double Xs[LDT * CAP];
+  __shared__ double Xs[LDT * CAPR];
   const double* sm = small_of(d, s);
   for (int idx = threadIdx.x; idx < r * r; idx += NTHR) {
     const int a = idx % r, b = idx / r;
@@ -767,6 +782,17 @@ __global__ __launch_bounds__(NTHR) void k_moments(Dev d) {
 void launch_moments(const Dev& d, hipStream_t st) {
   const int nb = (d.N + NTHR - 1) / NTHR;
   hipLaunchKernelGGL(k_moments, dim3(nb < 16 ? nb : 16, d.nsub), dim3(NTHR), 0, st, d);
+}
+
+// Allow the dynamically sized kernels the whole LDS of a compute unit.
+void init_kernels() {
+  const int max_lds = 160 * 1024;
+  (void)hipFuncSetAttribute((const void*)k_aug_form, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+  (void)hipFuncSetAttribute((const void*)k_gemm, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds - 256);
+  (void)hipFuncSetAttribute((const void*)k_ang_reduce, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+  (void)hipFuncSetAttribute((const void*)k_kstep, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+  (void)hipFuncSetAttribute((const void*)k_spatial_reduce, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+  (void)hipFuncSetAttribute((const void*)k_lstep, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
 }
 
 }  // namespace dd
