@@ -331,127 +331,4 @@ __device__ void copy_from_lds(double* dst, int ldd, const double* src, int rows,
   __syncthreads();
 }
 
-
-// ---------------------------------------------------------------------------
-// Single-wavefront variant of the one-sided Jacobi above (same rotations,
-// same stopping rule), run by the first wavefront of the workgroup while the
-// other wavefronts wait at the caller's barrier.  Inside one wavefront LDS
-// operations complete in issue order, so rounds are separated by a wavefront
-// barrier (a compiler fence) instead of s_barrier, and the three inner
-// products of a pair are reduced across its lane group with DPP row
-// operations.  Returns the number of sweeps (negative if not converged).
-
-__device__ inline void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-template <int G, int RMAX>
-__device__ int jacobi_wave_g(double* B, int rows, int n, double* V, double tol, double floor2, int max_sweeps) {
-  const int lane64 = threadIdx.x;  // caller guarantees threadIdx.x < 64
-  const int n2 = n + (n & 1);
-  const int npair = n2 / 2;
-  const int nm1 = n2 - 1;
-  const int grp = lane64 / G, lane = lane64 % G;
-  const double tol2 = tol * tol;
-  const bool active = grp < npair;
-  int sweeps = 0;
-  bool converged = false;
-  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-    sweeps = sweep + 1;
-    bool rot = false;
-    int va = grp - 1, vb = n2 - 2 - grp;
-    for (int round = 0; round < nm1; ++round) {
-      int p = 0, q = n;
-      if (active) {
-        const int a = grp == 0 ? 0 : va + 1;
-        const int b = vb + 1;
-        p = a < b ? a : b;
-        q = a < b ? b : a;
-      }
-      const bool live = active && q < n;
-      double xs[RMAX], ys[RMAX];
-      double al = 0.0, be = 0.0, ga = 0.0;
-#pragma unroll
-      for (int k = 0; k < RMAX; ++k) {
-        const int i = lane + k * G;
-        xs[k] = 0.0;
-        ys[k] = 0.0;
-        if (live && i < rows) {
-          xs[k] = B[i + p * LDA];
-          ys[k] = B[i + q * LDA];
-        }
-        al = fma(xs[k], xs[k], al);
-        be = fma(ys[k], ys[k], be);
-        ga = fma(xs[k], ys[k], ga);
-      }
-      al = group_sum_dpp<G>(al);
-      be = group_sum_dpp<G>(be);
-      ga = group_sum_dpp<G>(ga);
-      if (live && ga != 0.0 && al > floor2 && be > floor2 && ga * ga > tol2 * al * be) {
-        double c, sn;
-        jacobi_rotation(al, be, ga, c, sn);
-#pragma unroll
-        for (int k = 0; k < RMAX; ++k) {
-          const int i = lane + k * G;
-          if (i < rows) {
-            B[i + p * LDA] = c * xs[k] - sn * ys[k];
-            B[i + q * LDA] = fma(sn, xs[k], c * ys[k]);
-          }
-        }
-        for (int i = lane; i < n; i += G) {
-          const double x = V[i + p * LDA], y = V[i + q * LDA];
-          V[i + p * LDA] = c * x - sn * y;
-          V[i + q * LDA] = fma(sn, x, c * y);
-        }
-        rot = true;
-      }
-      if (++va >= nm1) va -= nm1;
-      if (++vb >= nm1) vb -= nm1;
-      wave_sync();
-    }
-    if (!__any(rot)) {
-      converged = true;
-      break;
-    }
-  }
-  return converged ? sweeps : -sweeps;
-}
-
-// Dispatch on n: the lane group is the largest power of two with
-// G * npair <= 64, and each lane holds rows / G rows of a pair in registers
-// (rows <= 64).  Called by the whole workgroup; returns the sweep count.
-__device__ inline int jacobi_wave(const Dev& d, double* B, int rows, int n, double* V, double tol, double floor_rel,
-                                  int max_sweeps) {
-  __shared__ double red[NTHR];
-  __shared__ int res;
-  double part = 0.0;
-  for (int idx = threadIdx.x; idx < rows * n; idx += NTHR) {
-    const double x = B[idx % rows + (idx / rows) * LDA];
-    part = fma(x, x, part);
-  }
-  const double floor2 = floor_rel * floor_rel * block_sum(part, red);
-  for (int idx = threadIdx.x; idx < n * n; idx += NTHR) {
-    const int i = idx % n, j = idx / n;
-    V[i + j * LDA] = (i == j) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  if (threadIdx.x < 64) {
-    const int npair = (n + (n & 1)) / 2;
-    int r;
-    if (n <= 1) r = 0;
-    else if (npair * 16 <= 64) r = jacobi_wave_g<16, 4>(B, rows, n, V, tol, floor2, max_sweeps);
-    else if (npair * 8 <= 64) r = jacobi_wave_g<8, 8>(B, rows, n, V, tol, floor2, max_sweeps);
-    else if (npair * 4 <= 64) r = jacobi_wave_g<4, 16>(B, rows, n, V, tol, floor2, max_sweeps);
-    else r = jacobi_wave_g<2, 32>(B, rows, n, V, tol, floor2, max_sweeps);
-    if (threadIdx.x == 0) res = r;
-  }
-  __syncthreads();
-  const int r = res;
-  if (r < 0 && tol < 1e-12 && threadIdx.x == 0) atomicOr(d.flags, FLAG_JACOBI_NOCONV);
-  __syncthreads();
-  return r;
-}
-
 }  // namespace dd

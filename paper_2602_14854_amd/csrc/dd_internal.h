@@ -165,6 +165,15 @@ struct GramAcc {
   }
 };
 
+// Order the LDS accesses of one wavefront around a point where its lanes
+// exchange data through LDS (LDS operations of a wavefront complete in issue
+// order; this keeps the compiler from moving them across the point).
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // deterministic pseudo-random value in [-1, 1) (splitmix64 finaliser)
 __device__ inline double hash_unit(uint64_t x) {
   x += 0x9e3779b97f4a7c15ull;

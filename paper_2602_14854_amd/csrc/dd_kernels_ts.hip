@@ -1,81 +1,114 @@
-// Tall-skinny kernels of the DD-DLRA step: every launch covers all
-// subdomains of a batch (blockIdx.y) and a strided set of 64-row tiles of the
-// cell or direction dimension (blockIdx.x).  Reductions over rows (Gram
-// matrices, Galerkin matrices) leave one partial per workgroup; the small
-// per-subdomain kernels add the partials in a fixed order, so results are
-// bitwise reproducible.
+// Tall-skinny kernels of the DD-DLRA step on the FP64 matrix cores.
+//
+// Every launch covers all subdomains of a batch (blockIdx.y).  Inside a
+// subdomain the rows (cells or directions) are cut into strips of 16; strip
+// st belongs to wavefront st mod (4 gridDim.x) of the workgroups blockIdx.x,
+// so a workgroup takes 64 consecutive rows at a time and no barrier is
+// needed inside the strip loop.  All global loads of a strip are issued
+// before its first matrix-core instruction.  Reductions over rows (Gram and
+// Galerkin matrices) stay in the wavefronts' accumulators, are summed over
+// the workgroup in a fixed order and leave one partial per workgroup; the
+// small per-subdomain kernels add the partials in a fixed order, so results
+// are bitwise reproducible.
 //
 // Memory layout (per subdomain, column-major, one column contiguous):
 //   cells  p = iy*lnx + ix  -> x-neighbours at p+-1, y-neighbours at p+-lnx
 //   directions q            -> rows of V, V-hat, L
-// Consecutive threads take consecutive rows, so every global access of a
-// column is coalesced for both the x- and the y-stencil.
-#include "dd_internal.h"
+#include <algorithm>
+#include <type_traits>
+
+#include "dd_mfma.h"
 
 namespace dd {
 
 constexpr int CAPR = 21;  // largest stored rank (3 * CAPR <= CAP)
+constexpr int KSR = 6;    // k-steps of 4 covering CAPR
+
+__host__ __device__ constexpr int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
 // ----------------------------------------------------------------------------
 // Augmentation matrix (Algorithm 4, step 1), weighted by sqrt(w) so that the
 // plain Gram matrix is L0^T W L0:
 //   A[q, :] = sqrt(w_q) [ V[q,:] S^T | V_lo[q,:] S_lo^T | V_hi[q,:] S_hi^T ]
+// formed as one product [V | V_lo | V_hi] blockdiag(S^T, S_lo^T, S_hi^T);
+// leaves the partial Gram matrix A^T A.
 // ----------------------------------------------------------------------------
+template <int NCB, int KS>
 __global__ __launch_bounds__(NTHR) void k_aug_form(Dev d, int axis, int sd0) {
+  constexpr int LD = strip_ld<NCB>();
+  constexpr int NB = NCB * (NCB + 1) / 2;
   const int s = sd0 + blockIdx.y;
   const int nb[3] = {s, neighbour(d, s, axis, -1), neighbour(d, s, axis, +1)};
-  int rb[3], cb[3];
-  cb[0] = 0;
+  int rb[3];
   for (int b = 0; b < 3; ++b) rb[b] = nb[b] >= 0 ? d.rank[nb[b]] : 0;
-  cb[1] = rb[0];
-  cb[2] = rb[0] + rb[1];
+  const int c1 = rb[0], c2 = rb[0] + rb[1];
   const int m0 = rb[0] + rb[1] + rb[2];
   const int M = d.M, R = d.R;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l16 = lane & 15, kq = lane >> 4;
 
   extern __shared__ double lds[];
-  double* Ss = lds;                 // 3 blocks of R x R
-  double* Ys = lds + 3 * R * R;     // LDT x MA
-  for (int b = 0; b < 3; ++b) {
-    if (nb[b] < 0) continue;
-    const double* Sb = d.S + (int64_t)nb[b] * R * R;
-    for (int idx = threadIdx.x; idx < rb[b] * rb[b]; idx += NTHR) {
-      int i = idx % rb[b], k = idx / rb[b];
-      Ss[b * R * R + i + k * R] = Sb[i + k * R];
+  double* Bf = lds;                                   // KS * NCB fragments
+  double* Ys = lds + KS * NCB * 64 + wave * 16 * LD;  // wavefront strip
+  for (int idx = threadIdx.x; idx < KS * NCB * 64; idx += NTHR) {
+    const int l = idx & 63, f = idx >> 6, cb = f % NCB, ks = f / NCB;
+    const int kc = 4 * ks + (l >> 4), col = 16 * cb + (l & 15);
+    double v = 0.0;
+    if (kc < m0 && col < m0) {
+      const int bk = kc < c1 ? 0 : (kc < c2 ? 1 : 2);
+      const int bc = col < c1 ? 0 : (col < c2 ? 1 : 2);
+      if (bk == bc) {
+        const int off = bk == 0 ? 0 : (bk == 1 ? c1 : c2);
+        v = d.S[(int64_t)nb[bk] * R * R + (col - off) + (int64_t)(kc - off) * R];
+      }
     }
+    Bf[idx] = v;
   }
   __syncthreads();
 
+  const double* Vb[3];
+  for (int b = 0; b < 3; ++b) Vb[b] = nb[b] >= 0 ? d.V + (int64_t)nb[b] * M * R : d.V;
   double* As = d.A + (int64_t)s * M * d.MA;
-  GramAcc g;
-  g.zero();
-  const int i = threadIdx.x % TILE, cg = threadIdx.x / TILE;
-  for (int tile = blockIdx.x; tile < d.ntM; tile += gridDim.x) {
-    const int q0 = tile * TILE;
-    const int nr = min(TILE, M - q0);
-    const int q = q0 + i;
-    for (int j = cg; j < m0; j += NTHR / TILE) {
-      const int b = (j >= cb[2]) ? 2 : ((j >= cb[1]) ? 1 : 0);
-      const int jl = j - cb[b];
-      double acc = 0.0;
-      if (i < nr) {
-        const double* Vb = d.V + (int64_t)nb[b] * M * R;
-        const double* Sb = Ss + b * R * R;
-        for (int k = 0; k < rb[b]; ++k) acc = fma(Vb[(int64_t)k * M + q], Sb[jl + k * R], acc);
-        acc *= d.sw[q];
-        As[(int64_t)j * M + q] = acc;
-      }
-      Ys[i + j * LDT] = (i < nr) ? acc : 0.0;
+  dbl4 g[NB];
+  zero_acc<NB>(g);
+  const int nst = ceil_div(M, 16);
+  for (int st = blockIdx.x * NW + wave; st < nst; st += gridDim.x * NW) {
+    const int q = st * 16 + l16;
+    const bool rin = q < M;
+    double xv[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int kc = 4 * ks + kq;
+      const int bk = kc < c1 ? 0 : (kc < c2 ? 1 : 2);
+      const int off = bk == 0 ? 0 : (bk == 1 ? c1 : c2);
+      xv[ks] = (rin && kc < m0) ? Vb[bk][(int64_t)(kc - off) * M + q] : 0.0;
     }
-    __syncthreads();
-    g.add(Ys, LDT, nr, m0);
-    __syncthreads();
+    dbl4 acc[NCB];
+    zero_acc<NCB>(acc);
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      if (4 * ks < m0) {
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) acc[cb] = mfma64(Bf[(ks * NCB + cb) * 64 + lane], xv[ks], acc[cb]);
+      }
+    }
+    const double swq = rin ? d.sw[q] : 0.0;
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int j = 16 * cb + 4 * v + kq;
+        const double val = acc[cb][v] * swq;
+        if (rin && j < m0) As[(int64_t)j * M + q] = val;
+        Ys[l16 * LD + j] = val;
+      }
+    }
+    wave_sync();
+    strip_gram<NCB, LD>(g, Ys);
+    wave_sync();
   }
-  g.store(gpart_of(d, s) + (int64_t)blockIdx.x * d.gpTile, m0);
-}
-
-void launch_aug_form(const Dev& d, int axis, int sd0, int nsd, hipStream_t st) {
-  const size_t lds = sizeof(double) * (3 * d.R * d.R + LDT * d.MA);
-  hipLaunchKernelGGL(k_aug_form, dim3(d.nwgM, nsd), dim3(NTHR), lds, st, d, axis, sd0);
+  wg_reduce_acc<NB>(g, lds);
+  if (wave == 0) store_gram<NCB>(g, gpart_of(d, s) + (int64_t)blockIdx.x * d.gpTile, m0, 1.0);
 }
 
 // ----------------------------------------------------------------------------
@@ -83,82 +116,79 @@ void launch_aug_form(const Dev& d, int axis, int sd0, int nsd, hipStream_t st) {
 // partial Gram matrix of Y.  X is rows x k, B is k x n (small workspace,
 // leading dimension bld).  Columns flagged in the fill mask are replaced by
 // deterministic pseudo-random values (used to complete a basis where the
-// augmentation matrix has no information).
+// data carry no information).
 // ----------------------------------------------------------------------------
-__global__ __launch_bounds__(NTHR) void k_gemm(Dev d, int axis, int sd0, const double* X, int64_t xsd,
-                                               int rows, int kdim, int ndim, int boff, int bld,
-                                               double* Y, int64_t ysd, const double* rowscale, int gram,
-                                               int fill_off, int ntiles, int kc) {
+template <int NCB, int KS>
+__global__ __launch_bounds__(NTHR) void k_gemm(Dev d, int axis, int sd0, const double* X, int64_t xsd, int rows,
+                                               int kdim, int ndim, int boff, int bld, double* Y, int64_t ysd,
+                                               const double* rowscale, int gram, int fill_off) {
+  constexpr int LD = strip_ld<NCB>();
+  constexpr int NB = NCB * (NCB + 1) / 2;
   const int s = sd0 + blockIdx.y;
   const int k = dim_of(d, s, axis, kdim);
   const int n = dim_of(d, s, axis, ndim);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l16 = lane & 15, kq = lane >> 4;
   extern __shared__ double lds[];
-  double* Bs = lds;                   // kc x n (leading dimension kc)
-  double* Xs = lds + kc * CAP;        // LDT x max(kc, n)
-  __shared__ int fillm[CAP];
+  double* Bf = lds;
+  double* Ys = lds + KS * NCB * 64 + wave * 16 * LD;
+  __shared__ int fillm[16 * NCB];
   const double* sm = small_of(d, s);
-  for (int idx = threadIdx.x; idx < k * n; idx += NTHR) {
-    int c = idx % k, j = idx / k;
-    Bs[c + j * kc] = sm[boff + c + j * bld];
+  for (int idx = threadIdx.x; idx < KS * NCB * 64; idx += NTHR) {
+    const int l = idx & 63, f = idx >> 6, cb = f % NCB, ks = f / NCB;
+    const int kc = 4 * ks + (l >> 4), col = 16 * cb + (l & 15);
+    Bf[idx] = (kc < k && col < n) ? sm[boff + kc + col * bld] : 0.0;
   }
-  for (int j = threadIdx.x; j < CAP; j += NTHR) fillm[j] = (fill_off >= 0 && j < n) ? (sm[fill_off + j] != 0.0) : 0;
+  for (int j = threadIdx.x; j < 16 * NCB; j += NTHR)
+    fillm[j] = (fill_off >= 0 && j < n) ? (sm[fill_off + j] != 0.0) : 0;
   __syncthreads();
 
   const double* Xsd = X + (int64_t)s * xsd;
   double* Ysd = Y + (int64_t)s * ysd;
-  GramAcc g;
-  g.zero();
-  const int i = threadIdx.x % TILE, cg = threadIdx.x / TILE;
-  constexpr int NJ = CAP / (NTHR / TILE);
-  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const int r0 = tile * TILE;
-    const int nr = min(TILE, rows - r0);
-    for (int idx = threadIdx.x; idx < TILE * k; idx += NTHR) {
-      int ii = idx % TILE, c = idx / TILE;
-      Xs[ii + c * LDT] = (ii < nr) ? Xsd[(int64_t)c * rows + r0 + ii] : 0.0;
+  dbl4 g[NB];
+  zero_acc<NB>(g);
+  const int nst = ceil_div(rows, 16);
+  for (int st = blockIdx.x * NW + wave; st < nst; st += gridDim.x * NW) {
+    const int row = st * 16 + l16;
+    const bool rin = row < rows;
+    double xv[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int kc = 4 * ks + kq;
+      xv[ks] = (rin && kc < k) ? Xsd[(int64_t)kc * rows + row] : 0.0;
     }
-    __syncthreads();
-    double acc[NJ];
+    dbl4 acc[NCB];
+    zero_acc<NCB>(acc);
 #pragma unroll
-    for (int jj = 0; jj < NJ; ++jj) acc[jj] = 0.0;
-    for (int c = 0; c < k; ++c) {
-      const double x = Xs[i + c * LDT];
+    for (int ks = 0; ks < KS; ++ks) {
+      if (4 * ks < k) {
 #pragma unroll
-      for (int jj = 0; jj < NJ; ++jj) {
-        const int j = cg + jj * (NTHR / TILE);
-        if (j < n) acc[jj] = fma(x, Bs[c + j * kc], acc[jj]);
+        for (int cb = 0; cb < NCB; ++cb) acc[cb] = mfma64(Bf[(ks * NCB + cb) * 64 + lane], xv[ks], acc[cb]);
       }
     }
-    __syncthreads();
-    const int row = r0 + i;
-    const double rs = (rowscale != nullptr && i < nr) ? rowscale[row] : 1.0;
+    const double rs = (rowscale != nullptr && rin) ? rowscale[row] : 1.0;
 #pragma unroll
-    for (int jj = 0; jj < NJ; ++jj) {
-      const int j = cg + jj * (NTHR / TILE);
-      if (j < n) {
-        double v = acc[jj] * rs;
-        if (fillm[j]) v = hash_unit(((uint64_t)s << 40) ^ ((uint64_t)j << 24) ^ (uint64_t)row);
-        if (i < nr) Ysd[(int64_t)j * rows + row] = v;
-        Xs[i + j * LDT] = (i < nr) ? v : 0.0;
+    for (int cb = 0; cb < NCB; ++cb) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int j = 16 * cb + 4 * v + kq;
+        double val = acc[cb][v] * rs;
+        if (fillm[j]) val = hash_unit(((uint64_t)s << 40) ^ ((uint64_t)j << 24) ^ (uint64_t)row);
+        if (!rin) val = 0.0;
+        if (rin && j < n) Ysd[(int64_t)j * rows + row] = val;
+        if (gram) Ys[l16 * LD + j] = val;
       }
     }
-    __syncthreads();
-    if (gram) g.add(Xs, LDT, nr, n);
-    __syncthreads();
+    if (gram) {
+      wave_sync();
+      strip_gram<NCB, LD>(g, Ys);
+      wave_sync();
+    }
   }
-  if (gram) g.store(gpart_of(d, s) + (int64_t)blockIdx.x * d.gpTile, n);
-}
-
-void launch_gemm(const Dev& d, int axis, int sd0, int nsd, const double* X, int64_t xsd, int rows,
-                 int kdim, int ndim, int boff, int bld, double* Y, int64_t ysd, const double* rowscale,
-                 bool gram, int fill_off, bool rows_are_cells, hipStream_t st) {
-  const int nwg = rows_are_cells ? d.nwgN : d.nwgM;
-  const int nt = rows_are_cells ? d.ntN : d.ntM;
-  auto cap = [&](int which) { return which == DIM_M0 ? d.MA : (which == DIM_T ? d.T : d.R); };
-  const int kc = cap(kdim), nc = cap(ndim);
-  const size_t lds = sizeof(double) * ((size_t)kc * CAP + (size_t)LDT * (kc > nc ? kc : nc));
-  hipLaunchKernelGGL(k_gemm, dim3(nwg, nsd), dim3(NTHR), lds, st, d, axis, sd0, X, xsd, rows, kdim, ndim,
-                     boff, bld, Y, ysd, rowscale, gram ? 1 : 0, fill_off, nt, kc);
+  if (gram) {
+    wg_reduce_acc<NB>(g, lds);
+    if (wave == 0) store_gram<NCB>(g, gpart_of(d, s) + (int64_t)blockIdx.x * d.gpTile, n, 1.0);
+  }
 }
 
 // ----------------------------------------------------------------------------
@@ -172,104 +202,132 @@ void launch_gemm(const Dev& d, int axis, int sd0, int nsd, const double* X, int6
 // Olo @R*T+3T*T (ld R), Ohi @2R*T+3T*T (ld R); the t x t blocks use
 // leading dimension t inside their T*T slots.
 // ----------------------------------------------------------------------------
+template <int NCT, int NCR>
 __global__ __launch_bounds__(NTHR) void k_ang_reduce(Dev d, int axis, int sd0) {
+  // wavefronts 0-1 form Tm, Olo, Ohi; wavefronts 2-3 form C, Ep, En; each
+  // pair walks the same strips
+  constexpr int LD = 16 * (NCT + 3 * NCR) + 1;  // strip: [Qh | sw V | sw V_lo | sw V_hi]
+  constexpr int NBT = NCT * (NCT + 1) / 2;
+  constexpr int NRT = NCR * NCT;
+  constexpr int NACC = 3 * NRT > 3 * NBT ? 3 * NRT : 3 * NBT;
+  constexpr int KST = 4 * NCT, KSV = 4 * NCR;  // k-steps of 4 columns per source
   const int s = sd0 + blockIdx.y;
   const int lo = neighbour(d, s, axis, -1), hi = neighbour(d, s, axis, +1);
   const int r = d.rank[s], rl = lo >= 0 ? d.rank[lo] : 0, rh = hi >= 0 ? d.rank[hi] : 0;
   const int t = d.tdim[s];
   const int M = d.M, R = d.R, T = d.T;
   const double* om = axis == 0 ? d.omx : d.omy;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l16 = lane & 15, kq = lane >> 4;
+  const bool grp_v = wave < 2;
   extern __shared__ double lds[];
-  double* Qs = lds;                       // LDT x T
-  double* Vs = lds + LDT * T;             // LDT x 3R
-  double* oms = Vs + LDT * 3 * R;         // TILE
+  double* Xs = lds + wave * (16 * LD + 16);  // strip, then 16 values of Omega
+  double* oms = Xs + 16 * LD;
 
-  double* out = gpart_of(d, s) + (int64_t)blockIdx.x * d.gpTile;
-  const int oT = 0, oC = R * T, oEp = oC + T * T, oEn = oEp + T * T, oOlo = oEn + T * T, oOhi = oOlo + R * T;
-  const int nT = r * t, nC = t * t, nOl = rl * t, nOh = rh * t;
-  const int ntot = nT + 3 * nC + nOl + nOh;
-  for (int e = threadIdx.x; e < ntot; e += NTHR) {
-    int o;
-    if (e < nT) o = oT + (e % r) + (e / r) * R;
-    else if (e < nT + nC) { int ee = e - nT; o = oC + ee; }
-    else if (e < nT + 2 * nC) { int ee = e - nT - nC; o = oEp + ee; }
-    else if (e < nT + 3 * nC) { int ee = e - nT - 2 * nC; o = oEn + ee; }
-    else if (e < nT + 3 * nC + nOl) { int ee = e - nT - 3 * nC; o = oOlo + (ee % rl) + (ee / rl) * R; }
-    else { int ee = e - nT - 3 * nC - nOl; o = oOhi + (ee % rh) + (ee / rh) * R; }
-    out[o] = 0.0;
-  }
   const double* Qsd = d.Qh + (int64_t)s * M * T;
-  const double* Vo = d.V + (int64_t)s * M * R;
-  const double* Vl = lo >= 0 ? d.V + (int64_t)lo * M * R : nullptr;
-  const double* Vh = hi >= 0 ? d.V + (int64_t)hi * M * R : nullptr;
-  for (int tile = blockIdx.x; tile < d.ntM; tile += gridDim.x) {
-    const int q0 = tile * TILE;
-    const int nr = min(TILE, M - q0);
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < TILE * t; idx += NTHR) {
-      int ii = idx % TILE, c = idx / TILE;
-      Qs[ii + c * LDT] = ii < nr ? Qsd[(int64_t)c * M + q0 + ii] : 0.0;
+  const double* Vsrc[3] = {d.V + (int64_t)s * M * R, lo >= 0 ? d.V + (int64_t)lo * M * R : d.V,
+                           hi >= 0 ? d.V + (int64_t)hi * M * R : d.V};
+  const int rv[3] = {r, rl, rh};
+  dbl4 acc[NACC];
+  zero_acc<NACC>(acc);
+  const int nst = ceil_div(M, 16);
+  for (int st = blockIdx.x * 2 + (wave & 1); st < nst; st += gridDim.x * 2) {
+    const int q = st * 16 + l16;
+    const bool rin = q < M;
+    double xq[KST];
+#pragma unroll
+    for (int ks = 0; ks < KST; ++ks) {
+      const int c = 4 * ks + kq;
+      xq[ks] = (rin && c < t) ? Qsd[(int64_t)c * M + q] : 0.0;
     }
-    const int rv = r + rl + rh;
-    for (int idx = threadIdx.x; idx < TILE * rv; idx += NTHR) {
-      int ii = idx % TILE, c = idx / TILE;
-      double v = 0.0;
-      if (ii < nr) {
-        const int q = q0 + ii;
-        if (c < r) v = Vo[(int64_t)c * M + q];
-        else if (c < r + rl) v = Vl[(int64_t)(c - r) * M + q];
-        else v = Vh[(int64_t)(c - r - rl) * M + q];
-        v *= d.sw[q];
-      }
-      Vs[ii + c * LDT] = v;
-    }
-    for (int ii = threadIdx.x; ii < TILE; ii += NTHR) {
-      oms[ii] = ii < nr ? om[q0 + ii] : 0.0;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < ntot; e += NTHR) {
-      double acc = 0.0;
-      int o;
-      if (e < nT) {
-        const int a = e % r, b = e / r;
-        for (int q = 0; q < nr; ++q) acc = fma(Vs[q + a * LDT], Qs[q + b * LDT], acc);
-        o = oT + a + b * R;
-      } else if (e < nT + 3 * nC) {
-        const int blk = (e - nT) / nC, ee = (e - nT) % nC;
-        const int a = ee % t, b = ee / t;
-        if (blk == 0) {
-          for (int q = 0; q < nr; ++q) acc = fma(Qs[q + a * LDT] * oms[q], Qs[q + b * LDT], acc);
-          o = oC + a + b * t;
-        } else if (blk == 1) {
-          for (int q = 0; q < nr; ++q)
-            if (oms[q] >= 0.0) acc = fma(Qs[q + a * LDT], Qs[q + b * LDT], acc);
-          o = oEp + a + b * t;
-        } else {
-          for (int q = 0; q < nr; ++q)
-            if (oms[q] < 0.0) acc = fma(Qs[q + a * LDT], Qs[q + b * LDT], acc);
-          o = oEn + a + b * t;
+    if (grp_v) {
+      double xv[3][KSV];
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+#pragma unroll
+        for (int ks = 0; ks < KSV; ++ks) {
+          const int c = 4 * ks + kq;
+          xv[b][ks] = (rin && c < rv[b]) ? Vsrc[b][(int64_t)c * M + q] : 0.0;
         }
-      } else if (e < nT + 3 * nC + nOl) {
-        const int ee = e - nT - 3 * nC;
-        const int a = ee % rl, b = ee / rl;
-        for (int q = 0; q < nr; ++q)
-          if (oms[q] >= 0.0 && q < nr) acc = fma(Vs[q + (r + a) * LDT], Qs[q + b * LDT], acc);
-        o = oOlo + a + b * R;
-      } else {
-        const int ee = e - nT - 3 * nC - nOl;
-        const int a = ee % rh, b = ee / rh;
-        for (int q = 0; q < nr; ++q)
-          if (oms[q] < 0.0) acc = fma(Vs[q + (r + rl + a) * LDT], Qs[q + b * LDT], acc);
-        o = oOhi + a + b * R;
       }
-      out[o] += acc;
+      const double swq = rin ? d.sw[q] : 0.0;
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+#pragma unroll
+        for (int ks = 0; ks < KSV; ++ks) Xs[l16 * LD + 16 * (NCT + b * NCR) + 4 * ks + kq] = xv[b][ks] * swq;
+      }
+    }
+    if (kq == 0) oms[l16] = rin ? om[q] : 0.0;
+#pragma unroll
+    for (int ks = 0; ks < KST; ++ks) Xs[l16 * LD + 4 * ks + kq] = xq[ks];
+    wave_sync();
+#pragma unroll
+    for (int kk = 0; kk < 16; kk += 4) {
+      const double o = oms[kk + kq];
+      const double wp = o >= 0.0 ? 1.0 : 0.0, wn = o < 0.0 ? 1.0 : 0.0;
+      const double* row = Xs + (kk + kq) * LD + l16;
+      double fq[NCT];
+#pragma unroll
+      for (int c = 0; c < NCT; ++c) fq[c] = row[16 * c];
+      if (grp_v) {
+        double fo[NCR], fl[NCR], fh[NCR];
+#pragma unroll
+        for (int c = 0; c < NCR; ++c) {
+          fo[c] = row[16 * (NCT + c)];
+          fl[c] = row[16 * (NCT + NCR + c)] * wp;
+          fh[c] = row[16 * (NCT + 2 * NCR + c)] * wn;
+        }
+#pragma unroll
+        for (int a = 0; a < NCR; ++a)
+#pragma unroll
+          for (int b = 0; b < NCT; ++b) {
+            const int i = a * NCT + b;
+            acc[i] = mfma64(fo[a], fq[b], acc[i]);
+            acc[NRT + i] = mfma64(fl[a], fq[b], acc[NRT + i]);
+            acc[2 * NRT + i] = mfma64(fh[a], fq[b], acc[2 * NRT + i]);
+          }
+      } else {
+        int i = 0;
+#pragma unroll
+        for (int bi = 0; bi < NCT; ++bi) {
+#pragma unroll
+          for (int bj = bi; bj < NCT; ++bj) {
+            acc[i] = mfma64(fq[bi] * o, fq[bj], acc[i]);
+            acc[NBT + i] = mfma64(fq[bi] * wp, fq[bj], acc[NBT + i]);
+            acc[2 * NBT + i] = mfma64(fq[bi] * wn, fq[bj], acc[2 * NBT + i]);
+            ++i;
+          }
+        }
+      }
+    }
+    wave_sync();
+  }
+  pair_reduce_acc<NACC>(acc, lds);
+  double* out = gpart_of(d, s) + (int64_t)blockIdx.x * d.gpTile;
+  const int oC = R * T, oEp = oC + T * T, oEn = oEp + T * T, oOlo = oEn + T * T, oOhi = oOlo + R * T;
+  if (wave == 0) {
+#pragma unroll
+    for (int a = 0; a < NCR; ++a)
+#pragma unroll
+      for (int b = 0; b < NCT; ++b) {
+        const int i = a * NCT + b;
+        store_block(out, R, r, t, a, b, acc[i], 1.0);
+        store_block(out + oOlo, R, rl, t, a, b, acc[NRT + i], 1.0);
+        store_block(out + oOhi, R, rh, t, a, b, acc[2 * NRT + i], 1.0);
+      }
+  } else if (wave == 2) {
+    int i = 0;
+#pragma unroll
+    for (int bi = 0; bi < NCT; ++bi) {
+#pragma unroll
+      for (int bj = bi; bj < NCT; ++bj) {
+        store_sym_block(out + oC, t, t, bi, bj, acc[i], 1.0);
+        store_sym_block(out + oEp, t, t, bi, bj, acc[NBT + i], 1.0);
+        store_sym_block(out + oEn, t, t, bi, bj, acc[2 * NBT + i], 1.0);
+        ++i;
+      }
     }
   }
-}
-
-void launch_ang_reduce(const Dev& d, int axis, int sd0, int nsd, hipStream_t st) {
-  const size_t lds = sizeof(double) * ((size_t)LDT * (d.T + 3 * d.R) + TILE);
-  hipLaunchKernelGGL(k_ang_reduce, dim3(d.nwgM, nsd), dim3(NTHR), lds, st, d, axis, sd0);
 }
 
 // ----------------------------------------------------------------------------
@@ -282,142 +340,131 @@ void launch_ang_reduce(const Dev& d, int axis, int sd0, int nsd, hipStream_t st)
 // coefficient matrices (r x t) come from the eigen-split C = C+ + C-.
 // Also leaves the partial Gram matrix K1^T K1.
 // ----------------------------------------------------------------------------
-__global__ __launch_bounds__(NTHR) void k_kstep(Dev d, int axis, int sd0) {
+template <int NCB>
+__global__ __launch_bounds__(NTHR) void k_kstep(Dev d, int axis, int sd0, int ksr) {
+  constexpr int LD = strip_ld<NCB>();
+  constexpr int NB = NCB * (NCB + 1) / 2;
   const int s = sd0 + blockIdx.y;
   const int lo = neighbour(d, s, axis, -1), hi = neighbour(d, s, axis, +1);
   const int r = d.rank[s], rl = lo >= 0 ? d.rank[lo] : 0, rh = hi >= 0 ? d.rank[hi] : 0;
   const int t = d.tdim[s];
   const int N = d.N, R = d.R;
-  const int T = d.T;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l16 = lane & 15, kq = lane >> 4;
   extern __shared__ double lds[];
-  double* Cf = lds;                 // 7 blocks of R x T (leading dimension R)
-  double* Ks = lds + 7 * R * T;     // LDT x T
-  const double* sm = small_of(d, s);
-  const int offs[7] = {d.oM0, d.oMm, d.oMp, d.oGLo, d.oGHi, d.oGLoN, d.oGHiN};
-  const int rows[7] = {r, r, r, r, r, rl, rh};
-  for (int m = 0; m < 7; ++m) {
-    for (int idx = threadIdx.x; idx < rows[m] * t; idx += NTHR) {
-      int c = idx % rows[m], j = idx / rows[m];
-      Cf[m * R * T + c + j * R] = sm[offs[m] + c + j * R];
+  // fragments of the 7 coefficient blocks: Cf[((m * ksr + ks) * NCB + cb) * 64 + lane]
+  const int nfrag = 7 * ksr * NCB * 64;
+  double* Cf = lds;
+  double* Ys = lds + nfrag + wave * 16 * LD;
+  {
+    const double* sm = small_of(d, s);
+    const int offs[7] = {d.oM0, d.oMm, d.oMp, d.oGLo, d.oGHi, d.oGLoN, d.oGHiN};
+    const int rows[7] = {r, r, r, r, r, rl, rh};
+    for (int idx = threadIdx.x; idx < nfrag; idx += NTHR) {
+      const int l = idx & 63, f = idx >> 6, cb = f % NCB, ks = (f / NCB) % ksr, m = f / (NCB * ksr);
+      const int kc = 4 * ks + (l >> 4), col = 16 * cb + (l & 15);
+      Cf[idx] = (kc < rows[m] && col < t) ? sm[offs[m] + kc + col * R] : 0.0;
     }
   }
   __syncthreads();
-  const double* M0 = Cf;
-  const double* Mm = Cf + 1 * R * T;
-  const double* Mp = Cf + 2 * R * T;
-  const double* GLo = Cf + 3 * R * T;
-  const double* GHi = Cf + 4 * R * T;
-  const double* GLoN = Cf + 5 * R * T;
-  const double* GHiN = Cf + 6 * R * T;
+  auto frag = [&](int m, int ks, int cb) { return Cf[((m * ksr + ks) * NCB + cb) * 64 + lane]; };
 
   const double* Us = d.U + (int64_t)s * N * R;
-  const double* Ul = lo >= 0 ? d.U + (int64_t)lo * N * R : nullptr;
-  const double* Uh = hi >= 0 ? d.U + (int64_t)hi * N * R : nullptr;
-  double* K1 = d.K1 + (int64_t)s * N * T;
+  const double* Ul = lo >= 0 ? d.U + (int64_t)lo * N * R : d.U;
+  const double* Uh = hi >= 0 ? d.U + (int64_t)hi * N * R : d.U;
+  double* K1 = d.K1 + (int64_t)s * N * d.T;
   const int e = axis == 0 ? 1 : d.lnx;
   const int na = axis == 0 ? d.lnx : d.lny;
-  GramAcc g;
-  g.zero();
-  const int i = threadIdx.x % TILE, cg = threadIdx.x / TILE;
-  constexpr int NJ = CAP / (NTHR / TILE);
-  for (int tile = blockIdx.x; tile < d.ntN; tile += gridDim.x) {
-    const int p0 = tile * TILE;
-    const int nr = min(TILE, N - p0);
-    const int p = p0 + i;
-    double acc[NJ];
+  dbl4 g[NB];
+  zero_acc<NB>(g);
+  const int nst = ceil_div(N, 16);
+  for (int st = blockIdx.x * NW + wave; st < nst; st += gridDim.x * NW) {
+    const int p = st * 16 + l16;
+    const bool rin = p < N;
+    const int ix = p % d.lnx, iy = p / d.lnx;
+    const int ia = axis == 0 ? ix : iy;
+    const int f = axis == 0 ? iy : ix;
+    const bool hm = rin && ia > 0, hp = rin && ia < na - 1;
+    const bool flo = rin && ia == 0, fhi = rin && ia == na - 1;
+    double u0[KSR], um[KSR], up[KSR];
 #pragma unroll
-    for (int jj = 0; jj < NJ; ++jj) acc[jj] = 0.0;
-    if (i < nr) {
-      const int ix = p % d.lnx, iy = p / d.lnx;
-      const int ia = axis == 0 ? ix : iy;
-      const int f = axis == 0 ? iy : ix;
-      for (int c = 0; c < r; ++c) {
-        const double u = Us[(int64_t)c * N + p];
+    for (int ks = 0; ks < KSR; ++ks) {
+      const int kc = 4 * ks + kq;
+      const bool kin = ks < ksr && kc < r;
+      const int64_t col = (int64_t)kc * N;
+      u0[ks] = (rin && kin) ? Us[col + p] : 0.0;
+      um[ks] = (hm && kin) ? Us[col + p - e] : 0.0;
+      up[ks] = (hp && kin) ? Us[col + p + e] : 0.0;
+    }
+    dbl4 acc[NCB];
+    zero_acc<NCB>(acc);
 #pragma unroll
-        for (int jj = 0; jj < NJ; ++jj) {
-          const int j = cg + jj * (NTHR / TILE);
-          if (j < t) acc[jj] = fma(u, M0[c + j * R], acc[jj]);
+    for (int ks = 0; ks < KSR; ++ks) {
+      if (ks < ksr) {
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+          acc[cb] = mfma64(frag(0, ks, cb), u0[ks], acc[cb]);
+          acc[cb] = mfma64(frag(1, ks, cb), um[ks], acc[cb]);
+          acc[cb] = mfma64(frag(2, ks, cb), up[ks], acc[cb]);
         }
       }
-      if (ia > 0) {
-        for (int c = 0; c < r; ++c) {
-          const double u = Us[(int64_t)c * N + p - e];
+    }
+    if (__any(flo)) {
+      const int pn = face_cell(d, axis, true, f);
+      double gn[KSR];
 #pragma unroll
-          for (int jj = 0; jj < NJ; ++jj) {
-            const int j = cg + jj * (NTHR / TILE);
-            if (j < t) acc[jj] = fma(u, Mm[c + j * R], acc[jj]);
-          }
-        }
-      } else {
-        for (int c = 0; c < r; ++c) {
-          const double u = Us[(int64_t)c * N + p];
+      for (int ks = 0; ks < KSR; ++ks) {
+        const int kc = 4 * ks + kq;
+        gn[ks] = (flo && lo >= 0 && ks < ksr && kc < rl) ? Ul[(int64_t)kc * N + pn] : 0.0;
+      }
 #pragma unroll
-          for (int jj = 0; jj < NJ; ++jj) {
-            const int j = cg + jj * (NTHR / TILE);
-            if (j < t) acc[jj] = fma(u, GLo[c + j * R], acc[jj]);
-          }
-        }
-        if (lo >= 0) {
-          const int pn = face_cell(d, axis, true, f);
-          for (int c = 0; c < rl; ++c) {
-            const double u = Ul[(int64_t)c * N + pn];
+      for (int ks = 0; ks < KSR; ++ks) {
+        if (ks < ksr) {
+          const double gu = flo ? u0[ks] : 0.0;
 #pragma unroll
-            for (int jj = 0; jj < NJ; ++jj) {
-              const int j = cg + jj * (NTHR / TILE);
-              if (j < t) acc[jj] = fma(u, GLoN[c + j * R], acc[jj]);
-            }
+          for (int cb = 0; cb < NCB; ++cb) {
+            acc[cb] = mfma64(frag(3, ks, cb), gu, acc[cb]);
+            acc[cb] = mfma64(frag(5, ks, cb), gn[ks], acc[cb]);
           }
         }
       }
-      if (ia < na - 1) {
-        for (int c = 0; c < r; ++c) {
-          const double u = Us[(int64_t)c * N + p + e];
+    }
+    if (__any(fhi)) {
+      const int pn = face_cell(d, axis, false, f);
+      double gn[KSR];
 #pragma unroll
-          for (int jj = 0; jj < NJ; ++jj) {
-            const int j = cg + jj * (NTHR / TILE);
-            if (j < t) acc[jj] = fma(u, Mp[c + j * R], acc[jj]);
-          }
-        }
-      } else {
-        for (int c = 0; c < r; ++c) {
-          const double u = Us[(int64_t)c * N + p];
+      for (int ks = 0; ks < KSR; ++ks) {
+        const int kc = 4 * ks + kq;
+        gn[ks] = (fhi && hi >= 0 && ks < ksr && kc < rh) ? Uh[(int64_t)kc * N + pn] : 0.0;
+      }
 #pragma unroll
-          for (int jj = 0; jj < NJ; ++jj) {
-            const int j = cg + jj * (NTHR / TILE);
-            if (j < t) acc[jj] = fma(u, GHi[c + j * R], acc[jj]);
-          }
-        }
-        if (hi >= 0) {
-          const int pn = face_cell(d, axis, false, f);
-          for (int c = 0; c < rh; ++c) {
-            const double u = Uh[(int64_t)c * N + pn];
+      for (int ks = 0; ks < KSR; ++ks) {
+        if (ks < ksr) {
+          const double gu = fhi ? u0[ks] : 0.0;
 #pragma unroll
-            for (int jj = 0; jj < NJ; ++jj) {
-              const int j = cg + jj * (NTHR / TILE);
-              if (j < t) acc[jj] = fma(u, GHiN[c + j * R], acc[jj]);
-            }
+          for (int cb = 0; cb < NCB; ++cb) {
+            acc[cb] = mfma64(frag(4, ks, cb), gu, acc[cb]);
+            acc[cb] = mfma64(frag(6, ks, cb), gn[ks], acc[cb]);
           }
         }
       }
     }
 #pragma unroll
-    for (int jj = 0; jj < NJ; ++jj) {
-      const int j = cg + jj * (NTHR / TILE);
-      if (j < t) {
-        if (i < nr) K1[(int64_t)j * N + p] = acc[jj];
-        Ks[i + j * LDT] = (i < nr) ? acc[jj] : 0.0;
+    for (int cb = 0; cb < NCB; ++cb) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int j = 16 * cb + 4 * v + kq;
+        const double val = rin ? acc[cb][v] : 0.0;
+        if (rin && j < t) K1[(int64_t)j * N + p] = val;
+        Ys[l16 * LD + j] = val;
       }
     }
-    __syncthreads();
-    g.add(Ks, LDT, nr, t);
-    __syncthreads();
+    wave_sync();
+    strip_gram<NCB, LD>(g, Ys);
+    wave_sync();
   }
-  g.store(gpart_of(d, s) + (int64_t)blockIdx.x * d.gpTile, t);
-}
-
-void launch_kstep(const Dev& d, int axis, int sd0, int nsd, hipStream_t st) {
-  const size_t lds = sizeof(double) * ((size_t)7 * d.R * d.T + (size_t)LDT * d.T);
-  hipLaunchKernelGGL(k_kstep, dim3(d.nwgN, nsd), dim3(NTHR), lds, st, d, axis, sd0);
+  wg_reduce_acc<NB>(g, lds);
+  if (wave == 0) store_gram<NCB>(g, gpart_of(d, s) + (int64_t)blockIdx.x * d.gpTile, t, 1.0);
 }
 
 // ----------------------------------------------------------------------------
@@ -427,52 +474,74 @@ void launch_kstep(const Dev& d, int axis, int sd0, int nsd, hipStream_t st) {
 // with Q = h U^1; dividing by h gives h^2 U^T D-+_0 U.  Partial layout:
 // Gm @0, Gp @T*T, both t x t with leading dimension t.
 // ----------------------------------------------------------------------------
+template <int NCB>
 __global__ __launch_bounds__(NTHR) void k_spatial_reduce(Dev d, int axis, int sd0, const double* Q) {
+  // wavefronts 0-1 form Gm, wavefronts 2-3 form Gp; each pair walks the
+  // same strips
+  constexpr int LD = strip_ld<NCB>();
+  constexpr int KS = 4 * NCB;
+  constexpr int NQ = NCB * NCB;
   const int s = sd0 + blockIdx.y;
   const int t = d.tdim[s];
   const int N = d.N, T = d.T;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l16 = lane & 15, kq = lane >> 4;
+  const bool low = wave < 2;
   extern __shared__ double lds[];
-  double* Qs = lds;                 // LDT x T each
-  double* Dm = lds + LDT * T;
-  double* Dp = lds + 2 * LDT * T;
+  double* Qs = lds + wave * 2 * 16 * LD;  // Q strip and its one-sided difference
+  double* Ds = Qs + 16 * LD;
   const double* Qsd = Q + (int64_t)s * N * T;
-  double* out = gpart_of(d, s) + (int64_t)blockIdx.x * d.gpTile;
-  for (int e2 = threadIdx.x; e2 < 2 * t * t; e2 += NTHR) out[(e2 < t * t) ? e2 : (T * T + e2 - t * t)] = 0.0;
   const int e = axis == 0 ? 1 : d.lnx;
   const int na = axis == 0 ? d.lnx : d.lny;
-  for (int tile = blockIdx.x; tile < d.ntN; tile += gridDim.x) {
-    const int p0 = tile * TILE;
-    const int nr = min(TILE, N - p0);
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < TILE * t; idx += NTHR) {
-      const int ii = idx % TILE, c = idx / TILE;
-      double q = 0.0, qm = 0.0, qp = 0.0;
-      if (ii < nr) {
-        const int p = p0 + ii;
-        const int ia = axis == 0 ? (p % d.lnx) : (p / d.lnx);
-        q = Qsd[(int64_t)c * N + p];
-        qm = q - (ia > 0 ? Qsd[(int64_t)c * N + p - e] : 0.0);
-        qp = (ia < na - 1 ? Qsd[(int64_t)c * N + p + e] : 0.0) - q;
+  dbl4 acc[NQ];
+  zero_acc<NQ>(acc);
+  const int nst = ceil_div(N, 16);
+  for (int st = blockIdx.x * 2 + (wave & 1); st < nst; st += gridDim.x * 2) {
+    const int p = st * 16 + l16;
+    const bool rin = p < N;
+    const int ia = axis == 0 ? (p % d.lnx) : (p / d.lnx);
+    // neighbour row across the face this wavefront differences over
+    const bool hn = low ? (rin && ia > 0) : (rin && ia < na - 1);
+    const int pn = low ? p - e : p + e;
+    double x0[KS], xn[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int c = 4 * ks + kq;
+      const int64_t col = (int64_t)c * N;
+      x0[ks] = (rin && c < t) ? Qsd[col + p] : 0.0;
+      xn[ks] = (hn && c < t) ? Qsd[col + pn] : 0.0;
+    }
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int o = l16 * LD + 4 * ks + kq;
+      Qs[o] = x0[ks];
+      Ds[o] = low ? x0[ks] - xn[ks] : xn[ks] - x0[ks];
+    }
+    wave_sync();
+#pragma unroll
+    for (int kk = 0; kk < 16; kk += 4) {
+      const int o = (kk + kq) * LD + l16;
+      double fq[NCB], fd[NCB];
+#pragma unroll
+      for (int c = 0; c < NCB; ++c) {
+        fq[c] = Qs[o + 16 * c];
+        fd[c] = Ds[o + 16 * c];
       }
-      Qs[ii + c * LDT] = q;
-      Dm[ii + c * LDT] = qm;
-      Dp[ii + c * LDT] = qp;
+#pragma unroll
+      for (int bi = 0; bi < NCB; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < NCB; ++bj) acc[bi * NCB + bj] = mfma64(fq[bi], fd[bj], acc[bi * NCB + bj]);
     }
-    __syncthreads();
-    for (int e2 = threadIdx.x; e2 < 2 * t * t; e2 += NTHR) {
-      const int blk = e2 / (t * t), ee = e2 % (t * t);
-      const int a = ee % t, b = ee / t;
-      const double* D = blk == 0 ? Dm : Dp;
-      double acc = 0.0;
-      for (int q = 0; q < nr; ++q) acc = fma(Qs[q + a * LDT], D[q + b * LDT], acc);
-      out[blk * T * T + ee] += acc;
-    }
+    wave_sync();
   }
-}
-
-void launch_spatial_reduce(const Dev& d, int axis, int sd0, int nsd, const double* Q, hipStream_t st) {
-  const size_t lds = sizeof(double) * 3 * (size_t)LDT * d.T;
-  hipLaunchKernelGGL(k_spatial_reduce, dim3(d.nwgN, nsd), dim3(NTHR), lds, st, d, axis, sd0, Q);
+  pair_reduce_acc<NQ>(acc, lds);
+  if ((wave & 1) == 0) {
+    double* out = gpart_of(d, s) + (int64_t)blockIdx.x * d.gpTile + (low ? 0 : T * T);
+#pragma unroll
+    for (int bi = 0; bi < NCB; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < NCB; ++bj) store_block(out, t, t, t, bi, bj, acc[bi * NCB + bj], 1.0);
+  }
 }
 
 // ----------------------------------------------------------------------------
@@ -481,138 +550,176 @@ void launch_spatial_reduce(const Dev& d, int axis, int sd0, int nsd, const doubl
 // with P0 = S2^T, Pm = -dt c Hm^T, Pp = -dt c Hp^T; each direction is
 // upwinded by the sign of its own Omega.  Leaves the partial Gram of AL.
 // ----------------------------------------------------------------------------
-__global__ __launch_bounds__(NTHR) void k_lstep(Dev d, int axis, int sd0) {
+template <int NCB, int KS>
+__global__ __launch_bounds__(NTHR) void k_lstep(Dev d, int axis, int sd0, int kst) {
+  constexpr int LD = strip_ld<NCB>();
+  constexpr int NB = NCB * (NCB + 1) / 2;
   const int s = sd0 + blockIdx.y;
   const int t = d.tdim[s];
   const int M = d.M, T = d.T;
   const double* om = axis == 0 ? d.omx : d.omy;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l16 = lane & 15, kq = lane >> 4;
   extern __shared__ double lds[];
-  double* P = lds;                  // 3 blocks of T x T (leading dimension T)
-  double* Xs = lds + 3 * T * T;     // LDT x T
-  const double* sm = small_of(d, s);
-  for (int idx = threadIdx.x; idx < t * t; idx += NTHR) {
-    const int c = idx % t, j = idx / t;
-    P[c + j * T] = sm[d.oP0 + c + j * T];
-    P[T * T + c + j * T] = sm[d.oPm + c + j * T];
-    P[2 * T * T + c + j * T] = sm[d.oPp + c + j * T];
+  // fragments of P0, Pm, Pp: Pf[((m * kst + ks) * NCB + cb) * 64 + lane]
+  const int nfrag = 3 * kst * NCB * 64;
+  double* Pf = lds;
+  double* Ys = lds + nfrag + wave * 16 * LD;
+  {
+    const double* sm = small_of(d, s);
+    const int offs[3] = {d.oP0, d.oPm, d.oPp};
+    for (int idx = threadIdx.x; idx < nfrag; idx += NTHR) {
+      const int l = idx & 63, f = idx >> 6, cb = f % NCB, ks = (f / NCB) % kst, m = f / (NCB * kst);
+      const int kc = 4 * ks + (l >> 4), col = 16 * cb + (l & 15);
+      Pf[idx] = (kc < t && col < t) ? sm[offs[m] + kc + col * T] : 0.0;
+    }
   }
   __syncthreads();
   const double* Qsd = d.Qh + (int64_t)s * M * T;
   double* ALs = d.AL + (int64_t)s * M * T;
-  GramAcc g;
-  g.zero();
-  const int i = threadIdx.x % TILE, cg = threadIdx.x / TILE;
-  constexpr int NJ = CAP / (NTHR / TILE);
-  for (int tile = blockIdx.x; tile < d.ntM; tile += gridDim.x) {
-    const int q0 = tile * TILE;
-    const int nr = min(TILE, M - q0);
-    for (int idx = threadIdx.x; idx < TILE * t; idx += NTHR) {
-      const int ii = idx % TILE, c = idx / TILE;
-      Xs[ii + c * LDT] = ii < nr ? Qsd[(int64_t)c * M + q0 + ii] : 0.0;
+  dbl4 g[NB];
+  zero_acc<NB>(g);
+  const int nst = ceil_div(M, 16);
+  for (int st = blockIdx.x * NW + wave; st < nst; st += gridDim.x * NW) {
+    const int q = st * 16 + l16;
+    const bool rin = q < M;
+    double xv[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int kc = 4 * ks + kq;
+      xv[ks] = (rin && ks < kst && kc < t) ? Qsd[(int64_t)kc * M + q] : 0.0;
     }
-    __syncthreads();
-    const int q = q0 + i;
-    const double o = (i < nr) ? om[q] : 0.0;
-    const double* Ps = (o >= 0.0) ? P + T * T : P + 2 * T * T;
-    double acc[NJ];
+    const double o = rin ? om[q] : 0.0;
+    const double op = o >= 0.0 ? o : 0.0, on = o < 0.0 ? o : 0.0;
+    dbl4 acc[NCB];
+    zero_acc<NCB>(acc);
 #pragma unroll
-    for (int jj = 0; jj < NJ; ++jj) acc[jj] = 0.0;
-    for (int c = 0; c < t; ++c) {
-      const double x = Xs[i + c * LDT];
+    for (int ks = 0; ks < KS; ++ks) {
+      if (ks < kst) {
+        const double xmv = xv[ks] * op, xpv = xv[ks] * on;
 #pragma unroll
-      for (int jj = 0; jj < NJ; ++jj) {
-        const int j = cg + jj * (NTHR / TILE);
-        if (j < t) acc[jj] = fma(x, fma(o, Ps[c + j * T], P[c + j * T]), acc[jj]);
+        for (int cb = 0; cb < NCB; ++cb) {
+          const int b = (ks * NCB + cb) * 64 + lane;
+          acc[cb] = mfma64(Pf[b], xv[ks], acc[cb]);
+          acc[cb] = mfma64(Pf[b + kst * NCB * 64], xmv, acc[cb]);
+          acc[cb] = mfma64(Pf[b + 2 * kst * NCB * 64], xpv, acc[cb]);
+        }
       }
     }
-    __syncthreads();
 #pragma unroll
-    for (int jj = 0; jj < NJ; ++jj) {
-      const int j = cg + jj * (NTHR / TILE);
-      if (j < t) {
-        if (i < nr) ALs[(int64_t)j * M + q] = acc[jj];
-        Xs[i + j * LDT] = (i < nr) ? acc[jj] : 0.0;
+    for (int cb = 0; cb < NCB; ++cb) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int j = 16 * cb + 4 * v + kq;
+        const double val = rin ? acc[cb][v] : 0.0;
+        if (rin && j < t) ALs[(int64_t)j * M + q] = val;
+        Ys[l16 * LD + j] = val;
       }
     }
-    __syncthreads();
-    g.add(Xs, LDT, nr, t);
-    __syncthreads();
+    wave_sync();
+    strip_gram<NCB, LD>(g, Ys);
+    wave_sync();
   }
-  g.store(gpart_of(d, s) + (int64_t)blockIdx.x * d.gpTile, t);
-}
-
-void launch_lstep(const Dev& d, int axis, int sd0, int nsd, hipStream_t st) {
-  const size_t lds = sizeof(double) * ((size_t)3 * d.T * d.T + (size_t)LDT * d.T);
-  hipLaunchKernelGGL(k_lstep, dim3(d.nwgM, nsd), dim3(NTHR), lds, st, d, axis, sd0);
+  wg_reduce_acc<NB>(g, lds);
+  if (wave == 0) store_gram<NCB>(g, gpart_of(d, s) + (int64_t)blockIdx.x * d.gpTile, t, 1.0);
 }
 
 // ----------------------------------------------------------------------------
 // Collision stage K-step (eq. coll_evolK), K = U S, m = V^T w:
 //   K1[p] = (1 - dt c_t[p]) K[p] + dt (c_s[p]/W) (K[p].m) m + dt Q[p] m
-// Leaves the partial Gram of K1 (r columns).
+// formed from one product U [S | S m], whose last column is K[p].m.  Leaves
+// the partial Gram of K1 (r columns).
 // ----------------------------------------------------------------------------
+template <int NCB>
 __global__ __launch_bounds__(NTHR) void k_coll_kstep(Dev d, int sd0) {
+  constexpr int LD = strip_ld<NCB>();
+  constexpr int NB = NCB * (NCB + 1) / 2;
   const int s = sd0 + blockIdx.y;
   const int r = d.rank[s];
   const int N = d.N, R = d.R;
-  __shared__ double Ss[CAPR * CAPR];
-  __shared__ double mv[CAPR];
-  __shared__ double Ks[LDT * CAPR];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l16 = lane & 15, kq = lane >> 4;
+  __shared__ double Bs[CAPR * (CAPR + 1)];  // [S | S m], leading dimension CAPR
+  __shared__ double mv[16 * NCB];
+  __shared__ double Bf[KSR * NCB * 64];
+  __shared__ double Ysh[NW * 16 * LD];
+  double* Ys = Ysh + wave * 16 * LD;
   const double* sm = small_of(d, s);
   const double* Sg = d.S + (int64_t)s * R * R;
   for (int idx = threadIdx.x; idx < r * r; idx += NTHR) {
     const int a = idx % r, b = idx / r;
-    Ss[a + b * CAPR] = Sg[a + b * R];
+    Bs[a + b * CAPR] = Sg[a + b * R];
   }
-  for (int a = threadIdx.x; a < r; a += NTHR) mv[a] = sm[d.oMv + a];
+  for (int a = threadIdx.x; a < 16 * NCB; a += NTHR) mv[a] = a < r ? sm[d.oMv + a] : 0.0;
   __syncthreads();
+  for (int a = threadIdx.x; a < r; a += NTHR) {
+    double acc = 0.0;
+    for (int b = 0; b < r; ++b) acc = fma(Bs[a + b * CAPR], mv[b], acc);
+    Bs[a + r * CAPR] = acc;
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < KSR * NCB * 64; idx += NTHR) {
+    const int l = idx & 63, f = idx >> 6, cb = f % NCB, ks = f / NCB;
+    const int kc = 4 * ks + (l >> 4), col = 16 * cb + (l & 15);
+    Bf[idx] = (kc < r && col <= r) ? Bs[kc + col * CAPR] : 0.0;
+  }
+  __syncthreads();
+
   const double* Us = d.U + (int64_t)s * N * R;
   const double* cs = d.cs + (int64_t)s * N;
   const double* ct = d.ct + (int64_t)s * N;
   const double* Qs = d.Qsrc + (int64_t)s * N;
   double* K1 = d.K1 + (int64_t)s * N * d.T;
   const double dt = d.dt, iW = 1.0 / d.W;
-  GramAcc g;
-  g.zero();
-  const int i = threadIdx.x % TILE, cg = threadIdx.x / TILE;
-  for (int tile = blockIdx.x; tile < d.ntN; tile += gridDim.x) {
-    const int p0 = tile * TILE;
-    const int nr = min(TILE, N - p0);
-    const int p = p0 + i;
-    double Kp[CAPR];
+  const int ksr = ceil_div(r, 4);
+  const int src_lane = l16 + 16 * (r & 3);  // lane holding column r of this row
+  dbl4 g[NB];
+  zero_acc<NB>(g);
+  const int nst = ceil_div(N, 16);
+  for (int st = blockIdx.x * NW + wave; st < nst; st += gridDim.x * NW) {
+    const int p = st * 16 + l16;
+    const bool rin = p < N;
+    double xv[KSR];
 #pragma unroll
-    for (int b = 0; b < CAPR; ++b) Kp[b] = 0.0;
-    double km = 0.0;
-    if (i < nr) {
-      for (int a = 0; a < r; ++a) {
-        const double u = Us[(int64_t)a * N + p];
-#pragma unroll
-        for (int b = 0; b < CAPR; ++b)
-          if (b < r) Kp[b] = fma(u, Ss[a + b * CAPR], Kp[b]);
-      }
-#pragma unroll
-      for (int b = 0; b < CAPR; ++b)
-        if (b < r) km = fma(Kp[b], mv[b], km);
+    for (int ks = 0; ks < KSR; ++ks) {
+      const int kc = 4 * ks + kq;
+      xv[ks] = (rin && kc < r) ? Us[(int64_t)kc * N + p] : 0.0;
     }
-    const double a0 = (i < nr) ? 1.0 - dt * ct[p] : 0.0;
-    const double a1 = (i < nr) ? dt * (cs[p] * iW * km + Qs[p]) : 0.0;
+    const double ctp = rin ? ct[p] : 0.0, csp = rin ? cs[p] : 0.0, qp = rin ? Qs[p] : 0.0;
+    dbl4 acc[NCB];
+    zero_acc<NCB>(acc);
 #pragma unroll
-    for (int b = 0; b < CAPR; ++b) {
-      if (b < r && (b % (NTHR / TILE)) == cg) {
-        const double v = (i < nr) ? fma(a0, Kp[b], a1 * mv[b]) : 0.0;
-        if (i < nr) K1[(int64_t)b * N + p] = v;
-        Ks[i + b * LDT] = v;
+    for (int ks = 0; ks < KSR; ++ks) {
+      if (ks < ksr) {
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) acc[cb] = mfma64(Bf[(ks * NCB + cb) * 64 + lane], xv[ks], acc[cb]);
       }
     }
-    __syncthreads();
-    g.add(Ks, LDT, nr, r);
-    __syncthreads();
+    double kmv = 0.0;
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        if (16 * cb + 4 * v + kq == r) kmv = acc[cb][v];
+    const double km = __shfl(kmv, src_lane, 64);
+    const double a0 = rin ? 1.0 - dt * ctp : 0.0;
+    const double a1 = rin ? dt * (csp * iW * km + qp) : 0.0;
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int j = 16 * cb + 4 * v + kq;
+        const double val = (rin && j < r) ? fma(a0, acc[cb][v], a1 * mv[j]) : 0.0;
+        if (rin && j < r) K1[(int64_t)j * N + p] = val;
+        Ys[l16 * LD + j] = val;
+      }
+    }
+    wave_sync();
+    strip_gram<NCB, LD>(g, Ys);
+    wave_sync();
   }
-  g.store(gpart_of(d, s) + (int64_t)blockIdx.x * d.gpTile, r);
-}
-
-void launch_coll_kstep(const Dev& d, int sd0, int nsd, hipStream_t st) {
-  hipLaunchKernelGGL(k_coll_kstep, dim3(d.nwgN, nsd), dim3(NTHR), 0, st, d, sd0);
+  wg_reduce_acc<NB>(g, Ysh);
+  if (wave == 0) store_gram<NCB>(g, gpart_of(d, s) + (int64_t)blockIdx.x * d.gpTile, r, 1.0);
 }
 
 // ----------------------------------------------------------------------------
@@ -620,60 +727,83 @@ void launch_coll_kstep(const Dev& d, int sd0, int nsd, hipStream_t st) {
 // state buffer):  Gs = h^2 U^T diag(c_s) U,  Gt = h^2 U^T diag(c_t) U,
 // qv = h^2 U^T Q.  Partial layout: Gs @0, Gt @R*R (ld R), qv @2R*R.
 // ----------------------------------------------------------------------------
+template <int NCB>
 __global__ __launch_bounds__(NTHR) void k_coll_reduce(Dev d, int sd0) {
+  constexpr int LD = strip_ld<NCB>();
+  constexpr int NB = NCB * (NCB + 1) / 2;
+  constexpr int NACC = 2 * NB + NCB;
+  constexpr int KS = 4 * NCB;
   const int s = sd0 + blockIdx.y;
   const int r = d.rank[s];
   const int N = d.N, R = d.R;
-  __shared__ double Us[LDT * CAPR];
-  __shared__ double w3[3 * TILE];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l16 = lane & 15, kq = lane >> 4;
+  __shared__ double sh[NW * (16 * LD + 48)];
+  __shared__ double red[NACC * 256];
+  double* Us = sh + wave * (16 * LD + 48);  // strip, then c_s, c_t, Q of its rows
+  double* wv = Us + 16 * LD;
   const double* Ug = d.U + (int64_t)s * N * R;
   const double* cs = d.cs + (int64_t)s * N;
   const double* ct = d.ct + (int64_t)s * N;
   const double* Qg = d.Qsrc + (int64_t)s * N;
-  double* out = gpart_of(d, s) + (int64_t)blockIdx.x * d.gpTile;
-  const int ntot = 2 * r * r + r;
-  for (int e = threadIdx.x; e < ntot; e += NTHR) {
-    int o;
-    if (e < 2 * r * r) { const int blk = e / (r * r), ee = e % (r * r); o = blk * R * R + (ee % r) + (ee / r) * R; }
-    else o = 2 * R * R + (e - 2 * r * r);
-    out[o] = 0.0;
-  }
-  const double h2 = d.h * d.h;
-  for (int tile = blockIdx.x; tile < d.ntN; tile += gridDim.x) {
-    const int p0 = tile * TILE;
-    const int nr = min(TILE, N - p0);
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < TILE * r; idx += NTHR) {
-      const int ii = idx % TILE, c = idx / TILE;
-      Us[ii + c * LDT] = ii < nr ? Ug[(int64_t)c * N + p0 + ii] : 0.0;
+  dbl4 acc[NACC];
+  zero_acc<NACC>(acc);
+  const int nst = ceil_div(N, 16);
+  for (int st = blockIdx.x * NW + wave; st < nst; st += gridDim.x * NW) {
+    const int p = st * 16 + l16;
+    const bool rin = p < N;
+    double xv[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int c = 4 * ks + kq;
+      xv[ks] = (rin && c < r) ? Ug[(int64_t)c * N + p] : 0.0;
     }
-    for (int ii = threadIdx.x; ii < TILE; ii += NTHR) {
-      w3[ii] = ii < nr ? cs[p0 + ii] : 0.0;
-      w3[TILE + ii] = ii < nr ? ct[p0 + ii] : 0.0;
-      w3[2 * TILE + ii] = ii < nr ? Qg[p0 + ii] : 0.0;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < ntot; e += NTHR) {
-      double acc = 0.0;
-      int o;
-      if (e < 2 * r * r) {
-        const int blk = e / (r * r), ee = e % (r * r);
-        const int a = ee % r, b = ee / r;
-        const double* wt = w3 + blk * TILE;
-        for (int q = 0; q < nr; ++q) acc = fma(Us[q + a * LDT] * wt[q], Us[q + b * LDT], acc);
-        o = blk * R * R + a + b * R;
-      } else {
-        const int a = e - 2 * r * r;
-        for (int q = 0; q < nr; ++q) acc = fma(Us[q + a * LDT], w3[2 * TILE + q], acc);
-        o = 2 * R * R + a;
+    double wsrc = 0.0;
+    if (rin) wsrc = kq == 0 ? cs[p] : (kq == 1 ? ct[p] : (kq == 2 ? Qg[p] : 0.0));
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) Us[l16 * LD + 4 * ks + kq] = xv[ks];
+    if (kq < 3) wv[kq * 16 + l16] = wsrc;
+    wave_sync();
+#pragma unroll
+    for (int kk = 0; kk < 16; kk += 4) {
+      const int row = kk + kq;
+      const double ws = wv[row], wt = wv[16 + row], wq = wv[32 + row];
+      double f[NCB];
+#pragma unroll
+      for (int c = 0; c < NCB; ++c) f[c] = Us[row * LD + 16 * c + l16];
+      int idx = 0;
+#pragma unroll
+      for (int bi = 0; bi < NCB; ++bi) {
+#pragma unroll
+        for (int bj = bi; bj < NCB; ++bj) {
+          acc[idx] = mfma64(f[bi] * ws, f[bj], acc[idx]);
+          acc[idx + NB] = mfma64(f[bi] * wt, f[bj], acc[idx + NB]);
+          ++idx;
+        }
       }
-      out[o] += h2 * acc;
+      const double bq = l16 == 0 ? wq : 0.0;
+#pragma unroll
+      for (int c = 0; c < NCB; ++c) acc[2 * NB + c] = mfma64(f[c], bq, acc[2 * NB + c]);
     }
+    wave_sync();
   }
-}
-
-void launch_coll_reduce(const Dev& d, int sd0, int nsd, hipStream_t st) {
-  hipLaunchKernelGGL(k_coll_reduce, dim3(d.nwgN, nsd), dim3(NTHR), 0, st, d, sd0);
+  wg_reduce_acc<NACC>(acc, red);
+  if (wave == 0) {
+    double* out = gpart_of(d, s) + (int64_t)blockIdx.x * d.gpTile;
+    const double h2 = d.h * d.h;
+    int idx = 0;
+#pragma unroll
+    for (int bi = 0; bi < NCB; ++bi) {
+#pragma unroll
+      for (int bj = bi; bj < NCB; ++bj) {
+        store_sym_block(out, R, r, bi, bj, acc[idx], h2);
+        store_sym_block(out + R * R, R, r, bi, bj, acc[idx + NB], h2);
+        ++idx;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < NCB; ++c) store_block(out + 2 * R * R, 1, r, 1, c, 0, acc[2 * NB + c], h2);
+  }
 }
 
 // ----------------------------------------------------------------------------
@@ -681,62 +811,68 @@ void launch_coll_reduce(const Dev& d, int sd0, int nsd, hipStream_t st) {
 //   AL[q,:] = sqrt(w_q) (V[q,:] P + crow),  P = S2^T (I - dt Gt),
 //   crow = dt ((S2 m)^T Gs / W + q^T).  Leaves the partial Gram of AL.
 // ----------------------------------------------------------------------------
+template <int NCB>
 __global__ __launch_bounds__(NTHR) void k_coll_lstep(Dev d, int sd0) {
+  constexpr int LD = strip_ld<NCB>();
+  constexpr int NB = NCB * (NCB + 1) / 2;
   const int s = sd0 + blockIdx.y;
   const int r = d.rank[s];
   const int M = d.M, R = d.R;
-  __shared__ double Ps[CAPR * CAPR];
-  __shared__ double cr[CAPR];
-  __shared__ double Xs[LDT * CAPR];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l16 = lane & 15, kq = lane >> 4;
+  __shared__ double cr[16 * NCB];
+  __shared__ double Bf[KSR * NCB * 64];
+  __shared__ double Ysh[NW * 16 * LD];
+  double* Ys = Ysh + wave * 16 * LD;
   const double* sm = small_of(d, s);
-  for (int idx = threadIdx.x; idx < r * r; idx += NTHR) {
-    const int a = idx % r, b = idx / r;
-    Ps[a + b * CAPR] = sm[d.oP0 + a + b * R];
+  for (int idx = threadIdx.x; idx < KSR * NCB * 64; idx += NTHR) {
+    const int l = idx & 63, f = idx >> 6, cb = f % NCB, ks = f / NCB;
+    const int kc = 4 * ks + (l >> 4), col = 16 * cb + (l & 15);
+    Bf[idx] = (kc < r && col < r) ? sm[d.oP0 + kc + col * R] : 0.0;
   }
-  for (int a = threadIdx.x; a < r; a += NTHR) cr[a] = sm[d.oCrow + a];
+  for (int a = threadIdx.x; a < 16 * NCB; a += NTHR) cr[a] = a < r ? sm[d.oCrow + a] : 0.0;
   __syncthreads();
   const double* Vs = d.V + (int64_t)s * M * R;
   double* ALs = d.AL + (int64_t)s * M * d.T;
-  GramAcc g;
-  g.zero();
-  const int i = threadIdx.x % TILE, cg = threadIdx.x / TILE;
-  for (int tile = blockIdx.x; tile < d.ntM; tile += gridDim.x) {
-    const int q0 = tile * TILE;
-    const int nr = min(TILE, M - q0);
-    for (int idx = threadIdx.x; idx < TILE * r; idx += NTHR) {
-      const int ii = idx % TILE, c = idx / TILE;
-      Xs[ii + c * LDT] = ii < nr ? Vs[(int64_t)c * M + q0 + ii] : 0.0;
+  const int ksr = ceil_div(r, 4);
+  dbl4 g[NB];
+  zero_acc<NB>(g);
+  const int nst = ceil_div(M, 16);
+  for (int st = blockIdx.x * NW + wave; st < nst; st += gridDim.x * NW) {
+    const int q = st * 16 + l16;
+    const bool rin = q < M;
+    double xv[KSR];
+#pragma unroll
+    for (int ks = 0; ks < KSR; ++ks) {
+      const int kc = 4 * ks + kq;
+      xv[ks] = (rin && kc < r) ? Vs[(int64_t)kc * M + q] : 0.0;
     }
-    __syncthreads();
-    const int q = q0 + i;
-    double acc[CAPR];
+    const double swq = rin ? d.sw[q] : 0.0;
+    dbl4 acc[NCB];
+    zero_acc<NCB>(acc);
 #pragma unroll
-    for (int b = 0; b < CAPR; ++b) acc[b] = 0.0;
-    for (int c = 0; c < r; ++c) {
-      const double x = Xs[i + c * LDT];
+    for (int ks = 0; ks < KSR; ++ks) {
+      if (ks < ksr) {
 #pragma unroll
-      for (int b = 0; b < CAPR; ++b)
-        if (b < r) acc[b] = fma(x, Ps[c + b * CAPR], acc[b]);
-    }
-    const double swq = (i < nr) ? d.sw[q] : 0.0;
-    __syncthreads();
-#pragma unroll
-    for (int b = 0; b < CAPR; ++b) {
-      if (b < r && (b % (NTHR / TILE)) == cg) {
-        const double v = swq * (acc[b] + cr[b]);
-        if (i < nr) ALs[(int64_t)b * M + q] = v;
-        Xs[i + b * LDT] = (i < nr) ? v : 0.0;
+        for (int cb = 0; cb < NCB; ++cb) acc[cb] = mfma64(Bf[(ks * NCB + cb) * 64 + lane], xv[ks], acc[cb]);
       }
     }
-    __syncthreads();
-    g.add(Xs, LDT, nr, r);
-    __syncthreads();
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int j = 16 * cb + 4 * v + kq;
+        const double val = (rin && j < r) ? swq * (acc[cb][v] + cr[j]) : 0.0;
+        if (rin && j < r) ALs[(int64_t)j * M + q] = val;
+        Ys[l16 * LD + j] = val;
+      }
+    }
+    wave_sync();
+    strip_gram<NCB, LD>(g, Ys);
+    wave_sync();
   }
-  g.store(gpart_of(d, s) + (int64_t)blockIdx.x * d.gpTile, r);
-}
-
-void launch_coll_lstep(const Dev& d, int sd0, int nsd, hipStream_t st) {
-  hipLaunchKernelGGL(k_coll_lstep, dim3(d.nwgM, nsd), dim3(NTHR), 0, st, d, sd0);
+  wg_reduce_acc<NB>(g, Ysh);
+  if (wave == 0) store_gram<NCB>(g, gpart_of(d, s) + (int64_t)blockIdx.x * d.gpTile, r, 1.0);
 }
 
 // ----------------------------------------------------------------------------
@@ -779,6 +915,137 @@ __global__ __launch_bounds__(NTHR) void k_moments(Dev d) {
   }
 }
 
+// ============================================================================
+// Host-side launchers: pick the template instance from the capacities.
+// ============================================================================
+namespace {
+
+template <int V>
+using ic = std::integral_constant<int, V>;
+
+// column blocks of 16 covering a capacity of n columns (1..4)
+int ncb_of(int n) { return n <= 16 ? 1 : (n <= 32 ? 2 : (n <= 48 ? 3 : 4)); }
+
+template <class F>
+void with_ncb(int ncb, F f) {
+  switch (ncb) {
+    case 1: f(ic<1>{}); break;
+    case 2: f(ic<2>{}); break;
+    case 3: f(ic<3>{}); break;
+    default: f(ic<4>{}); break;
+  }
+}
+
+// k-steps of 4 in buckets of 16 columns (4, 8, 12, 16)
+template <class F>
+void with_ks(int kcap, F f) {
+  with_ncb(ncb_of(kcap), [&](auto nk) { f(ic<4 * decltype(nk)::value>{}); });
+}
+
+constexpr size_t D8 = sizeof(double);
+
+// 160 KB of LDS per compute unit, less room for a kernel's static LDS
+void allow_lds(const void* fn) {
+  (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 159 * 1024);
+}
+
+}  // namespace
+
+void launch_aug_form(const Dev& d, int axis, int sd0, int nsd, hipStream_t st) {
+  const int nc = ncb_of(d.MA);
+  with_ncb(nc, [&](auto c) {
+    constexpr int NC = decltype(c)::value;
+    constexpr int KS = 4 * NC;
+    const size_t lds = D8 * std::max<size_t>(KS * NC * 64 + NW * 16 * strip_ld<NC>(), (size_t)NC * (NC + 1) / 2 * 256);
+    hipLaunchKernelGGL((k_aug_form<NC, KS>), dim3(d.nwgM, nsd), dim3(NTHR), lds, st, d, axis, sd0);
+  });
+}
+
+static int dim_cap(const Dev& d, int which) { return which == DIM_M0 ? d.MA : (which == DIM_T ? d.T : d.R); }
+
+void launch_gemm(const Dev& d, int axis, int sd0, int nsd, const double* X, int64_t xsd, int rows, int kdim,
+                 int ndim, int boff, int bld, double* Y, int64_t ysd, const double* rowscale, bool gram,
+                 int fill_off, bool rows_are_cells, hipStream_t st) {
+  const int nwg = rows_are_cells ? d.nwgN : d.nwgM;
+  with_ncb(ncb_of(dim_cap(d, ndim)), [&](auto c) {
+    constexpr int NC = decltype(c)::value;
+    with_ks(dim_cap(d, kdim), [&](auto k) {
+      constexpr int KS = decltype(k)::value;
+      const size_t lds =
+          D8 * std::max<size_t>(KS * NC * 64 + NW * 16 * strip_ld<NC>(), (size_t)NC * (NC + 1) / 2 * 256);
+      hipLaunchKernelGGL((k_gemm<NC, KS>), dim3(nwg, nsd), dim3(NTHR), lds, st, d, axis, sd0, X, xsd, rows, kdim,
+                         ndim, boff, bld, Y, ysd, rowscale, gram ? 1 : 0, fill_off);
+    });
+  });
+}
+
+void launch_ang_reduce(const Dev& d, int axis, int sd0, int nsd, hipStream_t st) {
+  with_ncb(ncb_of(d.T), [&](auto ct) {
+    constexpr int NT = decltype(ct)::value;
+    with_ncb(ncb_of(d.R), [&](auto cr) {
+      constexpr int NR = decltype(cr)::value;
+      constexpr int NACC = std::max(3 * NR * NT, 3 * NT * (NT + 1) / 2);
+      const size_t lds = D8 * std::max<size_t>(NW * (16 * (16 * (NT + 3 * NR) + 1) + 16), (size_t)2 * NACC * 256);
+      if constexpr (NR <= 2)  // stored ranks are at most 21
+        hipLaunchKernelGGL((k_ang_reduce<NT, NR>), dim3(d.nwgM, nsd), dim3(NTHR), lds, st, d, axis, sd0);
+    });
+  });
+}
+
+void launch_kstep(const Dev& d, int axis, int sd0, int nsd, hipStream_t st) {
+  const int ksr = ceil_div(d.R, 4);
+  with_ncb(ncb_of(d.T), [&](auto c) {
+    constexpr int NC = decltype(c)::value;
+    const size_t lds =
+        D8 * std::max<size_t>(7 * ksr * NC * 64 + NW * 16 * strip_ld<NC>(), (size_t)NC * (NC + 1) / 2 * 256);
+    hipLaunchKernelGGL((k_kstep<NC>), dim3(d.nwgN, nsd), dim3(NTHR), lds, st, d, axis, sd0, ksr);
+  });
+}
+
+void launch_spatial_reduce(const Dev& d, int axis, int sd0, int nsd, const double* Q, hipStream_t st) {
+  with_ncb(ncb_of(d.T), [&](auto c) {
+    constexpr int NC = decltype(c)::value;
+    const size_t lds = D8 * std::max<size_t>(NW * 2 * 16 * strip_ld<NC>(), (size_t)2 * NC * NC * 256);
+    hipLaunchKernelGGL((k_spatial_reduce<NC>), dim3(d.nwgN, nsd), dim3(NTHR), lds, st, d, axis, sd0, Q);
+  });
+}
+
+void launch_lstep(const Dev& d, int axis, int sd0, int nsd, hipStream_t st) {
+  const int kst = ceil_div(d.T, 4);
+  with_ncb(ncb_of(d.T), [&](auto c) {
+    constexpr int NC = decltype(c)::value;
+    constexpr int KS = 4 * NC;
+    const size_t lds =
+        D8 * std::max<size_t>(3 * kst * NC * 64 + NW * 16 * strip_ld<NC>(), (size_t)NC * (NC + 1) / 2 * 256);
+    hipLaunchKernelGGL((k_lstep<NC, KS>), dim3(d.nwgM, nsd), dim3(NTHR), lds, st, d, axis, sd0, kst);
+  });
+}
+
+void launch_coll_kstep(const Dev& d, int sd0, int nsd, hipStream_t st) {
+  // one column beyond the rank carries K.m
+  with_ncb(ncb_of(d.R + 1), [&](auto c) {
+    constexpr int NC = decltype(c)::value;
+    if constexpr (NC <= 2)
+      hipLaunchKernelGGL((k_coll_kstep<NC>), dim3(d.nwgN, nsd), dim3(NTHR), 0, st, d, sd0);
+  });
+}
+
+void launch_coll_reduce(const Dev& d, int sd0, int nsd, hipStream_t st) {
+  with_ncb(ncb_of(d.R), [&](auto c) {
+    constexpr int NC = decltype(c)::value;
+    if constexpr (NC <= 2)
+      hipLaunchKernelGGL((k_coll_reduce<NC>), dim3(d.nwgN, nsd), dim3(NTHR), 0, st, d, sd0);
+  });
+}
+
+void launch_coll_lstep(const Dev& d, int sd0, int nsd, hipStream_t st) {
+  with_ncb(ncb_of(d.R), [&](auto c) {
+    constexpr int NC = decltype(c)::value;
+    if constexpr (NC <= 2)
+      hipLaunchKernelGGL((k_coll_lstep<NC>), dim3(d.nwgM, nsd), dim3(NTHR), 0, st, d, sd0);
+  });
+}
+
 void launch_moments(const Dev& d, hipStream_t st) {
   const int nb = (d.N + NTHR - 1) / NTHR;
   hipLaunchKernelGGL(k_moments, dim3(nb < 16 ? nb : 16, d.nsub), dim3(NTHR), 0, st, d);
@@ -786,13 +1053,30 @@ void launch_moments(const Dev& d, hipStream_t st) {
 
 // Allow the dynamically sized kernels the whole LDS of a compute unit.
 void init_kernels() {
-  const int max_lds = 160 * 1024;
-  (void)hipFuncSetAttribute((const void*)k_aug_form, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
-  (void)hipFuncSetAttribute((const void*)k_gemm, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds - 256);
-  (void)hipFuncSetAttribute((const void*)k_ang_reduce, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
-  (void)hipFuncSetAttribute((const void*)k_kstep, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
-  (void)hipFuncSetAttribute((const void*)k_spatial_reduce, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
-  (void)hipFuncSetAttribute((const void*)k_lstep, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+  for (int nc = 1; nc <= 4; ++nc) {
+    with_ncb(nc, [&](auto c) {
+      constexpr int NC = decltype(c)::value;
+      allow_lds((const void*)k_aug_form<NC, 4 * NC>);
+      allow_lds((const void*)k_kstep<NC>);
+      allow_lds((const void*)k_spatial_reduce<NC>);
+      allow_lds((const void*)k_lstep<NC, 4 * NC>);
+      for (int kc = 1; kc <= 4; ++kc) {
+        with_ncb(kc, [&](auto k) {
+          constexpr int KS = 4 * decltype(k)::value;
+          allow_lds((const void*)k_gemm<NC, KS>);
+        });
+      }
+      for (int nr = 1; nr <= 2; ++nr) {
+        with_ncb(nr, [&](auto r) {
+          constexpr int NR = decltype(r)::value;
+          if constexpr (NR <= 2) allow_lds((const void*)k_ang_reduce<NC, NR>);
+        });
+      }
+    });
+  }
+  // an attribute the runtime refused would otherwise surface at the first
+  // launch check; a kernel that then lacks LDS fails its own launch instead
+  (void)hipGetLastError();
 }
 
 }  // namespace dd
