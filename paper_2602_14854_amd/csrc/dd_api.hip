@@ -41,14 +41,14 @@ namespace {
 thread_local std::string g_err;
 
 enum Kind {
-  K_AUG_FORM, K_AUG_EIG1, K_GEMM_AUG_ROT, K_AUG_EIG2, K_GEMM_VHAT, K_CHOL, K_GEMM_QR_VHAT, K_ANG_REDUCE,
+  K_AUG_FORM, K_GEMM_QR_A, K_AUG_SVD, K_GEMM_VHAT, K_CHOL, K_GEMM_QR_VHAT, K_ANG_REDUCE,
   K_ADV_PREP, K_KSTEP, K_GEMM_QR_K, K_SPATIAL_REDUCE, K_ADV_SSTEP, K_LSTEP, K_GEMM_QR_L, K_TRUNC,
   K_GEMM_FINAL_U, K_GEMM_FINAL_V, K_SET_RANK, K_COLL_PREP, K_COLL_KSTEP, K_COLL_REDUCE, K_COLL_SSTEP,
   K_COLL_LSTEP, K_COLL_FINAL, K_COUNT
 };
 
 const char* const kKindName[K_COUNT] = {
-  "k_aug_form", "s_aug_eig1", "k_gemm[aug Z=A*Y1]", "s_aug_eig2", "k_gemm[V-hat=Z*Coef]", "s_chol",
+  "k_aug_form", "k_gemm[QR A]", "s_aug_svd", "k_gemm[V-hat=A*Coef]", "s_chol",
   "k_gemm[QR V-hat]", "k_ang_reduce", "s_adv_prep", "k_kstep", "k_gemm[QR K1]", "k_spatial_reduce",
   "s_adv_sstep", "k_lstep", "k_gemm[QR L1]", "s_trunc", "k_gemm[U=Q*Bu]", "k_gemm[V=QL*Bv]", "s_set_rank",
   "s_coll_prep", "k_coll_kstep", "k_coll_reduce", "s_coll_sstep", "k_coll_lstep", "s_coll_final",
@@ -136,9 +136,9 @@ Layout make_layout(const dd_dlra_config* c) {
     return r;
   };
   int k = 0;
-  f[k++] = take(MA * MA);  // Y1
+  f[k++] = take(MA * MA);  // RaccA (Cholesky-QR factor of the augmentation matrix)
   f[k++] = take(MA * T);   // Coef
-  f[k++] = take(T);        // Fill
+  f[k++] = take(std::max(T, MA));  // Fill
   f[k++] = take(T * T);    // Rinv
   f[k++] = take(T * T);    // Racc
   f[k++] = take(T * T);    // Cp
@@ -168,6 +168,7 @@ Layout make_layout(const dd_dlra_config* c) {
   f[k++] = take(R * R);    // Gt
   f[k++] = take(R);        // Qv
   for (int i = 0; i < 6; ++i) f[k++] = take(T * T);  // W1..W6
+  f[k++] = take(MA * MA);  // RinvA
   L.smallStride = o;
   // arena
   const size_t d8 = sizeof(double);
@@ -269,7 +270,7 @@ void fill_dev(Dev& d, const Layout& L, const dd_dlra_config* c, char* base) {
   d.clamps = (unsigned long long*)(base + L.oFlags + 8);
   const int* f = L.off;
   int k = 0;
-  d.oY1 = f[k++]; d.oCoef = f[k++]; d.oFill = f[k++]; d.oRinv = f[k++]; d.oRacc = f[k++];
+  d.oRaccA = f[k++]; d.oCoef = f[k++]; d.oFill = f[k++]; d.oRinv = f[k++]; d.oRacc = f[k++];
   d.oCp = f[k++]; d.oCn = f[k++]; d.oAm = f[k++];
   d.oM0 = f[k++]; d.oMm = f[k++]; d.oMp = f[k++]; d.oGLo = f[k++]; d.oGHi = f[k++]; d.oGLoN = f[k++]; d.oGHiN = f[k++];
   d.oEp = f[k++]; d.oEn = f[k++]; d.oOlo = f[k++]; d.oOhi = f[k++]; d.oTm = f[k++];
@@ -277,6 +278,7 @@ void fill_dev(Dev& d, const Layout& L, const dd_dlra_config* c, char* base) {
   d.oP0 = f[k++]; d.oPm = f[k++]; d.oPp = f[k++]; d.oBu = f[k++]; d.oBv = f[k++];
   d.oSig = f[k++]; d.oMv = f[k++]; d.oCrow = f[k++]; d.oGs = f[k++]; d.oGt = f[k++]; d.oQv = f[k++];
   d.oW1 = f[k++]; d.oW2 = f[k++]; d.oW3 = f[k++]; d.oW4 = f[k++]; d.oW5 = f[k++]; d.oW6 = f[k++];
+  d.oRinvA = f[k++];
 }
 
 std::string check_factors(const dd_dlra_config* c, const Layout& L, const int32_t* rank, const double* const* U,
@@ -387,17 +389,23 @@ void chol_qr3(dd_dlra_handle h, int axis, int ndim, double* X, double* Y, int64_
   const Dev& d = h->d;
   hipStream_t st = h->stream;
   const int ngp = cells ? d.nwgN : d.nwgM;
-  phase(h, K_CHOL, [&](int s0, int ns) { dd::launch_chol(d, axis, s0, ns, ndim, rows, ngp, true, 1, 1.0, st); });
+  phase(h, K_CHOL, [&](int s0, int ns) {
+    dd::launch_chol(d, axis, s0, ns, ndim, rows, ngp, true, 1, 1.0, false, d.oRinv, d.oRacc, d.T, st);
+  });
   phase(h, gemm_kind, [&](int s0, int ns) {
     dd::launch_gemm(d, axis, s0, ns, X, sdstride, rows, ndim, ndim, d.oRinv, d.T, Y, sdstride, nullptr, true, d.oFill,
                     cells, st);
   });
-  phase(h, K_CHOL, [&](int s0, int ns) { dd::launch_chol(d, axis, s0, ns, ndim, rows, ngp, false, 2, 1.0, st); });
+  phase(h, K_CHOL, [&](int s0, int ns) {
+    dd::launch_chol(d, axis, s0, ns, ndim, rows, ngp, false, 2, 1.0, false, d.oRinv, d.oRacc, d.T, st);
+  });
   phase(h, gemm_kind, [&](int s0, int ns) {
     dd::launch_gemm(d, axis, s0, ns, Y, sdstride, rows, ndim, ndim, d.oRinv, d.T, X, sdstride, nullptr, true, d.oFill,
                     cells, st);
   });
-  phase(h, K_CHOL, [&](int s0, int ns) { dd::launch_chol(d, axis, s0, ns, ndim, rows, ngp, false, 2, bscale, st); });
+  phase(h, K_CHOL, [&](int s0, int ns) {
+    dd::launch_chol(d, axis, s0, ns, ndim, rows, ngp, false, 2, bscale, false, d.oRinv, d.oRacc, d.T, st);
+  });
   double* dst = final_dst ? final_dst : Y;
   const int64_t dsd = final_dst ? final_sd : sdstride;
   phase(h, gemm_kind, [&](int s0, int ns) {
@@ -410,24 +418,35 @@ void enqueue_advection(dd_dlra_handle h, int axis) {
   const Dev& d = h->d;
   hipStream_t st = h->stream;
   const int64_t sdMA = (int64_t)d.M * d.MA, sdMT = (int64_t)d.M * d.T, sdNT = (int64_t)d.N * d.T;
-  // Algorithm 4: augmentation, weighted SVD of L0 by two Gram/Jacobi passes
+  // Algorithm 4: augmentation.  A = sqrt(w) L0 = Q RaccA by three passes of
+  // shifted Cholesky QR (the first one pivoted; Q itself is not kept), then
+  // the SVD of the small factor and V-hat = A B Sigma^-2.
   phase(h, K_AUG_FORM, [&](int s0, int ns) { dd::launch_aug_form(d, axis, s0, ns, st); });
-  phase(h, K_AUG_EIG1, [&](int s0, int ns) { dd::launch_aug_eig1(d, axis, s0, ns, st); });
-  phase(h, K_GEMM_AUG_ROT, [&](int s0, int ns) {
-    dd::launch_gemm(d, axis, s0, ns, d.A, sdMA, d.M, dd::DIM_M0, dd::DIM_M0, d.oY1, d.MA, d.Z, sdMA, nullptr, true, -1,
-                    false, st);
-  });
-  phase(h, K_AUG_EIG2, [&](int s0, int ns) { dd::launch_aug_eig2(d, axis, s0, ns, st); });
+  for (int pass = 0; pass < 3; ++pass) {
+    phase(h, K_CHOL, [&](int s0, int ns) {
+      dd::launch_chol(d, axis, s0, ns, dd::DIM_M0, d.M, d.nwgM, pass == 0, pass == 0 ? 1 : 2, 1.0, pass == 0,
+                      d.oRinvA, d.oRaccA, d.MA, st);
+    });
+    if (pass == 2) break;
+    // pass 0: Z = A P R^-1; pass 1: Z <- Z R^-1 in place (each strip of rows
+    // is read completely before it is written)
+    phase(h, K_GEMM_QR_A, [&](int s0, int ns) {
+      dd::launch_gemm(d, axis, s0, ns, pass == 0 ? d.A : d.Z, sdMA, d.M, dd::DIM_M0, dd::DIM_M0, d.oRinvA, d.MA,
+                      d.Z, sdMA, nullptr, true, d.oFill, false, st);
+    });
+  }
+  phase(h, K_AUG_SVD, [&](int s0, int ns) { dd::launch_aug_svd(d, axis, s0, ns, st); });
   phase(h, K_GEMM_VHAT, [&](int s0, int ns) {
-    dd::launch_gemm(d, axis, s0, ns, d.Z, sdMA, d.M, dd::DIM_M0, dd::DIM_T, d.oCoef, d.MA, d.Qh, sdMT, nullptr, true,
+    dd::launch_gemm(d, axis, s0, ns, d.A, sdMA, d.M, dd::DIM_M0, dd::DIM_T, d.oCoef, d.MA, d.Qh, sdMT, nullptr, true,
                     d.oFill, false, st);
   });
   // two Cholesky QR passes make V-hat orthonormal to working precision
   for (int pass = 0; pass < 2; ++pass) {
     double* src = pass == 0 ? d.Qh : d.Qh2;
     double* dst = pass == 0 ? d.Qh2 : d.Qh;
-    phase(h, K_CHOL,
-          [&](int s0, int ns) { dd::launch_chol(d, axis, s0, ns, dd::DIM_T, d.M, d.nwgM, false, 0, 1.0, st); });
+    phase(h, K_CHOL, [&](int s0, int ns) {
+      dd::launch_chol(d, axis, s0, ns, dd::DIM_T, d.M, d.nwgM, false, 0, 1.0, false, d.oRinv, d.oRacc, d.T, st);
+    });
     phase(h, K_GEMM_QR_VHAT, [&](int s0, int ns) {
       dd::launch_gemm(d, axis, s0, ns, src, sdMT, d.M, dd::DIM_T, dd::DIM_T, d.oRinv, d.T, dst, sdMT, nullptr,
                       pass == 0, d.oFill, false, st);

@@ -25,11 +25,14 @@ __device__ inline double block_sum(double v, double* red) {
 
 
 // C (m x n) = alpha * op(A) op(B) (+ beta C); generic pointers, no aliasing.
+// The inner loop is unrolled so that operands in global memory are fetched
+// eight at a time rather than one dependent load per step.
 __device__ void mm(double* C, int ldc, const double* A, int lda, bool ta, const double* B, int ldb,
                    bool tb, int m, int n, int k, double alpha, double beta) {
   for (int idx = threadIdx.x; idx < m * n; idx += NTHR) {
     const int i = idx % m, j = idx / m;
     double acc = 0.0;
+#pragma unroll 8
     for (int l = 0; l < k; ++l) {
       const double a = ta ? A[l + i * lda] : A[i + l * lda];
       const double b = tb ? B[j + l * ldb] : B[l + j * ldb];
@@ -41,15 +44,39 @@ __device__ void mm(double* C, int ldc, const double* A, int lda, bool ta, const 
 }
 
 // dst (rows x cols, ldd) = sum over ngp workgroup partials of the block at
-// offset off (leading dimension lds) -- fixed order, deterministic.
+// offset off (leading dimension lds) -- fixed order over the partials, so
+// deterministic.  Each thread takes four entries and fetches four partials of
+// each before adding, keeping 16 loads in flight.
 __device__ void sum_partials(const Dev& d, int s, int ngp, int off, int lds, int rows, int cols, double* dst,
                              int ldd, double scale) {
-  const double* gp = gpart_of(d, s);
-  for (int idx = threadIdx.x; idx < rows * cols; idx += NTHR) {
-    const int i = idx % rows, j = idx / rows;
-    double acc = 0.0;
-    for (int w = 0; w < ngp; ++w) acc += gp[(int64_t)w * d.gpTile + off + i + j * lds];
-    dst[i + j * ldd] = scale * acc;
+  const double* gp = gpart_of(d, s) + off;
+  const int n = rows * cols;
+  for (int base = threadIdx.x; base < n; base += 4 * NTHR) {
+    int src[4];
+    double acc[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int idx = base + e * NTHR;
+      src[e] = idx < n ? (idx % rows) + (idx / rows) * lds : -1;
+      acc[e] = 0.0;
+    }
+    for (int w0 = 0; w0 < ngp; w0 += 4) {
+      double v[4][4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          v[e][u] = (src[e] >= 0 && w0 + u < ngp) ? gp[(int64_t)(w0 + u) * d.gpTile + src[e]] : 0.0;
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[e] += v[e][u];
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int idx = base + e * NTHR;
+      if (idx < n) dst[(idx % rows) + (idx / rows) * ldd] = scale * acc[e];
+    }
   }
   __syncthreads();
 }
@@ -114,7 +141,8 @@ __device__ inline void jacobi_rotation(double al, double be, double ga, double& 
 // the same rotations accumulate in V (n x n, LDS, ld LDA), so that on exit
 // B_out = B_in V with orthogonal columns.  For an SVD B_in = U Sigma V^T the
 // column norms are the singular values; for a positive definite B_in the
-// columns of V are its eigenvectors and the norms its eigenvalues.
+// columns of V are its eigenvectors and the norms its eigenvalues.  With
+// V == nullptr the rotations are not accumulated.
 // Column pairs are taken in round-robin rounds; each pair is owned by a group
 // of g lanes (a power of two inside one wavefront) that reduce the three
 // inner products with shuffles, so a round needs a single barrier.  A pair is
@@ -134,9 +162,11 @@ __device__ int jacobi_1s_g(const Dev& d, double* B, int rows, int n, double* V, 
     part = fma(x, x, part);
   }
   const double floor2 = floor_rel * floor_rel * block_sum(part, red);
-  for (int idx = threadIdx.x; idx < n * n; idx += NTHR) {
-    const int i = idx % n, j = idx / n;
-    V[i + j * LDA] = (i == j) ? 1.0 : 0.0;
+  if (V != nullptr) {
+    for (int idx = threadIdx.x; idx < n * n; idx += NTHR) {
+      const int i = idx % n, j = idx / n;
+      V[i + j * LDA] = (i == j) ? 1.0 : 0.0;
+    }
   }
   __syncthreads();
   if (n <= 1) return 0;
@@ -181,10 +211,12 @@ __device__ int jacobi_1s_g(const Dev& d, double* B, int rows, int n, double* V, 
               B[i + p * LDA] = c * x - sn * y;
               B[i + q * LDA] = fma(sn, x, c * y);
             }
-            for (int i = lane; i < n; i += g) {
-              const double x = V[i + p * LDA], y = V[i + q * LDA];
-              V[i + p * LDA] = c * x - sn * y;
-              V[i + q * LDA] = fma(sn, x, c * y);
+            if (V != nullptr) {
+              for (int i = lane; i < n; i += g) {
+                const double x = V[i + p * LDA], y = V[i + q * LDA];
+                V[i + p * LDA] = c * x - sn * y;
+                V[i + q * LDA] = fma(sn, x, c * y);
+              }
             }
             if (lane == 0) rotated = 1;
           }
@@ -238,69 +270,204 @@ __device__ void sort_desc(const double* vals, int n, int* perm) {
   __syncthreads();
 }
 
-// In-place upper Cholesky of the n x n matrix G (LDS, ld LDA): G = R^T R.
-// A pivot that is not larger than 1e-20 times the column's own diagonal
-// entry means the column is numerically dependent on the earlier ones (the
-// matrix being factored is rank-deficient).  Such a pivot is set to 1 so the
-// factorisation continues as if the column were a fresh unit direction, and
-// dep[k] is set: the caller replaces that column by a pseudo-random vector
-// and zeroes the row in the accumulated R, which keeps A = Q R exact up to
-// the dependent column's residual.  A non-finite pivot latches
-// FLAG_NONFINITE.
-__device__ void chol_upper(const Dev& d, double* G, int n, int* dep) {
-  __shared__ double diag0[CAP];
-  for (int i = threadIdx.x; i < n; i += NTHR) {
-    diag0[i] = G[i + i * LDA];
-    dep[i] = 0;
-  }
-  __syncthreads();
-  for (int k = 0; k < n; ++k) {
-    if (threadIdx.x == 0) {
-      double dk = G[k + k * LDA];
-      if (!isfinite(dk)) {
-        atomicOr(d.flags, FLAG_NONFINITE);
-        dk = 1.0;
-        dep[k] = 1;
-      } else if (!(dk > 1e-20 * diag0[k])) {
-        dk = 1.0;
-        dep[k] = 1;
-      }
-      G[k + k * LDA] = sqrt(dk);
+// Sum of v over the 64 lanes of a wavefront (every lane gets the total).
+__device__ inline double wave_sum(double v) {
+  v = group_sum_dpp<16>(v);
+  v += __shfl_xor(v, 16, 64);
+  v += __shfl_xor(v, 32, 64);
+  return v;
+}
+
+// Upper-triangle entries (i <= j) of an n x n matrix owned by this thread:
+// packed index q = tid + NTHR m for m < NO.  Unused slots hold i = j = -1.
+// NO = own_slots(n) suffices for an n x n matrix.
+constexpr int own_slots(int n) { return (n * (n + 1) / 2 + NTHR - 1) / NTHR; }
+
+template <int NO>
+__device__ inline void owned_pairs(int n, int* oi, int* oj) {
+  const int np = n * (n + 1) / 2;
+#pragma unroll
+  for (int m = 0; m < NO; ++m) {
+    const int q = threadIdx.x + m * NTHR;
+    int i = -1, j = -1;
+    if (q < np) {
+      j = (int)((sqrtf(8.0f * q + 1.0f) - 1.0f) * 0.5f);
+      if (j * (j + 1) / 2 > q) --j;
+      if ((j + 1) * (j + 2) / 2 <= q) ++j;
+      i = q - j * (j + 1) / 2;
     }
-    __syncthreads();
-    const double rkk = G[k + k * LDA];
-    for (int j = k + 1 + threadIdx.x; j < n; j += NTHR) G[k + j * LDA] /= rkk;
-    for (int i = k + 1 + threadIdx.x; i < n; i += NTHR) G[i + k * LDA] = 0.0;
-    __syncthreads();
-    const int m = n - k - 1;
-    for (int idx = threadIdx.x; idx < m * m; idx += NTHR) {
-      const int i = k + 1 + idx % m, j = k + 1 + idx / m;
-      if (i <= j) G[i + j * LDA] -= G[k + i * LDA] * G[k + j * LDA];
-    }
-    __syncthreads();
+    oi[m] = i;
+    oj[m] = j;
   }
 }
 
-// X = R^{-1} for upper triangular R (both LDS, ld LDA): back substitution of
-// R X = I row by row from the bottom, each row eliminated from the rows
-// above in parallel (two barriers per row).
-__device__ void tri_inv_upper(const double* R, double* X, int n) {
-  for (int idx = threadIdx.x; idx < n * n; idx += NTHR) {
-    const int i = idx % n, j = idx / n;
-    X[i + j * LDA] = (i == j) ? 1.0 : 0.0;
+// Largest value over the 64 lanes of a wavefront, every lane gets it.
+__device__ inline double wave_max(double v) {
+  union { double d; int i[2]; } a, b;
+  a.d = v;
+  // xor 1, xor 2, half-row mirror, row mirror: the maximum of each row of 16
+  b.i[0] = __builtin_amdgcn_update_dpp(0, a.i[0], 0xB1, 0xF, 0xF, false);
+  b.i[1] = __builtin_amdgcn_update_dpp(0, a.i[1], 0xB1, 0xF, 0xF, false);
+  a.d = fmax(a.d, b.d);
+  b.i[0] = __builtin_amdgcn_update_dpp(0, a.i[0], 0x4E, 0xF, 0xF, false);
+  b.i[1] = __builtin_amdgcn_update_dpp(0, a.i[1], 0x4E, 0xF, 0xF, false);
+  a.d = fmax(a.d, b.d);
+  b.i[0] = __builtin_amdgcn_update_dpp(0, a.i[0], 0x141, 0xF, 0xF, false);
+  b.i[1] = __builtin_amdgcn_update_dpp(0, a.i[1], 0x141, 0xF, 0xF, false);
+  a.d = fmax(a.d, b.d);
+  b.i[0] = __builtin_amdgcn_update_dpp(0, a.i[0], 0x140, 0xF, 0xF, false);
+  b.i[1] = __builtin_amdgcn_update_dpp(0, a.i[1], 0x140, 0xF, 0xF, false);
+  a.d = fmax(a.d, b.d);
+  a.d = fmax(a.d, __shfl_xor(a.d, 16, 64));
+  a.d = fmax(a.d, __shfl_xor(a.d, 32, 64));
+  return a.d;
+}
+
+// value of v in lane `lane` (wave-uniform)
+__device__ inline double lane_value(double v, int lane) {
+  union { double d; int i[2]; } a;
+  a.d = v;
+  a.i[0] = __builtin_amdgcn_readlane(a.i[0], lane);
+  a.i[1] = __builtin_amdgcn_readlane(a.i[1], lane);
+  return a.d;
+}
+
+// Pivot key: the non-negative value with its lowest 6 mantissa bits replaced
+// by 63 - index, so that the largest key picks the largest value (to 2^-46
+// relative) and, among equal ones, the smallest index.  Read back as a
+// double, keys of non-negative values keep their order.
+__device__ inline double pivot_key(double v, int i) {
+  const double c = v > 0.0 ? v : 0.0;
+  return __longlong_as_double((__double_as_longlong(c) & ~63ll) | (long long)(63 - i));
+}
+
+// Cholesky factorisation of the symmetric n x n matrix G (LDS, ld LDA; only
+// the upper triangle is read), optionally with diagonal pivoting:
+//   G[perm, perm] = R^T R,  R upper triangular (left in G, ld LDA),
+// where perm = identity without pivoting; with pivoting, step k takes the
+// largest remaining diagonal entry of the Schur complement (the column order
+// of pivoted QR of the matrix whose Gram G is).  X (LDS, ld LDA) is scratch.
+// A pivot not larger than 1e-20 times the column's own initial diagonal
+// marks a numerically dependent column: the pivot is replaced by 1 so the
+// factorisation continues as if the column were a fresh unit direction, and
+// dep[k] is set (the caller replaces that column of Q by a pseudo-random
+// vector and zeroes row k of R).  A non-finite pivot latches FLAG_NONFINITE
+// and is treated the same way.
+// The elimination runs in the original index space (pivoting only chooses
+// the next index), each thread owning fixed upper-triangle entries; a step
+// issues all its LDS reads at once and ends with the only barrier.  With
+// pivoting every wavefront finds the pivot itself (maximum of packed
+// value/index keys over its lanes).
+template <int NO, bool PIVOT>
+__device__ void chol_piv(const Dev& d, double* G, double* X, int n, int* perm, int* dep) {
+  __shared__ double diag0[CAP];
+  __shared__ double dpiv[CAP];
+  int oi[NO], oj[NO];
+  owned_pairs<NO>(n, oi, oj);
+  const int j = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  if (threadIdx.x < n) diag0[threadIdx.x] = G[threadIdx.x * (LDA + 1)];
+  __syncthreads();
+  uint64_t done = 0;  // indices already eliminated (identical in every thread)
+  for (int k = 0; k < n; ++k) {
+    int p = k;
+    double dk;
+    if (PIVOT) {
+      const bool cand = lane < n && !((done >> lane) & 1);
+      const double v = cand ? G[lane * (LDA + 1)] : 0.0;
+      const double kmax = wave_max(cand ? pivot_key(v, lane) : 0.0);
+      p = 63 - (int)(__double_as_longlong(kmax) & 63);
+      dk = lane_value(v, p);
+    } else {
+      dk = G[k * (LDA + 1)];
+    }
+    const double d0 = diag0[p];
+    // pivot row (Schur values at this step) in the original index space
+    const double xrec = (threadIdx.x < n) ? G[(lane < p ? lane : p) + (lane < p ? p : lane) * LDA] : 0.0;
+    double gpi[NO], gpj[NO], gij[NO];
+    bool act[NO];
+#pragma unroll
+    for (int m = 0; m < NO; ++m) {
+      const int i = oi[m], jj = oj[m];
+      act[m] = PIVOT ? (i >= 0 && !((done >> i) & 1) && !((done >> jj) & 1) && i != p && jj != p) : (i > k);
+      if (act[m]) {
+        gpi[m] = G[(i < p ? i : p) + (i < p ? p : i) * LDA];
+        gpj[m] = G[(jj < p ? jj : p) + (jj < p ? p : jj) * LDA];
+        gij[m] = G[i + jj * LDA];
+      }
+    }
+    bool isdep = false;
+    if (!isfinite(dk)) {
+      dk = 1.0;
+      isdep = true;
+      if (threadIdx.x == 0) atomicOr(d.flags, FLAG_NONFINITE);
+    } else if (!(dk > 1e-20 * d0)) {
+      dk = 1.0;
+      isdep = true;
+    }
+    const double inv = rcp_nr(dk);
+    done |= 1ull << p;
+    if (threadIdx.x == 0) {
+      perm[k] = p;
+      dep[k] = isdep ? 1 : 0;
+      dpiv[k] = dk;
+    }
+    if (threadIdx.x < n) X[k + threadIdx.x * LDA] = xrec;
+#pragma unroll
+    for (int m = 0; m < NO; ++m)
+      if (act[m]) G[oi[m] + oj[m] * LDA] = fma(-gpi[m] * inv, gpj[m], gij[m]);
+    __syncthreads();
+  }
+  if (threadIdx.x < n) dpiv[threadIdx.x] = sqrt(dpiv[threadIdx.x]);
+  __syncthreads();
+  // R[k][l] = (pivot row k at column perm[l]) / rdiag[k] for l > k
+  if (j < n) {
+    const int pl = perm[j];
+    for (int k = g; k < n; k += 4) {
+      double v = 0.0;
+      if (j == k) v = dpiv[k];
+      else if (j > k) v = X[k + pl * LDA] * rcp_nr(dpiv[k]);
+      G[k + j * LDA] = v;
+    }
   }
   __syncthreads();
-  for (int k = n - 1; k >= 0; --k) {
-    const double ir = 1.0 / R[k + k * LDA];
-    for (int j = k + threadIdx.x; j < n; j += NTHR) X[k + j * LDA] *= ir;
-    __syncthreads();
-    const int w = n - k;
-    for (int idx = threadIdx.x; idx < k * w; idx += NTHR) {
-      const int i = idx % k, j = k + idx / k;
-      X[i + j * LDA] = fma(-R[i + k * LDA], X[k + j * LDA], X[i + j * LDA]);
+}
+
+// X = R^{-1} for upper triangular R (both LDS, ld LDA), right-looking back
+// substitution with one barrier per step: once rows > k have been removed
+// from row k, row k is final up to the factor 1/R[k][k] and is removed from
+// all rows above in parallel (each thread owning fixed entries, reads first).
+template <int NO>
+__device__ void tri_inv(const double* R, double* X, int n) {
+  __shared__ double rinv[CAP];
+  int oi[NO], oj[NO];
+  owned_pairs<NO>(n, oi, oj);
+  const int j = threadIdx.x & 63, g = threadIdx.x >> 6;
+  if (j < n)
+    for (int i = g; i < n; i += 4) X[i + j * LDA] = (i == j) ? 1.0 : 0.0;
+  if (threadIdx.x < n) rinv[threadIdx.x] = 1.0 / R[threadIdx.x * (LDA + 1)];
+  __syncthreads();
+  for (int k = n - 1; k > 0; --k) {
+    const double rk = rinv[k];
+    double rik[NO], xkj[NO], xij[NO];
+    bool act[NO];
+#pragma unroll
+    for (int m = 0; m < NO; ++m) {
+      act[m] = oi[m] >= 0 && oi[m] < k && oj[m] >= k;
+      if (act[m]) {
+        rik[m] = R[oi[m] + k * LDA];
+        xkj[m] = X[k + oj[m] * LDA];
+        xij[m] = X[oi[m] + oj[m] * LDA];
+      }
     }
+#pragma unroll
+    for (int m = 0; m < NO; ++m)
+      if (act[m]) X[oi[m] + oj[m] * LDA] = fma(-rik[m] * rk, xkj[m], xij[m]);
     __syncthreads();
   }
+  if (j < n)
+    for (int i = g; i < n; i += 4) X[i + j * LDA] *= rinv[i];
+  __syncthreads();
 }
 
 // smallest k with (sum_{j >= k} sig_j^2)^(1/2) <= tol (Algorithms 4, 5)
@@ -315,10 +482,21 @@ __device__ int tail_rank(const double* sig, int n, double tol) {
   return k;
 }
 
+// dst (LDS, ld LDA) = src (rows x cols, ld lds), eight loads in flight per thread
 __device__ void copy_to_lds(double* dst, const double* src, int lds, int rows, int cols) {
-  for (int idx = threadIdx.x; idx < rows * cols; idx += NTHR) {
-    const int i = idx % rows, j = idx / rows;
-    dst[i + j * LDA] = src[i + j * lds];
+  const int n = rows * cols;
+  for (int base = threadIdx.x; base < n; base += 8 * NTHR) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int idx = base + u * NTHR;
+      v[u] = idx < n ? src[(idx % rows) + (idx / rows) * lds] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int idx = base + u * NTHR;
+      if (idx < n) dst[(idx % rows) + (idx / rows) * LDA] = v[u];
+    }
   }
   __syncthreads();
 }

@@ -8,10 +8,8 @@
 namespace dd {
 
 constexpr int NTHR = 256;        // threads per workgroup (4 wavefronts of 64)
-constexpr int TILE = 64;         // rows per tall-skinny tile
-constexpr int LDT = TILE + 1;    // padded leading dimension of LDS tiles
+constexpr int TILE = 64;         // rows per workgroup pass of the tall-skinny kernels
 constexpr int CAP = 64;          // largest T (intermediate rank) and MA (= r + r_lo + r_hi)
-constexpr int GPAIRS = (CAP * (CAP + 1) / 2 + NTHR - 1) / NTHR;  // Gram pairs per thread
 
 // error bits latched in Dev::flags
 enum : unsigned {
@@ -73,9 +71,9 @@ struct Dev {
   double* Qsrc;            // [nsub][N]
   int nx;                  // global cells along x (moments)
   // small workspace offsets (doubles)
-  int oY1, oCoef, oFill, oRinv, oRacc, oCp, oCn, oAm, oM0, oMm, oMp, oGLo, oGHi, oGLoN, oGHiN;
+  int oRaccA, oCoef, oFill, oRinv, oRacc, oCp, oCn, oAm, oM0, oMm, oMp, oGLo, oGHi, oGLoN, oGHiN;
   int oEp, oEn, oOlo, oOhi, oTm, oGm, oGp, oBKlo, oBKhi, oS1, oS2, oP0, oPm, oPp, oBu, oBv;
-  int oSig, oMv, oCrow, oGs, oGt, oQv, oW1, oW2, oW3, oW4, oW5, oW6;
+  int oSig, oMv, oCrow, oGs, oGt, oQv, oW1, oW2, oW3, oW4, oW5, oW6, oRinvA;
 };
 
 __host__ __device__ inline int neighbour(const Dev& d, int s, int axis, int side) {
@@ -124,47 +122,6 @@ __device__ inline void unpack_pair(int k, int& i, int& j) {
   i = k - jj * (jj + 1) / 2;
 }
 
-// Gram accumulator: each thread owns up to GPAIRS entries (i <= j) of an
-// n x n Gram matrix and sums rows of LDS tiles into them.
-struct GramAcc {
-  double a[GPAIRS];
-  __device__ void zero() {
-#pragma unroll
-    for (int m = 0; m < GPAIRS; ++m) a[m] = 0.0;
-  }
-  // buf: column-major tile with leading dimension ld, nrows valid rows
-  __device__ void add(const double* buf, int ld, int nrows, int n) {
-    const int npair = n * (n + 1) / 2;
-#pragma unroll
-    for (int m = 0; m < GPAIRS; ++m) {
-      int k = threadIdx.x + m * NTHR;
-      if (k < npair) {
-        int i, j;
-        unpack_pair(k, i, j);
-        const double* ci = buf + i * ld;
-        const double* cj = buf + j * ld;
-        double s = 0.0;
-        for (int r = 0; r < nrows; ++r) s = fma(ci[r], cj[r], s);
-        a[m] += s;
-      }
-    }
-  }
-  // full symmetric n x n into out (leading dimension n)
-  __device__ void store(double* out, int n) const {
-    const int npair = n * (n + 1) / 2;
-#pragma unroll
-    for (int m = 0; m < GPAIRS; ++m) {
-      int k = threadIdx.x + m * NTHR;
-      if (k < npair) {
-        int i, j;
-        unpack_pair(k, i, j);
-        out[i + j * n] = a[m];
-        out[j + i * n] = a[m];
-      }
-    }
-  }
-};
-
 // Order the LDS accesses of one wavefront around a point where its lanes
 // exchange data through LDS (LDS operations of a wavefront complete in issue
 // order; this keeps the compiler from moving them across the point).
@@ -202,10 +159,9 @@ void launch_coll_reduce(const Dev& d, int sd0, int nsd, hipStream_t st);
 void launch_coll_lstep(const Dev& d, int sd0, int nsd, hipStream_t st);
 void launch_moments(const Dev& d, hipStream_t st);
 // small (one workgroup per subdomain) kernels
-void launch_aug_eig1(const Dev& d, int axis, int sd0, int nsd, hipStream_t st);
-void launch_aug_eig2(const Dev& d, int axis, int sd0, int nsd, hipStream_t st);
+void launch_aug_svd(const Dev& d, int axis, int sd0, int nsd, hipStream_t st);
 void launch_chol(const Dev& d, int axis, int sd0, int nsd, int ndim, int rows, int ngp, bool shift,
-                 int acc_mode, double bscale, hipStream_t st);
+                 int acc_mode, double bscale, bool pivot, int oRinv, int oRacc, int ld, hipStream_t st);
 void launch_adv_prep(const Dev& d, int axis, int sd0, int nsd, hipStream_t st);
 void launch_adv_sstep(const Dev& d, int axis, int sd0, int nsd, const double* Q, hipStream_t st);
 void launch_trunc(const Dev& d, int axis, int sd0, int nsd, hipStream_t st);

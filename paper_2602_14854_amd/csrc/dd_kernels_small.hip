@@ -12,45 +12,47 @@ constexpr int CAPR = 21;
 
 // ---------------------------------------------------------------- augmentation
 
-// First pass of the weighted SVD of L0 (Algorithm 4, step 2): eigenvectors of
-// the Gram matrix A^T A, A = sqrt(w) L0.
-__global__ __launch_bounds__(NTHR) void s_aug_eig1(Dev d, int axis, int sd0) {
-  const int s = sd0 + blockIdx.x;
-  const int m0 = m0_of(d, s, axis);
-  __shared__ double G[LDA * CAP];
-  __shared__ double Y[LDA * CAP];
-  sum_partials(d, s, d.nwgM, 0, m0, m0, m0, G, LDA, 1.0);
-  // a loose pass suffices: it only has to make the columns of Z = A Y1
-  // nearly orthogonal; the second pass resolves the small singular values
-  jacobi_1s(d, G, m0, m0, Y, 1e-8, 1e-14, 40);
-  copy_from_lds(small_of(d, s) + d.oY1, d.MA, Y, m0, m0, 1.0);
-}
-
-void launch_aug_eig1(const Dev& d, int axis, int sd0, int nsd, hipStream_t st) {
-  hipLaunchKernelGGL(s_aug_eig1, dim3(nsd), dim3(NTHR), 0, st, d, axis, sd0);
-}
-
-// Second pass: Gram of Z = A Y1 (nearly diagonal, so Jacobi resolves small
-// singular values to relative accuracy), singular values, the rank rule of
-// Algorithm 4 step 3, and the coefficients of V-hat = Z Y2[:, :t] / sigma.
-__global__ __launch_bounds__(NTHR) void s_aug_eig2(Dev d, int axis, int sd0) {
+// SVD of the weighted augmentation matrix A = sqrt(w) L0 (Algorithm 4, steps
+// 2-4) from its Cholesky-QR factor A = Q Racc (Racc = R P^T, pivoted in the
+// first pass): the one-sided Jacobi on X = Racc^T, X W = B with orthogonal
+// columns, gives Racc = W Sigma Btilde^T, so the right singular vectors of A
+// are the normalised columns of B and the singular values their norms (the
+// pivoting makes the sweeps converge fast; the rotations themselves are not
+// needed).  Then the rank rule of step 3 and the coefficients of
+// sqrt(w) V-hat = A B[:, :t] Sigma^-2.
+__global__ __launch_bounds__(NTHR) void s_aug_svd(Dev d, int axis, int sd0) {
   const int s = sd0 + blockIdx.x;
   const int m0 = m0_of(d, s, axis);
   const int r = d.rank[s];
-  __shared__ double G[LDA * CAP];
-  __shared__ double Y[LDA * CAP];
+  __shared__ double B[LDA * CAP];
   __shared__ double sig[CAP];
-  __shared__ double lam[CAP];
+  __shared__ double nrm[CAP];
   __shared__ int perm[CAP];
   __shared__ int tsh;
-  sum_partials(d, s, d.nwgM, 0, m0, m0, m0, G, LDA, 1.0);
-  // G2 is nearly diagonal: the eigenvalues are the column norms of G2 Y2;
-  // its entries scale like sigma_i sigma_j, so the noise floor of a null
-  // direction is (u sigma_1)^2
-  jacobi_1s(d, G, m0, m0, Y, 1e-15, 1e-28, 40);
-  col_norms(G, m0, m0, lam);
-  sort_desc(lam, m0, perm);
-  for (int j = threadIdx.x; j < m0; j += NTHR) sig[j] = sqrt(fmax(lam[perm[j]], 0.0));
+  double* sm = small_of(d, s);
+  {
+    // B = Racc^T, eight loads in flight per thread
+    const double* Ra = sm + d.oRaccA;
+    const int n = m0 * m0;
+    for (int base = threadIdx.x; base < n; base += 8 * NTHR) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int idx = base + u * NTHR;
+        v[u] = idx < n ? Ra[(idx % m0) + (idx / m0) * d.MA] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int idx = base + u * NTHR;
+        if (idx < n) B[(idx / m0) + (idx % m0) * LDA] = v[u];
+      }
+    }
+    __syncthreads();
+  }
+  jacobi_1s(d, B, m0, m0, nullptr, 1e-15, 1e-15, 40);
+  col_norms(B, m0, m0, nrm);
+  sort_desc(nrm, m0, perm);
+  for (int j = threadIdx.x; j < m0; j += NTHR) sig[j] = nrm[perm[j]];
   __syncthreads();
   if (threadIdx.x == 0) {
     int t;
@@ -73,76 +75,103 @@ __global__ __launch_bounds__(NTHR) void s_aug_eig2(Dev d, int axis, int sd0) {
   }
   __syncthreads();
   const int t = tsh;
-  double* sm = small_of(d, s);
   for (int j = threadIdx.x; j < m0; j += NTHR) sm[d.oSig + j] = sig[j];
   const double s0 = sig[0];
   for (int idx = threadIdx.x; idx < m0 * t; idx += NTHR) {
     const int i = idx % m0, j = idx / m0;
     const bool ok = s0 > 0.0 && sig[j] > 1e-13 * s0;
-    sm[d.oCoef + i + j * d.MA] = ok ? Y[i + perm[j] * LDA] / sig[j] : 0.0;
+    sm[d.oCoef + i + j * d.MA] = ok ? B[i + perm[j] * LDA] / (sig[j] * sig[j]) : 0.0;
   }
   for (int j = threadIdx.x; j < t; j += NTHR) sm[d.oFill + j] = (s0 > 0.0 && sig[j] > 1e-13 * s0) ? 0.0 : 1.0;
 }
 
-void launch_aug_eig2(const Dev& d, int axis, int sd0, int nsd, hipStream_t st) {
-  hipLaunchKernelGGL(s_aug_eig2, dim3(nsd), dim3(NTHR), 0, st, d, axis, sd0);
+void launch_aug_svd(const Dev& d, int axis, int sd0, int nsd, hipStream_t st) {
+  hipLaunchKernelGGL(s_aug_svd, dim3(nsd), dim3(NTHR), 0, st, d, axis, sd0);
 }
 
 // ---------------------------------------------------------------- Cholesky QR
 
-// One pass of (shifted) Cholesky QR: G = sum of partials (n x n), optional
-// shift 11 (rows n + n (n+1)) u tr(G) (Fukaya et al., shifted CholeskyQR),
-// R = chol(G), Rinv = bscale R^{-1} for the next tall-skinny product, the
-// fill mask of numerically dependent columns, and the running product of R
-// factors (acc_mode 1: start, 2: left-multiply) with the dependent rows
-// zeroed.
+// One pass of (shifted, optionally pivoted) Cholesky QR of X = Q R: G = sum
+// of partials (n x n), optional shift 11 (rows n + n (n+1)) u tr(G) (Fukaya
+// et al., shifted CholeskyQR), G[perm, perm] = R^T R, and
+//   Rinv slot: P R^{-1} (rows permuted back, scaled by bscale) for the next
+//              tall-skinny product Q = X P R^{-1},
+//   fill slot: the mask of numerically dependent columns of Q,
+//   Racc slot: the running factor with X = Q Racc -- acc_mode 1 starts it
+//              with R P^T, acc_mode 2 left-multiplies it by R -- with the rows
+//              of dependent columns zeroed.
+// Slots have leading dimension ld.
+template <int NO>
 __global__ __launch_bounds__(NTHR) void s_chol(Dev d, int axis, int sd0, int ndim, int rows, int ngp, int shift,
-                                              int acc_mode, double bscale) {
+                                              int acc_mode, double bscale, int pivot, int oRinv, int oRacc, int ld) {
   const int s = sd0 + blockIdx.x;
   const int n = dim_of(d, s, axis, ndim);
   __shared__ double G[LDA * CAP];
   __shared__ double X[LDA * CAP];
   __shared__ int dep[CAP];
+  __shared__ int perm[CAP];
   sum_partials(d, s, ngp, 0, n, n, n, G, LDA, 1.0);
   if (shift) {
-    __shared__ double red[NTHR];
-    double part = 0.0;
-    for (int i = threadIdx.x; i < n; i += NTHR) part += G[i + i * LDA];
-    const double sh = 11.0 * ((double)rows * n + (double)n * (n + 1)) * U_ROUND * block_sum(part, red);
-    for (int i = threadIdx.x; i < n; i += NTHR) G[i + i * LDA] += sh;
+    // every wavefront forms the trace itself
+    const int lane = threadIdx.x & 63;
+    const double tr = wave_sum(lane < n ? G[lane * (LDA + 1)] : 0.0);
+    const double sh = 11.0 * ((double)rows * n + (double)n * (n + 1)) * U_ROUND * tr;
+    __syncthreads();
+    if (threadIdx.x < n) G[threadIdx.x * (LDA + 1)] += sh;
     __syncthreads();
   }
-  chol_upper(d, G, n, dep);
-  tri_inv_upper(G, X, n);
+  if (pivot) chol_piv<NO, true>(d, G, X, n, perm, dep);
+  else chol_piv<NO, false>(d, G, X, n, perm, dep);
+  tri_inv<NO>(G, X, n);
   double* sm = small_of(d, s);
-  copy_from_lds(sm + d.oRinv, d.T, X, n, n, bscale);
+  // thread (column c = tid % 64, rows i = tid / 64 mod 4) for the n x n outputs
+  const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
+  // P R^{-1}: row i of R^{-1} becomes row perm[i]
+  if (c < n)
+    for (int i = g; i < n; i += 4) sm[oRinv + perm[i] + c * ld] = bscale * X[i + c * LDA];
   for (int j = threadIdx.x; j < n; j += NTHR) sm[d.oFill + j] = dep[j] ? 1.0 : 0.0;
-  // rows of dependent columns do not contribute to A = Q R
-  for (int idx = threadIdx.x; idx < n * n; idx += NTHR) {
-    const int i = idx % n, j = idx / n;
-    if (dep[i]) G[i + j * LDA] = 0.0;
-  }
+  // rows of dependent columns do not contribute to X = Q R
+  if (c < n)
+    for (int i = g; i < n; i += 4)
+      if (dep[i]) G[i + c * LDA] = 0.0;
   __syncthreads();
   if (acc_mode == 1) {
-    copy_from_lds(sm + d.oRacc, d.T, G, n, n, 1.0);
-  } else if (acc_mode == 2) {
-    // X = G * Racc (upper x upper), then store
-    const double* Ra = sm + d.oRacc;
-    for (int idx = threadIdx.x; idx < n * n; idx += NTHR) {
-      const int i = idx % n, j = idx / n;
-      double acc = 0.0;
-      for (int k = i; k <= j; ++k) acc = fma(G[i + k * LDA], Ra[k + j * d.T], acc);
-      X[i + j * LDA] = (i <= j) ? acc : 0.0;
+    // Racc = R P^T: column c of R becomes column perm[c]
+    if (c < n) {
+      const int pc = perm[c];
+      for (int i = g; i < n; i += 4) sm[oRacc + i + pc * ld] = G[i + c * LDA];
     }
-    __syncthreads();
-    copy_from_lds(sm + d.oRacc, d.T, X, n, n, 1.0);
+  } else if (acc_mode == 2) {
+    // Racc <- R Racc, with Racc staged in LDS
+    copy_to_lds(X, sm + oRacc, ld, n, n);
+    if (c < n) {
+      for (int i = g; i < n; i += 4) {
+        double acc = 0.0;
+        for (int k = i; k < n; ++k) acc = fma(G[i + k * LDA], X[k + c * LDA], acc);
+        sm[oRacc + i + c * ld] = acc;
+      }
+    }
   }
 }
 
 void launch_chol(const Dev& d, int axis, int sd0, int nsd, int ndim, int rows, int ngp, bool shift, int acc_mode,
-                 double bscale, hipStream_t st) {
-  hipLaunchKernelGGL(s_chol, dim3(nsd), dim3(NTHR), 0, st, d, axis, sd0, ndim, rows, ngp, shift ? 1 : 0, acc_mode,
-                     bscale);
+                 double bscale, bool pivot, int oRinv, int oRacc, int ld, hipStream_t st) {
+  const int cap = ndim == DIM_M0 ? d.MA : (ndim == DIM_T ? d.T : d.R);
+#define DD_CHOL(NO)                                                                                               \
+  hipLaunchKernelGGL(s_chol<NO>, dim3(nsd), dim3(NTHR), 0, st, d, axis, sd0, ndim, rows, ngp, shift ? 1 : 0,     \
+                     acc_mode, bscale, pivot ? 1 : 0, oRinv, oRacc, ld)
+  switch (own_slots(cap)) {
+    case 1: DD_CHOL(1); break;
+    case 2: DD_CHOL(2); break;
+    case 3: DD_CHOL(3); break;
+    case 4: DD_CHOL(4); break;
+    case 5: DD_CHOL(5); break;
+    case 6: DD_CHOL(6); break;
+    case 7: DD_CHOL(7); break;
+    case 8: DD_CHOL(8); break;
+    default: DD_CHOL(9); break;
+  }
+#undef DD_CHOL
 }
 
 // ---------------------------------------------------------------- advection
@@ -283,6 +312,7 @@ __global__ __launch_bounds__(NTHR) void s_adv_sstep(Dev d, int axis, int sd0, co
     const int i = ee % t, c = ee / t;
     (void)nc;
     double acc = 0.0;
+#pragma unroll 8
     for (int f = 0; f < nf; ++f) {
       const int pl = face_cell(d, axis, false, f), ph = face_cell(d, axis, true, f);
       if (blk == 0) acc = fma(Q[(int64_t)i * N + pl], Us[(int64_t)c * N + pl], acc);
@@ -486,25 +516,32 @@ void launch_set_rank(const Dev& d, int sd0, int nsd, hipStream_t st) {
 
 // ---------------------------------------------------------------- collision
 
-// m = V^T w (the angular averages <V_j>, eq. coll_evolK)
+// m = V^T w (the angular averages <V_j>, eq. coll_evolK): every thread
+// accumulates all r sums over its directions, then r threads add the
+// NTHR partials in a fixed order.
 __global__ __launch_bounds__(NTHR) void s_coll_prep(Dev d, int sd0) {
   const int s = sd0 + blockIdx.x;
   const int r = d.rank[s];
   const int M = d.M, R = d.R;
-  __shared__ double red[NTHR];
+  __shared__ double red[CAPR * NTHR];
   const double* Vs = d.V + (int64_t)s * M * R;
-  double* sm = small_of(d, s);
-  for (int a = 0; a < r; ++a) {
-    double acc = 0.0;
-    for (int q = threadIdx.x; q < M; q += NTHR) acc = fma(Vs[(int64_t)a * M + q], d.w[q], acc);
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int off = NTHR / 2; off > 0; off >>= 1) {
-      if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) sm[d.oMv + a] = red[0];
-    __syncthreads();
+  double acc[CAPR];
+#pragma unroll
+  for (int a = 0; a < CAPR; ++a) acc[a] = 0.0;
+  for (int q = threadIdx.x; q < M; q += NTHR) {
+    const double wq = d.w[q];
+#pragma unroll
+    for (int a = 0; a < CAPR; ++a)
+      if (a < r) acc[a] = fma(Vs[(int64_t)a * M + q], wq, acc[a]);
+  }
+#pragma unroll
+  for (int a = 0; a < CAPR; ++a)
+    if (a < r) red[a * NTHR + threadIdx.x] = acc[a];
+  __syncthreads();
+  if (threadIdx.x < r) {
+    double sum = 0.0;
+    for (int k = 0; k < NTHR; ++k) sum += red[threadIdx.x * NTHR + k];
+    small_of(d, s)[d.oMv + threadIdx.x] = sum;
   }
 }
 
@@ -515,62 +552,59 @@ void launch_coll_prep(const Dev& d, int sd0, int nsd, hipStream_t st) {
 // S-step (eq. coll_evolS) and L-step coefficients (eq. coll_evolL):
 //   S2 = S1 + dt (-(1/W) Gs S1 m m^T + Gt S1 - q m^T),  S1 = h Racc,
 //   P = S2^T (I - dt Gt),  crow = dt ((S2 m)^T Gs / W + q^T).
+// All operands are staged in LDS (leading dimension CAPR).
 __global__ __launch_bounds__(NTHR) void s_coll_sstep(Dev d, int sd0) {
   const int s = sd0 + blockIdx.x;
   const int r = d.rank[s];
   const int R = d.R, T = d.T;
+  constexpr int L = CAPR;
   double* sm = small_of(d, s);
-  double* Gs = sm + d.oGs;
-  double* Gt = sm + d.oGt;
-  double* qv = sm + d.oQv;
-  sum_partials(d, s, d.nwgN, 0, R, r, r, Gs, R, 1.0);
-  sum_partials(d, s, d.nwgN, R * R, R, r, r, Gt, R, 1.0);
-  sum_partials(d, s, d.nwgN, 2 * R * R, R, r, 1, qv, R, 1.0);
-  const double* mv = sm + d.oMv;
-  double* S1 = sm + d.oS1;
-  double* S2 = sm + d.oS2;
-  __shared__ double v1[CAPR], v2[CAPR], v3[CAPR];
+  __shared__ double Gs[L * L], Gt[L * L], S1[L * L], S2[L * L];
+  __shared__ double qv[L], mv[L], v1[L], v2[L], v3[L];
+  sum_partials(d, s, d.nwgN, 0, R, r, r, Gs, L, 1.0);
+  sum_partials(d, s, d.nwgN, R * R, R, r, r, Gt, L, 1.0);
+  sum_partials(d, s, d.nwgN, 2 * R * R, R, r, 1, qv, L, 1.0);
   for (int idx = threadIdx.x; idx < r * r; idx += NTHR) {
     const int i = idx % r, j = idx / r;
-    S1[i + j * R] = d.h * sm[d.oRacc + i + j * T];
+    S1[i + j * L] = d.h * sm[d.oRacc + i + j * T];
   }
+  for (int i = threadIdx.x; i < r; i += NTHR) mv[i] = sm[d.oMv + i];
   __syncthreads();
   for (int i = threadIdx.x; i < r; i += NTHR) {
     double acc = 0.0;
-    for (int k = 0; k < r; ++k) acc = fma(S1[i + k * R], mv[k], acc);
+    for (int k = 0; k < r; ++k) acc = fma(S1[i + k * L], mv[k], acc);
     v1[i] = acc;
   }
   __syncthreads();
   for (int i = threadIdx.x; i < r; i += NTHR) {
     double acc = 0.0;
-    for (int k = 0; k < r; ++k) acc = fma(Gs[i + k * R], v1[k], acc);
+    for (int k = 0; k < r; ++k) acc = fma(Gs[i + k * L], v1[k], acc);
     v2[i] = acc;
   }
-  __syncthreads();
-  mm(S2, R, Gt, R, false, S1, R, false, r, r, r, 1.0, 0.0);
+  mm(S2, L, Gt, L, false, S1, L, false, r, r, r, 1.0, 0.0);
   const double dt = d.dt, iW = 1.0 / d.W;
   for (int idx = threadIdx.x; idx < r * r; idx += NTHR) {
     const int i = idx % r, j = idx / r;
-    const int o = i + j * R;
+    const int o = i + j * L;
     S2[o] = S1[o] + dt * (-iW * v2[i] * mv[j] + S2[o] - qv[i] * mv[j]);
   }
   __syncthreads();
   // P = S2^T (I - dt Gt)
   for (int idx = threadIdx.x; idx < r * r; idx += NTHR) {
     const int i = idx % r, j = idx / r;
-    double acc = S2[j + i * R];
-    for (int k = 0; k < r; ++k) acc = fma(-dt * S2[k + i * R], Gt[k + j * R], acc);
+    double acc = S2[j + i * L];
+    for (int k = 0; k < r; ++k) acc = fma(-dt * S2[k + i * L], Gt[k + j * L], acc);
     sm[d.oP0 + i + j * R] = acc;
   }
   for (int i = threadIdx.x; i < r; i += NTHR) {
     double acc = 0.0;
-    for (int k = 0; k < r; ++k) acc = fma(S2[i + k * R], mv[k], acc);
+    for (int k = 0; k < r; ++k) acc = fma(S2[i + k * L], mv[k], acc);
     v3[i] = acc;
   }
   __syncthreads();
   for (int j = threadIdx.x; j < r; j += NTHR) {
     double acc = 0.0;
-    for (int i = 0; i < r; ++i) acc = fma(v3[i], Gs[i + j * R], acc);
+    for (int i = 0; i < r; ++i) acc = fma(v3[i], Gs[i + j * L], acc);
     sm[d.oCrow + j] = dt * (acc * iW + qv[j]);
   }
 }
