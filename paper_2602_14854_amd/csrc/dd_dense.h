@@ -11,7 +11,7 @@ constexpr int LDA = CAP + 1;                        // padded leading dimension 
 constexpr double U_ROUND = 1.1102230246251565e-16;  // 2^-53
 
 // sum of v over the workgroup (red: NTHR doubles of LDS scratch)
-__device__ inline double block_sum(double v, double* red) {
+__device__ __forceinline__ double block_sum(double v, double* red) {
   red[threadIdx.x] = v;
   __syncthreads();
   for (int off = NTHR / 2; off > 0; off >>= 1) {
@@ -27,7 +27,7 @@ __device__ inline double block_sum(double v, double* red) {
 // C (m x n) = alpha * op(A) op(B) (+ beta C); generic pointers, no aliasing.
 // The inner loop is unrolled so that operands in global memory are fetched
 // eight at a time rather than one dependent load per step.
-__device__ void mm(double* C, int ldc, const double* A, int lda, bool ta, const double* B, int ldb,
+__device__ __forceinline__ void mm(double* C, int ldc, const double* A, int lda, bool ta, const double* B, int ldb,
                    bool tb, int m, int n, int k, double alpha, double beta) {
   for (int idx = threadIdx.x; idx < m * n; idx += NTHR) {
     const int i = idx % m, j = idx / m;
@@ -47,7 +47,7 @@ __device__ void mm(double* C, int ldc, const double* A, int lda, bool ta, const 
 // offset off (leading dimension lds) -- fixed order over the partials, so
 // deterministic.  Each thread takes four entries and fetches four partials of
 // each before adding, keeping 16 loads in flight.
-__device__ void sum_partials(const Dev& d, int s, int ngp, int off, int lds, int rows, int cols, double* dst,
+__device__ __forceinline__ void sum_partials(const Dev& d, int s, int ngp, int off, int lds, int rows, int cols, double* dst,
                              int ldd, double scale) {
   const double* gp = gpart_of(d, s) + off;
   const int n = rows * cols;
@@ -83,7 +83,7 @@ __device__ void sum_partials(const Dev& d, int s, int ngp, int off, int lds, int
 
 // sum over aligned groups of G lanes (G = 1, 2, 4, 8 or 16) with DPP
 template <int G>
-__device__ inline double group_sum_dpp(double v) {
+__device__ __forceinline__ double group_sum_dpp(double v) {
   if (G == 1) return v;
   union { double d; int i[2]; } a, b;
   a.d = v;
@@ -115,19 +115,19 @@ __device__ inline double group_sum_dpp(double v) {
 // s = c t.  The square roots and the reciprocal use the hardware
 // approximations followed by two Newton steps each (each step squares the
 // relative error, so an initial 2^-22 reaches working precision).
-__device__ inline double rsqrt_nr(double x) {
+__device__ __forceinline__ double rsqrt_nr(double x) {
   double r = __builtin_amdgcn_rsq(x);
   r = r * fma(-0.5 * x * r, r, 1.5);
   return r * fma(-0.5 * x * r, r, 1.5);
 }
 
-__device__ inline double rcp_nr(double x) {
+__device__ __forceinline__ double rcp_nr(double x) {
   double r = __builtin_amdgcn_rcp(x);
   r = r * fma(-x, r, 2.0);
   return r * fma(-x, r, 2.0);
 }
 
-__device__ inline void jacobi_rotation(double al, double be, double ga, double& c, double& sn) {
+__device__ __forceinline__ void jacobi_rotation(double al, double be, double ga, double& c, double& sn) {
   const double df = be - al;
   const double h2 = fma(df, df, 4.0 * ga * ga);
   const double hyp = h2 * rsqrt_nr(h2);
@@ -142,19 +142,22 @@ __device__ inline void jacobi_rotation(double al, double be, double ga, double& 
 // B_out = B_in V with orthogonal columns.  For an SVD B_in = U Sigma V^T the
 // column norms are the singular values; for a positive definite B_in the
 // columns of V are its eigenvectors and the norms its eigenvalues.  With
-// V == nullptr the rotations are not accumulated.
+// ACCV false the rotations are not accumulated.
 // Column pairs are taken in round-robin rounds; each pair is owned by a group
-// of g lanes (a power of two inside one wavefront) that reduce the three
-// inner products with shuffles, so a round needs a single barrier.  A pair is
-// rotated while |b_p . b_q| > tol ||b_p|| ||b_q||; the relative test gives
-// the small singular values of graded matrices to high relative accuracy.
-// Columns whose norm is below floor_rel ||B||_F carry only rounding noise
-// (a rank-deficient B) and are not rotated: rotating noise against large
-// columns would keep it from ever meeting the relative test.
-template <int GMAX>
-__device__ int jacobi_1s_g(const Dev& d, double* B, int rows, int n, double* V, double tol, double floor_rel,
+// of G lanes (inside one wavefront), each lane holding up to RPL rows of the
+// two columns (and of the two columns of V) in registers for the whole
+// round, so a round is one batch of LDS reads, three group reductions with
+// DPP, the rotation and one batch of LDS writes, then a single barrier.  A
+// pair is rotated while |b_p . b_q| > tol ||b_p|| ||b_q||; the relative test
+// gives the small singular values of graded matrices to high relative
+// accuracy.  Columns whose norm is below floor_rel ||B||_F carry only
+// rounding noise (a rank-deficient B) and are not rotated: rotating noise
+// against large columns would keep it from ever meeting the relative test.
+// Returns the number of sweeps (negative if not converged).
+template <int G, int RPL, bool ACCV>
+__device__ __forceinline__ int jacobi_1s_g(const Dev& d, double* B, int rows, int n, double* V, double tol, double floor_rel,
                            int max_sweeps) {
-  __shared__ int rotated;
+  __shared__ int rotated[3];  // per-sweep flags: set, read, cleared in rotation
   __shared__ double red[NTHR];
   double part = 0.0;
   for (int idx = threadIdx.x; idx < rows * n; idx += NTHR) {
@@ -162,73 +165,78 @@ __device__ int jacobi_1s_g(const Dev& d, double* B, int rows, int n, double* V, 
     part = fma(x, x, part);
   }
   const double floor2 = floor_rel * floor_rel * block_sum(part, red);
-  if (V != nullptr) {
+  if (ACCV) {
     for (int idx = threadIdx.x; idx < n * n; idx += NTHR) {
       const int i = idx % n, j = idx / n;
       V[i + j * LDA] = (i == j) ? 1.0 : 0.0;
     }
   }
+  if (threadIdx.x < 3) rotated[threadIdx.x] = 0;
   __syncthreads();
   if (n <= 1) return 0;
   const int n2 = n + (n & 1);
   const int npair = n2 / 2;
   const int nm1 = n2 - 1;
-  constexpr int g = GMAX;
-  const int grp = threadIdx.x / g, lane = threadIdx.x % g;
+  const int grp = threadIdx.x / G, lane = threadIdx.x % G;
   const double tol2 = tol * tol;
   bool converged = false;
   int sweeps = 0;
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     sweeps = sweep + 1;
-    if (threadIdx.x == 0) rotated = 0;
-    __syncthreads();
+    const int slot = sweep % 3;
+    if (threadIdx.x == 0) rotated[(sweep + 1) % 3] = 0;
     // round-robin positions: position 0 is fixed, positions 1..n2-1 rotate
     int va = grp - 1, vb = n2 - 2 - grp;  // (position - 1 + round), kept below nm1
     for (int round = 0; round < nm1; ++round) {
-      {
-        const int a = grp == 0 ? 0 : va + 1;
-        const int b = vb + 1;
-        const int p = a < b ? a : b, q = a < b ? b : a;
-        const bool live = grp < npair && q < n;
-        double al = 0.0, be = 0.0, ga = 0.0;
-        if (live) {
-          for (int i = lane; i < rows; i += g) {
-            const double x = B[i + p * LDA], y = B[i + q * LDA];
-            al = fma(x, x, al);
-            be = fma(y, y, be);
-            ga = fma(x, y, ga);
+      const int a = grp == 0 ? 0 : va + 1;
+      const int b = vb + 1;
+      const int p = a < b ? a : b, q = a < b ? b : a;
+      const bool live = grp < npair && q < n;
+      double x[RPL], y[RPL], vx[RPL], vy[RPL];
+#pragma unroll
+      for (int m = 0; m < RPL; ++m) {
+        const int i = lane + G * m;
+        const bool in = live && i < rows;
+        x[m] = in ? B[i + p * LDA] : 0.0;
+        y[m] = in ? B[i + q * LDA] : 0.0;
+        if (ACCV) {
+          const bool inv = live && i < n;
+          vx[m] = inv ? V[i + p * LDA] : 0.0;
+          vy[m] = inv ? V[i + q * LDA] : 0.0;
+        }
+      }
+      double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+      for (int m = 0; m < RPL; ++m) {
+        al = fma(x[m], x[m], al);
+        be = fma(y[m], y[m], be);
+        ga = fma(x[m], y[m], ga);
+      }
+      al = group_sum_dpp<G>(al);
+      be = group_sum_dpp<G>(be);
+      ga = group_sum_dpp<G>(ga);
+      if (live && ga != 0.0 && al > floor2 && be > floor2 && ga * ga > tol2 * al * be) {
+        double c, sn;
+        jacobi_rotation(al, be, ga, c, sn);
+#pragma unroll
+        for (int m = 0; m < RPL; ++m) {
+          const int i = lane + G * m;
+          if (i < rows) {
+            B[i + p * LDA] = c * x[m] - sn * y[m];
+            B[i + q * LDA] = fma(sn, x[m], c * y[m]);
+          }
+          if (ACCV && i < n) {
+            V[i + p * LDA] = c * vx[m] - sn * vy[m];
+            V[i + q * LDA] = fma(sn, vx[m], c * vy[m]);
           }
         }
-        {
-          al = group_sum_dpp<GMAX>(al);
-          be = group_sum_dpp<GMAX>(be);
-          ga = group_sum_dpp<GMAX>(ga);
-          if (live && ga != 0.0 && al > floor2 && be > floor2 && ga * ga > tol2 * al * be) {
-            double c, sn;
-            jacobi_rotation(al, be, ga, c, sn);
-            for (int i = lane; i < rows; i += g) {
-              const double x = B[i + p * LDA], y = B[i + q * LDA];
-              B[i + p * LDA] = c * x - sn * y;
-              B[i + q * LDA] = fma(sn, x, c * y);
-            }
-            if (V != nullptr) {
-              for (int i = lane; i < n; i += g) {
-                const double x = V[i + p * LDA], y = V[i + q * LDA];
-                V[i + p * LDA] = c * x - sn * y;
-                V[i + q * LDA] = fma(sn, x, c * y);
-              }
-            }
-            if (lane == 0) rotated = 1;
-          }
-        }
+        if (lane == 0) rotated[slot] = 1;
       }
       if (++va >= nm1) va -= nm1;
       if (++vb >= nm1) vb -= nm1;
       __syncthreads();
     }
-    const int any = rotated;
-    __syncthreads();
-    if (!any) {
+    if (!rotated[slot]) {
       converged = true;
       break;
     }
@@ -238,16 +246,20 @@ __device__ int jacobi_1s_g(const Dev& d, double* B, int rows, int n, double* V, 
   return converged ? sweeps : -sweeps;
 }
 
-// One-sided Jacobi with the default lane-group size.
-__device__ inline int jacobi_1s(const Dev& d, double* B, int rows, int n, double* V, double tol, double floor_rel,
+// One-sided Jacobi, lane groups and register rows chosen from the size:
+// 16 lanes per pair up to 32 columns, else 8 (rows <= 64 either way).
+__device__ __forceinline__ int jacobi_1s(const Dev& d, double* B, int rows, int n, double* V, double tol, double floor_rel,
                                 int max_sweeps) {
-  const int npair = (n + (n & 1)) / 2;
-  if (npair * 16 <= NTHR) return jacobi_1s_g<16>(d, B, rows, n, V, tol, floor_rel, max_sweeps);
-  return jacobi_1s_g<8>(d, B, rows, n, V, tol, floor_rel, max_sweeps);
+  if (n <= 32 && rows <= 32) {
+    if (V) return jacobi_1s_g<16, 2, true>(d, B, rows, n, V, tol, floor_rel, max_sweeps);
+    return jacobi_1s_g<16, 2, false>(d, B, rows, n, V, tol, floor_rel, max_sweeps);
+  }
+  if (V) return jacobi_1s_g<8, 8, true>(d, B, rows, n, V, tol, floor_rel, max_sweeps);
+  return jacobi_1s_g<8, 8, false>(d, B, rows, n, V, tol, floor_rel, max_sweeps);
 }
 
 // norms of the columns of B (rows x n, LDS) into out[n]
-__device__ void col_norms(const double* B, int rows, int n, double* out) {
+__device__ __forceinline__ void col_norms(const double* B, int rows, int n, double* out) {
   for (int j = threadIdx.x; j < n; j += NTHR) {
     double acc = 0.0;
     for (int i = 0; i < rows; ++i) acc = fma(B[i + j * LDA], B[i + j * LDA], acc);
@@ -257,7 +269,7 @@ __device__ void col_norms(const double* B, int rows, int n, double* out) {
 }
 
 // perm[j] = index of the j-th largest of vals[0..n) (ties keep index order)
-__device__ void sort_desc(const double* vals, int n, int* perm) {
+__device__ __forceinline__ void sort_desc(const double* vals, int n, int* perm) {
   for (int j = threadIdx.x; j < n; j += NTHR) {
     const double v = vals[j];
     int rank = 0;
@@ -271,7 +283,7 @@ __device__ void sort_desc(const double* vals, int n, int* perm) {
 }
 
 // Sum of v over the 64 lanes of a wavefront (every lane gets the total).
-__device__ inline double wave_sum(double v) {
+__device__ __forceinline__ double wave_sum(double v) {
   v = group_sum_dpp<16>(v);
   v += __shfl_xor(v, 16, 64);
   v += __shfl_xor(v, 32, 64);
@@ -284,7 +296,7 @@ __device__ inline double wave_sum(double v) {
 constexpr int own_slots(int n) { return (n * (n + 1) / 2 + NTHR - 1) / NTHR; }
 
 template <int NO>
-__device__ inline void owned_pairs(int n, int* oi, int* oj) {
+__device__ __forceinline__ void owned_pairs(int n, int* oi, int* oj) {
   const int np = n * (n + 1) / 2;
 #pragma unroll
   for (int m = 0; m < NO; ++m) {
@@ -302,7 +314,7 @@ __device__ inline void owned_pairs(int n, int* oi, int* oj) {
 }
 
 // Largest value over the 64 lanes of a wavefront, every lane gets it.
-__device__ inline double wave_max(double v) {
+__device__ __forceinline__ double wave_max(double v) {
   union { double d; int i[2]; } a, b;
   a.d = v;
   // xor 1, xor 2, half-row mirror, row mirror: the maximum of each row of 16
@@ -324,7 +336,7 @@ __device__ inline double wave_max(double v) {
 }
 
 // value of v in lane `lane` (wave-uniform)
-__device__ inline double lane_value(double v, int lane) {
+__device__ __forceinline__ double lane_value(double v, int lane) {
   union { double d; int i[2]; } a;
   a.d = v;
   a.i[0] = __builtin_amdgcn_readlane(a.i[0], lane);
@@ -336,7 +348,7 @@ __device__ inline double lane_value(double v, int lane) {
 // by 63 - index, so that the largest key picks the largest value (to 2^-46
 // relative) and, among equal ones, the smallest index.  Read back as a
 // double, keys of non-negative values keep their order.
-__device__ inline double pivot_key(double v, int i) {
+__device__ __forceinline__ double pivot_key(double v, int i) {
   const double c = v > 0.0 ? v : 0.0;
   return __longlong_as_double((__double_as_longlong(c) & ~63ll) | (long long)(63 - i));
 }
@@ -359,7 +371,7 @@ __device__ inline double pivot_key(double v, int i) {
 // pivoting every wavefront finds the pivot itself (maximum of packed
 // value/index keys over its lanes).
 template <int NO, bool PIVOT>
-__device__ void chol_piv(const Dev& d, double* G, double* X, int n, int* perm, int* dep) {
+__device__ __forceinline__ void chol_piv(const Dev& d, double* G, double* X, int n, int* perm, int* dep) {
   __shared__ double diag0[CAP];
   __shared__ double dpiv[CAP];
   int oi[NO], oj[NO];
@@ -438,7 +450,7 @@ __device__ void chol_piv(const Dev& d, double* G, double* X, int n, int* perm, i
 // from row k, row k is final up to the factor 1/R[k][k] and is removed from
 // all rows above in parallel (each thread owning fixed entries, reads first).
 template <int NO>
-__device__ void tri_inv(const double* R, double* X, int n) {
+__device__ __forceinline__ void tri_inv(const double* R, double* X, int n) {
   __shared__ double rinv[CAP];
   int oi[NO], oj[NO];
   owned_pairs<NO>(n, oi, oj);
@@ -471,7 +483,7 @@ __device__ void tri_inv(const double* R, double* X, int n) {
 }
 
 // smallest k with (sum_{j >= k} sig_j^2)^(1/2) <= tol (Algorithms 4, 5)
-__device__ int tail_rank(const double* sig, int n, double tol) {
+__device__ __forceinline__ int tail_rank(const double* sig, int n, double tol) {
   double tail2 = 0.0;
   int k = n;
   for (int j = n - 1; j >= 0; --j) {
@@ -483,7 +495,7 @@ __device__ int tail_rank(const double* sig, int n, double tol) {
 }
 
 // dst (LDS, ld LDA) = src (rows x cols, ld lds), eight loads in flight per thread
-__device__ void copy_to_lds(double* dst, const double* src, int lds, int rows, int cols) {
+__device__ __forceinline__ void copy_to_lds(double* dst, const double* src, int lds, int rows, int cols) {
   const int n = rows * cols;
   for (int base = threadIdx.x; base < n; base += 8 * NTHR) {
     double v[8];
@@ -501,7 +513,7 @@ __device__ void copy_to_lds(double* dst, const double* src, int lds, int rows, i
   __syncthreads();
 }
 
-__device__ void copy_from_lds(double* dst, int ldd, const double* src, int rows, int cols, double scale) {
+__device__ __forceinline__ void copy_from_lds(double* dst, int ldd, const double* src, int rows, int cols, double scale) {
   for (int idx = threadIdx.x; idx < rows * cols; idx += NTHR) {
     const int i = idx % rows, j = idx / rows;
     dst[i + j * ldd] = scale * src[i + j * LDA];
