@@ -460,7 +460,7 @@ void enqueue_advection(dd_dlra_handle h, int axis) {
   chol_qr3(h, axis, dd::DIM_T, d.K1, d.K2, sdNT, d.N, true, nullptr, 0, nullptr, 1.0, K_GEMM_QR_K);
   // step 3: S-step
   phase(h, K_SPATIAL_REDUCE, [&](int s0, int ns) { dd::launch_spatial_reduce(d, axis, s0, ns, d.K2, st); });
-  phase(h, K_ADV_SSTEP, [&](int s0, int ns) { dd::launch_adv_sstep(d, axis, s0, ns, d.K2, st); });
+  phase(h, K_ADV_SSTEP, [&](int s0, int ns) { dd::launch_adv_sstep(d, axis, s0, ns, st); });
   // steps 4-5: L-step, weighted QR
   phase(h, K_LSTEP, [&](int s0, int ns) { dd::launch_lstep(d, axis, s0, ns, st); });
   chol_qr3(h, axis, dd::DIM_T, d.AL, d.AL2, sdMT, d.M, false, nullptr, 0, nullptr, 1.0, K_GEMM_QR_L);

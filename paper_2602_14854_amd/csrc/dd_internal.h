@@ -163,7 +163,7 @@ void launch_aug_svd(const Dev& d, int axis, int sd0, int nsd, hipStream_t st);
 void launch_chol(const Dev& d, int axis, int sd0, int nsd, int ndim, int rows, int ngp, bool shift,
                  int acc_mode, double bscale, bool pivot, int oRinv, int oRacc, int ld, hipStream_t st);
 void launch_adv_prep(const Dev& d, int axis, int sd0, int nsd, hipStream_t st);
-void launch_adv_sstep(const Dev& d, int axis, int sd0, int nsd, const double* Q, hipStream_t st);
+void launch_adv_sstep(const Dev& d, int axis, int sd0, int nsd, hipStream_t st);
 void launch_trunc(const Dev& d, int axis, int sd0, int nsd, hipStream_t st);
 void launch_set_rank(const Dev& d, int sd0, int nsd, hipStream_t st);
 void launch_coll_prep(const Dev& d, int sd0, int nsd, hipStream_t st);

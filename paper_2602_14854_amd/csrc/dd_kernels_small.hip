@@ -280,50 +280,28 @@ void launch_adv_prep(const Dev& d, int axis, int sd0, int nsd, hipStream_t st) {
 //   H-(S) = Gm S - BKlo,  H+(S) = Gp S + BKhi,
 //   S1 = h Racc,  S2 = S1 + dt c (H-(S1) C+ + H+(S1) C-),
 // and P0 = S2^T, Pm = -dt c H-(S2)^T, Pp = -dt c H+(S2)^T for the L-step.
-__global__ __launch_bounds__(NTHR) void s_adv_sstep(Dev d, int axis, int sd0, const double* Qb) {
+__global__ __launch_bounds__(NTHR) void s_adv_sstep(Dev d, int axis, int sd0) {
   const int s = sd0 + blockIdx.x;
   const int lo = neighbour(d, s, axis, -1), hi = neighbour(d, s, axis, +1);
   const int r = d.rank[s], rl = lo >= 0 ? d.rank[lo] : 0, rh = hi >= 0 ? d.rank[hi] : 0;
   const int t = d.tdim[s];
-  const int N = d.N, R = d.R, T = d.T;
+  const int R = d.R, T = d.T;
   double* sm = small_of(d, s);
   const double ih = 1.0 / d.h;
   double* Gm = sm + d.oGm;
   double* Gp = sm + d.oGp;
   sum_partials(d, s, d.nwgN, 0, t, t, t, Gm, T, ih);
   sum_partials(d, s, d.nwgN, T * T, t, t, t, Gp, T, ih);
-  // face products
-  const double* Q = Qb + (int64_t)s * N * T;
-  const double* Us = d.U + (int64_t)s * N * R;
-  const double* Ul = lo >= 0 ? d.U + (int64_t)lo * N * R : nullptr;
-  const double* Uh = hi >= 0 ? d.U + (int64_t)hi * N * R : nullptr;
-  const int nf = face_len(d, axis);
+  // face products, summed from the spatial-reduction partials
   double* Xlo = sm + d.oW1;  // t x r
   double* Xhi = sm + d.oW2;  // t x r
   double* Xln = sm + d.oW3;  // t x rl
   double* Xhn = sm + d.oW4;  // t x rh
-  const int ntot = t * r * 2 + t * rl + t * rh;
-  for (int e = threadIdx.x; e < ntot; e += NTHR) {
-    int blk, ee, nc;
-    if (e < t * r) { blk = 0; ee = e; nc = r; }
-    else if (e < 2 * t * r) { blk = 1; ee = e - t * r; nc = r; }
-    else if (e < 2 * t * r + t * rl) { blk = 2; ee = e - 2 * t * r; nc = rl; }
-    else { blk = 3; ee = e - 2 * t * r - t * rl; nc = rh; }
-    const int i = ee % t, c = ee / t;
-    (void)nc;
-    double acc = 0.0;
-#pragma unroll 8
-    for (int f = 0; f < nf; ++f) {
-      const int pl = face_cell(d, axis, false, f), ph = face_cell(d, axis, true, f);
-      if (blk == 0) acc = fma(Q[(int64_t)i * N + pl], Us[(int64_t)c * N + pl], acc);
-      else if (blk == 1) acc = fma(Q[(int64_t)i * N + ph], Us[(int64_t)c * N + ph], acc);
-      else if (blk == 2) acc = fma(Q[(int64_t)i * N + pl], Ul[(int64_t)c * N + ph], acc);
-      else acc = fma(Q[(int64_t)i * N + ph], Uh[(int64_t)c * N + pl], acc);
-    }
-    double* dst = blk == 0 ? Xlo : blk == 1 ? Xhi : blk == 2 ? Xln : Xhn;
-    dst[i + c * T] = acc;
-  }
-  __syncthreads();
+  const int oX = 2 * T * T;
+  sum_partials(d, s, d.nwgN, oX, T, t, r, Xlo, T, 1.0);
+  sum_partials(d, s, d.nwgN, oX + T * R, T, t, r, Xhi, T, 1.0);
+  if (rl > 0) sum_partials(d, s, d.nwgN, oX + 2 * T * R, T, t, rl, Xln, T, 1.0);
+  if (rh > 0) sum_partials(d, s, d.nwgN, oX + 3 * T * R, T, t, rh, Xhn, T, 1.0);
   double* W5 = sm + d.oW5;
   double* W6 = sm + d.oW6;
   double* BKlo = sm + d.oBKlo;
@@ -378,8 +356,8 @@ __global__ __launch_bounds__(NTHR) void s_adv_sstep(Dev d, int axis, int sd0, co
   }
 }
 
-void launch_adv_sstep(const Dev& d, int axis, int sd0, int nsd, const double* Q, hipStream_t st) {
-  hipLaunchKernelGGL(s_adv_sstep, dim3(nsd), dim3(NTHR), 0, st, d, axis, sd0, Q);
+void launch_adv_sstep(const Dev& d, int axis, int sd0, int nsd, hipStream_t st) {
+  hipLaunchKernelGGL(s_adv_sstep, dim3(nsd), dim3(NTHR), 0, st, d, axis, sd0);
 }
 
 // Truncation (Algorithm 5) of S3 = RL^T: SVD through two Jacobi passes on

@@ -471,37 +471,53 @@ __global__ __launch_bounds__(NTHR) void k_kstep(Dev d, int axis, int sd0, int ks
 // Spatial Galerkin matrices of the S- and L-steps (eqs. advx_evolS/L):
 //   Gm[i,j] = sum_p Q[p,i] (Q[p,j] - Q[p-e,j])   (zero beyond the low face)
 //   Gp[i,j] = sum_p Q[p,i] (Q[p+e,j] - Q[p,j])   (zero beyond the high face)
-// with Q = h U^1; dividing by h gives h^2 U^T D-+_0 U.  Partial layout:
-// Gm @0, Gp @T*T, both t x t with leading dimension t.
+// with Q = h U^1; dividing by h gives h^2 U^T D-+_0 U.  Also the face
+// products of the frozen inflow data (t x r blocks):
+//   Xlo = Q[lo face]^T U[lo face],   Xln = Q[lo face]^T U_lo[its hi face],
+//   Xhi = Q[hi face]^T U[hi face],   Xhn = Q[hi face]^T U_hi[its lo face].
+// Partial layout: Gm @0, Gp @T*T (t x t, ld t), Xlo @2T*T, Xhi @2T*T+T*R,
+// Xln @2T*T+2T*R, Xhn @2T*T+3T*R (t x r_*, ld T).
 // ----------------------------------------------------------------------------
-template <int NCB>
+template <int NCT, int NCR>
 __global__ __launch_bounds__(NTHR) void k_spatial_reduce(Dev d, int axis, int sd0, const double* Q) {
-  // wavefronts 0-1 form Gm, wavefronts 2-3 form Gp; each pair walks the
-  // same strips
-  constexpr int LD = strip_ld<NCB>();
-  constexpr int KS = 4 * NCB;
-  constexpr int NQ = NCB * NCB;
+  // wavefronts 0-1 form Gm and the low-face products, wavefronts 2-3 Gp and
+  // the high-face products; each pair walks the same strips
+  constexpr int LD = strip_ld<NCT>();
+  constexpr int LDR = strip_ld<NCR>();
+  constexpr int KS = 4 * NCT, KSR_ = 4 * NCR;
+  constexpr int NQ = NCT * NCT;
+  constexpr int NX = NCT * NCR;
+  constexpr int NACC = NQ + 2 * NX;
   const int s = sd0 + blockIdx.y;
   const int t = d.tdim[s];
-  const int N = d.N, T = d.T;
+  const int N = d.N, T = d.T, R = d.R;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int l16 = lane & 15, kq = lane >> 4;
   const bool low = wave < 2;
+  const int nbr = neighbour(d, s, axis, low ? -1 : +1);
+  const int r = d.rank[s], rn = nbr >= 0 ? d.rank[nbr] : 0;
   extern __shared__ double lds[];
-  double* Qs = lds + wave * 2 * 16 * LD;  // Q strip and its one-sided difference
-  double* Ds = Qs + 16 * LD;
+  double* Qs = lds + wave * (2 * 16 * LD + 2 * 16 * LDR);  // Q strip, its one-sided difference,
+  double* Ds = Qs + 16 * LD;                               // then U and U_nbr rows on the face
+  double* Uo = Ds + 16 * LD;
+  double* Un = Uo + 16 * LDR;
   const double* Qsd = Q + (int64_t)s * N * T;
+  const double* Us = d.U + (int64_t)s * N * R;
+  const double* Unb = nbr >= 0 ? d.U + (int64_t)nbr * N * R : d.U;
   const int e = axis == 0 ? 1 : d.lnx;
   const int na = axis == 0 ? d.lnx : d.lny;
-  dbl4 acc[NQ];
-  zero_acc<NQ>(acc);
+  dbl4 acc[NACC];  // [0, NQ): Gm or Gp; then own-face and neighbour-face products
+  zero_acc<NACC>(acc);
   const int nst = ceil_div(N, 16);
   for (int st = blockIdx.x * 2 + (wave & 1); st < nst; st += gridDim.x * 2) {
     const int p = st * 16 + l16;
     const bool rin = p < N;
-    const int ia = axis == 0 ? (p % d.lnx) : (p / d.lnx);
+    const int ix = p % d.lnx, iy = p / d.lnx;
+    const int ia = axis == 0 ? ix : iy;
+    const int f = axis == 0 ? iy : ix;
     // neighbour row across the face this wavefront differences over
     const bool hn = low ? (rin && ia > 0) : (rin && ia < na - 1);
+    const bool face = low ? (rin && ia == 0) : (rin && ia == na - 1);
     const int pn = low ? p - e : p + e;
     double x0[KS], xn[KS];
 #pragma unroll
@@ -510,6 +526,23 @@ __global__ __launch_bounds__(NTHR) void k_spatial_reduce(Dev d, int axis, int sd
       const int64_t col = (int64_t)c * N;
       x0[ks] = (rin && c < t) ? Qsd[col + p] : 0.0;
       xn[ks] = (hn && c < t) ? Qsd[col + pn] : 0.0;
+    }
+    const bool any_face = __any(face);
+    if (any_face) {
+      // the face cell of the neighbour that touches this cell
+      const int pf = face_cell(d, axis, low, f);
+      double uo[KSR_], un[KSR_];
+#pragma unroll
+      for (int ks = 0; ks < KSR_; ++ks) {
+        const int c = 4 * ks + kq;
+        uo[ks] = (face && c < r) ? Us[(int64_t)c * N + p] : 0.0;
+        un[ks] = (face && c < rn) ? Unb[(int64_t)c * N + pf] : 0.0;
+      }
+#pragma unroll
+      for (int ks = 0; ks < KSR_; ++ks) {
+        Uo[l16 * LDR + 4 * ks + kq] = uo[ks];
+        Un[l16 * LDR + 4 * ks + kq] = un[ks];
+      }
     }
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
@@ -521,26 +554,51 @@ __global__ __launch_bounds__(NTHR) void k_spatial_reduce(Dev d, int axis, int sd
 #pragma unroll
     for (int kk = 0; kk < 16; kk += 4) {
       const int o = (kk + kq) * LD + l16;
-      double fq[NCB], fd[NCB];
+      double fq[NCT], fd[NCT];
 #pragma unroll
-      for (int c = 0; c < NCB; ++c) {
+      for (int c = 0; c < NCT; ++c) {
         fq[c] = Qs[o + 16 * c];
         fd[c] = Ds[o + 16 * c];
       }
 #pragma unroll
-      for (int bi = 0; bi < NCB; ++bi)
+      for (int bi = 0; bi < NCT; ++bi)
 #pragma unroll
-        for (int bj = 0; bj < NCB; ++bj) acc[bi * NCB + bj] = mfma64(fq[bi], fd[bj], acc[bi * NCB + bj]);
+        for (int bj = 0; bj < NCT; ++bj) acc[bi * NCT + bj] = mfma64(fq[bi], fd[bj], acc[bi * NCT + bj]);
+      if (any_face) {
+        const int ou = (kk + kq) * LDR + l16;
+        double fo[NCR], fn[NCR];
+#pragma unroll
+        for (int c = 0; c < NCR; ++c) {
+          fo[c] = Uo[ou + 16 * c];
+          fn[c] = Un[ou + 16 * c];
+        }
+#pragma unroll
+        for (int bi = 0; bi < NCT; ++bi)
+#pragma unroll
+          for (int bc = 0; bc < NCR; ++bc) {
+            acc[NQ + bi * NCR + bc] = mfma64(fq[bi], fo[bc], acc[NQ + bi * NCR + bc]);
+            acc[NQ + NX + bi * NCR + bc] = mfma64(fq[bi], fn[bc], acc[NQ + NX + bi * NCR + bc]);
+          }
+      }
     }
     wave_sync();
   }
-  pair_reduce_acc<NQ>(acc, lds);
+  pair_reduce_acc<NACC>(acc, lds);
   if ((wave & 1) == 0) {
-    double* out = gpart_of(d, s) + (int64_t)blockIdx.x * d.gpTile + (low ? 0 : T * T);
+    double* out = gpart_of(d, s) + (int64_t)blockIdx.x * d.gpTile;
+    double* og = out + (low ? 0 : T * T);
+    double* oo = out + 2 * T * T + (low ? 0 : T * R);
+    double* on = out + 2 * T * T + 2 * T * R + (low ? 0 : T * R);
 #pragma unroll
-    for (int bi = 0; bi < NCB; ++bi)
+    for (int bi = 0; bi < NCT; ++bi) {
 #pragma unroll
-      for (int bj = 0; bj < NCB; ++bj) store_block(out, t, t, t, bi, bj, acc[bi * NCB + bj], 1.0);
+      for (int bj = 0; bj < NCT; ++bj) store_block(og, t, t, t, bi, bj, acc[bi * NCT + bj], 1.0);
+#pragma unroll
+      for (int bc = 0; bc < NCR; ++bc) {
+        store_block(oo, T, t, r, bi, bc, acc[NQ + bi * NCR + bc], 1.0);
+        store_block(on, T, t, rn, bi, bc, acc[NQ + NX + bi * NCR + bc], 1.0);
+      }
+    }
   }
 }
 
@@ -1003,10 +1061,16 @@ void launch_kstep(const Dev& d, int axis, int sd0, int nsd, hipStream_t st) {
 }
 
 void launch_spatial_reduce(const Dev& d, int axis, int sd0, int nsd, const double* Q, hipStream_t st) {
-  with_ncb(ncb_of(d.T), [&](auto c) {
-    constexpr int NC = decltype(c)::value;
-    const size_t lds = D8 * std::max<size_t>(NW * 2 * 16 * strip_ld<NC>(), (size_t)2 * NC * NC * 256);
-    hipLaunchKernelGGL((k_spatial_reduce<NC>), dim3(d.nwgN, nsd), dim3(NTHR), lds, st, d, axis, sd0, Q);
+  with_ncb(ncb_of(d.T), [&](auto ct) {
+    constexpr int NT = decltype(ct)::value;
+    with_ncb(ncb_of(d.R), [&](auto cr) {
+      constexpr int NR = decltype(cr)::value;
+      constexpr int NACC = NT * NT + 2 * NT * NR;
+      const size_t lds =
+          D8 * std::max<size_t>(NW * 2 * 16 * (strip_ld<NT>() + strip_ld<NR>()), (size_t)2 * NACC * 256);
+      if constexpr (NR <= 2)  // stored ranks are at most 21
+        hipLaunchKernelGGL((k_spatial_reduce<NT, NR>), dim3(d.nwgN, nsd), dim3(NTHR), lds, st, d, axis, sd0, Q);
+    });
   });
 }
 
@@ -1058,7 +1122,6 @@ void init_kernels() {
       constexpr int NC = decltype(c)::value;
       allow_lds((const void*)k_aug_form<NC, 4 * NC>);
       allow_lds((const void*)k_kstep<NC>);
-      allow_lds((const void*)k_spatial_reduce<NC>);
       allow_lds((const void*)k_lstep<NC, 4 * NC>);
       for (int kc = 1; kc <= 4; ++kc) {
         with_ncb(kc, [&](auto k) {
@@ -1069,7 +1132,10 @@ void init_kernels() {
       for (int nr = 1; nr <= 2; ++nr) {
         with_ncb(nr, [&](auto r) {
           constexpr int NR = decltype(r)::value;
-          if constexpr (NR <= 2) allow_lds((const void*)k_ang_reduce<NC, NR>);
+          if constexpr (NR <= 2) {
+            allow_lds((const void*)k_ang_reduce<NC, NR>);
+            allow_lds((const void*)k_spatial_reduce<NC, NR>);
+          }
         });
       }
     });
