@@ -51,7 +51,17 @@ typedef enum {
   DD_ESTATE = -6     /* call not valid in the handle's current state           */
 } dd_status;
 
-enum { DD_PREC_FP64 = 0, DD_PREC_MIXED_FP32 = 1 };
+/* Precision of the step.  DD_PREC_FP64: everything in FP64.  The mixed modes
+ * keep the K-, L-step and V-hat working arrays (K1, the QR of K1, L1, the QR
+ * of L1, V-hat: the widest tall-skinny data, t = the intermediate rank
+ * columns) in FP32 in device memory and form the K-/L-step contractions and
+ * the final basis rotations on the matrix cores in FP32 (DD_PREC_MIXED_FP32)
+ * or as split BF16 products hi*hi + hi*lo + lo*hi with FP32 accumulation
+ * (DD_PREC_MIXED_BF16).  The stored factors U, S, V, the augmentation matrix
+ * and its SVD, the Gram and Galerkin reductions, the Cholesky QR factors and
+ * products, the S-step and the eigen-split stay FP64, and so does everything
+ * returned through this interface. */
+enum { DD_PREC_FP64 = 0, DD_PREC_MIXED_FP32 = 1, DD_PREC_MIXED_BF16 = 2 };
 enum { DD_RANK_FIXED = 0, DD_RANK_ADAPTIVE = 1 };
 enum { DD_EXEC_PER_SUBDOMAIN = 0, DD_EXEC_BATCHED = 1, DD_EXEC_BATCHED_GRAPH = 2 };
 enum { DD_BC_VACUUM = 0 };

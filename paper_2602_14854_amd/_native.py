@@ -14,7 +14,7 @@ from typing import List, Optional, Sequence, Tuple
 import numpy as np
 
 DD_OK, DD_EINVAL, DD_ENOMEM, DD_EHIP, DD_ERANK, DD_ENUMERIC, DD_ESTATE = 0, -1, -2, -3, -4, -5, -6
-DD_PREC_FP64, DD_PREC_MIXED_FP32 = 0, 1
+DD_PREC_FP64, DD_PREC_MIXED_FP32, DD_PREC_MIXED_BF16 = 0, 1, 2
 DD_RANK_FIXED, DD_RANK_ADAPTIVE = 0, 1
 DD_EXEC_PER_SUBDOMAIN, DD_EXEC_BATCHED, DD_EXEC_BATCHED_GRAPH = 0, 1, 2
 

@@ -104,7 +104,7 @@ std::string validate(const dd_dlra_config* c) {
   if (c->r_int_max < R) return "r_int_max must be at least the stored-rank capacity";
   if (c->r_int_max > dd::CAP) return "r_int_max beyond the supported maximum of 64";
   if (3 * R > dd::CAP) return "stored-rank capacity beyond the supported maximum of 21";
-  if (c->precision != DD_PREC_FP64) return "only DD_PREC_FP64 is available";
+  if (c->precision < DD_PREC_FP64 || c->precision > DD_PREC_MIXED_BF16) return "unknown precision";
   if (c->exec_mode < DD_EXEC_PER_SUBDOMAIN || c->exec_mode > DD_EXEC_BATCHED_GRAPH) return "unknown exec_mode";
   for (int f = 0; f < 4; ++f)
     if (c->bc[f] != DD_BC_VACUUM) return "only vacuum physical boundaries are available";
@@ -172,6 +172,8 @@ Layout make_layout(const dd_dlra_config* c) {
   L.smallStride = o;
   // arena
   const size_t d8 = sizeof(double);
+  // K-, L-step and V-hat working arrays: FP32 in the mixed modes
+  const size_t es = c->precision == DD_PREC_FP64 ? sizeof(double) : sizeof(float);
   const size_t ns = L.nsub;
   size_t b = 0;
   auto seg = [&](size_t bytes) {
@@ -184,12 +186,12 @@ Layout make_layout(const dd_dlra_config* c) {
   L.oS = seg(ns * R * R * d8);
   L.oA = seg(ns * L.M * MA * d8);
   L.oZ = seg(ns * L.M * MA * d8);
-  L.oQh = seg(ns * L.M * T * d8);
-  L.oQh2 = seg(ns * L.M * T * d8);
-  L.oK1 = seg(ns * L.N * T * d8);
-  L.oK2 = seg(ns * L.N * T * d8);
-  L.oAL = seg(ns * L.M * T * d8);
-  L.oAL2 = seg(ns * L.M * T * d8);
+  L.oQh = seg(ns * L.M * T * es);
+  L.oQh2 = seg(ns * L.M * T * es);
+  L.oK1 = seg(ns * L.N * T * es);
+  L.oK2 = seg(ns * L.N * T * es);
+  L.oAL = seg(ns * L.M * T * es);
+  L.oAL2 = seg(ns * L.M * T * es);
   L.oGP = seg(ns * L.gpStride * d8);
   L.oSM = seg(ns * L.smallStride * d8);
   L.oRho = seg((size_t)c->nx * c->ny * d8);
@@ -235,6 +237,7 @@ void fill_dev(Dev& d, const Layout& L, const dd_dlra_config* c, char* base) {
   d.r_max = c->rank_mode == DD_RANK_FIXED ? c->r_fixed : c->r_max;
   d.r_int_max = c->r_int_max;
   d.strict = c->strict_caps;
+  d.prec = c->precision;
   d.tol = c->tol;
   d.tol_aug_rel = c->tol_aug_rel;
   d.U = (double*)(base + L.oU);
@@ -242,12 +245,12 @@ void fill_dev(Dev& d, const Layout& L, const dd_dlra_config* c, char* base) {
   d.S = (double*)(base + L.oS);
   d.A = (double*)(base + L.oA);
   d.Z = (double*)(base + L.oZ);
-  d.Qh = (double*)(base + L.oQh);
-  d.Qh2 = (double*)(base + L.oQh2);
-  d.K1 = (double*)(base + L.oK1);
-  d.K2 = (double*)(base + L.oK2);
-  d.AL = (double*)(base + L.oAL);
-  d.AL2 = (double*)(base + L.oAL2);
+  d.Qh = (void*)(base + L.oQh);
+  d.Qh2 = (void*)(base + L.oQh2);
+  d.K1 = (void*)(base + L.oK1);
+  d.K2 = (void*)(base + L.oK2);
+  d.AL = (void*)(base + L.oAL);
+  d.AL2 = (void*)(base + L.oAL2);
   d.gpart = (double*)(base + L.oGP);
   d.small = (double*)(base + L.oSM);
   d.rho = (double*)(base + L.oRho);
@@ -384,7 +387,7 @@ void phase(dd_dlra_handle h, int kind, F&& f) {
 // ndim) leaving Q in Y (X is used as scratch); the R factors accumulate in
 // the small workspace.  With final_dst set, the last product writes there
 // instead (stride ysd_final, optional row scale, Rinv scaled by bscale).
-void chol_qr3(dd_dlra_handle h, int axis, int ndim, double* X, double* Y, int64_t sdstride, int rows, bool cells,
+void chol_qr3(dd_dlra_handle h, int axis, int ndim, void* X, void* Y, int64_t sdstride, int rows, bool cells,
               double* final_dst, int64_t final_sd, const double* final_rowscale, double bscale, int gemm_kind) {
   const Dev& d = h->d;
   hipStream_t st = h->stream;
@@ -393,24 +396,24 @@ void chol_qr3(dd_dlra_handle h, int axis, int ndim, double* X, double* Y, int64_
     dd::launch_chol(d, axis, s0, ns, ndim, rows, ngp, true, 1, 1.0, false, d.oRinv, d.oRacc, d.T, st);
   });
   phase(h, gemm_kind, [&](int s0, int ns) {
-    dd::launch_gemm(d, axis, s0, ns, X, sdstride, rows, ndim, ndim, d.oRinv, d.T, Y, sdstride, nullptr, true, d.oFill,
-                    cells, st);
+    dd::launch_gemm(d, axis, s0, ns, X, false, sdstride, rows, ndim, ndim, d.oRinv, d.T, Y, false, sdstride, nullptr,
+                    true, d.oFill, cells, true, st);
   });
   phase(h, K_CHOL, [&](int s0, int ns) {
     dd::launch_chol(d, axis, s0, ns, ndim, rows, ngp, false, 2, 1.0, false, d.oRinv, d.oRacc, d.T, st);
   });
   phase(h, gemm_kind, [&](int s0, int ns) {
-    dd::launch_gemm(d, axis, s0, ns, Y, sdstride, rows, ndim, ndim, d.oRinv, d.T, X, sdstride, nullptr, true, d.oFill,
-                    cells, st);
+    dd::launch_gemm(d, axis, s0, ns, Y, false, sdstride, rows, ndim, ndim, d.oRinv, d.T, X, false, sdstride, nullptr,
+                    true, d.oFill, cells, true, st);
   });
   phase(h, K_CHOL, [&](int s0, int ns) {
     dd::launch_chol(d, axis, s0, ns, ndim, rows, ngp, false, 2, bscale, false, d.oRinv, d.oRacc, d.T, st);
   });
-  double* dst = final_dst ? final_dst : Y;
+  void* dst = final_dst ? (void*)final_dst : Y;
   const int64_t dsd = final_dst ? final_sd : sdstride;
   phase(h, gemm_kind, [&](int s0, int ns) {
-    dd::launch_gemm(d, axis, s0, ns, X, sdstride, rows, ndim, ndim, d.oRinv, d.T, dst, dsd, final_rowscale, false,
-                    d.oFill, cells, st);
+    dd::launch_gemm(d, axis, s0, ns, X, false, sdstride, rows, ndim, ndim, d.oRinv, d.T, dst, final_dst != nullptr,
+                    dsd, final_rowscale, false, d.oFill, cells, true, st);
   });
 }
 
@@ -431,25 +434,25 @@ void enqueue_advection(dd_dlra_handle h, int axis) {
     // pass 0: Z = A P R^-1; pass 1: Z <- Z R^-1 in place (each strip of rows
     // is read completely before it is written)
     phase(h, K_GEMM_QR_A, [&](int s0, int ns) {
-      dd::launch_gemm(d, axis, s0, ns, pass == 0 ? d.A : d.Z, sdMA, d.M, dd::DIM_M0, dd::DIM_M0, d.oRinvA, d.MA,
-                      d.Z, sdMA, nullptr, true, d.oFill, false, st);
+      dd::launch_gemm(d, axis, s0, ns, pass == 0 ? d.A : d.Z, true, sdMA, d.M, dd::DIM_M0, dd::DIM_M0, d.oRinvA,
+                      d.MA, d.Z, true, sdMA, nullptr, true, d.oFill, false, true, st);
     });
   }
   phase(h, K_AUG_SVD, [&](int s0, int ns) { dd::launch_aug_svd(d, axis, s0, ns, st); });
   phase(h, K_GEMM_VHAT, [&](int s0, int ns) {
-    dd::launch_gemm(d, axis, s0, ns, d.A, sdMA, d.M, dd::DIM_M0, dd::DIM_T, d.oCoef, d.MA, d.Qh, sdMT, nullptr, true,
-                    d.oFill, false, st);
+    dd::launch_gemm(d, axis, s0, ns, d.A, true, sdMA, d.M, dd::DIM_M0, dd::DIM_T, d.oCoef, d.MA, d.Qh, false, sdMT,
+                    nullptr, true, d.oFill, false, true, st);
   });
   // two Cholesky QR passes make V-hat orthonormal to working precision
   for (int pass = 0; pass < 2; ++pass) {
-    double* src = pass == 0 ? d.Qh : d.Qh2;
-    double* dst = pass == 0 ? d.Qh2 : d.Qh;
+    void* src = pass == 0 ? d.Qh : d.Qh2;
+    void* dst = pass == 0 ? d.Qh2 : d.Qh;
     phase(h, K_CHOL, [&](int s0, int ns) {
       dd::launch_chol(d, axis, s0, ns, dd::DIM_T, d.M, d.nwgM, false, 0, 1.0, false, d.oRinv, d.oRacc, d.T, st);
     });
     phase(h, K_GEMM_QR_VHAT, [&](int s0, int ns) {
-      dd::launch_gemm(d, axis, s0, ns, src, sdMT, d.M, dd::DIM_T, dd::DIM_T, d.oRinv, d.T, dst, sdMT, nullptr,
-                      pass == 0, d.oFill, false, st);
+      dd::launch_gemm(d, axis, s0, ns, src, false, sdMT, d.M, dd::DIM_T, dd::DIM_T, d.oRinv, d.T, dst, false, sdMT,
+                      nullptr, pass == 0, d.oFill, false, true, st);
     });
   }
   // angular Galerkin matrices, eigen-split of C, K-step coefficients
@@ -467,12 +470,12 @@ void enqueue_advection(dd_dlra_handle h, int axis) {
   // Algorithm 5: truncation, then rotate the bases into the state
   phase(h, K_TRUNC, [&](int s0, int ns) { dd::launch_trunc(d, axis, s0, ns, st); });
   phase(h, K_GEMM_FINAL_U, [&](int s0, int ns) {
-    dd::launch_gemm(d, axis, s0, ns, d.K2, sdNT, d.N, dd::DIM_T, dd::DIM_RNEW, d.oBu, d.T, d.U, (int64_t)d.N * d.R,
-                    nullptr, false, -1, true, st);
+    dd::launch_gemm(d, axis, s0, ns, d.K2, false, sdNT, d.N, dd::DIM_T, dd::DIM_RNEW, d.oBu, d.T, d.U, true,
+                    (int64_t)d.N * d.R, nullptr, false, -1, true, false, st);
   });
   phase(h, K_GEMM_FINAL_V, [&](int s0, int ns) {
-    dd::launch_gemm(d, axis, s0, ns, d.AL2, sdMT, d.M, dd::DIM_T, dd::DIM_RNEW, d.oBv, d.T, d.V, (int64_t)d.M * d.R,
-                    d.isw, false, -1, false, st);
+    dd::launch_gemm(d, axis, s0, ns, d.AL2, false, sdMT, d.M, dd::DIM_T, dd::DIM_RNEW, d.oBv, d.T, d.V, true,
+                    (int64_t)d.M * d.R, d.isw, false, -1, false, false, st);
   });
   phase(h, K_SET_RANK, [&](int s0, int ns) { dd::launch_set_rank(d, s0, ns, st); });
 }

@@ -33,10 +33,11 @@ struct Dev {
   int gpTile;              // doubles per workgroup partial
   int64_t gpStride;        // doubles of partials per subdomain
   int64_t smallStride;     // doubles of small workspace per subdomain
-  // rank rules
+  // rank rules and precision mode (DD_PREC_*)
   int rank_mode, r_fixed, r_min, r_max, r_int_max, strict;
+  int prec;
   double tol, tol_aug_rel;
-  // state
+  // state (FP64 in every mode)
   double* U;               // [nsub][R][N]
   double* V;               // [nsub][R][M]
   double* S;               // [nsub][R][R]
@@ -48,15 +49,16 @@ struct Dev {
   int forced;
   unsigned* flags;         // [1]
   unsigned long long* clamps;  // [1]
-  // scratch
+  // scratch; the K-, L-step and V-hat working arrays (void*) hold FP64 in
+  // DD_PREC_FP64 and FP32 in the mixed modes
   double* A;               // [nsub][MA][M]   weighted augmentation matrix
   double* Z;               // [nsub][MA][M]
-  double* Qh;              // [nsub][T][M]    sqrt(w) * V-hat
-  double* Qh2;             // [nsub][T][M]
-  double* K1;              // [nsub][T][N]
-  double* K2;              // [nsub][T][N]
-  double* AL;              // [nsub][T][M]
-  double* AL2;             // [nsub][T][M]
+  void* Qh;                // [nsub][T][M]    sqrt(w) * V-hat
+  void* Qh2;               // [nsub][T][M]
+  void* K1;                // [nsub][T][N]
+  void* K2;                // [nsub][T][N]
+  void* AL;                // [nsub][T][M]
+  void* AL2;               // [nsub][T][M]
   double* gpart;           // [nsub][gpStride]
   double* small;           // [nsub][smallStride]
   double* rho;             // [ny*nx]
@@ -147,12 +149,15 @@ namespace dd {
 // tall-skinny kernels
 void init_kernels();
 void launch_aug_form(const Dev& d, int axis, int sd0, int nsd, hipStream_t st);
-void launch_gemm(const Dev& d, int axis, int sd0, int nsd, const double* X, int64_t xsd, int rows,
-                 int kdim, int ndim, int boff, int bld, double* Y, int64_t ysd, const double* rowscale,
-                 bool gram, int fill_off, bool rows_are_cells, hipStream_t st);
+// Y = diag(rowscale) X B.  x64 / y64: X / Y is an FP64 array (else of the
+// working type of the precision mode); exact: formed in FP64 whatever the
+// precision mode (QR and SVD products).
+void launch_gemm(const Dev& d, int axis, int sd0, int nsd, const void* X, bool x64, int64_t xsd, int rows,
+                 int kdim, int ndim, int boff, int bld, void* Y, bool y64, int64_t ysd, const double* rowscale,
+                 bool gram, int fill_off, bool rows_are_cells, bool exact, hipStream_t st);
 void launch_ang_reduce(const Dev& d, int axis, int sd0, int nsd, hipStream_t st);
 void launch_kstep(const Dev& d, int axis, int sd0, int nsd, hipStream_t st);
-void launch_spatial_reduce(const Dev& d, int axis, int sd0, int nsd, const double* Q, hipStream_t st);
+void launch_spatial_reduce(const Dev& d, int axis, int sd0, int nsd, const void* Q, hipStream_t st);
 void launch_lstep(const Dev& d, int axis, int sd0, int nsd, hipStream_t st);
 void launch_coll_kstep(const Dev& d, int sd0, int nsd, hipStream_t st);
 void launch_coll_reduce(const Dev& d, int sd0, int nsd, hipStream_t st);

@@ -17,12 +17,12 @@
 #include <algorithm>
 #include <type_traits>
 
+#include "dd_dlra.h"
 #include "dd_mfma.h"
 
 namespace dd {
 
 constexpr int CAPR = 21;  // largest stored rank (3 * CAPR <= CAP)
-constexpr int KSR = 6;    // k-steps of 4 covering CAPR
 
 __host__ __device__ constexpr int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
@@ -33,8 +33,10 @@ __host__ __device__ constexpr int ceil_div(int a, int b) { return (a + b - 1) / 
 // formed as one product [V | V_lo | V_hi] blockdiag(S^T, S_lo^T, S_hi^T);
 // leaves the partial Gram matrix A^T A.
 // ----------------------------------------------------------------------------
-template <int NCB, int KS>
+template <class S, int P, int NCB, int KS>
 __global__ __launch_bounds__(NTHR) void k_aug_form(Dev d, int axis, int sd0) {
+  using F = typename Prec<P>::F;
+  using Acc = typename Prec<P>::Acc;
   constexpr int LD = strip_ld<NCB>();
   constexpr int NB = NCB * (NCB + 1) / 2;
   const int s = sd0 + blockIdx.y;
@@ -48,11 +50,11 @@ __global__ __launch_bounds__(NTHR) void k_aug_form(Dev d, int axis, int sd0) {
   const int l16 = lane & 15, kq = lane >> 4;
 
   extern __shared__ double lds[];
-  double* Bf = lds;                                   // KS * NCB fragments
-  double* Ys = lds + KS * NCB * 64 + wave * 16 * LD;  // wavefront strip
+  F* Bf = reinterpret_cast<F*>(lds);                                  // KS * NCB fragments
+  double* Ys = lds + frag_doubles<P>(KS * NCB * 64) + wave * 16 * LD;  // wavefront strip
   for (int idx = threadIdx.x; idx < KS * NCB * 64; idx += NTHR) {
-    const int l = idx & 63, f = idx >> 6, cb = f % NCB, ks = f / NCB;
-    const int kc = 4 * ks + (l >> 4), col = 16 * cb + (l & 15);
+    const int l = idx & 63, f = idx >> 6, cb = f % NCB, u = f / NCB;
+    const int kc = sub_col<P>(u, l >> 4), col = 16 * cb + (l & 15);
     double v = 0.0;
     if (kc < m0 && col < m0) {
       const int bk = kc < c1 ? 0 : (kc < c2 ? 1 : 2);
@@ -62,45 +64,40 @@ __global__ __launch_bounds__(NTHR) void k_aug_form(Dev d, int axis, int sd0) {
         v = d.S[(int64_t)nb[bk] * R * R + (col - off) + (int64_t)(kc - off) * R];
       }
     }
-    Bf[idx] = v;
+    Bf[idx] = (F)v;
   }
   __syncthreads();
 
   const double* Vb[3];
   for (int b = 0; b < 3; ++b) Vb[b] = nb[b] >= 0 ? d.V + (int64_t)nb[b] * M * R : d.V;
-  double* As = d.A + (int64_t)s * M * d.MA;
+  S* As = (S*)d.A + (int64_t)s * M * d.MA;
+  const int nlive = live_sub<P>(m0);
   dbl4 g[NB];
   zero_acc<NB>(g);
   const int nst = ceil_div(M, 16);
   for (int st = blockIdx.x * NW + wave; st < nst; st += gridDim.x * NW) {
     const int q = st * 16 + l16;
     const bool rin = q < M;
-    double xv[KS];
+    F xv[KS];
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      const int kc = 4 * ks + kq;
+    for (int u = 0; u < KS; ++u) {
+      const int kc = sub_col<P>(u, kq);
       const int bk = kc < c1 ? 0 : (kc < c2 ? 1 : 2);
       const int off = bk == 0 ? 0 : (bk == 1 ? c1 : c2);
-      xv[ks] = (rin && kc < m0) ? Vb[bk][(int64_t)(kc - off) * M + q] : 0.0;
+      xv[u] = (rin && kc < m0) ? (F)Vb[bk][(int64_t)(kc - off) * M + q] : (F)0;
     }
-    dbl4 acc[NCB];
-    zero_acc<NCB>(acc);
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      if (4 * ks < m0) {
-#pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) acc[cb] = mfma64(Bf[(ks * NCB + cb) * 64 + lane], xv[ks], acc[cb]);
-      }
-    }
+    Acc acc[NCB];
+    zero_prod<P>(acc, NCB);
+    prod_acc<P, NCB, KS>(acc, Bf, xv, nlive);
     const double swq = rin ? d.sw[q] : 0.0;
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int j = 16 * cb + 4 * v + kq;
-        const double val = acc[cb][v] * swq;
+        const int j = out_col<P>(cb, v, kq);
+        const S val = (S)((double)acc[cb][v] * swq);
         if (rin && j < m0) As[(int64_t)j * M + q] = val;
-        Ys[l16 * LD + j] = val;
+        Ys[l16 * LD + j] = (double)val;
       }
     }
     wave_sync();
@@ -118,10 +115,12 @@ __global__ __launch_bounds__(NTHR) void k_aug_form(Dev d, int axis, int sd0) {
 // deterministic pseudo-random values (used to complete a basis where the
 // data carry no information).
 // ----------------------------------------------------------------------------
-template <int NCB, int KS>
-__global__ __launch_bounds__(NTHR) void k_gemm(Dev d, int axis, int sd0, const double* X, int64_t xsd, int rows,
-                                               int kdim, int ndim, int boff, int bld, double* Y, int64_t ysd,
+template <class SI, class S, int P, int NCB, int KS>
+__global__ __launch_bounds__(NTHR) void k_gemm(Dev d, int axis, int sd0, const void* X, int64_t xsd, int rows,
+                                               int kdim, int ndim, int boff, int bld, void* Y, int64_t ysd,
                                                const double* rowscale, int gram, int fill_off) {
+  using F = typename Prec<P>::F;
+  using Acc = typename Prec<P>::Acc;
   constexpr int LD = strip_ld<NCB>();
   constexpr int NB = NCB * (NCB + 1) / 2;
   const int s = sd0 + blockIdx.y;
@@ -130,53 +129,49 @@ __global__ __launch_bounds__(NTHR) void k_gemm(Dev d, int axis, int sd0, const d
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int l16 = lane & 15, kq = lane >> 4;
   extern __shared__ double lds[];
-  double* Bf = lds;
-  double* Ys = lds + KS * NCB * 64 + wave * 16 * LD;
+  F* Bf = reinterpret_cast<F*>(lds);
+  double* Ys = lds + frag_doubles<P>(KS * NCB * 64) + wave * 16 * LD;
   __shared__ int fillm[16 * NCB];
   const double* sm = small_of(d, s);
   for (int idx = threadIdx.x; idx < KS * NCB * 64; idx += NTHR) {
-    const int l = idx & 63, f = idx >> 6, cb = f % NCB, ks = f / NCB;
-    const int kc = 4 * ks + (l >> 4), col = 16 * cb + (l & 15);
-    Bf[idx] = (kc < k && col < n) ? sm[boff + kc + col * bld] : 0.0;
+    const int l = idx & 63, f = idx >> 6, cb = f % NCB, u = f / NCB;
+    const int kc = sub_col<P>(u, l >> 4), col = 16 * cb + (l & 15);
+    Bf[idx] = (kc < k && col < n) ? (F)sm[boff + kc + col * bld] : (F)0;
   }
   for (int j = threadIdx.x; j < 16 * NCB; j += NTHR)
     fillm[j] = (fill_off >= 0 && j < n) ? (sm[fill_off + j] != 0.0) : 0;
   __syncthreads();
 
-  const double* Xsd = X + (int64_t)s * xsd;
-  double* Ysd = Y + (int64_t)s * ysd;
+  const SI* Xsd = (const SI*)X + (int64_t)s * xsd;
+  S* Ysd = (S*)Y + (int64_t)s * ysd;
+  const int nlive = live_sub<P>(k);
   dbl4 g[NB];
   zero_acc<NB>(g);
   const int nst = ceil_div(rows, 16);
   for (int st = blockIdx.x * NW + wave; st < nst; st += gridDim.x * NW) {
     const int row = st * 16 + l16;
     const bool rin = row < rows;
-    double xv[KS];
+    F xv[KS];
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      const int kc = 4 * ks + kq;
-      xv[ks] = (rin && kc < k) ? Xsd[(int64_t)kc * rows + row] : 0.0;
+    for (int u = 0; u < KS; ++u) {
+      const int kc = sub_col<P>(u, kq);
+      xv[u] = (rin && kc < k) ? (F)Xsd[(int64_t)kc * rows + row] : (F)0;
     }
-    dbl4 acc[NCB];
-    zero_acc<NCB>(acc);
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      if (4 * ks < k) {
-#pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) acc[cb] = mfma64(Bf[(ks * NCB + cb) * 64 + lane], xv[ks], acc[cb]);
-      }
-    }
+    Acc acc[NCB];
+    zero_prod<P>(acc, NCB);
+    prod_acc<P, NCB, KS>(acc, Bf, xv, nlive);
     const double rs = (rowscale != nullptr && rin) ? rowscale[row] : 1.0;
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int j = 16 * cb + 4 * v + kq;
-        double val = acc[cb][v] * rs;
+        const int j = out_col<P>(cb, v, kq);
+        double val = (double)acc[cb][v] * rs;
         if (fillm[j]) val = hash_unit(((uint64_t)s << 40) ^ ((uint64_t)j << 24) ^ (uint64_t)row);
         if (!rin) val = 0.0;
-        if (rin && j < n) Ysd[(int64_t)j * rows + row] = val;
-        if (gram) Ys[l16 * LD + j] = val;
+        const S sv = (S)val;
+        if (rin && j < n) Ysd[(int64_t)j * rows + row] = sv;
+        if (gram) Ys[l16 * LD + j] = (double)sv;
       }
     }
     if (gram) {
@@ -202,7 +197,7 @@ __global__ __launch_bounds__(NTHR) void k_gemm(Dev d, int axis, int sd0, const d
 // Olo @R*T+3T*T (ld R), Ohi @2R*T+3T*T (ld R); the t x t blocks use
 // leading dimension t inside their T*T slots.
 // ----------------------------------------------------------------------------
-template <int NCT, int NCR>
+template <class S, int NCT, int NCR>
 __global__ __launch_bounds__(NTHR) void k_ang_reduce(Dev d, int axis, int sd0) {
   // wavefronts 0-1 form Tm, Olo, Ohi; wavefronts 2-3 form C, Ep, En; each
   // pair walks the same strips
@@ -224,9 +219,10 @@ __global__ __launch_bounds__(NTHR) void k_ang_reduce(Dev d, int axis, int sd0) {
   double* Xs = lds + wave * (16 * LD + 16);  // strip, then 16 values of Omega
   double* oms = Xs + 16 * LD;
 
-  const double* Qsd = d.Qh + (int64_t)s * M * T;
-  const double* Vsrc[3] = {d.V + (int64_t)s * M * R, lo >= 0 ? d.V + (int64_t)lo * M * R : d.V,
-                           hi >= 0 ? d.V + (int64_t)hi * M * R : d.V};
+  const S* Qsd = (const S*)d.Qh + (int64_t)s * M * T;
+  const double* Vs = d.V;
+  const double* Vsrc[3] = {Vs + (int64_t)s * M * R, lo >= 0 ? Vs + (int64_t)lo * M * R : Vs,
+                           hi >= 0 ? Vs + (int64_t)hi * M * R : Vs};
   const int rv[3] = {r, rl, rh};
   dbl4 acc[NACC];
   zero_acc<NACC>(acc);
@@ -238,7 +234,7 @@ __global__ __launch_bounds__(NTHR) void k_ang_reduce(Dev d, int axis, int sd0) {
 #pragma unroll
     for (int ks = 0; ks < KST; ++ks) {
       const int c = 4 * ks + kq;
-      xq[ks] = (rin && c < t) ? Qsd[(int64_t)c * M + q] : 0.0;
+      xq[ks] = (rin && c < t) ? (double)Qsd[(int64_t)c * M + q] : 0.0;
     }
     if (grp_v) {
       double xv[3][KSV];
@@ -340,10 +336,13 @@ __global__ __launch_bounds__(NTHR) void k_ang_reduce(Dev d, int axis, int sd0) {
 // coefficient matrices (r x t) come from the eigen-split C = C+ + C-.
 // Also leaves the partial Gram matrix K1^T K1.
 // ----------------------------------------------------------------------------
-template <int NCB>
+template <class S, int P, int NCB>
 __global__ __launch_bounds__(NTHR) void k_kstep(Dev d, int axis, int sd0, int ksr) {
+  using F = typename Prec<P>::F;
+  using Acc = typename Prec<P>::Acc;
   constexpr int LD = strip_ld<NCB>();
   constexpr int NB = NCB * (NCB + 1) / 2;
+  constexpr int KSP = P == 2 ? 8 : 6;  // sub-steps covering the largest stored rank
   const int s = sd0 + blockIdx.y;
   const int lo = neighbour(d, s, axis, -1), hi = neighbour(d, s, axis, +1);
   const int r = d.rank[s], rl = lo >= 0 ? d.rank[lo] : 0, rh = hi >= 0 ? d.rank[hi] : 0;
@@ -352,27 +351,28 @@ __global__ __launch_bounds__(NTHR) void k_kstep(Dev d, int axis, int sd0, int ks
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int l16 = lane & 15, kq = lane >> 4;
   extern __shared__ double lds[];
-  // fragments of the 7 coefficient blocks: Cf[((m * ksr + ks) * NCB + cb) * 64 + lane]
+  // fragments of the 7 coefficient blocks: Cf[((m * ksr + u) * NCB + cb) * 64 + lane]
   const int nfrag = 7 * ksr * NCB * 64;
-  double* Cf = lds;
-  double* Ys = lds + nfrag + wave * 16 * LD;
+  F* Cf = reinterpret_cast<F*>(lds);
+  double* Ys = lds + frag_doubles<P>(nfrag) + wave * 16 * LD;
   {
     const double* sm = small_of(d, s);
     const int offs[7] = {d.oM0, d.oMm, d.oMp, d.oGLo, d.oGHi, d.oGLoN, d.oGHiN};
     const int rows[7] = {r, r, r, r, r, rl, rh};
     for (int idx = threadIdx.x; idx < nfrag; idx += NTHR) {
-      const int l = idx & 63, f = idx >> 6, cb = f % NCB, ks = (f / NCB) % ksr, m = f / (NCB * ksr);
-      const int kc = 4 * ks + (l >> 4), col = 16 * cb + (l & 15);
-      Cf[idx] = (kc < rows[m] && col < t) ? sm[offs[m] + kc + col * R] : 0.0;
+      const int l = idx & 63, f = idx >> 6, cb = f % NCB, u = (f / NCB) % ksr, m = f / (NCB * ksr);
+      const int kc = sub_col<P>(u, l >> 4), col = 16 * cb + (l & 15);
+      Cf[idx] = (kc < rows[m] && col < t) ? (F)sm[offs[m] + kc + col * R] : (F)0;
     }
   }
   __syncthreads();
-  auto frag = [&](int m, int ks, int cb) { return Cf[((m * ksr + ks) * NCB + cb) * 64 + lane]; };
+  const int bstride = ksr * NCB * 64;
 
-  const double* Us = d.U + (int64_t)s * N * R;
-  const double* Ul = lo >= 0 ? d.U + (int64_t)lo * N * R : d.U;
-  const double* Uh = hi >= 0 ? d.U + (int64_t)hi * N * R : d.U;
-  double* K1 = d.K1 + (int64_t)s * N * d.T;
+  const double* Ub = d.U;
+  const double* Us = Ub + (int64_t)s * N * R;
+  const double* Ul = lo >= 0 ? Ub + (int64_t)lo * N * R : Ub;
+  const double* Uh = hi >= 0 ? Ub + (int64_t)hi * N * R : Ub;
+  S* K1 = (S*)d.K1 + (int64_t)s * N * d.T;
   const int e = axis == 0 ? 1 : d.lnx;
   const int na = axis == 0 ? d.lnx : d.lny;
   dbl4 g[NB];
@@ -386,77 +386,53 @@ __global__ __launch_bounds__(NTHR) void k_kstep(Dev d, int axis, int sd0, int ks
     const int f = axis == 0 ? iy : ix;
     const bool hm = rin && ia > 0, hp = rin && ia < na - 1;
     const bool flo = rin && ia == 0, fhi = rin && ia == na - 1;
-    double u0[KSR], um[KSR], up[KSR];
+    F u0[KSP], um[KSP], up[KSP];
 #pragma unroll
-    for (int ks = 0; ks < KSR; ++ks) {
-      const int kc = 4 * ks + kq;
-      const bool kin = ks < ksr && kc < r;
+    for (int u = 0; u < KSP; ++u) {
+      const int kc = sub_col<P>(u, kq);
+      const bool kin = u < ksr && kc < r;
       const int64_t col = (int64_t)kc * N;
-      u0[ks] = (rin && kin) ? Us[col + p] : 0.0;
-      um[ks] = (hm && kin) ? Us[col + p - e] : 0.0;
-      up[ks] = (hp && kin) ? Us[col + p + e] : 0.0;
+      u0[u] = (rin && kin) ? (F)Us[col + p] : (F)0;
+      um[u] = (hm && kin) ? (F)Us[col + p - e] : (F)0;
+      up[u] = (hp && kin) ? (F)Us[col + p + e] : (F)0;
     }
-    dbl4 acc[NCB];
-    zero_acc<NCB>(acc);
-#pragma unroll
-    for (int ks = 0; ks < KSR; ++ks) {
-      if (ks < ksr) {
-#pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) {
-          acc[cb] = mfma64(frag(0, ks, cb), u0[ks], acc[cb]);
-          acc[cb] = mfma64(frag(1, ks, cb), um[ks], acc[cb]);
-          acc[cb] = mfma64(frag(2, ks, cb), up[ks], acc[cb]);
-        }
-      }
-    }
+    Acc acc[NCB];
+    zero_prod<P>(acc, NCB);
+    prod_acc<P, NCB, KSP>(acc, Cf, u0, ksr);
+    prod_acc<P, NCB, KSP>(acc, Cf + bstride, um, ksr);
+    prod_acc<P, NCB, KSP>(acc, Cf + 2 * bstride, up, ksr);
     if (__any(flo)) {
       const int pn = face_cell(d, axis, true, f);
-      double gn[KSR];
+      F gu[KSP], gn[KSP];
 #pragma unroll
-      for (int ks = 0; ks < KSR; ++ks) {
-        const int kc = 4 * ks + kq;
-        gn[ks] = (flo && lo >= 0 && ks < ksr && kc < rl) ? Ul[(int64_t)kc * N + pn] : 0.0;
+      for (int u = 0; u < KSP; ++u) {
+        const int kc = sub_col<P>(u, kq);
+        gu[u] = flo ? u0[u] : (F)0;
+        gn[u] = (flo && lo >= 0 && u < ksr && kc < rl) ? (F)Ul[(int64_t)kc * N + pn] : (F)0;
       }
-#pragma unroll
-      for (int ks = 0; ks < KSR; ++ks) {
-        if (ks < ksr) {
-          const double gu = flo ? u0[ks] : 0.0;
-#pragma unroll
-          for (int cb = 0; cb < NCB; ++cb) {
-            acc[cb] = mfma64(frag(3, ks, cb), gu, acc[cb]);
-            acc[cb] = mfma64(frag(5, ks, cb), gn[ks], acc[cb]);
-          }
-        }
-      }
+      prod_acc<P, NCB, KSP>(acc, Cf + 3 * bstride, gu, ksr);
+      prod_acc<P, NCB, KSP>(acc, Cf + 5 * bstride, gn, ksr);
     }
     if (__any(fhi)) {
       const int pn = face_cell(d, axis, false, f);
-      double gn[KSR];
+      F gu[KSP], gn[KSP];
 #pragma unroll
-      for (int ks = 0; ks < KSR; ++ks) {
-        const int kc = 4 * ks + kq;
-        gn[ks] = (fhi && hi >= 0 && ks < ksr && kc < rh) ? Uh[(int64_t)kc * N + pn] : 0.0;
+      for (int u = 0; u < KSP; ++u) {
+        const int kc = sub_col<P>(u, kq);
+        gu[u] = fhi ? u0[u] : (F)0;
+        gn[u] = (fhi && hi >= 0 && u < ksr && kc < rh) ? (F)Uh[(int64_t)kc * N + pn] : (F)0;
       }
-#pragma unroll
-      for (int ks = 0; ks < KSR; ++ks) {
-        if (ks < ksr) {
-          const double gu = fhi ? u0[ks] : 0.0;
-#pragma unroll
-          for (int cb = 0; cb < NCB; ++cb) {
-            acc[cb] = mfma64(frag(4, ks, cb), gu, acc[cb]);
-            acc[cb] = mfma64(frag(6, ks, cb), gn[ks], acc[cb]);
-          }
-        }
-      }
+      prod_acc<P, NCB, KSP>(acc, Cf + 4 * bstride, gu, ksr);
+      prod_acc<P, NCB, KSP>(acc, Cf + 6 * bstride, gn, ksr);
     }
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int j = 16 * cb + 4 * v + kq;
-        const double val = rin ? acc[cb][v] : 0.0;
+        const int j = out_col<P>(cb, v, kq);
+        const S val = rin ? (S)acc[cb][v] : (S)0;
         if (rin && j < t) K1[(int64_t)j * N + p] = val;
-        Ys[l16 * LD + j] = val;
+        Ys[l16 * LD + j] = (double)val;
       }
     }
     wave_sync();
@@ -478,8 +454,8 @@ __global__ __launch_bounds__(NTHR) void k_kstep(Dev d, int axis, int sd0, int ks
 // Partial layout: Gm @0, Gp @T*T (t x t, ld t), Xlo @2T*T, Xhi @2T*T+T*R,
 // Xln @2T*T+2T*R, Xhn @2T*T+3T*R (t x r_*, ld T).
 // ----------------------------------------------------------------------------
-template <int NCT, int NCR>
-__global__ __launch_bounds__(NTHR) void k_spatial_reduce(Dev d, int axis, int sd0, const double* Q) {
+template <class S, int NCT, int NCR>
+__global__ __launch_bounds__(NTHR) void k_spatial_reduce(Dev d, int axis, int sd0, const void* Q) {
   // wavefronts 0-1 form Gm and the low-face products, wavefronts 2-3 Gp and
   // the high-face products; each pair walks the same strips
   constexpr int LD = strip_ld<NCT>();
@@ -501,7 +477,7 @@ __global__ __launch_bounds__(NTHR) void k_spatial_reduce(Dev d, int axis, int sd
   double* Ds = Qs + 16 * LD;                               // then U and U_nbr rows on the face
   double* Uo = Ds + 16 * LD;
   double* Un = Uo + 16 * LDR;
-  const double* Qsd = Q + (int64_t)s * N * T;
+  const S* Qsd = (const S*)Q + (int64_t)s * N * T;
   const double* Us = d.U + (int64_t)s * N * R;
   const double* Unb = nbr >= 0 ? d.U + (int64_t)nbr * N * R : d.U;
   const int e = axis == 0 ? 1 : d.lnx;
@@ -524,8 +500,8 @@ __global__ __launch_bounds__(NTHR) void k_spatial_reduce(Dev d, int axis, int sd
     for (int ks = 0; ks < KS; ++ks) {
       const int c = 4 * ks + kq;
       const int64_t col = (int64_t)c * N;
-      x0[ks] = (rin && c < t) ? Qsd[col + p] : 0.0;
-      xn[ks] = (hn && c < t) ? Qsd[col + pn] : 0.0;
+      x0[ks] = (rin && c < t) ? (double)Qsd[col + p] : 0.0;
+      xn[ks] = (hn && c < t) ? (double)Qsd[col + pn] : 0.0;
     }
     const bool any_face = __any(face);
     if (any_face) {
@@ -608,8 +584,10 @@ __global__ __launch_bounds__(NTHR) void k_spatial_reduce(Dev d, int axis, int sd
 // with P0 = S2^T, Pm = -dt c Hm^T, Pp = -dt c Hp^T; each direction is
 // upwinded by the sign of its own Omega.  Leaves the partial Gram of AL.
 // ----------------------------------------------------------------------------
-template <int NCB, int KS>
+template <class S, int P, int NCB, int KS>
 __global__ __launch_bounds__(NTHR) void k_lstep(Dev d, int axis, int sd0, int kst) {
+  using F = typename Prec<P>::F;
+  using Acc = typename Prec<P>::Acc;
   constexpr int LD = strip_ld<NCB>();
   constexpr int NB = NCB * (NCB + 1) / 2;
   const int s = sd0 + blockIdx.y;
@@ -619,59 +597,52 @@ __global__ __launch_bounds__(NTHR) void k_lstep(Dev d, int axis, int sd0, int ks
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int l16 = lane & 15, kq = lane >> 4;
   extern __shared__ double lds[];
-  // fragments of P0, Pm, Pp: Pf[((m * kst + ks) * NCB + cb) * 64 + lane]
+  // fragments of P0, Pm, Pp: Pf[((m * kst + u) * NCB + cb) * 64 + lane]
   const int nfrag = 3 * kst * NCB * 64;
-  double* Pf = lds;
-  double* Ys = lds + nfrag + wave * 16 * LD;
+  F* Pf = reinterpret_cast<F*>(lds);
+  double* Ys = lds + frag_doubles<P>(nfrag) + wave * 16 * LD;
   {
     const double* sm = small_of(d, s);
     const int offs[3] = {d.oP0, d.oPm, d.oPp};
     for (int idx = threadIdx.x; idx < nfrag; idx += NTHR) {
-      const int l = idx & 63, f = idx >> 6, cb = f % NCB, ks = (f / NCB) % kst, m = f / (NCB * kst);
-      const int kc = 4 * ks + (l >> 4), col = 16 * cb + (l & 15);
-      Pf[idx] = (kc < t && col < t) ? sm[offs[m] + kc + col * T] : 0.0;
+      const int l = idx & 63, f = idx >> 6, cb = f % NCB, u = (f / NCB) % kst, m = f / (NCB * kst);
+      const int kc = sub_col<P>(u, l >> 4), col = 16 * cb + (l & 15);
+      Pf[idx] = (kc < t && col < t) ? (F)sm[offs[m] + kc + col * T] : (F)0;
     }
   }
   __syncthreads();
-  const double* Qsd = d.Qh + (int64_t)s * M * T;
-  double* ALs = d.AL + (int64_t)s * M * T;
+  const int bstride = kst * NCB * 64;
+  const S* Qsd = (const S*)d.Qh + (int64_t)s * M * T;
+  S* ALs = (S*)d.AL + (int64_t)s * M * T;
   dbl4 g[NB];
   zero_acc<NB>(g);
   const int nst = ceil_div(M, 16);
   for (int st = blockIdx.x * NW + wave; st < nst; st += gridDim.x * NW) {
     const int q = st * 16 + l16;
     const bool rin = q < M;
-    double xv[KS];
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      const int kc = 4 * ks + kq;
-      xv[ks] = (rin && ks < kst && kc < t) ? Qsd[(int64_t)kc * M + q] : 0.0;
-    }
     const double o = rin ? om[q] : 0.0;
-    const double op = o >= 0.0 ? o : 0.0, on = o < 0.0 ? o : 0.0;
-    dbl4 acc[NCB];
-    zero_acc<NCB>(acc);
+    const F op = (F)(o >= 0.0 ? o : 0.0), on = (F)(o < 0.0 ? o : 0.0);
+    F xv[KS], xm[KS], xp[KS];
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      if (ks < kst) {
-        const double xmv = xv[ks] * op, xpv = xv[ks] * on;
-#pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) {
-          const int b = (ks * NCB + cb) * 64 + lane;
-          acc[cb] = mfma64(Pf[b], xv[ks], acc[cb]);
-          acc[cb] = mfma64(Pf[b + kst * NCB * 64], xmv, acc[cb]);
-          acc[cb] = mfma64(Pf[b + 2 * kst * NCB * 64], xpv, acc[cb]);
-        }
-      }
+    for (int u = 0; u < KS; ++u) {
+      const int kc = sub_col<P>(u, kq);
+      xv[u] = (rin && u < kst && kc < t) ? (F)Qsd[(int64_t)kc * M + q] : (F)0;
+      xm[u] = xv[u] * op;
+      xp[u] = xv[u] * on;
     }
+    Acc acc[NCB];
+    zero_prod<P>(acc, NCB);
+    prod_acc<P, NCB, KS>(acc, Pf, xv, kst);
+    prod_acc<P, NCB, KS>(acc, Pf + bstride, xm, kst);
+    prod_acc<P, NCB, KS>(acc, Pf + 2 * bstride, xp, kst);
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int j = 16 * cb + 4 * v + kq;
-        const double val = rin ? acc[cb][v] : 0.0;
+        const int j = out_col<P>(cb, v, kq);
+        const S val = rin ? (S)acc[cb][v] : (S)0;
         if (rin && j < t) ALs[(int64_t)j * M + q] = val;
-        Ys[l16 * LD + j] = val;
+        Ys[l16 * LD + j] = (double)val;
       }
     }
     wave_sync();
@@ -688,10 +659,13 @@ __global__ __launch_bounds__(NTHR) void k_lstep(Dev d, int axis, int sd0, int ks
 // formed from one product U [S | S m], whose last column is K[p].m.  Leaves
 // the partial Gram of K1 (r columns).
 // ----------------------------------------------------------------------------
-template <int NCB>
+template <class S, int P, int NCB>
 __global__ __launch_bounds__(NTHR) void k_coll_kstep(Dev d, int sd0) {
+  using F = typename Prec<P>::F;
+  using Acc = typename Prec<P>::Acc;
   constexpr int LD = strip_ld<NCB>();
   constexpr int NB = NCB * (NCB + 1) / 2;
+  constexpr int KSP = P == 2 ? 8 : 6;  // sub-steps covering the largest stored rank
   const int s = sd0 + blockIdx.y;
   const int r = d.rank[s];
   const int N = d.N, R = d.R;
@@ -699,7 +673,7 @@ __global__ __launch_bounds__(NTHR) void k_coll_kstep(Dev d, int sd0) {
   const int l16 = lane & 15, kq = lane >> 4;
   __shared__ double Bs[CAPR * (CAPR + 1)];  // [S | S m], leading dimension CAPR
   __shared__ double mv[16 * NCB];
-  __shared__ double Bf[KSR * NCB * 64];
+  __shared__ F Bf[KSP * NCB * 64];
   __shared__ double Ysh[NW * 16 * LD];
   double* Ys = Ysh + wave * 16 * LD;
   const double* sm = small_of(d, s);
@@ -716,10 +690,10 @@ __global__ __launch_bounds__(NTHR) void k_coll_kstep(Dev d, int sd0) {
     Bs[a + r * CAPR] = acc;
   }
   __syncthreads();
-  for (int idx = threadIdx.x; idx < KSR * NCB * 64; idx += NTHR) {
-    const int l = idx & 63, f = idx >> 6, cb = f % NCB, ks = f / NCB;
-    const int kc = 4 * ks + (l >> 4), col = 16 * cb + (l & 15);
-    Bf[idx] = (kc < r && col <= r) ? Bs[kc + col * CAPR] : 0.0;
+  for (int idx = threadIdx.x; idx < KSP * NCB * 64; idx += NTHR) {
+    const int l = idx & 63, f = idx >> 6, cb = f % NCB, u = f / NCB;
+    const int kc = sub_col<P>(u, l >> 4), col = 16 * cb + (l & 15);
+    Bf[idx] = (kc < r && col <= r) ? (F)Bs[kc + col * CAPR] : (F)0;
   }
   __syncthreads();
 
@@ -727,38 +701,32 @@ __global__ __launch_bounds__(NTHR) void k_coll_kstep(Dev d, int sd0) {
   const double* cs = d.cs + (int64_t)s * N;
   const double* ct = d.ct + (int64_t)s * N;
   const double* Qs = d.Qsrc + (int64_t)s * N;
-  double* K1 = d.K1 + (int64_t)s * N * d.T;
+  S* K1 = (S*)d.K1 + (int64_t)s * N * d.T;
   const double dt = d.dt, iW = 1.0 / d.W;
-  const int ksr = ceil_div(r, 4);
-  const int src_lane = l16 + 16 * (r & 3);  // lane holding column r of this row
+  const int ksr = live_sub<P>(r);
+  const int src_lane = l16 + 16 * out_kq<P>(r);  // lane holding column r of this row
   dbl4 g[NB];
   zero_acc<NB>(g);
   const int nst = ceil_div(N, 16);
   for (int st = blockIdx.x * NW + wave; st < nst; st += gridDim.x * NW) {
     const int p = st * 16 + l16;
     const bool rin = p < N;
-    double xv[KSR];
+    F xv[KSP];
 #pragma unroll
-    for (int ks = 0; ks < KSR; ++ks) {
-      const int kc = 4 * ks + kq;
-      xv[ks] = (rin && kc < r) ? Us[(int64_t)kc * N + p] : 0.0;
+    for (int u = 0; u < KSP; ++u) {
+      const int kc = sub_col<P>(u, kq);
+      xv[u] = (rin && kc < r) ? (F)Us[(int64_t)kc * N + p] : (F)0;
     }
     const double ctp = rin ? ct[p] : 0.0, csp = rin ? cs[p] : 0.0, qp = rin ? Qs[p] : 0.0;
-    dbl4 acc[NCB];
-    zero_acc<NCB>(acc);
-#pragma unroll
-    for (int ks = 0; ks < KSR; ++ks) {
-      if (ks < ksr) {
-#pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) acc[cb] = mfma64(Bf[(ks * NCB + cb) * 64 + lane], xv[ks], acc[cb]);
-      }
-    }
+    Acc acc[NCB];
+    zero_prod<P>(acc, NCB);
+    prod_acc<P, NCB, KSP>(acc, Bf, xv, ksr);
     double kmv = 0.0;
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
       for (int v = 0; v < 4; ++v)
-        if (16 * cb + 4 * v + kq == r) kmv = acc[cb][v];
+        if (out_col<P>(cb, v, kq) == r) kmv = (double)acc[cb][v];
     const double km = __shfl(kmv, src_lane, 64);
     const double a0 = rin ? 1.0 - dt * ctp : 0.0;
     const double a1 = rin ? dt * (csp * iW * km + qp) : 0.0;
@@ -766,10 +734,10 @@ __global__ __launch_bounds__(NTHR) void k_coll_kstep(Dev d, int sd0) {
     for (int cb = 0; cb < NCB; ++cb) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int j = 16 * cb + 4 * v + kq;
-        const double val = (rin && j < r) ? fma(a0, acc[cb][v], a1 * mv[j]) : 0.0;
+        const int j = out_col<P>(cb, v, kq);
+        const S val = (rin && j < r) ? (S)fma(a0, (double)acc[cb][v], a1 * mv[j]) : (S)0;
         if (rin && j < r) K1[(int64_t)j * N + p] = val;
-        Ys[l16 * LD + j] = val;
+        Ys[l16 * LD + j] = (double)val;
       }
     }
     wave_sync();
@@ -869,60 +837,57 @@ __global__ __launch_bounds__(NTHR) void k_coll_reduce(Dev d, int sd0) {
 //   AL[q,:] = sqrt(w_q) (V[q,:] P + crow),  P = S2^T (I - dt Gt),
 //   crow = dt ((S2 m)^T Gs / W + q^T).  Leaves the partial Gram of AL.
 // ----------------------------------------------------------------------------
-template <int NCB>
+template <class S, int P, int NCB>
 __global__ __launch_bounds__(NTHR) void k_coll_lstep(Dev d, int sd0) {
+  using F = typename Prec<P>::F;
+  using Acc = typename Prec<P>::Acc;
   constexpr int LD = strip_ld<NCB>();
   constexpr int NB = NCB * (NCB + 1) / 2;
+  constexpr int KSP = P == 2 ? 8 : 6;
   const int s = sd0 + blockIdx.y;
   const int r = d.rank[s];
   const int M = d.M, R = d.R;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int l16 = lane & 15, kq = lane >> 4;
   __shared__ double cr[16 * NCB];
-  __shared__ double Bf[KSR * NCB * 64];
+  __shared__ F Bf[KSP * NCB * 64];
   __shared__ double Ysh[NW * 16 * LD];
   double* Ys = Ysh + wave * 16 * LD;
   const double* sm = small_of(d, s);
-  for (int idx = threadIdx.x; idx < KSR * NCB * 64; idx += NTHR) {
-    const int l = idx & 63, f = idx >> 6, cb = f % NCB, ks = f / NCB;
-    const int kc = 4 * ks + (l >> 4), col = 16 * cb + (l & 15);
-    Bf[idx] = (kc < r && col < r) ? sm[d.oP0 + kc + col * R] : 0.0;
+  for (int idx = threadIdx.x; idx < KSP * NCB * 64; idx += NTHR) {
+    const int l = idx & 63, f = idx >> 6, cb = f % NCB, u = f / NCB;
+    const int kc = sub_col<P>(u, l >> 4), col = 16 * cb + (l & 15);
+    Bf[idx] = (kc < r && col < r) ? (F)sm[d.oP0 + kc + col * R] : (F)0;
   }
   for (int a = threadIdx.x; a < 16 * NCB; a += NTHR) cr[a] = a < r ? sm[d.oCrow + a] : 0.0;
   __syncthreads();
   const double* Vs = d.V + (int64_t)s * M * R;
-  double* ALs = d.AL + (int64_t)s * M * d.T;
-  const int ksr = ceil_div(r, 4);
+  S* ALs = (S*)d.AL + (int64_t)s * M * d.T;
+  const int ksr = live_sub<P>(r);
   dbl4 g[NB];
   zero_acc<NB>(g);
   const int nst = ceil_div(M, 16);
   for (int st = blockIdx.x * NW + wave; st < nst; st += gridDim.x * NW) {
     const int q = st * 16 + l16;
     const bool rin = q < M;
-    double xv[KSR];
+    F xv[KSP];
 #pragma unroll
-    for (int ks = 0; ks < KSR; ++ks) {
-      const int kc = 4 * ks + kq;
-      xv[ks] = (rin && kc < r) ? Vs[(int64_t)kc * M + q] : 0.0;
+    for (int u = 0; u < KSP; ++u) {
+      const int kc = sub_col<P>(u, kq);
+      xv[u] = (rin && kc < r) ? (F)Vs[(int64_t)kc * M + q] : (F)0;
     }
     const double swq = rin ? d.sw[q] : 0.0;
-    dbl4 acc[NCB];
-    zero_acc<NCB>(acc);
-#pragma unroll
-    for (int ks = 0; ks < KSR; ++ks) {
-      if (ks < ksr) {
-#pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) acc[cb] = mfma64(Bf[(ks * NCB + cb) * 64 + lane], xv[ks], acc[cb]);
-      }
-    }
+    Acc acc[NCB];
+    zero_prod<P>(acc, NCB);
+    prod_acc<P, NCB, KSP>(acc, Bf, xv, ksr);
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int j = 16 * cb + 4 * v + kq;
-        const double val = (rin && j < r) ? swq * (acc[cb][v] + cr[j]) : 0.0;
+        const int j = out_col<P>(cb, v, kq);
+        const S val = (rin && j < r) ? (S)(swq * ((double)acc[cb][v] + cr[j])) : (S)0;
         if (rin && j < r) ALs[(int64_t)j * M + q] = val;
-        Ys[l16 * LD + j] = val;
+        Ys[l16 * LD + j] = (double)val;
       }
     }
     wave_sync();
@@ -974,18 +939,23 @@ __global__ __launch_bounds__(NTHR) void k_moments(Dev d) {
 }
 
 // ============================================================================
-// Host-side launchers: pick the template instance from the capacities.
+// Host-side launchers: pick the template instance from the precision mode and
+// the capacities.
 // ============================================================================
 namespace {
 
 template <int V>
 using ic = std::integral_constant<int, V>;
+template <class T>
+struct tag {
+  using type = T;
+};
 
 // column blocks of 16 covering a capacity of n columns (1..4)
 int ncb_of(int n) { return n <= 16 ? 1 : (n <= 32 ? 2 : (n <= 48 ? 3 : 4)); }
 
-template <class F>
-void with_ncb(int ncb, F f) {
+template <class Fn>
+void with_ncb(int ncb, Fn f) {
   switch (ncb) {
     case 1: f(ic<1>{}); break;
     case 2: f(ic<2>{}); break;
@@ -994,11 +964,31 @@ void with_ncb(int ncb, F f) {
   }
 }
 
-// k-steps of 4 in buckets of 16 columns (4, 8, 12, 16)
-template <class F>
-void with_ks(int kcap, F f) {
+// 4-column sub-steps in buckets of 16 columns (4, 8, 12, 16)
+template <class Fn>
+void with_ks(int kcap, Fn f) {
   with_ncb(ncb_of(kcap), [&](auto nk) { f(ic<4 * decltype(nk)::value>{}); });
 }
+
+// storage type and product precision of a launch: FP64 mode stores and
+// computes in FP64; the mixed modes store in FP32 and compute products in
+// FP32 or split BF16, except QR products (exact), which stay FP64
+template <class Fn>
+void with_prec(int prec, bool exact, Fn f) {
+  if (prec == DD_PREC_FP64) f(tag<double>{}, ic<0>{});
+  else if (exact) f(tag<float>{}, ic<0>{});
+  else if (prec == DD_PREC_MIXED_FP32) f(tag<float>{}, ic<1>{});
+  else f(tag<float>{}, ic<2>{});
+}
+
+template <class Fn>
+void with_store(int prec, Fn f) {
+  if (prec == DD_PREC_FP64) f(tag<double>{});
+  else f(tag<float>{});
+}
+
+// sub-steps of the coefficient fragments for a capacity of n rows
+int sub_steps(int P, int n) { return P == 2 ? 4 * ceil_div(n, 16) : ceil_div(n, 4); }
 
 constexpr size_t D8 = sizeof(double);
 
@@ -1007,90 +997,127 @@ void allow_lds(const void* fn) {
   (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 159 * 1024);
 }
 
+template <int P, int NC>
+size_t strip_bytes(size_t frag_values) {
+  return D8 * std::max<size_t>(frag_doubles<P>(frag_values) + NW * 16 * strip_ld<NC>(), (size_t)NC * (NC + 1) / 2 * 256);
+}
+
 }  // namespace
 
+// the augmentation matrix is the input of the FP64 SVD: FP64 in every mode
 void launch_aug_form(const Dev& d, int axis, int sd0, int nsd, hipStream_t st) {
-  const int nc = ncb_of(d.MA);
-  with_ncb(nc, [&](auto c) {
+  with_ncb(ncb_of(d.MA), [&](auto c) {
     constexpr int NC = decltype(c)::value;
     constexpr int KS = 4 * NC;
-    const size_t lds = D8 * std::max<size_t>(KS * NC * 64 + NW * 16 * strip_ld<NC>(), (size_t)NC * (NC + 1) / 2 * 256);
-    hipLaunchKernelGGL((k_aug_form<NC, KS>), dim3(d.nwgM, nsd), dim3(NTHR), lds, st, d, axis, sd0);
+    const size_t lds = strip_bytes<0, NC>(KS * NC * 64);
+    hipLaunchKernelGGL((k_aug_form<double, 0, NC, KS>), dim3(d.nwgM, nsd), dim3(NTHR), lds, st, d, axis, sd0);
   });
 }
 
 static int dim_cap(const Dev& d, int which) { return which == DIM_M0 ? d.MA : (which == DIM_T ? d.T : d.R); }
 
-void launch_gemm(const Dev& d, int axis, int sd0, int nsd, const double* X, int64_t xsd, int rows, int kdim,
-                 int ndim, int boff, int bld, double* Y, int64_t ysd, const double* rowscale, bool gram,
-                 int fill_off, bool rows_are_cells, hipStream_t st) {
+void launch_gemm(const Dev& d, int axis, int sd0, int nsd, const void* X, bool x64, int64_t xsd, int rows, int kdim,
+                 int ndim, int boff, int bld, void* Y, bool y64, int64_t ysd, const double* rowscale, bool gram,
+                 int fill_off, bool rows_are_cells, bool exact, hipStream_t st) {
   const int nwg = rows_are_cells ? d.nwgN : d.nwgM;
-  with_ncb(ncb_of(dim_cap(d, ndim)), [&](auto c) {
-    constexpr int NC = decltype(c)::value;
-    with_ks(dim_cap(d, kdim), [&](auto k) {
-      constexpr int KS = decltype(k)::value;
-      const size_t lds =
-          D8 * std::max<size_t>(KS * NC * 64 + NW * 16 * strip_ld<NC>(), (size_t)NC * (NC + 1) / 2 * 256);
-      hipLaunchKernelGGL((k_gemm<NC, KS>), dim3(nwg, nsd), dim3(NTHR), lds, st, d, axis, sd0, X, xsd, rows, kdim,
-                         ndim, boff, bld, Y, ysd, rowscale, gram ? 1 : 0, fill_off);
+  auto go = [&](auto ti, auto to, auto pc) {
+    using SI = typename decltype(ti)::type;
+    using SO = typename decltype(to)::type;
+    constexpr int P = decltype(pc)::value;
+    with_ncb(ncb_of(dim_cap(d, ndim)), [&](auto c) {
+      constexpr int NC = decltype(c)::value;
+      with_ks(dim_cap(d, kdim), [&](auto k) {
+        constexpr int KS = decltype(k)::value;
+        const size_t lds = strip_bytes<P, NC>(KS * NC * 64);
+        hipLaunchKernelGGL((k_gemm<SI, SO, P, NC, KS>), dim3(nwg, nsd), dim3(NTHR), lds, st, d, axis, sd0, X, xsd,
+                           rows, kdim, ndim, boff, bld, Y, ysd, rowscale, gram ? 1 : 0, fill_off);
+      });
     });
+  };
+  // FP64 mode: everything FP64.  Mixed modes: the working arrays are FP32;
+  // the state and the augmentation matrix stay FP64.
+  with_prec(d.prec, exact, [&](auto ts, auto pc) {
+    using W = typename decltype(ts)::type;
+    if (x64 && y64) go(tag<double>{}, tag<double>{}, pc);
+    else if (x64) go(tag<double>{}, tag<W>{}, pc);
+    else if (y64) go(tag<W>{}, tag<double>{}, pc);
+    else go(tag<W>{}, tag<W>{}, pc);
   });
 }
 
 void launch_ang_reduce(const Dev& d, int axis, int sd0, int nsd, hipStream_t st) {
-  with_ncb(ncb_of(d.T), [&](auto ct) {
-    constexpr int NT = decltype(ct)::value;
-    with_ncb(ncb_of(d.R), [&](auto cr) {
-      constexpr int NR = decltype(cr)::value;
-      constexpr int NACC = std::max(3 * NR * NT, 3 * NT * (NT + 1) / 2);
-      const size_t lds = D8 * std::max<size_t>(NW * (16 * (16 * (NT + 3 * NR) + 1) + 16), (size_t)2 * NACC * 256);
-      if constexpr (NR <= 2)  // stored ranks are at most 21
-        hipLaunchKernelGGL((k_ang_reduce<NT, NR>), dim3(d.nwgM, nsd), dim3(NTHR), lds, st, d, axis, sd0);
+  with_store(d.prec, [&](auto ts) {
+    using S = typename decltype(ts)::type;
+    with_ncb(ncb_of(d.T), [&](auto ct) {
+      constexpr int NT = decltype(ct)::value;
+      with_ncb(ncb_of(d.R), [&](auto cr) {
+        constexpr int NR = decltype(cr)::value;
+        constexpr int NACC = std::max(3 * NR * NT, 3 * NT * (NT + 1) / 2);
+        const size_t lds = D8 * std::max<size_t>(NW * (16 * (16 * (NT + 3 * NR) + 1) + 16), (size_t)2 * NACC * 256);
+        if constexpr (NR <= 2)  // stored ranks are at most 21
+          hipLaunchKernelGGL((k_ang_reduce<S, NT, NR>), dim3(d.nwgM, nsd), dim3(NTHR), lds, st, d, axis, sd0);
+      });
     });
   });
 }
 
 void launch_kstep(const Dev& d, int axis, int sd0, int nsd, hipStream_t st) {
-  const int ksr = ceil_div(d.R, 4);
-  with_ncb(ncb_of(d.T), [&](auto c) {
-    constexpr int NC = decltype(c)::value;
-    const size_t lds =
-        D8 * std::max<size_t>(7 * ksr * NC * 64 + NW * 16 * strip_ld<NC>(), (size_t)NC * (NC + 1) / 2 * 256);
-    hipLaunchKernelGGL((k_kstep<NC>), dim3(d.nwgN, nsd), dim3(NTHR), lds, st, d, axis, sd0, ksr);
+  with_prec(d.prec, false, [&](auto ts, auto pc) {
+    using S = typename decltype(ts)::type;
+    constexpr int P = decltype(pc)::value;
+    const int ksr = sub_steps(P, d.R);
+    with_ncb(ncb_of(d.T), [&](auto c) {
+      constexpr int NC = decltype(c)::value;
+      const size_t lds = strip_bytes<P, NC>(7 * ksr * NC * 64);
+      hipLaunchKernelGGL((k_kstep<S, P, NC>), dim3(d.nwgN, nsd), dim3(NTHR), lds,
+                         st, d, axis, sd0, ksr);
+    });
   });
 }
 
-void launch_spatial_reduce(const Dev& d, int axis, int sd0, int nsd, const double* Q, hipStream_t st) {
-  with_ncb(ncb_of(d.T), [&](auto ct) {
-    constexpr int NT = decltype(ct)::value;
-    with_ncb(ncb_of(d.R), [&](auto cr) {
-      constexpr int NR = decltype(cr)::value;
-      constexpr int NACC = NT * NT + 2 * NT * NR;
-      const size_t lds =
-          D8 * std::max<size_t>(NW * 2 * 16 * (strip_ld<NT>() + strip_ld<NR>()), (size_t)2 * NACC * 256);
-      if constexpr (NR <= 2)  // stored ranks are at most 21
-        hipLaunchKernelGGL((k_spatial_reduce<NT, NR>), dim3(d.nwgN, nsd), dim3(NTHR), lds, st, d, axis, sd0, Q);
+void launch_spatial_reduce(const Dev& d, int axis, int sd0, int nsd, const void* Q, hipStream_t st) {
+  with_store(d.prec, [&](auto ts) {
+    using S = typename decltype(ts)::type;
+    with_ncb(ncb_of(d.T), [&](auto ct) {
+      constexpr int NT = decltype(ct)::value;
+      with_ncb(ncb_of(d.R), [&](auto cr) {
+        constexpr int NR = decltype(cr)::value;
+        constexpr int NACC = NT * NT + 2 * NT * NR;
+        const size_t lds =
+            D8 * std::max<size_t>(NW * 2 * 16 * (strip_ld<NT>() + strip_ld<NR>()), (size_t)2 * NACC * 256);
+        if constexpr (NR <= 2)  // stored ranks are at most 21
+          hipLaunchKernelGGL((k_spatial_reduce<S, NT, NR>), dim3(d.nwgN, nsd), dim3(NTHR), lds, st, d, axis, sd0,
+                             Q);
+      });
     });
   });
 }
 
 void launch_lstep(const Dev& d, int axis, int sd0, int nsd, hipStream_t st) {
-  const int kst = ceil_div(d.T, 4);
-  with_ncb(ncb_of(d.T), [&](auto c) {
-    constexpr int NC = decltype(c)::value;
-    constexpr int KS = 4 * NC;
-    const size_t lds =
-        D8 * std::max<size_t>(3 * kst * NC * 64 + NW * 16 * strip_ld<NC>(), (size_t)NC * (NC + 1) / 2 * 256);
-    hipLaunchKernelGGL((k_lstep<NC, KS>), dim3(d.nwgM, nsd), dim3(NTHR), lds, st, d, axis, sd0, kst);
+  with_prec(d.prec, false, [&](auto ts, auto pc) {
+    using S = typename decltype(ts)::type;
+    constexpr int P = decltype(pc)::value;
+    const int kst = sub_steps(P, d.T);
+    with_ncb(ncb_of(d.T), [&](auto c) {
+      constexpr int NC = decltype(c)::value;
+      constexpr int KS = 4 * NC;
+      const size_t lds = strip_bytes<P, NC>(3 * kst * NC * 64);
+      hipLaunchKernelGGL((k_lstep<S, P, NC, KS>), dim3(d.nwgM, nsd), dim3(NTHR), lds,
+                         st, d, axis, sd0, kst);
+    });
   });
 }
 
 void launch_coll_kstep(const Dev& d, int sd0, int nsd, hipStream_t st) {
-  // one column beyond the rank carries K.m
-  with_ncb(ncb_of(d.R + 1), [&](auto c) {
-    constexpr int NC = decltype(c)::value;
-    if constexpr (NC <= 2)
-      hipLaunchKernelGGL((k_coll_kstep<NC>), dim3(d.nwgN, nsd), dim3(NTHR), 0, st, d, sd0);
+  with_prec(d.prec, false, [&](auto ts, auto pc) {
+    using S = typename decltype(ts)::type;
+    constexpr int P = decltype(pc)::value;
+    // one column beyond the rank carries K.m
+    with_ncb(ncb_of(d.R + 1), [&](auto c) {
+      constexpr int NC = decltype(c)::value;
+      if constexpr (NC <= 2)
+        hipLaunchKernelGGL((k_coll_kstep<S, P, NC>), dim3(d.nwgN, nsd), dim3(NTHR), 0, st, d, sd0);
+    });
   });
 }
 
@@ -1103,10 +1130,14 @@ void launch_coll_reduce(const Dev& d, int sd0, int nsd, hipStream_t st) {
 }
 
 void launch_coll_lstep(const Dev& d, int sd0, int nsd, hipStream_t st) {
-  with_ncb(ncb_of(d.R), [&](auto c) {
-    constexpr int NC = decltype(c)::value;
-    if constexpr (NC <= 2)
-      hipLaunchKernelGGL((k_coll_lstep<NC>), dim3(d.nwgM, nsd), dim3(NTHR), 0, st, d, sd0);
+  with_prec(d.prec, false, [&](auto ts, auto pc) {
+    using S = typename decltype(ts)::type;
+    constexpr int P = decltype(pc)::value;
+    with_ncb(ncb_of(d.R), [&](auto c) {
+      constexpr int NC = decltype(c)::value;
+      if constexpr (NC <= 2)
+        hipLaunchKernelGGL((k_coll_lstep<S, P, NC>), dim3(d.nwgM, nsd), dim3(NTHR), 0, st, d, sd0);
+    });
   });
 }
 
@@ -1117,28 +1148,39 @@ void launch_moments(const Dev& d, hipStream_t st) {
 
 // Allow the dynamically sized kernels the whole LDS of a compute unit.
 void init_kernels() {
-  for (int nc = 1; nc <= 4; ++nc) {
-    with_ncb(nc, [&](auto c) {
-      constexpr int NC = decltype(c)::value;
-      allow_lds((const void*)k_aug_form<NC, 4 * NC>);
-      allow_lds((const void*)k_kstep<NC>);
-      allow_lds((const void*)k_lstep<NC, 4 * NC>);
-      for (int kc = 1; kc <= 4; ++kc) {
-        with_ncb(kc, [&](auto k) {
-          constexpr int KS = 4 * decltype(k)::value;
-          allow_lds((const void*)k_gemm<NC, KS>);
-        });
-      }
-      for (int nr = 1; nr <= 2; ++nr) {
-        with_ncb(nr, [&](auto r) {
-          constexpr int NR = decltype(r)::value;
-          if constexpr (NR <= 2) {
-            allow_lds((const void*)k_ang_reduce<NC, NR>);
-            allow_lds((const void*)k_spatial_reduce<NC, NR>);
-          }
-        });
-      }
-    });
+  for (int prec = 0; prec < 3; ++prec) {
+    for (int exact = 0; exact < 2; ++exact) {
+      with_prec(prec, exact != 0, [&](auto ts, auto pc) {
+        using W = typename decltype(ts)::type;
+        constexpr int P = decltype(pc)::value;
+        for (int nc = 1; nc <= 4; ++nc) {
+          with_ncb(nc, [&](auto c) {
+            constexpr int NC = decltype(c)::value;
+            allow_lds((const void*)k_aug_form<double, 0, NC, 4 * NC>);
+            allow_lds((const void*)k_kstep<W, P, NC>);
+            allow_lds((const void*)k_lstep<W, P, NC, 4 * NC>);
+            for (int kc = 1; kc <= 4; ++kc) {
+              with_ncb(kc, [&](auto k) {
+                constexpr int KS = 4 * decltype(k)::value;
+                allow_lds((const void*)k_gemm<double, double, P, NC, KS>);
+                allow_lds((const void*)k_gemm<double, W, P, NC, KS>);
+                allow_lds((const void*)k_gemm<W, double, P, NC, KS>);
+                allow_lds((const void*)k_gemm<W, W, P, NC, KS>);
+              });
+            }
+            for (int nr = 1; nr <= 2; ++nr) {
+              with_ncb(nr, [&](auto r) {
+                constexpr int NR = decltype(r)::value;
+                if constexpr (NR <= 2) {
+                  allow_lds((const void*)k_ang_reduce<W, NC, NR>);
+                  allow_lds((const void*)k_spatial_reduce<W, NC, NR>);
+                }
+              });
+            }
+          });
+        }
+      });
+    }
   }
   // an attribute the runtime refused would otherwise surface at the first
   // launch check; a kernel that then lacks LDS fails its own launch instead

@@ -38,6 +38,119 @@ __device__ inline void zero_acc(dbl4* a) {
   for (int i = 0; i < NA; ++i) a[i] = zero4();
 }
 
+// ---------------------------------------------------------------------------
+// Precision of the tall-skinny products.  P = 0: FP64 (v_mfma_f64_16x16x4f64);
+// P = 1: FP32 operands, FP32 accumulation (v_mfma_f32_16x16x4f32); P = 2:
+// split BF16, x = hi + lo with hi = bf16(x), lo = bf16(x - hi), and
+// a b ~ hi_a hi_b + hi_a lo_b + lo_a hi_b accumulated in FP32
+// (v_mfma_f32_16x16x16bf16_1k, three per product).  The FP32-accumulating
+// instructions hold D[4 (l/16) + v][l % 16] in component v of lane l (the
+// FP64 one D[4 v + l/16][l % 16]).
+// Operands are handled in 4-column sub-steps u: lane (l16 = l % 16,
+// kq = l / 16) holds column sub_col(u, kq) of its row; for P = 2 four
+// consecutive sub-steps form one 16-column instruction whose lane operand is
+// columns 16 g + 4 kq + 0..3.
+// ---------------------------------------------------------------------------
+typedef float flt4 __attribute__((ext_vector_type(4)));
+typedef short shrt4 __attribute__((ext_vector_type(4)));
+
+template <int P> struct Prec;
+template <> struct Prec<0> { using F = double; using Acc = dbl4; };
+template <> struct Prec<1> { using F = float; using Acc = flt4; };
+template <> struct Prec<2> { using F = float; using Acc = flt4; };
+
+template <int P>
+__device__ __forceinline__ int sub_col(int u, int kq) {
+  return P == 2 ? 16 * (u >> 2) + 4 * kq + (u & 3) : 4 * u + kq;
+}
+
+// column of the product held in component v of column block cb
+template <int P>
+__device__ __forceinline__ int out_col(int cb, int v, int kq) {
+  return P == 0 ? 16 * cb + 4 * v + kq : 16 * cb + 4 * kq + v;
+}
+
+// lane group (l / 16) that holds product column c
+template <int P>
+__device__ __forceinline__ int out_kq(int c) {
+  return P == 0 ? (c & 3) : ((c & 15) >> 2);
+}
+
+// sub-steps actually executed for k live columns (whole instructions)
+template <int P>
+__device__ __forceinline__ int live_sub(int k) {
+  return P == 2 ? 4 * ((k + 15) / 16) : (k + 3) / 4;
+}
+
+template <int P>
+__device__ __forceinline__ void zero_prod(typename Prec<P>::Acc* a, int n) {
+  for (int i = 0; i < n; ++i) a[i] = typename Prec<P>::Acc{0, 0, 0, 0};
+}
+
+__device__ __forceinline__ void bf16_split(float x, short& hi, short& lo) {
+  const __bf16 h = (__bf16)x;
+  const __bf16 l = (__bf16)(x - (float)h);
+  hi = __builtin_bit_cast(short, h);
+  lo = __builtin_bit_cast(short, l);
+}
+
+// acc[cb] += sum over sub-steps u < nlive of (fragment u, block cb) x xv[u].
+// frag[(u * NCB + cb) * 64 + lane] is the coefficient operand B[sub_col(u,
+// kq)][16 cb + l16]; xv[u] the row's value in column sub_col(u, kq).
+template <int P, int NCB, int NSUB>
+__device__ __forceinline__ void prod_acc(typename Prec<P>::Acc* acc, const typename Prec<P>::F* frag,
+                                         const typename Prec<P>::F* xv, int nlive) {
+  const int lane = threadIdx.x & 63;
+  if constexpr (P == 2) {
+#pragma unroll
+    for (int g = 0; g < NSUB / 4; ++g) {
+      if (4 * g < nlive) {
+        shrt4 xh, xl;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          short h, l;
+          bf16_split(xv[4 * g + i], h, l);
+          xh[i] = h;
+          xl[i] = l;
+        }
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+          shrt4 ah, al;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            short h, l;
+            bf16_split(frag[((4 * g + i) * NCB + cb) * 64 + lane], h, l);
+            ah[i] = h;
+            al[i] = l;
+          }
+          acc[cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, xh, acc[cb], 0, 0, 0);
+          acc[cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, xl, acc[cb], 0, 0, 0);
+          acc[cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, xh, acc[cb], 0, 0, 0);
+        }
+      }
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < NSUB; ++u) {
+      if (u < nlive) {
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+          if constexpr (P == 0)
+            acc[cb] = mfma64(frag[(u * NCB + cb) * 64 + lane], xv[u], acc[cb]);
+          else
+            acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(frag[(u * NCB + cb) * 64 + lane], xv[u], acc[cb], 0, 0, 0);
+        }
+      }
+    }
+  }
+}
+
+// doubles of LDS taken by n fragment values of precision P
+template <int P>
+constexpr size_t frag_doubles(size_t n) {
+  return P == 0 ? n : (n + 1) / 2;
+}
+
 // leading dimension (doubles) of a row-major LDS strip with NCB column blocks
 template <int NCB>
 constexpr int strip_ld() { return 16 * NCB + 1; }

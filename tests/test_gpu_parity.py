@@ -16,6 +16,7 @@ from oracle import ddlra as dd
 pytestmark = pytest.mark.gpu
 
 STRICT = 1e-10
+MIXED = 1e-4  # scalar-flux bar of the mixed-precision modes
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -354,3 +355,80 @@ def test_raw_workloads_within_oracle_spread(name, nsteps):
     err = rho_err(rho, dd.moments(ref, prob))
     say(f"  {name}: gpu-vs-oracle {err:.3e}, oracle spread {spread:.3e}")
     assert err <= max(STRICT, 20.0 * spread)
+
+
+# ----------------------------------------------------------------------------
+# mixed precision: FP32 storage, FP32 or split-BF16 products, FP64 QR,
+# S-step and SVD; scalar flux against the FP64 oracle
+# ----------------------------------------------------------------------------
+
+_ORACLE_CACHE = {}
+
+
+def _oracle_cached(name, nsteps):
+    key = (name, nsteps)
+    if key not in _ORACLE_CACHE:
+        wl = wk.make_workload(name)
+        ref, prob = oracle_steps(wl, nsteps)
+        _ORACLE_CACHE[key] = (wl, dd.moments(ref, prob))
+    return _ORACLE_CACHE[key]
+
+
+def _mixed_run(wl, nsteps, prec):
+    import paper_2602_14854_amd as pkg
+    mode = {"fp32": pkg.DD_PREC_MIXED_FP32, "bf16": pkg.DD_PREC_MIXED_BF16}[prec]
+    e = engine(wl, precision=mode)
+    e.step(nsteps)
+    rho = e.moments()
+    e.close()
+    assert np.all(np.isfinite(rho))
+    return rho
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("name,nsteps", [("wc-C1", 3), ("wc-C2", 2)])
+def test_mixed_precision_scalar_flux(name, nsteps, prec):
+    wl, rho_ref = _oracle_cached(name, nsteps)
+    say(f"case: {name}, {nsteps} steps, mixed {prec}")
+    err = rho_err(_mixed_run(wl, nsteps, prec), rho_ref)
+    say(f"  {name} mixed {prec}: scalar-flux err {err:.3e}")
+    assert err < MIXED
+
+
+def _fp32_sensitivity(wl, nsteps, rho_ref):
+    """Scalar-flux distance between the FP64 oracle and the same oracle with
+    the arrays that the mixed modes keep in FP32 rounded to FP32: the K- and
+    L-step results before every QR, and V-hat.  It is the size of change
+    that FP32 storage of the working arrays alone causes."""
+    f_sp, f_ang, f_aug = dd.qr_spatial, dd.qr_angular, dd.augment
+    f32 = lambda x: x.astype(np.float32).astype(np.float64)
+
+    def aug(*a, **k):
+        K, Vh, t, sig, cl = f_aug(*a, **k)
+        return K, f32(Vh), t, sig, cl
+
+    try:
+        dd.qr_spatial = lambda K, prob: f_sp(f32(K), prob)
+        dd.qr_angular = lambda L, prob: f_ang(f32(L), prob)
+        dd.augment = aug
+        st, prob = oracle_steps(wl, nsteps)
+    finally:
+        dd.qr_spatial, dd.qr_angular, dd.augment = f_sp, f_ang, f_aug
+    return rho_err(dd.moments(st, prob), rho_ref)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("name,nsteps", [("C1", 10), ("C2", 2)])
+def test_mixed_precision_raw_within_fp32_sensitivity(name, nsteps, prec):
+    """The raw workloads carry singular values ~1e-8 (C1) of the largest, so
+    the QR of K1 amplifies any FP32 rounding by that condition number; the
+    bar is the oracle's own change under FP32 rounding of K1 and L1."""
+    wl, rho_ref = _oracle_cached(name, nsteps)
+    key = (name, nsteps, "fp32sens")
+    if key not in _ORACLE_CACHE:
+        _ORACLE_CACHE[key] = _fp32_sensitivity(wl, nsteps, rho_ref)
+    sens = _ORACLE_CACHE[key]
+    say(f"case: raw {name}, {nsteps} steps, mixed {prec}")
+    err = rho_err(_mixed_run(wl, nsteps, prec), rho_ref)
+    say(f"  {name} mixed {prec}: scalar-flux err {err:.3e}, oracle FP32 sensitivity {sens:.3e}")
+    assert err <= max(MIXED, 10.0 * sens)
