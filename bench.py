@@ -23,7 +23,10 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-FP64_PEAK_TFLOPS = 78.6
+# dense matrix-core peaks (TFLOP/s) of the products in each precision mode:
+# FP64 MFMA, FP32 MFMA, and BF16 MFMA for the split-BF16 mode (whose three
+# products per multiply are counted once, as algorithmic flops)
+MFMA_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
 
 WORKLOAD_NAMES = {
     "C1": "gaussian 32x32 cells, 2x2 subdomains, 64 directions, rank 5",
@@ -32,10 +35,13 @@ WORKLOAD_NAMES = {
 }
 
 
-def algorithmic_cost(wl, tmax):
+def algorithmic_cost(wl, tmax, work_bytes=8.0):
     """Algorithmic HBM bytes and flops per launch of each kernel kind for one
-    step (FP64: 8 bytes per element), from the shapes the step must touch.
-    t_s (intermediate rank) is taken as tmax[s]; r_s the stored rank."""
+    step, from the shapes the step must touch.  The stored factors U, V and
+    the augmentation matrix are FP64 (8 bytes per element); the K-, L-step
+    and V-hat working arrays take work_bytes per element (8 in FP64 mode, 4
+    in the mixed modes).  t_s (intermediate rank) is taken as tmax[s]; r_s
+    the stored rank."""
     import numpy as np
     N, M, ns = wl.N, wl.M, wl.n_sub
     r = np.asarray(wl.ranks(), float)
@@ -55,24 +61,58 @@ def algorithmic_cost(wl, tmax):
         return np.asarray(out)
 
     m = (m0(0) + m0(1)) / 2.0
-    B = 8.0
+    B, W = 8.0, float(work_bytes)
     cost = {}
     # per advection stage, summed over subdomains; 2 stages per step -> 2 launches
-    cost["k_kstep"] = (B * N * np.sum(r + t), 2.0 * N * np.sum(3 * r * t + t * (t + 1) / 2), 2)
-    cost["k_spatial_reduce"] = (B * N * np.sum(t), 4.0 * N * np.sum(t * t), 2)
+    cost["k_kstep"] = (N * np.sum(B * r + W * t), 2.0 * N * np.sum(3 * r * t + t * (t + 1) / 2), 2)
+    cost["k_spatial_reduce"] = (W * N * np.sum(t), 4.0 * N * np.sum(t * t), 2)
     cost["k_aug_form"] = (B * M * np.sum(2 * m), 2.0 * M * np.sum(m * m), 2)
-    cost["k_ang_reduce"] = (B * M * np.sum(t + m), 2.0 * M * np.sum(r * t + 3 * t * t + (m - r) * t), 2)
-    cost["k_lstep"] = (B * M * np.sum(2 * t), 2.0 * M * np.sum(2 * t * t), 2)
-    # the three QR products of K1 per advection stage (t columns) and of the
-    # collision stage (r columns): 9 launches per step
-    cost["k_gemm[QR K1]"] = (B * N * (6 * np.sum(2 * t) + 3 * np.sum(2 * r)) / 9.0,
-                             2.0 * N * (6 * np.sum(t * t) + 3 * np.sum(r * r)) / 9.0, 9)
-    cost["k_gemm[QR L1]"] = (B * M * (6 * np.sum(2 * t) + 3 * np.sum(2 * r)) / 9.0,
-                             2.0 * M * (6 * np.sum(t * t) + 3 * np.sum(r * r)) / 9.0, 9)
-    cost["k_coll_kstep"] = (B * N * np.sum(2 * r + 3), 2.0 * N * np.sum(r * r + 4 * r), 1)
+    cost["k_ang_reduce"] = (M * np.sum(W * t + B * m), 2.0 * M * np.sum(r * t + 3 * t * t + (m - r) * t), 2)
+    cost["k_lstep"] = (W * M * np.sum(2 * t), 2.0 * M * np.sum(2 * t * t), 2)
+    # the three Cholesky-QR products of K1 and of L1 per advection stage (t
+    # columns; 6 launches per step), and of the collision stage (r columns;
+    # its last product writes the FP64 state)
+    cost["k_gemm[QR K1]"] = (W * N * np.sum(2 * t), 2.0 * N * np.sum(t * t), 6)
+    cost["k_gemm[QR L1]"] = (W * M * np.sum(2 * t), 2.0 * M * np.sum(t * t), 6)
+    cost["k_gemm[QR K1 collision]"] = (N * np.sum((5 * W + B) * r) / 3.0, 2.0 * N * np.sum(r * r), 3)
+    cost["k_gemm[QR L1 collision]"] = (M * np.sum((5 * W + B) * r) / 3.0, 2.0 * M * np.sum(r * r), 3)
+    cost["k_coll_kstep"] = (N * np.sum(B * (r + 3) + W * r), 2.0 * N * np.sum(r * r + 4 * r), 1)
     cost["k_coll_reduce"] = (B * N * np.sum(r + 3), 2.0 * N * np.sum(2 * r * r + r), 1)
-    cost["k_gemm[U=Q*Bu]"] = (B * N * np.sum(t + r), 2.0 * N * np.sum(t * r), 2)
+    cost["k_gemm[U=Q*Bu]"] = (N * np.sum(W * t + B * r), 2.0 * N * np.sum(t * r), 2)
     return cost
+
+
+TS_SOURCES = ("paper_2602_14854_amd/csrc/dd_kernels_ts.hip", "paper_2602_14854_amd/csrc/dd_mfma.h")
+
+
+def ts_source_hash():
+    """Short hash of the tall-skinny kernel sources: traffic measured with
+    hardware counters stays valid only while these are unchanged."""
+    import hashlib
+    h = hashlib.sha256()
+    for rel in TS_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload, precision):
+    """HBM bytes per launch of `kernel` from the counter summaries committed
+    under profiles/ (lines 'traffic kernel=.. workload=.. precision=..
+    bytes_per_launch=.. source=..'), or None when there is none for the
+    current kernel sources."""
+    import glob
+    import re
+    src = ts_source_hash()
+    pat = re.compile(r"\s*traffic kernel=(.+?) workload=(\S+) precision=(\S+) bytes_per_launch=(\S+) source=(\S+)")
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        with open(path) as f:
+            for line in f:
+                m = pat.match(line)
+                if m and m.group(1) == kernel and m.group(2) == workload and m.group(3) == precision \
+                        and m.group(5) == src:
+                    return float(m.group(4))
+    return None
 
 
 def cpu_baseline(wl, budget_s=12.0, max_steps=30):
@@ -109,7 +149,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", default="C2")
     ap.add_argument("--mode", default="graph", choices=["graph", "batched", "per-subdomain"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"])
     ap.add_argument("--profile-steps", type=int, default=3)
+    ap.add_argument("--profile-repeat", type=int, default=10,
+                    help="back-to-back launches per timed tall-skinny phase")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -128,10 +171,11 @@ def main():
     wl = wk.make_workload(args.config)
     mode = {"graph": pkg.DD_EXEC_BATCHED_GRAPH, "batched": pkg.DD_EXEC_BATCHED,
             "per-subdomain": pkg.DD_EXEC_PER_SUBDOMAIN}[args.mode]
+    prec = {"fp64": pkg.DD_PREC_FP64, "fp32": pkg.DD_PREC_MIXED_FP32, "bf16": pkg.DD_PREC_MIXED_BF16}[args.precision]
     stream = torch.cuda.Stream()
-    eng = pkg.DDDLRA(wl, exec_mode=mode, stream=stream)
+    eng = pkg.DDDLRA(wl, exec_mode=mode, precision=prec, stream=stream)
     print(f"[bench] workload {args.config}: {wl.nx}x{wl.ny} cells, {wl.px}x{wl.py} subdomains, "
-          f"M={wl.M}, rank {wl.r_fixed}, mode {args.mode}", file=sys.stderr, flush=True)
+          f"M={wl.M}, rank {wl.r_fixed}, mode {args.mode}, precision {args.precision}", file=sys.stderr, flush=True)
     eng.step(args.warmup)
     eng.sync()
     r0, _, _ = eng.ranks()
@@ -154,7 +198,7 @@ def main():
 
     # per-kernel timing: the same kernels, launched phase by phase with
     # hipEvent pairs on the engine's stream
-    eng.profile(True)
+    eng.profile(max(1, args.profile_repeat))
     for _ in range(args.profile_steps):
         for st in (0, 1, 2):
             eng.stage(st)
@@ -164,7 +208,7 @@ def main():
     prof_total = sum(ms for _, ms in stats.values())
     kern = {k: {"launches": n, "avg_us": 1e3 * ms / max(n, 1), "share": ms / prof_total}
             for k, (n, ms) in stats.items() if n > 0}
-    costs = algorithmic_cost(wl, tmax)
+    costs = algorithmic_cost(wl, tmax, 8.0 if args.precision == "fp64" else 4.0)
     ts = {k: v for k, v in kern.items() if k in costs}
     dom = max(ts, key=lambda k: ts[k]["share"])
     nbytes, nflops, _ = costs[dom]
@@ -172,16 +216,18 @@ def main():
     gbs = nbytes / avg_s / 1e9
     tfl = nflops / avg_s / 1e12
     intensity = nflops / nbytes
-    bound = "hbm" if intensity < FP64_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9) else "alu"
+    peak_tf = MFMA_PEAK_TFLOPS[args.precision]
+    bound = "hbm" if intensity < peak_tf * 1e12 / (HBM_PEAK_GBS * 1e9) else "mfma"
     if bound == "hbm":
         roof = {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(gbs / HBM_PEAK_GBS, 4)}
     else:
-        roof = {"bound": "alu", "achieved": round(tfl, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(tfl / FP64_PEAK_TFLOPS, 4)}
+        roof = {"bound": "mfma", "achieved": round(tfl, 3), "peak": peak_tf, "unit": "TFLOP/s",
+                "frac": round(tfl / peak_tf, 4)}
+    traffic = measured_traffic(dom, args.config, args.precision)
     roof.update({"kernel": dom, "avg_us": round(ts[dom]["avg_us"], 3),
                  "algorithmic_bytes_per_launch": int(nbytes), "algorithmic_flops_per_launch": int(nflops),
-                 "traffic": None})
+                 "traffic": None if traffic is None else int(traffic)})
 
     out = {
         "metric": "subdomain-cell·angle·rank updates/s per step",
@@ -194,11 +240,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": {"fp64": "f64", "fp32": "f32+f64", "bf16": "bf16x3+f64"}[args.precision],
         "data": "synthetic",
         "config": {"workload": WORKLOAD_NAMES.get(args.config, args.config), "name": args.config,
                    "subdomains": wl.n_sub, "cells_per_subdomain": wl.N, "directions": wl.M,
                    "rank": int(wl.r_fixed), "r_int_max": int(wl.r_int_max), "exec_mode": args.mode,
+                   "precision": args.precision,
                    "max_intermediate_rank": int(np.max(tmax)), "updates_per_step": updates},
         "roofline": roof,
         "kernels": {k: {"avg_us": round(v["avg_us"], 2), "share": round(v["share"], 4), "launches": v["launches"]}

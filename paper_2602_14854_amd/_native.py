@@ -244,9 +244,12 @@ class DDDLRA:
         self._check(self.lib.dd_dlra_force_ranks(self.h, None if ta is None else ta.ctypes.data_as(_IP),
                                                   None if ra is None else ra.ctypes.data_as(_IP)))
 
-    def profile(self, enable: bool = True):
-        """Bracket later non-graph phase launches with hipEvents."""
-        self._check(self.lib.dd_dlra_profile(self.h, 1 if enable else 0))
+    def profile(self, enable=True):
+        """Bracket later non-graph phase launches with hipEvents.  An integer
+        k > 1 also launches each repeatable tall-skinny phase k times inside
+        its event pair."""
+        level = int(enable) if not isinstance(enable, bool) else (1 if enable else 0)
+        self._check(self.lib.dd_dlra_profile(self.h, level))
 
     def kernel_stats(self) -> dict:
         """{kernel name: (launches, total milliseconds)} of the profiled launches."""
