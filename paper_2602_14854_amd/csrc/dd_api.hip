@@ -124,9 +124,11 @@ Layout make_layout(const dd_dlra_config* c) {
   L.M = c->n_dir;
   L.ntN = (L.N + dd::TILE - 1) / dd::TILE;
   L.ntM = (L.M + dd::TILE - 1) / dd::TILE;
-  const int target = std::max(1, (1024 + L.nsub - 1) / L.nsub);
-  L.nwgN = std::min(std::min(L.ntN, target), 64);
-  L.nwgM = std::min(std::min(L.ntM, target), 64);
+  // room for partial sums of up to this many workgroups per subdomain (the
+  // grid actually used is chosen at creation from the kernels' occupancy)
+  const int cap = std::min(64, std::max(1, (2048 + L.nsub - 1) / L.nsub));
+  L.nwgN = std::min(L.ntN, cap);
+  L.nwgM = std::min(L.ntM, cap);
   const int R = L.R, T = L.T, MA = L.MA;
   L.gpTile = std::max(std::max(MA * MA, 3 * T * T + 3 * R * T), std::max(2 * T * T, 2 * R * R + R));
   L.gpStride = (int64_t)std::max(L.nwgN, L.nwgM) * L.gpTile;
@@ -648,6 +650,19 @@ dd_status dd_dlra_create(const dd_dlra_config* cfg, const int32_t* rank0, const 
   }
   fill_dev(h->d, L, cfg, (char*)h->ws);
   Dev& d = h->d;
+  {
+    // one round of resident workgroups covers the batch: each wavefront then
+    // walks many strips with its loads running ahead of its products
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0) {
+      h->err = "cannot query the compute-unit count";
+      return fail(DD_EHIP);
+    }
+    const int per_sd = std::max(1, ncu * dd::ts_resident_wgs(d) / d.nsub);
+    d.nwgN = std::min(per_sd, L.nwgN);
+    d.nwgM = std::min(per_sd, L.nwgM);
+  }
   if (hipMemsetAsync(h->ws, 0, L.bytes, h->stream) != hipSuccess) {
     h->err = "hipMemsetAsync failed";
     return fail(DD_EHIP);

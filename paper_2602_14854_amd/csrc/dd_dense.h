@@ -4,6 +4,7 @@
 #pragma once
 
 #include "dd_internal.h"
+#include "dd_mfma.h"
 
 namespace dd {
 
@@ -24,56 +25,90 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 }
 
 
-// C (m x n) = alpha * op(A) op(B) (+ beta C); generic pointers, no aliasing.
-// The inner loop is unrolled so that operands in global memory are fetched
-// eight at a time rather than one dependent load per step.
+// C (m x n) = alpha * op(A) op(B) (+ beta C) for m, n, k <= CAP; generic
+// pointers (LDS or global), no aliasing.  On the FP64 matrix cores: the
+// 16 x 16 output tiles are dealt to the wavefronts, and a wavefront issues
+// every operand load of a tile (clamped to valid addresses, out-of-range
+// values replaced by zero) before its first v_mfma_f64_16x16x4f64, so a tile
+// costs one load latency instead of one per k.
 __device__ __forceinline__ void mm(double* C, int ldc, const double* A, int lda, bool ta, const double* B, int ldb,
                    bool tb, int m, int n, int k, double alpha, double beta) {
-  for (int idx = threadIdx.x; idx < m * n; idx += NTHR) {
-    const int i = idx % m, j = idx / m;
-    double acc = 0.0;
-#pragma unroll 8
-    for (int l = 0; l < k; ++l) {
-      const double a = ta ? A[l + i * lda] : A[i + l * lda];
-      const double b = tb ? B[j + l * ldb] : B[l + j * ldb];
-      acc = fma(a, b, acc);
+  constexpr int KMAX = CAP / 4;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l16 = lane & 15, kq = lane >> 4;
+  const int tm = (m + 15) >> 4, tn = (n + 15) >> 4, nk = (k + 3) >> 2;
+  for (int tile = wave; tile < tm * tn; tile += NW) {
+    const int i0 = 16 * (tile % tm), j0 = 16 * (tile / tm);
+    const int i = i0 + l16, j = j0 + l16;  // A row and B column of this lane
+    const int ic = i < m ? i : 0, jc = j < n ? j : 0;
+    double av[KMAX], bv[KMAX];
+#pragma unroll
+    for (int s4 = 0; s4 < KMAX; ++s4) {
+      if (s4 < nk) {
+        const int l = 4 * s4 + kq;
+        const int lc = l < k ? l : 0;
+        av[s4] = ta ? A[lc + ic * lda] : A[ic + lc * lda];
+        bv[s4] = tb ? B[jc + lc * ldb] : B[lc + jc * ldb];
+      }
     }
-    C[i + j * ldc] = (beta == 0.0) ? alpha * acc : alpha * acc + beta * C[i + j * ldc];
+    dbl4 acc = zero4();
+#pragma unroll
+    for (int s4 = 0; s4 < KMAX; ++s4) {
+      if (s4 < nk) {
+        const int l = 4 * s4 + kq;
+        const double a = (i < m && l < k) ? av[s4] : 0.0;
+        const double b = (j < n && l < k) ? bv[s4] : 0.0;
+        acc = mfma64(a, b, acc);
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int ci = i0 + 4 * v + kq, cj = j0 + l16;
+      if (ci < m && cj < n) {
+        double* c = C + ci + (int64_t)cj * ldc;
+        *c = (beta == 0.0) ? alpha * acc[v] : fma(alpha, acc[v], beta * *c);
+      }
+    }
   }
   __syncthreads();
 }
 
 // dst (rows x cols, ldd) = sum over ngp workgroup partials of the block at
 // offset off (leading dimension lds) -- fixed order over the partials, so
-// deterministic.  Each thread takes four entries and fetches four partials of
-// each before adding, keeping 16 loads in flight.
+// deterministic.  Each thread takes eight entries and fetches four partials
+// of each before adding, keeping 32 loads in flight (addresses of absent
+// entries or partials are clamped to a valid one and the value dropped).
 __device__ __forceinline__ void sum_partials(const Dev& d, int s, int ngp, int off, int lds, int rows, int cols, double* dst,
                              int ldd, double scale) {
+  constexpr int E = 8, U = 4;
   const double* gp = gpart_of(d, s) + off;
   const int n = rows * cols;
-  for (int base = threadIdx.x; base < n; base += 4 * NTHR) {
-    int src[4];
-    double acc[4];
+  for (int base = threadIdx.x; base < n; base += E * NTHR) {
+    int src[E];
+    double acc[E];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+    for (int e = 0; e < E; ++e) {
       const int idx = base + e * NTHR;
-      src[e] = idx < n ? (idx % rows) + (idx / rows) * lds : -1;
+      src[e] = idx < n ? (idx % rows) + (idx / rows) * lds : 0;
       acc[e] = 0.0;
     }
-    for (int w0 = 0; w0 < ngp; w0 += 4) {
-      double v[4][4];
+    for (int w0 = 0; w0 < ngp; w0 += U) {
+      double v[E][U];
 #pragma unroll
-      for (int e = 0; e < 4; ++e)
+      for (int e = 0; e < E; ++e)
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-          v[e][u] = (src[e] >= 0 && w0 + u < ngp) ? gp[(int64_t)(w0 + u) * d.gpTile + src[e]] : 0.0;
+        for (int u = 0; u < U; ++u) {
+          const int w = w0 + u < ngp ? w0 + u : 0;
+          v[e][u] = gp[(int64_t)w * d.gpTile + src[e]];
+        }
 #pragma unroll
-      for (int e = 0; e < 4; ++e)
+      for (int e = 0; e < E; ++e)
 #pragma unroll
-        for (int u = 0; u < 4; ++u) acc[e] += v[e][u];
+        for (int u = 0; u < U; ++u)
+          if (w0 + u < ngp) acc[e] += v[e][u];
     }
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+    for (int e = 0; e < E; ++e) {
       const int idx = base + e * NTHR;
       if (idx < n) dst[(idx % rows) + (idx / rows) * ldd] = scale * acc[e];
     }
@@ -290,29 +325,6 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Upper-triangle entries (i <= j) of an n x n matrix owned by this thread:
-// packed index q = tid + NTHR m for m < NO.  Unused slots hold i = j = -1.
-// NO = own_slots(n) suffices for an n x n matrix.
-constexpr int own_slots(int n) { return (n * (n + 1) / 2 + NTHR - 1) / NTHR; }
-
-template <int NO>
-__device__ __forceinline__ void owned_pairs(int n, int* oi, int* oj) {
-  const int np = n * (n + 1) / 2;
-#pragma unroll
-  for (int m = 0; m < NO; ++m) {
-    const int q = threadIdx.x + m * NTHR;
-    int i = -1, j = -1;
-    if (q < np) {
-      j = (int)((sqrtf(8.0f * q + 1.0f) - 1.0f) * 0.5f);
-      if (j * (j + 1) / 2 > q) --j;
-      if ((j + 1) * (j + 2) / 2 <= q) ++j;
-      i = q - j * (j + 1) / 2;
-    }
-    oi[m] = i;
-    oj[m] = j;
-  }
-}
-
 // Largest value over the 64 lanes of a wavefront, every lane gets it.
 __device__ __forceinline__ double wave_max(double v) {
   union { double d; int i[2]; } a, b;
@@ -353,132 +365,107 @@ __device__ __forceinline__ double pivot_key(double v, int i) {
   return __longlong_as_double((__double_as_longlong(c) & ~63ll) | (long long)(63 - i));
 }
 
-// Cholesky factorisation of the symmetric n x n matrix G (LDS, ld LDA; only
-// the upper triangle is read), optionally with diagonal pivoting:
-//   G[perm, perm] = R^T R,  R upper triangular (left in G, ld LDA),
-// where perm = identity without pivoting; with pivoting, step k takes the
-// largest remaining diagonal entry of the Schur complement (the column order
-// of pivoted QR of the matrix whose Gram G is).  X (LDS, ld LDA) is scratch.
-// A pivot not larger than 1e-20 times the column's own initial diagonal
-// marks a numerically dependent column: the pivot is replaced by 1 so the
-// factorisation continues as if the column were a fresh unit direction, and
-// dep[k] is set (the caller replaces that column of Q by a pseudo-random
-// vector and zeroes row k of R).  A non-finite pivot latches FLAG_NONFINITE
-// and is treated the same way.
-// The elimination runs in the original index space (pivoting only chooses
-// the next index), each thread owning fixed upper-triangle entries; a step
-// issues all its LDS reads at once and ends with the only barrier.  With
-// pivoting every wavefront finds the pivot itself (maximum of packed
-// value/index keys over its lanes).
-template <int NO, bool PIVOT>
-__device__ __forceinline__ void chol_piv(const Dev& d, double* G, double* X, int n, int* perm, int* dep) {
-  __shared__ double diag0[CAP];
-  __shared__ double dpiv[CAP];
-  int oi[NO], oj[NO];
-  owned_pairs<NO>(n, oi, oj);
-  const int j = threadIdx.x & 63, g = threadIdx.x >> 6;
-  const int lane = threadIdx.x & 63;
-  if (threadIdx.x < n) diag0[threadIdx.x] = G[threadIdx.x * (LDA + 1)];
-  __syncthreads();
-  uint64_t done = 0;  // indices already eliminated (identical in every thread)
-  for (int k = 0; k < n; ++k) {
-    int p = k;
-    double dk;
-    if (PIVOT) {
-      const bool cand = lane < n && !((done >> lane) & 1);
-      const double v = cand ? G[lane * (LDA + 1)] : 0.0;
-      const double kmax = wave_max(cand ? pivot_key(v, lane) : 0.0);
-      p = 63 - (int)(__double_as_longlong(kmax) & 63);
-      dk = lane_value(v, p);
-    } else {
-      dk = G[k * (LDA + 1)];
-    }
-    const double d0 = diag0[p];
-    // pivot row (Schur values at this step) in the original index space
-    const double xrec = (threadIdx.x < n) ? G[(lane < p ? lane : p) + (lane < p ? p : lane) * LDA] : 0.0;
-    double gpi[NO], gpj[NO], gij[NO];
-    bool act[NO];
+// Cholesky factorisation of the symmetric n x n matrix G (n <= NMAX; LDS, ld
+// LDA, upper triangle read), optionally with diagonal pivoting,
+//   G[perm, perm] = R^T R,  R upper triangular,
+// and the inverse R^{-1}, both by wavefront 0 alone with no workgroup
+// barrier.  Lane j keeps row entries R[0..k][j] of its own (original) column
+// j in registers and its current Schur diagonal.  Step k (left-looking):
+// the pivot p is k, or with pivoting the largest remaining Schur diagonal
+// (smallest index among equal ones); every lane forms
+//   R[k][j] = (G[p][j] - sum_{l<k} R[l][p] R[l][j]) / R[k][p],
+// reading R[l][p] from lane p with v_readlane.  A pivot not larger than 1e-20
+// times the column's own initial diagonal (or non-finite) marks a
+// numerically dependent column: the pivot is replaced by 1 (the Schur row is
+// kept as the row of R) and dep[k] is set; the caller completes Q with a
+// pseudo-random column there and zeroes row k of R.  The inverse of the
+// permuted factor R P is a right-looking back substitution, again from
+// registers.  On return (after a barrier): G = R P (upper, zero below), X =
+// (R P)^{-1}, perm, dep.  All threads call.
+template <int NMAX, bool PIVOT>
+__device__ __forceinline__ void chol_inv_wave(const Dev& d, double* G, double* X, int n, int* perm, int* dep) {
+  if (threadIdx.x < 64) {
+    const int j = threadIdx.x;
+    double rc[NMAX];  // rc[l] = R[l][j]
+    double dg = j < n ? G[j * (LDA + 1)] : 0.0;
+    const double d0 = dg;
+    bool done = j >= n;
+    int myk = -1;
+    int pk[NMAX];  // pivot index of each step (wave-uniform)
 #pragma unroll
-    for (int m = 0; m < NO; ++m) {
-      const int i = oi[m], jj = oj[m];
-      act[m] = PIVOT ? (i >= 0 && !((done >> i) & 1) && !((done >> jj) & 1) && i != p && jj != p) : (i > k);
-      if (act[m]) {
-        gpi[m] = G[(i < p ? i : p) + (i < p ? p : i) * LDA];
-        gpj[m] = G[(jj < p ? jj : p) + (jj < p ? p : jj) * LDA];
-        gij[m] = G[i + jj * LDA];
+    for (int k = 0; k < NMAX; ++k) {
+      rc[k] = 0.0;
+      pk[k] = k;
+      if (k < n) {
+        int p = k;
+        if (PIVOT) {
+          const double kmax = wave_max(done ? 0.0 : pivot_key(dg, j));
+          p = 63 - (int)(__double_as_longlong(kmax) & 63);
+        }
+        pk[k] = p;
+        const double g = G[(p < j ? p : j) + (p < j ? j : p) * LDA];
+        double dk = lane_value(dg, p);
+        const double d0k = lane_value(d0, p);
+        bool isdep = false;
+        if (!isfinite(dk)) {
+          dk = 1.0;
+          isdep = true;
+          if (j == 0) atomicOr(d.flags, FLAG_NONFINITE);
+        } else if (!(dk > 1e-20 * d0k)) {
+          dk = 1.0;
+          isdep = true;
+        }
+        const double rinv = rsqrt_nr(dk);
+        double a0 = g, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll
+        for (int l = 0; l < k; l += 4) {
+          a0 = fma(-lane_value(rc[l], p), rc[l], a0);
+          if (l + 1 < k) a1 = fma(-lane_value(rc[l + 1], p), rc[l + 1], a1);
+          if (l + 2 < k) a2 = fma(-lane_value(rc[l + 2], p), rc[l + 2], a2);
+          if (l + 3 < k) a3 = fma(-lane_value(rc[l + 3], p), rc[l + 3], a3);
+        }
+        const double rkj = (a0 + a1) + (a2 + a3);
+        if (j == p) {
+          rc[k] = dk * rinv;
+          done = true;
+          myk = k;
+        } else if (!done) {
+          rc[k] = rkj * rinv;
+          dg = fma(-rc[k], rc[k], dg);
+        }
+        if (j == 0) {
+          perm[k] = p;
+          dep[k] = isdep ? 1 : 0;
+        }
       }
     }
-    bool isdep = false;
-    if (!isfinite(dk)) {
-      dk = 1.0;
-      isdep = true;
-      if (threadIdx.x == 0) atomicOr(d.flags, FLAG_NONFINITE);
-    } else if (!(dk > 1e-20 * d0)) {
-      dk = 1.0;
-      isdep = true;
-    }
-    const double inv = rcp_nr(dk);
-    done |= 1ull << p;
-    if (threadIdx.x == 0) {
-      perm[k] = p;
-      dep[k] = isdep ? 1 : 0;
-      dpiv[k] = dk;
-    }
-    if (threadIdx.x < n) X[k + threadIdx.x * LDA] = xrec;
+    // R P: the column of lane j is column myk of the permuted factor
+    if (myk >= 0) {
 #pragma unroll
-    for (int m = 0; m < NO; ++m)
-      if (act[m]) G[oi[m] + oj[m] * LDA] = fma(-gpi[m] * inv, gpj[m], gij[m]);
-    __syncthreads();
-  }
-  if (threadIdx.x < n) dpiv[threadIdx.x] = sqrt(dpiv[threadIdx.x]);
-  __syncthreads();
-  // R[k][l] = (pivot row k at column perm[l]) / rdiag[k] for l > k
-  if (j < n) {
-    const int pl = perm[j];
-    for (int k = g; k < n; k += 4) {
-      double v = 0.0;
-      if (j == k) v = dpiv[k];
-      else if (j > k) v = X[k + pl * LDA] * rcp_nr(dpiv[k]);
-      G[k + j * LDA] = v;
+      for (int i = 0; i < NMAX; ++i)
+        if (i < n) G[i + myk * LDA] = i <= myk ? rc[i] : 0.0;
     }
-  }
-  __syncthreads();
-}
-
-// X = R^{-1} for upper triangular R (both LDS, ld LDA), right-looking back
-// substitution with one barrier per step: once rows > k have been removed
-// from row k, row k is final up to the factor 1/R[k][k] and is removed from
-// all rows above in parallel (each thread owning fixed entries, reads first).
-template <int NO>
-__device__ __forceinline__ void tri_inv(const double* R, double* X, int n) {
-  __shared__ double rinv[CAP];
-  int oi[NO], oj[NO];
-  owned_pairs<NO>(n, oi, oj);
-  const int j = threadIdx.x & 63, g = threadIdx.x >> 6;
-  if (j < n)
-    for (int i = g; i < n; i += 4) X[i + j * LDA] = (i == j) ? 1.0 : 0.0;
-  if (threadIdx.x < n) rinv[threadIdx.x] = 1.0 / R[threadIdx.x * (LDA + 1)];
-  __syncthreads();
-  for (int k = n - 1; k > 0; --k) {
-    const double rk = rinv[k];
-    double rik[NO], xkj[NO], xij[NO];
-    bool act[NO];
+    // X = (R P)^{-1}: lane q holds column q; column k of R P is held by
+    // lane pk[k] (entries rc[0..k])
+    const int q = j;
+    double x[NMAX];
 #pragma unroll
-    for (int m = 0; m < NO; ++m) {
-      act[m] = oi[m] >= 0 && oi[m] < k && oj[m] >= k;
-      if (act[m]) {
-        rik[m] = R[oi[m] + k * LDA];
-        xkj[m] = X[k + oj[m] * LDA];
-        xij[m] = X[oi[m] + oj[m] * LDA];
+    for (int i = 0; i < NMAX; ++i) x[i] = i == q ? 1.0 : 0.0;
+#pragma unroll
+    for (int k = NMAX - 1; k >= 0; --k) {
+      if (k < n) {
+        const int pl = pk[k];
+        x[k] *= rcp_nr(lane_value(rc[k], pl));
+#pragma unroll
+        for (int i = 0; i < k; ++i) x[i] = fma(-lane_value(rc[i], pl), x[k], x[i]);
       }
     }
+    if (q < n) {
 #pragma unroll
-    for (int m = 0; m < NO; ++m)
-      if (act[m]) X[oi[m] + oj[m] * LDA] = fma(-rik[m] * rk, xkj[m], xij[m]);
-    __syncthreads();
+      for (int i = 0; i < NMAX; ++i)
+        if (i < n) X[i + q * LDA] = x[i];
+    }
   }
-  if (j < n)
-    for (int i = g; i < n; i += 4) X[i + j * LDA] *= rinv[i];
   __syncthreads();
 }
 

@@ -31,7 +31,7 @@ struct Dev {
   int ntN, ntM;            // tiles over cells / over directions
   int nwgN, nwgM;          // workgroups per subdomain for cell / direction kernels
   int gpTile;              // doubles per workgroup partial
-  int64_t gpStride;        // doubles of partials per subdomain
+  int64_t gpStride;        // doubles of partials per subdomain (room for the largest grid)
   int64_t smallStride;     // doubles of small workspace per subdomain
   // rank rules and precision mode (DD_PREC_*)
   int rank_mode, r_fixed, r_min, r_max, r_int_max, strict;
@@ -148,6 +148,7 @@ __device__ inline double hash_unit(uint64_t x) {
 namespace dd {
 // tall-skinny kernels
 void init_kernels();
+int ts_resident_wgs(const Dev& d);
 void launch_aug_form(const Dev& d, int axis, int sd0, int nsd, hipStream_t st);
 // Y = diag(rowscale) X B.  x64 / y64: X / Y is an FP64 array (else of the
 // working type of the precision mode); exact: formed in FP64 whatever the

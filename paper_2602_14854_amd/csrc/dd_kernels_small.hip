@@ -101,7 +101,7 @@ void launch_aug_svd(const Dev& d, int axis, int sd0, int nsd, hipStream_t st) {
 //              with R P^T, acc_mode 2 left-multiplies it by R -- with the rows
 //              of dependent columns zeroed.
 // Slots have leading dimension ld.
-template <int NO>
+template <int NMAX>
 __global__ __launch_bounds__(NTHR) void s_chol(Dev d, int axis, int sd0, int ndim, int rows, int ngp, int shift,
                                               int acc_mode, double bscale, int pivot, int oRinv, int oRacc, int ld) {
   const int s = sd0 + blockIdx.x;
@@ -120,9 +120,8 @@ __global__ __launch_bounds__(NTHR) void s_chol(Dev d, int axis, int sd0, int ndi
     if (threadIdx.x < n) G[threadIdx.x * (LDA + 1)] += sh;
     __syncthreads();
   }
-  if (pivot) chol_piv<NO, true>(d, G, X, n, perm, dep);
-  else chol_piv<NO, false>(d, G, X, n, perm, dep);
-  tri_inv<NO>(G, X, n);
+  if (pivot) chol_inv_wave<NMAX, true>(d, G, X, n, perm, dep);
+  else chol_inv_wave<NMAX, false>(d, G, X, n, perm, dep);
   double* sm = small_of(d, s);
   // thread (column c = tid % 64, rows i = tid / 64 mod 4) for the n x n outputs
   const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
@@ -144,33 +143,20 @@ __global__ __launch_bounds__(NTHR) void s_chol(Dev d, int axis, int sd0, int ndi
   } else if (acc_mode == 2) {
     // Racc <- R Racc, with Racc staged in LDS
     copy_to_lds(X, sm + oRacc, ld, n, n);
-    if (c < n) {
-      for (int i = g; i < n; i += 4) {
-        double acc = 0.0;
-        for (int k = i; k < n; ++k) acc = fma(G[i + k * LDA], X[k + c * LDA], acc);
-        sm[oRacc + i + c * ld] = acc;
-      }
-    }
+    mm(sm + oRacc, ld, G, LDA, false, X, LDA, false, n, n, n, 1.0, 0.0);
   }
 }
 
 void launch_chol(const Dev& d, int axis, int sd0, int nsd, int ndim, int rows, int ngp, bool shift, int acc_mode,
                  double bscale, bool pivot, int oRinv, int oRacc, int ld, hipStream_t st) {
   const int cap = ndim == DIM_M0 ? d.MA : (ndim == DIM_T ? d.T : d.R);
-#define DD_CHOL(NO)                                                                                               \
-  hipLaunchKernelGGL(s_chol<NO>, dim3(nsd), dim3(NTHR), 0, st, d, axis, sd0, ndim, rows, ngp, shift ? 1 : 0,     \
+#define DD_CHOL(NMAX)                                                                                             \
+  hipLaunchKernelGGL(s_chol<NMAX>, dim3(nsd), dim3(NTHR), 0, st, d, axis, sd0, ndim, rows, ngp, shift ? 1 : 0,   \
                      acc_mode, bscale, pivot ? 1 : 0, oRinv, oRacc, ld)
-  switch (own_slots(cap)) {
-    case 1: DD_CHOL(1); break;
-    case 2: DD_CHOL(2); break;
-    case 3: DD_CHOL(3); break;
-    case 4: DD_CHOL(4); break;
-    case 5: DD_CHOL(5); break;
-    case 6: DD_CHOL(6); break;
-    case 7: DD_CHOL(7); break;
-    case 8: DD_CHOL(8); break;
-    default: DD_CHOL(9); break;
-  }
+  if (cap <= 16) DD_CHOL(16);
+  else if (cap <= 32) DD_CHOL(32);
+  else if (cap <= 48) DD_CHOL(48);
+  else DD_CHOL(64);
 #undef DD_CHOL
 }
 

@@ -4,8 +4,11 @@
 // subdomain the rows (cells or directions) are cut into strips of 16; strip
 // st belongs to wavefront st mod (4 gridDim.x) of the workgroups blockIdx.x,
 // so a workgroup takes 64 consecutive rows at a time and no barrier is
-// needed inside the strip loop.  All global loads of a strip are issued
-// before its first matrix-core instruction.  Reductions over rows (Gram and
+// needed inside the strip loop.  The loop is software-pipelined: the global
+// loads of a wavefront's next strip are issued before the matrix-core
+// instructions of the current one, so load latency overlaps the products
+// (the grids are sized so that one to a few workgroups per compute unit
+// cover the whole batch, and each wavefront walks many strips).  Reductions over rows (Gram and
 // Galerkin matrices) stay in the wavefronts' accumulators, are summed over
 // the workgroup in a fixed order and leave one partial per workgroup; the
 // small per-subdomain kernels add the partials in a fixed order, so results
@@ -71,24 +74,39 @@ __global__ __launch_bounds__(NTHR) void k_aug_form(Dev d, int axis, int sd0) {
   const double* Vb[3];
   for (int b = 0; b < 3; ++b) Vb[b] = nb[b] >= 0 ? d.V + (int64_t)nb[b] * M * R : d.V;
   S* As = (S*)d.A + (int64_t)s * M * d.MA;
-  const int nlive = live_sub<P>(m0);
   dbl4 g[NB];
   zero_acc<NB>(g);
   const int nst = ceil_div(M, 16);
-  for (int st = blockIdx.x * NW + wave; st < nst; st += gridDim.x * NW) {
+  const int stride = gridDim.x * NW;
+  F xn[KS];
+  // loads never branch: indices are clamped to valid ones and the value of
+  // an absent entry is replaced by zero
+  auto load = [&](int st_) {
+    const int q_ = st_ * 16 + l16;
+    const int qc = q_ < M ? q_ : M - 1;
+#pragma unroll
+    for (int u = 0; u < KS; ++u) {
+      const int kc = sub_col<P>(u, kq);
+      const bool in = q_ < M && kc < m0;
+      const int kk = in ? kc : 0;
+      const int bk = kk < c1 ? 0 : (kk < c2 ? 1 : 2);
+      const int off = bk == 0 ? 0 : (bk == 1 ? c1 : c2);
+      const double v = Vb[bk][(int64_t)(kk - off) * M + qc];
+      xn[u] = in ? (F)v : (F)0;
+    }
+  };
+  int st = blockIdx.x * NW + wave;
+  if (st < nst) load(st);
+  for (; st < nst; st += stride) {
     const int q = st * 16 + l16;
     const bool rin = q < M;
     F xv[KS];
 #pragma unroll
-    for (int u = 0; u < KS; ++u) {
-      const int kc = sub_col<P>(u, kq);
-      const int bk = kc < c1 ? 0 : (kc < c2 ? 1 : 2);
-      const int off = bk == 0 ? 0 : (bk == 1 ? c1 : c2);
-      xv[u] = (rin && kc < m0) ? (F)Vb[bk][(int64_t)(kc - off) * M + q] : (F)0;
-    }
+    for (int u = 0; u < KS; ++u) xv[u] = xn[u];
+    if (st + stride < nst) load(st + stride);
     Acc acc[NCB];
     zero_prod<P>(acc, NCB);
-    prod_acc<P, NCB, KS>(acc, Bf, xv, nlive);
+    prod_acc<P, NCB, KS>(acc, Bf, xv);
     const double swq = rin ? d.sw[q] : 0.0;
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) {
@@ -144,22 +162,34 @@ __global__ __launch_bounds__(NTHR) void k_gemm(Dev d, int axis, int sd0, const v
 
   const SI* Xsd = (const SI*)X + (int64_t)s * xsd;
   S* Ysd = (S*)Y + (int64_t)s * ysd;
-  const int nlive = live_sub<P>(k);
   dbl4 g[NB];
   zero_acc<NB>(g);
   const int nst = ceil_div(rows, 16);
-  for (int st = blockIdx.x * NW + wave; st < nst; st += gridDim.x * NW) {
+  const int stride = gridDim.x * NW;
+  F xn[KS];
+  auto load = [&](int st_) {
+    const int row_ = st_ * 16 + l16;
+    const int rc = row_ < rows ? row_ : rows - 1;
+#pragma unroll
+    for (int u = 0; u < KS; ++u) {
+      const int kc = sub_col<P>(u, kq);
+      const bool in = row_ < rows && kc < k;
+      const SI v = Xsd[(int64_t)(in ? kc : 0) * rows + rc];
+      xn[u] = in ? (F)v : (F)0;
+    }
+  };
+  int st = blockIdx.x * NW + wave;
+  if (st < nst) load(st);
+  for (; st < nst; st += stride) {
     const int row = st * 16 + l16;
     const bool rin = row < rows;
     F xv[KS];
 #pragma unroll
-    for (int u = 0; u < KS; ++u) {
-      const int kc = sub_col<P>(u, kq);
-      xv[u] = (rin && kc < k) ? (F)Xsd[(int64_t)kc * rows + row] : (F)0;
-    }
+    for (int u = 0; u < KS; ++u) xv[u] = xn[u];
+    if (st + stride < nst) load(st + stride);
     Acc acc[NCB];
     zero_prod<P>(acc, NCB);
-    prod_acc<P, NCB, KS>(acc, Bf, xv, nlive);
+    prod_acc<P, NCB, KS>(acc, Bf, xv);
     const double rs = (rowscale != nullptr && rin) ? rowscale[row] : 1.0;
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) {
@@ -227,15 +257,29 @@ __global__ __launch_bounds__(NTHR) void k_ang_reduce(Dev d, int axis, int sd0) {
   dbl4 acc[NACC];
   zero_acc<NACC>(acc);
   const int nst = ceil_div(M, 16);
-  for (int st = blockIdx.x * 2 + (wave & 1); st < nst; st += gridDim.x * 2) {
+  const int stride = gridDim.x * 2;
+  // only the V-hat rows are prefetched (the three V sources would exceed the
+  // register budget of the wavefronts that hold the r x t accumulators)
+  S xn[KST];
+  auto load = [&](int st_) {
+    const int q_ = st_ * 16 + l16;
+    const int qc = q_ < M ? q_ : M - 1;
+#pragma unroll
+    for (int ks = 0; ks < KST; ++ks) {
+      const int c = 4 * ks + kq;
+      const S v = Qsd[(int64_t)(c < t ? c : 0) * M + qc];
+      xn[ks] = (q_ < M && c < t) ? v : (S)0;
+    }
+  };
+  int st = blockIdx.x * 2 + (wave & 1);
+  if (st < nst) load(st);
+  for (; st < nst; st += stride) {
     const int q = st * 16 + l16;
     const bool rin = q < M;
     double xq[KST];
 #pragma unroll
-    for (int ks = 0; ks < KST; ++ks) {
-      const int c = 4 * ks + kq;
-      xq[ks] = (rin && c < t) ? (double)Qsd[(int64_t)c * M + q] : 0.0;
-    }
+    for (int ks = 0; ks < KST; ++ks) xq[ks] = (double)xn[ks];
+    if (st + stride < nst) load(st + stride);
     if (grp_v) {
       double xv[3][KSV];
 #pragma unroll
@@ -243,7 +287,9 @@ __global__ __launch_bounds__(NTHR) void k_ang_reduce(Dev d, int axis, int sd0) {
 #pragma unroll
         for (int ks = 0; ks < KSV; ++ks) {
           const int c = 4 * ks + kq;
-          xv[b][ks] = (rin && c < rv[b]) ? Vsrc[b][(int64_t)c * M + q] : 0.0;
+          const bool in = rin && c < rv[b];
+          const double v = Vsrc[b][(int64_t)(in ? c : 0) * M + (rin ? q : M - 1)];
+          xv[b][ks] = in ? v : 0.0;
         }
       }
       const double swq = rin ? d.sw[q] : 0.0;
@@ -336,13 +382,13 @@ __global__ __launch_bounds__(NTHR) void k_ang_reduce(Dev d, int axis, int sd0) {
 // coefficient matrices (r x t) come from the eigen-split C = C+ + C-.
 // Also leaves the partial Gram matrix K1^T K1.
 // ----------------------------------------------------------------------------
-template <class S, int P, int NCB>
-__global__ __launch_bounds__(NTHR) void k_kstep(Dev d, int axis, int sd0, int ksr) {
+template <class S, int P, int NCB, int KSP>
+__global__ __launch_bounds__(NTHR) void k_kstep(Dev d, int axis, int sd0) {
   using F = typename Prec<P>::F;
   using Acc = typename Prec<P>::Acc;
   constexpr int LD = strip_ld<NCB>();
   constexpr int NB = NCB * (NCB + 1) / 2;
-  constexpr int KSP = P == 2 ? 8 : 6;  // sub-steps covering the largest stored rank
+  // KSP: sub-steps covering the stored-rank capacity
   const int s = sd0 + blockIdx.y;
   const int lo = neighbour(d, s, axis, -1), hi = neighbour(d, s, axis, +1);
   const int r = d.rank[s], rl = lo >= 0 ? d.rank[lo] : 0, rh = hi >= 0 ? d.rank[hi] : 0;
@@ -351,8 +397,8 @@ __global__ __launch_bounds__(NTHR) void k_kstep(Dev d, int axis, int sd0, int ks
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int l16 = lane & 15, kq = lane >> 4;
   extern __shared__ double lds[];
-  // fragments of the 7 coefficient blocks: Cf[((m * ksr + u) * NCB + cb) * 64 + lane]
-  const int nfrag = 7 * ksr * NCB * 64;
+  // fragments of the 7 coefficient blocks: Cf[((m * KSP + u) * NCB + cb) * 64 + lane]
+  constexpr int nfrag = 7 * KSP * NCB * 64;
   F* Cf = reinterpret_cast<F*>(lds);
   double* Ys = lds + frag_doubles<P>(nfrag) + wave * 16 * LD;
   {
@@ -360,13 +406,13 @@ __global__ __launch_bounds__(NTHR) void k_kstep(Dev d, int axis, int sd0, int ks
     const int offs[7] = {d.oM0, d.oMm, d.oMp, d.oGLo, d.oGHi, d.oGLoN, d.oGHiN};
     const int rows[7] = {r, r, r, r, r, rl, rh};
     for (int idx = threadIdx.x; idx < nfrag; idx += NTHR) {
-      const int l = idx & 63, f = idx >> 6, cb = f % NCB, u = (f / NCB) % ksr, m = f / (NCB * ksr);
+      const int l = idx & 63, f = idx >> 6, cb = f % NCB, u = (f / NCB) % KSP, m = f / (NCB * KSP);
       const int kc = sub_col<P>(u, l >> 4), col = 16 * cb + (l & 15);
       Cf[idx] = (kc < rows[m] && col < t) ? (F)sm[offs[m] + kc + col * R] : (F)0;
     }
   }
   __syncthreads();
-  const int bstride = ksr * NCB * 64;
+  constexpr int bstride = KSP * NCB * 64;
 
   const double* Ub = d.U;
   const double* Us = Ub + (int64_t)s * N * R;
@@ -378,29 +424,48 @@ __global__ __launch_bounds__(NTHR) void k_kstep(Dev d, int axis, int sd0, int ks
   dbl4 g[NB];
   zero_acc<NB>(g);
   const int nst = ceil_div(N, 16);
-  for (int st = blockIdx.x * NW + wave; st < nst; st += gridDim.x * NW) {
+  const int stride = gridDim.x * NW;
+  F n0[KSP], nm[KSP], np[KSP];
+  auto load = [&](int st_) {
+    const int p_ = st_ * 16 + l16;
+    const bool rin_ = p_ < N;
+    const int pc = rin_ ? p_ : N - 1;
+    const int ia_ = axis == 0 ? pc % d.lnx : pc / d.lnx;
+    const bool hm_ = rin_ && ia_ > 0, hp_ = rin_ && ia_ < na - 1;
+    const int pm_ = hm_ ? pc - e : pc, pp_ = hp_ ? pc + e : pc;
+#pragma unroll
+    for (int u = 0; u < KSP; ++u) {
+      const int kc = sub_col<P>(u, kq);
+      const bool kin = kc < r;
+      const int64_t col = (int64_t)(kin ? kc : 0) * N;
+      const double v0 = Us[col + pc], vm = Us[col + pm_], vp = Us[col + pp_];
+      n0[u] = (rin_ && kin) ? (F)v0 : (F)0;
+      nm[u] = (hm_ && kin) ? (F)vm : (F)0;
+      np[u] = (hp_ && kin) ? (F)vp : (F)0;
+    }
+  };
+  int st = blockIdx.x * NW + wave;
+  if (st < nst) load(st);
+  for (; st < nst; st += stride) {
     const int p = st * 16 + l16;
     const bool rin = p < N;
     const int ix = p % d.lnx, iy = p / d.lnx;
     const int ia = axis == 0 ? ix : iy;
     const int f = axis == 0 ? iy : ix;
-    const bool hm = rin && ia > 0, hp = rin && ia < na - 1;
     const bool flo = rin && ia == 0, fhi = rin && ia == na - 1;
     F u0[KSP], um[KSP], up[KSP];
 #pragma unroll
     for (int u = 0; u < KSP; ++u) {
-      const int kc = sub_col<P>(u, kq);
-      const bool kin = u < ksr && kc < r;
-      const int64_t col = (int64_t)kc * N;
-      u0[u] = (rin && kin) ? (F)Us[col + p] : (F)0;
-      um[u] = (hm && kin) ? (F)Us[col + p - e] : (F)0;
-      up[u] = (hp && kin) ? (F)Us[col + p + e] : (F)0;
+      u0[u] = n0[u];
+      um[u] = nm[u];
+      up[u] = np[u];
     }
+    if (st + stride < nst) load(st + stride);
     Acc acc[NCB];
     zero_prod<P>(acc, NCB);
-    prod_acc<P, NCB, KSP>(acc, Cf, u0, ksr);
-    prod_acc<P, NCB, KSP>(acc, Cf + bstride, um, ksr);
-    prod_acc<P, NCB, KSP>(acc, Cf + 2 * bstride, up, ksr);
+    prod_acc<P, NCB, KSP>(acc, Cf, u0);
+    prod_acc<P, NCB, KSP>(acc, Cf + bstride, um);
+    prod_acc<P, NCB, KSP>(acc, Cf + 2 * bstride, up);
     if (__any(flo)) {
       const int pn = face_cell(d, axis, true, f);
       F gu[KSP], gn[KSP];
@@ -408,10 +473,12 @@ __global__ __launch_bounds__(NTHR) void k_kstep(Dev d, int axis, int sd0, int ks
       for (int u = 0; u < KSP; ++u) {
         const int kc = sub_col<P>(u, kq);
         gu[u] = flo ? u0[u] : (F)0;
-        gn[u] = (flo && lo >= 0 && u < ksr && kc < rl) ? (F)Ul[(int64_t)kc * N + pn] : (F)0;
+        const bool in = flo && lo >= 0 && kc < rl;
+        const double v = Ul[(int64_t)(in ? kc : 0) * N + pn];
+        gn[u] = in ? (F)v : (F)0;
       }
-      prod_acc<P, NCB, KSP>(acc, Cf + 3 * bstride, gu, ksr);
-      prod_acc<P, NCB, KSP>(acc, Cf + 5 * bstride, gn, ksr);
+      prod_acc<P, NCB, KSP>(acc, Cf + 3 * bstride, gu);
+      prod_acc<P, NCB, KSP>(acc, Cf + 5 * bstride, gn);
     }
     if (__any(fhi)) {
       const int pn = face_cell(d, axis, false, f);
@@ -420,10 +487,12 @@ __global__ __launch_bounds__(NTHR) void k_kstep(Dev d, int axis, int sd0, int ks
       for (int u = 0; u < KSP; ++u) {
         const int kc = sub_col<P>(u, kq);
         gu[u] = fhi ? u0[u] : (F)0;
-        gn[u] = (fhi && hi >= 0 && u < ksr && kc < rh) ? (F)Uh[(int64_t)kc * N + pn] : (F)0;
+        const bool in = fhi && hi >= 0 && kc < rh;
+        const double v = Uh[(int64_t)(in ? kc : 0) * N + pn];
+        gn[u] = in ? (F)v : (F)0;
       }
-      prod_acc<P, NCB, KSP>(acc, Cf + 4 * bstride, gu, ksr);
-      prod_acc<P, NCB, KSP>(acc, Cf + 6 * bstride, gn, ksr);
+      prod_acc<P, NCB, KSP>(acc, Cf + 4 * bstride, gu);
+      prod_acc<P, NCB, KSP>(acc, Cf + 6 * bstride, gn);
     }
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) {
@@ -485,24 +554,39 @@ __global__ __launch_bounds__(NTHR) void k_spatial_reduce(Dev d, int axis, int sd
   dbl4 acc[NACC];  // [0, NQ): Gm or Gp; then own-face and neighbour-face products
   zero_acc<NACC>(acc);
   const int nst = ceil_div(N, 16);
-  for (int st = blockIdx.x * 2 + (wave & 1); st < nst; st += gridDim.x * 2) {
+  const int stride = gridDim.x * 2;
+  S b0[KS], bn[KS];
+  auto load = [&](int st_) {
+    const int p_ = st_ * 16 + l16;
+    const bool rin_ = p_ < N;
+    const int ia_ = axis == 0 ? p_ % d.lnx : p_ / d.lnx;
+    // neighbour row across the face this wavefront differences over
+    const bool hn_ = low ? (rin_ && ia_ > 0) : (rin_ && ia_ < na - 1);
+    const int pn_ = low ? p_ - e : p_ + e;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int c = 4 * ks + kq;
+      const int64_t col = (int64_t)c * N;
+      b0[ks] = (rin_ && c < t) ? Qsd[col + p_] : (S)0;
+      bn[ks] = (hn_ && c < t) ? Qsd[col + pn_] : (S)0;
+    }
+  };
+  int st = blockIdx.x * 2 + (wave & 1);
+  if (st < nst) load(st);
+  for (; st < nst; st += stride) {
     const int p = st * 16 + l16;
     const bool rin = p < N;
     const int ix = p % d.lnx, iy = p / d.lnx;
     const int ia = axis == 0 ? ix : iy;
     const int f = axis == 0 ? iy : ix;
-    // neighbour row across the face this wavefront differences over
-    const bool hn = low ? (rin && ia > 0) : (rin && ia < na - 1);
     const bool face = low ? (rin && ia == 0) : (rin && ia == na - 1);
-    const int pn = low ? p - e : p + e;
     double x0[KS], xn[KS];
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
-      const int c = 4 * ks + kq;
-      const int64_t col = (int64_t)c * N;
-      x0[ks] = (rin && c < t) ? (double)Qsd[col + p] : 0.0;
-      xn[ks] = (hn && c < t) ? (double)Qsd[col + pn] : 0.0;
+      x0[ks] = (double)b0[ks];
+      xn[ks] = (double)bn[ks];
     }
+    if (st + stride < nst) load(st + stride);
     const bool any_face = __any(face);
     if (any_face) {
       // the face cell of the neighbour that touches this cell
@@ -585,7 +669,7 @@ __global__ __launch_bounds__(NTHR) void k_spatial_reduce(Dev d, int axis, int sd
 // upwinded by the sign of its own Omega.  Leaves the partial Gram of AL.
 // ----------------------------------------------------------------------------
 template <class S, int P, int NCB, int KS>
-__global__ __launch_bounds__(NTHR) void k_lstep(Dev d, int axis, int sd0, int kst) {
+__global__ __launch_bounds__(NTHR) void k_lstep(Dev d, int axis, int sd0) {
   using F = typename Prec<P>::F;
   using Acc = typename Prec<P>::Acc;
   constexpr int LD = strip_ld<NCB>();
@@ -597,44 +681,62 @@ __global__ __launch_bounds__(NTHR) void k_lstep(Dev d, int axis, int sd0, int ks
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int l16 = lane & 15, kq = lane >> 4;
   extern __shared__ double lds[];
-  // fragments of P0, Pm, Pp: Pf[((m * kst + u) * NCB + cb) * 64 + lane]
-  const int nfrag = 3 * kst * NCB * 64;
+  // fragments of P0, Pm, Pp: Pf[((m * KS + u) * NCB + cb) * 64 + lane]
+  constexpr int nfrag = 3 * KS * NCB * 64;
   F* Pf = reinterpret_cast<F*>(lds);
   double* Ys = lds + frag_doubles<P>(nfrag) + wave * 16 * LD;
   {
     const double* sm = small_of(d, s);
     const int offs[3] = {d.oP0, d.oPm, d.oPp};
     for (int idx = threadIdx.x; idx < nfrag; idx += NTHR) {
-      const int l = idx & 63, f = idx >> 6, cb = f % NCB, u = (f / NCB) % kst, m = f / (NCB * kst);
+      const int l = idx & 63, f = idx >> 6, cb = f % NCB, u = (f / NCB) % KS, m = f / (NCB * KS);
       const int kc = sub_col<P>(u, l >> 4), col = 16 * cb + (l & 15);
       Pf[idx] = (kc < t && col < t) ? (F)sm[offs[m] + kc + col * T] : (F)0;
     }
   }
   __syncthreads();
-  const int bstride = kst * NCB * 64;
+  constexpr int bstride = KS * NCB * 64;
   const S* Qsd = (const S*)d.Qh + (int64_t)s * M * T;
   S* ALs = (S*)d.AL + (int64_t)s * M * T;
   dbl4 g[NB];
   zero_acc<NB>(g);
   const int nst = ceil_div(M, 16);
-  for (int st = blockIdx.x * NW + wave; st < nst; st += gridDim.x * NW) {
+  const int stride = gridDim.x * NW;
+  F xn[KS];
+  double on_ = 0.0;
+  auto load = [&](int st_) {
+    const int q_ = st_ * 16 + l16;
+    const int qc = q_ < M ? q_ : M - 1;
+#pragma unroll
+    for (int u = 0; u < KS; ++u) {
+      const int kc = sub_col<P>(u, kq);
+      const bool in = q_ < M && kc < t;
+      const S v = Qsd[(int64_t)(in ? kc : 0) * M + qc];
+      xn[u] = in ? (F)v : (F)0;
+    }
+    const double o_ = om[qc];
+    on_ = q_ < M ? o_ : 0.0;
+  };
+  int st = blockIdx.x * NW + wave;
+  if (st < nst) load(st);
+  for (; st < nst; st += stride) {
     const int q = st * 16 + l16;
     const bool rin = q < M;
-    const double o = rin ? om[q] : 0.0;
+    const double o = on_;
     const F op = (F)(o >= 0.0 ? o : 0.0), on = (F)(o < 0.0 ? o : 0.0);
     F xv[KS], xm[KS], xp[KS];
 #pragma unroll
     for (int u = 0; u < KS; ++u) {
-      const int kc = sub_col<P>(u, kq);
-      xv[u] = (rin && u < kst && kc < t) ? (F)Qsd[(int64_t)kc * M + q] : (F)0;
+      xv[u] = xn[u];
       xm[u] = xv[u] * op;
       xp[u] = xv[u] * on;
     }
+    if (st + stride < nst) load(st + stride);
     Acc acc[NCB];
     zero_prod<P>(acc, NCB);
-    prod_acc<P, NCB, KS>(acc, Pf, xv, kst);
-    prod_acc<P, NCB, KS>(acc, Pf + bstride, xm, kst);
-    prod_acc<P, NCB, KS>(acc, Pf + 2 * bstride, xp, kst);
+    prod_acc<P, NCB, KS>(acc, Pf, xv);
+    prod_acc<P, NCB, KS>(acc, Pf + bstride, xm);
+    prod_acc<P, NCB, KS>(acc, Pf + 2 * bstride, xp);
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) {
 #pragma unroll
@@ -659,13 +761,13 @@ __global__ __launch_bounds__(NTHR) void k_lstep(Dev d, int axis, int sd0, int ks
 // formed from one product U [S | S m], whose last column is K[p].m.  Leaves
 // the partial Gram of K1 (r columns).
 // ----------------------------------------------------------------------------
-template <class S, int P, int NCB>
+template <class S, int P, int NCB, int KSP>
 __global__ __launch_bounds__(NTHR) void k_coll_kstep(Dev d, int sd0) {
   using F = typename Prec<P>::F;
   using Acc = typename Prec<P>::Acc;
   constexpr int LD = strip_ld<NCB>();
   constexpr int NB = NCB * (NCB + 1) / 2;
-  constexpr int KSP = P == 2 ? 8 : 6;  // sub-steps covering the largest stored rank
+  // KSP: sub-steps covering the stored-rank capacity
   const int s = sd0 + blockIdx.y;
   const int r = d.rank[s];
   const int N = d.N, R = d.R;
@@ -703,24 +805,42 @@ __global__ __launch_bounds__(NTHR) void k_coll_kstep(Dev d, int sd0) {
   const double* Qs = d.Qsrc + (int64_t)s * N;
   S* K1 = (S*)d.K1 + (int64_t)s * N * d.T;
   const double dt = d.dt, iW = 1.0 / d.W;
-  const int ksr = live_sub<P>(r);
   const int src_lane = l16 + 16 * out_kq<P>(r);  // lane holding column r of this row
   dbl4 g[NB];
   zero_acc<NB>(g);
   const int nst = ceil_div(N, 16);
-  for (int st = blockIdx.x * NW + wave; st < nst; st += gridDim.x * NW) {
+  const int stride = gridDim.x * NW;
+  F xn[KSP];
+  double ctn = 0.0, csn = 0.0, qn = 0.0;
+  auto load = [&](int st_) {
+    const int p_ = st_ * 16 + l16;
+    const bool rin_ = p_ < N;
+    const int pc = rin_ ? p_ : N - 1;
+#pragma unroll
+    for (int u = 0; u < KSP; ++u) {
+      const int kc = sub_col<P>(u, kq);
+      const bool in = rin_ && kc < r;
+      const double v = Us[(int64_t)(in ? kc : 0) * N + pc];
+      xn[u] = in ? (F)v : (F)0;
+    }
+    const double a = ct[pc], b = cs[pc], c = Qs[pc];
+    ctn = rin_ ? a : 0.0;
+    csn = rin_ ? b : 0.0;
+    qn = rin_ ? c : 0.0;
+  };
+  int st = blockIdx.x * NW + wave;
+  if (st < nst) load(st);
+  for (; st < nst; st += stride) {
     const int p = st * 16 + l16;
     const bool rin = p < N;
     F xv[KSP];
 #pragma unroll
-    for (int u = 0; u < KSP; ++u) {
-      const int kc = sub_col<P>(u, kq);
-      xv[u] = (rin && kc < r) ? (F)Us[(int64_t)kc * N + p] : (F)0;
-    }
-    const double ctp = rin ? ct[p] : 0.0, csp = rin ? cs[p] : 0.0, qp = rin ? Qs[p] : 0.0;
+    for (int u = 0; u < KSP; ++u) xv[u] = xn[u];
+    const double ctp = ctn, csp = csn, qp = qn;
+    if (st + stride < nst) load(st + stride);
     Acc acc[NCB];
     zero_prod<P>(acc, NCB);
-    prod_acc<P, NCB, KSP>(acc, Bf, xv, ksr);
+    prod_acc<P, NCB, KSP>(acc, Bf, xv);
     double kmv = 0.0;
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb)
@@ -775,17 +895,32 @@ __global__ __launch_bounds__(NTHR) void k_coll_reduce(Dev d, int sd0) {
   dbl4 acc[NACC];
   zero_acc<NACC>(acc);
   const int nst = ceil_div(N, 16);
-  for (int st = blockIdx.x * NW + wave; st < nst; st += gridDim.x * NW) {
-    const int p = st * 16 + l16;
-    const bool rin = p < N;
-    double xv[KS];
+  const int stride = gridDim.x * NW;
+  double xn[KS];
+  double wn = 0.0;
+  auto load = [&](int st_) {
+    const int p_ = st_ * 16 + l16;
+    const bool rin_ = p_ < N;
+    const int pc = rin_ ? p_ : N - 1;
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
       const int c = 4 * ks + kq;
-      xv[ks] = (rin && c < r) ? Ug[(int64_t)c * N + p] : 0.0;
+      const bool in = rin_ && c < r;
+      const double v = Ug[(int64_t)(in ? c : 0) * N + pc];
+      xn[ks] = in ? v : 0.0;
     }
-    double wsrc = 0.0;
-    if (rin) wsrc = kq == 0 ? cs[p] : (kq == 1 ? ct[p] : (kq == 2 ? Qg[p] : 0.0));
+    const double* src = kq == 0 ? cs : (kq == 1 ? ct : Qg);
+    const double w_ = src[pc];
+    wn = (rin_ && kq < 3) ? w_ : 0.0;
+  };
+  int st = blockIdx.x * NW + wave;
+  if (st < nst) load(st);
+  for (; st < nst; st += stride) {
+    double xv[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) xv[ks] = xn[ks];
+    const double wsrc = wn;
+    if (st + stride < nst) load(st + stride);
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) Us[l16 * LD + 4 * ks + kq] = xv[ks];
     if (kq < 3) wv[kq * 16 + l16] = wsrc;
@@ -837,13 +972,12 @@ __global__ __launch_bounds__(NTHR) void k_coll_reduce(Dev d, int sd0) {
 //   AL[q,:] = sqrt(w_q) (V[q,:] P + crow),  P = S2^T (I - dt Gt),
 //   crow = dt ((S2 m)^T Gs / W + q^T).  Leaves the partial Gram of AL.
 // ----------------------------------------------------------------------------
-template <class S, int P, int NCB>
+template <class S, int P, int NCB, int KSP>
 __global__ __launch_bounds__(NTHR) void k_coll_lstep(Dev d, int sd0) {
   using F = typename Prec<P>::F;
   using Acc = typename Prec<P>::Acc;
   constexpr int LD = strip_ld<NCB>();
   constexpr int NB = NCB * (NCB + 1) / 2;
-  constexpr int KSP = P == 2 ? 8 : 6;
   const int s = sd0 + blockIdx.y;
   const int r = d.rank[s];
   const int M = d.M, R = d.R;
@@ -863,23 +997,38 @@ __global__ __launch_bounds__(NTHR) void k_coll_lstep(Dev d, int sd0) {
   __syncthreads();
   const double* Vs = d.V + (int64_t)s * M * R;
   S* ALs = (S*)d.AL + (int64_t)s * M * d.T;
-  const int ksr = live_sub<P>(r);
   dbl4 g[NB];
   zero_acc<NB>(g);
   const int nst = ceil_div(M, 16);
-  for (int st = blockIdx.x * NW + wave; st < nst; st += gridDim.x * NW) {
+  const int stride = gridDim.x * NW;
+  F xn[KSP];
+  double swn = 0.0;
+  auto load = [&](int st_) {
+    const int q_ = st_ * 16 + l16;
+    const int qc = q_ < M ? q_ : M - 1;
+#pragma unroll
+    for (int u = 0; u < KSP; ++u) {
+      const int kc = sub_col<P>(u, kq);
+      const bool in = q_ < M && kc < r;
+      const double v = Vs[(int64_t)(in ? kc : 0) * M + qc];
+      xn[u] = in ? (F)v : (F)0;
+    }
+    const double w_ = d.sw[qc];
+    swn = q_ < M ? w_ : 0.0;
+  };
+  int st = blockIdx.x * NW + wave;
+  if (st < nst) load(st);
+  for (; st < nst; st += stride) {
     const int q = st * 16 + l16;
     const bool rin = q < M;
     F xv[KSP];
 #pragma unroll
-    for (int u = 0; u < KSP; ++u) {
-      const int kc = sub_col<P>(u, kq);
-      xv[u] = (rin && kc < r) ? (F)Vs[(int64_t)kc * M + q] : (F)0;
-    }
-    const double swq = rin ? d.sw[q] : 0.0;
+    for (int u = 0; u < KSP; ++u) xv[u] = xn[u];
+    const double swq = swn;
+    if (st + stride < nst) load(st + stride);
     Acc acc[NCB];
     zero_prod<P>(acc, NCB);
-    prod_acc<P, NCB, KSP>(acc, Bf, xv, ksr);
+    prod_acc<P, NCB, KSP>(acc, Bf, xv);
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) {
 #pragma unroll
@@ -964,12 +1113,6 @@ void with_ncb(int ncb, Fn f) {
   }
 }
 
-// 4-column sub-steps in buckets of 16 columns (4, 8, 12, 16)
-template <class Fn>
-void with_ks(int kcap, Fn f) {
-  with_ncb(ncb_of(kcap), [&](auto nk) { f(ic<4 * decltype(nk)::value>{}); });
-}
-
 // storage type and product precision of a launch: FP64 mode stores and
 // computes in FP64; the mixed modes store in FP32 and compute products in
 // FP32 or split BF16, except QR products (exact), which stay FP64
@@ -988,7 +1131,25 @@ void with_store(int prec, Fn f) {
 }
 
 // sub-steps of the coefficient fragments for a capacity of n rows
-int sub_steps(int P, int n) { return P == 2 ? 4 * ceil_div(n, 16) : ceil_div(n, 4); }
+int sub_steps(int P, int n) { return P == 2 ? 8 * ceil_div(n, 32) : ceil_div(n, 4); }
+
+// compile-time sub-step count covering the stored-rank capacity (at most
+// CAPR = 21 ranks: six 4-column sub-steps, or one 32-column BF16 group)
+template <int P, class Fn>
+void with_ksp(int rcap, Fn f) {
+  if constexpr (P == 2) {
+    f(ic<8>{});
+  } else {
+    switch (ceil_div(rcap, 4)) {
+      case 1: f(ic<1>{}); break;
+      case 2: f(ic<2>{}); break;
+      case 3: f(ic<3>{}); break;
+      case 4: f(ic<4>{}); break;
+      case 5: f(ic<5>{}); break;
+      default: f(ic<6>{}); break;
+    }
+  }
+}
 
 constexpr size_t D8 = sizeof(double);
 
@@ -1026,8 +1187,8 @@ void launch_gemm(const Dev& d, int axis, int sd0, int nsd, const void* X, bool x
     constexpr int P = decltype(pc)::value;
     with_ncb(ncb_of(dim_cap(d, ndim)), [&](auto c) {
       constexpr int NC = decltype(c)::value;
-      with_ks(dim_cap(d, kdim), [&](auto k) {
-        constexpr int KS = decltype(k)::value;
+      with_ncb(ncb_of(dim_cap(d, kdim)), [&](auto k) {
+        constexpr int KS = sub_cap<P>(decltype(k)::value);
         const size_t lds = strip_bytes<P, NC>(KS * NC * 64);
         hipLaunchKernelGGL((k_gemm<SI, SO, P, NC, KS>), dim3(nwg, nsd), dim3(NTHR), lds, st, d, axis, sd0, X, xsd,
                            rows, kdim, ndim, boff, bld, Y, ysd, rowscale, gram ? 1 : 0, fill_off);
@@ -1065,12 +1226,13 @@ void launch_kstep(const Dev& d, int axis, int sd0, int nsd, hipStream_t st) {
   with_prec(d.prec, false, [&](auto ts, auto pc) {
     using S = typename decltype(ts)::type;
     constexpr int P = decltype(pc)::value;
-    const int ksr = sub_steps(P, d.R);
-    with_ncb(ncb_of(d.T), [&](auto c) {
-      constexpr int NC = decltype(c)::value;
-      const size_t lds = strip_bytes<P, NC>(7 * ksr * NC * 64);
-      hipLaunchKernelGGL((k_kstep<S, P, NC>), dim3(d.nwgN, nsd), dim3(NTHR), lds,
-                         st, d, axis, sd0, ksr);
+    with_ksp<P>(d.R, [&](auto kp) {
+      constexpr int KSP = decltype(kp)::value;
+      with_ncb(ncb_of(d.T), [&](auto c) {
+        constexpr int NC = decltype(c)::value;
+        const size_t lds = strip_bytes<P, NC>(7 * KSP * NC * 64);
+        hipLaunchKernelGGL((k_kstep<S, P, NC, KSP>), dim3(d.nwgN, nsd), dim3(NTHR), lds, st, d, axis, sd0);
+      });
     });
   });
 }
@@ -1097,13 +1259,11 @@ void launch_lstep(const Dev& d, int axis, int sd0, int nsd, hipStream_t st) {
   with_prec(d.prec, false, [&](auto ts, auto pc) {
     using S = typename decltype(ts)::type;
     constexpr int P = decltype(pc)::value;
-    const int kst = sub_steps(P, d.T);
     with_ncb(ncb_of(d.T), [&](auto c) {
       constexpr int NC = decltype(c)::value;
-      constexpr int KS = 4 * NC;
-      const size_t lds = strip_bytes<P, NC>(3 * kst * NC * 64);
-      hipLaunchKernelGGL((k_lstep<S, P, NC, KS>), dim3(d.nwgM, nsd), dim3(NTHR), lds,
-                         st, d, axis, sd0, kst);
+      constexpr int KS = sub_cap<P>(NC);
+      const size_t lds = strip_bytes<P, NC>(3 * KS * NC * 64);
+      hipLaunchKernelGGL((k_lstep<S, P, NC, KS>), dim3(d.nwgM, nsd), dim3(NTHR), lds, st, d, axis, sd0);
     });
   });
 }
@@ -1113,10 +1273,13 @@ void launch_coll_kstep(const Dev& d, int sd0, int nsd, hipStream_t st) {
     using S = typename decltype(ts)::type;
     constexpr int P = decltype(pc)::value;
     // one column beyond the rank carries K.m
-    with_ncb(ncb_of(d.R + 1), [&](auto c) {
-      constexpr int NC = decltype(c)::value;
-      if constexpr (NC <= 2)
-        hipLaunchKernelGGL((k_coll_kstep<S, P, NC>), dim3(d.nwgN, nsd), dim3(NTHR), 0, st, d, sd0);
+    with_ksp<P>(d.R, [&](auto kp) {
+      constexpr int KSP = decltype(kp)::value;
+      with_ncb(ncb_of(d.R + 1), [&](auto c) {
+        constexpr int NC = decltype(c)::value;
+        if constexpr (NC <= 2)
+          hipLaunchKernelGGL((k_coll_kstep<S, P, NC, KSP>), dim3(d.nwgN, nsd), dim3(NTHR), 0, st, d, sd0);
+      });
     });
   });
 }
@@ -1133,10 +1296,13 @@ void launch_coll_lstep(const Dev& d, int sd0, int nsd, hipStream_t st) {
   with_prec(d.prec, false, [&](auto ts, auto pc) {
     using S = typename decltype(ts)::type;
     constexpr int P = decltype(pc)::value;
-    with_ncb(ncb_of(d.R), [&](auto c) {
-      constexpr int NC = decltype(c)::value;
-      if constexpr (NC <= 2)
-        hipLaunchKernelGGL((k_coll_lstep<S, P, NC>), dim3(d.nwgM, nsd), dim3(NTHR), 0, st, d, sd0);
+    with_ksp<P>(d.R, [&](auto kp) {
+      constexpr int KSP = decltype(kp)::value;
+      with_ncb(ncb_of(d.R), [&](auto c) {
+        constexpr int NC = decltype(c)::value;
+        if constexpr (NC <= 2)
+          hipLaunchKernelGGL((k_coll_lstep<S, P, NC, KSP>), dim3(d.nwgM, nsd), dim3(NTHR), 0, st, d, sd0);
+      });
     });
   });
 }
@@ -1144,6 +1310,40 @@ void launch_coll_lstep(const Dev& d, int sd0, int nsd, hipStream_t st) {
 void launch_moments(const Dev& d, hipStream_t st) {
   const int nb = (d.N + NTHR - 1) / NTHR;
   hipLaunchKernelGGL(k_moments, dim3(nb < 16 ? nb : 16, d.nsub), dim3(NTHR), 0, st, d);
+}
+
+// Workgroups per compute unit that stay resident for the heaviest
+// tall-skinny kernels of this configuration (the smallest over the K-step,
+// its QR products, the spatial reductions and the L-step).
+int ts_resident_wgs(const Dev& d) {
+  int occ = 1 << 20;
+  auto take = [&](const void* fn, size_t lds) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, NTHR, lds) == hipSuccess && nb > 0)
+      occ = std::min(occ, nb);
+  };
+  with_prec(d.prec, false, [&](auto ts, auto pc) {
+    using S = typename decltype(ts)::type;
+    constexpr int P = decltype(pc)::value;
+    with_ncb(ncb_of(d.T), [&](auto c) {
+      constexpr int NC = decltype(c)::value;
+      constexpr int KS = 4 * NC;
+      with_ksp<P>(d.R, [&](auto kp) {
+        constexpr int KSP = decltype(kp)::value;
+        take((const void*)k_kstep<S, P, NC, KSP>, strip_bytes<P, NC>(7 * KSP * NC * 64));
+      });
+      take((const void*)k_lstep<S, P, NC, sub_cap<P>(NC)>, strip_bytes<P, NC>(3 * sub_cap<P>(NC) * NC * 64));
+      take((const void*)k_gemm<S, S, 0, NC, KS>, strip_bytes<0, NC>(KS * NC * 64));
+      with_ncb(ncb_of(d.R), [&](auto cr) {
+        constexpr int NR = decltype(cr)::value;
+        constexpr int NACC = NC * NC + 2 * NC * NR;
+        if constexpr (NR <= 2)
+          take((const void*)k_spatial_reduce<S, NC, NR>,
+               D8 * std::max<size_t>(NW * 2 * 16 * (strip_ld<NC>() + strip_ld<NR>()), (size_t)2 * NACC * 256));
+      });
+    });
+  });
+  return occ == (1 << 20) ? 1 : occ;
 }
 
 // Allow the dynamically sized kernels the whole LDS of a compute unit.
@@ -1157,11 +1357,12 @@ void init_kernels() {
           with_ncb(nc, [&](auto c) {
             constexpr int NC = decltype(c)::value;
             allow_lds((const void*)k_aug_form<double, 0, NC, 4 * NC>);
-            allow_lds((const void*)k_kstep<W, P, NC>);
-            allow_lds((const void*)k_lstep<W, P, NC, 4 * NC>);
+            for (int rc = 1; rc <= CAPR; rc += 4)
+              with_ksp<P>(rc, [&](auto kp) { allow_lds((const void*)k_kstep<W, P, NC, decltype(kp)::value>); });
+            allow_lds((const void*)k_lstep<W, P, NC, sub_cap<P>(NC)>);
             for (int kc = 1; kc <= 4; ++kc) {
               with_ncb(kc, [&](auto k) {
-                constexpr int KS = 4 * decltype(k)::value;
+                constexpr int KS = sub_cap<P>(decltype(k)::value);
                 allow_lds((const void*)k_gemm<double, double, P, NC, KS>);
                 allow_lds((const void*)k_gemm<double, W, P, NC, KS>);
                 allow_lds((const void*)k_gemm<W, double, P, NC, KS>);

@@ -43,16 +43,17 @@ __device__ inline void zero_acc(dbl4* a) {
 // P = 1: FP32 operands, FP32 accumulation (v_mfma_f32_16x16x4f32); P = 2:
 // split BF16, x = hi + lo with hi = bf16(x), lo = bf16(x - hi), and
 // a b ~ hi_a hi_b + hi_a lo_b + lo_a hi_b accumulated in FP32
-// (v_mfma_f32_16x16x16bf16_1k, three per product).  The FP32-accumulating
-// instructions hold D[4 (l/16) + v][l % 16] in component v of lane l (the
-// FP64 one D[4 v + l/16][l % 16]).
-// Operands are handled in 4-column sub-steps u: lane (l16 = l % 16,
-// kq = l / 16) holds column sub_col(u, kq) of its row; for P = 2 four
-// consecutive sub-steps form one 16-column instruction whose lane operand is
-// columns 16 g + 4 kq + 0..3.
+// (v_mfma_f32_16x16x32_bf16, three per product; its operand in lane l is
+// A[l % 16][8 (l/16) + i], i < 8).  The FP32-accumulating instructions hold
+// D[4 (l/16) + v][l % 16] in component v of lane l (the FP64 one
+// D[4 v + l/16][l % 16]).
+// Operands are handled in sub-steps u: lane (l16 = l % 16, kq = l / 16)
+// holds column sub_col(u, kq) of its row.  For P = 0, 1 a sub-step is one
+// 4-column instruction; for P = 2 eight consecutive sub-steps form one
+// 32-column instruction whose lane operand is columns 32 g + 8 kq + 0..7.
 // ---------------------------------------------------------------------------
 typedef float flt4 __attribute__((ext_vector_type(4)));
-typedef short shrt4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 template <int P> struct Prec;
 template <> struct Prec<0> { using F = double; using Acc = dbl4; };
@@ -61,7 +62,7 @@ template <> struct Prec<2> { using F = float; using Acc = flt4; };
 
 template <int P>
 __device__ __forceinline__ int sub_col(int u, int kq) {
-  return P == 2 ? 16 * (u >> 2) + 4 * kq + (u & 3) : 4 * u + kq;
+  return P == 2 ? 32 * (u >> 3) + 8 * kq + (u & 7) : 4 * u + kq;
 }
 
 // column of the product held in component v of column block cb
@@ -78,8 +79,14 @@ __device__ __forceinline__ int out_kq(int c) {
 
 // sub-steps actually executed for k live columns (whole instructions)
 template <int P>
-__device__ __forceinline__ int live_sub(int k) {
-  return P == 2 ? 4 * ((k + 15) / 16) : (k + 3) / 4;
+__host__ __device__ constexpr int live_sub(int k) {
+  return P == 2 ? 8 * ((k + 31) / 32) : (k + 3) / 4;
+}
+
+// sub-steps of an operand array covering a capacity of 16 nc columns
+template <int P>
+constexpr int sub_cap(int nc) {
+  return P == 2 ? 8 * ((nc + 1) / 2) : 4 * nc;
 }
 
 template <int P>
@@ -87,59 +94,57 @@ __device__ __forceinline__ void zero_prod(typename Prec<P>::Acc* a, int n) {
   for (int i = 0; i < n; ++i) a[i] = typename Prec<P>::Acc{0, 0, 0, 0};
 }
 
-__device__ __forceinline__ void bf16_split(float x, short& hi, short& lo) {
-  const __bf16 h = (__bf16)x;
-  const __bf16 l = (__bf16)(x - (float)h);
-  hi = __builtin_bit_cast(short, h);
-  lo = __builtin_bit_cast(short, l);
+__device__ __forceinline__ void bf16_split(float x, __bf16& hi, __bf16& lo) {
+  hi = (__bf16)x;
+  lo = (__bf16)(x - (float)hi);
 }
 
-// acc[cb] += sum over sub-steps u < nlive of (fragment u, block cb) x xv[u].
+// acc[cb] += sum over the NSUB sub-steps u of (fragment u, block cb) x xv[u].
 // frag[(u * NCB + cb) * 64 + lane] is the coefficient operand B[sub_col(u,
-// kq)][16 cb + l16]; xv[u] the row's value in column sub_col(u, kq).
+// kq)][16 cb + l16]; xv[u] the row's value in column sub_col(u, kq).  All
+// NSUB sub-steps are issued (operands beyond the live columns are zero): a
+// branch between matrix-core instructions would make the compiler copy the
+// accumulators between register files around it.
 template <int P, int NCB, int NSUB>
 __device__ __forceinline__ void prod_acc(typename Prec<P>::Acc* acc, const typename Prec<P>::F* frag,
-                                         const typename Prec<P>::F* xv, int nlive) {
+                                         const typename Prec<P>::F* xv) {
   const int lane = threadIdx.x & 63;
   if constexpr (P == 2) {
+    static_assert(NSUB % 8 == 0, "split-BF16 operands come in whole 32-column instructions");
 #pragma unroll
-    for (int g = 0; g < NSUB / 4; ++g) {
-      if (4 * g < nlive) {
-        shrt4 xh, xl;
+    for (int g = 0; g < NSUB / 8; ++g) {
+      bf16x8 xh, xl;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          short h, l;
-          bf16_split(xv[4 * g + i], h, l);
-          xh[i] = h;
-          xl[i] = l;
+      for (int i = 0; i < 8; ++i) {
+        __bf16 h, l;
+        bf16_split(xv[8 * g + i], h, l);
+        xh[i] = h;
+        xl[i] = l;
+      }
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) {
+        bf16x8 ah, al;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          __bf16 h, l;
+          bf16_split(frag[((8 * g + i) * NCB + cb) * 64 + lane], h, l);
+          ah[i] = h;
+          al[i] = l;
         }
-#pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) {
-          shrt4 ah, al;
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            short h, l;
-            bf16_split(frag[((4 * g + i) * NCB + cb) * 64 + lane], h, l);
-            ah[i] = h;
-            al[i] = l;
-          }
-          acc[cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, xh, acc[cb], 0, 0, 0);
-          acc[cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, xl, acc[cb], 0, 0, 0);
-          acc[cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, xh, acc[cb], 0, 0, 0);
-        }
+        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, xh, acc[cb], 0, 0, 0);
+        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, xl, acc[cb], 0, 0, 0);
+        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, xh, acc[cb], 0, 0, 0);
       }
     }
   } else {
 #pragma unroll
     for (int u = 0; u < NSUB; ++u) {
-      if (u < nlive) {
 #pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) {
-          if constexpr (P == 0)
-            acc[cb] = mfma64(frag[(u * NCB + cb) * 64 + lane], xv[u], acc[cb]);
-          else
-            acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(frag[(u * NCB + cb) * 64 + lane], xv[u], acc[cb], 0, 0, 0);
-        }
+      for (int cb = 0; cb < NCB; ++cb) {
+        if constexpr (P == 0)
+          acc[cb] = mfma64(frag[(u * NCB + cb) * 64 + lane], xv[u], acc[cb]);
+        else
+          acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(frag[(u * NCB + cb) * 64 + lane], xv[u], acc[cb], 0, 0, 0);
       }
     }
   }
