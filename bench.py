@@ -115,6 +115,67 @@ def measured_traffic(kernel, workload, precision):
     return None
 
 
+def precision_comparison(pkg, wl, base_prec, base_ms, steps, warmup, flux_steps=2):
+    """The metric's third part: the mixed-precision paths against the FP64
+    path on the same workload -- time per step (graph mode, timed like the
+    main line) and the scalar-flux error after flux_steps steps relative to
+    the FP64 path's flux (which the parity tests hold within 1e-10 of the
+    oracle).  A mixed path counts as equally accurate when its error is at
+    most 1e-4 (the stated bar for mixed paths)."""
+    import numpy as np
+    import torch
+    names = {"fp64": pkg.DD_PREC_FP64, "fp32": pkg.DD_PREC_MIXED_FP32, "bf16": pkg.DD_PREC_MIXED_BF16}
+
+    def flux(prec):
+        eng = pkg.DDDLRA(wl, exec_mode=pkg.DD_EXEC_BATCHED_GRAPH, precision=names[prec])
+        eng.step(flux_steps)
+        rho = eng.moments()
+        eng.close()
+        return rho
+
+    def timed(prec):
+        stream = torch.cuda.Stream()
+        eng = pkg.DDDLRA(wl, exec_mode=pkg.DD_EXEC_BATCHED_GRAPH, precision=names[prec], stream=stream)
+        eng.step(warmup)
+        eng.sync()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        eng.step(steps)
+        e1.record(stream)
+        stream.synchronize()
+        eng.close()
+        return e0.elapsed_time(e1) / steps
+
+    ref = flux("fp64")
+    ms = {"fp64": base_ms if base_prec == "fp64" else timed("fp64")}
+    out = {"reference": f"FP64 path, scalar flux after {flux_steps} steps", "fp64_ms_per_step": round(ms["fp64"], 4)}
+    for prec in ("fp32", "bf16"):
+        m = base_ms if base_prec == prec else timed(prec)
+        err = float(np.linalg.norm(flux(prec) - ref) / np.linalg.norm(ref))
+        out[prec] = {"ms_per_step": round(m, 4), "speedup_vs_fp64": round(ms["fp64"] / m, 4),
+                     "flux_rel_err": err, "equal_accuracy": bool(err <= 1e-4)}
+    return out
+
+
+def measured_mfma_busy(kernel, workload, precision):
+    """Matrix-core busy fraction of `kernel` from the counter summaries under
+    profiles/ (lines 'mfma kernel=.. workload=.. precision=.. busy=..
+    source=..'), or None when there is none for the current kernel sources."""
+    import glob
+    import re
+    src = ts_source_hash()
+    pat = re.compile(r"\s*mfma kernel=(.+?) workload=(\S+) precision=(\S+) busy=(\S+) source=(\S+)")
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        with open(path) as f:
+            for line in f:
+                m = pat.match(line)
+                if m and m.group(1) == kernel and m.group(2) == workload and m.group(3) == precision \
+                        and m.group(5) == src:
+                    return float(m.group(4))
+    return None
+
+
 def cpu_baseline(wl, budget_s=12.0, max_steps=30):
     """The FP64 oracle on the host cores, on the first steps of the same
     workload until about budget_s seconds of work."""
@@ -152,8 +213,9 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"])
     ap.add_argument("--profile-steps", type=int, default=3)
     ap.add_argument("--profile-repeat", type=int, default=10,
-                    help="back-to-back launches per timed tall-skinny phase")
+                    help="repetitions (replayed as one graph) per timed tall-skinny phase")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-precision-compare", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
@@ -227,7 +289,8 @@ def main():
     traffic = measured_traffic(dom, args.config, args.precision)
     roof.update({"kernel": dom, "avg_us": round(ts[dom]["avg_us"], 3),
                  "algorithmic_bytes_per_launch": int(nbytes), "algorithmic_flops_per_launch": int(nflops),
-                 "traffic": None if traffic is None else int(traffic)})
+                 "traffic": None if traffic is None else int(traffic),
+                 "mfma_busy": measured_mfma_busy(dom, args.config, args.precision)})
 
     out = {
         "metric": "subdomain-cell·angle·rank updates/s per step",
@@ -251,6 +314,9 @@ def main():
         "kernels": {k: {"avg_us": round(v["avg_us"], 2), "share": round(v["share"], 4), "launches": v["launches"]}
                     for k, v in sorted(kern.items(), key=lambda kv: -kv[1]["share"])},
     }
+    if not args.no_precision_compare:
+        print("[bench] mixed precision against FP64", file=sys.stderr, flush=True)
+        out["mixed_vs_fp64"] = precision_comparison(pkg, wl, args.precision, ms_per_step, args.steps, args.warmup)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl)

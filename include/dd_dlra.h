@@ -154,9 +154,10 @@ dd_status dd_dlra_force_ranks(dd_dlra_handle h, const int32_t* t, const int32_t*
  * PER_SUBDOMAIN and BATCHED, and dd_dlra_stage) are bracketed by hipEvent
  * pairs on the handle's stream, one pair per phase.  With enable = k > 1 the
  * tall-skinny phases whose launch leaves the same result when repeated are
- * launched k times inside their pair and count k launches (their average
- * then carries little dispatch overhead); the factors are unchanged by the
- * repetition.  enable < 0 returns DD_EINVAL.  dd_dlra_kernel_stats
+ * captured k times into a graph that is replayed inside their pair, and the
+ * measured time is divided by k (the per-launch average then carries little
+ * dispatch overhead, and the totals stay those of one pass); the factors are
+ * unchanged by the repetition.  enable < 0 returns DD_EINVAL.  dd_dlra_kernel_stats
  * synchronises, folds the pending pairs into per-kernel totals and copies
  * out launches[k] and total_ms[k] for k < n (any pointer may be NULL);
  * *n_kernels receives the number of kernel kinds.  dd_dlra_kernel_name

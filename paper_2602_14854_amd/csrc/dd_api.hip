@@ -33,7 +33,10 @@ struct dd_dlra_s {
   bool capturing = false;
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
-  std::vector<std::pair<int, int>> pending;  // (kernel kind, launches) per event pair
+  struct Pending {
+    int kind, launches, reps;  // launches inside the event pair, of which reps repeat the phase
+  };
+  std::vector<Pending> pending;
   std::vector<int64_t> k_launch;
   std::vector<double> k_ms;
 };
@@ -429,7 +432,7 @@ void phase(dd_dlra_handle h, int kind, F&& f) {
   }
   if (timed && e0 && e1) {
     (void)hipEventRecord(e1, h->stream);
-    h->pending.push_back({kind, launches});
+    h->pending.push_back({kind, launches, reps});
   }
 }
 
@@ -771,8 +774,10 @@ dd_status dd_dlra_kernel_stats(dd_dlra_handle h, int32_t n, int64_t* launches, d
   for (size_t i = 0; i < h->pending.size(); ++i) {
     float ms = 0.0f;
     HIPCHK(hipEventElapsedTime(&ms, h->ev_pool[2 * i], h->ev_pool[2 * i + 1]));
-    h->k_ms[h->pending[i].first] += ms;
-    h->k_launch[h->pending[i].first] += h->pending[i].second;
+    // a repeated phase counts once: its time and launches per repetition
+    const auto& pd = h->pending[i];
+    h->k_ms[pd.kind] += ms / pd.reps;
+    h->k_launch[pd.kind] += pd.launches / pd.reps;
   }
   h->pending.clear();
   h->ev_used = 0;
