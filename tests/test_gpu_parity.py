@@ -304,6 +304,41 @@ def test_wc_C2_full_size_two_steps():
     assert er < STRICT and es < STRICT
 
 
+_C3 = {}
+
+
+def _wc_c3_oracle():
+    """One oracle step of the well-conditioned C3 workload (448 x 448 cells,
+    7 x 7 subdomains of 64 x 64, 1024 directions, rank 20), computed once."""
+    if not _C3:
+        wl = wk.make_workload("wc-C3")
+        ref, prob = oracle_steps(wl, 1)
+        _C3.update(wl=wl, ref=ref, prob=prob, rho=dd.moments(ref, prob))
+    return _C3
+
+
+def test_wc_C3_full_size_one_step():
+    say("case: wc-C3 full size (448x448, 49 subdomains, M=1024, rank 20), 1 step (graph mode)")
+    c = _wc_c3_oracle()
+    e = engine(c["wl"])
+    e.step(1)
+    rho = e.moments()
+    got = e.state()
+    e.close()
+    es, er = dd.state_rel_error(got, c["ref"], c["prob"]), rho_err(rho, c["rho"])
+    say(f"  wc-C3: state err {es:.3e}, scalar-flux err {er:.3e}")
+    assert er < STRICT and es < STRICT
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_mixed_precision_wc_C3(prec):
+    say(f"case: wc-C3 full size, 1 step, mixed {prec}")
+    c = _wc_c3_oracle()
+    err = rho_err(_mixed_run(c["wl"], 1, prec), c["rho"])
+    say(f"  wc-C3 mixed {prec}: scalar-flux err {err:.3e}")
+    assert err < MIXED
+
+
 def _oracle_spread(wl, nsteps):
     """Largest scalar-flux distance between the oracle and two mathematically
     identical variants of it: the columns of the augmentation matrix in
