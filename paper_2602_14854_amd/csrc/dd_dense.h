@@ -3,6 +3,8 @@
 // triangular inverse, products, sorting and the tail rank rule.
 #pragma once
 
+#include <type_traits>
+
 #include "dd_internal.h"
 #include "dd_mfma.h"
 
@@ -73,47 +75,92 @@ __device__ __forceinline__ void mm(double* C, int ldc, const double* A, int lda,
   __syncthreads();
 }
 
-// dst (rows x cols, ldd) = sum over ngp workgroup partials of the block at
-// offset off (leading dimension lds) -- fixed order over the partials, so
-// deterministic.  Each thread takes eight entries and fetches four partials
-// of each before adding, keeping 32 loads in flight (addresses of absent
-// entries or partials are clamped to a valid one and the value dropped).
+// One block of a partial-sum reduction: dst (rows x cols, ldd) = scale *
+// the sum over the workgroup partials of the block at offset off (leading
+// dimension lds).
+struct PartBlock {
+  int off, lds, rows, cols;
+  double* dst;
+  int ldd;
+  double scale;
+};
+
+// Sum up to NBLK blocks of ngp workgroup partials in one pass over the
+// concatenated entries, in a fixed order over the partials (deterministic).
+// Each thread takes E entries and U partials of each per round, E U = 32
+// loads in flight, with U chosen from ngp so that few rounds remain;
+// addresses of absent entries or partials are clamped to a valid one and the
+// value dropped.  Blocks with rows * cols == 0 are skipped.  All threads call.
+template <int NBLK>
+__device__ __forceinline__ void sum_partials_blocks(const Dev& d, int s, int ngp, const PartBlock (&blk)[NBLK]) {
+  const double* gp = gpart_of(d, s);
+  int start[NBLK + 1];
+  start[0] = 0;
+#pragma unroll
+  for (int b = 0; b < NBLK; ++b) start[b + 1] = start[b] + blk[b].rows * blk[b].cols;
+  const int total = start[NBLK];
+  auto run = [&](auto eu) {
+    constexpr int E = decltype(eu)::value, U = 32 / E;
+    for (int base = threadIdx.x; base < total; base += E * NTHR) {
+      int src[E], bi[E], loc[E];
+      double acc[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int idx = base + e * NTHR;
+        bi[e] = -1;
+        loc[e] = -1;
+        src[e] = 0;
+        // static block indices only (a runtime index into blk would put it
+        // in scratch memory)
+#pragma unroll
+        for (int q = 0; q < NBLK; ++q) {
+          if (idx >= start[q] && idx < start[q + 1]) {
+            const int li = idx - start[q];
+            bi[e] = q;
+            loc[e] = li;
+            src[e] = blk[q].off + (li % blk[q].rows) + (li / blk[q].rows) * blk[q].lds;
+          }
+        }
+        acc[e] = 0.0;
+      }
+      for (int w0 = 0; w0 < ngp; w0 += U) {
+        double v[E][U];
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int w = w0 + u < ngp ? w0 + u : 0;
+            v[e][u] = gp[(int64_t)w * d.gpTile + src[e]];
+          }
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+#pragma unroll
+          for (int u = 0; u < U; ++u)
+            if (w0 + u < ngp) acc[e] += v[e][u];
+      }
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+#pragma unroll
+        for (int q = 0; q < NBLK; ++q) {
+          if (bi[e] == q)
+            blk[q].dst[(loc[e] % blk[q].rows) + (loc[e] / blk[q].rows) * blk[q].ldd] = blk[q].scale * acc[e];
+        }
+      }
+    }
+  };
+  using std::integral_constant;
+  if (ngp > 8) run(integral_constant<int, 2>{});
+  else if (ngp > 4) run(integral_constant<int, 4>{});
+  else run(integral_constant<int, 8>{});
+  __syncthreads();
+}
+
+// dst (rows x cols, ldd) = scale * sum over ngp workgroup partials of the
+// block at offset off (leading dimension lds).
 __device__ __forceinline__ void sum_partials(const Dev& d, int s, int ngp, int off, int lds, int rows, int cols, double* dst,
                              int ldd, double scale) {
-  constexpr int E = 8, U = 4;
-  const double* gp = gpart_of(d, s) + off;
-  const int n = rows * cols;
-  for (int base = threadIdx.x; base < n; base += E * NTHR) {
-    int src[E];
-    double acc[E];
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const int idx = base + e * NTHR;
-      src[e] = idx < n ? (idx % rows) + (idx / rows) * lds : 0;
-      acc[e] = 0.0;
-    }
-    for (int w0 = 0; w0 < ngp; w0 += U) {
-      double v[E][U];
-#pragma unroll
-      for (int e = 0; e < E; ++e)
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int w = w0 + u < ngp ? w0 + u : 0;
-          v[e][u] = gp[(int64_t)w * d.gpTile + src[e]];
-        }
-#pragma unroll
-      for (int e = 0; e < E; ++e)
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-          if (w0 + u < ngp) acc[e] += v[e][u];
-    }
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const int idx = base + e * NTHR;
-      if (idx < n) dst[(idx % rows) + (idx / rows) * ldd] = scale * acc[e];
-    }
-  }
-  __syncthreads();
+  const PartBlock blk[1] = {{off, lds, rows, cols, dst, ldd, scale}};
+  sum_partials_blocks<1>(d, s, ngp, blk);
 }
 
 // sum over aligned groups of G lanes (G = 1, 2, 4, 8 or 16) with DPP

@@ -179,12 +179,12 @@ __global__ __launch_bounds__(NTHR) void s_adv_prep(Dev d, int axis, int sd0) {
   __shared__ double P[LDA * CAP];
   __shared__ double lam[CAP];
   const int pT = 0, pC = R * T, pEp = pC + T * T, pEn = pEp + T * T, pOlo = pEn + T * T, pOhi = pOlo + R * T;
-  sum_partials(d, s, d.nwgM, pT, R, r, t, sm + d.oTm, R, 1.0);
-  sum_partials(d, s, d.nwgM, pEp, t, t, t, sm + d.oEp, T, 1.0);
-  sum_partials(d, s, d.nwgM, pEn, t, t, t, sm + d.oEn, T, 1.0);
-  if (rl > 0) sum_partials(d, s, d.nwgM, pOlo, R, rl, t, sm + d.oOlo, R, 1.0);
-  if (rh > 0) sum_partials(d, s, d.nwgM, pOhi, R, rh, t, sm + d.oOhi, R, 1.0);
-  sum_partials(d, s, d.nwgM, pC, t, t, t, A, LDA, 1.0);
+  {
+    const PartBlock blk[6] = {{pT, R, r, t, sm + d.oTm, R, 1.0},      {pEp, t, t, t, sm + d.oEp, T, 1.0},
+                              {pEn, t, t, t, sm + d.oEn, T, 1.0},     {pOlo, R, rl, t, sm + d.oOlo, R, 1.0},
+                              {pOhi, R, rh, t, sm + d.oOhi, R, 1.0},  {pC, t, t, t, A, LDA, 1.0}};
+    sum_partials_blocks<6>(d, s, d.nwgM, blk);
+  }
   // symmetrise C (the partial sums are symmetric up to rounding order)
   for (int idx = threadIdx.x; idx < t * t; idx += NTHR) {
     const int i = idx % t, j = idx / t;
@@ -276,18 +276,22 @@ __global__ __launch_bounds__(NTHR) void s_adv_sstep(Dev d, int axis, int sd0) {
   const double ih = 1.0 / d.h;
   double* Gm = sm + d.oGm;
   double* Gp = sm + d.oGp;
-  sum_partials(d, s, d.nwgN, 0, t, t, t, Gm, T, ih);
-  sum_partials(d, s, d.nwgN, T * T, t, t, t, Gp, T, ih);
-  // face products, summed from the spatial-reduction partials
+  // Galerkin matrices and the face products, summed from the
+  // spatial-reduction partials in one pass
   double* Xlo = sm + d.oW1;  // t x r
   double* Xhi = sm + d.oW2;  // t x r
   double* Xln = sm + d.oW3;  // t x rl
   double* Xhn = sm + d.oW4;  // t x rh
   const int oX = 2 * T * T;
-  sum_partials(d, s, d.nwgN, oX, T, t, r, Xlo, T, 1.0);
-  sum_partials(d, s, d.nwgN, oX + T * R, T, t, r, Xhi, T, 1.0);
-  if (rl > 0) sum_partials(d, s, d.nwgN, oX + 2 * T * R, T, t, rl, Xln, T, 1.0);
-  if (rh > 0) sum_partials(d, s, d.nwgN, oX + 3 * T * R, T, t, rh, Xhn, T, 1.0);
+  {
+    const PartBlock blk[6] = {{0, t, t, t, Gm, T, ih},
+                              {T * T, t, t, t, Gp, T, ih},
+                              {oX, T, t, r, Xlo, T, 1.0},
+                              {oX + T * R, T, t, r, Xhi, T, 1.0},
+                              {oX + 2 * T * R, T, t, rl, Xln, T, 1.0},
+                              {oX + 3 * T * R, T, t, rh, Xhn, T, 1.0}};
+    sum_partials_blocks<6>(d, s, d.nwgN, blk);
+  }
   double* W5 = sm + d.oW5;
   double* W6 = sm + d.oW6;
   double* BKlo = sm + d.oBKlo;
@@ -525,9 +529,10 @@ __global__ __launch_bounds__(NTHR) void s_coll_sstep(Dev d, int sd0) {
   double* sm = small_of(d, s);
   __shared__ double Gs[L * L], Gt[L * L], S1[L * L], S2[L * L];
   __shared__ double qv[L], mv[L], v1[L], v2[L], v3[L];
-  sum_partials(d, s, d.nwgN, 0, R, r, r, Gs, L, 1.0);
-  sum_partials(d, s, d.nwgN, R * R, R, r, r, Gt, L, 1.0);
-  sum_partials(d, s, d.nwgN, 2 * R * R, R, r, 1, qv, L, 1.0);
+  {
+    const PartBlock blk[3] = {{0, R, r, r, Gs, L, 1.0}, {R * R, R, r, r, Gt, L, 1.0}, {2 * R * R, R, r, 1, qv, L, 1.0}};
+    sum_partials_blocks<3>(d, s, d.nwgN, blk);
+  }
   for (int idx = threadIdx.x; idx < r * r; idx += NTHR) {
     const int i = idx % r, j = idx / r;
     S1[i + j * L] = d.h * sm[d.oRacc + i + j * T];
