@@ -460,6 +460,19 @@ def moments(state, prob):
     return rho
 
 
+def currents(state, prob):
+    """First angular moments, the current density j = int Omega f dOmega:
+    jx = sum_q w_q Omega_x,q f_q and jy likewise, assembled on the global
+    grid [ny*nx] (the flux of the transported quantity through a face)."""
+    jx = np.zeros(prob.nx * prob.ny)
+    jy = np.zeros(prob.nx * prob.ny)
+    for s, (U, S, V) in enumerate(state):
+        cells = prob.local_cells(s)
+        jx[cells] = U @ (S @ (V.T @ (prob.w * prob.omega[0])))
+        jy[cells] = U @ (S @ (V.T @ (prob.w * prob.omega[1])))
+    return jx, jy
+
+
 def assemble(state, prob):
     """The full distribution F (global cells x directions); for tiny grids."""
     F = np.zeros((prob.nx * prob.ny, prob.M))

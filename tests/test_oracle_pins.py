@@ -411,3 +411,38 @@ def test_mirror_symmetry_low_rank(axis):
     Fb = dd.assemble(b, prob).reshape(ny, nx, -1)
     Fa_m = (Fa[:, ::-1, :] if axis == 0 else Fa[::-1, :, :])[:, :, perm]
     assert rel(Fb, Fa_m) < 1e-12
+
+
+# ----------------------------------------------------------------------------
+# observables: current density (first angular moments)
+# ----------------------------------------------------------------------------
+
+def test_currents_equal_assembled_distribution():
+    """jx, jy from the factors equal the quadrature of Omega f over the
+    assembled full distribution (brute force on the C1 grid)."""
+    wl = wk.make_workload("wc-C1")
+    prob = dd.Problem(wl)
+    state = dd.initial_state(wl)
+    F = dd.assemble(state, prob)
+    jx, jy = dd.currents(state, prob)
+    assert rel(jx, F @ (prob.w * prob.omega[0])) < 1e-13
+    assert rel(jy, F @ (prob.w * prob.omega[1])) < 1e-13
+    assert rel(dd.moments(state, prob), F @ prob.w) < 1e-13
+
+
+def test_isotropic_distribution_carries_no_current():
+    """An isotropic f(x, Omega) = g(x) has zero current: the direction set is
+    symmetric, so sum_q w_q Omega_q = 0."""
+    wl = wk.make_workload("wc-C1")
+    prob = dd.Problem(wl)
+    rng = np.random.default_rng(11)
+    state = []
+    for s in range(prob.n_sub):
+        g = rng.standard_normal(prob.N)
+        U = (g / (prob.h * np.linalg.norm(g)))[:, None]          # h^2 U^T U = 1
+        V = np.full((prob.M, 1), 1.0 / math.sqrt(prob.W))        # V^T W V = 1
+        state.append((U, np.array([[2.0]]), V))
+    rho = dd.moments(state, prob)
+    jx, jy = dd.currents(state, prob)
+    scale = np.linalg.norm(rho)
+    assert np.linalg.norm(jx) < 1e-14 * scale and np.linalg.norm(jy) < 1e-14 * scale
