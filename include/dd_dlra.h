@@ -133,10 +133,14 @@ dd_status dd_dlra_get_ranks(dd_dlra_handle h, int32_t* r, int32_t* t_max, int64_
 dd_status dd_dlra_get_factors(dd_dlra_handle h, int32_t sd, int32_t cap, int32_t* r,
                               double* U, double* S, double* V);
 
-/* Scalar flux rho = sum_q w_q f_q on the global grid [ny*nx] (Section 2).
- * dst_is_device != 0: rho is a device pointer written asynchronously on the
- * handle's stream; otherwise a host pointer (synchronises). */
-dd_status dd_dlra_moments(dd_dlra_handle h, double* rho, int32_t dst_is_device);
+/* Angular moments of f on the global grid [ny*nx], cell p = iy*nx + ix:
+ * scalar flux rho = sum_q w_q f_q (Section 2) and, when jx and jy are not
+ * NULL, the current density jx = sum_q w_q Omega_x,q f_q, jy likewise (the
+ * first moments, computed from the factors as U (S (V^T (w Omega))).  rho is
+ * required; jx and jy must both be given or both be NULL (else DD_EINVAL).
+ * dst_is_device != 0: the pointers are device memory written asynchronously
+ * on the handle's stream; otherwise host memory (the call synchronises). */
+dd_status dd_dlra_moments(dd_dlra_handle h, double* rho, double* jx, double* jy, int32_t dst_is_device);
 
 /* Replace the factors of every subdomain (same layouts as dd_dlra_create);
  * used for checkpoint/restart.  Synchronises. */

@@ -77,7 +77,7 @@ def load_library():
     lib.dd_dlra_stage.argtypes = [vp, ctypes.c_int32]
     lib.dd_dlra_get_ranks.argtypes = [vp, _IP, _IP, ctypes.POINTER(ctypes.c_int64)]
     lib.dd_dlra_get_factors.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, _IP, _DP, _DP, _DP]
-    lib.dd_dlra_moments.argtypes = [vp, _DP, ctypes.c_int32]
+    lib.dd_dlra_moments.argtypes = [vp, _DP, _DP, _DP, ctypes.c_int32]
     lib.dd_dlra_set_factors.argtypes = [vp, _IP, ctypes.POINTER(_DP), ctypes.POINTER(_DP), ctypes.POINTER(_DP)]
     lib.dd_dlra_force_ranks.argtypes = [vp, _IP, _IP]
     lib.dd_dlra_profile.argtypes = [vp, ctypes.c_int32]
@@ -228,11 +228,17 @@ class DDDLRA:
     def moments(self, out=None):
         """Scalar flux on the global grid; out may be a CUDA torch tensor."""
         if out is not None:
-            self._check(self.lib.dd_dlra_moments(self.h, ctypes.cast(out.data_ptr(), _DP), 1))
+            self._check(self.lib.dd_dlra_moments(self.h, ctypes.cast(out.data_ptr(), _DP), None, None, 1))
             return out
         rho = np.zeros(self.nx * self.ny)
-        self._check(self.lib.dd_dlra_moments(self.h, _dp(rho), 0))
+        self._check(self.lib.dd_dlra_moments(self.h, _dp(rho), None, None, 0))
         return rho
+
+    def currents(self):
+        """(rho, jx, jy): scalar flux and current density on the global grid."""
+        rho, jx, jy = (np.zeros(self.nx * self.ny) for _ in range(3))
+        self._check(self.lib.dd_dlra_moments(self.h, _dp(rho), _dp(jx), _dp(jy), 0))
+        return rho, jx, jy
 
     def set_factors(self, U: Sequence, S: Sequence, V: Sequence):
         keep, pu, ps, pv = _factor_ptrs(U, S, V)

@@ -202,7 +202,7 @@ Layout make_layout(const dd_dlra_config* c) {
   L.oAL2 = seg(ns * L.M * T * es);
   L.oGP = seg(ns * L.gpStride * d8);
   L.oSM = seg(ns * L.smallStride * d8);
-  L.oRho = seg((size_t)c->nx * c->ny * d8);
+  L.oRho = seg(3 * (size_t)c->nx * c->ny * d8);
   L.oIn = seg(5 * (size_t)L.M * d8);
   L.oCs = seg(ns * L.N * d8);
   L.oCt = seg(ns * L.N * d8);
@@ -852,16 +852,24 @@ dd_status dd_dlra_get_factors(dd_dlra_handle h, int32_t sd, int32_t cap, int32_t
   return check_flags(h);
 }
 
-dd_status dd_dlra_moments(dd_dlra_handle h, double* rho, int32_t dst_is_device) {
-  if (!h || !rho) return DD_EINVAL;
-  const Dev& d = h->d;
-  dd::launch_moments(d, h->stream);
-  const size_t n = (size_t)h->cfg.nx * h->cfg.ny;
-  if (dst_is_device) {
-    HIPCHK(hipMemcpyAsync(rho, d.rho, n * 8, hipMemcpyDeviceToDevice, h->stream));
-    return DD_OK;
+dd_status dd_dlra_moments(dd_dlra_handle h, double* rho, double* jx, double* jy, int32_t dst_is_device) {
+  if (!h) return DD_EINVAL;
+  if (!rho) {
+    h->err = "rho is NULL";
+    return DD_EINVAL;
   }
-  HIPCHK(hipMemcpyAsync(rho, d.rho, n * 8, hipMemcpyDeviceToHost, h->stream));
+  if ((jx == nullptr) != (jy == nullptr)) {
+    h->err = "jx and jy must both be given or both be NULL";
+    return DD_EINVAL;
+  }
+  const Dev& d = h->d;
+  const int nmom = jx ? 3 : 1;
+  dd::launch_moments(d, nmom, h->stream);
+  const size_t n = (size_t)h->cfg.nx * h->cfg.ny;
+  double* dst[3] = {rho, jx, jy};
+  const hipMemcpyKind kind = dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  for (int m = 0; m < nmom; ++m) HIPCHK(hipMemcpyAsync(dst[m], d.rho + m * n, n * 8, kind, h->stream));
+  if (dst_is_device) return DD_OK;
   HIPCHK(hipStreamSynchronize(h->stream));
   return check_flags(h);
 }

@@ -61,7 +61,7 @@ struct Dev {
   void* AL2;               // [nsub][T][M]
   double* gpart;           // [nsub][gpStride]
   double* small;           // [nsub][smallStride]
-  double* rho;             // [ny*nx]
+  double* rho;             // [3][ny*nx]: rho, jx, jy
   // inputs
   double* omx;             // [M]
   double* omy;             // [M]
@@ -163,7 +163,7 @@ void launch_lstep(const Dev& d, int axis, int sd0, int nsd, hipStream_t st);
 void launch_coll_kstep(const Dev& d, int sd0, int nsd, hipStream_t st);
 void launch_coll_reduce(const Dev& d, int sd0, int nsd, hipStream_t st);
 void launch_coll_lstep(const Dev& d, int sd0, int nsd, hipStream_t st);
-void launch_moments(const Dev& d, hipStream_t st);
+void launch_moments(const Dev& d, int nmom, hipStream_t st);
 // small (one workgroup per subdomain) kernels
 void launch_aug_svd(const Dev& d, int axis, int sd0, int nsd, hipStream_t st);
 void launch_chol(const Dev& d, int axis, int sd0, int nsd, int ndim, int rows, int ngp, bool shift,

@@ -1048,42 +1048,49 @@ __global__ __launch_bounds__(NTHR) void k_coll_lstep(Dev d, int sd0) {
 }
 
 // ----------------------------------------------------------------------------
-// Scalar flux rho = U (S (V^T w)) on the global grid (Section 2).
+// Angular moments on the global grid: scalar flux rho = U (S (V^T w)) (Section
+// 2) and current density jx = U (S (V^T (w Omega_x))), jy likewise; written to
+// d.rho, d.rho + nx ny and d.rho + 2 nx ny.  nmom = 1 forms rho only.
 // ----------------------------------------------------------------------------
-__global__ __launch_bounds__(NTHR) void k_moments(Dev d) {
+__global__ __launch_bounds__(NTHR) void k_moments(Dev d, int nmom) {
   const int s = blockIdx.y;
   const int r = d.rank[s];
   const int N = d.N, M = d.M, R = d.R;
-  __shared__ double mv[CAPR];
-  __shared__ double smv[CAPR];
-  __shared__ double red[NTHR];
+  __shared__ double mv[3 * CAPR];
+  __shared__ double smv[3 * CAPR];
   const double* Vs = d.V + (int64_t)s * M * R;
-  for (int a = 0; a < r; ++a) {
+  // (V^T (w Omega_m))_a for a < r, m < nmom (Omega_0 = 1), one per thread in
+  // a fixed order over the directions
+  for (int idx = threadIdx.x; idx < nmom * r; idx += NTHR) {
+    const int a = idx % r, m = idx / r;
+    const double* om = m == 1 ? d.omx : d.omy;
     double acc = 0.0;
-    for (int q = threadIdx.x; q < M; q += NTHR) acc = fma(Vs[(int64_t)a * M + q], d.w[q], acc);
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int off = NTHR / 2; off > 0; off >>= 1) {
-      if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-      __syncthreads();
+    for (int q = 0; q < M; ++q) {
+      const double wq = m == 0 ? d.w[q] : d.w[q] * om[q];
+      acc = fma(Vs[(int64_t)a * M + q], wq, acc);
     }
-    if (threadIdx.x == 0) mv[a] = red[0];
-    __syncthreads();
+    mv[m * CAPR + a] = acc;
   }
+  __syncthreads();
   const double* Sg = d.S + (int64_t)s * R * R;
-  for (int a = threadIdx.x; a < r; a += NTHR) {
+  for (int idx = threadIdx.x; idx < nmom * r; idx += NTHR) {
+    const int a = idx % r, m = idx / r;
     double acc = 0.0;
-    for (int b = 0; b < r; ++b) acc = fma(Sg[a + b * R], mv[b], acc);
-    smv[a] = acc;
+    for (int b = 0; b < r; ++b) acc = fma(Sg[a + b * R], mv[m * CAPR + b], acc);
+    smv[m * CAPR + a] = acc;
   }
   __syncthreads();
   const double* Us = d.U + (int64_t)s * N * R;
   const int sx = s % d.px, sy = s / d.px;
+  const int64_t plane = (int64_t)d.nx * d.lny * d.py;  // cells of the global grid
   for (int p = blockIdx.x * NTHR + threadIdx.x; p < N; p += gridDim.x * NTHR) {
-    double acc = 0.0;
-    for (int a = 0; a < r; ++a) acc = fma(Us[(int64_t)a * N + p], smv[a], acc);
     const int ix = p % d.lnx, iy = p / d.lnx;
-    d.rho[(int64_t)(sy * d.lny + iy) * d.nx + sx * d.lnx + ix] = acc;
+    const int64_t g = (int64_t)(sy * d.lny + iy) * d.nx + sx * d.lnx + ix;
+    for (int m = 0; m < nmom; ++m) {
+      double acc = 0.0;
+      for (int a = 0; a < r; ++a) acc = fma(Us[(int64_t)a * N + p], smv[m * CAPR + a], acc);
+      d.rho[m * plane + g] = acc;
+    }
   }
 }
 
@@ -1307,9 +1314,9 @@ void launch_coll_lstep(const Dev& d, int sd0, int nsd, hipStream_t st) {
   });
 }
 
-void launch_moments(const Dev& d, hipStream_t st) {
+void launch_moments(const Dev& d, int nmom, hipStream_t st) {
   const int nb = (d.N + NTHR - 1) / NTHR;
-  hipLaunchKernelGGL(k_moments, dim3(nb < 16 ? nb : 16, d.nsub), dim3(NTHR), 0, st, d);
+  hipLaunchKernelGGL(k_moments, dim3(nb < 16 ? nb : 16, d.nsub), dim3(NTHR), 0, st, d, nmom);
 }
 
 // Workgroups per compute unit that stay resident for the heaviest

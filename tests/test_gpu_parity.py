@@ -132,11 +132,28 @@ def test_steps_wc_C1():
     e = engine(wl)
     e.step(3)
     rho = e.moments()
+    rho2, jx, jy = e.currents()
     got = e.state()
     e.close()
     es, er = dd.state_rel_error(got, ref, prob), rho_err(rho, dd.moments(ref, prob))
-    say(f"  wc-C1: state err {es:.3e}, scalar-flux err {er:.3e}")
-    assert es < STRICT and er < STRICT
+    jxr, jyr = dd.currents(ref, prob)
+    ej = max(rho_err(jx, jxr), rho_err(jy, jyr))
+    say(f"  wc-C1: state err {es:.3e}, scalar-flux err {er:.3e}, current err {ej:.3e}")
+    assert es < STRICT and er < STRICT and ej < STRICT
+    assert np.array_equal(rho, rho2)
+
+
+def test_moments_arguments_validated():
+    import ctypes
+    wl = wk.make_workload("wc-C1")
+    e = engine(wl)
+    rho = np.zeros(wl.nx * wl.ny)
+    p = rho.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    try:
+        assert e.lib.dd_dlra_moments(e.h, p, p, None, 0) == -1   # jx without jy
+        assert e.lib.dd_dlra_moments(e.h, None, None, None, 0) == -1
+    finally:
+        e.close()
 
 
 def test_ragged_shapes_adaptive_uneven_ranks():
