@@ -197,10 +197,20 @@ def cpu_baseline(wl, budget_s=12.0, max_steps=30):
         st = dd.dd_step(st, prob)
         n += 1
     el = time.perf_counter() - t0
+    model = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": upd / el, "unit": "updates/s", "cores": threads or os.cpu_count(),
             "kind": "oracle",
             "sample": f"steps 2..{n + 1} of the same workload ({n} timed steps, {el:.1f} s, "
-                      f"{el / n * 1e3:.0f} ms/step), NumPy/LAPACK FP64"}
+                      f"{el / n * 1e3:.0f} ms/step), NumPy/LAPACK FP64 on {model}, "
+                      f"{os.cpu_count()} logical CPUs visible"}
 
 
 def main():
@@ -286,11 +296,16 @@ def main():
     else:
         roof = {"bound": "mfma", "achieved": round(tfl, 3), "peak": peak_tf, "unit": "TFLOP/s",
                 "frac": round(tfl / peak_tf, 4)}
+    # attainable-roofline fraction: the time the kernel would take at the
+    # binding roof (HBM for its bytes or the matrix cores for its flops)
+    # over the time it takes
+    attainable = max(nbytes / (HBM_PEAK_GBS * 1e9), nflops / (peak_tf * 1e12)) / avg_s
     traffic = measured_traffic(dom, args.config, args.precision)
     roof.update({"kernel": dom, "avg_us": round(ts[dom]["avg_us"], 3),
                  "algorithmic_bytes_per_launch": int(nbytes), "algorithmic_flops_per_launch": int(nflops),
                  "traffic": None if traffic is None else int(traffic),
-                 "mfma_busy": measured_mfma_busy(dom, args.config, args.precision)})
+                 "mfma_busy": measured_mfma_busy(dom, args.config, args.precision),
+                 "attainable_frac": round(attainable, 4)})
 
     out = {
         "metric": "subdomain-cell·angle·rank updates/s per step",
@@ -310,6 +325,7 @@ def main():
                    "rank": int(wl.r_fixed), "r_int_max": int(wl.r_int_max), "exec_mode": args.mode,
                    "precision": args.precision,
                    "max_intermediate_rank": int(np.max(tmax)), "updates_per_step": updates},
+        "phase_space_points_per_s": float(wl.n_sub * wl.N * wl.M) / (ms_per_step * 1e-3),
         "roofline": roof,
         "kernels": {k: {"avg_us": round(v["avg_us"], 2), "share": round(v["share"], 4), "launches": v["launches"]}
                     for k, v in sorted(kern.items(), key=lambda kv: -kv[1]["share"])},
