@@ -115,7 +115,7 @@ def measured_traffic(kernel, workload, precision):
     return None
 
 
-def precision_comparison(pkg, wl, base_prec, base_ms, steps, warmup, flux_steps=2):
+def precision_comparison(pkg, wl, base_prec, base_ms, steps, warmup, tune, flux_steps=2):
     """The metric's third part: the mixed-precision paths against the FP64
     path on the same workload -- time per step (graph mode, timed like the
     main line) and the scalar-flux error after flux_steps steps relative to
@@ -136,6 +136,7 @@ def precision_comparison(pkg, wl, base_prec, base_ms, steps, warmup, flux_steps=
     def timed(prec):
         stream = torch.cuda.Stream()
         eng = pkg.DDDLRA(wl, exec_mode=pkg.DD_EXEC_BATCHED_GRAPH, precision=names[prec], stream=stream)
+        tune(eng)
         eng.step(warmup)
         eng.sync()
         e0 = torch.cuda.Event(enable_timing=True)
@@ -226,6 +227,9 @@ def main():
                     help="repetitions (replayed as one graph) per timed tall-skinny phase")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision-compare", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--wg-per-subdomain", type=int, default=0,
+                    help="fix the tall-skinny workgroups per subdomain instead of autotuning")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
@@ -248,6 +252,14 @@ def main():
     eng = pkg.DDDLRA(wl, exec_mode=mode, precision=prec, stream=stream)
     print(f"[bench] workload {args.config}: {wl.nx}x{wl.ny} cells, {wl.px}x{wl.py} subdomains, "
           f"M={wl.M}, rank {wl.r_fixed}, mode {args.mode}, precision {args.precision}", file=sys.stderr, flush=True)
+    wg_choice, tune_ms = None, None
+    if args.wg_per_subdomain:
+        eng.set_tiling(args.wg_per_subdomain)
+        wg_choice = args.wg_per_subdomain
+    elif not args.no_autotune:
+        wg_choice, tune_ms = eng.autotune(3)
+        print(f"[bench] autotune: {wg_choice} workgroups per subdomain ({tune_ms:.3f} ms/step)",
+              file=sys.stderr, flush=True)
     eng.step(args.warmup)
     eng.sync()
     r0, _, _ = eng.ranks()
@@ -324,7 +336,8 @@ def main():
                    "subdomains": wl.n_sub, "cells_per_subdomain": wl.N, "directions": wl.M,
                    "rank": int(wl.r_fixed), "r_int_max": int(wl.r_int_max), "exec_mode": args.mode,
                    "precision": args.precision,
-                   "max_intermediate_rank": int(np.max(tmax)), "updates_per_step": updates},
+                   "max_intermediate_rank": int(np.max(tmax)), "updates_per_step": updates,
+                   "wg_per_subdomain": wg_choice},
         "phase_space_points_per_s": float(wl.n_sub * wl.N * wl.M) / (ms_per_step * 1e-3),
         "roofline": roof,
         "kernels": {k: {"avg_us": round(v["avg_us"], 2), "share": round(v["share"], 4), "launches": v["launches"]}
@@ -332,7 +345,13 @@ def main():
     }
     if not args.no_precision_compare:
         print("[bench] mixed precision against FP64", file=sys.stderr, flush=True)
-        out["mixed_vs_fp64"] = precision_comparison(pkg, wl, args.precision, ms_per_step, args.steps, args.warmup)
+        def tune(e):
+            if args.wg_per_subdomain:
+                e.set_tiling(args.wg_per_subdomain)
+            elif not args.no_autotune:
+                e.autotune(3)
+        out["mixed_vs_fp64"] = precision_comparison(pkg, wl, args.precision, ms_per_step, args.steps, args.warmup,
+                                                    tune)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl)

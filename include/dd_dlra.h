@@ -171,6 +171,28 @@ dd_status dd_dlra_kernel_stats(dd_dlra_handle h, int32_t n, int64_t* launches, d
                                int32_t* n_kernels);
 const char* dd_dlra_kernel_name(int32_t k);
 
+/* Autotuner: choose the number of workgroups per subdomain of the
+ * tall-skinny kernels (the decomposition of each subdomain's cells and
+ * directions into row tiles) by timing the live problem.  Candidates are
+ * 1/4, 1/2, 1, 2 and 4 times one round of resident workgroups per subdomain
+ * (clipped to the room reserved for partial sums and to one tile of 64 rows
+ * per workgroup); each runs one warm-up and `steps` timed steps in the
+ * handle's execution mode, and the whole workspace is copied aside before
+ * the trials and restored after each one, so the factors, ranks and flags
+ * are unchanged on return.  The fastest candidate stays in effect (a
+ * captured graph is recaptured at the next step).  *wg_per_subdomain and
+ * *ms_per_step (either may be NULL) receive the choice and its time per
+ * step.  Needs a temporary device allocation of the workspace size
+ * (DD_ENOMEM if it fails); DD_ESTATE while kernel profiling is on; DD_EINVAL
+ * for steps < 1.  Synchronises. */
+dd_status dd_dlra_autotune(dd_dlra_handle h, int32_t steps, int32_t* wg_per_subdomain, double* ms_per_step);
+
+/* Set the workgroups per subdomain of the tall-skinny kernels directly (for
+ * instance a choice of dd_dlra_autotune kept from an earlier run), clipped to
+ * the reserved room and to one 64-row tile per workgroup.  DD_EINVAL for
+ * wg_per_subdomain < 1.  Synchronises; a captured graph is recaptured. */
+dd_status dd_dlra_set_tiling(dd_dlra_handle h, int32_t wg_per_subdomain);
+
 /* Wait for the handle's stream and report latched device errors. */
 dd_status dd_dlra_sync(dd_dlra_handle h);
 

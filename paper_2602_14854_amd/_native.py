@@ -20,7 +20,8 @@ DD_EXEC_PER_SUBDOMAIN, DD_EXEC_BATCHED, DD_EXEC_BATCHED_GRAPH = 0, 1, 2
 
 EXPORTS = (
     "dd_dlra_workspace_size", "dd_dlra_create", "dd_dlra_step", "dd_dlra_stage", "dd_dlra_get_ranks",
-    "dd_dlra_get_factors", "dd_dlra_moments", "dd_dlra_set_factors", "dd_dlra_force_ranks",
+    "dd_dlra_get_factors", "dd_dlra_moments", "dd_dlra_set_factors", "dd_dlra_force_ranks", "dd_dlra_autotune",
+    "dd_dlra_set_tiling",
     "dd_dlra_profile", "dd_dlra_kernel_stats", "dd_dlra_kernel_name",
     "dd_dlra_sync", "dd_dlra_destroy", "dd_dlra_last_error",
 )
@@ -78,6 +79,8 @@ def load_library():
     lib.dd_dlra_get_ranks.argtypes = [vp, _IP, _IP, ctypes.POINTER(ctypes.c_int64)]
     lib.dd_dlra_get_factors.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, _IP, _DP, _DP, _DP]
     lib.dd_dlra_moments.argtypes = [vp, _DP, _DP, _DP, ctypes.c_int32]
+    lib.dd_dlra_autotune.argtypes = [vp, ctypes.c_int32, _IP, _DP]
+    lib.dd_dlra_set_tiling.argtypes = [vp, ctypes.c_int32]
     lib.dd_dlra_set_factors.argtypes = [vp, _IP, ctypes.POINTER(_DP), ctypes.POINTER(_DP), ctypes.POINTER(_DP)]
     lib.dd_dlra_force_ranks.argtypes = [vp, _IP, _IP]
     lib.dd_dlra_profile.argtypes = [vp, ctypes.c_int32]
@@ -233,6 +236,18 @@ class DDDLRA:
         rho = np.zeros(self.nx * self.ny)
         self._check(self.lib.dd_dlra_moments(self.h, _dp(rho), None, None, 0))
         return rho
+
+    def autotune(self, steps: int = 2) -> Tuple[int, float]:
+        """Pick the workgroups per subdomain of the tall-skinny kernels by
+        timing the live problem (state unchanged); returns (choice, ms/step)."""
+        wg = ctypes.c_int32(0)
+        ms = ctypes.c_double(0.0)
+        self._check(self.lib.dd_dlra_autotune(self.h, int(steps), ctypes.byref(wg), ctypes.byref(ms)))
+        return int(wg.value), float(ms.value)
+
+    def set_tiling(self, wg_per_subdomain: int):
+        """Workgroups per subdomain of the tall-skinny kernels."""
+        self._check(self.lib.dd_dlra_set_tiling(self.h, int(wg_per_subdomain)))
 
     def currents(self):
         """(rho, jx, jy): scalar flux and current density on the global grid."""

@@ -741,6 +741,111 @@ dd_status dd_dlra_step(dd_dlra_handle h, int32_t n_steps) {
   return DD_OK;
 }
 
+namespace {
+
+void drop_graph(dd_dlra_handle h) {
+  if (h->gexec) {
+    (void)hipGraphExecDestroy(h->gexec);
+    h->gexec = nullptr;
+  }
+  if (h->graph) {
+    (void)hipGraphDestroy(h->graph);
+    h->graph = nullptr;
+  }
+}
+
+}  // namespace
+
+dd_status dd_dlra_set_tiling(dd_dlra_handle h, int32_t wg_per_subdomain) {
+  if (!h) return DD_EINVAL;
+  if (wg_per_subdomain < 1) {
+    h->err = "wg_per_subdomain must be >= 1";
+    return DD_EINVAL;
+  }
+  Dev& d = h->d;
+  HIPCHK(hipStreamSynchronize(h->stream));
+  const int capN = std::max(1, (int)(d.gpStride / d.gpTile));
+  const int w = std::min((int)wg_per_subdomain, capN);
+  d.nwgN = std::min(w, d.ntN);
+  d.nwgM = std::min(w, d.ntM);
+  drop_graph(h);
+  return DD_OK;
+}
+
+dd_status dd_dlra_autotune(dd_dlra_handle h, int32_t steps, int32_t* wg_per_subdomain, double* ms_per_step) {
+  if (!h) return DD_EINVAL;
+  if (steps < 1) {
+    h->err = "steps must be >= 1";
+    return DD_EINVAL;
+  }
+  if (h->profiling) {
+    h->err = "autotune while kernel profiling is on";
+    return DD_ESTATE;
+  }
+  Dev& d = h->d;
+  HIPCHK(hipStreamSynchronize(h->stream));
+  // the trials run real steps: the whole workspace (state, ranks, flags,
+  // scratch) is kept aside and put back after each trial
+  void* snap = nullptr;
+  if (hipMalloc(&snap, h->ws_bytes) != hipSuccess) {
+    h->err = "hipMalloc of the autotune snapshot failed";
+    return DD_ENOMEM;
+  }
+  auto restore = [&]() { return hipMemcpyAsync(h->ws, snap, h->ws_bytes, hipMemcpyDeviceToDevice, h->stream); };
+  hipError_t e = hipMemcpyAsync(snap, h->ws, h->ws_bytes, hipMemcpyDeviceToDevice, h->stream);
+  int dev = 0, ncu = 0;
+  if (e == hipSuccess) e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  const int capN = std::max(1, (int)(d.gpStride / d.gpTile));
+  const int base = std::max(1, ncu * dd::ts_resident_wgs(d) / d.nsub);
+  std::vector<int> cands;
+  for (int c : {base / 4, base / 2, base, 2 * base, 4 * base}) {
+    const int v = std::max(1, std::min(c, capN));
+    if (std::find(cands.begin(), cands.end(), v) == cands.end()) cands.push_back(v);
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  const int ntN = d.ntN, ntM = d.ntM;
+  int best = -1;
+  float best_ms = 0.0f;
+  for (size_t i = 0; i < cands.size() && e == hipSuccess; ++i) {
+    d.nwgN = std::min(cands[i], ntN);
+    d.nwgM = std::min(cands[i], ntM);
+    drop_graph(h);
+    dd_status st = dd_dlra_step(h, 1);  // warm-up (captures the graph in graph mode)
+    if (st != DD_OK) {
+      e = hipErrorUnknown;
+      break;
+    }
+    e = hipEventRecord(e0, h->stream);
+    if (e == hipSuccess && dd_dlra_step(h, steps) != DD_OK) e = hipErrorUnknown;
+    if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e == hipSuccess) e = restore();
+    if (e == hipSuccess && (best < 0 || ms < best_ms)) {
+      best = cands[i];
+      best_ms = ms;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  (void)hipFree(snap);
+  drop_graph(h);
+  if (e != hipSuccess || best < 0) {
+    h->err = "autotune trial failed";
+    return DD_EHIP;
+  }
+  d.nwgN = std::min(best, ntN);
+  d.nwgM = std::min(best, ntM);
+  if (wg_per_subdomain) *wg_per_subdomain = best;
+  if (ms_per_step) *ms_per_step = best_ms / steps;
+  return DD_OK;
+}
+
 dd_status dd_dlra_stage(dd_dlra_handle h, int32_t stage) {
   if (!h) return DD_EINVAL;
   if (stage < 0 || stage > 2) {
@@ -907,15 +1012,7 @@ dd_status dd_dlra_force_ranks(dd_dlra_handle h, const int32_t* t, const int32_t*
   HIPCHK(hipStreamSynchronize(h->stream));
   HIPCHK(hipMemcpy(h->d.force, f.data(), f.size() * sizeof(int), hipMemcpyHostToDevice));
   h->d.forced = (t || r_out) ? 1 : 0;
-  // a captured graph holds the old kernel arguments
-  if (h->gexec) {
-    (void)hipGraphExecDestroy(h->gexec);
-    h->gexec = nullptr;
-  }
-  if (h->graph) {
-    (void)hipGraphDestroy(h->graph);
-    h->graph = nullptr;
-  }
+  drop_graph(h);  // a captured graph holds the old kernel arguments
   return DD_OK;
 }
 

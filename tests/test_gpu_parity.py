@@ -143,6 +143,24 @@ def test_steps_wc_C1():
     assert np.array_equal(rho, rho2)
 
 
+def test_autotune_keeps_state_and_parity():
+    wl = wk.make_workload("wc-C1")
+    say("case: wc-C1, autotune, then 3 steps")
+    ref, prob = oracle_steps(wl, 3)
+    e = engine(wl)
+    before = e.state()
+    wg, ms = e.autotune(2)
+    after = e.state()
+    say(f"  autotune chose {wg} workgroups per subdomain ({ms:.3f} ms/step)")
+    assert wg >= 1 and ms > 0.0
+    for (u0, s0, v0), (u1, s1, v1) in zip(before, after):
+        assert np.array_equal(u0, u1) and np.array_equal(s0, s1) and np.array_equal(v0, v1)
+    e.step(3)
+    got = e.state()
+    e.close()
+    assert dd.state_rel_error(got, ref, prob) < STRICT
+
+
 def test_moments_arguments_validated():
     import ctypes
     wl = wk.make_workload("wc-C1")
