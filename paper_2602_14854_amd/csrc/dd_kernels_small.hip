@@ -93,7 +93,8 @@ void launch_aug_svd(const Dev& d, int axis, int sd0, int nsd, hipStream_t st) {
 
 // One pass of (shifted, optionally pivoted) Cholesky QR of X = Q R: G = sum
 // of partials (n x n), optional shift 11 (rows n + n (n+1)) u tr(G) (Fukaya
-// et al., shifted CholeskyQR), G[perm, perm] = R^T R, and
+// et al., shifted CholeskyQR), G[perm, perm] = R^T R (R upper triangular, or
+// the symmetric square root when G is within 1e-5 of the identity), and
 //   Rinv slot: P R^{-1} (rows permuted back, scaled by bscale) for the next
 //              tall-skinny product Q = X P R^{-1},
 //   fill slot: the mask of numerically dependent columns of Q,
@@ -120,8 +121,47 @@ __global__ __launch_bounds__(NTHR) void s_chol(Dev d, int axis, int sd0, int ndi
     if (threadIdx.x < n) G[threadIdx.x * (LDA + 1)] += sh;
     __syncthreads();
   }
-  if (pivot) chol_inv_wave<NMAX, true>(d, G, X, n, perm, dep);
-  else chol_inv_wave<NMAX, false>(d, G, X, n, perm, dep);
+  // A Gram within 1e-5 (Frobenius) of the identity -- the last pass of a
+  // Cholesky QR, whose input is already orthonormal up to rounding -- takes
+  // the symmetric factor instead of the triangular one: with E = G - I,
+  //   R = G^(1/2) = I + E/2 - E^2/8,  R^-1 = G^(-1/2) = I - E/2 + 3 E^2/8,
+  // both exact to O(|E|^3) <= 1e-15 and R R^-1 = I + O(E^3); any R with
+  // G = R^T R gives an orthonormal Q = X R^-1 and X = Q R.
+  bool near_identity = false;
+  if (!pivot && !shift) {
+    __shared__ double red[NTHR];
+    double part = 0.0;
+    for (int idx = threadIdx.x; idx < n * n; idx += NTHR) {
+      const int i = idx % n, j = idx / n;
+      const double e = G[i + j * LDA] - (i == j ? 1.0 : 0.0);
+      part = fma(e, e, part);
+    }
+    near_identity = block_sum(part, red) <= 1e-10;
+  }
+  if (near_identity) {
+    __shared__ double E2[LDA * CAP];
+    for (int idx = threadIdx.x; idx < n * n; idx += NTHR) {
+      const int i = idx % n, j = idx / n;
+      X[i + j * LDA] = G[i + j * LDA] - (i == j ? 1.0 : 0.0);  // E
+    }
+    __syncthreads();
+    mm(E2, LDA, X, LDA, false, X, LDA, false, n, n, n, 1.0, 0.0);
+    for (int idx = threadIdx.x; idx < n * n; idx += NTHR) {
+      const int i = idx % n, j = idx / n;
+      const double e = X[i + j * LDA], e2 = E2[i + j * LDA], id = i == j ? 1.0 : 0.0;
+      G[i + j * LDA] = id + 0.5 * e - 0.125 * e2;
+      X[i + j * LDA] = id - 0.5 * e + 0.375 * e2;
+    }
+    for (int k = threadIdx.x; k < n; k += NTHR) {
+      perm[k] = k;
+      dep[k] = 0;
+    }
+    __syncthreads();
+  } else if (pivot) {
+    chol_inv_wave<NMAX, true>(d, G, X, n, perm, dep);
+  } else {
+    chol_inv_wave<NMAX, false>(d, G, X, n, perm, dep);
+  }
   double* sm = small_of(d, s);
   // thread (column c = tid % 64, rows i = tid / 64 mod 4) for the n x n outputs
   const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
