@@ -94,7 +94,7 @@ void launch_aug_svd(const Dev& d, int axis, int sd0, int nsd, hipStream_t st) {
 // One pass of (shifted, optionally pivoted) Cholesky QR of X = Q R: G = sum
 // of partials (n x n), optional shift 11 (rows n + n (n+1)) u tr(G) (Fukaya
 // et al., shifted CholeskyQR), G[perm, perm] = R^T R (R upper triangular, or
-// the symmetric square root when G is within 1e-5 of the identity), and
+// the symmetric square root when G is within 1e-3 of the identity), and
 //   Rinv slot: P R^{-1} (rows permuted back, scaled by bscale) for the next
 //              tall-skinny product Q = X P R^{-1},
 //   fill slot: the mask of numerically dependent columns of Q,
@@ -121,13 +121,16 @@ __global__ __launch_bounds__(NTHR) void s_chol(Dev d, int axis, int sd0, int ndi
     if (threadIdx.x < n) G[threadIdx.x * (LDA + 1)] += sh;
     __syncthreads();
   }
-  // A Gram within 1e-5 (Frobenius) of the identity -- the last pass of a
-  // Cholesky QR, whose input is already orthonormal up to rounding -- takes
-  // the symmetric factor instead of the triangular one: with E = G - I,
-  //   R = G^(1/2) = I + E/2 - E^2/8,  R^-1 = G^(-1/2) = I - E/2 + 3 E^2/8,
-  // both exact to O(|E|^3) <= 1e-15 and R R^-1 = I + O(E^3); any R with
-  // G = R^T R gives an orthonormal Q = X R^-1 and X = Q R.
-  bool near_identity = false;
+  // A Gram within 1e-3 (Frobenius) of the identity -- the last pass of a
+  // Cholesky QR, whose input is already orthonormal up to rounding, or a
+  // pass over a nearly orthonormal input -- takes the symmetric factor
+  // instead of the triangular one: with E = G - I, the binomial series
+  //   R    = G^(1/2)  = I + E/2 - E^2/8 + E^3/16 - 5 E^4/128 ...,
+  //   R^-1 = G^(-1/2) = I - E/2 + 3 E^2/8 - 5 E^3/16 + 35 E^4/128 ...,
+  // cut after E^2 when |E| <= 1e-5 (remainder 0.3 |E|^3 <= 3e-16) and after
+  // E^4 otherwise (remainder 0.25 |E|^5 <= 2.5e-16); R R^-1 = I to the same
+  // order, and any R with G = R^T R gives an orthonormal Q = X R^-1.
+  int near_order = 0;
   if (!pivot && !shift) {
     __shared__ double red[NTHR];
     double part = 0.0;
@@ -136,21 +139,35 @@ __global__ __launch_bounds__(NTHR) void s_chol(Dev d, int axis, int sd0, int ndi
       const double e = G[i + j * LDA] - (i == j ? 1.0 : 0.0);
       part = fma(e, e, part);
     }
-    near_identity = block_sum(part, red) <= 1e-10;
+    const double fro2 = block_sum(part, red);
+    near_order = fro2 <= 1e-10 ? 2 : (fro2 <= 1e-6 ? 4 : 0);
   }
-  if (near_identity) {
+  if (near_order > 0) {
     __shared__ double E2[LDA * CAP];
+    __shared__ double E3[LDA * CAP];
     for (int idx = threadIdx.x; idx < n * n; idx += NTHR) {
       const int i = idx % n, j = idx / n;
       X[i + j * LDA] = G[i + j * LDA] - (i == j ? 1.0 : 0.0);  // E
     }
     __syncthreads();
-    mm(E2, LDA, X, LDA, false, X, LDA, false, n, n, n, 1.0, 0.0);
+    mm(E2, LDA, X, LDA, false, X, LDA, false, n, n, n, 1.0, 0.0);  // E^2
+    const bool o4 = near_order == 4;
+    if (o4) {
+      mm(E3, LDA, X, LDA, false, E2, LDA, false, n, n, n, 1.0, 0.0);  // E^3
+      mm(G, LDA, E2, LDA, false, E2, LDA, false, n, n, n, 1.0, 0.0);  // E^4
+    }
     for (int idx = threadIdx.x; idx < n * n; idx += NTHR) {
       const int i = idx % n, j = idx / n;
-      const double e = X[i + j * LDA], e2 = E2[i + j * LDA], id = i == j ? 1.0 : 0.0;
-      G[i + j * LDA] = id + 0.5 * e - 0.125 * e2;
-      X[i + j * LDA] = id - 0.5 * e + 0.375 * e2;
+      const int o = i + j * LDA;
+      const double e = X[o], e2 = E2[o], id = i == j ? 1.0 : 0.0;
+      double r = id + 0.5 * e - 0.125 * e2, ri = id - 0.5 * e + 0.375 * e2;
+      if (o4) {
+        const double e3 = E3[o], e4 = G[o];
+        r += 0.0625 * e3 - 0.0390625 * e4;
+        ri += -0.3125 * e3 + 0.2734375 * e4;
+      }
+      G[o] = r;
+      X[o] = ri;
     }
     for (int k = threadIdx.x; k < n; k += NTHR) {
       perm[k] = k;
