@@ -253,7 +253,10 @@ __global__ __launch_bounds__(NTHR) void s_adv_prep(Dev d, int axis, int sd0) {
   }
   __syncthreads();
   // eigenvectors of C from the one-sided Jacobi of the positive definite
-  // C + shift I; eigenvalue = column norm - shift
+  // C + shift I, whose eigenvalues lie in [shift - |C|, shift + |C|] (condition
+  // at most 5): the rotated columns are b_j = (lambda_j + shift) p_j, so the
+  // eigenvalue is the column norm - shift and p_j the normalised column (no
+  // accumulation of the rotations is needed)
   __shared__ double red[NTHR];
   double part = 0.0;
   for (int idx = threadIdx.x; idx < t * t; idx += NTHR) {
@@ -263,8 +266,13 @@ __global__ __launch_bounds__(NTHR) void s_adv_prep(Dev d, int axis, int sd0) {
   const double shift = 1.5 * sqrt(block_sum(part, red)) + 1e-300;
   for (int i = threadIdx.x; i < t; i += NTHR) A[i + i * LDA] += shift;
   __syncthreads();
-  jacobi_1s(d, A, t, t, P, 1e-15, 0.0, 40);
+  jacobi_1s(d, A, t, t, nullptr, 1e-15, 0.0, 40);
   col_norms(A, t, t, lam);
+  for (int idx = threadIdx.x; idx < t * t; idx += NTHR) {
+    const int i = idx % t, j = idx / t;
+    P[i + j * LDA] = A[i + j * LDA] / lam[j];
+  }
+  __syncthreads();
   for (int j = threadIdx.x; j < t; j += NTHR) lam[j] -= shift;
   __syncthreads();
   double* Cp = sm + d.oCp;
