@@ -48,15 +48,15 @@ thread_local std::string g_err;
 enum Kind {
   K_AUG_FORM, K_GEMM_QR_A, K_AUG_SVD, K_GEMM_VHAT, K_CHOL, K_GEMM_QR_VHAT, K_ANG_REDUCE,
   K_ADV_PREP, K_KSTEP, K_GEMM_QR_K, K_SPATIAL_REDUCE, K_ADV_SSTEP, K_LSTEP, K_GEMM_QR_L, K_TRUNC,
-  K_GEMM_FINAL_U, K_GEMM_FINAL_V, K_SET_RANK, K_COLL_PREP, K_COLL_KSTEP, K_COLL_REDUCE, K_COLL_SSTEP,
-  K_COLL_LSTEP, K_COLL_FINAL, K_GEMM_QR_KC, K_GEMM_QR_LC, K_COUNT
+  K_GEMM_FINAL_U, K_GEMM_FINAL_V, K_COLL_PREP, K_COLL_KSTEP, K_COLL_REDUCE, K_COLL_SSTEP,
+  K_COLL_LSTEP, K_GEMM_QR_KC, K_GEMM_QR_LC, K_COUNT
 };
 
 const char* const kKindName[K_COUNT] = {
   "k_aug_form", "k_gemm[QR A]", "s_aug_svd", "k_gemm[V-hat=A*Coef]", "s_chol",
   "k_gemm[QR V-hat]", "k_ang_reduce", "s_adv_prep", "k_kstep", "k_gemm[QR K1]", "k_spatial_reduce",
-  "s_adv_sstep", "k_lstep", "k_gemm[QR L1]", "s_trunc", "k_gemm[U=Q*Bu]", "k_gemm[V=QL*Bv]", "s_set_rank",
-  "s_coll_prep", "k_coll_kstep", "k_coll_reduce", "s_coll_sstep", "k_coll_lstep", "s_coll_final",
+  "s_adv_sstep", "k_lstep", "k_gemm[QR L1]", "s_trunc", "k_gemm[U=Q*Bu]", "k_gemm[V=QL*Bv]",
+  "s_coll_prep", "k_coll_kstep", "k_coll_reduce", "s_coll_sstep", "k_coll_lstep",
   "k_gemm[QR K1 collision]", "k_gemm[QR L1 collision]",
 };
 
@@ -439,9 +439,13 @@ void phase(dd_dlra_handle h, int kind, F&& f) {
 // Shifted Cholesky QR with three passes on X (rows x n; n = dim of kind
 // ndim) leaving Q in Y (X is used as scratch); the R factors accumulate in
 // the small workspace.  With final_dst set, the last product writes there
-// instead (stride ysd_final, optional row scale, Rinv scaled by bscale).
+// instead (stride ysd_final, optional row scale, Rinv scaled by bscale);
+// with s_dst set, the last Cholesky pass also stores Racc^T there as the
+// coefficient matrix of each subdomain.  With defer_last, the last product
+// is left to the caller: Q = X Rinv with Rinv in the small workspace.
 void chol_qr3(dd_dlra_handle h, int axis, int ndim, void* X, void* Y, int64_t sdstride, int rows, bool cells,
-              double* final_dst, int64_t final_sd, const double* final_rowscale, double bscale, int gemm_kind) {
+              double* final_dst, int64_t final_sd, const double* final_rowscale, double bscale, int gemm_kind,
+              double* s_dst = nullptr, bool defer_last = false) {
   const Dev& d = h->d;
   hipStream_t st = h->stream;
   const int ngp = cells ? d.nwgN : d.nwgM;
@@ -460,8 +464,9 @@ void chol_qr3(dd_dlra_handle h, int axis, int ndim, void* X, void* Y, int64_t sd
                     true, d.oFill, cells, true, st);
   });
   phase(h, K_CHOL, [&](int s0, int ns) {
-    dd::launch_chol(d, axis, s0, ns, ndim, rows, ngp, false, 2, bscale, false, d.oRinv, d.oRacc, d.T, st);
+    dd::launch_chol(d, axis, s0, ns, ndim, rows, ngp, false, 2, bscale, false, d.oRinv, d.oRacc, d.T, st, s_dst);
   });
+  if (defer_last) return;
   void* dst = final_dst ? (void*)final_dst : Y;
   const int64_t dsd = final_dst ? final_sd : sdstride;
   phase(h, gemm_kind, [&](int s0, int ns) {
@@ -519,18 +524,18 @@ void enqueue_advection(dd_dlra_handle h, int axis) {
   phase(h, K_ADV_SSTEP, [&](int s0, int ns) { dd::launch_adv_sstep(d, axis, s0, ns, st); });
   // steps 4-5: L-step, weighted QR
   phase(h, K_LSTEP, [&](int s0, int ns) { dd::launch_lstep(d, axis, s0, ns, st); });
-  chol_qr3(h, axis, dd::DIM_T, d.AL, d.AL2, sdMT, d.M, false, nullptr, 0, nullptr, 1.0, K_GEMM_QR_L);
+  // (the last product, Q_L = X2 Rinv, is folded into the final V product)
+  chol_qr3(h, axis, dd::DIM_T, d.AL, d.AL2, sdMT, d.M, false, nullptr, 0, nullptr, 1.0, K_GEMM_QR_L, nullptr, true);
   // Algorithm 5: truncation, then rotate the bases into the state
-  phase(h, K_TRUNC, [&](int s0, int ns) { dd::launch_trunc(d, axis, s0, ns, st); });
+  phase(h, K_TRUNC, [&](int s0, int ns) { dd::launch_trunc(d, axis, s0, ns, true, st); });
   phase(h, K_GEMM_FINAL_U, [&](int s0, int ns) {
     dd::launch_gemm(d, axis, s0, ns, d.K2, false, sdNT, d.N, dd::DIM_T, dd::DIM_RNEW, d.oBu, d.T, d.U, true,
                     (int64_t)d.N * d.R, nullptr, false, -1, true, false, st);
   });
   phase(h, K_GEMM_FINAL_V, [&](int s0, int ns) {
-    dd::launch_gemm(d, axis, s0, ns, d.AL2, false, sdMT, d.M, dd::DIM_T, dd::DIM_RNEW, d.oBv, d.T, d.V, true,
-                    (int64_t)d.M * d.R, d.isw, false, -1, false, false, st);
+    dd::launch_gemm(d, axis, s0, ns, d.AL, false, sdMT, d.M, dd::DIM_T, dd::DIM_RNEW, d.oBv, d.T, d.V, true,
+                    (int64_t)d.M * d.R, d.isw, false, -1, false, false, st, /*set_rank=*/true);
   });
-  phase(h, K_SET_RANK, [&](int s0, int ns) { dd::launch_set_rank(d, s0, ns, st); });
 }
 
 void enqueue_collision(dd_dlra_handle h) {
@@ -544,9 +549,9 @@ void enqueue_collision(dd_dlra_handle h) {
   phase(h, K_COLL_REDUCE, [&](int s0, int ns) { dd::launch_coll_reduce(d, s0, ns, st); });
   phase(h, K_COLL_SSTEP, [&](int s0, int ns) { dd::launch_coll_sstep(d, s0, ns, st); });
   phase(h, K_COLL_LSTEP, [&](int s0, int ns) { dd::launch_coll_lstep(d, s0, ns, st); });
-  // weighted QR of L1; V^1 = Q / sqrt(w) straight into the state
-  chol_qr3(h, 0, dd::DIM_R, d.AL, d.AL2, sdMT, d.M, false, d.V, (int64_t)d.M * d.R, d.isw, 1.0, K_GEMM_QR_LC);
-  phase(h, K_COLL_FINAL, [&](int s0, int ns) { dd::launch_coll_final(d, s0, ns, st); });
+  // weighted QR of L1 (Algorithm 3, step 5): V^1 = Q / sqrt(w) straight into
+  // the state, S^1 = RL^T from the last Cholesky pass
+  chol_qr3(h, 0, dd::DIM_R, d.AL, d.AL2, sdMT, d.M, false, d.V, (int64_t)d.M * d.R, d.isw, 1.0, K_GEMM_QR_LC, d.S);
 }
 
 void enqueue_step(dd_dlra_handle h) {

@@ -27,14 +27,16 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 }
 
 
-// C (m x n) = alpha * op(A) op(B) (+ beta C) for m, n, k <= CAP; generic
-// pointers (LDS or global), no aliasing.  On the FP64 matrix cores: the
-// 16 x 16 output tiles are dealt to the wavefronts, and a wavefront issues
-// every operand load of a tile (clamped to valid addresses, out-of-range
-// values replaced by zero) before its first v_mfma_f64_16x16x4f64, so a tile
-// costs one load latency instead of one per k.
-__device__ __forceinline__ void mm(double* C, int ldc, const double* A, int lda, bool ta, const double* B, int ldb,
-                   bool tb, int m, int n, int k, double alpha, double beta) {
+// C (m x n) = alpha * op(A) op(B) + beta D for m, n, k <= CAP, where the
+// addend D (ld ldd) is C itself (mm) or another buffer (mm_add); generic
+// pointers (LDS or global), C aliasing neither A nor B.  On the FP64 matrix
+// cores: the 16 x 16 output tiles are dealt to the wavefronts, and a
+// wavefront issues every operand load of a tile (clamped to valid addresses,
+// out-of-range values replaced by zero) before its first
+// v_mfma_f64_16x16x4f64, so a tile costs one load latency instead of one per k.
+__device__ __forceinline__ void mm_add(double* C, int ldc, const double* A, int lda, bool ta, const double* B, int ldb,
+                                       bool tb, int m, int n, int k, double alpha, double beta, const double* D,
+                                       int ldd) {
   constexpr int KMAX = CAP / 4;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int l16 = lane & 15, kq = lane >> 4;
@@ -67,8 +69,66 @@ __device__ __forceinline__ void mm(double* C, int ldc, const double* A, int lda,
     for (int v = 0; v < 4; ++v) {
       const int ci = i0 + 4 * v + kq, cj = j0 + l16;
       if (ci < m && cj < n) {
-        double* c = C + ci + (int64_t)cj * ldc;
-        *c = (beta == 0.0) ? alpha * acc[v] : fma(alpha, acc[v], beta * *c);
+        const double dv = (beta == 0.0) ? 0.0 : beta * D[ci + (int64_t)cj * ldd];
+        C[ci + (int64_t)cj * ldc] = (beta == 0.0) ? alpha * acc[v] : fma(alpha, acc[v], dv);
+      }
+    }
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ void mm(double* C, int ldc, const double* A, int lda, bool ta, const double* B, int ldb,
+                                   bool tb, int m, int n, int k, double alpha, double beta) {
+  mm_add(C, ldc, A, lda, ta, B, ldb, tb, m, n, k, alpha, beta, C, ldc);
+}
+
+// C = alpha A B + beta D for zero-padded square LDS matrices of order 16 NT
+// (ld LDA) whose result is symmetric (A and B symmetric and commuting, as
+// for polynomials in one symmetric matrix), with B and D symmetric.  Only
+// the tiles on and above the diagonal are formed, and each value is stored
+// at (i, j) and (j, i), so C comes out exactly symmetric: iterations built
+// on it keep exact symmetry, and B can be read along its columns
+// (conflict-free).  C must differ from A, B and D unless beta is 0 (then D
+// may be C).  Each tile runs two accumulator chains (even and odd k steps)
+// to halve the dependent v_mfma_f64_16x16x4f64 sequence.  Entries past the
+// order of the data are zero in A, B and D and stay zero in C.
+template <int NT>
+__device__ __forceinline__ void sym_mm(double* C, const double* A, const double* B, double alpha, double beta,
+                                       const double* D) {
+  constexpr int NK = 4 * NT;  // k steps of 4
+  constexpr int NTILE = NT * (NT + 1) / 2;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l16 = lane & 15, kq = lane >> 4;
+  for (int tile = wave; tile < NTILE; tile += NW) {
+    // tile -> (I, J), I <= J, column by column of the upper triangle
+    int I = tile, J = 0;
+#pragma unroll
+    for (int c = 0; c < NT; ++c)
+      if (I > J) {
+        I -= J + 1;
+        ++J;
+      }
+    const int i0 = 16 * I, j0 = 16 * J;
+    double av[NK], bv[NK];
+#pragma unroll
+    for (int s4 = 0; s4 < NK; ++s4) {
+      av[s4] = A[i0 + l16 + (4 * s4 + kq) * LDA];
+      bv[s4] = B[j0 + l16 + (4 * s4 + kq) * LDA];
+    }
+    dbl4 e = zero4(), o = zero4();
+#pragma unroll
+    for (int s4 = 0; s4 < NK; s4 += 2) {
+      e = mfma64(av[s4], bv[s4], e);
+      o = mfma64(av[s4 + 1], bv[s4 + 1], o);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = i0 + 4 * v + kq, c = j0 + l16;
+      const double acc = e[v] + o[v];
+      const double val = beta == 0.0 ? alpha * acc : fma(alpha, acc, beta * D[r + c * LDA]);
+      if (I < J || r <= c) {
+        C[r + c * LDA] = val;
+        C[c + r * LDA] = val;
       }
     }
   }

@@ -155,7 +155,7 @@ void launch_aug_form(const Dev& d, int axis, int sd0, int nsd, hipStream_t st);
 // precision mode (QR and SVD products).
 void launch_gemm(const Dev& d, int axis, int sd0, int nsd, const void* X, bool x64, int64_t xsd, int rows,
                  int kdim, int ndim, int boff, int bld, void* Y, bool y64, int64_t ysd, const double* rowscale,
-                 bool gram, int fill_off, bool rows_are_cells, bool exact, hipStream_t st);
+                 bool gram, int fill_off, bool rows_are_cells, bool exact, hipStream_t st, bool set_rank = false);
 void launch_ang_reduce(const Dev& d, int axis, int sd0, int nsd, hipStream_t st);
 void launch_kstep(const Dev& d, int axis, int sd0, int nsd, hipStream_t st);
 void launch_spatial_reduce(const Dev& d, int axis, int sd0, int nsd, const void* Q, hipStream_t st);
@@ -167,12 +167,10 @@ void launch_moments(const Dev& d, int nmom, hipStream_t st);
 // small (one workgroup per subdomain) kernels
 void launch_aug_svd(const Dev& d, int axis, int sd0, int nsd, hipStream_t st);
 void launch_chol(const Dev& d, int axis, int sd0, int nsd, int ndim, int rows, int ngp, bool shift,
-                 int acc_mode, double bscale, bool pivot, int oRinv, int oRacc, int ld, hipStream_t st);
+                 int acc_mode, double bscale, bool pivot, int oRinv, int oRacc, int ld, hipStream_t st, double* sout = nullptr);
 void launch_adv_prep(const Dev& d, int axis, int sd0, int nsd, hipStream_t st);
 void launch_adv_sstep(const Dev& d, int axis, int sd0, int nsd, hipStream_t st);
-void launch_trunc(const Dev& d, int axis, int sd0, int nsd, hipStream_t st);
-void launch_set_rank(const Dev& d, int sd0, int nsd, hipStream_t st);
+void launch_trunc(const Dev& d, int axis, int sd0, int nsd, bool fold_rinv, hipStream_t st);
 void launch_coll_prep(const Dev& d, int sd0, int nsd, hipStream_t st);
 void launch_coll_sstep(const Dev& d, int sd0, int nsd, hipStream_t st);
-void launch_coll_final(const Dev& d, int sd0, int nsd, hipStream_t st);
 }  // namespace dd

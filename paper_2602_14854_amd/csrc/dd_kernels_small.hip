@@ -101,14 +101,18 @@ void launch_aug_svd(const Dev& d, int axis, int sd0, int nsd, hipStream_t st) {
 //   Racc slot: the running factor with X = Q Racc -- acc_mode 1 starts it
 //              with R P^T, acc_mode 2 left-multiplies it by R -- with the rows
 //              of dependent columns zeroed.
-// Slots have leading dimension ld.
+// Slots have leading dimension ld.  With sout set (acc_mode 2 only), the
+// transposed final factor Racc^T, zero-padded to R x R, is also stored as the
+// subdomain's coefficient matrix (the S of X = Q S^T).
 template <int NMAX>
 __global__ __launch_bounds__(NTHR) void s_chol(Dev d, int axis, int sd0, int ndim, int rows, int ngp, int shift,
-                                              int acc_mode, double bscale, int pivot, int oRinv, int oRacc, int ld) {
+                                              int acc_mode, double bscale, int pivot, int oRinv, int oRacc, int ld,
+                                              double* sout) {
   const int s = sd0 + blockIdx.x;
   const int n = dim_of(d, s, axis, ndim);
   __shared__ double G[LDA * CAP];
   __shared__ double X[LDA * CAP];
+  __shared__ double E2[LDA * CAP];
   __shared__ int dep[CAP];
   __shared__ int perm[CAP];
   sum_partials(d, s, ngp, 0, n, n, n, G, LDA, 1.0);
@@ -143,7 +147,6 @@ __global__ __launch_bounds__(NTHR) void s_chol(Dev d, int axis, int sd0, int ndi
     near_order = fro2 <= 1e-10 ? 2 : (fro2 <= 1e-6 ? 4 : 0);
   }
   if (near_order > 0) {
-    __shared__ double E2[LDA * CAP];
     __shared__ double E3[LDA * CAP];
     for (int idx = threadIdx.x; idx < n * n; idx += NTHR) {
       const int i = idx % n, j = idx / n;
@@ -200,16 +203,29 @@ __global__ __launch_bounds__(NTHR) void s_chol(Dev d, int axis, int sd0, int ndi
   } else if (acc_mode == 2) {
     // Racc <- R Racc, with Racc staged in LDS
     copy_to_lds(X, sm + oRacc, ld, n, n);
-    mm(sm + oRacc, ld, G, LDA, false, X, LDA, false, n, n, n, 1.0, 0.0);
+    if (sout == nullptr) {
+      mm(sm + oRacc, ld, G, LDA, false, X, LDA, false, n, n, n, 1.0, 0.0);
+    } else {
+      mm(E2, LDA, G, LDA, false, X, LDA, false, n, n, n, 1.0, 0.0);
+      copy_from_lds(sm + oRacc, ld, E2, n, n, 1.0);
+      const int R = d.R;
+      double* Sg = sout + (int64_t)s * R * R;
+      for (int idx = threadIdx.x; idx < R * R; idx += NTHR) {
+        const int i = idx % R, j = idx / R;
+        const double v = (i < n && j < n) ? E2[j + i * LDA] : 0.0;
+        Sg[idx] = v;
+        if (!isfinite(v)) atomicOr(d.flags, FLAG_NONFINITE);
+      }
+    }
   }
 }
 
 void launch_chol(const Dev& d, int axis, int sd0, int nsd, int ndim, int rows, int ngp, bool shift, int acc_mode,
-                 double bscale, bool pivot, int oRinv, int oRacc, int ld, hipStream_t st) {
+                 double bscale, bool pivot, int oRinv, int oRacc, int ld, hipStream_t st, double* sout) {
   const int cap = ndim == DIM_M0 ? d.MA : (ndim == DIM_T ? d.T : d.R);
 #define DD_CHOL(NMAX)                                                                                             \
   hipLaunchKernelGGL(s_chol<NMAX>, dim3(nsd), dim3(NTHR), 0, st, d, axis, sd0, ndim, rows, ngp, shift ? 1 : 0,   \
-                     acc_mode, bscale, pivot ? 1 : 0, oRinv, oRacc, ld)
+                     acc_mode, bscale, pivot ? 1 : 0, oRinv, oRacc, ld, sout)
   if (cap <= 16) DD_CHOL(16);
   else if (cap <= 32) DD_CHOL(32);
   else if (cap <= 48) DD_CHOL(48);
@@ -219,8 +235,55 @@ void launch_chol(const Dev& d, int axis, int sd0, int nsd, int ndim, int rows, i
 
 // ---------------------------------------------------------------- advection
 
-// Angular Galerkin matrices -> eigen-split C = P diag(lam) P^T (Appendix A),
-// C+ = P diag(max(lam,0)) P^T, C- = P diag(min(lam,0)) P^T, and the
+// |C| = sign(C) C for a symmetric C (t x t in LDS, ld LDA), left in Y:
+// then C+ = (C + |C|) / 2 = P diag(max(lam, 0)) P^T and C- = (C - |C|) / 2
+// without the eigenvectors.  sign(C) by the scaled Newton-Schulz iteration
+// (Chen and Chow, 2014): X0 = C / |C|_F has its eigenvalues in
+// [-1, -l] u [l, 1], and
+//   X <- a X (3 I - a^2 X^2) / 2,  a = sqrt(3 / (1 + l + l^2)),
+// maps that set into [-1, -l'] u [l', 1] with l' = a l (3 - a^2 l^2) / 2
+// (about 2.6 l while l is small, then quadratic convergence).  Starting
+// from l = 1e-13 / sqrt(t), eigenvalues below 1e-13 |C|_F / sqrt(t) may keep
+// a partial sign, which moves C+- by at most that much.  Two products of
+// order 16 NT per iteration on the FP64 matrix cores, and an iteration count
+// that depends on t alone.  C is zero-padded to order 16 NT in place; X, Y
+// and W are LDS work buffers of the same shape.
+template <int NT>
+__device__ void abs_split(double* C, double* X, double* Y, double* W, int t) {
+  constexpr int NP = 16 * NT;
+  __shared__ double red[NTHR];
+  double part = 0.0;
+  for (int idx = threadIdx.x; idx < NP * NP; idx += NTHR) {
+    const int i = idx % NP, j = idx / NP;
+    const double c = (i < t && j < t) ? C[i + j * LDA] : 0.0;
+    part = fma(c, c, part);
+  }
+  const double fro = sqrt(block_sum(part, red));
+  const double ifro = fro > 0.0 ? 1.0 / fro : 0.0;
+  for (int idx = threadIdx.x; idx < NP * NP; idx += NTHR) {
+    const int i = idx % NP, j = idx / NP;
+    const double c = (i < t && j < t) ? C[i + j * LDA] : 0.0;
+    C[i + j * LDA] = c;
+    X[i + j * LDA] = c * ifro;
+  }
+  __syncthreads();
+  double l = 1e-13 / sqrt((double)t);
+  for (int it = 0; it < 64 && 1.0 - l > 1e-15; ++it) {
+    const double a2 = 3.0 / (1.0 + l + l * l), a = sqrt(a2);
+    const double c1 = 1.5 * a, c3 = -0.5 * a * a2;
+    sym_mm<NT>(Y, X, X, 1.0, 0.0, Y);  // X^2
+    sym_mm<NT>(W, X, Y, c3, c1, X);    // c1 X + c3 X^3
+    double* sw = X;
+    X = W;
+    W = sw;
+    l = l * (c1 + c3 * l * l);
+  }
+  sym_mm<NT>(Y, X, C, 1.0, 0.0, Y);  // sign(C) C
+}
+
+// Angular Galerkin matrices -> the upwind split C = C+ + C- of Appendix A
+// (C = P diag(lam) P^T, C+ = P diag(max(lam,0)) P^T, C- = P diag(min(lam,0))
+// P^T), and the
 // coefficient matrices of the fused K-step (with nu = dt c / h, Am = S T):
 //   M0 = Am (I - nu C+ + nu C-), Mm = nu Am C+, Mp = -nu Am C-,
 //   GLo = nu Am En C+, GHi = -nu Am Ep C-,
@@ -233,8 +296,7 @@ __global__ __launch_bounds__(NTHR) void s_adv_prep(Dev d, int axis, int sd0) {
   const int R = d.R, T = d.T;
   double* sm = small_of(d, s);
   __shared__ double A[LDA * CAP];
-  __shared__ double P[LDA * CAP];
-  __shared__ double lam[CAP];
+  __shared__ double Xb[LDA * CAP];
   const int pT = 0, pC = R * T, pEp = pC + T * T, pEn = pEp + T * T, pOlo = pEn + T * T, pOhi = pOlo + R * T;
   {
     const PartBlock blk[6] = {{pT, R, r, t, sm + d.oTm, R, 1.0},      {pEp, t, t, t, sm + d.oEp, T, 1.0},
@@ -252,41 +314,22 @@ __global__ __launch_bounds__(NTHR) void s_adv_prep(Dev d, int axis, int sd0) {
     }
   }
   __syncthreads();
-  // eigenvectors of C from the one-sided Jacobi of the positive definite
-  // C + shift I, whose eigenvalues lie in [shift - |C|, shift + |C|] (condition
-  // at most 5): the rotated columns are b_j = (lambda_j + shift) p_j, so the
-  // eigenvalue is the column norm - shift and p_j the normalised column (no
-  // accumulation of the rotations is needed)
-  __shared__ double red[NTHR];
-  double part = 0.0;
-  for (int idx = threadIdx.x; idx < t * t; idx += NTHR) {
-    const double x = A[idx % t + (idx / t) * LDA];
-    part = fma(x, x, part);
+  // C+ and C- without the eigenvectors (see abs_split)
+  __shared__ double X2[LDA * CAP];
+  __shared__ double Xn[LDA * CAP];
+  switch ((t + 15) >> 4) {
+    case 1: abs_split<1>(A, Xb, X2, Xn, t); break;
+    case 2: abs_split<2>(A, Xb, X2, Xn, t); break;
+    case 3: abs_split<3>(A, Xb, X2, Xn, t); break;
+    default: abs_split<4>(A, Xb, X2, Xn, t); break;
   }
-  const double shift = 1.5 * sqrt(block_sum(part, red)) + 1e-300;
-  for (int i = threadIdx.x; i < t; i += NTHR) A[i + i * LDA] += shift;
-  __syncthreads();
-  jacobi_1s(d, A, t, t, nullptr, 1e-15, 0.0, 40);
-  col_norms(A, t, t, lam);
-  for (int idx = threadIdx.x; idx < t * t; idx += NTHR) {
-    const int i = idx % t, j = idx / t;
-    P[i + j * LDA] = A[i + j * LDA] / lam[j];
-  }
-  __syncthreads();
-  for (int j = threadIdx.x; j < t; j += NTHR) lam[j] -= shift;
-  __syncthreads();
   double* Cp = sm + d.oCp;
   double* Cn = sm + d.oCn;
   for (int idx = threadIdx.x; idx < t * t; idx += NTHR) {
     const int i = idx % t, j = idx / t;
-    double ap = 0.0, an = 0.0;
-    for (int k = 0; k < t; ++k) {
-      const double pp = P[i + k * LDA] * P[j + k * LDA];
-      ap = fma(pp, fmax(lam[k], 0.0), ap);
-      an = fma(pp, fmin(lam[k], 0.0), an);
-    }
-    Cp[i + j * T] = ap;
-    Cn[i + j * T] = an;
+    const double c = A[i + j * LDA], ab = 0.5 * (X2[i + j * LDA] + X2[j + i * LDA]);
+    Cp[i + j * T] = 0.5 * (c + ab);
+    Cn[i + j * T] = 0.5 * (c - ab);
   }
   __syncthreads();
   const double nu = d.dt * d.c / d.h;
@@ -418,8 +461,11 @@ void launch_adv_sstep(const Dev& d, int axis, int sd0, int nsd, hipStream_t st) 
 // Truncation (Algorithm 5) of S3 = RL^T: SVD through two Jacobi passes on
 // Gram matrices (S3^T S3, then (S3 Y1)^T (S3 Y1)), rank rule, and the
 // rotations Bu = U~[:, :r'] / h, Bv = V~[:, :r'] for the final products.
-// Writes S = diag(sigma[:r']) into the state and r' into rnew.
-__global__ __launch_bounds__(NTHR) void s_trunc(Dev d, int axis, int sd0) {
+// Writes S = diag(sigma[:r']) into the state and r' into rnew.  With
+// fold_rinv, the last Cholesky-QR product of L is folded into the rotation:
+// Bv = Rinv V~[:, :r'] with Rinv the last pass's inverse factor, so that
+// V = X2 Bv / sqrt(w) straight from the second-pass output X2.
+__global__ __launch_bounds__(NTHR) void s_trunc(Dev d, int axis, int sd0, int fold_rinv) {
   const int s = sd0 + blockIdx.x;
   const int t = d.tdim[s];
   const int R = d.R, T = d.T;
@@ -532,19 +578,16 @@ __global__ __launch_bounds__(NTHR) void s_trunc(Dev d, int axis, int sd0) {
     Sg[idx] = v;
   }
   if (threadIdx.x < rp && !isfinite(sig[threadIdx.x])) atomicOr(d.flags, FLAG_NONFINITE);
+  if (fold_rinv) {
+    // G is free again; the barriers above ordered the Bv stores
+    __syncthreads();
+    mm(G, LDA, sm + d.oRinv, T, false, sm + d.oBv, T, false, t, rp, t, 1.0, 0.0);
+    copy_from_lds(sm + d.oBv, T, G, t, rp, 1.0);
+  }
 }
 
-void launch_trunc(const Dev& d, int axis, int sd0, int nsd, hipStream_t st) {
-  hipLaunchKernelGGL(s_trunc, dim3(nsd), dim3(NTHR), 0, st, d, axis, sd0);
-}
-
-__global__ void s_set_rank(Dev d, int sd0, int nsd) {
-  const int s = sd0 + blockIdx.x * blockDim.x + threadIdx.x;
-  if (s < sd0 + nsd) d.rank[s] = d.rnew[s];
-}
-
-void launch_set_rank(const Dev& d, int sd0, int nsd, hipStream_t st) {
-  hipLaunchKernelGGL(s_set_rank, dim3((nsd + 63) / 64), dim3(64), 0, st, d, sd0, nsd);
+void launch_trunc(const Dev& d, int axis, int sd0, int nsd, bool fold_rinv, hipStream_t st) {
+  hipLaunchKernelGGL(s_trunc, dim3(nsd), dim3(NTHR), 0, st, d, axis, sd0, fold_rinv ? 1 : 0);
 }
 
 // ---------------------------------------------------------------- collision
@@ -645,26 +688,6 @@ __global__ __launch_bounds__(NTHR) void s_coll_sstep(Dev d, int sd0) {
 
 void launch_coll_sstep(const Dev& d, int sd0, int nsd, hipStream_t st) {
   hipLaunchKernelGGL(s_coll_sstep, dim3(nsd), dim3(NTHR), 0, st, d, sd0);
-}
-
-// S = RL^T after the weighted QR of L1 (Algorithm 3, step 5)
-__global__ __launch_bounds__(NTHR) void s_coll_final(Dev d, int sd0) {
-  const int s = sd0 + blockIdx.x;
-  const int r = d.rank[s];
-  const int R = d.R, T = d.T;
-  const double* sm = small_of(d, s);
-  double* Sg = d.S + (int64_t)s * R * R;
-  for (int idx = threadIdx.x; idx < R * R; idx += NTHR) {
-    const int i = idx % R, j = idx / R;
-    double v = 0.0;
-    if (i < r && j < r) v = sm[d.oRacc + j + i * T];
-    Sg[idx] = v;
-    if (!isfinite(v)) atomicOr(d.flags, FLAG_NONFINITE);
-  }
-}
-
-void launch_coll_final(const Dev& d, int sd0, int nsd, hipStream_t st) {
-  hipLaunchKernelGGL(s_coll_final, dim3(nsd), dim3(NTHR), 0, st, d, sd0);
 }
 
 }  // namespace dd

@@ -131,12 +131,14 @@ __global__ __launch_bounds__(NTHR) void k_aug_form(Dev d, int axis, int sd0) {
 // partial Gram matrix of Y.  X is rows x k, B is k x n (small workspace,
 // leading dimension bld).  Columns flagged in the fill mask are replaced by
 // deterministic pseudo-random values (used to complete a basis where the
-// data carry no information).
+// data carry no information).  With set_rank, the first workgroup of each
+// subdomain also commits the truncated rank (the product reads only the
+// augmented and new ranks, never the current one).
 // ----------------------------------------------------------------------------
 template <class SI, class S, int P, int NCB, int KS>
 __global__ __launch_bounds__(NTHR) void k_gemm(Dev d, int axis, int sd0, const void* X, int64_t xsd, int rows,
                                                int kdim, int ndim, int boff, int bld, void* Y, int64_t ysd,
-                                               const double* rowscale, int gram, int fill_off) {
+                                               const double* rowscale, int gram, int fill_off, int set_rank) {
   using F = typename Prec<P>::F;
   using Acc = typename Prec<P>::Acc;
   constexpr int LD = strip_ld<NCB>();
@@ -158,6 +160,7 @@ __global__ __launch_bounds__(NTHR) void k_gemm(Dev d, int axis, int sd0, const v
   }
   for (int j = threadIdx.x; j < 16 * NCB; j += NTHR)
     fillm[j] = (fill_off >= 0 && j < n) ? (sm[fill_off + j] != 0.0) : 0;
+  if (set_rank && blockIdx.x == 0 && threadIdx.x == 0) d.rank[s] = d.rnew[s];
   __syncthreads();
 
   const SI* Xsd = (const SI*)X + (int64_t)s * xsd;
@@ -1186,7 +1189,7 @@ static int dim_cap(const Dev& d, int which) { return which == DIM_M0 ? d.MA : (w
 
 void launch_gemm(const Dev& d, int axis, int sd0, int nsd, const void* X, bool x64, int64_t xsd, int rows, int kdim,
                  int ndim, int boff, int bld, void* Y, bool y64, int64_t ysd, const double* rowscale, bool gram,
-                 int fill_off, bool rows_are_cells, bool exact, hipStream_t st) {
+                 int fill_off, bool rows_are_cells, bool exact, hipStream_t st, bool set_rank) {
   const int nwg = rows_are_cells ? d.nwgN : d.nwgM;
   auto go = [&](auto ti, auto to, auto pc) {
     using SI = typename decltype(ti)::type;
@@ -1198,7 +1201,7 @@ void launch_gemm(const Dev& d, int axis, int sd0, int nsd, const void* X, bool x
         constexpr int KS = sub_cap<P>(decltype(k)::value);
         const size_t lds = strip_bytes<P, NC>(KS * NC * 64);
         hipLaunchKernelGGL((k_gemm<SI, SO, P, NC, KS>), dim3(nwg, nsd), dim3(NTHR), lds, st, d, axis, sd0, X, xsd,
-                           rows, kdim, ndim, boff, bld, Y, ysd, rowscale, gram ? 1 : 0, fill_off);
+                           rows, kdim, ndim, boff, bld, Y, ysd, rowscale, gram ? 1 : 0, fill_off, set_rank ? 1 : 0);
       });
     });
   };
