@@ -31,50 +31,59 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 // addend D (ld ldd) is C itself (mm) or another buffer (mm_add); generic
 // pointers (LDS or global), C aliasing neither A nor B.  On the FP64 matrix
 // cores: the 16 x 16 output tiles are dealt to the wavefronts, and a
-// wavefront issues every operand load of a tile (clamped to valid addresses,
-// out-of-range values replaced by zero) before its first
-// v_mfma_f64_16x16x4f64, so a tile costs one load latency instead of one per k.
-__device__ __forceinline__ void mm_add(double* C, int ldc, const double* A, int lda, bool ta, const double* B, int ldb,
-                                       bool tb, int m, int n, int k, double alpha, double beta, const double* D,
-                                       int ldd) {
-  constexpr int KMAX = CAP / 4;
+// wavefront issues every operand load of a tile (at clamped, always valid
+// addresses; out-of-range values replaced by zero) before its first
+// v_mfma_f64_16x16x4f64, so a tile costs one load latency instead of one
+// per k.  The k loop has a compile-time length NK (steps of 4: k rounded up
+// to 16, 32 or 64) and runs as two accumulator chains.
+template <int NK>
+__device__ __forceinline__ void mm_body(double* C, int ldc, const double* A, int lda, bool ta, const double* B,
+                                        int ldb, bool tb, int m, int n, int k, double alpha, double beta,
+                                        const double* D, int ldd) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int l16 = lane & 15, kq = lane >> 4;
-  const int tm = (m + 15) >> 4, tn = (n + 15) >> 4, nk = (k + 3) >> 2;
+  const int tm = (m + 15) >> 4, tn = (n + 15) >> 4;
+  // tile / tm for tile < 16 and tm <= 4 without a division
+  const int magic = tm == 1 ? 64 : (tm == 2 ? 32 : (tm == 3 ? 22 : 16));
   for (int tile = wave; tile < tm * tn; tile += NW) {
-    const int i0 = 16 * (tile % tm), j0 = 16 * (tile / tm);
+    const int tj = (tile * magic) >> 6, ti = tile - tj * tm;
+    const int i0 = 16 * ti, j0 = 16 * tj;
     const int i = i0 + l16, j = j0 + l16;  // A row and B column of this lane
     const int ic = i < m ? i : 0, jc = j < n ? j : 0;
-    double av[KMAX], bv[KMAX];
+    double av[NK], bv[NK];
 #pragma unroll
-    for (int s4 = 0; s4 < KMAX; ++s4) {
-      if (s4 < nk) {
-        const int l = 4 * s4 + kq;
-        const int lc = l < k ? l : 0;
-        av[s4] = ta ? A[lc + ic * lda] : A[ic + lc * lda];
-        bv[s4] = tb ? B[jc + lc * ldb] : B[lc + jc * ldb];
-      }
+    for (int s4 = 0; s4 < NK; ++s4) {
+      const int l = 4 * s4 + kq;
+      const int lc = l < k ? l : 0;
+      av[s4] = ta ? A[lc + ic * lda] : A[ic + lc * lda];
+      bv[s4] = tb ? B[jc + lc * ldb] : B[lc + jc * ldb];
     }
-    dbl4 acc = zero4();
+    dbl4 e = zero4(), o = zero4();
 #pragma unroll
-    for (int s4 = 0; s4 < KMAX; ++s4) {
-      if (s4 < nk) {
-        const int l = 4 * s4 + kq;
-        const double a = (i < m && l < k) ? av[s4] : 0.0;
-        const double b = (j < n && l < k) ? bv[s4] : 0.0;
-        acc = mfma64(a, b, acc);
-      }
+    for (int s4 = 0; s4 < NK; s4 += 2) {
+      const int l = 4 * s4 + kq;
+      e = mfma64((i < m && l < k) ? av[s4] : 0.0, (j < n && l < k) ? bv[s4] : 0.0, e);
+      o = mfma64((i < m && l + 4 < k) ? av[s4 + 1] : 0.0, (j < n && l + 4 < k) ? bv[s4 + 1] : 0.0, o);
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int ci = i0 + 4 * v + kq, cj = j0 + l16;
       if (ci < m && cj < n) {
+        const double acc = e[v] + o[v];
         const double dv = (beta == 0.0) ? 0.0 : beta * D[ci + (int64_t)cj * ldd];
-        C[ci + (int64_t)cj * ldc] = (beta == 0.0) ? alpha * acc[v] : fma(alpha, acc[v], dv);
+        C[ci + (int64_t)cj * ldc] = (beta == 0.0) ? alpha * acc : fma(alpha, acc, dv);
       }
     }
   }
   __syncthreads();
+}
+
+__device__ __forceinline__ void mm_add(double* C, int ldc, const double* A, int lda, bool ta, const double* B, int ldb,
+                                       bool tb, int m, int n, int k, double alpha, double beta, const double* D,
+                                       int ldd) {
+  if (k <= 16) mm_body<4>(C, ldc, A, lda, ta, B, ldb, tb, m, n, k, alpha, beta, D, ldd);
+  else if (k <= 32) mm_body<8>(C, ldc, A, lda, ta, B, ldb, tb, m, n, k, alpha, beta, D, ldd);
+  else mm_body<16>(C, ldc, A, lda, ta, B, ldb, tb, m, n, k, alpha, beta, D, ldd);
 }
 
 __device__ __forceinline__ void mm(double* C, int ldc, const double* A, int lda, bool ta, const double* B, int ldb,
