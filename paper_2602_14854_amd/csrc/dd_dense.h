@@ -287,6 +287,62 @@ __device__ __forceinline__ void jacobi_rotation(double al, double be, double ga,
   sn = c * t;
 }
 
+// True when a further Jacobi sweep over B (rows x n, LDS, ld LDA) would not
+// rotate any pair: no |b_p . b_q| exceeds tol ||b_p|| ||b_q|| among columns
+// above the noise floor.  All the inner products at once on the FP64 matrix
+// cores (the tiles of B^T B on and above the diagonal into Gq, LDS, ld LDA;
+// NK = rows/4 rounded up), instead of the n - 1 rounds of a sweep.  flag is
+// LDS scratch.
+template <int NK>
+__device__ __forceinline__ bool jacobi_quiet(const double* B, int rows, int n, double tol2, double floor2, double* Gq,
+                                             int* flag) {
+  if (threadIdx.x == 0) *flag = 0;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l16 = lane & 15, kq = lane >> 4;
+  const int tn = (n + 15) >> 4;
+  for (int tile = wave; tile < tn * (tn + 1) / 2; tile += NW) {
+    int I = tile, J = 0;
+#pragma unroll
+    for (int c = 0; c < CAP / 16; ++c)
+      if (I > J) {
+        I -= J + 1;
+        ++J;
+      }
+    const int i = 16 * I + l16, j = 16 * J + l16;  // columns p (A side) and q (B side) of this lane
+    const int ic = i < n ? i : 0, jc = j < n ? j : 0;
+    double av[NK], bv[NK];
+#pragma unroll
+    for (int s4 = 0; s4 < NK; ++s4) {
+      const int l = 4 * s4 + kq;
+      const int lc = l < rows ? l : 0;
+      av[s4] = B[lc + ic * LDA];
+      bv[s4] = B[lc + jc * LDA];
+    }
+    dbl4 e = zero4(), o = zero4();
+#pragma unroll
+    for (int s4 = 0; s4 < NK; s4 += 2) {
+      const int l = 4 * s4 + kq;
+      e = mfma64((i < n && l < rows) ? av[s4] : 0.0, (j < n && l < rows) ? bv[s4] : 0.0, e);
+      o = mfma64((i < n && l + 4 < rows) ? av[s4 + 1] : 0.0, (j < n && l + 4 < rows) ? bv[s4 + 1] : 0.0, o);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int p = 16 * I + 4 * v + kq, q = 16 * J + l16;
+      if (p <= q && q < n) Gq[p + q * LDA] = e[v] + o[v];
+    }
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < n * n; idx += NTHR) {
+    const int p = idx % n, q = idx / n;
+    if (p < q) {
+      const double ga = Gq[p + q * LDA], al = Gq[p * (LDA + 1)], be = Gq[q * (LDA + 1)];
+      if (ga != 0.0 && al > floor2 && be > floor2 && ga * ga > tol2 * al * be) *flag = 1;
+    }
+  }
+  __syncthreads();
+  return *flag == 0;
+}
+
 // One-sided (Hestenes) Jacobi on the columns of B (rows x n, LDS, ld LDA):
 // plane rotations from the right make the columns of B mutually orthogonal;
 // the same rotations accumulate in V (n x n, LDS, ld LDA), so that on exit
@@ -304,12 +360,17 @@ __device__ __forceinline__ void jacobi_rotation(double al, double be, double ga,
 // accuracy.  Columns whose norm is below floor_rel ||B||_F carry only
 // rounding noise (a rank-deficient B) and are not rotated: rotating noise
 // against large columns would keep it from ever meeting the relative test.
+// From the second sweep on, a sweep that rotated something is followed by
+// the all-pairs test of jacobi_quiet: when it passes, the next sweep would
+// only confirm convergence, and is skipped.
 // Returns the number of sweeps (negative if not converged).
 template <int G, int RPL, bool ACCV>
 __device__ __forceinline__ int jacobi_1s_g(const Dev& d, double* B, int rows, int n, double* V, double tol, double floor_rel,
-                           int max_sweeps) {
+                           int max_sweeps, double* Gq) {
   __shared__ int rotated[3];  // per-sweep flags: set, read, cleared in rotation
   __shared__ double red[NTHR];
+  __shared__ int bigrot[3];   // per-sweep flags of rotations with |sin| > 1e-6
+  __shared__ int qflag;
   double part = 0.0;
   for (int idx = threadIdx.x; idx < rows * n; idx += NTHR) {
     const double x = B[idx % rows + (idx / rows) * LDA];
@@ -323,6 +384,7 @@ __device__ __forceinline__ int jacobi_1s_g(const Dev& d, double* B, int rows, in
     }
   }
   if (threadIdx.x < 3) rotated[threadIdx.x] = 0;
+  if (threadIdx.x < 3) bigrot[threadIdx.x] = 0;
   __syncthreads();
   if (n <= 1) return 0;
   const int n2 = n + (n & 1);
@@ -336,6 +398,7 @@ __device__ __forceinline__ int jacobi_1s_g(const Dev& d, double* B, int rows, in
     sweeps = sweep + 1;
     const int slot = sweep % 3;
     if (threadIdx.x == 0) rotated[(sweep + 1) % 3] = 0;
+    if (threadIdx.x == 0) bigrot[(sweep + 1) % 3] = 0;
     // round-robin positions: position 0 is fixed, positions 1..n2-1 rotate
     int va = grp - 1, vb = n2 - 2 - grp;  // (position - 1 + round), kept below nm1
     for (int round = 0; round < nm1; ++round) {
@@ -382,12 +445,19 @@ __device__ __forceinline__ int jacobi_1s_g(const Dev& d, double* B, int rows, in
           }
         }
         if (lane == 0) rotated[slot] = 1;
+        if (lane == 0 && fabs(sn) > 1e-6) bigrot[slot] = 1;
       }
       if (++va >= nm1) va -= nm1;
       if (++vb >= nm1) vb -= nm1;
       __syncthreads();
     }
     if (!rotated[slot]) {
+      converged = true;
+      break;
+    }
+    // a sweep that would rotate nothing only confirms convergence: after a
+    // sweep of small rotations only, test all pairs at once instead
+    if (sweep >= 1 && !bigrot[slot] && jacobi_quiet<(G * RPL + 3) / 4>(B, rows, n, tol2, floor2, Gq, &qflag)) {
       converged = true;
       break;
     }
@@ -401,12 +471,13 @@ __device__ __forceinline__ int jacobi_1s_g(const Dev& d, double* B, int rows, in
 // 16 lanes per pair up to 32 columns, else 8 (rows <= 64 either way).
 __device__ __forceinline__ int jacobi_1s(const Dev& d, double* B, int rows, int n, double* V, double tol, double floor_rel,
                                 int max_sweeps) {
+  __shared__ double Gq[LDA * CAP];  // all-pairs test scratch
   if (n <= 32 && rows <= 32) {
-    if (V) return jacobi_1s_g<16, 2, true>(d, B, rows, n, V, tol, floor_rel, max_sweeps);
-    return jacobi_1s_g<16, 2, false>(d, B, rows, n, V, tol, floor_rel, max_sweeps);
+    if (V) return jacobi_1s_g<16, 2, true>(d, B, rows, n, V, tol, floor_rel, max_sweeps, Gq);
+    return jacobi_1s_g<16, 2, false>(d, B, rows, n, V, tol, floor_rel, max_sweeps, Gq);
   }
-  if (V) return jacobi_1s_g<8, 8, true>(d, B, rows, n, V, tol, floor_rel, max_sweeps);
-  return jacobi_1s_g<8, 8, false>(d, B, rows, n, V, tol, floor_rel, max_sweeps);
+  if (V) return jacobi_1s_g<8, 8, true>(d, B, rows, n, V, tol, floor_rel, max_sweeps, Gq);
+  return jacobi_1s_g<8, 8, false>(d, B, rows, n, V, tol, floor_rel, max_sweeps, Gq);
 }
 
 // norms of the columns of B (rows x n, LDS) into out[n]
