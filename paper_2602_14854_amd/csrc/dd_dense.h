@@ -552,11 +552,78 @@ __device__ __forceinline__ double pivot_key(double v, int i) {
   return __longlong_as_double((__double_as_longlong(c) & ~63ll) | (long long)(63 - i));
 }
 
+// X = R^{-1} for an upper triangular R (n x n in LDS, ld LDA, n <= 16 NT),
+// by 16 x 16 blocks: the padding of R up to order 16 ceil(n/16) is set to
+// the identity, wavefront I inverts the diagonal block R_II by back
+// substitution (lane q < 16 holds column q; the rows of R_II are broadcast
+// LDS reads), and the off-diagonal blocks follow by superdiagonals,
+//   X_IJ = -X_II (sum_{K=I+1..J} R_IK X_KJ),
+// one wavefront per block, on the FP64 matrix cores: the inner sum leaves
+// the MFMA accumulator in exactly the layout of the B operand of the outer
+// product, so it never goes through LDS.  X comes out zero below the
+// diagonal and identity in the padding.
+template <int NT>
+__device__ __forceinline__ void tri_inv_blocked(double* R, double* X, int n) {
+  __shared__ double dinv[16 * NT];
+  const int nb = (n + 15) >> 4, np = 16 * nb;
+  for (int idx = threadIdx.x; idx < np * np; idx += NTHR) {
+    const int i = idx % np, j = idx / np;
+    if (i >= n || j >= n) R[i + j * LDA] = i == j ? 1.0 : 0.0;
+    if (i > j || (i >> 4) != (j >> 4)) X[i + j * LDA] = 0.0;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < np; i += NTHR) dinv[i] = rcp_nr(R[i * (LDA + 1)]);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (wave < nb && lane < 16) {
+    const int b0 = 16 * wave, q = lane;
+    double x[16];
+#pragma unroll
+    for (int i = 15; i >= 0; --i) {
+      double acc = i == q ? 1.0 : 0.0;
+#pragma unroll
+      for (int l = i + 1; l < 16; ++l) acc = fma(-R[b0 + i + (b0 + l) * LDA], x[l], acc);
+      x[i] = acc * dinv[b0 + i];
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) X[b0 + i + (b0 + q) * LDA] = i <= q ? x[i] : 0.0;
+  }
+  __syncthreads();
+  const int l16 = lane & 15, kq = lane >> 4;
+#pragma unroll
+  for (int dd = 1; dd < NT; ++dd) {
+    if (dd < nb) {
+      const int I = wave, J = wave + dd;
+      if (J < nb) {
+        const int i0 = 16 * I, j0 = 16 * J;
+        dbl4 e = zero4(), o = zero4();
+#pragma unroll
+        for (int K = 1; K <= dd; ++K) {
+          const int k0 = 16 * (I + K);
+#pragma unroll
+          for (int s4 = 0; s4 < 4; s4 += 2) {
+            e = mfma64(R[i0 + l16 + (k0 + 4 * s4 + kq) * LDA], X[k0 + 4 * s4 + kq + (j0 + l16) * LDA], e);
+            o = mfma64(R[i0 + l16 + (k0 + 4 * s4 + 4 + kq) * LDA], X[k0 + 4 * s4 + 4 + kq + (j0 + l16) * LDA], o);
+          }
+        }
+        const dbl4 t = e + o;  // T = sum_K R_IK X_KJ, row 4v + kq, column l16
+        dbl4 y = zero4();
+#pragma unroll
+        for (int v = 0; v < 4; ++v) y = mfma64(X[i0 + l16 + (i0 + 4 * v + kq) * LDA], t[v], y);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) X[i0 + 4 * v + kq + (j0 + l16) * LDA] = -y[v];
+      }
+      __syncthreads();
+    }
+  }
+}
+
+
 // Cholesky factorisation of the symmetric n x n matrix G (n <= NMAX; LDS, ld
 // LDA, upper triangle read), optionally with diagonal pivoting,
 //   G[perm, perm] = R^T R,  R upper triangular,
-// and the inverse R^{-1}, both by wavefront 0 alone with no workgroup
-// barrier.  Lane j keeps row entries R[0..k][j] of its own (original) column
+// and the inverse R^{-1}.  The factor is formed by wavefront 0 alone with no
+// workgroup barrier: lane j keeps row entries R[0..k][j] of its own (original) column
 // j in registers and its current Schur diagonal.  Step k (left-looking):
 // the pivot p is k, or with pivoting the largest remaining Schur diagonal
 // (smallest index among equal ones); every lane forms
@@ -565,10 +632,11 @@ __device__ __forceinline__ double pivot_key(double v, int i) {
 // times the column's own initial diagonal (or non-finite) marks a
 // numerically dependent column: the pivot is replaced by 1 (the Schur row is
 // kept as the row of R) and dep[k] is set; the caller completes Q with a
-// pseudo-random column there and zeroes row k of R.  The inverse of the
-// permuted factor R P is a right-looking back substitution, again from
-// registers.  On return (after a barrier): G = R P (upper, zero below), X =
-// (R P)^{-1}, perm, dep.  All threads call.
+// pseudo-random column there and zeroes row k of R.  The inverse follows by
+// 16 x 16 blocks on all wavefronts (tri_inv_blocked).  On return (after a
+// barrier): G = R (pivot order: column k of R belongs to original column
+// perm[k]; upper, zero below, identity padding to a multiple of 16), X =
+// R^{-1} (same layout), perm, dep.  All threads call.
 template <int NMAX, bool PIVOT>
 __device__ __forceinline__ void chol_inv_wave(const Dev& d, double* G, double* X, int n, int* perm, int* dep) {
   if (threadIdx.x < 64) {
@@ -632,28 +700,10 @@ __device__ __forceinline__ void chol_inv_wave(const Dev& d, double* G, double* X
       for (int i = 0; i < NMAX; ++i)
         if (i < n) G[i + myk * LDA] = i <= myk ? rc[i] : 0.0;
     }
-    // X = (R P)^{-1}: lane q holds column q; column k of R P is held by
-    // lane pk[k] (entries rc[0..k])
-    const int q = j;
-    double x[NMAX];
-#pragma unroll
-    for (int i = 0; i < NMAX; ++i) x[i] = i == q ? 1.0 : 0.0;
-#pragma unroll
-    for (int k = NMAX - 1; k >= 0; --k) {
-      if (k < n) {
-        const int pl = pk[k];
-        x[k] *= rcp_nr(lane_value(rc[k], pl));
-#pragma unroll
-        for (int i = 0; i < k; ++i) x[i] = fma(-lane_value(rc[i], pl), x[k], x[i]);
-      }
-    }
-    if (q < n) {
-#pragma unroll
-      for (int i = 0; i < NMAX; ++i)
-        if (i < n) X[i + q * LDA] = x[i];
-    }
   }
   __syncthreads();
+  // X = R^{-1} (R upper triangular in G, pivot order), blockwise
+  tri_inv_blocked<(NMAX + 15) / 16>(G, X, n);
 }
 
 // smallest k with (sum_{j >= k} sig_j^2)^(1/2) <= tol (Algorithms 4, 5)
