@@ -628,7 +628,9 @@ __device__ __forceinline__ void tri_inv_blocked(double* R, double* X, int n) {
 // the pivot p is k, or with pivoting the largest remaining Schur diagonal
 // (smallest index among equal ones); every lane forms
 //   R[k][j] = (G[p][j] - sum_{l<k} R[l][p] R[l][j]) / R[k][p],
-// reading R[l][p] from lane p with v_readlane.  A pivot not larger than 1e-20
+// reading R[l][p] from the LDS buffer Rt (CAP x (CAP + 1) doubles), where
+// lane p stored row entry R[k][p] when it formed it: broadcast reads, no
+// v_readlane chain.  A pivot not larger than 1e-20
 // times the column's own initial diagonal (or non-finite) marks a
 // numerically dependent column: the pivot is replaced by 1 (the Schur row is
 // kept as the row of R) and dep[k] is set; the caller completes Q with a
@@ -638,7 +640,8 @@ __device__ __forceinline__ void tri_inv_blocked(double* R, double* X, int n) {
 // perm[k]; upper, zero below, identity padding to a multiple of 16), X =
 // R^{-1} (same layout), perm, dep.  All threads call.
 template <int NMAX, bool PIVOT>
-__device__ __forceinline__ void chol_inv_wave(const Dev& d, double* G, double* X, int n, int* perm, int* dep) {
+__device__ __forceinline__ void chol_inv_wave(const Dev& d, double* G, double* X, int n, int* perm, int* dep,
+                                              double* Rt) {
   if (threadIdx.x < 64) {
     const int j = threadIdx.x;
     double rc[NMAX];  // rc[l] = R[l][j]
@@ -671,13 +674,16 @@ __device__ __forceinline__ void chol_inv_wave(const Dev& d, double* G, double* X
           isdep = true;
         }
         const double rinv = rsqrt_nr(dk);
+        // R[l][p], l < k: the pivot lane's entries, written to Rt at the
+        // steps that formed them; broadcast reads (one address per wave)
+        const double* rp = Rt + p * (CAP + 1);
         double a0 = g, a1 = 0.0, a2 = 0.0, a3 = 0.0;
 #pragma unroll
         for (int l = 0; l < k; l += 4) {
-          a0 = fma(-lane_value(rc[l], p), rc[l], a0);
-          if (l + 1 < k) a1 = fma(-lane_value(rc[l + 1], p), rc[l + 1], a1);
-          if (l + 2 < k) a2 = fma(-lane_value(rc[l + 2], p), rc[l + 2], a2);
-          if (l + 3 < k) a3 = fma(-lane_value(rc[l + 3], p), rc[l + 3], a3);
+          a0 = fma(-rp[l], rc[l], a0);
+          if (l + 1 < k) a1 = fma(-rp[l + 1], rc[l + 1], a1);
+          if (l + 2 < k) a2 = fma(-rp[l + 2], rc[l + 2], a2);
+          if (l + 3 < k) a3 = fma(-rp[l + 3], rc[l + 3], a3);
         }
         const double rkj = (a0 + a1) + (a2 + a3);
         if (j == p) {
@@ -687,6 +693,7 @@ __device__ __forceinline__ void chol_inv_wave(const Dev& d, double* G, double* X
         } else if (!done) {
           rc[k] = rkj * rinv;
           dg = fma(-rc[k], rc[k], dg);
+          Rt[j * (CAP + 1) + k] = rc[k];
         }
         if (j == 0) {
           perm[k] = p;

@@ -93,7 +93,8 @@ void launch_aug_svd(const Dev& d, int axis, int sd0, int nsd, hipStream_t st) {
 
 // One pass of (shifted, optionally pivoted) Cholesky QR of X = Q R: G = sum
 // of partials (n x n), optional shift 11 (rows n + n (n+1)) u tr(G) (Fukaya
-// et al., shifted CholeskyQR), G[perm, perm] = R^T R (R upper triangular, or
+// et al., shifted CholeskyQR; without pivoting first tried unshifted, see
+// below), G[perm, perm] = R^T R (R upper triangular, or
 // the symmetric square root when G is within 1e-3 of the identity), and
 //   Rinv slot: P R^{-1} (rows permuted back, scaled by bscale) for the next
 //              tall-skinny product Q = X P R^{-1},
@@ -113,18 +114,28 @@ __global__ __launch_bounds__(NTHR) void s_chol(Dev d, int axis, int sd0, int ndi
   __shared__ double G[LDA * CAP];
   __shared__ double X[LDA * CAP];
   __shared__ double E2[LDA * CAP];
+  __shared__ double E3[LDA * CAP];
   __shared__ int dep[CAP];
   __shared__ int perm[CAP];
+  __shared__ int retry;
   sum_partials(d, s, ngp, 0, n, n, n, G, LDA, 1.0);
-  if (shift) {
-    // every wavefront forms the trace itself
+  // the shift 11 (rows n + n (n+1)) u tr(G), every wavefront forming the
+  // trace itself
+  auto add_shift = [&]() {
     const int lane = threadIdx.x & 63;
     const double tr = wave_sum(lane < n ? G[lane * (LDA + 1)] : 0.0);
     const double sh = 11.0 * ((double)rows * n + (double)n * (n + 1)) * U_ROUND * tr;
     __syncthreads();
     if (threadIdx.x < n) G[threadIdx.x * (LDA + 1)] += sh;
     __syncthreads();
-  }
+  };
+  // Without pivoting the shifted pass is first tried without its shift: a
+  // Gram that is not too ill-conditioned factors as it is, and the next pass
+  // then starts near the identity (orthogonality error about cond(X)^2 u
+  // instead of the shift's O(1)).  When a column keeps less than 1e-12 of its
+  // diagonal (or is flagged dependent), the shifted factorisation is done.
+  const bool try_plain = shift && !pivot;
+  if (shift && !try_plain) add_shift();
   // A Gram within 1e-3 (Frobenius) of the identity -- the last pass of a
   // Cholesky QR, whose input is already orthonormal up to rounding, or a
   // pass over a nearly orthonormal input -- takes the symmetric factor
@@ -147,7 +158,6 @@ __global__ __launch_bounds__(NTHR) void s_chol(Dev d, int axis, int sd0, int ndi
     near_order = fro2 <= 1e-10 ? 2 : (fro2 <= 1e-6 ? 4 : 0);
   }
   if (near_order > 0) {
-    __shared__ double E3[LDA * CAP];
     for (int idx = threadIdx.x; idx < n * n; idx += NTHR) {
       const int i = idx % n, j = idx / n;
       X[i + j * LDA] = G[i + j * LDA] - (i == j ? 1.0 : 0.0);  // E
@@ -178,9 +188,31 @@ __global__ __launch_bounds__(NTHR) void s_chol(Dev d, int axis, int sd0, int ndi
     }
     __syncthreads();
   } else if (pivot) {
-    chol_inv_wave<NMAX, true>(d, G, X, n, perm, dep);
+    chol_inv_wave<NMAX, true>(d, G, X, n, perm, dep, E2);
+  } else if (try_plain) {
+    for (int idx = threadIdx.x; idx < n * n; idx += NTHR) {
+      const int i = idx % n, j = idx / n;
+      E3[i + j * LDA] = G[i + j * LDA];
+    }
+    if (threadIdx.x == 0) retry = 0;
+    __syncthreads();
+    chol_inv_wave<NMAX, false>(d, G, X, n, perm, dep, E2);
+    for (int k = threadIdx.x; k < n; k += NTHR) {
+      const double r = G[k * (LDA + 1)];
+      if (dep[k] || !(r * r >= 1e-12 * E3[k * (LDA + 1)])) retry = 1;
+    }
+    __syncthreads();
+    if (retry) {
+      for (int idx = threadIdx.x; idx < n * n; idx += NTHR) {
+        const int i = idx % n, j = idx / n;
+        G[i + j * LDA] = E3[i + j * LDA];
+      }
+      __syncthreads();
+      add_shift();
+      chol_inv_wave<NMAX, false>(d, G, X, n, perm, dep, E2);
+    }
   } else {
-    chol_inv_wave<NMAX, false>(d, G, X, n, perm, dep);
+    chol_inv_wave<NMAX, false>(d, G, X, n, perm, dep, E2);
   }
   double* sm = small_of(d, s);
   // thread (column c = tid % 64, rows i = tid / 64 mod 4) for the n x n outputs
