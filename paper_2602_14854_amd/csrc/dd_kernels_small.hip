@@ -93,8 +93,8 @@ void launch_aug_svd(const Dev& d, int axis, int sd0, int nsd, hipStream_t st) {
 
 // One pass of (shifted, optionally pivoted) Cholesky QR of X = Q R: G = sum
 // of partials (n x n), optional shift 11 (rows n + n (n+1)) u tr(G) (Fukaya
-// et al., shifted CholeskyQR; without pivoting first tried unshifted, see
-// below), G[perm, perm] = R^T R (R upper triangular, or
+// et al., shifted CholeskyQR; first tried unshifted, see below),
+// G[perm, perm] = R^T R (R upper triangular, or
 // the symmetric square root when G is within 1e-3 of the identity), and
 //   Rinv slot: P R^{-1} (rows permuted back, scaled by bscale) for the next
 //              tall-skinny product Q = X P R^{-1},
@@ -129,13 +129,12 @@ __global__ __launch_bounds__(NTHR) void s_chol(Dev d, int axis, int sd0, int ndi
     if (threadIdx.x < n) G[threadIdx.x * (LDA + 1)] += sh;
     __syncthreads();
   };
-  // Without pivoting the shifted pass is first tried without its shift: a
-  // Gram that is not too ill-conditioned factors as it is, and the next pass
-  // then starts near the identity (orthogonality error about cond(X)^2 u
-  // instead of the shift's O(1)).  When a column keeps less than 1e-12 of its
-  // diagonal (or is flagged dependent), the shifted factorisation is done.
-  const bool try_plain = shift && !pivot;
-  if (shift && !try_plain) add_shift();
+  // The shifted pass is first tried without its shift: a Gram that is not
+  // too ill-conditioned factors as it is, and the next pass then starts near
+  // the identity (orthogonality error about cond(X)^2 u instead of the
+  // shift's O(1)).  When a column keeps less than 1e-12 of its diagonal (or
+  // is flagged dependent), the shifted factorisation is done instead.
+  const bool try_plain = shift != 0;
   // A Gram within 1e-3 (Frobenius) of the identity -- the last pass of a
   // Cholesky QR, whose input is already orthonormal up to rounding, or a
   // pass over a nearly orthonormal input -- takes the symmetric factor
@@ -187,8 +186,6 @@ __global__ __launch_bounds__(NTHR) void s_chol(Dev d, int axis, int sd0, int ndi
       dep[k] = 0;
     }
     __syncthreads();
-  } else if (pivot) {
-    chol_inv_wave<NMAX, true>(d, G, X, n, perm, dep, E2);
   } else if (try_plain) {
     for (int idx = threadIdx.x; idx < n * n; idx += NTHR) {
       const int i = idx % n, j = idx / n;
@@ -196,10 +193,11 @@ __global__ __launch_bounds__(NTHR) void s_chol(Dev d, int axis, int sd0, int ndi
     }
     if (threadIdx.x == 0) retry = 0;
     __syncthreads();
-    chol_inv_wave<NMAX, false>(d, G, X, n, perm, dep, E2);
+    if (pivot) chol_inv_wave<NMAX, true>(d, G, X, n, perm, dep, E2);
+    else chol_inv_wave<NMAX, false>(d, G, X, n, perm, dep, E2);
     for (int k = threadIdx.x; k < n; k += NTHR) {
       const double r = G[k * (LDA + 1)];
-      if (dep[k] || !(r * r >= 1e-12 * E3[k * (LDA + 1)])) retry = 1;
+      if (dep[k] || !(r * r >= 1e-12 * E3[perm[k] * (LDA + 1)])) retry = 1;
     }
     __syncthreads();
     if (retry) {
@@ -209,8 +207,11 @@ __global__ __launch_bounds__(NTHR) void s_chol(Dev d, int axis, int sd0, int ndi
       }
       __syncthreads();
       add_shift();
-      chol_inv_wave<NMAX, false>(d, G, X, n, perm, dep, E2);
+      if (pivot) chol_inv_wave<NMAX, true>(d, G, X, n, perm, dep, E2);
+      else chol_inv_wave<NMAX, false>(d, G, X, n, perm, dep, E2);
     }
+  } else if (pivot) {
+    chol_inv_wave<NMAX, true>(d, G, X, n, perm, dep, E2);
   } else {
     chol_inv_wave<NMAX, false>(d, G, X, n, perm, dep, E2);
   }
