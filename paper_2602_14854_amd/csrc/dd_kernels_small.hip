@@ -275,12 +275,16 @@ void launch_chol(const Dev& d, int axis, int sd0, int nsd, int ndim, int rows, i
 // [-1, -l] u [l, 1], and
 //   X <- a X (3 I - a^2 X^2) / 2,  a = sqrt(3 / (1 + l + l^2)),
 // maps that set into [-1, -l'] u [l', 1] with l' = a l (3 - a^2 l^2) / 2
-// (about 2.6 l while l is small, then quadratic convergence).  Starting
-// from l = 1e-13 / sqrt(t), eigenvalues below 1e-13 |C|_F / sqrt(t) may keep
-// a partial sign, which moves C+- by at most that much.  Two products of
-// order 16 NT per iteration on the FP64 matrix cores, and an iteration count
-// that depends on t alone.  C is zero-padded to order 16 NT in place; X, Y
-// and W are LDS work buffers of the same shape.
+// (about 2.6 l while l is small, then quadratic convergence).  The scaled
+// phase starts from l = 1e-6 / sqrt(t) (20 iterations); each step maps
+// [0, l] monotonically into [0, l'], so eigenvalues below that bound end it
+// somewhere in (0, 1) with their sign, and the unscaled iteration
+// X <- X (3 I - X^2) / 2 (at most 48 steps) then carries them to +-1 until
+// an update changes X by at most 1e-14 in Frobenius norm; exactly zero
+// eigenvalues stay zero.  A component still moving by less than that is at
+// most 2e-14 |C|_F, and so is its error in C+-.  Two products of order
+// 16 NT per iteration on the FP64 matrix cores.  C is zero-padded to order
+// 16 NT in place; X, Y and W are LDS work buffers of the same shape.
 template <int NT>
 __device__ void abs_split(double* C, double* X, double* Y, double* W, int t) {
   constexpr int NP = 16 * NT;
@@ -300,7 +304,7 @@ __device__ void abs_split(double* C, double* X, double* Y, double* W, int t) {
     X[i + j * LDA] = c * ifro;
   }
   __syncthreads();
-  double l = 1e-13 / sqrt((double)t);
+  double l = 1e-6 / sqrt((double)t);
   for (int it = 0; it < 64 && 1.0 - l > 1e-15; ++it) {
     const double a2 = 3.0 / (1.0 + l + l * l), a = sqrt(a2);
     const double c1 = 1.5 * a, c3 = -0.5 * a * a2;
@@ -310,6 +314,21 @@ __device__ void abs_split(double* C, double* X, double* Y, double* W, int t) {
     X = W;
     W = sw;
     l = l * (c1 + c3 * l * l);
+  }
+  for (int it = 0; it < 48; ++it) {
+    sym_mm<NT>(Y, X, X, 1.0, 0.0, Y);    // X^2
+    sym_mm<NT>(W, X, Y, -0.5, 1.5, X);   // (3 X - X^3) / 2
+    double ch = 0.0;
+    for (int idx = threadIdx.x; idx < NP * NP; idx += NTHR) {
+      const int o = idx % NP + (idx / NP) * LDA;
+      const double dlt = W[o] - X[o];
+      ch = fma(dlt, dlt, ch);
+    }
+    const double ch2 = block_sum(ch, red);
+    double* sw = X;
+    X = W;
+    W = sw;
+    if (ch2 <= 1e-28) break;
   }
   sym_mm<NT>(Y, X, C, 1.0, 0.0, Y);  // sign(C) C
 }
