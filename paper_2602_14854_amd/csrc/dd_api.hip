@@ -49,7 +49,8 @@ enum Kind {
   K_AUG_FORM, K_GEMM_QR_A, K_AUG_SVD, K_GEMM_VHAT, K_CHOL, K_GEMM_QR_VHAT, K_ANG_REDUCE,
   K_ADV_PREP, K_KSTEP, K_GEMM_QR_K, K_SPATIAL_REDUCE, K_ADV_SSTEP, K_LSTEP, K_GEMM_QR_L, K_TRUNC,
   K_GEMM_FINAL_U, K_GEMM_FINAL_V, K_COLL_PREP, K_COLL_KSTEP, K_COLL_REDUCE, K_COLL_SSTEP,
-  K_COLL_LSTEP, K_GEMM_QR_KC, K_GEMM_QR_LC, K_COUNT
+  K_COLL_LSTEP, K_GEMM_QR_KC, K_GEMM_QR_LC, K_GEMM_QR_K_IP, K_GEMM_QR_L_IP, K_GEMM_QR_KC_IP, K_GEMM_QR_LC_IP,
+  K_COUNT
 };
 
 const char* const kKindName[K_COUNT] = {
@@ -57,7 +58,8 @@ const char* const kKindName[K_COUNT] = {
   "k_gemm[QR V-hat]", "k_ang_reduce", "s_adv_prep", "k_kstep", "k_gemm[QR K1]", "k_spatial_reduce",
   "s_adv_sstep", "k_lstep", "k_gemm[QR L1]", "s_trunc", "k_gemm[U=Q*Bu]", "k_gemm[V=QL*Bv]",
   "s_coll_prep", "k_coll_kstep", "k_coll_reduce", "s_coll_sstep", "k_coll_lstep",
-  "k_gemm[QR K1 collision]", "k_gemm[QR L1 collision]",
+  "k_gemm[QR K1 collision]", "k_gemm[QR L1 collision]", "k_gemm[QR K1 in place]", "k_gemm[QR L1 in place]",
+  "k_gemm[QR K1 collision in place]", "k_gemm[QR L1 collision in place]",
 };
 
 struct Layout {
@@ -66,7 +68,7 @@ struct Layout {
   int off[48];
   size_t bytes;
   // byte offsets of the arena segments
-  size_t oU, oV, oS, oA, oZ, oQh, oQh2, oK1, oK2, oAL, oAL2, oGP, oSM, oRho, oIn, oCs, oCt, oQ, oInt, oFlags;
+  size_t oU, oV, oS, oA, oZ, oQh, oK1, oK2, oAL, oAL2, oGP, oSM, oRho, oIn, oCs, oCt, oQ, oInt, oFlags;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -177,6 +179,7 @@ Layout make_layout(const dd_dlra_config* c) {
   f[k++] = take(R);        // Qv
   for (int i = 0; i < 6; ++i) f[k++] = take(T * T);  // W1..W6
   f[k++] = take(MA * MA);  // RinvA
+  f[k++] = take(1);        // Skip (the last Cholesky-QR pass may be skipped)
   L.smallStride = o;
   // arena
   const size_t d8 = sizeof(double);
@@ -195,7 +198,6 @@ Layout make_layout(const dd_dlra_config* c) {
   L.oA = seg(ns * L.M * MA * d8);
   L.oZ = seg(ns * L.M * MA * d8);
   L.oQh = seg(ns * L.M * T * es);
-  L.oQh2 = seg(ns * L.M * T * es);
   L.oK1 = seg(ns * L.N * T * es);
   L.oK2 = seg(ns * L.N * T * es);
   L.oAL = seg(ns * L.M * T * es);
@@ -254,7 +256,6 @@ void fill_dev(Dev& d, const Layout& L, const dd_dlra_config* c, char* base) {
   d.A = (double*)(base + L.oA);
   d.Z = (double*)(base + L.oZ);
   d.Qh = (void*)(base + L.oQh);
-  d.Qh2 = (void*)(base + L.oQh2);
   d.K1 = (void*)(base + L.oK1);
   d.K2 = (void*)(base + L.oK2);
   d.AL = (void*)(base + L.oAL);
@@ -290,6 +291,7 @@ void fill_dev(Dev& d, const Layout& L, const dd_dlra_config* c, char* base) {
   d.oSig = f[k++]; d.oMv = f[k++]; d.oCrow = f[k++]; d.oGs = f[k++]; d.oGt = f[k++]; d.oQv = f[k++];
   d.oW1 = f[k++]; d.oW2 = f[k++]; d.oW3 = f[k++]; d.oW4 = f[k++]; d.oW5 = f[k++]; d.oW6 = f[k++];
   d.oRinvA = f[k++];
+  d.oSkip = f[k++];
 }
 
 std::string check_factors(const dd_dlra_config* c, const Layout& L, const int32_t* rank, const double* const* U,
@@ -369,11 +371,11 @@ hipEvent_t next_event(dd_dlra_handle h) {
 // once per subdomain (the plain per-subdomain mode); with profiling on (and
 // not capturing a graph) the phase is bracketed by a pair of events.
 // Phases whose launch reads one set of buffers and overwrites another, so
-// that launching them again leaves the same result (the in-place second pass
-// of the augmentation QR and the small kernels are not).
+// that launching them again leaves the same result (the in-place Cholesky-QR
+// passes and the small kernels are not).
 bool repeatable(int kind) {
   switch (kind) {
-    case K_AUG_FORM: case K_GEMM_VHAT: case K_GEMM_QR_VHAT: case K_ANG_REDUCE: case K_KSTEP: case K_GEMM_QR_K:
+    case K_AUG_FORM: case K_GEMM_VHAT: case K_ANG_REDUCE: case K_KSTEP: case K_GEMM_QR_K:
     case K_SPATIAL_REDUCE: case K_LSTEP: case K_GEMM_QR_L: case K_GEMM_FINAL_U: case K_GEMM_FINAL_V:
     case K_COLL_KSTEP: case K_COLL_REDUCE: case K_COLL_LSTEP: case K_GEMM_QR_KC: case K_GEMM_QR_LC:
       return true;
@@ -437,15 +439,20 @@ void phase(dd_dlra_handle h, int kind, F&& f) {
 }
 
 // Shifted Cholesky QR with three passes on X (rows x n; n = dim of kind
-// ndim) leaving Q in Y (X is used as scratch); the R factors accumulate in
-// the small workspace.  With final_dst set, the last product writes there
-// instead (stride ysd_final, optional row scale, Rinv scaled by bscale);
-// with s_dst set, the last Cholesky pass also stores Racc^T there as the
-// coefficient matrix of each subdomain.  With defer_last, the last product
-// is left to the caller: Q = X Rinv with Rinv in the small workspace.
+// ndim) leaving Q in Y: the first pass reads X and writes Y, the second and
+// third work on Y in place (each strip of rows is read completely before it
+// is written); the R factors accumulate in the small workspace.  When the
+// second pass takes the near-identity factor (its Gram within 1e-3 of the
+// identity), its output is already orthonormal to rounding: the third
+// Cholesky pass then takes R = I and its in-place product exits at once.  With final_dst set, the last
+// product writes there instead (stride final_sd, optional row scale, Rinv
+// scaled by bscale); with s_dst set, the last Cholesky pass also stores
+// Racc^T there as the coefficient matrix of each subdomain.  With
+// defer_last, the last product is left to the caller: Q = Y Rinv with Rinv
+// in the small workspace.
 void chol_qr3(dd_dlra_handle h, int axis, int ndim, void* X, void* Y, int64_t sdstride, int rows, bool cells,
               double* final_dst, int64_t final_sd, const double* final_rowscale, double bscale, int gemm_kind,
-              double* s_dst = nullptr, bool defer_last = false) {
+              int ip_kind, double* s_dst = nullptr, bool defer_last = false) {
   const Dev& d = h->d;
   hipStream_t st = h->stream;
   const int ngp = cells ? d.nwgN : d.nwgM;
@@ -457,21 +464,21 @@ void chol_qr3(dd_dlra_handle h, int axis, int ndim, void* X, void* Y, int64_t sd
                     true, d.oFill, cells, true, st);
   });
   phase(h, K_CHOL, [&](int s0, int ns) {
-    dd::launch_chol(d, axis, s0, ns, ndim, rows, ngp, false, 2, 1.0, false, d.oRinv, d.oRacc, d.T, st);
+    dd::launch_chol(d, axis, s0, ns, ndim, rows, ngp, false, 2, 1.0, false, d.oRinv, d.oRacc, d.T, st, nullptr, 1);
   });
-  phase(h, gemm_kind, [&](int s0, int ns) {
-    dd::launch_gemm(d, axis, s0, ns, Y, false, sdstride, rows, ndim, ndim, d.oRinv, d.T, X, false, sdstride, nullptr,
+  phase(h, ip_kind, [&](int s0, int ns) {
+    dd::launch_gemm(d, axis, s0, ns, Y, false, sdstride, rows, ndim, ndim, d.oRinv, d.T, Y, false, sdstride, nullptr,
                     true, d.oFill, cells, true, st);
   });
   phase(h, K_CHOL, [&](int s0, int ns) {
-    dd::launch_chol(d, axis, s0, ns, ndim, rows, ngp, false, 2, bscale, false, d.oRinv, d.oRacc, d.T, st, s_dst);
+    dd::launch_chol(d, axis, s0, ns, ndim, rows, ngp, false, 2, bscale, false, d.oRinv, d.oRacc, d.T, st, s_dst, 2);
   });
   if (defer_last) return;
   void* dst = final_dst ? (void*)final_dst : Y;
   const int64_t dsd = final_dst ? final_sd : sdstride;
-  phase(h, gemm_kind, [&](int s0, int ns) {
-    dd::launch_gemm(d, axis, s0, ns, X, false, sdstride, rows, ndim, ndim, d.oRinv, d.T, dst, final_dst != nullptr,
-                    dsd, final_rowscale, false, d.oFill, cells, true, st);
+  phase(h, final_dst ? gemm_kind : ip_kind, [&](int s0, int ns) {
+    dd::launch_gemm(d, axis, s0, ns, Y, false, sdstride, rows, ndim, ndim, d.oRinv, d.T, dst, final_dst != nullptr,
+                    dsd, final_rowscale, false, d.oFill, cells, true, st, false, final_dst ? -1 : d.oSkip);
   });
 }
 
@@ -486,7 +493,7 @@ void enqueue_advection(dd_dlra_handle h, int axis) {
   for (int pass = 0; pass < 3; ++pass) {
     phase(h, K_CHOL, [&](int s0, int ns) {
       dd::launch_chol(d, axis, s0, ns, dd::DIM_M0, d.M, d.nwgM, pass == 0, pass == 0 ? 1 : 2, 1.0, pass == 0,
-                      d.oRinvA, d.oRaccA, d.MA, st);
+                      d.oRinvA, d.oRaccA, d.MA, st, nullptr, pass);
     });
     if (pass == 2) break;
     // pass 0: Z = A P R^-1; pass 1: Z <- Z R^-1 in place (each strip of rows
@@ -501,16 +508,17 @@ void enqueue_advection(dd_dlra_handle h, int axis) {
     dd::launch_gemm(d, axis, s0, ns, d.A, true, sdMA, d.M, dd::DIM_M0, dd::DIM_T, d.oCoef, d.MA, d.Qh, false, sdMT,
                     nullptr, true, d.oFill, false, true, st);
   });
-  // two Cholesky QR passes make V-hat orthonormal to working precision
+  // two Cholesky QR passes in place make V-hat orthonormal to working
+  // precision (the second is skipped when the first took the near-identity
+  // factor)
   for (int pass = 0; pass < 2; ++pass) {
-    void* src = pass == 0 ? d.Qh : d.Qh2;
-    void* dst = pass == 0 ? d.Qh2 : d.Qh;
     phase(h, K_CHOL, [&](int s0, int ns) {
-      dd::launch_chol(d, axis, s0, ns, dd::DIM_T, d.M, d.nwgM, false, 0, 1.0, false, d.oRinv, d.oRacc, d.T, st);
+      dd::launch_chol(d, axis, s0, ns, dd::DIM_T, d.M, d.nwgM, false, 0, 1.0, false, d.oRinv, d.oRacc, d.T, st,
+                      nullptr, pass + 1);
     });
     phase(h, K_GEMM_QR_VHAT, [&](int s0, int ns) {
-      dd::launch_gemm(d, axis, s0, ns, src, false, sdMT, d.M, dd::DIM_T, dd::DIM_T, d.oRinv, d.T, dst, false, sdMT,
-                      nullptr, pass == 0, d.oFill, false, true, st);
+      dd::launch_gemm(d, axis, s0, ns, d.Qh, false, sdMT, d.M, dd::DIM_T, dd::DIM_T, d.oRinv, d.T, d.Qh, false, sdMT,
+                      nullptr, pass == 0, d.oFill, false, true, st, false, pass == 1 ? d.oSkip : -1);
     });
   }
   // angular Galerkin matrices, eigen-split of C, K-step coefficients
@@ -518,14 +526,15 @@ void enqueue_advection(dd_dlra_handle h, int axis) {
   phase(h, K_ADV_PREP, [&](int s0, int ns) { dd::launch_adv_prep(d, axis, s0, ns, st); });
   // Algorithm 1/2 steps 1-2: K-step, QR
   phase(h, K_KSTEP, [&](int s0, int ns) { dd::launch_kstep(d, axis, s0, ns, st); });
-  chol_qr3(h, axis, dd::DIM_T, d.K1, d.K2, sdNT, d.N, true, nullptr, 0, nullptr, 1.0, K_GEMM_QR_K);
+  chol_qr3(h, axis, dd::DIM_T, d.K1, d.K2, sdNT, d.N, true, nullptr, 0, nullptr, 1.0, K_GEMM_QR_K, K_GEMM_QR_K_IP);
   // step 3: S-step
   phase(h, K_SPATIAL_REDUCE, [&](int s0, int ns) { dd::launch_spatial_reduce(d, axis, s0, ns, d.K2, st); });
   phase(h, K_ADV_SSTEP, [&](int s0, int ns) { dd::launch_adv_sstep(d, axis, s0, ns, st); });
   // steps 4-5: L-step, weighted QR
   phase(h, K_LSTEP, [&](int s0, int ns) { dd::launch_lstep(d, axis, s0, ns, st); });
-  // (the last product, Q_L = X2 Rinv, is folded into the final V product)
-  chol_qr3(h, axis, dd::DIM_T, d.AL, d.AL2, sdMT, d.M, false, nullptr, 0, nullptr, 1.0, K_GEMM_QR_L, nullptr, true);
+  // (the last product, Q_L = Y Rinv, is folded into the final V product)
+  chol_qr3(h, axis, dd::DIM_T, d.AL, d.AL2, sdMT, d.M, false, nullptr, 0, nullptr, 1.0, K_GEMM_QR_L, K_GEMM_QR_L_IP,
+           nullptr, true);
   // Algorithm 5: truncation, then rotate the bases into the state
   phase(h, K_TRUNC, [&](int s0, int ns) { dd::launch_trunc(d, axis, s0, ns, true, st); });
   phase(h, K_GEMM_FINAL_U, [&](int s0, int ns) {
@@ -533,7 +542,7 @@ void enqueue_advection(dd_dlra_handle h, int axis) {
                     (int64_t)d.N * d.R, nullptr, false, -1, true, false, st);
   });
   phase(h, K_GEMM_FINAL_V, [&](int s0, int ns) {
-    dd::launch_gemm(d, axis, s0, ns, d.AL, false, sdMT, d.M, dd::DIM_T, dd::DIM_RNEW, d.oBv, d.T, d.V, true,
+    dd::launch_gemm(d, axis, s0, ns, d.AL2, false, sdMT, d.M, dd::DIM_T, dd::DIM_RNEW, d.oBv, d.T, d.V, true,
                     (int64_t)d.M * d.R, d.isw, false, -1, false, false, st, /*set_rank=*/true);
   });
 }
@@ -545,13 +554,15 @@ void enqueue_collision(dd_dlra_handle h) {
   phase(h, K_COLL_PREP, [&](int s0, int ns) { dd::launch_coll_prep(d, s0, ns, st); });
   phase(h, K_COLL_KSTEP, [&](int s0, int ns) { dd::launch_coll_kstep(d, s0, ns, st); });
   // QR of K1; the last product writes U^1 = Q / h straight into the state
-  chol_qr3(h, 0, dd::DIM_R, d.K1, d.K2, sdNT, d.N, true, d.U, (int64_t)d.N * d.R, nullptr, 1.0 / d.h, K_GEMM_QR_KC);
+  chol_qr3(h, 0, dd::DIM_R, d.K1, d.K2, sdNT, d.N, true, d.U, (int64_t)d.N * d.R, nullptr, 1.0 / d.h, K_GEMM_QR_KC,
+           K_GEMM_QR_KC_IP);
   phase(h, K_COLL_REDUCE, [&](int s0, int ns) { dd::launch_coll_reduce(d, s0, ns, st); });
   phase(h, K_COLL_SSTEP, [&](int s0, int ns) { dd::launch_coll_sstep(d, s0, ns, st); });
   phase(h, K_COLL_LSTEP, [&](int s0, int ns) { dd::launch_coll_lstep(d, s0, ns, st); });
   // weighted QR of L1 (Algorithm 3, step 5): V^1 = Q / sqrt(w) straight into
   // the state, S^1 = RL^T from the last Cholesky pass
-  chol_qr3(h, 0, dd::DIM_R, d.AL, d.AL2, sdMT, d.M, false, d.V, (int64_t)d.M * d.R, d.isw, 1.0, K_GEMM_QR_LC, d.S);
+  chol_qr3(h, 0, dd::DIM_R, d.AL, d.AL2, sdMT, d.M, false, d.V, (int64_t)d.M * d.R, d.isw, 1.0, K_GEMM_QR_LC,
+           K_GEMM_QR_LC_IP, d.S);
 }
 
 void enqueue_step(dd_dlra_handle h) {

@@ -54,7 +54,6 @@ struct Dev {
   double* A;               // [nsub][MA][M]   weighted augmentation matrix
   double* Z;               // [nsub][MA][M]
   void* Qh;                // [nsub][T][M]    sqrt(w) * V-hat
-  void* Qh2;               // [nsub][T][M]
   void* K1;                // [nsub][T][N]
   void* K2;                // [nsub][T][N]
   void* AL;                // [nsub][T][M]
@@ -75,7 +74,7 @@ struct Dev {
   // small workspace offsets (doubles)
   int oRaccA, oCoef, oFill, oRinv, oRacc, oCp, oCn, oAm, oM0, oMm, oMp, oGLo, oGHi, oGLoN, oGHiN;
   int oEp, oEn, oOlo, oOhi, oTm, oGm, oGp, oBKlo, oBKhi, oS1, oS2, oP0, oPm, oPp, oBu, oBv;
-  int oSig, oMv, oCrow, oGs, oGt, oQv, oW1, oW2, oW3, oW4, oW5, oW6, oRinvA;
+  int oSig, oMv, oCrow, oGs, oGt, oQv, oW1, oW2, oW3, oW4, oW5, oW6, oRinvA, oSkip;
 };
 
 __host__ __device__ inline int neighbour(const Dev& d, int s, int axis, int side) {
@@ -155,7 +154,8 @@ void launch_aug_form(const Dev& d, int axis, int sd0, int nsd, hipStream_t st);
 // precision mode (QR and SVD products).
 void launch_gemm(const Dev& d, int axis, int sd0, int nsd, const void* X, bool x64, int64_t xsd, int rows,
                  int kdim, int ndim, int boff, int bld, void* Y, bool y64, int64_t ysd, const double* rowscale,
-                 bool gram, int fill_off, bool rows_are_cells, bool exact, hipStream_t st, bool set_rank = false);
+                 bool gram, int fill_off, bool rows_are_cells, bool exact, hipStream_t st, bool set_rank = false,
+                 int skip_off = -1);
 void launch_ang_reduce(const Dev& d, int axis, int sd0, int nsd, hipStream_t st);
 void launch_kstep(const Dev& d, int axis, int sd0, int nsd, hipStream_t st);
 void launch_spatial_reduce(const Dev& d, int axis, int sd0, int nsd, const void* Q, hipStream_t st);
@@ -167,7 +167,8 @@ void launch_moments(const Dev& d, int nmom, hipStream_t st);
 // small (one workgroup per subdomain) kernels
 void launch_aug_svd(const Dev& d, int axis, int sd0, int nsd, hipStream_t st);
 void launch_chol(const Dev& d, int axis, int sd0, int nsd, int ndim, int rows, int ngp, bool shift,
-                 int acc_mode, double bscale, bool pivot, int oRinv, int oRacc, int ld, hipStream_t st, double* sout = nullptr);
+                 int acc_mode, double bscale, bool pivot, int oRinv, int oRacc, int ld, hipStream_t st, double* sout = nullptr,
+                 int skip_mode = 0);
 void launch_adv_prep(const Dev& d, int axis, int sd0, int nsd, hipStream_t st);
 void launch_adv_sstep(const Dev& d, int axis, int sd0, int nsd, hipStream_t st);
 void launch_trunc(const Dev& d, int axis, int sd0, int nsd, bool fold_rinv, hipStream_t st);

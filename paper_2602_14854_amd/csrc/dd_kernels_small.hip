@@ -105,12 +105,36 @@ void launch_aug_svd(const Dev& d, int axis, int sd0, int nsd, hipStream_t st) {
 // Slots have leading dimension ld.  With sout set (acc_mode 2 only), the
 // transposed final factor Racc^T, zero-padded to R x R, is also stored as the
 // subdomain's coefficient matrix (the S of X = Q S^T).
+// skip_mode 1 (a middle pass) records in the skip slot whether this pass took
+// the near-identity factor: its series remainder is below 3e-16, so its
+// output is orthonormal to rounding, and the next, last pass (skip_mode 2)
+// takes R = I without reading its Gram -- Rinv = bscale I, Racc unchanged --
+// while its product, if it only re-orthonormalises in place, exits at once.
 template <int NMAX>
 __global__ __launch_bounds__(NTHR) void s_chol(Dev d, int axis, int sd0, int ndim, int rows, int ngp, int shift,
                                               int acc_mode, double bscale, int pivot, int oRinv, int oRacc, int ld,
-                                              double* sout) {
+                                              double* sout, int skip_mode) {
   const int s = sd0 + blockIdx.x;
   const int n = dim_of(d, s, axis, ndim);
+  if (skip_mode == 2 && small_of(d, s)[d.oSkip] != 0.0) {
+    double* sm = small_of(d, s);
+    for (int idx = threadIdx.x; idx < n * n; idx += NTHR) {
+      const int i = idx % n, j = idx / n;
+      sm[oRinv + i + j * ld] = i == j ? bscale : 0.0;
+    }
+    for (int j = threadIdx.x; j < n; j += NTHR) sm[d.oFill + j] = 0.0;
+    if (sout != nullptr) {
+      const int R = d.R;
+      double* Sg = sout + (int64_t)s * R * R;
+      for (int idx = threadIdx.x; idx < R * R; idx += NTHR) {
+        const int i = idx % R, j = idx / R;
+        const double v = (i < n && j < n) ? sm[oRacc + j + i * ld] : 0.0;
+        Sg[idx] = v;
+        if (!isfinite(v)) atomicOr(d.flags, FLAG_NONFINITE);
+      }
+    }
+    return;
+  }
   __shared__ double G[LDA * CAP];
   __shared__ double X[LDA * CAP];
   __shared__ double E2[LDA * CAP];
@@ -145,6 +169,7 @@ __global__ __launch_bounds__(NTHR) void s_chol(Dev d, int axis, int sd0, int ndi
   // E^4 otherwise (remainder 0.25 |E|^5 <= 2.5e-16); R R^-1 = I to the same
   // order, and any R with G = R^T R gives an orthonormal Q = X R^-1.
   int near_order = 0;
+  double fro2 = 1.0;
   if (!pivot && !shift) {
     __shared__ double red[NTHR];
     double part = 0.0;
@@ -153,9 +178,10 @@ __global__ __launch_bounds__(NTHR) void s_chol(Dev d, int axis, int sd0, int ndi
       const double e = G[i + j * LDA] - (i == j ? 1.0 : 0.0);
       part = fma(e, e, part);
     }
-    const double fro2 = block_sum(part, red);
+    fro2 = block_sum(part, red);
     near_order = fro2 <= 1e-10 ? 2 : (fro2 <= 1e-6 ? 4 : 0);
   }
+  if (skip_mode == 1 && threadIdx.x == 0) small_of(d, s)[d.oSkip] = near_order > 0 ? 1.0 : 0.0;
   if (near_order > 0) {
     for (int idx = threadIdx.x; idx < n * n; idx += NTHR) {
       const int i = idx % n, j = idx / n;
@@ -254,11 +280,11 @@ __global__ __launch_bounds__(NTHR) void s_chol(Dev d, int axis, int sd0, int ndi
 }
 
 void launch_chol(const Dev& d, int axis, int sd0, int nsd, int ndim, int rows, int ngp, bool shift, int acc_mode,
-                 double bscale, bool pivot, int oRinv, int oRacc, int ld, hipStream_t st, double* sout) {
+                 double bscale, bool pivot, int oRinv, int oRacc, int ld, hipStream_t st, double* sout, int skip_mode) {
   const int cap = ndim == DIM_M0 ? d.MA : (ndim == DIM_T ? d.T : d.R);
 #define DD_CHOL(NMAX)                                                                                             \
   hipLaunchKernelGGL(s_chol<NMAX>, dim3(nsd), dim3(NTHR), 0, st, d, axis, sd0, ndim, rows, ngp, shift ? 1 : 0,   \
-                     acc_mode, bscale, pivot ? 1 : 0, oRinv, oRacc, ld, sout)
+                     acc_mode, bscale, pivot ? 1 : 0, oRinv, oRacc, ld, sout, skip_mode)
   if (cap <= 16) DD_CHOL(16);
   else if (cap <= 32) DD_CHOL(32);
   else if (cap <= 48) DD_CHOL(48);

@@ -133,12 +133,14 @@ __global__ __launch_bounds__(NTHR) void k_aug_form(Dev d, int axis, int sd0) {
 // deterministic pseudo-random values (used to complete a basis where the
 // data carry no information).  With set_rank, the first workgroup of each
 // subdomain also commits the truncated rank (the product reads only the
-// augmented and new ranks, never the current one).
+// augmented and new ranks, never the current one).  With skip_off >= 0, a
+// subdomain whose skip slot is set (B is the identity, Y is X) does nothing.
 // ----------------------------------------------------------------------------
 template <class SI, class S, int P, int NCB, int KS>
 __global__ __launch_bounds__(NTHR) void k_gemm(Dev d, int axis, int sd0, const void* X, int64_t xsd, int rows,
                                                int kdim, int ndim, int boff, int bld, void* Y, int64_t ysd,
-                                               const double* rowscale, int gram, int fill_off, int set_rank) {
+                                               const double* rowscale, int gram, int fill_off, int set_rank,
+                                               int skip_off) {
   using F = typename Prec<P>::F;
   using Acc = typename Prec<P>::Acc;
   constexpr int LD = strip_ld<NCB>();
@@ -153,6 +155,7 @@ __global__ __launch_bounds__(NTHR) void k_gemm(Dev d, int axis, int sd0, const v
   double* Ys = lds + frag_doubles<P>(KS * NCB * 64) + wave * 16 * LD;
   __shared__ int fillm[16 * NCB];
   const double* sm = small_of(d, s);
+  if (skip_off >= 0 && sm[skip_off] != 0.0) return;  // identity in place
   for (int idx = threadIdx.x; idx < KS * NCB * 64; idx += NTHR) {
     const int l = idx & 63, f = idx >> 6, cb = f % NCB, u = f / NCB;
     const int kc = sub_col<P>(u, l >> 4), col = 16 * cb + (l & 15);
@@ -1189,7 +1192,7 @@ static int dim_cap(const Dev& d, int which) { return which == DIM_M0 ? d.MA : (w
 
 void launch_gemm(const Dev& d, int axis, int sd0, int nsd, const void* X, bool x64, int64_t xsd, int rows, int kdim,
                  int ndim, int boff, int bld, void* Y, bool y64, int64_t ysd, const double* rowscale, bool gram,
-                 int fill_off, bool rows_are_cells, bool exact, hipStream_t st, bool set_rank) {
+                 int fill_off, bool rows_are_cells, bool exact, hipStream_t st, bool set_rank, int skip_off) {
   const int nwg = rows_are_cells ? d.nwgN : d.nwgM;
   auto go = [&](auto ti, auto to, auto pc) {
     using SI = typename decltype(ti)::type;
@@ -1201,7 +1204,7 @@ void launch_gemm(const Dev& d, int axis, int sd0, int nsd, const void* X, bool x
         constexpr int KS = sub_cap<P>(decltype(k)::value);
         const size_t lds = strip_bytes<P, NC>(KS * NC * 64);
         hipLaunchKernelGGL((k_gemm<SI, SO, P, NC, KS>), dim3(nwg, nsd), dim3(NTHR), lds, st, d, axis, sd0, X, xsd,
-                           rows, kdim, ndim, boff, bld, Y, ysd, rowscale, gram ? 1 : 0, fill_off, set_rank ? 1 : 0);
+                           rows, kdim, ndim, boff, bld, Y, ysd, rowscale, gram ? 1 : 0, fill_off, set_rank ? 1 : 0, skip_off);
       });
     });
   };
