@@ -470,14 +470,19 @@ __global__ __launch_bounds__(NTHR) void s_adv_sstep(Dev d, int axis, int sd0) {
   double* Xhn = sm + d.oW4;  // t x rh
   const int oX = 2 * T * T;
   {
-    const PartBlock blk[6] = {{0, t, t, t, Gm, T, ih},
-                              {T * T, t, t, t, Gp, T, ih},
+    const PartBlock blk[5] = {{0, t, t, t, Gp, T, ih},
                               {oX, T, t, r, Xlo, T, 1.0},
                               {oX + T * R, T, t, r, Xhi, T, 1.0},
                               {oX + 2 * T * R, T, t, rl, Xln, T, 1.0},
                               {oX + 3 * T * R, T, t, rh, Xhn, T, 1.0}};
-    sum_partials_blocks<6>(d, s, d.nwgN, blk);
+    sum_partials_blocks<5>(d, s, d.nwgN, blk);
   }
+  // Gm = -Gp^T (the spatial reduction forms Gp only)
+  for (int idx = threadIdx.x; idx < t * t; idx += NTHR) {
+    const int i = idx % t, j = idx / t;
+    Gm[i + j * T] = -Gp[j + i * T];
+  }
+  __syncthreads();
   double* W5 = sm + d.oW5;
   double* W6 = sm + d.oW6;
   double* BKlo = sm + d.oBKlo;

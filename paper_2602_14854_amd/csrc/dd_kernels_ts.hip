@@ -522,147 +522,149 @@ __global__ __launch_bounds__(NTHR) void k_kstep(Dev d, int axis, int sd0) {
 // Spatial Galerkin matrices of the S- and L-steps (eqs. advx_evolS/L):
 //   Gm[i,j] = sum_p Q[p,i] (Q[p,j] - Q[p-e,j])   (zero beyond the low face)
 //   Gp[i,j] = sum_p Q[p,i] (Q[p+e,j] - Q[p,j])   (zero beyond the high face)
-// with Q = h U^1; dividing by h gives h^2 U^T D-+_0 U.  Also the face
-// products of the frozen inflow data (t x r blocks):
+// with Q = h U^1.  Both follow from one product: with
+//   B[i,j] = sum_{p not on the high face} Q[p,i] Q[p+e,j]  and  C = Q^T Q,
+// shifting p by e shows sum_{p not on the low face} Q[p,i] Q[p-e,j] =
+// B[j,i], so Gp = B - C and Gm = C - B^T = -Gp^T (C is symmetric).  Gp is
+// formed as sum_p Q[p,i] (Q[p+e,j] - Q[p,j]) with the difference taken per
+// element in FP64 (exact for stored values, no cancellation between B and
+// C), and the S-step kernel sets Gm = -Gp^T.
+// Also the face products of the frozen inflow data (t x r blocks):
 //   Xlo = Q[lo face]^T U[lo face],   Xln = Q[lo face]^T U_lo[its hi face],
 //   Xhi = Q[hi face]^T U[hi face],   Xhn = Q[hi face]^T U_hi[its lo face].
-// Partial layout: Gm @0, Gp @T*T (t x t, ld t), Xlo @2T*T, Xhi @2T*T+T*R,
-// Xln @2T*T+2T*R, Xhn @2T*T+3T*R (t x r_*, ld T).
+// Gp: every wavefront walks its own strips of cells; the face products run
+// over the face cells gathered into strips of 16 (items dealt to the
+// wavefronts of all workgroups).  Partial layout: Gp @0 (t x t, ld t),
+// Xlo @2T*T, Xhi @2T*T+T*R, Xln @2T*T+2T*R, Xhn @2T*T+3T*R (t x r_*, ld T).
 // ----------------------------------------------------------------------------
 template <class S, int NCT, int NCR>
 __global__ __launch_bounds__(NTHR) void k_spatial_reduce(Dev d, int axis, int sd0, const void* Q) {
-  // wavefronts 0-1 form Gm and the low-face products, wavefronts 2-3 Gp and
-  // the high-face products; each pair walks the same strips
-  constexpr int LD = strip_ld<NCT>();
-  constexpr int LDR = strip_ld<NCR>();
-  constexpr int KS = 4 * NCT, KSR_ = 4 * NCR;
+  // Operands are loaded straight into the matrix-core lane layout (lane:
+  // column 16 c + l mod 16 of Q, row 4 k + l / 16 of the strip): a strip of
+  // 16 rows reads 16 columns x 16 rows, whole cache lines, with no LDS
+  // transposition.
   constexpr int NQ = NCT * NCT;
   constexpr int NX = NCT * NCR;
-  constexpr int NACC = NQ + 2 * NX;
   const int s = sd0 + blockIdx.y;
   const int t = d.tdim[s];
   const int N = d.N, T = d.T, R = d.R;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int l16 = lane & 15, kq = lane >> 4;
-  const bool low = wave < 2;
-  const int nbr = neighbour(d, s, axis, low ? -1 : +1);
-  const int r = d.rank[s], rn = nbr >= 0 ? d.rank[nbr] : 0;
   extern __shared__ double lds[];
-  double* Qs = lds + wave * (2 * 16 * LD + 2 * 16 * LDR);  // Q strip, its one-sided difference,
-  double* Ds = Qs + 16 * LD;                               // then U and U_nbr rows on the face
-  double* Uo = Ds + 16 * LD;
-  double* Un = Uo + 16 * LDR;
   const S* Qsd = (const S*)Q + (int64_t)s * N * T;
-  const double* Us = d.U + (int64_t)s * N * R;
-  const double* Unb = nbr >= 0 ? d.U + (int64_t)nbr * N * R : d.U;
   const int e = axis == 0 ? 1 : d.lnx;
   const int na = axis == 0 ? d.lnx : d.lny;
-  dbl4 acc[NACC];  // [0, NQ): Gm or Gp; then own-face and neighbour-face products
-  zero_acc<NACC>(acc);
+  double* out = gpart_of(d, s) + (int64_t)blockIdx.x * d.gpTile;
+  const int lo = neighbour(d, s, axis, -1), hi = neighbour(d, s, axis, +1);
+  const int r = d.rank[s], rl = lo >= 0 ? d.rank[lo] : 0, rh = hi >= 0 ? d.rank[hi] : 0;
+  const double* Us = d.U + (int64_t)s * N * R;
+  dbl4 acc[NQ + 4 * NX];  // Gp, then Xlo, Xln, Xhi, Xhn
+  zero_acc<NQ + 4 * NX>(acc);
   const int nst = ceil_div(N, 16);
-  const int stride = gridDim.x * 2;
-  S b0[KS], bn[KS];
+  const int stride = gridDim.x * NW;
+  S a0[4][NCT], a1[4][NCT];  // Q and Q shifted by +e, k steps x column blocks
   auto load = [&](int st_) {
-    const int p_ = st_ * 16 + l16;
-    const bool rin_ = p_ < N;
-    const int ia_ = axis == 0 ? p_ % d.lnx : p_ / d.lnx;
-    // neighbour row across the face this wavefront differences over
-    const bool hn_ = low ? (rin_ && ia_ > 0) : (rin_ && ia_ < na - 1);
-    const int pn_ = low ? p_ - e : p_ + e;
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      const int c = 4 * ks + kq;
-      const int64_t col = (int64_t)c * N;
-      b0[ks] = (rin_ && c < t) ? Qsd[col + p_] : (S)0;
-      bn[ks] = (hn_ && c < t) ? Qsd[col + pn_] : (S)0;
-    }
-  };
-  int st = blockIdx.x * 2 + (wave & 1);
-  if (st < nst) load(st);
-  for (; st < nst; st += stride) {
-    const int p = st * 16 + l16;
-    const bool rin = p < N;
-    const int ix = p % d.lnx, iy = p / d.lnx;
-    const int ia = axis == 0 ? ix : iy;
-    const int f = axis == 0 ? iy : ix;
-    const bool face = low ? (rin && ia == 0) : (rin && ia == na - 1);
-    double x0[KS], xn[KS];
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      x0[ks] = (double)b0[ks];
-      xn[ks] = (double)bn[ks];
-    }
-    if (st + stride < nst) load(st + stride);
-    const bool any_face = __any(face);
-    if (any_face) {
-      // the face cell of the neighbour that touches this cell
-      const int pf = face_cell(d, axis, low, f);
-      double uo[KSR_], un[KSR_];
-#pragma unroll
-      for (int ks = 0; ks < KSR_; ++ks) {
-        const int c = 4 * ks + kq;
-        uo[ks] = (face && c < r) ? Us[(int64_t)c * N + p] : 0.0;
-        un[ks] = (face && c < rn) ? Unb[(int64_t)c * N + pf] : 0.0;
-      }
-#pragma unroll
-      for (int ks = 0; ks < KSR_; ++ks) {
-        Uo[l16 * LDR + 4 * ks + kq] = uo[ks];
-        Un[l16 * LDR + 4 * ks + kq] = un[ks];
-      }
-    }
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      const int o = l16 * LD + 4 * ks + kq;
-      Qs[o] = x0[ks];
-      Ds[o] = low ? x0[ks] - xn[ks] : xn[ks] - x0[ks];
-    }
-    wave_sync();
-#pragma unroll
-    for (int kk = 0; kk < 16; kk += 4) {
-      const int o = (kk + kq) * LD + l16;
-      double fq[NCT], fd[NCT];
+    for (int kk = 0; kk < 4; ++kk) {
+      const int p_ = st_ * 16 + 4 * kk + kq;
+      const bool rin_ = p_ < N;
+      const int ia_ = axis == 0 ? p_ % d.lnx : p_ / d.lnx;
+      const bool hs_ = rin_ && ia_ < na - 1;  // p + e inside the subdomain
+      const int pr = rin_ ? p_ : 0, ps = hs_ ? p_ + e : 0;
 #pragma unroll
       for (int c = 0; c < NCT; ++c) {
-        fq[c] = Qs[o + 16 * c];
-        fd[c] = Ds[o + 16 * c];
+        const int col = 16 * c + l16;
+        const int cc = col < t ? col : 0;
+        const S v0 = Qsd[(int64_t)cc * N + pr];
+        const S v1 = Qsd[(int64_t)cc * N + ps];
+        a0[kk][c] = (rin_ && col < t) ? v0 : (S)0;
+        a1[kk][c] = (hs_ && col < t) ? v1 : (S)0;
+      }
+    }
+  };
+  int st = blockIdx.x * NW + wave;
+  if (st < nst) load(st);
+  // face products over the face cells, gathered into strips of 16: items
+  // (side, strip) dealt to the wavefronts of all workgroups, done while the
+  // first strip of Gp is in flight
+  const int flen = face_len(d, axis), nfs = ceil_div(flen, 16);
+  for (int item = blockIdx.x * NW + wave; item < 2 * nfs; item += stride) {
+    const int side = item / nfs;  // 0 low, 1 high (wave-uniform)
+    const int nb = side == 0 ? lo : hi;
+    const int rn = side == 0 ? rl : rh;
+    const double* Unb = nb >= 0 ? d.U + (int64_t)nb * N * R : d.U;
+    double q[4][NCT], uo[4][NCR], un[4][NCR];
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int fcell = (item % nfs) * 16 + 4 * kk + kq;
+      const bool ok = fcell < flen;
+      const int p = face_cell(d, axis, side == 1, ok ? fcell : 0);
+      const int pf = face_cell(d, axis, side == 0, ok ? fcell : 0);  // the neighbour's touching cell
+#pragma unroll
+      for (int c = 0; c < NCT; ++c) {
+        const int col = 16 * c + l16;
+        q[kk][c] = (ok && col < t) ? (double)Qsd[(int64_t)col * N + p] : 0.0;
       }
 #pragma unroll
-      for (int bi = 0; bi < NCT; ++bi)
+      for (int c = 0; c < NCR; ++c) {
+        const int col = 16 * c + l16;
+        uo[kk][c] = (ok && col < r) ? Us[(int64_t)col * N + p] : 0.0;
+        un[kk][c] = (ok && col < rn) ? Unb[(int64_t)col * N + pf] : 0.0;
+      }
+    }
+    if (side == 0) {
 #pragma unroll
-        for (int bj = 0; bj < NCT; ++bj) acc[bi * NCT + bj] = mfma64(fq[bi], fd[bj], acc[bi * NCT + bj]);
-      if (any_face) {
-        const int ou = (kk + kq) * LDR + l16;
-        double fo[NCR], fn[NCR];
-#pragma unroll
-        for (int c = 0; c < NCR; ++c) {
-          fo[c] = Uo[ou + 16 * c];
-          fn[c] = Un[ou + 16 * c];
-        }
+      for (int kk = 0; kk < 4; ++kk)
 #pragma unroll
         for (int bi = 0; bi < NCT; ++bi)
 #pragma unroll
           for (int bc = 0; bc < NCR; ++bc) {
-            acc[NQ + bi * NCR + bc] = mfma64(fq[bi], fo[bc], acc[NQ + bi * NCR + bc]);
-            acc[NQ + NX + bi * NCR + bc] = mfma64(fq[bi], fn[bc], acc[NQ + NX + bi * NCR + bc]);
+            acc[NQ + bi * NCR + bc] = mfma64(q[kk][bi], uo[kk][bc], acc[NQ + bi * NCR + bc]);
+            acc[NQ + NX + bi * NCR + bc] = mfma64(q[kk][bi], un[kk][bc], acc[NQ + NX + bi * NCR + bc]);
           }
-      }
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+        for (int bi = 0; bi < NCT; ++bi)
+#pragma unroll
+          for (int bc = 0; bc < NCR; ++bc) {
+            acc[NQ + 2 * NX + bi * NCR + bc] = mfma64(q[kk][bi], uo[kk][bc], acc[NQ + 2 * NX + bi * NCR + bc]);
+            acc[NQ + 3 * NX + bi * NCR + bc] = mfma64(q[kk][bi], un[kk][bc], acc[NQ + 3 * NX + bi * NCR + bc]);
+          }
     }
-    wave_sync();
   }
-  pair_reduce_acc<NACC>(acc, lds);
-  if ((wave & 1) == 0) {
-    double* out = gpart_of(d, s) + (int64_t)blockIdx.x * d.gpTile;
-    double* og = out + (low ? 0 : T * T);
-    double* oo = out + 2 * T * T + (low ? 0 : T * R);
-    double* on = out + 2 * T * T + 2 * T * R + (low ? 0 : T * R);
+  // Gp over all strips, every wavefront on its own strips
+  for (; st < nst; st += stride) {
+    double x0[4][NCT], x1[4][NCT];
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+      for (int c = 0; c < NCT; ++c) {
+        x0[kk][c] = (double)a0[kk][c];
+        x1[kk][c] = (double)a1[kk][c];
+      }
+    if (st + stride < nst) load(st + stride);
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+      for (int bi = 0; bi < NCT; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < NCT; ++bj)
+          acc[bi * NCT + bj] = mfma64(x0[kk][bi], x1[kk][bj] - x0[kk][bj], acc[bi * NCT + bj]);
+  }
+  wg_reduce_acc<NQ + 4 * NX>(acc, lds);
+  if (wave == 0) {
 #pragma unroll
     for (int bi = 0; bi < NCT; ++bi) {
 #pragma unroll
-      for (int bj = 0; bj < NCT; ++bj) store_block(og, t, t, t, bi, bj, acc[bi * NCT + bj], 1.0);
+      for (int bj = 0; bj < NCT; ++bj) store_block(out, t, t, t, bi, bj, acc[bi * NCT + bj], 1.0);
 #pragma unroll
       for (int bc = 0; bc < NCR; ++bc) {
-        store_block(oo, T, t, r, bi, bc, acc[NQ + bi * NCR + bc], 1.0);
-        store_block(on, T, t, rn, bi, bc, acc[NQ + NX + bi * NCR + bc], 1.0);
+        store_block(out + 2 * T * T, T, t, r, bi, bc, acc[NQ + bi * NCR + bc], 1.0);
+        store_block(out + 2 * T * T + 2 * T * R, T, t, rl, bi, bc, acc[NQ + NX + bi * NCR + bc], 1.0);
+        store_block(out + 2 * T * T + T * R, T, t, r, bi, bc, acc[NQ + 2 * NX + bi * NCR + bc], 1.0);
+        store_block(out + 2 * T * T + 3 * T * R, T, t, rh, bi, bc, acc[NQ + 3 * NX + bi * NCR + bc], 1.0);
       }
     }
   }
@@ -1257,9 +1259,8 @@ void launch_spatial_reduce(const Dev& d, int axis, int sd0, int nsd, const void*
       constexpr int NT = decltype(ct)::value;
       with_ncb(ncb_of(d.R), [&](auto cr) {
         constexpr int NR = decltype(cr)::value;
-        constexpr int NACC = NT * NT + 2 * NT * NR;
-        const size_t lds =
-            D8 * std::max<size_t>(NW * 2 * 16 * (strip_ld<NT>() + strip_ld<NR>()), (size_t)2 * NACC * 256);
+        constexpr int NACC = NT * NT + 4 * NT * NR;
+        const size_t lds = D8 * (size_t)NACC * 256;  // the workgroup reduction
         if constexpr (NR <= 2)  // stored ranks are at most 21
           hipLaunchKernelGGL((k_spatial_reduce<S, NT, NR>), dim3(d.nwgN, nsd), dim3(NTHR), lds, st, d, axis, sd0,
                              Q);
