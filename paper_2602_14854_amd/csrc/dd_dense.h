@@ -35,7 +35,7 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 // addresses; out-of-range values replaced by zero) before its first
 // v_mfma_f64_16x16x4f64, so a tile costs one load latency instead of one
 // per k.  The k loop has a compile-time length NK (steps of 4: k rounded up
-// to 16, 32 or 64) and runs as two accumulator chains.
+// to 16, 32, 48 or 64) and runs as two accumulator chains.
 template <int NK>
 __device__ __forceinline__ void mm_body(double* C, int ldc, const double* A, int lda, bool ta, const double* B,
                                         int ldb, bool tb, int m, int n, int k, double alpha, double beta,
@@ -83,6 +83,7 @@ __device__ __forceinline__ void mm_add(double* C, int ldc, const double* A, int 
                                        int ldd) {
   if (k <= 16) mm_body<4>(C, ldc, A, lda, ta, B, ldb, tb, m, n, k, alpha, beta, D, ldd);
   else if (k <= 32) mm_body<8>(C, ldc, A, lda, ta, B, ldb, tb, m, n, k, alpha, beta, D, ldd);
+  else if (k <= 48) mm_body<12>(C, ldc, A, lda, ta, B, ldb, tb, m, n, k, alpha, beta, D, ldd);
   else mm_body<16>(C, ldc, A, lda, ta, B, ldb, tb, m, n, k, alpha, beta, D, ldd);
 }
 
@@ -101,10 +102,11 @@ __device__ __forceinline__ void mm(double* C, int ldc, const double* A, int lda,
 // may be C).  Each tile runs two accumulator chains (even and odd k steps)
 // to halve the dependent v_mfma_f64_16x16x4f64 sequence.  Entries past the
 // order of the data are zero in A, B and D and stay zero in C.
-template <int NT>
+template <int NT, int NK = 4 * NT>
 __device__ __forceinline__ void sym_mm(double* C, const double* A, const double* B, double alpha, double beta,
                                        const double* D) {
-  constexpr int NK = 4 * NT;  // k steps of 4
+  // NK k steps of 4 (even; 4 NK at least the order of the data, beyond which
+  // the operands are zero)
   constexpr int NTILE = NT * (NT + 1) / 2;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int l16 = lane & 15, kq = lane >> 4;

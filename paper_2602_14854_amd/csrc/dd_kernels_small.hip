@@ -309,9 +309,10 @@ void launch_chol(const Dev& d, int axis, int sd0, int nsd, int ndim, int rows, i
 // an update changes X by at most 1e-14 in Frobenius norm; exactly zero
 // eigenvalues stay zero.  A component still moving by less than that is at
 // most 2e-14 |C|_F, and so is its error in C+-.  Two products of order
-// 16 NT per iteration on the FP64 matrix cores.  C is zero-padded to order
-// 16 NT in place; X, Y and W are LDS work buffers of the same shape.
-template <int NT>
+// 16 NT per iteration on the FP64 matrix cores, NK k steps of 4 each.  C is
+// zero-padded to order 16 NT in place; X, Y and W are LDS work buffers of
+// the same shape.
+template <int NT, int NK>
 __device__ void abs_split(double* C, double* X, double* Y, double* W, int t) {
   constexpr int NP = 16 * NT;
   __shared__ double red[NTHR];
@@ -334,16 +335,16 @@ __device__ void abs_split(double* C, double* X, double* Y, double* W, int t) {
   for (int it = 0; it < 64 && 1.0 - l > 1e-15; ++it) {
     const double a2 = 3.0 / (1.0 + l + l * l), a = sqrt(a2);
     const double c1 = 1.5 * a, c3 = -0.5 * a * a2;
-    sym_mm<NT>(Y, X, X, 1.0, 0.0, Y);  // X^2
-    sym_mm<NT>(W, X, Y, c3, c1, X);    // c1 X + c3 X^3
+    sym_mm<NT, NK>(Y, X, X, 1.0, 0.0, Y);  // X^2
+    sym_mm<NT, NK>(W, X, Y, c3, c1, X);    // c1 X + c3 X^3
     double* sw = X;
     X = W;
     W = sw;
     l = l * (c1 + c3 * l * l);
   }
   for (int it = 0; it < 48; ++it) {
-    sym_mm<NT>(Y, X, X, 1.0, 0.0, Y);    // X^2
-    sym_mm<NT>(W, X, Y, -0.5, 1.5, X);   // (3 X - X^3) / 2
+    sym_mm<NT, NK>(Y, X, X, 1.0, 0.0, Y);    // X^2
+    sym_mm<NT, NK>(W, X, Y, -0.5, 1.5, X);   // (3 X - X^3) / 2
     double ch = 0.0;
     for (int idx = threadIdx.x; idx < NP * NP; idx += NTHR) {
       const int o = idx % NP + (idx / NP) * LDA;
@@ -356,7 +357,7 @@ __device__ void abs_split(double* C, double* X, double* Y, double* W, int t) {
     W = sw;
     if (ch2 <= 1e-28) break;
   }
-  sym_mm<NT>(Y, X, C, 1.0, 0.0, Y);  // sign(C) C
+  sym_mm<NT, NK>(Y, X, C, 1.0, 0.0, Y);  // sign(C) C
 }
 
 // Angular Galerkin matrices -> the upwind split C = C+ + C- of Appendix A
@@ -395,11 +396,16 @@ __global__ __launch_bounds__(NTHR) void s_adv_prep(Dev d, int axis, int sd0) {
   // C+ and C- without the eigenvectors (see abs_split)
   __shared__ double X2[LDA * CAP];
   __shared__ double Xn[LDA * CAP];
-  switch ((t + 15) >> 4) {
-    case 1: abs_split<1>(A, Xb, X2, Xn, t); break;
-    case 2: abs_split<2>(A, Xb, X2, Xn, t); break;
-    case 3: abs_split<3>(A, Xb, X2, Xn, t); break;
-    default: abs_split<4>(A, Xb, X2, Xn, t); break;
+  // tiles of 16 and k steps of 4 (an even number) covering t
+  switch ((t + 7) >> 3) {
+    case 1: abs_split<1, 2>(A, Xb, X2, Xn, t); break;
+    case 2: abs_split<1, 4>(A, Xb, X2, Xn, t); break;
+    case 3: abs_split<2, 6>(A, Xb, X2, Xn, t); break;
+    case 4: abs_split<2, 8>(A, Xb, X2, Xn, t); break;
+    case 5: abs_split<3, 10>(A, Xb, X2, Xn, t); break;
+    case 6: abs_split<3, 12>(A, Xb, X2, Xn, t); break;
+    case 7: abs_split<4, 14>(A, Xb, X2, Xn, t); break;
+    default: abs_split<4, 16>(A, Xb, X2, Xn, t); break;
   }
   double* Cp = sm + d.oCp;
   double* Cn = sm + d.oCn;
