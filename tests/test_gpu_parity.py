@@ -210,6 +210,31 @@ def test_one_cell_wide_subdomains():
     assert dd.state_rel_error(got, ref, prob) < STRICT
 
 
+@pytest.mark.parametrize("lo,bound", [(-6, STRICT), (-9, 1e-6)])
+def test_graded_factors(lo, bound):
+    """Singular values of S from 1 down to 10^lo, S a full (rotated) matrix.
+    Down to 1e-6 the step matches the oracle to the FP64 bar.  Below, the
+    first stage from such a state agrees only to about u cond(A) times the
+    coupling of the K-step (4e-9 at 1e-9; later stages, from the diagonal S
+    that truncation leaves, agree to 1e-15): the augmented basis is formed
+    as A (U Sigma^-1) from the small SVD, and the rounding of that product
+    is not confined to range(A), so the weakest basis direction is off by
+    about u cond(A) -- a NumPy replay of the same route against the oracle
+    reproduces 3.8e-9, while the oracle itself (LAPACK, orthogonal
+    transformations) moves by less than 1e-13 under a 1e-15 input
+    perturbation or a change of SVD driver.  The second case holds that
+    measured level."""
+    wl = small_case(seed=21, px=2, py=2, lnx=8, lny=6, dirs=wk.product_directions(6, 6), ranks=[6] * 4,
+                    sig=np.logspace(0, lo, 6))
+    say(f"case: 2x2 of 8x6, ranks 6, singular values 1 .. 1e{lo}")
+    ref, prob = oracle_steps(wl, 2)
+    e = engine(wl)
+    e.step(2)
+    got = e.state()
+    e.close()
+    assert dd.state_rel_error(got, ref, prob) < bound
+
+
 def test_single_subdomain():
     wl = small_case(seed=12, px=1, py=1, lnx=9, lny=7, ranks=[4])
     say("case: one subdomain of 9x7 cells")
