@@ -258,6 +258,28 @@ def test_maximum_capacity():
     assert es < STRICT and er < STRICT
 
 
+def test_zero_state_without_source_stays_zero():
+    """Degenerate input: S = 0 everywhere and no source.  Every K-step
+    output is exactly zero, so every QR completes its basis with substitute
+    columns and every Galerkin product vanishes; the state must stay exactly
+    zero with no non-finite value raised on the way (the oracle gives zero
+    as well, with arbitrary bases)."""
+    def init(N, M, r, h, w, rng, s):
+        u, _, v = wk.random_factors(N, M, r, h, w, rng)
+        return u, np.zeros((r, r)), v
+    wl = small_case(seed=41, Q=np.zeros(16 * 16), init=init)
+    say("case: zero state, no source, 2x2 of 8x8, M=16, r=3, 2 steps")
+    ref, prob = oracle_steps(wl, 2)
+    e = engine(wl)
+    e.step(2)
+    got = e.state()
+    rho = e.moments()
+    e.close()
+    assert np.all(rho == 0.0)
+    assert all(np.all(S == 0.0) for (_, S, _) in got)
+    assert np.all(dd.moments(ref, prob) == 0.0)
+
+
 def test_single_subdomain():
     wl = small_case(seed=12, px=1, py=1, lnx=9, lny=7, ranks=[4])
     say("case: one subdomain of 9x7 cells")
