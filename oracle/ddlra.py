@@ -17,7 +17,10 @@ eigen-decomposition of C).  Readings used where the paper is silent:
   R8      x uses omega_x, y uses omega_y; eigenvalue 0 contributes nothing.
   R9      the S-step is the Galerkin projection of the K-step operator; the
           L-step upwinds each direction by the sign of its own omega.
-  R10     explicit Euler for every K, S and L substep.
+  R10     explicit Euler for every K, S and L substep; the classic
+          four-stage Runge-Kutta method (Section 4 states that the paper's
+          runs use it) is available per problem, each substep integrated
+          over dt with its boundary data frozen.
   R12     Algorithm 4's top block of S-hat is S^0 V^{0T} W V-hat.
   R14/R15 rank rules (see aug_rank / trunc_rank).
   R16     the collision stage does not truncate.
@@ -58,6 +61,9 @@ class Problem:
         self.r_int_max = int(wl.r_int_max)
         self.tol = float(wl.tol)
         self.tol_aug_rel = float(wl.tol_aug_rel)
+        self.integrator = str(getattr(wl, "integrator", "euler"))
+        if self.integrator not in ("euler", "rk4"):
+            raise ValueError("integrator must be 'euler' or 'rk4'")
         n_sub = wl.px * wl.py
         self.sigma_s, self.sigma_t, self.Q = [], [], []
         for s in range(n_sub):
@@ -296,11 +302,26 @@ def boundary_K(s, axis, K, V_hat, snapshot, prob):
 
 
 # ----------------------------------------------------------------------------
+# time integration of one substep
+# ----------------------------------------------------------------------------
+
+def rk4(f, y0, dt):
+    """One step of the classic four-stage Runge-Kutta method for y' = f(y)
+    (the substeps are autonomous: their boundary data are frozen, R7)."""
+    k1 = f(y0)
+    k2 = f(y0 + 0.5 * dt * k1)
+    k3 = f(y0 + 0.5 * dt * k2)
+    k4 = f(y0 + dt * k3)
+    return y0 + (dt / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
+
+
+# ----------------------------------------------------------------------------
 # Algorithms 1 and 2: projector splitting for x / y advection
 # ----------------------------------------------------------------------------
 
 def psi_advect(K0, V_hat, Kb_lo, Kb_hi, axis, prob, rec=None):
-    """Algorithm 1 (axis 0) or Algorithm 2 (axis 1) with explicit Euler (R10).
+    """Algorithm 1 (axis 0) or Algorithm 2 (axis 1) with explicit Euler or
+    RK4 substeps (R10).
 
     Returns (U^1, S^3, V^1) with F = U^1 S^3 V^{1T}."""
     w = prob.w
@@ -308,17 +329,29 @@ def psi_advect(K0, V_hat, Kb_lo, Kb_hi, axis, prob, rec=None):
     dt, h = prob.dt, prob.h
     C = V_hat.T @ ((w * om)[:, None] * V_hat)        # <V_j, v V_k> (Appendix A, R8)
     lam, P = np.linalg.eigh(C)
+    rk = prob.integrator == "rk4"
     # step 1: K-step (eq. advx_evolK) with frozen boundary values
-    K1 = K0 + dt * kstep_rhs(K0, P, lam, Kb_lo, Kb_hi, axis, prob)
+    if rk:
+        K1 = rk4(lambda K: kstep_rhs(K, P, lam, Kb_lo, Kb_hi, axis, prob), K0, dt)
+    else:
+        K1 = K0 + dt * kstep_rhs(K0, P, lam, Kb_lo, Kb_hi, axis, prob)
     # step 2: QR
     U1, S1 = qr_spatial(K1, prob)
     # step 3: S-step (eq. advx_evolS), integrated with the opposite sign
-    S2 = S1 - dt * (h * h) * (U1.T @ kstep_rhs(U1 @ S1, P, lam, Kb_lo, Kb_hi, axis, prob))
+    if rk:
+        S2 = rk4(lambda S: -(h * h) * (U1.T @ kstep_rhs(U1 @ S, P, lam, Kb_lo, Kb_hi, axis, prob)), S1, dt)
+    else:
+        S2 = S1 - dt * (h * h) * (U1.T @ kstep_rhs(U1 @ S1, P, lam, Kb_lo, Kb_hi, axis, prob))
     # step 4: L-step (eq. advx_evolL) from L = V-hat S^{2T}; the per-direction
     # boundary value of f is K^b V-hat^T (R9)
-    F2 = U1 @ S2 @ V_hat.T
-    A = direction_rhs(F2, om, Kb_lo @ V_hat.T, Kb_hi @ V_hat.T, axis, prob)
-    L1 = V_hat @ S2.T + dt * ((h * h) * (U1.T @ A)).T
+    G_lo, G_hi = Kb_lo @ V_hat.T, Kb_hi @ V_hat.T
+    if rk:
+        L1 = rk4(lambda L: ((h * h) * (U1.T @ direction_rhs(U1 @ L.T, om, G_lo, G_hi, axis, prob))).T,
+                 V_hat @ S2.T, dt)
+    else:
+        F2 = U1 @ S2 @ V_hat.T
+        A = direction_rhs(F2, om, G_lo, G_hi, axis, prob)
+        L1 = V_hat @ S2.T + dt * ((h * h) * (U1.T @ A)).T
     # step 5: QR
     V1, S3 = qr_angular(L1, prob)
     if rec is not None:
@@ -342,28 +375,32 @@ def truncate(U, S, V, prob):
 # ----------------------------------------------------------------------------
 
 def psi_collision(U, S, V, s, prob, rec=None):
-    """Algorithm 3 with explicit Euler, eqs. coll_evolK/S/L; 1/(2 pi) becomes
-    1/W (R1, R22)."""
+    """Algorithm 3 with explicit Euler or RK4 substeps (R10), eqs.
+    coll_evolK/S/L; 1/(2 pi) becomes 1/W (R1, R22)."""
     w, W, dt, h = prob.w, prob.W, prob.dt, prob.h
     cs, ct, Qs = prob.sigma_s[s], prob.sigma_t[s], prob.Q[s]
     m = V.T @ w                                         # <V_j>
     K = U @ S
+    rk = prob.integrator == "rk4"
     # step 1: K-step
-    rhsK = (cs / W)[:, None] * (K @ m)[:, None] * m[None, :] - ct[:, None] * K + Qs[:, None] * m[None, :]
-    K1 = K + dt * rhsK
+    def fK(K):
+        return (cs / W)[:, None] * (K @ m)[:, None] * m[None, :] - ct[:, None] * K + Qs[:, None] * m[None, :]
+    K1 = rk4(fK, K, dt) if rk else K + dt * fK(K)
     # step 2: QR
     U1, S1 = qr_spatial(K1, prob)
     # step 3: S-step
     Gs = (h * h) * (U1.T @ (cs[:, None] * U1))          # <U_i, c_s U_l>
     Gt = (h * h) * (U1.T @ (ct[:, None] * U1))          # <U_i, c_t U_l>
     q = (h * h) * (U1.T @ Qs)                           # <U_i, Q>
-    rhsS = -(1.0 / W) * Gs @ S1 @ np.outer(m, m) + Gt @ S1 - np.outer(q, m)
-    S2 = S1 + dt * rhsS
+    def fS(S):
+        return -(1.0 / W) * Gs @ S @ np.outer(m, m) + Gt @ S - np.outer(q, m)
+    S2 = rk4(fS, S1, dt) if rk else S1 + dt * fS(S1)
     # step 4: L-step from L = V S^{2T}
     L = V @ S2.T
     ones = np.ones(prob.M)
-    rhsL = (1.0 / W) * np.outer(ones, (w @ L) @ Gs.T) - L @ Gt.T + np.outer(ones, q)
-    L1 = L + dt * rhsL
+    def fL(L):
+        return (1.0 / W) * np.outer(ones, (w @ L) @ Gs.T) - L @ Gt.T + np.outer(ones, q)
+    L1 = rk4(fL, L, dt) if rk else L + dt * fL(L)
     # step 5: QR
     V1, S3 = qr_angular(L1, prob)
     if rec is not None:

@@ -2,8 +2,8 @@
 
 The distribution is stored densely as F[iy, ix, q] on the whole grid.  One
 step is the Lie splitting of Section 3 (x-advection, then y-advection, then
-absorption/scattering/source), each part advanced by one explicit Euler step,
-with the first-order upwind difference of Appendix A applied direction by
+absorption/scattering/source), each part advanced by one explicit Euler step
+(or one classic RK4 step), with the first-order upwind difference of Appendix A applied direction by
 direction.  Physical boundaries are vacuum: zero inflow.  Scattering uses
 c_s rho / W with rho = sum_q w_q f_q (R1, R22).
 
@@ -28,6 +28,7 @@ class Grid:
         self.ss = np.asarray(wl.sigma_s, float).reshape(wl.ny, wl.nx)
         self.st = self.ss + np.asarray(wl.sigma_a, float).reshape(wl.ny, wl.nx)
         self.Q = np.asarray(wl.Q, float).reshape(wl.ny, wl.nx)
+        self.integrator = str(getattr(wl, "integrator", "euler"))
 
 
 def upwind_derivative(F, axis, omega, h, inflow_lo=None, inflow_hi=None):
@@ -75,8 +76,22 @@ def collide(F, g: Grid):
     return F + g.dt * collide_operator(F, g)
 
 
+def _rk4(f, y, dt):
+    # classic four-stage Runge-Kutta step for y' = f(y)
+    a = f(y)
+    b = f(y + (dt / 2) * a)
+    c = f(y + (dt / 2) * b)
+    e = f(y + dt * c)
+    return y + (dt / 6) * (a + 2 * b + 2 * c + e)
+
+
 def step(F, g: Grid):
-    """One Lie-split explicit-Euler S_N step: x, then y, then collision."""
+    """One Lie-split S_N step: x, then y, then collision, each part advanced
+    by one explicit Euler step or one classic RK4 step (g.integrator)."""
+    if g.integrator == "rk4":
+        F = _rk4(lambda X: advect_operator(X, 0, g), F, g.dt)
+        F = _rk4(lambda X: advect_operator(X, 1, g), F, g.dt)
+        return _rk4(lambda X: collide_operator(X, g), F, g.dt)
     F = advect(F, 0, g)
     F = advect(F, 1, g)
     return collide(F, g)

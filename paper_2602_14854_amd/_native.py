@@ -111,6 +111,9 @@ class _ConfigHolder:
     """Keeps the numpy arrays a Config points to alive."""
 
     def __init__(self, wl, precision: int, exec_mode: int, strict: int):
+        if str(getattr(wl, "integrator", "euler")) != "euler":
+            raise NotImplementedError("the HIP engine advances every substep by one explicit Euler step; "
+                                      "RK4 substeps are not available in it")
         self.ox = _f64(wl.omega_x)
         self.oy = _f64(wl.omega_y)
         self.w = _f64(wl.w)

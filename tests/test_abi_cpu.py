@@ -110,6 +110,14 @@ def test_invalid_configs_rejected(over, needle):
 
 
 @needs_lib
+def test_rk4_substeps_refused_by_the_engine():
+    """RK4 substeps exist in the oracle only: the binding refuses such a
+    problem before anything reaches the library."""
+    with pytest.raises(NotImplementedError):
+        pkg.workspace_size(_cfg(integrator="rk4"))
+
+
+@needs_lib
 def test_negative_cross_section_rejected():
     wl = _cfg()
     wl.sigma_s = wl.sigma_s.copy()

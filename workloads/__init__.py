@@ -61,6 +61,7 @@ class Workload:
     V0: List[np.ndarray]
     seed: int = 0
     note: str = ""
+    integrator: str = "euler"    # substep integrator: "euler" or "rk4"
 
     @property
     def lnx(self) -> int:
