@@ -49,7 +49,7 @@ __global__ __launch_bounds__(NTHR) void s_aug_svd(Dev d, int axis, int sd0) {
     }
     __syncthreads();
   }
-  jacobi_1s(d, B, m0, m0, nullptr, 1e-15, 1e-15, 40);
+  jacobi_1s(d, B, m0, m0, nullptr, 1e-14, 1e-15, 40);
   col_norms(B, m0, m0, nrm);
   sort_desc(nrm, m0, perm);
   for (int j = threadIdx.x; j < m0; j += NTHR) sig[j] = nrm[perm[j]];
@@ -575,7 +575,7 @@ __global__ __launch_bounds__(NTHR) void s_trunc(Dev d, int axis, int sd0, int fo
     G[i + j * LDA] = RL[j + i * T];
   }
   __syncthreads();
-  jacobi_1s(d, G, t, t, Y, 1e-15, 1e-15, 40);
+  jacobi_1s(d, G, t, t, Y, 1e-14, 1e-15, 40);
   col_norms(G, t, t, sv);
   sort_desc(sv, t, perm);
   for (int j = threadIdx.x; j < t; j += NTHR) sig[j] = sv[perm[j]];
