@@ -372,6 +372,55 @@ def test_torch_workspace_stream_and_device_moments():
 # full configuration sizes (the benchmark's launch configuration)
 # ----------------------------------------------------------------------------
 
+def _c4_at_capacity(seed=1404, rcap=21):
+    """The batched uneven-rank geometry (512x512 cells, 8x8 subdomains of
+    64x64, 1024 directions, sigma_s 100 | 0.01, adaptive tol 1e-4, r_min 2)
+    with the rank cap lowered to the engine's capacity: initial ranks drawn
+    from 2..21, S = diag(10^(-4.5 j / r_k)), r_int_max = 42."""
+    wl = wk.make_workload("C4")
+    rng = np.random.default_rng(seed)
+    N, M = wl.lnx * wl.lny, wl.w.shape[0]
+    h = (wl.x1 - wl.x0) / wl.nx
+    U0, S0, V0 = [], [], []
+    for _ in range(wl.px * wl.py):
+        rk = int(rng.integers(2, rcap + 1))
+        u, sg, v = wk.random_factors(N, M, rk, h, wl.w, rng, sig=10.0 ** (-4.5 * np.arange(rk) / rk))
+        U0.append(u); S0.append(sg); V0.append(v)
+    wl.U0, wl.S0, wl.V0 = U0, S0, V0
+    wl.r_max, wl.r_int_max = rcap, 2 * rcap
+    return wl
+
+
+@pytest.mark.timeout(300)
+def test_uneven_adaptive_ranks_at_full_size():
+    """One x-advection stage of the uneven-rank adaptive configuration at
+    its full grid, direction count and subdomain count (rank cap at the
+    engine's capacity).  Every subdomain's intermediate and new rank equals
+    the oracle's (its tail sums keep a relative margin above 1e-3 from the
+    tolerance here, so the integer decisions are not rounding-sensitive).
+    The K-step output of some subdomains is exactly rank-deficient here
+    (sigma_min / sigma_max about 1e-18 in the oracle), so the basis
+    completion is arbitrary and the stage result is not unique (the oracle
+    differs from itself at the 1e-5 level under a reordering of its
+    augmentation columns); the flux is held to 20 times that spread."""
+    wl = _c4_at_capacity()
+    say("case: 512x512 cells, 8x8 subdomains of 64x64, M=1024, adaptive tol 1e-4, ranks 2..21, x stage")
+    prob = dd.Problem(wl)
+    recs = []
+    ref, _, spread = _oracle_spread(wl, 1, advance=lambda st, pr: dd.stage_advect(st, 0, pr))
+    dd.stage_advect(dd.initial_state(wl), 0, prob, records=recs)
+    e = engine(wl)
+    e.stage(0)
+    r, tmax, _ = e.ranks()
+    rho = e.moments()
+    e.close()
+    assert list(tmax) == [rec["t"] for rec in recs]
+    assert list(r) == [S.shape[0] for _, S, _ in ref]
+    err = rho_err(rho, dd.moments(ref, prob))
+    say(f"  ranks {min(r)}..{max(r)}, t {min(tmax)}..{max(tmax)}: flux err {err:.3e}, oracle spread {spread:.3e}")
+    assert err <= max(STRICT, 20.0 * spread)
+
+
 def test_pure_absorption_property_at_lattice_size():
     """224x224 cells, 7x7 subdomains, 256 directions, rank 10: with c_adv = 0,
     c_s = 0 and uniform sigma_a one step multiplies F by
@@ -444,10 +493,12 @@ def test_mixed_precision_wc_C3(prec):
     assert err < MIXED
 
 
-def _oracle_spread(wl, nsteps):
+def _oracle_spread(wl, nsteps, advance=None):
     """Largest scalar-flux distance between the oracle and two mathematically
     identical variants of it: the columns of the augmentation matrix in
-    reverse order, and V-hat multiplied by a random rotation."""
+    reverse order, and V-hat multiplied by a random rotation.  advance
+    (state, prob) -> state is one unit of work (default: a whole step)."""
+    advance = advance or dd.dd_step
     prob = dd.Problem(wl)
     orig = dd.augment
 
@@ -472,10 +523,10 @@ def _oracle_spread(wl, nsteps):
     try:
         for _ in range(nsteps):
             dd.augment = orig
-            a = dd.dd_step(a, prob)
+            a = advance(a, prob)
             for k, f in enumerate((aug_rev, aug_rot)):
                 dd.augment = f
-                variants[k] = dd.dd_step(variants[k], prob)
+                variants[k] = advance(variants[k], prob)
     finally:
         dd.augment = orig
     ra = dd.moments(a, prob)
