@@ -32,6 +32,7 @@ WORKLOAD_NAMES = {
     "C1": "gaussian 32x32 cells, 2x2 subdomains, 64 directions, rank 5",
     "C2": "lattice 224x224 cells, 7x7 subdomains of 32x32, 256 directions, rank 10",
     "C3": "lattice 448x448 cells, 7x7 subdomains of 64x64, 1024 directions, rank 20",
+    "C4cap": "thick/thin 512x512 cells, 8x8 subdomains of 64x64, 1024 directions, adaptive ranks 2..21",
 }
 
 

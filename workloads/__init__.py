@@ -238,7 +238,7 @@ def make_workload(name: str, seed: Optional[int] = None, **over) -> Workload:
     localized sources, thick/thin regions).  'wc-*' variants replace the
     near-rank-one initial data by generic well-conditioned random factors
     (singular values 1 .. 1e-2) for strict FP64 parity."""
-    idx = {"C1": 1, "C2": 2, "C3": 3, "C4": 4, "C5": 5}
+    idx = {"C1": 1, "C2": 2, "C3": 3, "C4": 4, "C5": 5, "C4cap": 6}
     base = name.split(":")[0]
     cfg_i = idx.get(base.replace("wc-", ""), 0)
     if seed is None:
@@ -276,17 +276,18 @@ def make_workload(name: str, seed: Optional[int] = None, **over) -> Workload:
         mode, r_int = RANK_FIXED, 2 * r
         tol = 0.0
         r_min, r_max = r, r
-    elif key == "C4":
+    elif key in ("C4", "C4cap"):
+        # C4cap: the same geometry with the rank cap at 21 and r_int_max 42
         nx = ny = 512; px = py = 8; x0, x1, y0, y1 = 0.0, 1.0, 0.0, 1.0
         ox, oy, w = product_directions(32, 32)
-        r = 40; steps = 100
+        r = 40 if key == "C4" else 21; steps = 100
         X, Y = _cell_centres(nx, ny, x0, x1, y0, y1)
         ss = np.where(X < 0.5, 100.0, 0.01)
         sa = np.zeros(nx * ny)
         Q = np.zeros(nx * ny)
-        mode, r_int = RANK_ADAPTIVE, 80
+        mode, r_int = RANK_ADAPTIVE, 2 * r
         tol = 1e-4
-        r_min, r_max = 2, 40
+        r_min, r_max = 2, r
     elif key == "C5":
         nx = ny = 1024; px = py = 16; x0, x1, y0, y1 = -1.0, 1.0, -1.0, 1.0
         ox, oy, w = product_directions(32, 64)
@@ -327,9 +328,9 @@ def make_workload(name: str, seed: Optional[int] = None, **over) -> Workload:
         A = np.hstack([np.full((nx * ny, 1), 1e-9), 1e-12 * rng.standard_normal((nx * ny, r))])
         B = np.hstack([np.ones((M, 1)), rng.standard_normal((M, r))])
         U0, S0, V0 = _split_factors(nx, ny, px, py, h, A, B, [r] * n_sub, w)
-    elif key == "C4":
+    elif key in ("C4", "C4cap"):
         for s in range(n_sub):
-            rk = int(rng.integers(2, 41))
+            rk = int(rng.integers(2, r + 1))
             sig = 10.0 ** (-4.5 * np.arange(rk) / rk)
             u, sg, v = random_factors(N, M, rk, h, w, rng, sig=sig)
             U0.append(u); S0.append(sg); V0.append(v)
