@@ -92,6 +92,88 @@ __device__ __forceinline__ void mm(double* C, int ldc, const double* A, int lda,
   mm_add(C, ldc, A, lda, ta, B, ldb, tb, m, n, k, alpha, beta, C, ldc);
 }
 
+// One product C = alpha op(A) op(B) + beta D of mm_multi (same meaning and
+// limits as the arguments of mm_add).
+struct MMOp {
+  double* C;
+  int ldc;
+  const double* A;
+  int lda;
+  bool ta;
+  const double* B;
+  int ldb;
+  bool tb;
+  int m, n, k;
+  double alpha, beta;
+  const double* D;
+  int ldd;
+};
+
+// Several independent products in one pass: the 16 x 16 output tiles of
+// all of them are dealt to the wavefronts together, so their operand loads
+// overlap and the group costs one barrier instead of one per product (the
+// tiles are formed exactly as by mm_add).  No product may read another's
+// output.  All threads call.
+template <int NK, int NP>
+__device__ __forceinline__ void mm_multi_body(const MMOp (&ops)[NP]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l16 = lane & 15, kq = lane >> 4;
+  int first[NP + 1];
+  first[0] = 0;
+#pragma unroll
+  for (int q = 0; q < NP; ++q) first[q + 1] = first[q] + ((ops[q].m + 15) >> 4) * ((ops[q].n + 15) >> 4);
+  for (int tile = wave; tile < first[NP]; tile += NW) {
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      if (tile < first[q] || tile >= first[q + 1]) continue;
+      const MMOp& o = ops[q];
+      const int tm = (o.m + 15) >> 4;
+      const int magic = tm == 1 ? 64 : (tm == 2 ? 32 : (tm == 3 ? 22 : 16));
+      const int lt = tile - first[q];
+      const int tj = (lt * magic) >> 6, ti = lt - tj * tm;
+      const int i0 = 16 * ti, j0 = 16 * tj;
+      const int i = i0 + l16, j = j0 + l16;
+      const int ic = i < o.m ? i : 0, jc = j < o.n ? j : 0;
+      double av[NK], bv[NK];
+#pragma unroll
+      for (int s4 = 0; s4 < NK; ++s4) {
+        const int l = 4 * s4 + kq;
+        const int lc = l < o.k ? l : 0;
+        av[s4] = o.ta ? o.A[lc + ic * o.lda] : o.A[ic + lc * o.lda];
+        bv[s4] = o.tb ? o.B[jc + lc * o.ldb] : o.B[lc + jc * o.ldb];
+      }
+      dbl4 e = zero4(), od = zero4();
+#pragma unroll
+      for (int s4 = 0; s4 < NK; s4 += 2) {
+        const int l = 4 * s4 + kq;
+        e = mfma64((i < o.m && l < o.k) ? av[s4] : 0.0, (j < o.n && l < o.k) ? bv[s4] : 0.0, e);
+        od = mfma64((i < o.m && l + 4 < o.k) ? av[s4 + 1] : 0.0, (j < o.n && l + 4 < o.k) ? bv[s4 + 1] : 0.0, od);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int ci = i0 + 4 * v + kq, cj = j0 + l16;
+        if (ci < o.m && cj < o.n) {
+          const double acc = e[v] + od[v];
+          const double dv = (o.beta == 0.0) ? 0.0 : o.beta * o.D[ci + (int64_t)cj * o.ldd];
+          o.C[ci + (int64_t)cj * o.ldc] = (o.beta == 0.0) ? o.alpha * acc : fma(o.alpha, acc, dv);
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
+template <int NP>
+__device__ __forceinline__ void mm_multi(const MMOp (&ops)[NP]) {
+  int k = 0;
+#pragma unroll
+  for (int q = 0; q < NP; ++q) k = ops[q].k > k ? ops[q].k : k;
+  if (k <= 16) mm_multi_body<4, NP>(ops);
+  else if (k <= 32) mm_multi_body<8, NP>(ops);
+  else if (k <= 48) mm_multi_body<12, NP>(ops);
+  else mm_multi_body<16, NP>(ops);
+}
+
 // C = alpha A B + beta D for zero-padded square LDS matrices of order 16 NT
 // (ld LDA) whose result is symmetric (A and B symmetric and commuting, as
 // for polynomials in one symmetric matrix), with B and D symmetric.  Only

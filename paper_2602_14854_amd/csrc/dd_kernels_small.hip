@@ -483,57 +483,63 @@ __global__ __launch_bounds__(NTHR) void s_adv_sstep(Dev d, int axis, int sd0) {
                               {oX + 3 * T * R, T, t, rh, Xhn, T, 1.0}};
     sum_partials_blocks<5>(d, s, d.nwgN, blk);
   }
-  // Gm = -Gp^T (the spatial reduction forms Gp only)
-  for (int idx = threadIdx.x; idx < t * t; idx += NTHR) {
-    const int i = idx % t, j = idx / t;
-    Gm[i + j * T] = -Gp[j + i * T];
-  }
-  __syncthreads();
   double* W5 = sm + d.oW5;
   double* W6 = sm + d.oW6;
   double* BKlo = sm + d.oBKlo;
   double* BKhi = sm + d.oBKhi;
-  // BKlo = Xlo (Am En) + Xln (S_lo Olo)
-  mm(W5, R, sm + d.oAm, R, false, sm + d.oEn, T, false, r, t, t, 1.0, 0.0);
-  mm(BKlo, T, Xlo, T, false, W5, R, false, t, t, r, 1.0, 0.0);
-  if (rl > 0) {
-    mm(W6, R, d.S + (int64_t)lo * R * R, R, false, sm + d.oOlo, R, false, rl, t, rl, 1.0, 0.0);
-    mm(BKlo, T, Xln, T, false, W6, R, false, t, t, rl, 1.0, 1.0);
-  }
-  mm(W5, R, sm + d.oAm, R, false, sm + d.oEp, T, false, r, t, t, 1.0, 0.0);
-  mm(BKhi, T, Xhi, T, false, W5, R, false, t, t, r, 1.0, 0.0);
-  if (rh > 0) {
-    mm(W6, R, d.S + (int64_t)hi * R * R, R, false, sm + d.oOhi, R, false, rh, t, rh, 1.0, 0.0);
-    mm(BKhi, T, Xhn, T, false, W6, R, false, t, t, rh, 1.0, 1.0);
-  }
-  // S1 = h Racc
   double* S1 = sm + d.oS1;
   double* S2 = sm + d.oS2;
+  // independent products share a pass (mm_multi); S1 and S2 serve as
+  // scratch until they are formed
+  //   BKlo = Xlo (Am En) + Xln (S_lo Olo),  BKhi = Xhi (Am Ep) + Xhn (S_hi Ohi)
+  const double* Slo = lo >= 0 ? d.S + (int64_t)lo * R * R : d.S;
+  const double* Shi = hi >= 0 ? d.S + (int64_t)hi * R * R : d.S;
+  {
+    const MMOp ops[4] = {{W5, R, sm + d.oAm, R, false, sm + d.oEn, T, false, r, t, t, 1.0, 0.0, W5, R},
+                         {S1, T, sm + d.oAm, R, false, sm + d.oEp, T, false, r, t, t, 1.0, 0.0, S1, T},
+                         {W6, R, Slo, R, false, sm + d.oOlo, R, false, rl, t, rl, 1.0, 0.0, W6, R},
+                         {S2, T, Shi, R, false, sm + d.oOhi, R, false, rh, t, rh, 1.0, 0.0, S2, T}};
+    mm_multi(ops);
+  }
+  {
+    const MMOp ops[2] = {{BKlo, T, Xlo, T, false, W5, R, false, t, t, r, 1.0, 0.0, BKlo, T},
+                         {BKhi, T, Xhi, T, false, S1, T, false, t, t, r, 1.0, 0.0, BKhi, T}};
+    mm_multi(ops);
+  }
+  {
+    const MMOp ops[2] = {{BKlo, T, Xln, T, false, W6, R, false, t, t, rl, 1.0, 1.0, BKlo, T},
+                         {BKhi, T, Xhn, T, false, S2, T, false, t, t, rh, 1.0, 1.0, BKhi, T}};
+    mm_multi(ops);
+  }
+  // S1 = h Racc; Gm = -Gp^T (the spatial reduction forms Gp only)
   for (int idx = threadIdx.x; idx < t * t; idx += NTHR) {
     const int i = idx % t, j = idx / t;
     S1[i + j * T] = d.h * sm[d.oRacc + i + j * T];
+    Gm[i + j * T] = -Gp[j + i * T];
   }
   __syncthreads();
   double* Hm = sm + d.oW5;
   double* Hp = sm + d.oW6;
-  mm(Hm, T, Gm, T, false, S1, T, false, t, t, t, 1.0, 0.0);
-  mm(Hp, T, Gp, T, false, S1, T, false, t, t, t, 1.0, 0.0);
+  {
+    const MMOp ops[2] = {{Hm, T, Gm, T, false, S1, T, false, t, t, t, 1.0, 0.0, Hm, T},
+                         {Hp, T, Gp, T, false, S1, T, false, t, t, t, 1.0, 0.0, Hp, T}};
+    mm_multi(ops);
+  }
   for (int idx = threadIdx.x; idx < t * t; idx += NTHR) {
     const int o = (idx % t) + (idx / t) * T;
     Hm[o] -= BKlo[o];
     Hp[o] += BKhi[o];
-  }
-  __syncthreads();
-  for (int idx = threadIdx.x; idx < t * t; idx += NTHR) {
-    const int o = (idx % t) + (idx / t) * T;
     S2[o] = S1[o];
   }
   __syncthreads();
   const double dc = d.dt * d.c;
   mm(S2, T, Hm, T, false, sm + d.oCp, T, false, t, t, t, dc, 1.0);
   mm(S2, T, Hp, T, false, sm + d.oCn, T, false, t, t, t, dc, 1.0);
-  mm(Hm, T, Gm, T, false, S2, T, false, t, t, t, 1.0, 0.0);
-  mm(Hp, T, Gp, T, false, S2, T, false, t, t, t, 1.0, 0.0);
+  {
+    const MMOp ops[2] = {{Hm, T, Gm, T, false, S2, T, false, t, t, t, 1.0, 0.0, Hm, T},
+                         {Hp, T, Gp, T, false, S2, T, false, t, t, t, 1.0, 0.0, Hp, T}};
+    mm_multi(ops);
+  }
   for (int idx = threadIdx.x; idx < t * t; idx += NTHR) {
     const int i = idx % t, j = idx / t;
     const int o = i + j * T, ot = j + i * T;
