@@ -449,16 +449,15 @@ void phase(dd_dlra_handle h, int kind, F&& f) {
 // scaled by bscale); with s_dst set, the last Cholesky pass also stores
 // Racc^T there as the coefficient matrix of each subdomain.  With
 // defer_last, the last product is left to the caller: Q = Y Rinv with Rinv
-// in the small workspace.  With pivot_first, the first factorisation uses
-// diagonal pivoting (Racc = R3 R2 R1 P^T, Q in pivot order).
+// in the small workspace.
 void chol_qr3(dd_dlra_handle h, int axis, int ndim, void* X, void* Y, int64_t sdstride, int rows, bool cells,
               double* final_dst, int64_t final_sd, const double* final_rowscale, double bscale, int gemm_kind,
-              int ip_kind, double* s_dst = nullptr, bool defer_last = false, bool pivot_first = false) {
+              int ip_kind, double* s_dst = nullptr, bool defer_last = false) {
   const Dev& d = h->d;
   hipStream_t st = h->stream;
   const int ngp = cells ? d.nwgN : d.nwgM;
   phase(h, K_CHOL, [&](int s0, int ns) {
-    dd::launch_chol(d, axis, s0, ns, ndim, rows, ngp, true, 1, 1.0, pivot_first, d.oRinv, d.oRacc, d.T, st);
+    dd::launch_chol(d, axis, s0, ns, ndim, rows, ngp, true, 1, 1.0, false, d.oRinv, d.oRacc, d.T, st);
   });
   phase(h, gemm_kind, [&](int s0, int ns) {
     dd::launch_gemm(d, axis, s0, ns, X, false, sdstride, rows, ndim, ndim, d.oRinv, d.T, Y, false, sdstride, nullptr,
@@ -533,13 +532,9 @@ void enqueue_advection(dd_dlra_handle h, int axis) {
   phase(h, K_ADV_SSTEP, [&](int s0, int ns) { dd::launch_adv_sstep(d, axis, s0, ns, st); });
   // steps 4-5: L-step, weighted QR
   phase(h, K_LSTEP, [&](int s0, int ns) { dd::launch_lstep(d, axis, s0, ns, st); });
-  // (the last product, Q_L = Y Rinv, is folded into the final V product).
-  // The first pass is pivoted: S3 = Racc^T is then a row permutation of the
-  // transposed pivoted factor, on whose columns the truncation's one-sided
-  // Jacobi converges in fewer sweeps (preconditioning by a pivoted QR, after
-  // Drmac and Veselic)
+  // (the last product, Q_L = Y Rinv, is folded into the final V product)
   chol_qr3(h, axis, dd::DIM_T, d.AL, d.AL2, sdMT, d.M, false, nullptr, 0, nullptr, 1.0, K_GEMM_QR_L, K_GEMM_QR_L_IP,
-           nullptr, true, true);
+           nullptr, true);
   // Algorithm 5: truncation, then rotate the bases into the state
   phase(h, K_TRUNC, [&](int s0, int ns) { dd::launch_trunc(d, axis, s0, ns, true, st); });
   phase(h, K_GEMM_FINAL_U, [&](int s0, int ns) {
