@@ -302,7 +302,7 @@ void launch_chol(const Dev& d, int axis, int sd0, int nsd, int ndim, int rows, i
 //   X <- a X (3 I - a^2 X^2) / 2,  a = sqrt(3 / (1 + l + l^2)),
 // maps that set into [-1, -l'] u [l', 1] with l' = a l (3 - a^2 l^2) / 2
 // (about 2.6 l while l is small, then quadratic convergence).  The scaled
-// phase starts from l = 1e-6 / sqrt(t) (20 iterations); each step maps
+// phase starts from l = 1e-4 / sqrt(t) (about 15 iterations); each step maps
 // [0, l] monotonically into [0, l'], so eigenvalues below that bound end it
 // somewhere in (0, 1) with their sign, and the unscaled iteration
 // X <- X (3 I - X^2) / 2 (at most 48 steps) then carries them to +-1 until
@@ -331,7 +331,7 @@ __device__ void abs_split(double* C, double* X, double* Y, double* W, int t) {
     X[i + j * LDA] = c * ifro;
   }
   __syncthreads();
-  double l = 1e-6 / sqrt((double)t);
+  double l = 1e-4 / sqrt((double)t);
   for (int it = 0; it < 64 && 1.0 - l > 1e-15; ++it) {
     const double a2 = 3.0 / (1.0 + l + l * l), a = sqrt(a2);
     const double c1 = 1.5 * a, c3 = -0.5 * a * a2;
