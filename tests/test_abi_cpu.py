@@ -158,3 +158,26 @@ def test_rank_above_capacity_rejected():
     with pytest.raises(nat.DDError) as ei:
         pkg.DDDLRA(wl)
     assert "capacity" in str(ei.value)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: --gpus 2 exits with status 2 and says so,
+    before touching any device."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in (r.stdout + r.stderr)
+
+
+def test_capacity_variant_of_the_uneven_rank_workload():
+    """C4cap keeps C4's geometry and material layout but caps ranks at the
+    engine's capacity: initial ranks in 2..21, r_int_max 42, adaptive."""
+    a, b = wk.make_workload("C4"), wk.make_workload("C4cap")
+    assert (a.nx, a.px, a.w.shape, a.tol) == (b.nx, b.px, b.w.shape, b.tol)
+    assert np.array_equal(a.sigma_s, b.sigma_s)
+    assert (b.r_max, b.r_int_max, b.rank_mode) == (21, 42, wk.RANK_ADAPTIVE)
+    ranks = [S.shape[0] for S in b.S0]
+    assert min(ranks) >= 2 and max(ranks) <= 21 and len(set(ranks)) > 5
+    assert (a.r_max, a.r_int_max) == (40, 80)
