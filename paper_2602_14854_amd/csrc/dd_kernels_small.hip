@@ -176,18 +176,16 @@ __global__ __launch_bounds__(NTHR) void s_chol(Dev d, int axis, int sd0, int ndi
     for (int idx = threadIdx.x; idx < n * n; idx += NTHR) {
       const int i = idx % n, j = idx / n;
       const double e = G[i + j * LDA] - (i == j ? 1.0 : 0.0);
+      X[i + j * LDA] = e;  // E, kept for the near-identity factor
       part = fma(e, e, part);
     }
     fro2 = block_sum(part, red);
     near_order = fro2 <= 1e-10 ? 2 : (fro2 <= 1e-6 ? 4 : 0);
   }
   if (skip_mode == 1 && threadIdx.x == 0) small_of(d, s)[d.oSkip] = near_order > 0 ? 1.0 : 0.0;
+  double* sm0 = small_of(d, s);
   if (near_order > 0) {
-    for (int idx = threadIdx.x; idx < n * n; idx += NTHR) {
-      const int i = idx % n, j = idx / n;
-      X[i + j * LDA] = G[i + j * LDA] - (i == j ? 1.0 : 0.0);  // E
-    }
-    __syncthreads();
+    // X = E from the test above (block_sum's barriers made it visible)
     mm(E2, LDA, X, LDA, false, X, LDA, false, n, n, n, 1.0, 0.0);  // E^2
     const bool o4 = near_order == 4;
     if (o4) {
@@ -206,10 +204,13 @@ __global__ __launch_bounds__(NTHR) void s_chol(Dev d, int axis, int sd0, int ndi
       }
       G[o] = r;
       X[o] = ri;
+      // outputs of the symmetric factor (no pivoting, no dependent columns)
+      sm0[oRinv + i + j * ld] = bscale * ri;
     }
     for (int k = threadIdx.x; k < n; k += NTHR) {
       perm[k] = k;
       dep[k] = 0;
+      sm0[d.oFill + k] = 0.0;
     }
     __syncthreads();
   } else if (try_plain) {
@@ -241,18 +242,20 @@ __global__ __launch_bounds__(NTHR) void s_chol(Dev d, int axis, int sd0, int ndi
   } else {
     chol_inv_wave<NMAX, false>(d, G, X, n, perm, dep, E2);
   }
-  double* sm = small_of(d, s);
+  double* sm = sm0;
   // thread (column c = tid % 64, rows i = tid / 64 mod 4) for the n x n outputs
   const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
-  // P R^{-1}: row i of R^{-1} becomes row perm[i]
-  if (c < n)
-    for (int i = g; i < n; i += 4) sm[oRinv + perm[i] + c * ld] = bscale * X[i + c * LDA];
-  for (int j = threadIdx.x; j < n; j += NTHR) sm[d.oFill + j] = dep[j] ? 1.0 : 0.0;
-  // rows of dependent columns do not contribute to X = Q R
-  if (c < n)
-    for (int i = g; i < n; i += 4)
-      if (dep[i]) G[i + c * LDA] = 0.0;
-  __syncthreads();
+  if (near_order == 0) {
+    // P R^{-1}: row i of R^{-1} becomes row perm[i]
+    if (c < n)
+      for (int i = g; i < n; i += 4) sm[oRinv + perm[i] + c * ld] = bscale * X[i + c * LDA];
+    for (int j = threadIdx.x; j < n; j += NTHR) sm[d.oFill + j] = dep[j] ? 1.0 : 0.0;
+    // rows of dependent columns do not contribute to X = Q R
+    if (c < n)
+      for (int i = g; i < n; i += 4)
+        if (dep[i]) G[i + c * LDA] = 0.0;
+    __syncthreads();
+  }
   if (acc_mode == 1) {
     // Racc = R P^T: column c of R becomes column perm[c]
     if (c < n) {
