@@ -421,6 +421,31 @@ def test_uneven_adaptive_ranks_at_full_size():
     assert err <= max(STRICT, 20.0 * spread)
 
 
+@pytest.mark.parametrize("name,nsteps,prec", [("C2", 200, "fp64"), ("C3", 200, "fp64"), ("C3", 200, "fp32"),
+                                               ("C4cap", 100, "fp64")])
+def test_configured_run_length_stays_finite(name, nsteps, prec):
+    """The full configured number of steps in graph mode: the engine raises
+    on any non-finite value, Cholesky breakdown or unconverged Jacobi sweep
+    latched on the device, so completing the run and reading finite moments
+    is the check; the ranks stay within their bounds and the total mass
+    stays positive."""
+    import paper_2602_14854_amd as pkg
+    wl = wk.make_workload(name)
+    mode = {"fp64": pkg.DD_PREC_FP64, "fp32": pkg.DD_PREC_MIXED_FP32}[prec]
+    say(f"case: {name}, {nsteps} steps, {prec}, graph mode")
+    e = engine(wl, precision=mode)
+    e.step(nsteps)
+    rho = e.moments()
+    r, tmax, _ = e.ranks()
+    e.close()
+    assert np.all(np.isfinite(rho))
+    assert wl.r_min <= r.min() and r.max() <= wl.r_max and tmax.max() <= wl.r_int_max
+    h = (wl.x1 - wl.x0) / wl.nx
+    mass = h * h * float(rho.sum())
+    say(f"  after {nsteps} steps: ranks {r.min()}..{r.max()}, mass {mass:.6e}, max rho {rho.max():.3e}")
+    assert mass > 0.0
+
+
 def test_pure_absorption_property_at_lattice_size():
     """224x224 cells, 7x7 subdomains, 256 directions, rank 10: with c_adv = 0,
     c_s = 0 and uniform sigma_a one step multiplies F by
