@@ -118,3 +118,32 @@ def test_rk4_kstep_local_error_is_fifth_order(axis):
             e.append(rel(rec["K1"], ex))
         errs.append(max(e))
     assert 24.0 < errs[0] / errs[1] < 40.0, errs
+
+
+def test_rk4_advection_s_and_l_steps_local_error_is_fifth_order():
+    """The advection S- and L-step RK4 results against the exact flows of
+    the Euler right-hand sides of the same stage (S' = -h^2 U1^T A(U1 S),
+    L' = (h^2 U1^T A_dir(U1 L^T))^T with the frozen ghosts): halving dt
+    divides the local error by about 32, so the RK4 stages integrate the
+    same right-hand sides as the Euler substeps (a sign or transpose slip in
+    either would leave an O(dt) or O(1) gap instead)."""
+    errs = []
+    for cfl in (0.2, 0.1):
+        wl = wk.make_custom(8, 8, 2, 2, wk.product_directions(4, 4), [3] * 4, seed=9, cfl=cfl)
+        wl.integrator = "rk4"
+        prob = dd.Problem(wl)
+        h, om = prob.h, prob.omega[0]
+        recs = []
+        dd.stage_advect(dd.initial_state(wl), 0, prob, records=recs)
+        es, el = [], []
+        for rec in recs:
+            U1, Vh, P, lam = rec["U1"], rec["V_hat"], rec["P"], rec["lam"]
+            Kl, Kh = rec["Kb_lo"], rec["Kb_hi"]
+            fS = lambda S: -(h * h) * (U1.T @ dd.kstep_rhs(U1 @ S, P, lam, Kl, Kh, 0, prob))
+            es.append(rel(rec["S2"], _exact_affine_flow(fS, rec["S1"], prob.dt)))
+            Gl, Gh = Kl @ Vh.T, Kh @ Vh.T
+            fL = lambda L: ((h * h) * (U1.T @ dd.direction_rhs(U1 @ L.T, om, Gl, Gh, 0, prob))).T
+            el.append(rel(rec["L1"], _exact_affine_flow(fL, Vh @ rec["S2"].T, prob.dt)))
+        errs.append((max(es), max(el)))
+    (s1, l1), (s2, l2) = errs
+    assert 24.0 < s1 / s2 < 40.0 and 24.0 < l1 / l2 < 40.0, errs
