@@ -181,3 +181,15 @@ def test_capacity_variant_of_the_uneven_rank_workload():
     ranks = [S.shape[0] for S in b.S0]
     assert min(ranks) >= 2 and max(ranks) <= 21 and len(set(ranks)) > 5
     assert (a.r_max, a.r_int_max) == (40, 80)
+
+
+@pytest.mark.parametrize("name", ["C1", "C2", "wc-C2", "C4cap"])
+def test_workloads_are_seeded(name):
+    """Every input is generated from its seed: two builds agree bit for bit,
+    and another seed gives other initial factors."""
+    a, b = wk.make_workload(name), wk.make_workload(name)
+    for fa, fb in ((a.U0, b.U0), (a.S0, b.S0), (a.V0, b.V0)):
+        assert all(np.array_equal(x, y) for x, y in zip(fa, fb))
+    assert np.array_equal(a.sigma_s, b.sigma_s) and np.array_equal(a.Q, b.Q) and np.array_equal(a.w, b.w)
+    c = wk.make_workload(name, seed=a.seed + 1)
+    assert not all(np.array_equal(x, y) for x, y in zip(a.S0 + a.V0, c.S0 + c.V0))
