@@ -20,7 +20,10 @@ eigen-decomposition of C).  Readings used where the paper is silent:
   R10     explicit Euler for every K, S and L substep; the classic
           four-stage Runge-Kutta method (Section 4 states that the paper's
           runs use it) is available per problem, each substep integrated
-          over dt with its boundary data frozen.
+          over dt with its boundary data frozen; so is the exact flow of
+          each substep (matrix exponential of its affine right-hand side,
+          tiny grids only), the sub-flows under which the projector-splitting
+          integrator is exact (Section 2).
   R12     Algorithm 4's top block of S-hat is S^0 V^{0T} W V-hat.
   R14/R15 rank rules (see aug_rank / trunc_rank).
   R16     the collision stage does not truncate.
@@ -62,8 +65,8 @@ class Problem:
         self.tol = float(wl.tol)
         self.tol_aug_rel = float(wl.tol_aug_rel)
         self.integrator = str(getattr(wl, "integrator", "euler"))
-        if self.integrator not in ("euler", "rk4"):
-            raise ValueError("integrator must be 'euler' or 'rk4'")
+        if self.integrator not in ("euler", "rk4", "expm"):
+            raise ValueError("integrator must be 'euler', 'rk4' or 'expm'")
         n_sub = wl.px * wl.py
         self.sigma_s, self.sigma_t, self.Q = [], [], []
         for s in range(n_sub):
@@ -315,13 +318,42 @@ def rk4(f, y0, dt):
     return y0 + (dt / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
 
 
+def exact_flow(f, y0, dt):
+    """Exact solution at time dt of the affine ODE y' = f(y) = A y + b
+    (every substep of Algorithms 1-3 is affine in its unknown once the
+    boundary data are frozen).  A and b are read off f (b = f(0), column k
+    of A = f(e_k) - b) and the flow is exp(dt Z) [y0; 1] with
+    Z = [[A, b], [0, 0]].  Dense in y0.size: for tiny grids only."""
+    import scipy.linalg
+    shp = y0.shape
+    n = y0.size
+    b = np.asarray(f(np.zeros(shp))).ravel()
+    Z = np.zeros((n + 1, n + 1))
+    for k in range(n):
+        e = np.zeros(n)
+        e[k] = 1.0
+        Z[:n, k] = np.asarray(f(e.reshape(shp))).ravel() - b
+    Z[:n, n] = b
+    y = scipy.linalg.expm(dt * Z) @ np.append(y0.ravel(), 1.0)
+    return y[:n].reshape(shp)
+
+
+def integrate(f, y0, prob):
+    """One substep of length dt with the problem's integrator (R10)."""
+    if prob.integrator == "rk4":
+        return rk4(f, y0, prob.dt)
+    if prob.integrator == "expm":
+        return exact_flow(f, y0, prob.dt)
+    return y0 + prob.dt * f(y0)
+
+
 # ----------------------------------------------------------------------------
 # Algorithms 1 and 2: projector splitting for x / y advection
 # ----------------------------------------------------------------------------
 
 def psi_advect(K0, V_hat, Kb_lo, Kb_hi, axis, prob, rec=None):
-    """Algorithm 1 (axis 0) or Algorithm 2 (axis 1) with explicit Euler or
-    RK4 substeps (R10).
+    """Algorithm 1 (axis 0) or Algorithm 2 (axis 1) with explicit Euler, RK4
+    or exact substeps (R10).
 
     Returns (U^1, S^3, V^1) with F = U^1 S^3 V^{1T}."""
     w = prob.w
@@ -329,25 +361,26 @@ def psi_advect(K0, V_hat, Kb_lo, Kb_hi, axis, prob, rec=None):
     dt, h = prob.dt, prob.h
     C = V_hat.T @ ((w * om)[:, None] * V_hat)        # <V_j, v V_k> (Appendix A, R8)
     lam, P = np.linalg.eigh(C)
-    rk = prob.integrator == "rk4"
+    rk = prob.integrator != "euler"   # RK4 or exact sub-flows
     # step 1: K-step (eq. advx_evolK) with frozen boundary values
     if rk:
-        K1 = rk4(lambda K: kstep_rhs(K, P, lam, Kb_lo, Kb_hi, axis, prob), K0, dt)
+        K1 = integrate(lambda K: kstep_rhs(K, P, lam, Kb_lo, Kb_hi, axis, prob), K0, prob)
     else:
         K1 = K0 + dt * kstep_rhs(K0, P, lam, Kb_lo, Kb_hi, axis, prob)
     # step 2: QR
     U1, S1 = qr_spatial(K1, prob)
     # step 3: S-step (eq. advx_evolS), integrated with the opposite sign
     if rk:
-        S2 = rk4(lambda S: -(h * h) * (U1.T @ kstep_rhs(U1 @ S, P, lam, Kb_lo, Kb_hi, axis, prob)), S1, dt)
+        S2 = integrate(lambda S: -(h * h) * (U1.T @ kstep_rhs(U1 @ S, P, lam, Kb_lo, Kb_hi, axis, prob)),
+                       S1, prob)
     else:
         S2 = S1 - dt * (h * h) * (U1.T @ kstep_rhs(U1 @ S1, P, lam, Kb_lo, Kb_hi, axis, prob))
     # step 4: L-step (eq. advx_evolL) from L = V-hat S^{2T}; the per-direction
     # boundary value of f is K^b V-hat^T (R9)
     G_lo, G_hi = Kb_lo @ V_hat.T, Kb_hi @ V_hat.T
     if rk:
-        L1 = rk4(lambda L: ((h * h) * (U1.T @ direction_rhs(U1 @ L.T, om, G_lo, G_hi, axis, prob))).T,
-                 V_hat @ S2.T, dt)
+        L1 = integrate(lambda L: ((h * h) * (U1.T @ direction_rhs(U1 @ L.T, om, G_lo, G_hi, axis, prob))).T,
+                       V_hat @ S2.T, prob)
     else:
         F2 = U1 @ S2 @ V_hat.T
         A = direction_rhs(F2, om, G_lo, G_hi, axis, prob)
@@ -375,17 +408,17 @@ def truncate(U, S, V, prob):
 # ----------------------------------------------------------------------------
 
 def psi_collision(U, S, V, s, prob, rec=None):
-    """Algorithm 3 with explicit Euler or RK4 substeps (R10), eqs.
+    """Algorithm 3 with explicit Euler, RK4 or exact substeps (R10), eqs.
     coll_evolK/S/L; 1/(2 pi) becomes 1/W (R1, R22)."""
     w, W, dt, h = prob.w, prob.W, prob.dt, prob.h
     cs, ct, Qs = prob.sigma_s[s], prob.sigma_t[s], prob.Q[s]
     m = V.T @ w                                         # <V_j>
     K = U @ S
-    rk = prob.integrator == "rk4"
+    rk = prob.integrator != "euler"   # RK4 or exact sub-flows
     # step 1: K-step
     def fK(K):
         return (cs / W)[:, None] * (K @ m)[:, None] * m[None, :] - ct[:, None] * K + Qs[:, None] * m[None, :]
-    K1 = rk4(fK, K, dt) if rk else K + dt * fK(K)
+    K1 = integrate(fK, K, prob) if rk else K + dt * fK(K)
     # step 2: QR
     U1, S1 = qr_spatial(K1, prob)
     # step 3: S-step
@@ -394,13 +427,13 @@ def psi_collision(U, S, V, s, prob, rec=None):
     q = (h * h) * (U1.T @ Qs)                           # <U_i, Q>
     def fS(S):
         return -(1.0 / W) * Gs @ S @ np.outer(m, m) + Gt @ S - np.outer(q, m)
-    S2 = rk4(fS, S1, dt) if rk else S1 + dt * fS(S1)
+    S2 = integrate(fS, S1, prob) if rk else S1 + dt * fS(S1)
     # step 4: L-step from L = V S^{2T}
     L = V @ S2.T
     ones = np.ones(prob.M)
     def fL(L):
         return (1.0 / W) * np.outer(ones, (w @ L) @ Gs.T) - L @ Gt.T + np.outer(ones, q)
-    L1 = rk4(fL, L, dt) if rk else L + dt * fL(L)
+    L1 = integrate(fL, L, prob) if rk else L + dt * fL(L)
     # step 5: QR
     V1, S3 = qr_angular(L1, prob)
     if rec is not None:
