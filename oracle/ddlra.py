@@ -445,15 +445,22 @@ def psi_collision(U, S, V, s, prob, rec=None):
 # stages and the full step (Algorithm 6)
 # ----------------------------------------------------------------------------
 
-def stage_advect(state, axis, prob, rng=None, records=None):
+def stage_advect(state, axis, prob, rng=None, records=None, only=None):
     """Augment, advect and truncate every subdomain for one direction
     (Algorithm 6, steps 1-3 for x, 4-6 for y), all from a snapshot of the
     factors at the start of the stage (R6).  rng, if given, draws U_rand for
-    the literal form of Algorithm 4."""
+    the literal form of Algorithm 4.  only, if given, is a set of
+    subdomains: the others keep their input factors (to follow a few
+    subdomains of a large grid through their domain of dependence)."""
     snapshot = [tuple(f) for f in state]
     new = []
     for s in range(prob.n_sub):
         U, S, V = snapshot[s]
+        if only is not None and s not in only:
+            new.append((U, S, V))
+            if records is not None:
+                records.append(None)
+            continue
         nbrs = []
         for side in (-1, +1):
             n = prob.neighbour(s, axis, side)
@@ -476,11 +483,17 @@ def stage_advect(state, axis, prob, rng=None, records=None):
     return new
 
 
-def stage_collision(state, prob, records=None):
-    """Algorithm 6, step 7: Algorithm 3 on every subdomain, no truncation (R16)."""
+def stage_collision(state, prob, records=None, only=None):
+    """Algorithm 6, step 7: Algorithm 3 on every subdomain, no truncation
+    (R16); only as in stage_advect."""
     new = []
     for s in range(prob.n_sub):
         U, S, V = state[s]
+        if only is not None and s not in only:
+            new.append((U, S, V))
+            if records is not None:
+                records.append(None)
+            continue
         rec = {} if records is not None else None
         new.append(psi_collision(U, S, V, s, prob, rec))
         if records is not None:

@@ -7,7 +7,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["dd_api.hip", "dd_kernels_ts.hip", "dd_kernels_small.hip"]
+SOURCES = ["dd_api.hip", "dd_kernels_ts.hip", "dd_kernels_small.hip", "dd_wide.hip"]
 LIB = os.path.join(HERE, "libdd_dlra.so")
 
 FLAGS = [
@@ -18,7 +18,7 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False, jobs: int = 3) -> str:
+def build(verbose: bool = False, jobs: int = 4) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     inc = ["-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc")]
     objs, procs = [], []

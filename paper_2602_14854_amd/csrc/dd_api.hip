@@ -4,6 +4,7 @@
 // query calls.
 #include <math.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -12,6 +13,7 @@
 
 #include "dd_dlra.h"
 #include "dd_internal.h"
+#include "dd_wide.h"
 
 using dd::Dev;
 
@@ -50,6 +52,8 @@ enum Kind {
   K_ADV_PREP, K_KSTEP, K_GEMM_QR_K, K_SPATIAL_REDUCE, K_ADV_SSTEP, K_LSTEP, K_GEMM_QR_L, K_TRUNC,
   K_GEMM_FINAL_U, K_GEMM_FINAL_V, K_COLL_PREP, K_COLL_KSTEP, K_COLL_REDUCE, K_COLL_SSTEP,
   K_COLL_LSTEP, K_GEMM_QR_KC, K_GEMM_QR_LC, K_GEMM_QR_K_IP, K_GEMM_QR_L_IP, K_GEMM_QR_KC_IP, K_GEMM_QR_LC_IP,
+  K_W_GRAM_A, K_W_GRAM_VHAT, K_W_ANG, K_W_GRAM_K, K_W_SPATIAL, K_W_GRAM_L, K_W_GRAM_KC, K_W_COLL_REDUCE,
+  K_W_CHOL,
   K_COUNT
 };
 
@@ -60,9 +64,12 @@ const char* const kKindName[K_COUNT] = {
   "s_coll_prep", "k_coll_kstep", "k_coll_reduce", "s_coll_sstep", "k_coll_lstep",
   "k_gemm[QR K1 collision]", "k_gemm[QR L1 collision]", "k_gemm[QR K1 in place]", "k_gemm[QR L1 in place]",
   "k_gemm[QR K1 collision in place]", "k_gemm[QR L1 collision in place]",
+  "kw_xgram[Gram A]", "kw_xgram[Gram V-hat]", "kw_xgram[angular]", "kw_xgram[Gram K1]", "kw_xgram[spatial]",
+  "kw_xgram[Gram L1]", "kw_xgram[Gram K1 collision]", "kw_xgram[collision]", "sw_chol",
 };
 
 struct Layout {
+  int wide;
   int R, T, MA, N, M, nsub, ntN, ntM, nwgN, nwgM, gpTile;
   int64_t gpStride, smallStride;
   int off[48];
@@ -110,8 +117,8 @@ std::string validate(const dd_dlra_config* c) {
   if (!(c->tol_aug_rel >= 0.0)) return "tol_aug_rel must be >= 0";
   const int R = c->rank_mode == DD_RANK_FIXED ? c->r_fixed : c->r_max;
   if (c->r_int_max < R) return "r_int_max must be at least the stored-rank capacity";
-  if (c->r_int_max > dd::CAP) return "r_int_max beyond the supported maximum of 64";
-  if (3 * R > dd::CAP) return "stored-rank capacity beyond the supported maximum of 21";
+  if (c->r_int_max > dd::WCAP_T) return "r_int_max beyond the supported maximum of 128";
+  if (R > dd::WCAP_R) return "stored-rank capacity beyond the supported maximum of 64";
   if (c->precision < DD_PREC_FP64 || c->precision > DD_PREC_MIXED_BF16) return "unknown precision";
   if (c->exec_mode < DD_EXEC_PER_SUBDOMAIN || c->exec_mode > DD_EXEC_BATCHED_GRAPH) return "unknown exec_mode";
   for (int f = 0; f < 4; ++f)
@@ -119,8 +126,20 @@ std::string validate(const dd_dlra_config* c) {
   return "";
 }
 
+// The narrow plan's kernels hold up to 64 intermediate and augmentation
+// columns (stored ranks up to 21); larger capacities take the wide plan.
+// DD_DLRA_PLAN=wide in the environment selects the wide plan for any
+// capacity (used to test it on small problems).
+bool wide_plan(const dd_dlra_config* c) {
+  const int R = c->rank_mode == DD_RANK_FIXED ? c->r_fixed : c->r_max;
+  const char* env = getenv("DD_DLRA_PLAN");
+  if (env && strcmp(env, "wide") == 0) return true;
+  return c->r_int_max > dd::CAP || 3 * R > dd::CAP;
+}
+
 Layout make_layout(const dd_dlra_config* c) {
   Layout L;
+  L.wide = wide_plan(c) ? 1 : 0;
   L.R = c->rank_mode == DD_RANK_FIXED ? c->r_fixed : c->r_max;
   L.T = c->r_int_max;
   L.MA = 3 * L.R;
@@ -135,7 +154,7 @@ Layout make_layout(const dd_dlra_config* c) {
   L.nwgN = std::min(L.ntN, cap);
   L.nwgM = std::min(L.ntM, cap);
   const int R = L.R, T = L.T, MA = L.MA;
-  L.gpTile = std::max(std::max(MA * MA, 3 * T * T + 3 * R * T), std::max(2 * T * T, 2 * R * R + R));
+  L.gpTile = std::max(std::max(MA * MA, 3 * T * T + 3 * R * T), std::max(2 * T * T + 4 * T * R, 2 * R * R + R));
   L.gpStride = (int64_t)std::max(L.nwgN, L.nwgM) * L.gpTile;
   // small workspace
   int o = 0;
@@ -196,7 +215,7 @@ Layout make_layout(const dd_dlra_config* c) {
   L.oV = seg(ns * L.M * R * d8);
   L.oS = seg(ns * R * R * d8);
   L.oA = seg(ns * L.M * MA * d8);
-  L.oZ = seg(ns * L.M * MA * d8);
+  L.oZ = seg(ns * L.M * std::max(MA, T) * d8);  // the wide plan's second V-hat buffer
   L.oQh = seg(ns * L.M * T * es);
   L.oK1 = seg(ns * L.N * T * es);
   L.oK2 = seg(ns * L.N * T * es);
@@ -248,6 +267,7 @@ void fill_dev(Dev& d, const Layout& L, const dd_dlra_config* c, char* base) {
   d.r_int_max = c->r_int_max;
   d.strict = c->strict_caps;
   d.prec = c->precision;
+  d.wide = L.wide;
   d.tol = c->tol;
   d.tol_aug_rel = c->tol_aug_rel;
   d.U = (double*)(base + L.oU);
@@ -378,6 +398,8 @@ bool repeatable(int kind) {
     case K_AUG_FORM: case K_GEMM_VHAT: case K_ANG_REDUCE: case K_KSTEP: case K_GEMM_QR_K:
     case K_SPATIAL_REDUCE: case K_LSTEP: case K_GEMM_QR_L: case K_GEMM_FINAL_U: case K_GEMM_FINAL_V:
     case K_COLL_KSTEP: case K_COLL_REDUCE: case K_COLL_LSTEP: case K_GEMM_QR_KC: case K_GEMM_QR_LC:
+    case K_W_GRAM_A: case K_W_GRAM_VHAT: case K_W_ANG: case K_W_GRAM_K: case K_W_SPATIAL: case K_W_GRAM_L:
+    case K_W_GRAM_KC: case K_W_COLL_REDUCE:
       return true;
     default:
       return false;
@@ -565,7 +587,180 @@ void enqueue_collision(dd_dlra_handle h) {
            K_GEMM_QR_LC_IP, d.S);
 }
 
+
+// ---------------------------------------------------------------- wide plan
+
+dd::XSrc xsrc(const void* p, int64_t sd, int ld, int dim, bool is64, int side = 0, bool rowscale = false,
+              int face = 0) {
+  dd::XSrc x;
+  x.p = p;
+  x.sd = sd;
+  x.ld = ld;
+  x.dim = dim;
+  x.side = side;
+  x.rowscale = rowscale ? 1 : 0;
+  x.is64 = is64 ? 1 : 0;
+  x.vec = 0;
+  x.face = face;
+  return x;
+}
+
+dd::XJob xjob(const dd::XSrc& x, const dd::XSrc& y, int capx, int capy, int wmode, bool sym, int out_off,
+              int out_ld, double scale = 1.0, bool shift = false) {
+  dd::XJob j;
+  j.x = x;
+  j.y = y;
+  j.wmode = wmode;
+  j.shift = shift ? 1 : 0;
+  j.sym = sym ? 1 : 0;
+  j.out_off = out_off;
+  j.out_ld = out_ld;
+  j.scale = scale;
+  j.pa = (capx + 63) / 64;
+  j.pb = (capy + 63) / 64;
+  j.zbase = 0;
+  j.rows_cells = 0;
+  return j;
+}
+
+// partial Grams X^T X of a working array (ld rows), live ld
+void w_gram(dd_dlra_handle h, int kind, int axis, const void* X, bool is64, int64_t sd, int rows, int ndim, int cap,
+            bool cells) {
+  const Dev& d = h->d;
+  dd::XJobs jobs;
+  jobs.n = 1;
+  const dd::XSrc x = xsrc(X, sd, rows, ndim, is64);
+  jobs.j[0] = xjob(x, x, cap, cap, 0, true, 0, -1);
+  phase(h, kind, [&](int s0, int ns) { dd::launch_w_xgram(d, axis, s0, ns, jobs, cells, h->stream); });
+}
+
+// passes of Cholesky QR of X (rows x n, n = dim ndim <= 128) for the wide
+// plan, out of place, alternating between X and Y; acc: accumulate the R
+// factors in the small workspace.  Returns the buffer holding Q.
+void* w_chol_qr(dd_dlra_handle h, int axis, int ndim, void* X, void* Y, int64_t sd, int rows, bool cells, int passes,
+                bool acc, int gram_kind, int gemm_kind) {
+  const Dev& d = h->d;
+  const int ngp = cells ? d.nwgN : d.nwgM;
+  const int cap = ndim == dd::DIM_T ? d.T : d.R;
+  void* cur = X;
+  void* oth = Y;
+  for (int pass = 0; pass < passes; ++pass) {
+    w_gram(h, gram_kind, axis, cur, false, sd, rows, ndim, cap, cells);
+    phase(h, K_W_CHOL, [&](int s0, int ns) {
+      dd::launch_w_chol(d, axis, s0, ns, ndim, rows, ngp, acc ? (pass == 0 ? 1 : 2) : 0, 1.0, d.oRinv, d.oRacc, d.T,
+                        h->stream);
+    });
+    phase(h, gemm_kind, [&](int s0, int ns) {
+      dd::launch_w_gemm(d, axis, s0, ns, cur, false, sd, rows, ndim, ndim, d.oRinv, d.T, oth, false, sd, nullptr,
+                        d.oFill, cells, true, h->stream);
+    });
+    std::swap(cur, oth);
+  }
+  return cur;
+}
+
+void enqueue_advection_wide(dd_dlra_handle h, int axis) {
+  const Dev& d = h->d;
+  hipStream_t st = h->stream;
+  const int64_t sdMA = (int64_t)d.M * d.MA, sdMT = (int64_t)d.M * d.T, sdNT = (int64_t)d.N * d.T;
+  const int64_t sdMR = (int64_t)d.M * d.R, sdNR = (int64_t)d.N * d.R;
+  const int R = d.R, T = d.T;
+  // Algorithm 4: A = sqrt(w) L0, its Gram, the SVD through the pivoted
+  // Cholesky factor, V-hat = A B Sigma^-2, two Cholesky-QR passes
+  phase(h, K_AUG_FORM, [&](int s0, int ns) { dd::launch_w_aug_form(d, axis, s0, ns, st); });
+  w_gram(h, K_W_GRAM_A, axis, d.A, true, sdMA, d.M, dd::DIM_M0, d.MA, false);
+  phase(h, K_AUG_SVD, [&](int s0, int ns) { dd::launch_w_aug_svd(d, axis, s0, ns, st); });
+  phase(h, K_GEMM_VHAT, [&](int s0, int ns) {
+    dd::launch_w_gemm(d, axis, s0, ns, d.A, true, sdMA, d.M, dd::DIM_M0, dd::DIM_T, d.oCoef, d.MA, d.Qh, false, sdMT,
+                      nullptr, d.oFill, false, true, st);
+  });
+  void* q = w_chol_qr(h, axis, dd::DIM_T, d.Qh, d.Z, sdMT, d.M, false, 2, false, K_W_GRAM_VHAT, K_GEMM_QR_VHAT);
+  (void)q;  // two passes: V-hat is back in Qh
+  // angular Galerkin matrices (partial layout of the narrow plan)
+  {
+    dd::XJobs jobs;
+    const dd::XSrc qh = xsrc(d.Qh, sdMT, d.M, dd::DIM_T, false);
+    jobs.n = 6;
+    jobs.j[0] = xjob(xsrc(d.V, sdMR, d.M, dd::DIM_R, true, 0, true), qh, R, T, 0, false, 0, R);
+    jobs.j[1] = xjob(qh, qh, T, T, 1, true, R * T, -1);
+    jobs.j[2] = xjob(qh, qh, T, T, 2, true, R * T + T * T, -1);
+    jobs.j[3] = xjob(qh, qh, T, T, 3, true, R * T + 2 * T * T, -1);
+    jobs.j[4] = xjob(xsrc(d.V, sdMR, d.M, dd::DIM_R, true, -1, true), qh, R, T, 2, false, R * T + 3 * T * T, R);
+    jobs.j[5] = xjob(xsrc(d.V, sdMR, d.M, dd::DIM_R, true, +1, true), qh, R, T, 3, false, 2 * R * T + 3 * T * T, R);
+    phase(h, K_W_ANG, [&](int s0, int ns) { dd::launch_w_xgram(d, axis, s0, ns, jobs, false, st); });
+  }
+  phase(h, K_ADV_PREP, [&](int s0, int ns) { dd::launch_w_adv_prep(d, axis, s0, ns, st); });
+  // Algorithm 1/2 steps 1-2: K-step, QR (three passes: K1 -> K2 -> K1 -> K2)
+  phase(h, K_KSTEP, [&](int s0, int ns) { dd::launch_w_kstep(d, axis, s0, ns, st); });
+  void* Q = w_chol_qr(h, axis, dd::DIM_T, d.K1, d.K2, sdNT, d.N, true, 3, true, K_W_GRAM_K, K_GEMM_QR_K);
+  // step 3: spatial Galerkin matrix and the face products, S-step
+  {
+    dd::XJobs jobs;
+    const dd::XSrc qa = xsrc(Q, sdNT, d.N, dd::DIM_T, false);
+    const dd::XSrc ql = xsrc(Q, sdNT, d.N, dd::DIM_T, false, 0, false, 1);
+    const dd::XSrc qhf = xsrc(Q, sdNT, d.N, dd::DIM_T, false, 0, false, 2);
+    jobs.n = 5;
+    jobs.j[0] = xjob(qa, qa, T, T, 0, false, 0, -1, 1.0, true);
+    const int oX = 2 * T * T;
+    jobs.j[1] = xjob(ql, xsrc(d.U, sdNR, d.N, dd::DIM_R, true, 0, false, 1), T, R, 0, false, oX, T);
+    jobs.j[2] = xjob(qhf, xsrc(d.U, sdNR, d.N, dd::DIM_R, true, 0, false, 2), T, R, 0, false, oX + T * R, T);
+    jobs.j[3] = xjob(ql, xsrc(d.U, sdNR, d.N, dd::DIM_R, true, -1, false, 2), T, R, 0, false, oX + 2 * T * R, T);
+    jobs.j[4] = xjob(qhf, xsrc(d.U, sdNR, d.N, dd::DIM_R, true, +1, false, 1), T, R, 0, false, oX + 3 * T * R, T);
+    phase(h, K_W_SPATIAL, [&](int s0, int ns) { dd::launch_w_xgram(d, axis, s0, ns, jobs, true, st); });
+  }
+  phase(h, K_ADV_SSTEP, [&](int s0, int ns) { dd::launch_w_adv_sstep(d, axis, s0, ns, st); });
+  // steps 4-5: L-step, weighted QR (AL -> AL2 -> AL -> AL2)
+  phase(h, K_LSTEP, [&](int s0, int ns) { dd::launch_w_lstep(d, axis, s0, ns, st); });
+  void* QL = w_chol_qr(h, axis, dd::DIM_T, d.AL, d.AL2, sdMT, d.M, false, 3, true, K_W_GRAM_L, K_GEMM_QR_L);
+  // Algorithm 5: truncation, then rotate the bases into the state
+  phase(h, K_TRUNC, [&](int s0, int ns) { dd::launch_w_trunc(d, axis, s0, ns, st); });
+  phase(h, K_GEMM_FINAL_U, [&](int s0, int ns) {
+    dd::launch_w_gemm(d, axis, s0, ns, Q, false, sdNT, d.N, dd::DIM_T, dd::DIM_RNEW, d.oBu, d.T, d.U, true, sdNR,
+                      nullptr, -1, true, false, st);
+  });
+  phase(h, K_GEMM_FINAL_V, [&](int s0, int ns) {
+    dd::launch_w_gemm(d, axis, s0, ns, QL, false, sdMT, d.M, dd::DIM_T, dd::DIM_RNEW, d.oBv, d.T, d.V, true, sdMR,
+                      d.isw, -1, false, false, st, /*set_rank=*/true);
+  });
+}
+
+void enqueue_collision_wide(dd_dlra_handle h) {
+  const Dev& d = h->d;
+  hipStream_t st = h->stream;
+  const int64_t sdMT = (int64_t)d.M * d.T, sdNT = (int64_t)d.N * d.T, sdNR = (int64_t)d.N * d.R;
+  const int R = d.R;
+  phase(h, K_COLL_PREP, [&](int s0, int ns) { dd::launch_w_coll_prep(d, s0, ns, st); });
+  phase(h, K_COLL_KSTEP, [&](int s0, int ns) { dd::launch_w_coll_kstep(d, s0, ns, st); });
+  w_gram(h, K_W_GRAM_KC, 0, d.K1, false, sdNT, d.N, dd::DIM_R, R, true);
+  // QR of K1 (stored ranks <= 64: the narrow Cholesky-QR kernels); the last
+  // product writes U^1 = Q / h into the state
+  chol_qr3(h, 0, dd::DIM_R, d.K1, d.K2, sdNT, d.N, true, d.U, (int64_t)d.N * d.R, nullptr, 1.0 / d.h, K_GEMM_QR_KC,
+           K_GEMM_QR_KC_IP);
+  {
+    dd::XJobs jobs;
+    const dd::XSrc u = xsrc(d.U, sdNR, d.N, dd::DIM_R, true);
+    dd::XSrc qv = xsrc(d.Qsrc, d.N, d.N, dd::DIM_R, true);
+    qv.vec = 1;
+    const double h2 = d.h * d.h;
+    jobs.n = 3;
+    jobs.j[0] = xjob(u, u, R, R, 4, true, 0, R, h2);
+    jobs.j[1] = xjob(u, u, R, R, 5, true, R * R, R, h2);
+    jobs.j[2] = xjob(u, qv, R, 1, 0, false, 2 * R * R, R, h2);
+    phase(h, K_W_COLL_REDUCE, [&](int s0, int ns) { dd::launch_w_xgram(d, 0, s0, ns, jobs, true, st); });
+  }
+  phase(h, K_COLL_SSTEP, [&](int s0, int ns) { dd::launch_coll_sstep(d, s0, ns, st); });
+  phase(h, K_COLL_LSTEP, [&](int s0, int ns) { dd::launch_coll_lstep(d, s0, ns, st); });
+  chol_qr3(h, 0, dd::DIM_R, d.AL, d.AL2, sdMT, d.M, false, d.V, (int64_t)d.M * d.R, d.isw, 1.0, K_GEMM_QR_LC,
+           K_GEMM_QR_LC_IP, d.S);
+}
+
 void enqueue_step(dd_dlra_handle h) {
+  if (h->d.wide) {
+    enqueue_advection_wide(h, 0);
+    enqueue_advection_wide(h, 1);
+    enqueue_collision_wide(h);
+    return;
+  }
   enqueue_advection(h, 0);
   enqueue_advection(h, 1);
   enqueue_collision(h);
@@ -635,6 +830,7 @@ dd_status dd_dlra_create(const dd_dlra_config* cfg, const int32_t* rank0, const 
   static bool kernels_ready = false;
   if (!kernels_ready) {
     dd::init_kernels();
+    dd::init_wide_kernels();
     kernels_ready = true;
   }
   dd_dlra_handle h = new dd_dlra_s();
@@ -678,7 +874,8 @@ dd_status dd_dlra_create(const dd_dlra_config* cfg, const int32_t* rank0, const 
       h->err = "cannot query the compute-unit count";
       return fail(DD_EHIP);
     }
-    const int per_sd = std::max(1, ncu * dd::ts_resident_wgs(d) / d.nsub);
+    const int occ = d.wide ? 1 : dd::ts_resident_wgs(d);
+    const int per_sd = std::max(1, ncu * occ / d.nsub);
     d.nwgN = std::min(per_sd, L.nwgN);
     d.nwgM = std::min(per_sd, L.nwgM);
   }
@@ -868,8 +1065,13 @@ dd_status dd_dlra_stage(dd_dlra_handle h, int32_t stage) {
     h->err = "stage must be 0, 1 or 2";
     return DD_EINVAL;
   }
-  if (stage < 2) enqueue_advection(h, stage);
-  else enqueue_collision(h);
+  if (h->d.wide) {
+    if (stage < 2) enqueue_advection_wide(h, stage);
+    else enqueue_collision_wide(h);
+  } else {
+    if (stage < 2) enqueue_advection(h, stage);
+    else enqueue_collision(h);
+  }
   HIPCHK(hipGetLastError());
   return DD_OK;
 }

@@ -36,6 +36,7 @@ struct Dev {
   // rank rules and precision mode (DD_PREC_*)
   int rank_mode, r_fixed, r_min, r_max, r_int_max, strict;
   int prec;
+  int wide;                // 1: the wide launch plan (capacities beyond the narrow kernels)
   double tol, tol_aug_rel;
   // state (FP64 in every mode)
   double* U;               // [nsub][R][N]

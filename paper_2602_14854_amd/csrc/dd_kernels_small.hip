@@ -726,12 +726,13 @@ void launch_coll_prep(const Dev& d, int sd0, int nsd, hipStream_t st) {
 // S-step (eq. coll_evolS) and L-step coefficients (eq. coll_evolL):
 //   S2 = S1 + dt (-(1/W) Gs S1 m m^T + Gt S1 - q m^T),  S1 = h Racc,
 //   P = S2^T (I - dt Gt),  crow = dt ((S2 m)^T Gs / W + q^T).
-// All operands are staged in LDS (leading dimension CAPR).
+// All operands are staged in LDS (leading dimension L, the stored-rank
+// capacity: 21, or 64 in the wide plan).
+template <int L>
 __global__ __launch_bounds__(NTHR) void s_coll_sstep(Dev d, int sd0) {
   const int s = sd0 + blockIdx.x;
   const int r = d.rank[s];
   const int R = d.R, T = d.T;
-  constexpr int L = CAPR;
   double* sm = small_of(d, s);
   __shared__ double Gs[L * L], Gt[L * L], S1[L * L], S2[L * L];
   __shared__ double qv[L], mv[L], v1[L], v2[L], v3[L];
@@ -785,7 +786,8 @@ __global__ __launch_bounds__(NTHR) void s_coll_sstep(Dev d, int sd0) {
 }
 
 void launch_coll_sstep(const Dev& d, int sd0, int nsd, hipStream_t st) {
-  hipLaunchKernelGGL(s_coll_sstep, dim3(nsd), dim3(NTHR), 0, st, d, sd0);
+  if (d.R <= CAPR) hipLaunchKernelGGL(s_coll_sstep<CAPR>, dim3(nsd), dim3(NTHR), 0, st, d, sd0);
+  else hipLaunchKernelGGL(s_coll_sstep<64>, dim3(nsd), dim3(NTHR), 0, st, d, sd0);
 }
 
 }  // namespace dd

@@ -1064,8 +1064,9 @@ __global__ __launch_bounds__(NTHR) void k_moments(Dev d, int nmom) {
   const int s = blockIdx.y;
   const int r = d.rank[s];
   const int N = d.N, M = d.M, R = d.R;
-  __shared__ double mv[3 * CAPR];
-  __shared__ double smv[3 * CAPR];
+  constexpr int MV = 64;  // largest stored rank of either plan
+  __shared__ double mv[3 * MV];
+  __shared__ double smv[3 * MV];
   const double* Vs = d.V + (int64_t)s * M * R;
   // (V^T (w Omega_m))_a for a < r, m < nmom (Omega_0 = 1), one per thread in
   // a fixed order over the directions
@@ -1077,15 +1078,15 @@ __global__ __launch_bounds__(NTHR) void k_moments(Dev d, int nmom) {
       const double wq = m == 0 ? d.w[q] : d.w[q] * om[q];
       acc = fma(Vs[(int64_t)a * M + q], wq, acc);
     }
-    mv[m * CAPR + a] = acc;
+    mv[m * MV + a] = acc;
   }
   __syncthreads();
   const double* Sg = d.S + (int64_t)s * R * R;
   for (int idx = threadIdx.x; idx < nmom * r; idx += NTHR) {
     const int a = idx % r, m = idx / r;
     double acc = 0.0;
-    for (int b = 0; b < r; ++b) acc = fma(Sg[a + b * R], mv[m * CAPR + b], acc);
-    smv[m * CAPR + a] = acc;
+    for (int b = 0; b < r; ++b) acc = fma(Sg[a + b * R], mv[m * MV + b], acc);
+    smv[m * MV + a] = acc;
   }
   __syncthreads();
   const double* Us = d.U + (int64_t)s * N * R;
@@ -1096,7 +1097,7 @@ __global__ __launch_bounds__(NTHR) void k_moments(Dev d, int nmom) {
     const int64_t g = (int64_t)(sy * d.lny + iy) * d.nx + sx * d.lnx + ix;
     for (int m = 0; m < nmom; ++m) {
       double acc = 0.0;
-      for (int a = 0; a < r; ++a) acc = fma(Us[(int64_t)a * N + p], smv[m * CAPR + a], acc);
+      for (int a = 0; a < r; ++a) acc = fma(Us[(int64_t)a * N + p], smv[m * MV + a], acc);
       d.rho[m * plane + g] = acc;
     }
   }
@@ -1310,6 +1311,12 @@ void launch_coll_lstep(const Dev& d, int sd0, int nsd, hipStream_t st) {
   with_prec(d.prec, false, [&](auto ts, auto pc) {
     using S = typename decltype(ts)::type;
     constexpr int P = decltype(pc)::value;
+    if (d.R > CAPR) {
+      // the wide plan: stored ranks up to 64
+      constexpr int KSP = 16;  // 64 columns: sixteen 4-column steps, or two 32-column BF16 groups
+      hipLaunchKernelGGL((k_coll_lstep<S, P, 4, KSP>), dim3(d.nwgM, nsd), dim3(NTHR), 0, st, d, sd0);
+      return;
+    }
     with_ksp<P>(d.R, [&](auto kp) {
       constexpr int KSP = decltype(kp)::value;
       with_ncb(ncb_of(d.R), [&](auto c) {

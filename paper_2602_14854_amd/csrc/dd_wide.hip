@@ -1,0 +1,1811 @@
+// Kernels of the wide plan: the DD-DLRA step for capacities beyond the
+// narrow kernels' register and LDS layouts -- stored ranks up to 64,
+// intermediate ranks up to 128 and augmentation widths up to 192 (the
+// adaptive configurations of Algorithms 4-5 whose ranks grow near sources).
+//
+// Tall-skinny products (Y = X B) hold the coefficient fragments of one chunk
+// of output columns in LDS; the chunk index is blockIdx.z, so a product of n
+// columns runs as ceil(n / chunk) column slices over the same rows, and the
+// k dimension (up to 192) is walked in groups of 64 columns whose operand
+// loads are issued one group ahead of the matrix-core instructions.  Gram and
+// Galerkin reductions are separate launches (kw_xgram) that load both
+// operands straight into the matrix-core lane layout and leave one 64 x 64
+// block of one partial per workgroup.
+//
+// Small per-subdomain kernels run one workgroup of 1024 threads per
+// subdomain.  Matrices of order up to 128 sit in LDS; the augmentation Gram
+// (order up to 192) is kept as a packed lower triangle.  The one-sided
+// Jacobi SVD keeps its columns in registers: 16 wavefronts hold the column
+// pairs of a round-robin (caterpillar) ordering, the two columns of a pair
+// spread over the 64 lanes, and after each round only the pairs at the ends
+// of a wavefront's run exchange a column with the neighbouring wavefront
+// through LDS.
+#include <algorithm>
+#include <type_traits>
+
+#include "dd_dlra.h"
+#include "dd_dense.h"
+#include "dd_wide.h"
+
+namespace dd {
+
+constexpr int WTHR = 512;          // threads of a wide tall-skinny product
+constexpr int WNW = WTHR / 64;
+constexpr int XTHR = 256;          // threads of a wide reduction (kw_xgram)
+constexpr int STHR = 1024;         // threads of a wide small kernel
+constexpr int SNW = STHR / 64;
+constexpr int WLD = WCAP_T + 1;    // leading dimension of LDS matrices of order <= 128
+
+__host__ __device__ constexpr int wdiv(int a, int b) { return (a + b - 1) / b; }
+
+// ============================================================================
+// tall-skinny products
+// ============================================================================
+
+// Fragments of output columns [c0, c0 + 16 NCB) of B (k x n, ld bld) for ng
+// groups of 64 rows of B: frag[((g 16 + u) NCB + cb) 64 + lane] =
+// B[64 g + sub_col(u, lane / 16)][c0 + 16 cb + lane % 16].
+template <int P, int NCB>
+__device__ __forceinline__ void stage_frags(typename Prec<P>::F* frag, const double* B, int bld, int k, int n, int c0,
+                                            int ng) {
+  using F = typename Prec<P>::F;
+  const int total = ng * 16 * NCB * 64;
+  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+    const int l = idx & 63, f = idx >> 6, cb = f % NCB, u = f / NCB;
+    const int kc = 64 * (u >> 4) + sub_col<P>(u & 15, l >> 4), col = c0 + 16 * cb + (l & 15);
+    frag[idx] = (kc < k && col < n) ? (F)B[kc + (int64_t)col * bld] : (F)0;
+  }
+}
+
+// Y[:, c0 + j] = diag(rowscale) X B[:, c0 + j], c0 = 16 NCB blockIdx.z; X
+// rows x k (ld rows), B k x n in the small workspace.  Columns flagged in the
+// fill mask get deterministic pseudo-random values; with set_rank, one
+// workgroup of each subdomain commits the truncated rank.
+template <class SI, class SO, int P, int NCB>
+__global__ __launch_bounds__(WTHR) void kw_gemm(Dev d, int axis, int sd0, const void* X, int64_t xsd, int rows,
+                                                int kdim, int ndim, int boff, int bld, void* Y, int64_t ysd,
+                                                const double* rowscale, int fill_off, int set_rank) {
+  using F = typename Prec<P>::F;
+  using Acc = typename Prec<P>::Acc;
+  const int s = sd0 + blockIdx.y;
+  const int k = dim_of(d, s, axis, kdim);
+  const int n = dim_of(d, s, axis, ndim);
+  const int c0 = blockIdx.z * 16 * NCB;
+  if (set_rank && blockIdx.x == 0 && blockIdx.z == 0 && threadIdx.x == 0) d.rank[s] = d.rnew[s];
+  if (c0 >= n || k <= 0) return;
+  const int ng = wdiv(k, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l16 = lane & 15, kq = lane >> 4;
+  extern __shared__ double lds[];
+  F* frag = reinterpret_cast<F*>(lds);
+  __shared__ int fillm[16 * NCB];
+  const double* sm = small_of(d, s);
+  stage_frags<P, NCB>(frag, sm + boff, bld, k, n, c0, ng);
+  for (int j = threadIdx.x; j < 16 * NCB; j += WTHR)
+    fillm[j] = (fill_off >= 0 && c0 + j < n) ? (sm[fill_off + c0 + j] != 0.0) : 0;
+  __syncthreads();
+  const SI* Xs = (const SI*)X + (int64_t)s * xsd;
+  SO* Ys = (SO*)Y + (int64_t)s * ysd;
+  const int nst = wdiv(rows, 16);
+  const int stride = gridDim.x * WNW;
+  F xv[16], xn[16];
+  auto load = [&](int st_, int g_) {
+    const int row_ = st_ * 16 + l16;
+    const int rc = row_ < rows ? row_ : rows - 1;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int kc = 64 * g_ + sub_col<P>(u, kq);
+      const bool in = row_ < rows && kc < k;
+      const SI v = Xs[(int64_t)(in ? kc : 0) * rows + rc];
+      xn[u] = in ? (F)v : (F)0;
+    }
+  };
+  int st = blockIdx.x * WNW + wave, g = 0;
+  if (st < nst) load(st, 0);
+  Acc acc[NCB];
+  zero_prod<P>(acc, NCB);
+  while (st < nst) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) xv[u] = xn[u];
+    int st2 = st, g2 = g + 1;
+    if (g2 >= ng) {
+      g2 = 0;
+      st2 = st + stride;
+    }
+    if (st2 < nst) load(st2, g2);
+    prod_acc<P, NCB, 16>(acc, frag + g * 16 * NCB * 64, xv);
+    if (g == ng - 1) {
+      const int row = st * 16 + l16;
+      const bool rin = row < rows;
+      const double rs = (rowscale != nullptr && rin) ? rowscale[row] : 1.0;
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int j = out_col<P>(cb, v, kq);
+          double val = (double)acc[cb][v] * rs;
+          if (fillm[j]) val = hash_unit(((uint64_t)s << 40) ^ ((uint64_t)(c0 + j) << 24) ^ (uint64_t)row);
+          if (rin && c0 + j < n) Ys[(int64_t)(c0 + j) * rows + row] = (SO)val;
+        }
+      }
+      zero_prod<P>(acc, NCB);
+    }
+    st = st2;
+    g = g2;
+  }
+}
+
+// Augmentation matrix (Algorithm 4, step 1), one source block per blockIdx.z
+// (0: the subdomain, 1: its low neighbour, 2: its high neighbour):
+//   A[q, off_b + j] = sqrt(w_q) (V_b S_b^T)[q, j],  j < r_b.
+__global__ __launch_bounds__(WTHR) void kw_aug_form(Dev d, int axis, int sd0) {
+  constexpr int NCB = 4;
+  const int s = sd0 + blockIdx.y;
+  const int b = blockIdx.z;
+  const int lo = neighbour(d, s, axis, -1), hi = neighbour(d, s, axis, +1);
+  const int nb = b == 0 ? s : (b == 1 ? lo : hi);
+  if (nb < 0) return;
+  const int rs = d.rank[s], rl = lo >= 0 ? d.rank[lo] : 0;
+  const int off = b == 0 ? 0 : (b == 1 ? rs : rs + rl);
+  const int rb = d.rank[nb];
+  const int M = d.M, R = d.R;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l16 = lane & 15, kq = lane >> 4;
+  extern __shared__ double lds[];
+  double* frag = lds;  // 16 x NCB x 64
+  const double* Sn = d.S + (int64_t)nb * R * R;
+  for (int idx = threadIdx.x; idx < 16 * NCB * 64; idx += WTHR) {
+    const int l = idx & 63, f = idx >> 6, cb = f % NCB, u = f / NCB;
+    const int kc = sub_col<0>(u, l >> 4), col = 16 * cb + (l & 15);
+    frag[idx] = (kc < rb && col < rb) ? Sn[col + (int64_t)kc * R] : 0.0;  // S^T
+  }
+  __syncthreads();
+  const double* Vn = d.V + (int64_t)nb * M * R;
+  double* As = d.A + (int64_t)s * M * d.MA + (int64_t)off * M;
+  const int nst = wdiv(M, 16);
+  const int stride = gridDim.x * WNW;
+  for (int st = blockIdx.x * WNW + wave; st < nst; st += stride) {
+    const int q = st * 16 + l16;
+    const bool rin = q < M;
+    const int qc = rin ? q : M - 1;
+    double xv[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int kc = sub_col<0>(u, kq);
+      const bool in = rin && kc < rb;
+      const double v = Vn[(int64_t)(in ? kc : 0) * M + qc];
+      xv[u] = in ? v : 0.0;
+    }
+    dbl4 acc[NCB];
+    zero_acc<NCB>(acc);
+    prod_acc<0, NCB, 16>(acc, frag, xv);
+    const double swq = d.sw[qc];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int j = out_col<0>(cb, v, kq);
+        if (rin && j < rb) As[(int64_t)j * M + q] = acc[cb][v] * swq;
+      }
+  }
+}
+
+// K-step of an advection stage (eq. advx_evolK / advy_evolK, Appendix A),
+// fused with K = U (S T) and the inflow ghosts, for output columns
+// [c0, c0 + 32), c0 = 32 blockIdx.z:
+//   K1[p] = U[p] M0 + U[p-e] Mm + U[p+e] Mp,
+// the missing row at the low face replaced by U[p] GLo + U_lo[its high face]
+// GLoN and at the high face by U[p] GHi + U_hi[its low face] GHiN.  The
+// stored-rank dimension (up to 64) is walked in groups of 32 columns, only
+// as many as the ranks need.
+template <class S, int P>
+__global__ __launch_bounds__(WTHR) void kw_kstep(Dev d, int axis, int sd0) {
+  using F = typename Prec<P>::F;
+  using Acc = typename Prec<P>::Acc;
+  constexpr int NCB = 2, KSP = 16, KG = 8;  // KG sub-steps = 32 columns per group
+  const int s = sd0 + blockIdx.y;
+  const int t = d.tdim[s];
+  const int c0 = blockIdx.z * 16 * NCB;
+  if (c0 >= t) return;
+  const int lo = neighbour(d, s, axis, -1), hi = neighbour(d, s, axis, +1);
+  const int r = d.rank[s], rl = lo >= 0 ? d.rank[lo] : 0, rh = hi >= 0 ? d.rank[hi] : 0;
+  const int N = d.N, R = d.R;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l16 = lane & 15, kq = lane >> 4;
+  extern __shared__ double lds[];
+  constexpr int nfrag = 7 * KSP * NCB * 64;
+  constexpr int bstride = KSP * NCB * 64;
+  constexpr int gstride = KG * NCB * 64;
+  F* Cf = reinterpret_cast<F*>(lds);
+  {
+    const double* sm = small_of(d, s);
+    const int offs[7] = {d.oM0, d.oMm, d.oMp, d.oGLo, d.oGHi, d.oGLoN, d.oGHiN};
+    const int rows[7] = {r, r, r, r, r, rl, rh};
+    for (int idx = threadIdx.x; idx < nfrag; idx += WTHR) {
+      const int l = idx & 63, f = idx >> 6, cb = f % NCB, u = (f / NCB) % KSP, m = f / (NCB * KSP);
+      const int kc = 32 * (u / KG) + sub_col<P>(u % KG, l >> 4), col = c0 + 16 * cb + (l & 15);
+      Cf[idx] = (kc < rows[m] && col < t) ? (F)sm[offs[m] + kc + col * R] : (F)0;
+    }
+  }
+  __syncthreads();
+  const int kgr = (r + 31) / 32, kgl = (rl + 31) / 32, kgh = (rh + 31) / 32;
+  const double* Ub = d.U;
+  const double* Us = Ub + (int64_t)s * N * R;
+  const double* Ul = lo >= 0 ? Ub + (int64_t)lo * N * R : Ub;
+  const double* Uh = hi >= 0 ? Ub + (int64_t)hi * N * R : Ub;
+  S* K1 = (S*)d.K1 + (int64_t)s * N * d.T;
+  const int e = axis == 0 ? 1 : d.lnx;
+  const int na = axis == 0 ? d.lnx : d.lny;
+  const int nst = wdiv(N, 16);
+  const int stride = gridDim.x * WNW;
+  for (int st = blockIdx.x * WNW + wave; st < nst; st += stride) {
+    const int p = st * 16 + l16;
+    const bool rin = p < N;
+    const int pc = rin ? p : N - 1;
+    const int ia = axis == 0 ? pc % d.lnx : pc / d.lnx;
+    const int f = axis == 0 ? pc / d.lnx : pc % d.lnx;
+    const bool hm = rin && ia > 0, hp = rin && ia < na - 1;
+    const bool flo = rin && ia == 0, fhi = rin && ia == na - 1;
+    const int pm = hm ? pc - e : pc, pp = hp ? pc + e : pc;
+    Acc acc[NCB];
+    zero_prod<P>(acc, NCB);
+    for (int kg = 0; kg < kgr; ++kg) {
+      F u0[KG], um[KG], up[KG];
+#pragma unroll
+      for (int u = 0; u < KG; ++u) {
+        const int kc = 32 * kg + sub_col<P>(u, kq);
+        const bool kin = kc < r;
+        const int64_t col = (int64_t)(kin ? kc : 0) * N;
+        const double v0 = Us[col + pc], vm = Us[col + pm], vp = Us[col + pp];
+        u0[u] = (rin && kin) ? (F)v0 : (F)0;
+        um[u] = (hm && kin) ? (F)vm : (F)0;
+        up[u] = (hp && kin) ? (F)vp : (F)0;
+      }
+      prod_acc<P, NCB, KG>(acc, Cf + kg * gstride, u0);
+      prod_acc<P, NCB, KG>(acc, Cf + bstride + kg * gstride, um);
+      prod_acc<P, NCB, KG>(acc, Cf + 2 * bstride + kg * gstride, up);
+      // own face row: U[p] GLo at the low face, U[p] GHi at the high face
+      if (__any(flo || fhi)) {
+#pragma unroll
+        for (int u = 0; u < KG; ++u) {
+          um[u] = flo ? u0[u] : (F)0;
+          up[u] = fhi ? u0[u] : (F)0;
+        }
+        prod_acc<P, NCB, KG>(acc, Cf + 3 * bstride + kg * gstride, um);
+        prod_acc<P, NCB, KG>(acc, Cf + 4 * bstride + kg * gstride, up);
+      }
+    }
+    // the neighbours' face rows
+    if (__any(flo)) {
+      const int pn = face_cell(d, axis, true, f);
+      for (int kg = 0; kg < kgl; ++kg) {
+        F gn[KG];
+#pragma unroll
+        for (int u = 0; u < KG; ++u) {
+          const int kc = 32 * kg + sub_col<P>(u, kq);
+          const bool in = flo && lo >= 0 && kc < rl;
+          const double v = Ul[(int64_t)(in ? kc : 0) * N + pn];
+          gn[u] = in ? (F)v : (F)0;
+        }
+        prod_acc<P, NCB, KG>(acc, Cf + 5 * bstride + kg * gstride, gn);
+      }
+    }
+    if (__any(fhi)) {
+      const int pn = face_cell(d, axis, false, f);
+      for (int kg = 0; kg < kgh; ++kg) {
+        F gn[KG];
+#pragma unroll
+        for (int u = 0; u < KG; ++u) {
+          const int kc = 32 * kg + sub_col<P>(u, kq);
+          const bool in = fhi && hi >= 0 && kc < rh;
+          const double v = Uh[(int64_t)(in ? kc : 0) * N + pn];
+          gn[u] = in ? (F)v : (F)0;
+        }
+        prod_acc<P, NCB, KG>(acc, Cf + 6 * bstride + kg * gstride, gn);
+      }
+    }
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int j = c0 + out_col<P>(cb, v, kq);
+        if (rin && j < t) K1[(int64_t)j * N + p] = (S)acc[cb][v];
+      }
+  }
+}
+
+// L-step of an advection stage (eq. advx_evolL), weighted by sqrt(w), for
+// output columns [c0, c0 + 32):
+//   AL[q,:] = Qh[q,:] P0 + Omega_q^+ Qh[q,:] Pm + Omega_q^- Qh[q,:] Pp,
+// with one accumulator set per coefficient matrix and the per-direction
+// factors applied to the accumulators (each lane's accumulators belong to
+// its own direction).
+template <class S, int P>
+__global__ __launch_bounds__(WTHR) void kw_lstep(Dev d, int axis, int sd0) {
+  using F = typename Prec<P>::F;
+  using Acc = typename Prec<P>::Acc;
+  constexpr int NCB = 2, NG = WCAP_T / 64;
+  constexpr int gstride = 16 * NCB * 64;         // one group of one matrix
+  const int s = sd0 + blockIdx.y;
+  const int t = d.tdim[s];
+  const int c0 = blockIdx.z * 16 * NCB;
+  if (c0 >= t) return;
+  const int M = d.M, T = d.T;
+  const int ng = wdiv(t, 64);
+  const double* om = axis == 0 ? d.omx : d.omy;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l16 = lane & 15, kq = lane >> 4;
+  extern __shared__ double lds[];
+  F* Pf = reinterpret_cast<F*>(lds);  // [m][g] groups
+  {
+    const double* sm = small_of(d, s);
+    const int offs[3] = {d.oP0, d.oPm, d.oPp};
+    const int total = 3 * NG * gstride;
+    for (int idx = threadIdx.x; idx < total; idx += WTHR) {
+      const int l = idx & 63, f = idx >> 6, cb = f % NCB, u = (f / NCB) % 16, g = (f / (16 * NCB)) % NG,
+                m = f / (16 * NCB * NG);
+      const int kc = 64 * g + sub_col<P>(u, l >> 4), col = c0 + 16 * cb + (l & 15);
+      Pf[idx] = (kc < t && col < t) ? (F)sm[offs[m] + kc + col * T] : (F)0;
+    }
+  }
+  __syncthreads();
+  const S* Qsd = (const S*)d.Qh + (int64_t)s * M * T;
+  S* ALs = (S*)d.AL + (int64_t)s * M * T;
+  const int nst = wdiv(M, 16);
+  const int stride = gridDim.x * WNW;
+  F xv[16], xn[16];
+  auto load = [&](int st_, int g_) {
+    const int q_ = st_ * 16 + l16;
+    const int qc = q_ < M ? q_ : M - 1;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int kc = 64 * g_ + sub_col<P>(u, kq);
+      const bool in = q_ < M && kc < t;
+      const S v = Qsd[(int64_t)(in ? kc : 0) * M + qc];
+      xn[u] = in ? (F)v : (F)0;
+    }
+  };
+  int st = blockIdx.x * WNW + wave, g = 0;
+  if (st < nst) load(st, 0);
+  Acc a0[NCB], am[NCB], ap[NCB];
+  zero_prod<P>(a0, NCB);
+  zero_prod<P>(am, NCB);
+  zero_prod<P>(ap, NCB);
+  while (st < nst) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) xv[u] = xn[u];
+    int st2 = st, g2 = g + 1;
+    if (g2 >= ng) {
+      g2 = 0;
+      st2 = st + stride;
+    }
+    if (st2 < nst) load(st2, g2);
+    prod_acc<P, NCB, 16>(a0, Pf + (0 * NG + g) * gstride, xv);
+    prod_acc<P, NCB, 16>(am, Pf + (1 * NG + g) * gstride, xv);
+    prod_acc<P, NCB, 16>(ap, Pf + (2 * NG + g) * gstride, xv);
+    if (g == ng - 1) {
+      const int q = st * 16 + l16;
+      const bool rin = q < M;
+      const double o = rin ? om[q] : 0.0;
+      const double op = o >= 0.0 ? o : 0.0, on = o < 0.0 ? o : 0.0;
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int j = c0 + out_col<P>(cb, v, kq);
+          const double val = (double)a0[cb][v] + op * (double)am[cb][v] + on * (double)ap[cb][v];
+          if (rin && j < t) ALs[(int64_t)j * M + q] = (S)val;
+        }
+      zero_prod<P>(a0, NCB);
+      zero_prod<P>(am, NCB);
+      zero_prod<P>(ap, NCB);
+    }
+    st = st2;
+    g = g2;
+  }
+}
+
+// Collision K-step (eq. coll_evolK) for output columns [c0, c0 + 32), with
+// K = U S and m = V^T w:
+//   K1[p] = (1 - dt c_t[p]) K[p] + dt (c_s[p] / W (K[p].m) + Q[p]) m;
+// K[p].m = U[p] (S m) is an extra product block.
+template <class S, int P>
+__global__ __launch_bounds__(WTHR) void kw_coll_kstep(Dev d, int sd0) {
+  using F = typename Prec<P>::F;
+  using Acc = typename Prec<P>::Acc;
+  constexpr int NCB = 2, KSP = 16;
+  const int s = sd0 + blockIdx.y;
+  const int r = d.rank[s];
+  const int c0 = blockIdx.z * 16 * NCB;
+  if (c0 >= r) return;
+  const int N = d.N, R = d.R;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l16 = lane & 15, kq = lane >> 4;
+  __shared__ double mv[WCAP_R], smv[WCAP_R];
+  __shared__ F Bf[KSP * NCB * 64];
+  __shared__ F Be[KSP * 64];
+  const double* sm = small_of(d, s);
+  const double* Sg = d.S + (int64_t)s * R * R;
+  for (int a = threadIdx.x; a < WCAP_R; a += WTHR) mv[a] = a < r ? sm[d.oMv + a] : 0.0;
+  __syncthreads();
+  for (int a = threadIdx.x; a < WCAP_R; a += WTHR) {
+    double acc = 0.0;
+    for (int b = 0; b < r; ++b) acc = fma(Sg[a + b * R], mv[b], acc);
+    smv[a] = a < r ? acc : 0.0;
+  }
+  for (int idx = threadIdx.x; idx < KSP * NCB * 64; idx += WTHR) {
+    const int l = idx & 63, f = idx >> 6, cb = f % NCB, u = f / NCB;
+    const int kc = sub_col<P>(u, l >> 4), col = c0 + 16 * cb + (l & 15);
+    Bf[idx] = (kc < r && col < r) ? (F)Sg[kc + col * R] : (F)0;
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < KSP * 64; idx += WTHR) {
+    const int l = idx & 63, u = idx >> 6;
+    const int kc = sub_col<P>(u, l >> 4), col = l & 15;
+    Be[idx] = (kc < r && col == 0) ? (F)smv[kc] : (F)0;
+  }
+  __syncthreads();
+  const double* Us = d.U + (int64_t)s * N * R;
+  const double* cs = d.cs + (int64_t)s * N;
+  const double* ct = d.ct + (int64_t)s * N;
+  const double* Qs = d.Qsrc + (int64_t)s * N;
+  S* K1 = (S*)d.K1 + (int64_t)s * N * d.T;
+  const double dt = d.dt, iW = 1.0 / d.W;
+  const int nst = wdiv(N, 16);
+  const int stride = gridDim.x * WNW;
+  F xn[KSP];
+  auto load = [&](int st_) {
+    const int p_ = st_ * 16 + l16;
+    const int pc = p_ < N ? p_ : N - 1;
+#pragma unroll
+    for (int u = 0; u < KSP; ++u) {
+      const int kc = sub_col<P>(u, kq);
+      const bool in = p_ < N && kc < r;
+      const double v = Us[(int64_t)(in ? kc : 0) * N + pc];
+      xn[u] = in ? (F)v : (F)0;
+    }
+  };
+  int st = blockIdx.x * WNW + wave;
+  if (st < nst) load(st);
+  for (; st < nst; st += stride) {
+    F xv[KSP];
+#pragma unroll
+    for (int u = 0; u < KSP; ++u) xv[u] = xn[u];
+    if (st + stride < nst) load(st + stride);
+    const int p = st * 16 + l16;
+    const bool rin = p < N;
+    const int pc = rin ? p : N - 1;
+    Acc acc[NCB], ae[1];
+    zero_prod<P>(acc, NCB);
+    zero_prod<P>(ae, 1);
+    prod_acc<P, NCB, KSP>(acc, Bf, xv);
+    prod_acc<P, 1, KSP>(ae, Be, xv);
+    // column 0 of the extra block sits in component 0 of lanes 0..15
+    const double km = __shfl((double)ae[0][0], l16, 64);
+    const double a0 = rin ? 1.0 - dt * ct[pc] : 0.0;
+    const double a1 = rin ? dt * (cs[pc] * iW * km + Qs[pc]) : 0.0;
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int j = c0 + out_col<P>(cb, v, kq);
+        if (rin && j < r) K1[(int64_t)j * N + p] = (S)fma(a0, (double)acc[cb][v], a1 * mv[j]);
+      }
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Reductions over rows: for each job and each 64 x 64 block (a, b),
+//   out[64 a + i, 64 b + j] = scale sum_rows w(row) X[row, 64 a + i] Y'[row, 64 b + j]
+// where Y' is Y, or Y[p + e] - Y[p] (zero beyond the high face) for the
+// spatial Galerkin matrix.  blockIdx.z enumerates (job, block); each
+// workgroup writes its block of its own partial.  Symmetric jobs form the
+// blocks with a <= b and store each entry and its mirror (a diagonal block
+// only from i <= j), so the sum comes out exactly symmetric.
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ int src_subdomain(const Dev& d, int s, int axis, int side) {
+  return side == 0 ? s : neighbour(d, s, axis, side);
+}
+
+__device__ __forceinline__ int src_cols(const Dev& d, int s, int axis, const XSrc& x) {
+  if (x.vec) return 1;
+  const int sd = src_subdomain(d, s, axis, x.side);
+  if (sd < 0) return 0;
+  return x.side == 0 ? dim_of(d, s, axis, x.dim) : d.rank[sd];
+}
+
+// cell / direction index of row `row` of a source (rows are face entries for
+// face sources; the neighbour's face is the one touching this subdomain)
+__device__ __forceinline__ int src_row(const Dev& d, int axis, const XSrc& x, int row) {
+  if (x.face == 0) return row;
+  return face_cell(d, axis, x.face == 2, row);
+}
+
+template <class W>
+__device__ __forceinline__ double src_load(const Dev& d, int s, int axis, const XSrc& x, int row, int col) {
+  const int sd = src_subdomain(d, s, axis, x.side);
+  const int64_t base = (int64_t)(sd < 0 ? 0 : sd) * x.sd;
+  const int pr = src_row(d, axis, x, row);
+  double v;
+  if (x.vec) v = ((const double*)x.p)[base + pr];
+  else if (x.is64) v = ((const double*)x.p)[base + (int64_t)col * x.ld + pr];
+  else v = (double)((const W*)x.p)[base + (int64_t)col * x.ld + pr];
+  if (x.rowscale) v *= d.sw[pr];
+  return v;
+}
+
+template <class W>
+__global__ __launch_bounds__(XTHR) void kw_xgram(Dev d, int axis, int sd0, XJobs jobs) {
+  const int s = sd0 + blockIdx.y;
+  int jb = 0;
+#pragma unroll
+  for (int q = 1; q < XJOBS_MAX; ++q)
+    if (q < jobs.n && (int)blockIdx.z >= jobs.j[q].zbase) jb = q;
+  // a runtime index into the job array would place it in scratch memory:
+  // copy the selected job out with static indices
+  XJob J = jobs.j[0];
+#pragma unroll
+  for (int q = 1; q < XJOBS_MAX; ++q)
+    if (q == jb) J = jobs.j[q];
+  int pz = blockIdx.z - J.zbase, a, b;
+  if (J.sym) {
+    b = 0;
+    while (pz > b) {
+      pz -= b + 1;
+      ++b;
+    }
+    a = pz;
+  } else {
+    a = pz % J.pa;
+    b = pz / J.pa;
+  }
+  const int nx = src_cols(d, s, axis, J.x), ny = src_cols(d, s, axis, J.y);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l16 = lane & 15, kq = lane >> 4;
+  __shared__ double red[16 * 256];
+  const bool live = 64 * a < nx && 64 * b < ny;
+  const int rows = J.rows_cells ? (J.x.face ? face_len(d, axis) : d.N) : d.M;
+  const double* om = axis == 0 ? d.omx : d.omy;
+  const double* wcell = J.wmode == 4 ? d.cs + (int64_t)s * d.N : d.ct + (int64_t)s * d.N;
+  const int e = axis == 0 ? 1 : d.lnx;
+  const int na = axis == 0 ? d.lnx : d.lny;
+  dbl4 acc[16];
+  zero_acc<16>(acc);
+  if (live) {
+    const int nst = wdiv(rows, 16);
+    for (int st = blockIdx.x * 4 + wave; st < nst; st += gridDim.x * 4) {
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const int row = st * 16 + 4 * kk + kq;
+        const bool rin = row < rows;
+        const int rc = rin ? row : 0;
+        double wt = rin ? 1.0 : 0.0;
+        if (J.wmode == 1) wt *= om[rc];
+        else if (J.wmode == 2) wt *= om[rc] >= 0.0 ? 1.0 : 0.0;
+        else if (J.wmode == 3) wt *= om[rc] < 0.0 ? 1.0 : 0.0;
+        else if (J.wmode >= 4) wt *= wcell[rc];
+        bool hs = false;
+        if (J.shift) {
+          const int ia = axis == 0 ? rc % d.lnx : rc / d.lnx;
+          hs = ia < na - 1;
+        }
+        double xa[4], yb[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int ci = 64 * a + 16 * c + l16, cj = 64 * b + 16 * c + l16;
+          const bool xin = ci < nx, yin = cj < ny;
+          const double xv = src_load<W>(d, s, axis, J.x, rc, xin ? ci : 0);
+          double yv = src_load<W>(d, s, axis, J.y, rc, yin ? cj : 0);
+          if (J.shift) {
+            const double y1 = src_load<W>(d, s, axis, J.y, hs ? rc + e : rc, yin ? cj : 0);
+            yv = (hs ? y1 : 0.0) - yv;
+          }
+          xa[c] = xin ? xv * wt : 0.0;
+          yb[c] = (yin && rin) ? yv : 0.0;
+        }
+#pragma unroll
+        for (int ci = 0; ci < 4; ++ci)
+#pragma unroll
+          for (int cj = 0; cj < 4; ++cj) acc[ci * 4 + cj] = mfma64(xa[ci], yb[cj], acc[ci * 4 + cj]);
+      }
+    }
+  }
+  wg_reduce_acc<16>(acc, red);
+  if (wave != 0 || !live) return;
+  double* out = gpart_of(d, s) + (int64_t)blockIdx.x * d.gpTile + J.out_off;
+  const int ld = J.out_ld > 0 ? J.out_ld : nx;
+#pragma unroll
+  for (int ci = 0; ci < 4; ++ci)
+#pragma unroll
+    for (int cj = 0; cj < 4; ++cj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 64 * a + 16 * ci + 4 * v + kq, j = 64 * b + 16 * cj + l16;
+        if (i >= nx || j >= ny) continue;
+        const double val = J.scale * acc[ci * 4 + cj][v];
+        if (J.sym) {
+          if (a == b && i > j) continue;
+          out[i + (int64_t)j * ld] = val;
+          out[j + (int64_t)i * ld] = val;
+        } else {
+          out[i + (int64_t)j * ld] = val;
+        }
+      }
+}
+
+// ============================================================================
+// small kernels: building blocks for 1024-thread workgroups
+// ============================================================================
+
+// sum over the workgroup in a fixed order (red: SNW doubles of LDS)
+__device__ __forceinline__ double s_sum(double v, double* red) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double r = 0.0;
+  for (int w = 0; w < SNW; ++w) r += red[w];
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ double s_max(double v, double* red) {
+  v = wave_max(v);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double r = red[0];
+  for (int w = 1; w < SNW; ++w) r = fmax(r, red[w]);
+  __syncthreads();
+  return r;
+}
+
+// dst (rows x cols, ldd) = scale * sum over ngp partials of the block at off
+// (leading dimension ldp), partials added in a fixed order
+__device__ void s_sum_partials(const Dev& d, int s, int ngp, int off, int ldp, int rows, int cols, double* dst,
+                               int ldd, double scale) {
+  const double* gp = gpart_of(d, s);
+  const int total = rows * cols;
+  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+    const int i = idx % rows, j = idx / rows;
+    const int64_t src = off + i + (int64_t)j * ldp;
+    double acc = 0.0;
+    int w = 0;
+    for (; w + 4 <= ngp; w += 4) {
+      const double v0 = gp[(int64_t)w * d.gpTile + src], v1 = gp[(int64_t)(w + 1) * d.gpTile + src];
+      const double v2 = gp[(int64_t)(w + 2) * d.gpTile + src], v3 = gp[(int64_t)(w + 3) * d.gpTile + src];
+      acc += v0;
+      acc += v1;
+      acc += v2;
+      acc += v3;
+    }
+    for (; w < ngp; ++w) acc += gp[(int64_t)w * d.gpTile + src];
+    dst[i + (int64_t)j * ldd] = scale * acc;
+  }
+}
+
+// C (m x n, ldc) = alpha op(A) op(B) + beta D on the FP64 matrix cores, any
+// pointers (LDS or global), C aliasing neither A nor B; the 16 x 16 output
+// tiles are dealt to the wavefronts, k walked in steps of 64 with all operand
+// loads of a step issued first.  Ends with a barrier.
+__device__ void gmm(double* C, int ldc, const double* A, int lda, bool ta, const double* B, int ldb, bool tb, int m,
+                    int n, int k, double alpha, double beta, const double* D, int ldd) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+  const int l16 = lane & 15, kq = lane >> 4;
+  const int tm = wdiv(m, 16), tn = wdiv(n, 16);
+  for (int tile = wave; tile < tm * tn; tile += nw) {
+    const int ti = tile % tm, tj = tile / tm;
+    const int i0 = 16 * ti, j0 = 16 * tj;
+    const int i = i0 + l16, j = j0 + l16;
+    const int ic = i < m ? i : 0, jc = j < n ? j : 0;
+    dbl4 e = zero4(), o = zero4();
+    for (int k0 = 0; k0 < k; k0 += 64) {
+      double av[16], bv[16];
+#pragma unroll
+      for (int s4 = 0; s4 < 16; ++s4) {
+        const int l = k0 + 4 * s4 + kq;
+        const int lc = l < k ? l : 0;
+        const double a_ = ta ? A[lc + (int64_t)ic * lda] : A[ic + (int64_t)lc * lda];
+        const double b_ = tb ? B[jc + (int64_t)lc * ldb] : B[lc + (int64_t)jc * ldb];
+        av[s4] = (i < m && l < k) ? a_ : 0.0;
+        bv[s4] = (j < n && l < k) ? b_ : 0.0;
+      }
+#pragma unroll
+      for (int s4 = 0; s4 < 16; s4 += 2) {
+        e = mfma64(av[s4], bv[s4], e);
+        o = mfma64(av[s4 + 1], bv[s4 + 1], o);
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int ci = i0 + 4 * v + kq, cj = j0 + l16;
+      if (ci < m && cj < n) {
+        const double acc = e[v] + o[v];
+        C[ci + (int64_t)cj * ldc] = beta == 0.0 ? alpha * acc : fma(alpha, acc, beta * D[ci + (int64_t)cj * ldd]);
+      }
+    }
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ void gmm(double* C, int ldc, const double* A, int lda, bool ta, const double* B, int ldb,
+                                    bool tb, int m, int n, int k, double alpha, double beta) {
+  gmm(C, ldc, A, lda, ta, B, ldb, tb, m, n, k, alpha, beta, C, ldc);
+}
+
+// Right-looking Cholesky G = L L^T of the n x n matrix in LDS (lower
+// triangle, ld WLD; n <= 128) in place.  dep[k] = 1 marks a pivot at most
+// 1e-20 of its initial diagonal d0[k] (or not finite): its column is set to
+// the unit vector, so the factorisation goes on.  Returns the smallest ratio
+// pivot / d0 met (for the unshifted first try).  The strict upper triangle
+// is zeroed on exit.
+__device__ double lds_chol(const Dev& d, double* L, int n, const double* d0, int* dep, double* red) {
+  double& minratio = red[SNW];
+  if (threadIdx.x == 0) minratio = 1e300;
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    const double pv = L[k + k * WLD];
+    const bool isdep = !isfinite(pv) || !(pv > 1e-20 * d0[k]);
+    const double lkk = isdep ? 1.0 : sqrt(pv);
+    const double il = 1.0 / lkk;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      dep[k] = isdep ? 1 : 0;
+      minratio = fmin(minratio, isdep ? 0.0 : pv / d0[k]);
+      L[k + k * WLD] = lkk;
+      if (!isfinite(pv)) atomicOr(d.flags, FLAG_NONFINITE);
+    }
+    for (int i = k + 1 + (int)threadIdx.x; i < n; i += blockDim.x)
+      L[i + k * WLD] = isdep ? 0.0 : L[i + k * WLD] * il;
+    __syncthreads();
+    const int m = n - k - 1;
+    for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
+      const int i = k + 1 + idx % m, j = k + 1 + idx / m;
+      if (i >= j) L[i + j * WLD] = fma(-L[i + k * WLD], L[j + k * WLD], L[i + j * WLD]);
+    }
+    __syncthreads();
+  }
+  for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+    const int i = idx % n, j = idx / n;
+    if (i < j) L[i + j * WLD] = 0.0;
+  }
+  __syncthreads();
+  const double mr = minratio;
+  __syncthreads();
+  return mr;
+}
+
+// In-place inverse of the lower triangular L (n x n, LDS, ld WLD, unit
+// vectors in dependent columns keep it regular), column by column from the
+// last: X[j][j] = 1/L[j][j], X[i][j] = -X[j][j] sum_{j<l<=i} X[i][l] L[l][j].
+// Each row's sum is split over 8 lanes and added with DPP.
+__device__ void lds_tri_inv(double* L, int n, double* colj) {
+  for (int j = n - 1; j >= 0; --j) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) colj[i] = L[i + j * WLD];
+    __syncthreads();
+    const double xjj = 1.0 / colj[j];
+    const int grp = threadIdx.x >> 3, sub = threadIdx.x & 7;
+    double val = 0.0;
+    const int i = j + 1 + grp;
+    if (i < n) {
+      for (int l = j + 1 + sub; l <= i; l += 8) val = fma(L[i + l * WLD], colj[l], val);
+    }
+    val = group_sum_dpp<8>(val);
+    __syncthreads();
+    if (i < n && sub == 0) L[i + j * WLD] = -xjj * val;
+    if (threadIdx.x == 0) L[j + j * WLD] = xjj;
+    __syncthreads();
+  }
+}
+
+// ----------------------------------------------------------------------------
+// One-sided Jacobi with the columns in registers.  Pair slots: processor p
+// (0 <= p < P = n2/2) is slot k = p % PPW of wavefront p / PPW; it holds
+// columns top and bot (rows = lane + 64 i, i < RPL) and, with ACC, the
+// matching columns of the accumulated rotation J (n rows, JRPL per lane).
+// After each round the columns move by the caterpillar rule
+//   top'[0] = top[0], top'[1] = bot[0], top'[p] = top[p-1] (p >= 2),
+//   bot'[p] = bot[p+1] (p <= P-2), bot'[P-1] = top[P-1],
+// which meets every pair once in n2 - 1 rounds.  Moves inside a wavefront
+// are register copies; the two columns that cross to a neighbouring
+// wavefront go through a double-buffered LDS area (one barrier per round).
+// ----------------------------------------------------------------------------
+template <int PPW, int RPL, bool ACC, int JRPL>
+struct RingCols {
+  double tp[PPW][RPL], bt[PPW][RPL];
+  double jt[PPW][ACC ? JRPL : 1], jb[PPW][ACC ? JRPL : 1];
+};
+
+// LDS doubles needed by ring_jacobi
+template <int RPL, int JRPL, bool ACC>
+constexpr int ring_lds_doubles() { return 2 * 2 * SNW * 64 * (RPL + (ACC ? JRPL : 0)); }
+
+// Returns the sweeps done (negative if not converged within max_sweeps).
+template <int PPW, int RPL, bool ACC, int JRPL>
+__device__ int ring_jacobi(const Dev& d, RingCols<PPW, RPL, ACC, JRPL>& c, int rows, int n, double tol,
+                           double floor_rel, int max_sweeps, double* xbuf, double* red, int* rotflag) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int n2 = n + (n & 1);
+  const int P = n2 / 2;
+  const int p0 = wave * PPW;
+  // squared Frobenius norm for the noise floor
+  double part = 0.0;
+#pragma unroll
+  for (int k = 0; k < PPW; ++k)
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) part = fma(c.tp[k][i], c.tp[k][i], fma(c.bt[k][i], c.bt[k][i], part));
+  const double floor2 = floor_rel * floor_rel * s_sum(part, red);
+  const double tol2 = tol * tol;
+  if (n2 <= 1) return 0;
+  constexpr int CW = RPL + (ACC ? JRPL : 0);  // doubles per lane of one moving column
+  bool converged = false;
+  int sweeps = 0;
+  int buf = 0;
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    sweeps = sweep + 1;
+    bool rot = false;
+    for (int round = 0; round < n2 - 1; ++round) {
+      // inner products and rotations of this wavefront's pairs
+#pragma unroll
+      for (int k = 0; k < PPW; ++k) {
+        double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+          al = fma(c.tp[k][i], c.tp[k][i], al);
+          be = fma(c.bt[k][i], c.bt[k][i], be);
+          ga = fma(c.tp[k][i], c.bt[k][i], ga);
+        }
+        al = wave_sum(al);
+        be = wave_sum(be);
+        ga = wave_sum(ga);
+        const bool live = p0 + k < P;
+        if (live && ga != 0.0 && al > floor2 && be > floor2 && ga * ga > tol2 * al * be) {
+          double cs, sn;
+          jacobi_rotation(al, be, ga, cs, sn);
+#pragma unroll
+          for (int i = 0; i < RPL; ++i) {
+            const double x = c.tp[k][i], y = c.bt[k][i];
+            c.tp[k][i] = cs * x - sn * y;
+            c.bt[k][i] = fma(sn, x, cs * y);
+          }
+          if (ACC) {
+#pragma unroll
+            for (int i = 0; i < JRPL; ++i) {
+              const double x = c.jt[k][i], y = c.jb[k][i];
+              c.jt[k][i] = cs * x - sn * y;
+              c.jb[k][i] = fma(sn, x, cs * y);
+            }
+          }
+          rot = true;
+        }
+      }
+      if (P == 1) continue;  // a single pair: nothing moves
+      // columns leaving the wavefront: top of the last slot (to the next
+      // wavefront), bottom of the first slot (to the previous one)
+      double* ob = xbuf + buf * (2 * SNW * 64 * CW);
+      double* outT = ob + (0 * SNW + wave) * 64 * CW;
+      double* outB = ob + (1 * SNW + wave) * 64 * CW;
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+        outT[i * 64 + lane] = c.tp[PPW - 1][i];
+        outB[i * 64 + lane] = c.bt[0][i];
+      }
+      if (ACC) {
+#pragma unroll
+        for (int i = 0; i < JRPL; ++i) {
+          outT[(RPL + i) * 64 + lane] = c.jt[PPW - 1][i];
+          outB[(RPL + i) * 64 + lane] = c.jb[0][i];
+        }
+      }
+      __syncthreads();
+      // moves: bottoms shift down (towards smaller p), tops shift up
+      const double* inT = ob + (0 * SNW + (wave > 0 ? wave - 1 : 0)) * 64 * CW;   // previous wave's last top
+      const double* inB = ob + (1 * SNW + (wave < SNW - 1 ? wave + 1 : wave)) * 64 * CW;  // next wave's first bottom
+      double ntp[PPW][RPL], nbt[PPW][RPL];
+      double njt[PPW][ACC ? JRPL : 1], njb[PPW][ACC ? JRPL : 1];
+#pragma unroll
+      for (int k = 0; k < PPW; ++k) {
+        const int p = p0 + k;
+        // new top
+        if (k == 0) {
+          if (p == 0) {
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) ntp[k][i] = c.tp[0][i];
+            if (ACC)
+#pragma unroll
+              for (int i = 0; i < JRPL; ++i) njt[k][i] = c.jt[0][i];
+          } else {
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) ntp[k][i] = inT[i * 64 + lane];
+            if (ACC)
+#pragma unroll
+              for (int i = 0; i < JRPL; ++i) njt[k][i] = inT[(RPL + i) * 64 + lane];
+          }
+        } else if (p == 1) {
+#pragma unroll
+          for (int i = 0; i < RPL; ++i) ntp[k][i] = c.bt[0][i];
+          if (ACC)
+#pragma unroll
+            for (int i = 0; i < JRPL; ++i) njt[k][i] = c.jb[0][i];
+        } else {
+#pragma unroll
+          for (int i = 0; i < RPL; ++i) ntp[k][i] = c.tp[k - 1][i];
+          if (ACC)
+#pragma unroll
+            for (int i = 0; i < JRPL; ++i) njt[k][i] = c.jt[k - 1][i];
+        }
+        // new bottom
+        if (p == P - 1) {
+#pragma unroll
+          for (int i = 0; i < RPL; ++i) nbt[k][i] = c.tp[k][i];
+          if (ACC)
+#pragma unroll
+            for (int i = 0; i < JRPL; ++i) njb[k][i] = c.jt[k][i];
+        } else if (k == PPW - 1) {
+#pragma unroll
+          for (int i = 0; i < RPL; ++i) nbt[k][i] = inB[i * 64 + lane];
+          if (ACC)
+#pragma unroll
+            for (int i = 0; i < JRPL; ++i) njb[k][i] = inB[(RPL + i) * 64 + lane];
+        } else {
+#pragma unroll
+          for (int i = 0; i < RPL; ++i) nbt[k][i] = c.bt[k + 1][i];
+          if (ACC)
+#pragma unroll
+            for (int i = 0; i < JRPL; ++i) njb[k][i] = c.jb[k + 1][i];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < PPW; ++k) {
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+          c.tp[k][i] = ntp[k][i];
+          c.bt[k][i] = nbt[k][i];
+        }
+        if (ACC)
+#pragma unroll
+          for (int i = 0; i < JRPL; ++i) {
+            c.jt[k][i] = njt[k][i];
+            c.jb[k][i] = njb[k][i];
+          }
+      }
+      buf ^= 1;
+    }
+    // after n2 - 1 rounds every column is back in its starting slot
+    __syncthreads();
+    if (lane == 0) rotflag[wave] = rot ? 1 : 0;
+    __syncthreads();
+    int any = 0;
+    for (int w = 0; w < SNW; ++w) any |= rotflag[w];
+    __syncthreads();
+    if (!any) {
+      converged = true;
+      break;
+    }
+  }
+  if (!converged && threadIdx.x == 0) atomicOr(d.flags, FLAG_JACOBI_NOCONV);
+  return converged ? sweeps : -sweeps;
+}
+
+// column c of the ring layout: processor c / 2, top if c is even
+__device__ __forceinline__ void ring_slot(int c, int ppw, int& wave, int& k, bool& top) {
+  const int p = c >> 1;
+  wave = p / ppw;
+  k = p % ppw;
+  top = (c & 1) == 0;
+}
+
+// rank of the value of column c among n values (descending, ties by index)
+__device__ __forceinline__ int desc_rank(const double* v, int n, int c) {
+  const double x = v[c];
+  int r = 0;
+  for (int k = 0; k < n; ++k) r += (v[k] > x || (v[k] == x && k < c)) ? 1 : 0;
+  return r;
+}
+
+// ============================================================================
+// small kernels
+// ============================================================================
+
+// LDS scratch of a wide small kernel, declared once per kernel (arrays
+// declared inside the templated bodies would be allocated once per
+// instantiation).
+struct SmallScratch {
+  double red[SNW + 2];
+  int rotflag[SNW];
+  double v0[WCAP_A], v1[WCAP_A], v2[WCAP_A], v3[WCAP_A], v4[WCAP_A];
+  int i0[WCAP_A], i1[WCAP_A];
+  int ival[4];
+};
+
+// One pass of (shifted) Cholesky QR for the wide plan, n <= 128: sum of the
+// partial Grams, the factor G = R^T R (tried unshifted first; when a pivot
+// keeps less than 1e-12 of its diagonal the Gram is summed again with the
+// shift 11 (rows n + n (n+1)) u tr(G) of Fukaya et al. and factored again),
+//   Rinv slot: bscale R^{-1},  fill slot: dependent columns,
+//   Racc slot: R (acc_mode 1) or R Racc (acc_mode 2), rows of dependent
+//              columns zeroed.
+__global__ __launch_bounds__(STHR) void sw_chol(Dev d, int axis, int sd0, int ndim, int rows, int ngp, int acc_mode,
+                                               double bscale, int oRinv, int oRacc, int ld) {
+  const int s = sd0 + blockIdx.x;
+  const int n = dim_of(d, s, axis, ndim);
+  double* sm = small_of(d, s);
+  extern __shared__ double L[];  // n x n, ld WLD
+  __shared__ SmallScratch sc;
+  double* d0 = sc.v0;
+  int* dep = sc.i0;
+  if (n <= 0) return;
+  bool shifted = false;
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    s_sum_partials(d, s, ngp, 0, n, n, n, L, WLD, 1.0);
+    __syncthreads();
+    if (shifted) {
+      double part = 0.0;
+      for (int i = threadIdx.x; i < n; i += STHR) part += L[i * (WLD + 1)];
+      const double tr = s_sum(part, sc.red);
+      const double sh = 11.0 * ((double)rows * n + (double)n * (n + 1)) * U_ROUND * tr;
+      for (int i = threadIdx.x; i < n; i += STHR) L[i * (WLD + 1)] += sh;
+      __syncthreads();
+    }
+    for (int i = threadIdx.x; i < n; i += STHR) d0[i] = L[i * (WLD + 1)];
+    __syncthreads();
+    const double mr = lds_chol(d, L, n, d0, dep, sc.red);
+    if (shifted || mr >= 1e-12) break;
+    shifted = true;
+  }
+  // Racc update before L is inverted: R = L^T
+  double* Wt = sm + d.oW1;  // T x T scratch
+  if (acc_mode == 1) {
+    for (int idx = threadIdx.x; idx < n * n; idx += STHR) {
+      const int i = idx % n, j = idx / n;
+      sm[oRacc + i + j * ld] = (dep[i] || i > j) ? 0.0 : L[j + i * WLD];
+    }
+  } else if (acc_mode == 2) {
+    gmm(Wt, d.T, L, WLD, true, sm + oRacc, ld, false, n, n, n, 1.0, 0.0);
+    for (int idx = threadIdx.x; idx < n * n; idx += STHR) {
+      const int i = idx % n, j = idx / n;
+      sm[oRacc + i + j * ld] = dep[i] ? 0.0 : Wt[i + j * d.T];
+    }
+  }
+  __syncthreads();
+  lds_tri_inv(L, n, sc.v1);
+  // R^{-1} = (L^{-1})^T
+  for (int idx = threadIdx.x; idx < n * n; idx += STHR) {
+    const int i = idx % n, j = idx / n;
+    sm[oRinv + i + j * ld] = i <= j ? bscale * L[j + i * WLD] : 0.0;
+  }
+  for (int j = threadIdx.x; j < n; j += STHR) sm[d.oFill + j] = dep[j] ? 1.0 : 0.0;
+}
+
+// Augmentation SVD (Algorithm 4, steps 2-4) for widths m0 <= 192: the Gram
+// G = A^T A of A = sqrt(w) L0 is factored by a diagonally pivoted Cholesky
+// (packed lower triangle in LDS) that stops when the largest remaining pivot
+// is at most 1e-20 of the largest initial diagonal; the columns of the
+// factor L (G[perm, perm] = L L^T, rows in the original order) are then
+// orthogonalised by the ring Jacobi, L J = B, so that A B Sigma^-2 has
+// orthonormal columns: the left singular vectors of A, with sigma the
+// column norms of B.  Then the rank rule of step 3 and the coefficients of
+// sqrt(w) V-hat = A B[:, :t] Sigma^-2.  Singular values come from the Gram:
+// they are accurate to about u sigma_1^2 / sigma, which resolves the
+// absolute tolerances of the adaptive mode.
+template <int PPW, int RPL>
+__device__ void aug_svd_body(const Dev& d, int s, int axis, int m0, double* lds, SmallScratch& sc) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double* sm = small_of(d, s);
+  const int r = d.rank[s];
+  double* Gp = lds;            // packed lower triangle, m0 (m0 + 1) / 2
+  double* dg = sc.v0;          // current diagonal
+  double* d0s = sc.v1;
+  int* estep = sc.i0;          // elimination step of each column (NOT_ELIM: never)
+  double* lcol = sc.v2;
+  double* sigs = sc.v3;
+  double* sorted = sc.v4;
+  int* rk = sc.i1;
+  constexpr int NOT_ELIM = 1 << 20;
+  auto pk = [](int i, int j) { return i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i; };
+  // Gram from the partials (symmetric, ld m0), lower triangle packed
+  {
+    const double* gp = gpart_of(d, s);
+    const int ngp = d.nwgM;
+    for (int idx = threadIdx.x; idx < m0 * m0; idx += STHR) {
+      const int i = idx % m0, j = idx / m0;
+      if (i < j) continue;
+      const int64_t src = i + (int64_t)j * m0;
+      double acc = 0.0;
+      for (int w = 0; w < ngp; ++w) acc += gp[(int64_t)w * d.gpTile + src];
+      Gp[pk(i, j)] = acc;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < m0; i += STHR) {
+      dg[i] = Gp[pk(i, i)];
+      d0s[i] = dg[i];
+      estep[i] = NOT_ELIM;
+    }
+    __syncthreads();
+  }
+  double dmax = 0.0;
+  for (int i = threadIdx.x; i < m0; i += STHR) dmax = fmax(dmax, d0s[i]);
+  dmax = s_max(dmax, sc.red);
+  // pivoted right-looking Cholesky: pivot = the largest remaining diagonal,
+  // the smallest index among equal ones
+  for (int k = 0; k < m0; ++k) {
+    double key = 0.0;
+    for (int i = threadIdx.x; i < m0; i += STHR)
+      if (estep[i] > k) key = fmax(key, dg[i]);
+    const double best = s_max(key, sc.red);
+    if (threadIdx.x == 0) sc.ival[1] = m0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < m0; i += STHR)
+      if (estep[i] > k && dg[i] == best) atomicMin(&sc.ival[1], i);
+    __syncthreads();
+    const int p = sc.ival[1];
+    if (p >= m0 || !(best > 1e-20 * dmax) || !isfinite(best)) break;  // the rest is numerically dependent
+    const double lpp = sqrt(best), il = 1.0 / lpp;
+    for (int i = threadIdx.x; i < m0; i += STHR)
+      lcol[i] = (i == p) ? lpp : ((estep[i] > k) ? Gp[pk(i, p)] * il : 0.0);
+    __syncthreads();
+    if (threadIdx.x == 0) estep[p] = k;
+    for (int i = threadIdx.x; i < m0; i += STHR)
+      if (i != p && estep[i] > k) Gp[pk(i, p)] = lcol[i];
+    if (threadIdx.x == 0) Gp[pk(p, p)] = lpp;
+    // trailing update of the active block (p itself is no longer active)
+    for (int idx = threadIdx.x; idx < m0 * m0; idx += STHR) {
+      const int i = idx % m0, j = idx / m0;
+      if (i >= j && i != p && j != p && estep[i] > k && estep[j] > k)
+        Gp[pk(i, j)] = fma(-lcol[i], lcol[j], Gp[pk(i, j)]);
+    }
+    for (int i = threadIdx.x; i < m0; i += STHR)
+      if (i != p && estep[i] > k) dg[i] = fma(-lcol[i], lcol[i], dg[i]);
+    __syncthreads();
+  }
+  // columns of the factor into the ring registers: column c (original
+  // index) holds L(:, estep[c]), nonzero in rows eliminated at or after it
+  RingCols<PPW, RPL, false, 1> c;
+#pragma unroll
+  for (int k = 0; k < PPW; ++k)
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+      const int row = lane + 64 * i;
+      const int p = wave * PPW + k;
+      const int ct = 2 * p, cb = 2 * p + 1;
+      double vt = 0.0, vb = 0.0;
+      if (row < m0 && ct < m0 && estep[ct] < NOT_ELIM) {
+        if (row == ct) vt = Gp[pk(ct, ct)];
+        else if (estep[row] > estep[ct]) vt = Gp[pk(row, ct)];
+      }
+      if (row < m0 && cb < m0 && estep[cb] < NOT_ELIM) {
+        if (row == cb) vb = Gp[pk(cb, cb)];
+        else if (estep[row] > estep[cb]) vb = Gp[pk(row, cb)];
+      }
+      c.tp[k][i] = vt;
+      c.bt[k][i] = vb;
+    }
+  __syncthreads();  // LDS now free for the exchange buffers
+  ring_jacobi<PPW, RPL, false, 1>(d, c, m0, m0, 1e-14, 1e-15, 40, lds, sc.red, sc.rotflag);
+  // singular values: column norms
+#pragma unroll
+  for (int k = 0; k < PPW; ++k) {
+    double nt = 0.0, nb = 0.0;
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+      nt = fma(c.tp[k][i], c.tp[k][i], nt);
+      nb = fma(c.bt[k][i], c.bt[k][i], nb);
+    }
+    nt = wave_sum(nt);
+    nb = wave_sum(nb);
+    const int p = wave * PPW + k;
+    if (lane == 0) {
+      if (2 * p < m0) sigs[2 * p] = sqrt(nt);
+      if (2 * p + 1 < m0) sigs[2 * p + 1] = sqrt(nb);
+    }
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < m0; j += STHR) {
+    const int q = desc_rank(sigs, m0, j);
+    rk[j] = q;
+    sorted[q] = sigs[j];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t;
+    const int cap = min(min(m0, d.r_int_max), d.T);
+    if (d.forced && d.force[axis * d.nsub + s] > 0) {
+      t = min(d.force[axis * d.nsub + s], cap);
+    } else {
+      const double tol = (d.rank_mode == 0) ? d.tol_aug_rel * sorted[0] : d.tol;
+      t = max(r, tail_rank(sorted, m0, tol));
+      if (t > cap) {
+        t = cap;
+        atomicAdd(d.clamps, 1ull);
+        if (d.strict) atomicOr(d.flags, FLAG_RANK_CLAMP);
+      }
+    }
+    if (t < 1) t = 1;
+    sc.ival[0] = t;
+    d.tdim[s] = t;
+    if (t > d.tmax[s]) d.tmax[s] = t;
+  }
+  __syncthreads();
+  const int t = sc.ival[0];
+  const double s0 = sorted[0];
+  for (int j = threadIdx.x; j < m0; j += STHR) sm[d.oSig + j] = sorted[j];
+  for (int j = threadIdx.x; j < t; j += STHR)
+    sm[d.oFill + j] = (s0 > 0.0 && sorted[j] > 1e-13 * s0) ? 0.0 : 1.0;
+  // Coef[:, rank(c)] = b_c / sigma_c^2 for the kept columns
+#pragma unroll
+  for (int k = 0; k < PPW; ++k) {
+    const int p = wave * PPW + k;
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      const int col = 2 * p + half;
+      if (col >= m0) continue;
+      const int q = rk[col];
+      if (q >= t) continue;
+      const double sg = sigs[col];
+      const bool ok = s0 > 0.0 && sg > 1e-13 * s0;
+      const double isg2 = ok ? 1.0 / (sg * sg) : 0.0;
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+        const int row = lane + 64 * i;
+        if (row < m0) sm[d.oCoef + row + q * d.MA] = (half ? c.bt[k][i] : c.tp[k][i]) * isg2;
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(STHR) void sw_aug_svd(Dev d, int axis, int sd0) {
+  const int s = sd0 + blockIdx.x;
+  const int m0 = m0_of(d, s, axis);
+  extern __shared__ double lds[];
+  __shared__ SmallScratch sc;
+  if (m0 <= 64) aug_svd_body<2, 1>(d, s, axis, m0, lds, sc);
+  else if (m0 <= 128) aug_svd_body<4, 2>(d, s, axis, m0, lds, sc);
+  else aug_svd_body<6, 3>(d, s, axis, m0, lds, sc);
+}
+
+// Eigen-split of the angular Galerkin matrix C (Appendix A) for t <= 128 and
+// the K-step coefficient matrices.  C + sigma I with sigma = 1.5 |C|_F has
+// its spectrum in [0.5, 2.5] |C|_F: its Cholesky factor L is well
+// conditioned, and the ring Jacobi gives L J = B, whose columns are
+// eigenvectors of C scaled by sqrt(lambda + sigma).  Then C+ = P
+// diag(max(lambda, 0)) P^T and C- = P diag(min(lambda, 0)) P^T, and
+//   M0 = Am (I - nu C+ + nu C-), Mm = nu Am C+, Mp = -nu Am C-,
+//   GLo = nu Am En C+, GHi = -nu Am Ep C-,
+//   GLoN = nu S_lo Olo C+, GHiN = -nu S_hi Ohi C-,   Am = S Tm, nu = dt c / h.
+template <int PPW, int RPL>
+__device__ void adv_prep_body(const Dev& d, int s, int axis, int t, double* lds, SmallScratch& sc) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lo = neighbour(d, s, axis, -1), hi = neighbour(d, s, axis, +1);
+  const int r = d.rank[s], rl = lo >= 0 ? d.rank[lo] : 0, rh = hi >= 0 ? d.rank[hi] : 0;
+  const int R = d.R, T = d.T;
+  double* sm = small_of(d, s);
+  double* d0 = sc.v0;
+  int* dep = sc.i0;
+  double* lam = sc.v1;
+  double* isc = sc.v2;
+  double* Cl = lds;  // t x t, ld WLD
+  const int pT = 0, pC = R * T, pEp = pC + T * T, pEn = pEp + T * T, pOlo = pEn + T * T, pOhi = pOlo + R * T;
+  const int ngp = d.nwgM;
+  s_sum_partials(d, s, ngp, pT, R, r, t, sm + d.oTm, R, 1.0);
+  s_sum_partials(d, s, ngp, pEp, t, t, t, sm + d.oEp, T, 1.0);
+  s_sum_partials(d, s, ngp, pEn, t, t, t, sm + d.oEn, T, 1.0);
+  s_sum_partials(d, s, ngp, pOlo, R, rl, t, sm + d.oOlo, R, 1.0);
+  s_sum_partials(d, s, ngp, pOhi, R, rh, t, sm + d.oOhi, R, 1.0);
+  s_sum_partials(d, s, ngp, pC, t, t, t, Cl, WLD, 1.0);
+  __syncthreads();
+  double part = 0.0;
+  for (int idx = threadIdx.x; idx < t * t; idx += STHR) {
+    const int i = idx % t, j = idx / t;
+    part = fma(Cl[i + j * WLD], Cl[i + j * WLD], part);
+  }
+  const double fro = sqrt(s_sum(part, sc.red));
+  double* Cp = sm + d.oCp;
+  double* Cn = sm + d.oCn;
+  double* Bm = sm + d.oW4;  // eigen-columns B (t x t, ld T)
+  double* Bd = sm + d.oW5;
+  if (fro > 0.0) {
+    const double sig = 1.5 * fro;
+    for (int i = threadIdx.x; i < t; i += STHR) {
+      Cl[i * (WLD + 1)] += sig;
+      d0[i] = Cl[i * (WLD + 1)];
+    }
+    __syncthreads();
+    lds_chol(d, Cl, t, d0, dep, sc.red);
+    RingCols<PPW, RPL, false, 1> c;
+#pragma unroll
+    for (int k = 0; k < PPW; ++k)
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+        const int row = lane + 64 * i, p = wave * PPW + k;
+        const int ct = 2 * p, cb = 2 * p + 1;
+        c.tp[k][i] = (row < t && ct < t) ? Cl[row + ct * WLD] : 0.0;
+        c.bt[k][i] = (row < t && cb < t) ? Cl[row + cb * WLD] : 0.0;
+      }
+    __syncthreads();
+    ring_jacobi<PPW, RPL, false, 1>(d, c, t, t, 1e-14, 1e-15, 40, lds, sc.red, sc.rotflag);
+    // lambda = |b|^2 - sigma; B to the workspace
+#pragma unroll
+    for (int k = 0; k < PPW; ++k) {
+      const int p = wave * PPW + k;
+#pragma unroll
+      for (int half = 0; half < 2; ++half) {
+        const int col = 2 * p + half;
+        double nrm = 0.0;
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+          const double x = half ? c.bt[k][i] : c.tp[k][i];
+          nrm = fma(x, x, nrm);
+        }
+        nrm = wave_sum(nrm);
+        if (col < t) {
+#pragma unroll
+          for (int i = 0; i < RPL; ++i) {
+            const int row = lane + 64 * i;
+            if (row < t) Bm[row + col * T] = half ? c.bt[k][i] : c.tp[k][i];
+          }
+          if (lane == 0) {
+            lam[col] = nrm - sig;
+            isc[col] = nrm > 0.0 ? 1.0 / nrm : 0.0;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // C+ = B diag(max(lam,0) / |b|^2) B^T, C- likewise
+    for (int idx = threadIdx.x; idx < t * t; idx += STHR) {
+      const int i = idx % t, j = idx / t;
+      Bd[i + j * T] = Bm[i + j * T] * fmax(lam[j], 0.0) * isc[j];
+    }
+    __syncthreads();
+    gmm(Cp, T, Bd, T, false, Bm, T, true, t, t, t, 1.0, 0.0);
+    for (int idx = threadIdx.x; idx < t * t; idx += STHR) {
+      const int i = idx % t, j = idx / t;
+      Bd[i + j * T] = Bm[i + j * T] * fmin(lam[j], 0.0) * isc[j];
+    }
+    __syncthreads();
+    gmm(Cn, T, Bd, T, false, Bm, T, true, t, t, t, 1.0, 0.0);
+  } else {
+    for (int idx = threadIdx.x; idx < t * t; idx += STHR) {
+      const int i = idx % t, j = idx / t;
+      Cp[i + j * T] = 0.0;
+      Cn[i + j * T] = 0.0;
+    }
+    __syncthreads();
+  }
+  const double nu = d.dt * d.c / d.h;
+  const double* Sg = d.S + (int64_t)s * R * R;
+  double* Am = sm + d.oAm;
+  double* W1 = sm + d.oW1;
+  double* W2 = sm + d.oW2;
+  double* W3 = sm + d.oW3;
+  gmm(Am, R, Sg, R, false, sm + d.oTm, R, false, r, t, r, 1.0, 0.0);
+  gmm(W1, R, Am, R, false, Cp, T, false, r, t, t, 1.0, 0.0);
+  gmm(W2, R, Am, R, false, Cn, T, false, r, t, t, 1.0, 0.0);
+  for (int idx = threadIdx.x; idx < r * t; idx += STHR) {
+    const int i = idx % r, j = idx / r;
+    const int o = i + j * R;
+    sm[d.oM0 + o] = Am[o] - nu * W1[o] + nu * W2[o];
+    sm[d.oMm + o] = nu * W1[o];
+    sm[d.oMp + o] = -nu * W2[o];
+  }
+  __syncthreads();
+  gmm(W3, T, sm + d.oEn, T, false, Cp, T, false, t, t, t, 1.0, 0.0);
+  gmm(sm + d.oGLo, R, Am, R, false, W3, T, false, r, t, t, nu, 0.0);
+  gmm(W3, T, sm + d.oEp, T, false, Cn, T, false, t, t, t, 1.0, 0.0);
+  gmm(sm + d.oGHi, R, Am, R, false, W3, T, false, r, t, t, -nu, 0.0);
+  if (rl > 0) {
+    gmm(W1, R, sm + d.oOlo, R, false, Cp, T, false, rl, t, t, 1.0, 0.0);
+    gmm(sm + d.oGLoN, R, d.S + (int64_t)lo * R * R, R, false, W1, R, false, rl, t, rl, nu, 0.0);
+  }
+  if (rh > 0) {
+    gmm(W2, R, sm + d.oOhi, R, false, Cn, T, false, rh, t, t, 1.0, 0.0);
+    gmm(sm + d.oGHiN, R, d.S + (int64_t)hi * R * R, R, false, W2, R, false, rh, t, rh, -nu, 0.0);
+  }
+}
+
+__global__ __launch_bounds__(STHR) void sw_adv_prep(Dev d, int axis, int sd0) {
+  const int s = sd0 + blockIdx.x;
+  const int t = d.tdim[s];
+  extern __shared__ double lds[];
+  __shared__ SmallScratch sc;
+  if (t <= 64) adv_prep_body<2, 1>(d, s, axis, t, lds, sc);
+  else adv_prep_body<4, 2>(d, s, axis, t, lds, sc);
+}
+
+// S-step (eq. advx_evolS, integrated with the opposite sign) and the L-step
+// coefficients, as in the narrow plan (Q = h U^1, frozen boundary data):
+//   BKlo = Xlo (Am En) + Xln (S_lo Olo),  BKhi = Xhi (Am Ep) + Xhn (S_hi Ohi),
+//   H-(S) = Gm S - BKlo,  H+(S) = Gp S + BKhi,  Gm = -Gp^T,
+//   S1 = h Racc,  S2 = S1 + dt c (H-(S1) C+ + H+(S1) C-),
+//   P0 = S2^T, Pm = -dt c H-(S2)^T, Pp = -dt c H+(S2)^T.
+__global__ __launch_bounds__(STHR) void sw_adv_sstep(Dev d, int axis, int sd0) {
+  const int s = sd0 + blockIdx.x;
+  const int lo = neighbour(d, s, axis, -1), hi = neighbour(d, s, axis, +1);
+  const int r = d.rank[s], rl = lo >= 0 ? d.rank[lo] : 0, rh = hi >= 0 ? d.rank[hi] : 0;
+  const int t = d.tdim[s];
+  const int R = d.R, T = d.T;
+  double* sm = small_of(d, s);
+  const double ih = 1.0 / d.h;
+  double* Gm = sm + d.oGm;
+  double* Gp = sm + d.oGp;
+  double* Xlo = sm + d.oW1;
+  double* Xhi = sm + d.oW2;
+  double* Xln = sm + d.oW3;
+  double* Xhn = sm + d.oW4;
+  const int oX = 2 * T * T, ngp = d.nwgN;
+  s_sum_partials(d, s, ngp, 0, t, t, t, Gp, T, ih);
+  s_sum_partials(d, s, ngp, oX, T, t, r, Xlo, T, 1.0);
+  s_sum_partials(d, s, ngp, oX + T * R, T, t, r, Xhi, T, 1.0);
+  s_sum_partials(d, s, ngp, oX + 2 * T * R, T, t, rl, Xln, T, 1.0);
+  s_sum_partials(d, s, ngp, oX + 3 * T * R, T, t, rh, Xhn, T, 1.0);
+  __syncthreads();
+  double* W5 = sm + d.oW5;
+  double* W6 = sm + d.oW6;
+  double* BKlo = sm + d.oBKlo;
+  double* BKhi = sm + d.oBKhi;
+  double* S1 = sm + d.oS1;
+  double* S2 = sm + d.oS2;
+  const double* Slo = lo >= 0 ? d.S + (int64_t)lo * R * R : d.S;
+  const double* Shi = hi >= 0 ? d.S + (int64_t)hi * R * R : d.S;
+  gmm(W5, R, sm + d.oAm, R, false, sm + d.oEn, T, false, r, t, t, 1.0, 0.0);
+  gmm(S1, T, sm + d.oAm, R, false, sm + d.oEp, T, false, r, t, t, 1.0, 0.0);
+  gmm(BKlo, T, Xlo, T, false, W5, R, false, t, t, r, 1.0, 0.0);
+  gmm(BKhi, T, Xhi, T, false, S1, T, false, t, t, r, 1.0, 0.0);
+  if (rl > 0) {
+    gmm(W6, R, Slo, R, false, sm + d.oOlo, R, false, rl, t, rl, 1.0, 0.0);
+    gmm(BKlo, T, Xln, T, false, W6, R, false, t, t, rl, 1.0, 1.0);
+  }
+  if (rh > 0) {
+    gmm(S2, T, Shi, R, false, sm + d.oOhi, R, false, rh, t, rh, 1.0, 0.0);
+    gmm(BKhi, T, Xhn, T, false, S2, T, false, t, t, rh, 1.0, 1.0);
+  }
+  for (int idx = threadIdx.x; idx < t * t; idx += STHR) {
+    const int i = idx % t, j = idx / t;
+    S1[i + j * T] = d.h * sm[d.oRacc + i + j * T];
+    Gm[i + j * T] = -Gp[j + i * T];
+  }
+  __syncthreads();
+  double* Hm = W5;
+  double* Hp = W6;
+  gmm(Hm, T, Gm, T, false, S1, T, false, t, t, t, 1.0, 0.0);
+  gmm(Hp, T, Gp, T, false, S1, T, false, t, t, t, 1.0, 0.0);
+  for (int idx = threadIdx.x; idx < t * t; idx += STHR) {
+    const int o = (idx % t) + (idx / t) * T;
+    Hm[o] -= BKlo[o];
+    Hp[o] += BKhi[o];
+    S2[o] = S1[o];
+  }
+  __syncthreads();
+  const double dc = d.dt * d.c;
+  gmm(S2, T, Hm, T, false, sm + d.oCp, T, false, t, t, t, dc, 1.0);
+  gmm(S2, T, Hp, T, false, sm + d.oCn, T, false, t, t, t, dc, 1.0);
+  gmm(Hm, T, Gm, T, false, S2, T, false, t, t, t, 1.0, 0.0);
+  gmm(Hp, T, Gp, T, false, S2, T, false, t, t, t, 1.0, 0.0);
+  for (int idx = threadIdx.x; idx < t * t; idx += STHR) {
+    const int i = idx % t, j = idx / t;
+    const int o = i + j * T, ot = j + i * T;
+    sm[d.oP0 + ot] = S2[o];
+    sm[d.oPm + ot] = -dc * (Hm[o] - BKlo[o]);
+    sm[d.oPp + ot] = -dc * (Hp[o] + BKhi[o]);
+  }
+}
+
+// Truncation (Algorithm 5) for t <= 128: S3 = RL^T, ring Jacobi with the
+// rotations accumulated (S3 J = U~ Sigma, V~ = J), the rank rule, and the
+// rotations Bu = U~[:, :r'] / h, Bv = V~[:, :r'] of the final products;
+// S = diag(sigma[:r']) goes into the state and r' into rnew.
+template <int PPW, int RPL>
+__device__ void trunc_body(const Dev& d, int s, int axis, int t, double* lds, SmallScratch& sc) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int R = d.R, T = d.T;
+  double* sm = small_of(d, s);
+  double* sigs = sc.v0;
+  double* sorted = sc.v1;
+  int* rk = sc.i0;
+  const double* RL = sm + d.oRacc;
+  RingCols<PPW, RPL, true, RPL> c;
+#pragma unroll
+  for (int k = 0; k < PPW; ++k)
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+      const int row = lane + 64 * i, p = wave * PPW + k;
+      const int ct = 2 * p, cb = 2 * p + 1;
+      c.tp[k][i] = (row < t && ct < t) ? RL[ct + row * T] : 0.0;   // S3[row][col] = RL[col][row]
+      c.bt[k][i] = (row < t && cb < t) ? RL[cb + row * T] : 0.0;
+      c.jt[k][i] = (row == ct && ct < t) ? 1.0 : 0.0;
+      c.jb[k][i] = (row == cb && cb < t) ? 1.0 : 0.0;
+    }
+  ring_jacobi<PPW, RPL, true, RPL>(d, c, t, t, 1e-14, 1e-15, 40, lds, sc.red, sc.rotflag);
+#pragma unroll
+  for (int k = 0; k < PPW; ++k) {
+    double nt = 0.0, nb = 0.0;
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+      nt = fma(c.tp[k][i], c.tp[k][i], nt);
+      nb = fma(c.bt[k][i], c.bt[k][i], nb);
+    }
+    nt = wave_sum(nt);
+    nb = wave_sum(nb);
+    const int p = wave * PPW + k;
+    if (lane == 0) {
+      if (2 * p < t) sigs[2 * p] = sqrt(nt);
+      if (2 * p + 1 < t) sigs[2 * p + 1] = sqrt(nb);
+    }
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < t; j += STHR) {
+    const int q = desc_rank(sigs, t, j);
+    rk[j] = q;
+    sorted[q] = sigs[j];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int rp;
+    const int cap = min(min(d.r_max, t), R);
+    if (d.forced && d.force[2 * d.nsub + axis * d.nsub + s] > 0) {
+      rp = min(d.force[2 * d.nsub + axis * d.nsub + s], min(t, R));
+    } else if (d.rank_mode == 0) {
+      rp = min(d.r_fixed, min(t, R));
+    } else {
+      rp = max(d.r_min, tail_rank(sorted, t, d.tol));
+      if (rp > cap) {
+        rp = cap;
+        atomicAdd(d.clamps, 1ull);
+        if (d.strict) atomicOr(d.flags, FLAG_RANK_CLAMP);
+      }
+    }
+    if (rp < 1) rp = 1;
+    sc.ival[0] = rp;
+    d.rnew[s] = rp;
+    sc.ival[1] = 0;
+  }
+  __syncthreads();
+  const int rp = sc.ival[0];
+  const double s0 = sorted[0];
+  const double ih = 1.0 / d.h;
+  double* Ut = sm + d.oBu;
+  double* Bv = sm + d.oBv;
+#pragma unroll
+  for (int k = 0; k < PPW; ++k) {
+    const int p = wave * PPW + k;
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      const int col = 2 * p + half;
+      if (col >= t) continue;
+      const int q = rk[col];
+      if (q >= rp) continue;
+      const double sg = sigs[col];
+      const bool ok = s0 > 0.0 && sg > 1e-13 * s0;
+      if (!ok && lane == 0) sc.ival[1] = 1;
+      const double isg = ok ? 1.0 / sg : 0.0;
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+        const int row = lane + 64 * i;
+        if (row < t) {
+          const double b = half ? c.bt[k][i] : c.tp[k][i];
+          const double v = half ? c.jb[k][i] : c.jt[k][i];
+          Ut[row + q * T] =
+              ok ? b * isg : hash_unit(((uint64_t)s << 40) ^ ((uint64_t)(q + 1000) << 24) ^ (uint64_t)row);
+          Bv[row + q * T] = v;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // completed columns are made orthonormal to the others (two passes of
+  // modified Gram-Schmidt)
+  if (sc.ival[1]) {
+    for (int pass = 0; pass < 2; ++pass)
+      for (int j = 0; j < rp; ++j) {
+        for (int k = 0; k < j; ++k) {
+          double part = 0.0;
+          for (int i = threadIdx.x; i < t; i += STHR) part = fma(Ut[i + k * T], Ut[i + j * T], part);
+          const double dot = s_sum(part, sc.red);
+          for (int i = threadIdx.x; i < t; i += STHR) Ut[i + j * T] -= dot * Ut[i + k * T];
+          __syncthreads();
+        }
+        double part = 0.0;
+        for (int i = threadIdx.x; i < t; i += STHR) part = fma(Ut[i + j * T], Ut[i + j * T], part);
+        const double nrm = sqrt(s_sum(part, sc.red));
+        const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+        for (int i = threadIdx.x; i < t; i += STHR) Ut[i + j * T] *= inv;
+        __syncthreads();
+      }
+  }
+  for (int idx = threadIdx.x; idx < t * rp; idx += STHR) {
+    const int i = idx % t, j = idx / t;
+    Ut[i + j * T] *= ih;
+  }
+  double* Sg = d.S + (int64_t)s * R * R;
+  for (int idx = threadIdx.x; idx < R * R; idx += STHR) {
+    const int i = idx % R, j = idx / R;
+    Sg[idx] = (i == j && i < rp) ? sorted[i] : 0.0;
+  }
+  if (threadIdx.x < rp && !isfinite(sorted[threadIdx.x])) atomicOr(d.flags, FLAG_NONFINITE);
+}
+
+__global__ __launch_bounds__(STHR) void sw_trunc(Dev d, int axis, int sd0) {
+  const int s = sd0 + blockIdx.x;
+  const int t = d.tdim[s];
+  extern __shared__ double lds[];
+  __shared__ SmallScratch sc;
+  if (t <= 64) trunc_body<2, 1>(d, s, axis, t, lds, sc);
+  else trunc_body<4, 2>(d, s, axis, t, lds, sc);
+}
+
+// m = V^T w (eq. coll_evolK) for stored ranks up to 64: one wavefront per
+// column, lanes striding over the directions, summed in a fixed order.
+__global__ __launch_bounds__(STHR) void sw_coll_prep(Dev d, int sd0) {
+  const int s = sd0 + blockIdx.x;
+  const int r = d.rank[s];
+  const int M = d.M, R = d.R;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const double* Vs = d.V + (int64_t)s * M * R;
+  for (int a = wave; a < r; a += SNW) {
+    double acc = 0.0;
+    for (int q = lane; q < M; q += 64) acc = fma(Vs[(int64_t)a * M + q], d.w[q], acc);
+    acc = wave_sum(acc);
+    if (lane == 0) small_of(d, s)[d.oMv + a] = acc;
+  }
+}
+
+// ============================================================================
+// launchers
+// ============================================================================
+namespace {
+template <int V>
+using wic = std::integral_constant<int, V>;
+template <class T>
+struct wtag {
+  using type = T;
+};
+
+template <class Fn>
+void w_with_prec(int prec, bool exact, Fn f) {
+  if (prec == DD_PREC_FP64) f(wtag<double>{}, wic<0>{});
+  else if (exact) f(wtag<float>{}, wic<0>{});
+  else if (prec == DD_PREC_MIXED_FP32) f(wtag<float>{}, wic<1>{});
+  else f(wtag<float>{}, wic<2>{});
+}
+
+// the dynamic LDS of a kernel may exceed the default limit only after this
+// attribute is set; it is set once per kernel (at handle creation), outside
+// any graph capture
+void w_allow(const void* fn) {
+  (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+}
+
+int w_dim_cap(const Dev& d, int which) { return which == DIM_M0 ? d.MA : (which == DIM_T ? d.T : d.R); }
+
+size_t ring_bytes_max() { return sizeof(double) * ring_lds_doubles<3, 0, false>(); }
+}  // namespace
+
+void launch_w_gemm(const Dev& d, int axis, int sd0, int nsd, const void* X, bool x64, int64_t xsd, int rows,
+                   int kdim, int ndim, int boff, int bld, void* Y, bool y64, int64_t ysd, const double* rowscale,
+                   int fill_off, bool rows_are_cells, bool exact, hipStream_t st, bool set_rank) {
+  const int nwg = rows_are_cells ? d.nwgN : d.nwgM;
+  constexpr int NCB = 4;
+  const int nz = wdiv(w_dim_cap(d, ndim), 16 * NCB);
+  const int ng = wdiv(w_dim_cap(d, kdim), 64);
+  auto go = [&](auto ti, auto to, auto pc) {
+    using SI = typename decltype(ti)::type;
+    using SO = typename decltype(to)::type;
+    constexpr int P = decltype(pc)::value;
+    const size_t lds = sizeof(typename Prec<P>::F) * (size_t)ng * 16 * NCB * 64;
+    hipLaunchKernelGGL((kw_gemm<SI, SO, P, NCB>), dim3(nwg, nsd, nz), dim3(WTHR), lds, st, d, axis, sd0, X, xsd,
+                       rows, kdim, ndim, boff, bld, Y, ysd, rowscale, fill_off, set_rank ? 1 : 0);
+  };
+  w_with_prec(d.prec, exact, [&](auto ts, auto pc) {
+    using W = typename decltype(ts)::type;
+    if (x64 && y64) go(wtag<double>{}, wtag<double>{}, pc);
+    else if (x64) go(wtag<double>{}, wtag<W>{}, pc);
+    else if (y64) go(wtag<W>{}, wtag<double>{}, pc);
+    else go(wtag<W>{}, wtag<W>{}, pc);
+  });
+}
+
+void launch_w_aug_form(const Dev& d, int axis, int sd0, int nsd, hipStream_t st) {
+  const size_t lds = sizeof(double) * 16 * 4 * 64;
+  hipLaunchKernelGGL(kw_aug_form, dim3(d.nwgM, nsd, 3), dim3(WTHR), lds, st, d, axis, sd0);
+}
+
+void launch_w_kstep(const Dev& d, int axis, int sd0, int nsd, hipStream_t st) {
+  const int nz = wdiv(d.T, 32);
+  w_with_prec(d.prec, false, [&](auto ts, auto pc) {
+    using S = typename decltype(ts)::type;
+    constexpr int P = decltype(pc)::value;
+    const size_t lds = sizeof(typename Prec<P>::F) * 7 * 16 * 2 * 64;
+    hipLaunchKernelGGL((kw_kstep<S, P>), dim3(d.nwgN, nsd, nz), dim3(WTHR), lds, st, d, axis, sd0);
+  });
+}
+
+void launch_w_lstep(const Dev& d, int axis, int sd0, int nsd, hipStream_t st) {
+  const int nz = wdiv(d.T, 32);
+  w_with_prec(d.prec, false, [&](auto ts, auto pc) {
+    using S = typename decltype(ts)::type;
+    constexpr int P = decltype(pc)::value;
+    const size_t lds = sizeof(typename Prec<P>::F) * 3 * (WCAP_T / 64) * 16 * 2 * 64;
+    hipLaunchKernelGGL((kw_lstep<S, P>), dim3(d.nwgM, nsd, nz), dim3(WTHR), lds, st, d, axis, sd0);
+  });
+}
+
+void launch_w_coll_kstep(const Dev& d, int sd0, int nsd, hipStream_t st) {
+  const int nz = wdiv(d.R, 32);
+  w_with_prec(d.prec, false, [&](auto ts, auto pc) {
+    using S = typename decltype(ts)::type;
+    constexpr int P = decltype(pc)::value;
+    hipLaunchKernelGGL((kw_coll_kstep<S, P>), dim3(d.nwgN, nsd, nz), dim3(WTHR), 0, st, d, sd0);
+  });
+}
+
+void launch_w_xgram(const Dev& d, int axis, int sd0, int nsd, XJobs jobs, bool cells, hipStream_t st) {
+  int z = 0;
+  for (int q = 0; q < jobs.n; ++q) {
+    XJob& J = jobs.j[q];
+    J.zbase = z;
+    z += J.sym ? J.pa * (J.pa + 1) / 2 : J.pa * J.pb;
+    J.rows_cells = cells ? 1 : 0;
+  }
+  if (d.prec == DD_PREC_FP64)
+    hipLaunchKernelGGL(kw_xgram<double>, dim3(cells ? d.nwgN : d.nwgM, nsd, z), dim3(XTHR), 0, st, d, axis, sd0,
+                       jobs);
+  else
+    hipLaunchKernelGGL(kw_xgram<float>, dim3(cells ? d.nwgN : d.nwgM, nsd, z), dim3(XTHR), 0, st, d, axis, sd0,
+                       jobs);
+}
+
+void launch_w_chol(const Dev& d, int axis, int sd0, int nsd, int ndim, int rows, int ngp, int acc_mode,
+                   double bscale, int oRinv, int oRacc, int ld, hipStream_t st) {
+  const size_t lds = sizeof(double) * (size_t)WLD * WCAP_T;
+  hipLaunchKernelGGL(sw_chol, dim3(nsd), dim3(STHR), lds, st, d, axis, sd0, ndim, rows, ngp, acc_mode, bscale,
+                     oRinv, oRacc, ld);
+}
+
+void launch_w_aug_svd(const Dev& d, int axis, int sd0, int nsd, hipStream_t st) {
+  const size_t lds = std::max(sizeof(double) * (size_t)WCAP_A * (WCAP_A + 1) / 2, ring_bytes_max());
+  hipLaunchKernelGGL(sw_aug_svd, dim3(nsd), dim3(STHR), lds, st, d, axis, sd0);
+}
+
+void launch_w_adv_prep(const Dev& d, int axis, int sd0, int nsd, hipStream_t st) {
+  const size_t lds = std::max(sizeof(double) * (size_t)WLD * WCAP_T, ring_bytes_max());
+  hipLaunchKernelGGL(sw_adv_prep, dim3(nsd), dim3(STHR), lds, st, d, axis, sd0);
+}
+
+void launch_w_adv_sstep(const Dev& d, int axis, int sd0, int nsd, hipStream_t st) {
+  hipLaunchKernelGGL(sw_adv_sstep, dim3(nsd), dim3(STHR), 0, st, d, axis, sd0);
+}
+
+void launch_w_trunc(const Dev& d, int axis, int sd0, int nsd, hipStream_t st) {
+  const size_t lds = sizeof(double) * ring_lds_doubles<2, 2, true>();
+  hipLaunchKernelGGL(sw_trunc, dim3(nsd), dim3(STHR), lds, st, d, axis, sd0);
+}
+
+void launch_w_coll_prep(const Dev& d, int sd0, int nsd, hipStream_t st) {
+  hipLaunchKernelGGL(sw_coll_prep, dim3(nsd), dim3(STHR), 0, st, d, sd0);
+}
+
+void init_wide_kernels() {
+  for (int prec = 0; prec < 3; ++prec)
+    for (int exact = 0; exact < 2; ++exact)
+      w_with_prec(prec, exact != 0, [&](auto ts, auto pc) {
+        using W = typename decltype(ts)::type;
+        constexpr int P = decltype(pc)::value;
+        w_allow((const void*)kw_gemm<double, double, P, 4>);
+        w_allow((const void*)kw_gemm<double, W, P, 4>);
+        w_allow((const void*)kw_gemm<W, double, P, 4>);
+        w_allow((const void*)kw_gemm<W, W, P, 4>);
+        w_allow((const void*)kw_kstep<W, P>);
+        w_allow((const void*)kw_lstep<W, P>);
+      });
+  w_allow((const void*)kw_aug_form);
+  w_allow((const void*)sw_chol);
+  w_allow((const void*)sw_aug_svd);
+  w_allow((const void*)sw_adv_prep);
+  w_allow((const void*)sw_trunc);
+  (void)hipGetLastError();
+}
+
+}  // namespace dd

@@ -98,8 +98,8 @@ def test_unknown_precision_rejected():
     (dict(x1=5.0), "square"),
     (dict(dt=0.0), "dt"),
     (dict(r_int_max=3), "r_int_max"),
-    (dict(r_int_max=80), "64"),
-    (dict(r_fixed=30, r_int_max=60), "21"),
+    (dict(r_int_max=130), "128"),
+    (dict(r_fixed=70, r_int_max=128), "64"),
     (dict(rank_mode=7), "rank_mode"),
 ])
 def test_invalid_configs_rejected(over, needle):
@@ -107,6 +107,17 @@ def test_invalid_configs_rejected(over, needle):
         pkg.workspace_size(_cfg(**over))
     assert ei.value.status == nat.DD_EINVAL
     assert needle in str(ei.value)
+
+
+@needs_lib
+@pytest.mark.parametrize("name", ["C4", "C5"])
+def test_largest_configurations_accepted(name):
+    """The adaptive configurations with stored ranks up to 40 / 64 and
+    intermediate ranks up to 80 / 128 fit the engine's capacities (the wide
+    launch plan)."""
+    wl = wk.make_workload(name)
+    n = pkg.workspace_size(wl)
+    assert n > wl.n_sub * wl.N * wl.r_max * 8
 
 
 @needs_lib
