@@ -648,7 +648,7 @@ void* w_chol_qr(dd_dlra_handle h, int axis, int ndim, void* X, void* Y, int64_t 
     w_gram(h, gram_kind, axis, cur, false, sd, rows, ndim, cap, cells);
     phase(h, K_W_CHOL, [&](int s0, int ns) {
       dd::launch_w_chol(d, axis, s0, ns, ndim, rows, ngp, acc ? (pass == 0 ? 1 : 2) : 0, 1.0, d.oRinv, d.oRacc, d.T,
-                        h->stream);
+                        pass > 0, h->stream);
     });
     phase(h, gemm_kind, [&](int s0, int ns) {
       dd::launch_w_gemm(d, axis, s0, ns, cur, false, sd, rows, ndim, ndim, d.oRinv, d.T, oth, false, sd, nullptr,
@@ -874,7 +874,10 @@ dd_status dd_dlra_create(const dd_dlra_config* cfg, const int32_t* rank0, const 
       h->err = "cannot query the compute-unit count";
       return fail(DD_EHIP);
     }
-    const int occ = d.wide ? 1 : dd::ts_resident_wgs(d);
+    // the wide plan's workgroups of low-rank subdomains exit at once (column
+    // chunks beyond their ranks), so it takes more of them per subdomain:
+    // the high-rank subdomains then spread over more compute units
+    const int occ = d.wide ? 4 : dd::ts_resident_wgs(d);
     const int per_sd = std::max(1, ncu * occ / d.nsub);
     d.nwgN = std::min(per_sd, L.nwgN);
     d.nwgM = std::min(per_sd, L.nwgM);

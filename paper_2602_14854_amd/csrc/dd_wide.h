@@ -53,8 +53,10 @@ void launch_w_kstep(const Dev& d, int axis, int sd0, int nsd, hipStream_t st);
 void launch_w_lstep(const Dev& d, int axis, int sd0, int nsd, hipStream_t st);
 void launch_w_coll_kstep(const Dev& d, int sd0, int nsd, hipStream_t st);
 void launch_w_xgram(const Dev& d, int axis, int sd0, int nsd, XJobs jobs, bool cells, hipStream_t st);
+// near: a Gram within 1e-3 of the identity takes the symmetric factor from
+// the binomial series instead of the Cholesky factorisation
 void launch_w_chol(const Dev& d, int axis, int sd0, int nsd, int ndim, int rows, int ngp, int acc_mode,
-                   double bscale, int oRinv, int oRacc, int ld, hipStream_t st);
+                   double bscale, int oRinv, int oRacc, int ld, bool near, hipStream_t st);
 void launch_w_aug_svd(const Dev& d, int axis, int sd0, int nsd, hipStream_t st);
 void launch_w_adv_prep(const Dev& d, int axis, int sd0, int nsd, hipStream_t st);
 void launch_w_adv_sstep(const Dev& d, int axis, int sd0, int nsd, hipStream_t st);

@@ -736,6 +736,118 @@ __device__ __forceinline__ void gmm(double* C, int ldc, const double* A, int lda
   gmm(C, ldc, A, lda, ta, B, ldb, tb, m, n, k, alpha, beta, C, ldc);
 }
 
+// C = alpha A B + beta D for n x n matrices whose product is symmetric (A,
+// B, D symmetric, A and B commuting, as for polynomials in one symmetric
+// matrix): only the 16 x 16 tiles on and above the diagonal are formed and
+// each value is stored at (i, j) and (j, i) (in a diagonal tile only i <= j
+// writes), so C comes out exactly symmetric and iterations built on it keep
+// exact symmetry.  C differs from A, B and D unless beta = 0.  Ends with a
+// barrier.
+__device__ void gmm_sym(double* C, int ldc, const double* A, int lda, const double* B, int ldb, int n, double alpha,
+                        double beta, const double* D, int ldd) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+  const int l16 = lane & 15, kq = lane >> 4;
+  const int tn = wdiv(n, 16);
+  const int ntiles = tn * (tn + 1) / 2;
+  for (int tile = wave; tile < ntiles; tile += nw) {
+    int tj = 0, ti = tile;
+    while (ti > tj) {
+      ti -= tj + 1;
+      ++tj;
+    }
+    const int i0 = 16 * ti, j0 = 16 * tj;
+    const int i = i0 + l16, j = j0 + l16;
+    const int ic = i < n ? i : 0, jc = j < n ? j : 0;
+    dbl4 e = zero4(), o = zero4();
+    for (int k0 = 0; k0 < n; k0 += 64) {
+      double av[16], bv[16];
+#pragma unroll
+      for (int s4 = 0; s4 < 16; ++s4) {
+        const int l = k0 + 4 * s4 + kq;
+        const int lc = l < n ? l : 0;
+        const double a_ = A[ic + (int64_t)lc * lda];
+        const double b_ = B[lc + (int64_t)jc * ldb];
+        av[s4] = (i < n && l < n) ? a_ : 0.0;
+        bv[s4] = (j < n && l < n) ? b_ : 0.0;
+      }
+#pragma unroll
+      for (int s4 = 0; s4 < 16; s4 += 2) {
+        e = mfma64(av[s4], bv[s4], e);
+        o = mfma64(av[s4 + 1], bv[s4 + 1], o);
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int ci = i0 + 4 * v + kq, cj = j0 + l16;
+      if (ci < n && cj < n && (ti != tj || ci <= cj)) {
+        const double acc = e[v] + o[v];
+        const double val = beta == 0.0 ? alpha * acc : fma(alpha, acc, beta * D[ci + (int64_t)cj * ldd]);
+        C[ci + (int64_t)cj * ldc] = val;
+        C[cj + (int64_t)ci * ldc] = val;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// |C| = sign(C) C for a symmetric t x t matrix C (ld ld) into out, by the
+// scaled Newton-Schulz iteration of Chen and Chow (2014) on X0 = C / |C|_F:
+//   X <- a X (3 I - a^2 X^2) / 2,  a = sqrt(3 / (1 + l + l^2)),
+// which maps eigenvalues in [l, 1] into [l', 1], l' = a l (3 - a^2 l^2) / 2,
+// started from l = 1e-4 / sqrt(t), then the unscaled iteration
+// X <- X (3 I - X^2) / 2 until an update moves X by at most 1e-14
+// (Frobenius, at most 48 steps).  Eigenvalues below the scaled phase's bound
+// keep their sign; exactly zero ones stay zero.  X, Y and W are t x t work
+// buffers (ld ld).  Then C+ = (C + |C|) / 2 = P diag(max(lambda, 0)) P^T and
+// C- = (C - |C|) / 2 without the eigenvectors.
+__device__ void ns_abs(const double* C, double* X, double* Y, double* W, double* out, int t, int ld, double* red) {
+  double part = 0.0;
+  for (int idx = threadIdx.x; idx < t * t; idx += blockDim.x) {
+    const double c = C[(idx % t) + (int64_t)(idx / t) * ld];
+    part = fma(c, c, part);
+  }
+  const double fro = sqrt(s_sum(part, red));
+  if (!(fro > 0.0)) {
+    for (int idx = threadIdx.x; idx < t * t; idx += blockDim.x) out[(idx % t) + (int64_t)(idx / t) * ld] = 0.0;
+    __syncthreads();
+    return;
+  }
+  const double ifro = 1.0 / fro;
+  for (int idx = threadIdx.x; idx < t * t; idx += blockDim.x) {
+    const int o = (idx % t) + (idx / t) * ld;
+    X[o] = C[o] * ifro;
+  }
+  __syncthreads();
+  double l = 1e-4 / sqrt((double)t);
+  for (int it = 0; it < 64 && 1.0 - l > 1e-15; ++it) {
+    const double a2 = 3.0 / (1.0 + l + l * l), a = sqrt(a2);
+    const double c1 = 1.5 * a, c3 = -0.5 * a * a2;
+    gmm_sym(Y, ld, X, ld, X, ld, t, 1.0, 0.0, Y, ld);   // X^2
+    gmm_sym(W, ld, X, ld, Y, ld, t, c3, c1, X, ld);     // c1 X + c3 X^3
+    double* sw = X;
+    X = W;
+    W = sw;
+    l = l * (c1 + c3 * l * l);
+  }
+  for (int it = 0; it < 48; ++it) {
+    gmm_sym(Y, ld, X, ld, X, ld, t, 1.0, 0.0, Y, ld);
+    gmm_sym(W, ld, X, ld, Y, ld, t, -0.5, 1.5, X, ld);
+    double ch = 0.0;
+    for (int idx = threadIdx.x; idx < t * t; idx += blockDim.x) {
+      const int o = (idx % t) + (idx / t) * ld;
+      const double dl = W[o] - X[o];
+      ch = fma(dl, dl, ch);
+    }
+    const double ch2 = s_sum(ch, red);
+    double* sw = X;
+    X = W;
+    W = sw;
+    if (ch2 <= 1e-28) break;
+  }
+  gmm_sym(out, ld, X, ld, C, ld, t, 1.0, 0.0, out, ld);  // sign(C) C
+}
+
 // Right-looking Cholesky G = L L^T of the n x n matrix in LDS (lower
 // triangle, ld WLD; n <= 128) in place.  dep[k] = 1 marks a pivot at most
 // 1e-20 of its initial diagonal d0[k] (or not finite): its column is set to
@@ -812,6 +924,11 @@ __device__ void lds_tri_inv(double* L, int n, double* colj) {
 // which meets every pair once in n2 - 1 rounds.  Moves inside a wavefront
 // are register copies; the two columns that cross to a neighbouring
 // wavefront go through a double-buffered LDS area (one barrier per round).
+// The squared column norms travel with the columns and are updated with
+// each rotation (|x'|^2 = c^2 |x|^2 - 2 c s x.y + s^2 |y|^2, and likewise),
+// recomputed exactly at the start of every sweep, so a round sums one inner
+// product per pair; the rotation parameters of a wavefront's pairs are
+// formed side by side in its first lanes and read back as scalars.
 // ----------------------------------------------------------------------------
 template <int PPW, int RPL, bool ACC, int JRPL>
 struct RingCols {
@@ -819,9 +936,21 @@ struct RingCols {
   double jt[PPW][ACC ? JRPL : 1], jb[PPW][ACC ? JRPL : 1];
 };
 
-// LDS doubles needed by ring_jacobi
+// LDS doubles needed by ring_jacobi: a moving column carries its rows and
+// the rows of its J column (double-buffered, both directions), and its
+// squared norm, one value per wavefront
 template <int RPL, int JRPL, bool ACC>
-constexpr int ring_lds_doubles() { return 2 * 2 * SNW * 64 * (RPL + (ACC ? JRPL : 0)); }
+constexpr int ring_lds_doubles() { return 2 * 2 * SNW * 64 * (RPL + (ACC ? JRPL : 0)) + 2 * 2 * SNW; }
+
+// a wave-uniform double moved to scalar registers (keeps the per-pair
+// norms and inner products out of the vector register budget)
+__device__ __forceinline__ double uni(double x) {
+  union { double d; int i[2]; } a;
+  a.d = x;
+  a.i[0] = __builtin_amdgcn_readfirstlane(a.i[0]);
+  a.i[1] = __builtin_amdgcn_readfirstlane(a.i[1]);
+  return a.d;
+}
 
 // Returns the sweeps done (negative if not converged within max_sweeps).
 template <int PPW, int RPL, bool ACC, int JRPL>
@@ -841,44 +970,70 @@ __device__ int ring_jacobi(const Dev& d, RingCols<PPW, RPL, ACC, JRPL>& c, int r
   const double tol2 = tol * tol;
   if (n2 <= 1) return 0;
   constexpr int CW = RPL + (ACC ? JRPL : 0);  // doubles per lane of one moving column
+  double* nbuf = xbuf + 2 * 2 * SNW * 64 * CW;   // [buf][direction][wave] norms
   bool converged = false;
   int sweeps = 0;
   int buf = 0;
+  double nt[PPW], nb[PPW];
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     sweeps = sweep + 1;
     bool rot = false;
+    // exact squared norms at the start of the sweep
+#pragma unroll
+    for (int k = 0; k < PPW; ++k) {
+      double a = 0.0, b = 0.0;
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+        a = fma(c.tp[k][i], c.tp[k][i], a);
+        b = fma(c.bt[k][i], c.bt[k][i], b);
+      }
+      nt[k] = uni(wave_sum(a));
+      nb[k] = uni(wave_sum(b));
+    }
     for (int round = 0; round < n2 - 1; ++round) {
-      // inner products and rotations of this wavefront's pairs
+      double g[PPW];
 #pragma unroll
       for (int k = 0; k < PPW; ++k) {
-        double al = 0.0, be = 0.0, ga = 0.0;
+        double ga = 0.0;
 #pragma unroll
-        for (int i = 0; i < RPL; ++i) {
-          al = fma(c.tp[k][i], c.tp[k][i], al);
-          be = fma(c.bt[k][i], c.bt[k][i], be);
-          ga = fma(c.tp[k][i], c.bt[k][i], ga);
+        for (int i = 0; i < RPL; ++i) ga = fma(c.tp[k][i], c.bt[k][i], ga);
+        g[k] = uni(wave_sum(ga));
+      }
+      // lane k < PPW forms the rotation of pair k
+      double al = nt[0], be = nb[0], ga = g[0];
+#pragma unroll
+      for (int k = 1; k < PPW; ++k)
+        if (lane == k) {
+          al = nt[k];
+          be = nb[k];
+          ga = g[k];
         }
-        al = wave_sum(al);
-        be = wave_sum(be);
-        ga = wave_sum(ga);
-        const bool live = p0 + k < P;
-        if (live && ga != 0.0 && al > floor2 && be > floor2 && ga * ga > tol2 * al * be) {
-          double cs, sn;
-          jacobi_rotation(al, be, ga, cs, sn);
+      const bool mine = lane < PPW && p0 + lane < P;
+      const bool dorot = mine && ga != 0.0 && al > floor2 && be > floor2 && ga * ga > tol2 * al * be;
+      double cs = 1.0, sn = 0.0;
+      if (dorot) jacobi_rotation(al, be, ga, cs, sn);
+      const int flag = dorot ? 1 : 0;
+#pragma unroll
+      for (int k = 0; k < PPW; ++k) {
+        if (__builtin_amdgcn_readlane(flag, k)) {
+          const double ck = lane_value(cs, k), sk = lane_value(sn, k);
 #pragma unroll
           for (int i = 0; i < RPL; ++i) {
             const double x = c.tp[k][i], y = c.bt[k][i];
-            c.tp[k][i] = cs * x - sn * y;
-            c.bt[k][i] = fma(sn, x, cs * y);
+            c.tp[k][i] = ck * x - sk * y;
+            c.bt[k][i] = fma(sk, x, ck * y);
           }
           if (ACC) {
 #pragma unroll
             for (int i = 0; i < JRPL; ++i) {
               const double x = c.jt[k][i], y = c.jb[k][i];
-              c.jt[k][i] = cs * x - sn * y;
-              c.jb[k][i] = fma(sn, x, cs * y);
+              c.jt[k][i] = ck * x - sk * y;
+              c.jb[k][i] = fma(sk, x, ck * y);
             }
           }
+          const double a = nt[k], b = nb[k], cg = 2.0 * ck * sk * g[k];
+          nt[k] = uni(fma(ck * ck, a, fma(sk * sk, b, -cg)));
+          nb[k] = uni(fma(sk * sk, a, fma(ck * ck, b, cg)));
           rot = true;
         }
       }
@@ -900,77 +1055,76 @@ __device__ int ring_jacobi(const Dev& d, RingCols<PPW, RPL, ACC, JRPL>& c, int r
           outB[(RPL + i) * 64 + lane] = c.jb[0][i];
         }
       }
+      if (lane == 0) {
+        nbuf[(buf * 2 + 0) * SNW + wave] = nt[PPW - 1];
+        nbuf[(buf * 2 + 1) * SNW + wave] = nb[0];
+      }
       __syncthreads();
-      // moves: bottoms shift down (towards smaller p), tops shift up
-      const double* inT = ob + (0 * SNW + (wave > 0 ? wave - 1 : 0)) * 64 * CW;   // previous wave's last top
-      const double* inB = ob + (1 * SNW + (wave < SNW - 1 ? wave + 1 : wave)) * 64 * CW;  // next wave's first bottom
-      double ntp[PPW][RPL], nbt[PPW][RPL];
-      double njt[PPW][ACC ? JRPL : 1], njb[PPW][ACC ? JRPL : 1];
+      const double* inT = ob + (0 * SNW + (wave > 0 ? wave - 1 : 0)) * 64 * CW;
+      const double* inB = ob + (1 * SNW + (wave < SNW - 1 ? wave + 1 : wave)) * 64 * CW;
+      // in place: bottoms first in ascending slot order (each reads the old
+      // value of the next slot), then tops in descending order (each reads
+      // the old value of the previous slot); bot[0] is kept for top'[1]
+      double b0[RPL], jb0[ACC ? JRPL : 1];
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) b0[i] = c.bt[0][i];
+      if (ACC)
+#pragma unroll
+        for (int i = 0; i < JRPL; ++i) jb0[i] = c.jb[0][i];
+      const double nb0 = nb[0];
 #pragma unroll
       for (int k = 0; k < PPW; ++k) {
         const int p = p0 + k;
-        // new top
-        if (k == 0) {
-          if (p == 0) {
-#pragma unroll
-            for (int i = 0; i < RPL; ++i) ntp[k][i] = c.tp[0][i];
-            if (ACC)
-#pragma unroll
-              for (int i = 0; i < JRPL; ++i) njt[k][i] = c.jt[0][i];
-          } else {
-#pragma unroll
-            for (int i = 0; i < RPL; ++i) ntp[k][i] = inT[i * 64 + lane];
-            if (ACC)
-#pragma unroll
-              for (int i = 0; i < JRPL; ++i) njt[k][i] = inT[(RPL + i) * 64 + lane];
-          }
-        } else if (p == 1) {
-#pragma unroll
-          for (int i = 0; i < RPL; ++i) ntp[k][i] = c.bt[0][i];
-          if (ACC)
-#pragma unroll
-            for (int i = 0; i < JRPL; ++i) njt[k][i] = c.jb[0][i];
-        } else {
-#pragma unroll
-          for (int i = 0; i < RPL; ++i) ntp[k][i] = c.tp[k - 1][i];
-          if (ACC)
-#pragma unroll
-            for (int i = 0; i < JRPL; ++i) njt[k][i] = c.jt[k - 1][i];
-        }
-        // new bottom
         if (p == P - 1) {
 #pragma unroll
-          for (int i = 0; i < RPL; ++i) nbt[k][i] = c.tp[k][i];
+          for (int i = 0; i < RPL; ++i) c.bt[k][i] = c.tp[k][i];
           if (ACC)
 #pragma unroll
-            for (int i = 0; i < JRPL; ++i) njb[k][i] = c.jt[k][i];
+            for (int i = 0; i < JRPL; ++i) c.jb[k][i] = c.jt[k][i];
+          nb[k] = nt[k];
         } else if (k == PPW - 1) {
 #pragma unroll
-          for (int i = 0; i < RPL; ++i) nbt[k][i] = inB[i * 64 + lane];
+          for (int i = 0; i < RPL; ++i) c.bt[k][i] = inB[i * 64 + lane];
           if (ACC)
 #pragma unroll
-            for (int i = 0; i < JRPL; ++i) njb[k][i] = inB[(RPL + i) * 64 + lane];
+            for (int i = 0; i < JRPL; ++i) c.jb[k][i] = inB[(RPL + i) * 64 + lane];
+          nb[k] = uni(nbuf[(buf * 2 + 1) * SNW + (wave < SNW - 1 ? wave + 1 : wave)]);
         } else {
 #pragma unroll
-          for (int i = 0; i < RPL; ++i) nbt[k][i] = c.bt[k + 1][i];
+          for (int i = 0; i < RPL; ++i) c.bt[k][i] = c.bt[k + 1][i];
           if (ACC)
 #pragma unroll
-            for (int i = 0; i < JRPL; ++i) njb[k][i] = c.jb[k + 1][i];
+            for (int i = 0; i < JRPL; ++i) c.jb[k][i] = c.jb[k + 1][i];
+          nb[k] = nb[k + 1];
         }
       }
 #pragma unroll
-      for (int k = 0; k < PPW; ++k) {
+      for (int k = PPW - 1; k >= 0; --k) {
+        const int p = p0 + k;
+        if (k == 0) {
+          if (p != 0) {
 #pragma unroll
-        for (int i = 0; i < RPL; ++i) {
-          c.tp[k][i] = ntp[k][i];
-          c.bt[k][i] = nbt[k][i];
-        }
-        if (ACC)
+            for (int i = 0; i < RPL; ++i) c.tp[0][i] = inT[i * 64 + lane];
+            if (ACC)
 #pragma unroll
-          for (int i = 0; i < JRPL; ++i) {
-            c.jt[k][i] = njt[k][i];
-            c.jb[k][i] = njb[k][i];
+              for (int i = 0; i < JRPL; ++i) c.jt[0][i] = inT[(RPL + i) * 64 + lane];
+            nt[0] = uni(nbuf[(buf * 2 + 0) * SNW + (wave > 0 ? wave - 1 : 0)]);
           }
+        } else if (p == 1) {
+#pragma unroll
+          for (int i = 0; i < RPL; ++i) c.tp[k][i] = b0[i];
+          if (ACC)
+#pragma unroll
+            for (int i = 0; i < JRPL; ++i) c.jt[k][i] = jb0[i];
+          nt[k] = nb0;
+        } else {
+#pragma unroll
+          for (int i = 0; i < RPL; ++i) c.tp[k][i] = c.tp[k - 1][i];
+          if (ACC)
+#pragma unroll
+            for (int i = 0; i < JRPL; ++i) c.jt[k][i] = c.jt[k - 1][i];
+          nt[k] = nt[k - 1];
+        }
       }
       buf ^= 1;
     }
@@ -1029,7 +1183,7 @@ struct SmallScratch {
 //   Racc slot: R (acc_mode 1) or R Racc (acc_mode 2), rows of dependent
 //              columns zeroed.
 __global__ __launch_bounds__(STHR) void sw_chol(Dev d, int axis, int sd0, int ndim, int rows, int ngp, int acc_mode,
-                                               double bscale, int oRinv, int oRacc, int ld) {
+                                               double bscale, int oRinv, int oRacc, int ld, int near) {
   const int s = sd0 + blockIdx.x;
   const int n = dim_of(d, s, axis, ndim);
   double* sm = small_of(d, s);
@@ -1038,6 +1192,73 @@ __global__ __launch_bounds__(STHR) void sw_chol(Dev d, int axis, int sd0, int nd
   double* d0 = sc.v0;
   int* dep = sc.i0;
   if (n <= 0) return;
+  if (near) {
+    // A Gram within 1e-3 (Frobenius) of the identity (a pass over an input
+    // that is already orthonormal up to rounding) takes the symmetric factor
+    // from the binomial series in E = G - I:
+    //   R    = I + E/2 - E^2/8 + E^3/16 - 5 E^4/128,
+    //   R^-1 = I - E/2 + 3 E^2/8 - 5 E^3/16 + 35 E^4/128,
+    // cut after E^2 when |E|^2 <= 1e-10 (remainder 0.3 |E|^3 <= 3e-16) and
+    // after E^4 otherwise (remainder 0.25 |E|^5 <= 2.5e-16); any R with
+    // G = R^T R gives an orthonormal Q = X R^-1.
+    const int T = d.T;
+    double* E = sm + d.oW2;
+    double* E2 = sm + d.oW3;
+    double* E3 = sm + d.oW4;
+    double* E4 = sm + d.oW5;
+    s_sum_partials(d, s, ngp, 0, n, n, n, E, T, 1.0);
+    __syncthreads();
+    double part = 0.0;
+    for (int idx = threadIdx.x; idx < n * n; idx += STHR) {
+      const int i = idx % n, j = idx / n;
+      // symmetrise, subtract the identity
+      const double e = 0.5 * (E[i + j * T] + E[j + i * T]) - (i == j ? 1.0 : 0.0);
+      L[i + j * WLD] = e;
+      part = fma(e, e, part);
+    }
+    const double fro2 = s_sum(part, sc.red);
+    if (fro2 <= 1e-6) {
+      for (int idx = threadIdx.x; idx < n * n; idx += STHR) {
+        const int i = idx % n, j = idx / n;
+        E[i + j * T] = L[i + j * WLD];
+      }
+      __syncthreads();
+      const bool o4 = fro2 > 1e-10;
+      gmm_sym(E2, T, E, T, E, T, n, 1.0, 0.0, E2, T);
+      if (o4) {
+        gmm_sym(E3, T, E, T, E2, T, n, 1.0, 0.0, E3, T);
+        gmm_sym(E4, T, E2, T, E2, T, n, 1.0, 0.0, E4, T);
+      }
+      for (int idx = threadIdx.x; idx < n * n; idx += STHR) {
+        const int i = idx % n, j = idx / n;
+        const int o = i + j * T;
+        const double id = i == j ? 1.0 : 0.0, e = E[o], e2 = E2[o];
+        double r = id + 0.5 * e - 0.125 * e2, ri = id - 0.5 * e + 0.375 * e2;
+        if (o4) {
+          r += 0.0625 * E3[o] - 0.0390625 * E4[o];
+          ri += -0.3125 * E3[o] + 0.2734375 * E4[o];
+        }
+        L[i + j * WLD] = r;
+        sm[oRinv + i + j * ld] = bscale * ri;
+      }
+      for (int j = threadIdx.x; j < n; j += STHR) sm[d.oFill + j] = 0.0;
+      __syncthreads();
+      if (acc_mode == 1) {
+        for (int idx = threadIdx.x; idx < n * n; idx += STHR) {
+          const int i = idx % n, j = idx / n;
+          sm[oRacc + i + j * ld] = L[i + j * WLD];
+        }
+      } else if (acc_mode == 2) {
+        double* Wt = sm + d.oW1;
+        gmm(Wt, T, L, WLD, false, sm + oRacc, ld, false, n, n, n, 1.0, 0.0);
+        for (int idx = threadIdx.x; idx < n * n; idx += STHR) {
+          const int i = idx % n, j = idx / n;
+          sm[oRacc + i + j * ld] = Wt[i + j * T];
+        }
+      }
+      return;
+    }
+  }
   bool shifted = false;
   for (int attempt = 0; attempt < 2; ++attempt) {
     s_sum_partials(d, s, ngp, 0, n, n, n, L, WLD, 1.0);
@@ -1266,26 +1487,17 @@ __global__ __launch_bounds__(STHR) void sw_aug_svd(Dev d, int axis, int sd0) {
   else aug_svd_body<6, 3>(d, s, axis, m0, lds, sc);
 }
 
-// Eigen-split of the angular Galerkin matrix C (Appendix A) for t <= 128 and
-// the K-step coefficient matrices.  C + sigma I with sigma = 1.5 |C|_F has
-// its spectrum in [0.5, 2.5] |C|_F: its Cholesky factor L is well
-// conditioned, and the ring Jacobi gives L J = B, whose columns are
-// eigenvectors of C scaled by sqrt(lambda + sigma).  Then C+ = P
-// diag(max(lambda, 0)) P^T and C- = P diag(min(lambda, 0)) P^T, and
+// Upwind split of the angular Galerkin matrix C (Appendix A: C = P diag(lambda)
+// P^T, C+ = P diag(max(lambda, 0)) P^T, C- = P diag(min(lambda, 0)) P^T) for
+// t <= 128 by the sign function (ns_abs), and the K-step coefficients
 //   M0 = Am (I - nu C+ + nu C-), Mm = nu Am C+, Mp = -nu Am C-,
 //   GLo = nu Am En C+, GHi = -nu Am Ep C-,
 //   GLoN = nu S_lo Olo C+, GHiN = -nu S_hi Ohi C-,   Am = S Tm, nu = dt c / h.
-template <int PPW, int RPL>
 __device__ void adv_prep_body(const Dev& d, int s, int axis, int t, double* lds, SmallScratch& sc) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lo = neighbour(d, s, axis, -1), hi = neighbour(d, s, axis, +1);
   const int r = d.rank[s], rl = lo >= 0 ? d.rank[lo] : 0, rh = hi >= 0 ? d.rank[hi] : 0;
   const int R = d.R, T = d.T;
   double* sm = small_of(d, s);
-  double* d0 = sc.v0;
-  int* dep = sc.i0;
-  double* lam = sc.v1;
-  double* isc = sc.v2;
   double* Cl = lds;  // t x t, ld WLD
   const int pT = 0, pC = R * T, pEp = pC + T * T, pEn = pEp + T * T, pOlo = pEn + T * T, pOhi = pOlo + R * T;
   const int ngp = d.nwgM;
@@ -1296,82 +1508,23 @@ __device__ void adv_prep_body(const Dev& d, int s, int axis, int t, double* lds,
   s_sum_partials(d, s, ngp, pOhi, R, rh, t, sm + d.oOhi, R, 1.0);
   s_sum_partials(d, s, ngp, pC, t, t, t, Cl, WLD, 1.0);
   __syncthreads();
-  double part = 0.0;
-  for (int idx = threadIdx.x; idx < t * t; idx += STHR) {
-    const int i = idx % t, j = idx / t;
-    part = fma(Cl[i + j * WLD], Cl[i + j * WLD], part);
-  }
-  const double fro = sqrt(s_sum(part, sc.red));
   double* Cp = sm + d.oCp;
   double* Cn = sm + d.oCn;
-  double* Bm = sm + d.oW4;  // eigen-columns B (t x t, ld T)
-  double* Bd = sm + d.oW5;
-  if (fro > 0.0) {
-    const double sig = 1.5 * fro;
-    for (int i = threadIdx.x; i < t; i += STHR) {
-      Cl[i * (WLD + 1)] += sig;
-      d0[i] = Cl[i * (WLD + 1)];
-    }
-    __syncthreads();
-    lds_chol(d, Cl, t, d0, dep, sc.red);
-    RingCols<PPW, RPL, false, 1> c;
-#pragma unroll
-    for (int k = 0; k < PPW; ++k)
-#pragma unroll
-      for (int i = 0; i < RPL; ++i) {
-        const int row = lane + 64 * i, p = wave * PPW + k;
-        const int ct = 2 * p, cb = 2 * p + 1;
-        c.tp[k][i] = (row < t && ct < t) ? Cl[row + ct * WLD] : 0.0;
-        c.bt[k][i] = (row < t && cb < t) ? Cl[row + cb * WLD] : 0.0;
-      }
-    __syncthreads();
-    ring_jacobi<PPW, RPL, false, 1>(d, c, t, t, 1e-14, 1e-15, 40, lds, sc.red, sc.rotflag);
-    // lambda = |b|^2 - sigma; B to the workspace
-#pragma unroll
-    for (int k = 0; k < PPW; ++k) {
-      const int p = wave * PPW + k;
-#pragma unroll
-      for (int half = 0; half < 2; ++half) {
-        const int col = 2 * p + half;
-        double nrm = 0.0;
-#pragma unroll
-        for (int i = 0; i < RPL; ++i) {
-          const double x = half ? c.bt[k][i] : c.tp[k][i];
-          nrm = fma(x, x, nrm);
-        }
-        nrm = wave_sum(nrm);
-        if (col < t) {
-#pragma unroll
-          for (int i = 0; i < RPL; ++i) {
-            const int row = lane + 64 * i;
-            if (row < t) Bm[row + col * T] = half ? c.bt[k][i] : c.tp[k][i];
-          }
-          if (lane == 0) {
-            lam[col] = nrm - sig;
-            isc[col] = nrm > 0.0 ? 1.0 / nrm : 0.0;
-          }
-        }
-      }
-    }
-    __syncthreads();
-    // C+ = B diag(max(lam,0) / |b|^2) B^T, C- likewise
+  {
+    // symmetric C in the workspace, then the sign-function split
+    double* Cw = sm + d.oW4;
+    double* Ab = sm + d.oW3;
     for (int idx = threadIdx.x; idx < t * t; idx += STHR) {
       const int i = idx % t, j = idx / t;
-      Bd[i + j * T] = Bm[i + j * T] * fmax(lam[j], 0.0) * isc[j];
+      Cw[i + j * T] = 0.5 * (Cl[i + j * WLD] + Cl[j + i * WLD]);
     }
     __syncthreads();
-    gmm(Cp, T, Bd, T, false, Bm, T, true, t, t, t, 1.0, 0.0);
+    ns_abs(Cw, sm + d.oW5, sm + d.oW1, sm + d.oW2, Ab, t, T, sc.red);
     for (int idx = threadIdx.x; idx < t * t; idx += STHR) {
       const int i = idx % t, j = idx / t;
-      Bd[i + j * T] = Bm[i + j * T] * fmin(lam[j], 0.0) * isc[j];
-    }
-    __syncthreads();
-    gmm(Cn, T, Bd, T, false, Bm, T, true, t, t, t, 1.0, 0.0);
-  } else {
-    for (int idx = threadIdx.x; idx < t * t; idx += STHR) {
-      const int i = idx % t, j = idx / t;
-      Cp[i + j * T] = 0.0;
-      Cn[i + j * T] = 0.0;
+      const double c = Cw[i + j * T], ab = 0.5 * (Ab[i + j * T] + Ab[j + i * T]);
+      Cp[i + j * T] = 0.5 * (c + ab);
+      Cn[i + j * T] = 0.5 * (c - ab);
     }
     __syncthreads();
   }
@@ -1411,8 +1564,7 @@ __global__ __launch_bounds__(STHR) void sw_adv_prep(Dev d, int axis, int sd0) {
   const int t = d.tdim[s];
   extern __shared__ double lds[];
   __shared__ SmallScratch sc;
-  if (t <= 64) adv_prep_body<2, 1>(d, s, axis, t, lds, sc);
-  else adv_prep_body<4, 2>(d, s, axis, t, lds, sc);
+  adv_prep_body(d, s, axis, t, lds, sc);
 }
 
 // S-step (eq. advx_evolS, integrated with the opposite sign) and the L-step
@@ -1681,6 +1833,15 @@ void w_allow(const void* fn) {
 int w_dim_cap(const Dev& d, int which) { return which == DIM_M0 ? d.MA : (which == DIM_T ? d.T : d.R); }
 
 size_t ring_bytes_max() { return sizeof(double) * ring_lds_doubles<3, 0, false>(); }
+
+// every small kernel's dynamic LDS plus its static scratch fits the 160 KB
+// of a compute unit
+constexpr size_t LDS_CU = 160 * 1024;
+constexpr size_t AUG_LDS = sizeof(double) * (size_t)WCAP_A * (WCAP_A + 1) / 2;
+static_assert(sizeof(double) * ring_lds_doubles<3, 0, false>() <= AUG_LDS, "ring buffer of the augmentation SVD");
+static_assert(AUG_LDS + sizeof(SmallScratch) <= LDS_CU, "LDS of sw_aug_svd");
+static_assert(sizeof(double) * ring_lds_doubles<2, 2, true>() + sizeof(SmallScratch) <= LDS_CU, "LDS of sw_trunc");
+static_assert(sizeof(double) * (size_t)WLD * WCAP_T + sizeof(SmallScratch) <= LDS_CU, "LDS of sw_chol/adv_prep");
 }  // namespace
 
 void launch_w_gemm(const Dev& d, int axis, int sd0, int nsd, const void* X, bool x64, int64_t xsd, int rows,
@@ -1758,10 +1919,10 @@ void launch_w_xgram(const Dev& d, int axis, int sd0, int nsd, XJobs jobs, bool c
 }
 
 void launch_w_chol(const Dev& d, int axis, int sd0, int nsd, int ndim, int rows, int ngp, int acc_mode,
-                   double bscale, int oRinv, int oRacc, int ld, hipStream_t st) {
+                   double bscale, int oRinv, int oRacc, int ld, bool near, hipStream_t st) {
   const size_t lds = sizeof(double) * (size_t)WLD * WCAP_T;
   hipLaunchKernelGGL(sw_chol, dim3(nsd), dim3(STHR), lds, st, d, axis, sd0, ndim, rows, ngp, acc_mode, bscale,
-                     oRinv, oRacc, ld);
+                     oRinv, oRacc, ld, near ? 1 : 0);
 }
 
 void launch_w_aug_svd(const Dev& d, int axis, int sd0, int nsd, hipStream_t st) {
@@ -1770,7 +1931,7 @@ void launch_w_aug_svd(const Dev& d, int axis, int sd0, int nsd, hipStream_t st) 
 }
 
 void launch_w_adv_prep(const Dev& d, int axis, int sd0, int nsd, hipStream_t st) {
-  const size_t lds = std::max(sizeof(double) * (size_t)WLD * WCAP_T, ring_bytes_max());
+  const size_t lds = sizeof(double) * (size_t)WLD * WCAP_T;
   hipLaunchKernelGGL(sw_adv_prep, dim3(nsd), dim3(STHR), lds, st, d, axis, sd0);
 }
 
