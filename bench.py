@@ -253,8 +253,20 @@ def main():
     print(f"[bench] workload {args.config}: {wl.nx}x{wl.ny} cells, {wl.px}x{wl.py} subdomains, M={wl.M}, "
           f"rank cap {wl.r_max}, steps {args.warmup}+{steps}, mode {args.mode}, precision {args.precision}",
           file=sys.stderr, flush=True)
+    tiling = args.wg_per_subdomain
+    if not tiling and not args.no_autotune and wl.rank_mode == wk.RANK_ADAPTIVE:
+        # adaptive ranks grow over the run: tune the tiling on the state half
+        # way through the timed steps (a separate engine, advanced untimed)
+        tune_at = args.warmup + steps // 2
+        print(f"[bench] autotune on the state after {tune_at} steps", file=sys.stderr, flush=True)
+        te = pkg.DDDLRA(wl, exec_mode=pkg.DD_EXEC_BATCHED_GRAPH, precision=names[args.precision])
+        te.step(tune_at)
+        tiling, tune_ms = te.autotune(3)
+        te.close()
+        print(f"[bench] autotune: {tiling} workgroups per subdomain ({tune_ms:.3f} ms/step there)",
+              file=sys.stderr, flush=True)
     eng, ms_per_step, updates, ranks, wall, wg_choice, tune_ms = run_timed(
-        pkg, wl, mode, names[args.precision], args.warmup, steps, args.wg_per_subdomain, not args.no_autotune)
+        pkg, wl, mode, names[args.precision], args.warmup, steps, tiling, not args.no_autotune)
     r_end, tmax, clamps = eng.ranks()
     print(f"[bench] timed {steps} steps: {ms_per_step:.3f} ms/step (wall {wall:.2f} s), "
           f"wg/subdomain {wg_choice}, final ranks {int(r_end.min())}..{int(r_end.max())}",
