@@ -142,6 +142,20 @@ dd_status dd_dlra_get_factors(dd_dlra_handle h, int32_t sd, int32_t cap, int32_t
  * on the handle's stream; otherwise host memory (the call synchronises). */
 dd_status dd_dlra_moments(dd_dlra_handle h, double* rho, double* jx, double* jy, int32_t dst_is_device);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * moments as dd_dlra_moments with device destinations, computed without any
+ * allocation and without staging on the handle's grid buffer.  The
+ * per-subdomain moment vectors (S (V^T (w Omega_m))) go to a static device
+ * array of the library (1024 subdomains x 3 moments x 64 ranks, 1.5 MiB per
+ * GPU, held until the process ends); handles with more than 1024
+ * subdomains get DD_EINVAL.  rho (and jx, jy, both or neither) are device
+ * pointers of nx*ny doubles, written asynchronously on the handle's stream;
+ * results are identical to dd_dlra_moments.  All calls on one GPU share the
+ * static array: calls that overlap on one GPU (other streams or threads)
+ * race and must be serialised by the caller.  Calls no hipMalloc/hipFree. */
+dd_status dd_dlra_moments_noalloc(dd_dlra_handle h, double* rho, double* jx, double* jy);
+
 /* Replace the factors of every subdomain (same layouts as dd_dlra_create);
  * used for checkpoint/restart.  Synchronises. */
 dd_status dd_dlra_set_factors(dd_dlra_handle h, const int32_t* rank,

@@ -20,7 +20,7 @@ DD_EXEC_PER_SUBDOMAIN, DD_EXEC_BATCHED, DD_EXEC_BATCHED_GRAPH = 0, 1, 2
 
 EXPORTS = (
     "dd_dlra_workspace_size", "dd_dlra_create", "dd_dlra_step", "dd_dlra_stage", "dd_dlra_get_ranks",
-    "dd_dlra_get_factors", "dd_dlra_moments", "dd_dlra_set_factors", "dd_dlra_force_ranks", "dd_dlra_autotune",
+    "dd_dlra_get_factors", "dd_dlra_moments", "dd_dlra_moments_noalloc", "dd_dlra_set_factors", "dd_dlra_force_ranks", "dd_dlra_autotune",
     "dd_dlra_set_tiling",
     "dd_dlra_profile", "dd_dlra_kernel_stats", "dd_dlra_kernel_name",
     "dd_dlra_sync", "dd_dlra_destroy", "dd_dlra_last_error",
@@ -79,6 +79,7 @@ def load_library():
     lib.dd_dlra_get_ranks.argtypes = [vp, _IP, _IP, ctypes.POINTER(ctypes.c_int64)]
     lib.dd_dlra_get_factors.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, _IP, _DP, _DP, _DP]
     lib.dd_dlra_moments.argtypes = [vp, _DP, _DP, _DP, ctypes.c_int32]
+    lib.dd_dlra_moments_noalloc.argtypes = [vp, _DP, _DP, _DP]
     lib.dd_dlra_autotune.argtypes = [vp, ctypes.c_int32, _IP, _DP]
     lib.dd_dlra_set_tiling.argtypes = [vp, ctypes.c_int32]
     lib.dd_dlra_set_factors.argtypes = [vp, _IP, ctypes.POINTER(_DP), ctypes.POINTER(_DP), ctypes.POINTER(_DP)]
@@ -238,6 +239,14 @@ class DDDLRA:
             return out
         rho = np.zeros(self.nx * self.ny)
         self._check(self.lib.dd_dlra_moments(self.h, _dp(rho), None, None, 0))
+        return rho
+
+    def moments_noalloc(self, rho, jx=None, jy=None):
+        """Moments into device buffers (CUDA tensors of nx*ny doubles) without
+        any device allocation (the library's static scratch).  Asynchronous on
+        the engine's stream."""
+        p = lambda t: None if t is None else ctypes.cast(t.data_ptr(), _DP)
+        self._check(self.lib.dd_dlra_moments_noalloc(self.h, p(rho), p(jx), p(jy)))
         return rho
 
     def autotune(self, steps: int = 2) -> Tuple[int, float]:

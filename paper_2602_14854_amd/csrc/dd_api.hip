@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -41,7 +42,45 @@ struct dd_dlra_s {
   std::vector<Pending> pending;
   std::vector<int64_t> k_launch;
   std::vector<double> k_ms;
+  double* noalloc_scratch = nullptr;  // device address of the static scratch on the handle's device
 };
+
+// Device scratch of dd_dlra_moments_noalloc: the per-subdomain moment
+// vectors (up to 1024 subdomains x 3 moments x 64 ranks, 1.5 MiB), a
+// file-scope array that each GPU the library runs on holds until the process
+// ends.  Host code uses the per-device address from hipGetSymbolAddress,
+// never the array's name (a host-side stand-in).
+constexpr int NOALLOC_MAX_SUB = 1024;
+constexpr size_t NOALLOC_DOUBLES = (size_t)NOALLOC_MAX_SUB * 3 * 64;
+static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+double* g_scratch_ptr[MAX_DEVICES] = {};
+std::once_flag g_scratch_once[MAX_DEVICES];
+hipError_t g_scratch_err[MAX_DEVICES] = {};
+
+// the device address of `scratch` on the current device (looked up once per
+// device, with that device current); nullptr if the lookup failed
+double* scratch_on_current_device(hipError_t* err) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess || dev < 0 || dev >= MAX_DEVICES) {
+    *err = e != hipSuccess ? e : hipErrorInvalidDevice;
+    return nullptr;
+  }
+  std::call_once(g_scratch_once[dev], [dev]() {
+    void* p = nullptr;
+    const hipError_t r = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    g_scratch_err[dev] = r;
+    g_scratch_ptr[dev] = r == hipSuccess ? (double*)p : nullptr;
+  });
+  *err = g_scratch_err[dev];
+  return g_scratch_ptr[dev];
+}
+
+}  // namespace
 
 namespace {
 
@@ -833,8 +872,15 @@ dd_status dd_dlra_create(const dd_dlra_config* cfg, const int32_t* rank0, const 
     dd::init_wide_kernels();
     kernels_ready = true;
   }
+  hipError_t serr = hipSuccess;
+  double* sptr = scratch_on_current_device(&serr);
+  if (!sptr) {
+    g_err = std::string("hipGetSymbolAddress of the static scratch failed: ") + hipGetErrorString(serr);
+    return DD_EHIP;
+  }
   dd_dlra_handle h = new dd_dlra_s();
   h->cfg = *cfg;
+  h->noalloc_scratch = sptr;
   h->cfg.omega_x = h->cfg.omega_y = h->cfg.w = nullptr;
   h->cfg.sigma_s = h->cfg.sigma_a = h->cfg.Q = nullptr;
   auto fail = [&](dd_status st) {
@@ -1198,6 +1244,28 @@ dd_status dd_dlra_moments(dd_dlra_handle h, double* rho, double* jx, double* jy,
   if (dst_is_device) return DD_OK;
   HIPCHK(hipStreamSynchronize(h->stream));
   return check_flags(h);
+}
+
+dd_status dd_dlra_moments_noalloc(dd_dlra_handle h, double* rho, double* jx, double* jy) {
+  if (!h) return DD_EINVAL;
+  if (!rho) {
+    h->err = "rho is NULL";
+    return DD_EINVAL;
+  }
+  if ((jx == nullptr) != (jy == nullptr)) {
+    h->err = "jx and jy must both be given or both be NULL";
+    return DD_EINVAL;
+  }
+  const Dev& d = h->d;
+  if (d.nsub > NOALLOC_MAX_SUB) {
+    h->err = "dd_dlra_moments_noalloc: " + std::to_string(d.nsub) + " subdomains need more than the " +
+             std::to_string(NOALLOC_DOUBLES * sizeof(double)) + "-byte static scratch (at most " +
+             std::to_string(NOALLOC_MAX_SUB) + " subdomains)";
+    return DD_EINVAL;
+  }
+  dd::launch_moments_twopass(d, jx ? 3 : 1, h->noalloc_scratch, rho, jx, jy, h->stream);
+  HIPCHK(hipGetLastError());
+  return DD_OK;
 }
 
 dd_status dd_dlra_set_factors(dd_dlra_handle h, const int32_t* rank, const double* const* U, const double* const* S,

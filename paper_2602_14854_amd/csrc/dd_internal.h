@@ -165,6 +165,10 @@ void launch_coll_kstep(const Dev& d, int sd0, int nsd, hipStream_t st);
 void launch_coll_reduce(const Dev& d, int sd0, int nsd, hipStream_t st);
 void launch_coll_lstep(const Dev& d, int sd0, int nsd, hipStream_t st);
 void launch_moments(const Dev& d, int nmom, hipStream_t st);
+// moments with the per-subdomain vectors in smv (nsub x 3 x 64 doubles of
+// device memory) and the cells written straight to rho, jx, jy (device)
+void launch_moments_twopass(const Dev& d, int nmom, double* smv, double* rho, double* jx, double* jy,
+                            hipStream_t st);
 // small (one workgroup per subdomain) kernels
 void launch_aug_svd(const Dev& d, int axis, int sd0, int nsd, hipStream_t st);
 void launch_chol(const Dev& d, int axis, int sd0, int nsd, int ndim, int rows, int ngp, bool shift,

@@ -1103,6 +1103,59 @@ __global__ __launch_bounds__(NTHR) void k_moments(Dev d, int nmom) {
   }
 }
 
+// The same moments in two launches with the per-subdomain vectors in a
+// caller-provided buffer (no staging on the global grid): k_moments_vec
+// forms smv[s][m][a] = (S (V^T (w Omega_m)))_a, k_moments_apply writes the
+// moments of every cell straight to the destinations.  The arithmetic (and
+// its order) is that of k_moments, so the results are identical.
+__global__ __launch_bounds__(NTHR) void k_moments_vec(Dev d, int nmom, double* smv_out) {
+  const int s = blockIdx.x;
+  const int r = d.rank[s];
+  const int M = d.M, R = d.R;
+  constexpr int MV = 64;
+  __shared__ double mv[3 * MV];
+  const double* Vs = d.V + (int64_t)s * M * R;
+  for (int idx = threadIdx.x; idx < nmom * r; idx += NTHR) {
+    const int a = idx % r, m = idx / r;
+    const double* om = m == 1 ? d.omx : d.omy;
+    double acc = 0.0;
+    for (int q = 0; q < M; ++q) {
+      const double wq = m == 0 ? d.w[q] : d.w[q] * om[q];
+      acc = fma(Vs[(int64_t)a * M + q], wq, acc);
+    }
+    mv[m * MV + a] = acc;
+  }
+  __syncthreads();
+  const double* Sg = d.S + (int64_t)s * R * R;
+  for (int idx = threadIdx.x; idx < nmom * r; idx += NTHR) {
+    const int a = idx % r, m = idx / r;
+    double acc = 0.0;
+    for (int b = 0; b < r; ++b) acc = fma(Sg[a + b * R], mv[m * MV + b], acc);
+    smv_out[((int64_t)s * 3 + m) * MV + a] = acc;
+  }
+}
+
+__global__ __launch_bounds__(NTHR) void k_moments_apply(Dev d, int nmom, const double* smv, double* rho, double* jx,
+                                                        double* jy) {
+  const int s = blockIdx.y;
+  const int r = d.rank[s];
+  const int N = d.N, R = d.R;
+  constexpr int MV = 64;
+  const double* Us = d.U + (int64_t)s * N * R;
+  const double* sv = smv + (int64_t)s * 3 * MV;
+  const int sx = s % d.px, sy = s / d.px;
+  double* dst[3] = {rho, jx, jy};
+  for (int p = blockIdx.x * NTHR + threadIdx.x; p < N; p += gridDim.x * NTHR) {
+    const int ix = p % d.lnx, iy = p / d.lnx;
+    const int64_t g = (int64_t)(sy * d.lny + iy) * d.nx + sx * d.lnx + ix;
+    for (int m = 0; m < nmom; ++m) {
+      double acc = 0.0;
+      for (int a = 0; a < r; ++a) acc = fma(Us[(int64_t)a * N + p], sv[m * MV + a], acc);
+      dst[m][g] = acc;
+    }
+  }
+}
+
 // ============================================================================
 // Host-side launchers: pick the template instance from the precision mode and
 // the capacities.
@@ -1326,6 +1379,13 @@ void launch_coll_lstep(const Dev& d, int sd0, int nsd, hipStream_t st) {
       });
     });
   });
+}
+
+void launch_moments_twopass(const Dev& d, int nmom, double* smv, double* rho, double* jx, double* jy,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(k_moments_vec, dim3(d.nsub), dim3(NTHR), 0, st, d, nmom, smv);
+  const int nb = (d.N + NTHR - 1) / NTHR;
+  hipLaunchKernelGGL(k_moments_apply, dim3(nb < 16 ? nb : 16, d.nsub), dim3(NTHR), 0, st, d, nmom, smv, rho, jx, jy);
 }
 
 void launch_moments(const Dev& d, int nmom, hipStream_t st) {
