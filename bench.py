@@ -11,7 +11,9 @@ The timed region is steps W+1 .. W+K of that configured run from its
 specified initial condition (default W = 5, K = 495: the rest of the run),
 with the stored ranks read after every step (a synchronisation per step
 inside the timed region, which only adds time) so that the rank-weighted
-update count is exact.  Prints one JSON line.
+update count is exact.  The per-kernel figures (roofline of the dominant
+kernel, kernel shares) come from a replay of the same steps with each
+phase between hipEvent pairs.  Prints one JSON line.
 
   python bench.py [--steps K] [--warmup W] [--config C5] [--mode graph] [--precision fp64]
 """
@@ -117,18 +119,35 @@ def algorithmic_cost(wl, ranks, tdim, work_bytes=8.0):
     return c
 
 
+def kernel_source_hash():
+    """First 16 hex digits of the SHA-256 of the HIP sources (csrc/*.hip and
+    *.h in name order): counter figures taken on other sources are stale."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2602_14854_amd", "csrc")
+    for path in sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.h"))):
+        with open(path, "rb") as f:
+            h.update(os.path.basename(path).encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
 def measured_value(tag, kernel, workload, precision, field):
     """A counter figure of `kernel` from the summaries committed under
-    profiles/ (lines '<tag> kernel=.. workload=.. precision=.. <field>=..'),
-    or None."""
+    profiles/ (lines '<tag> kernel=.. workload=.. precision=.. <field>=..
+    source=<kernel_source_hash()>'), or None when there is none for the
+    current kernel sources."""
     import glob
     import re
-    pat = re.compile(r"\s*" + tag + r" kernel=(.+?) workload=(\S+) precision=(\S+) " + field + r"=(\S+)")
+    pat = re.compile(r"\s*" + tag + r" kernel=(.+?) workload=(\S+) precision=(\S+) " + field +
+                     r"=(\S+) source=(\S+)")
+    src = kernel_source_hash()
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         with open(path) as f:
             for line in f:
                 mm = pat.match(line)
-                if mm and mm.group(1) == kernel and mm.group(2) == workload and mm.group(3) == precision:
+                if (mm and mm.group(1) == kernel and mm.group(2) == workload and mm.group(3) == precision
+                        and mm.group(5) == src):
                     return float(mm.group(4))
     return None
 
@@ -222,9 +241,6 @@ def main():
     ap.add_argument("--config", default="C5")
     ap.add_argument("--mode", default="graph", choices=["graph", "batched", "per-subdomain"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"])
-    ap.add_argument("--profile-steps", type=int, default=1)
-    ap.add_argument("--profile-repeat", type=int, default=5,
-                    help="repetitions (replayed as one graph) per timed tall-skinny phase")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision-compare", action="store_true")
     ap.add_argument("--no-per-subdomain", action="store_true")
@@ -233,7 +249,7 @@ def main():
                     help="fix the tall-skinny workgroups per subdomain instead of autotuning")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the path would shard by blocks of subdomains with a halo exchange of low-rank traces)",
               file=sys.stderr)
         sys.exit(2)
@@ -272,23 +288,45 @@ def main():
           f"wg/subdomain {wg_choice}, final ranks {int(r_end.min())}..{int(r_end.max())}",
           file=sys.stderr, flush=True)
 
-    # per-kernel timing at the final state: the same kernels, launched phase
-    # by phase with hipEvent pairs on the engine's stream
-    eng.profile(max(1, args.profile_repeat))
-    for _ in range(args.profile_steps):
-        for st in (0, 1, 2):
-            eng.stage(st)
-    stats = eng.kernel_stats()
-    eng.profile(False)
-    r_prof, t_prof, _ = eng.ranks()
     eng.close()
-    prof_total = sum(ms for _, ms in stats.values())
-    kern = {k: {"launches": n, "avg_us": 1e3 * ms / max(n, 1), "share": ms / prof_total}
-            for k, (n, ms) in stats.items() if n > 0}
+
+    # per-kernel timing over the timed region: the same steps replayed from
+    # the same initial condition (the state sequence is deterministic), each
+    # phase launched on its own between hipEvent pairs on the engine's stream
+    # (the timed run launches one graph per step, which hides the kernels);
+    # the algorithmic cost of every launch from the ranks at the start of its
+    # step (stored ranks) and the largest intermediate ranks reached so far
+    print(f"[bench] per-kernel replay of steps {args.warmup + 1}..{args.warmup + steps}", file=sys.stderr,
+          flush=True)
     wbytes = 8.0 if args.precision == "fp64" else 4.0
-    # intermediate ranks of the profiled stages: the largest t each subdomain
-    # reached (an upper bound for the x and y stages alike)
-    costs = algorithmic_cost(wl, r_prof, t_prof, wbytes)
+    pe = pkg.DDDLRA(wl, exec_mode=mode, precision=names[args.precision])
+    if wg_choice:
+        pe.set_tiling(wg_choice)
+    pe.step(args.warmup)
+    pe.profile(1)
+    prev = pe.kernel_stats()
+    cost_sum = {}
+    for _ in range(steps):
+        r0, _, _ = pe.ranks()
+        for st in (0, 1, 2):
+            pe.stage(st)
+        cur = pe.kernel_stats()
+        _, t1, _ = pe.ranks()
+        c_step = algorithmic_cost(wl, r0, t1, wbytes)
+        for k, (n, _) in cur.items():
+            dn = n - prev.get(k, (0, 0.0))[0]
+            if dn and k in c_step:
+                b, f = cost_sum.get(k, (0.0, 0.0))
+                cost_sum[k] = (b + dn * c_step[k][0], f + dn * c_step[k][1])
+        prev = cur
+    pe.profile(False)
+    pe.close()
+    stats = prev
+    prof_total = sum(ms for _, ms in stats.values())
+    kern = {k: {"launches": n, "avg_us": 1e3 * ms / max(n, 1), "share": ms / prof_total, "ms": ms}
+            for k, (n, ms) in stats.items() if n > 0}
+    # per-launch algorithmic cost averaged over the replayed launches
+    costs = {k: (b / kern[k]["launches"], f / kern[k]["launches"]) for k, (b, f) in cost_sum.items()}
     peak_tf = MFMA_PEAK_TFLOPS[args.precision]
 
     def roofline(k):
@@ -319,10 +357,8 @@ def main():
     dom_ts = max(ts_known, key=lambda k: kern[k]["share"])
     small_share = sum(v["share"] for k, v in kern.items() if k.startswith(SMALL))
     # step-level algorithmic bytes over the step time (tall-skinny kernels)
-    step_bytes = 0.0
-    for k in ts_known:
-        step_bytes += costs[k][0] * kern[k]["launches"] / max(1, args.profile_steps)
-    prof_step_ms = prof_total / max(1, args.profile_steps)
+    step_bytes = sum(cost_sum[k][0] for k in ts_known) / steps
+    prof_step_ms = prof_total / steps
 
     out = {
         "metric": "subdomain-cell·angle·rank updates/s per step",
