@@ -210,20 +210,22 @@ def test_one_cell_wide_subdomains():
     assert dd.state_rel_error(got, ref, prob) < STRICT
 
 
-@pytest.mark.parametrize("lo,bound", [(-6, STRICT), (-9, 1e-6)])
+@pytest.mark.parametrize("lo,bound", [(-6, STRICT), (-9, 1e-8)])
 def test_graded_factors(lo, bound):
     """Singular values of S from 1 down to 10^lo, S a full (rotated) matrix.
     Down to 1e-6 the step matches the oracle to the FP64 bar.  Below, the
-    first stage from such a state agrees only to about u cond(A) times the
-    coupling of the K-step (4e-9 at 1e-9; later stages, from the diagonal S
-    that truncation leaves, agree to 1e-15): the augmented basis is formed
-    as A (U Sigma^-1) from the small SVD, and the rounding of that product
-    is not confined to range(A), so the weakest basis direction is off by
-    about u cond(A) -- a NumPy replay of the same route against the oracle
-    reproduces 3.8e-9, while the oracle itself (LAPACK, orthogonal
-    transformations) moves by less than 1e-13 under a 1e-15 input
-    perturbation or a change of SVD driver.  The second case holds that
-    measured level."""
+    first stage from such a state agrees to about u cond(A) times the
+    coupling of the K-step (4e-9 to 8e-9 at 1e-9; later stages, from the
+    diagonal S that truncation leaves, agree to 1e-15).  The limit is the
+    Cholesky QR of the augmentation matrix: it works on the Gram A^T A, in
+    which a direction of relative size 1e-9 sits at 1e-18, below the FP64
+    rounding of the strong ones, so the weakest basis direction carries an
+    error of about u cond(A) whichever way V-hat is then formed (from A and
+    the small SVD, or from the orthonormal factor and the accumulated
+    rotations, which measured 8.1e-9 here).  The oracle (LAPACK, orthogonal
+    transformations on A itself) moves by less than 1e-13 under a 1e-15
+    input perturbation.  The second case holds the measured level; a
+    Householder (TSQR) factorisation of A would be needed to close it."""
     wl = small_case(seed=21, px=2, py=2, lnx=8, lny=6, dirs=wk.product_directions(6, 6), ranks=[6] * 4,
                     sig=np.logspace(0, lo, 6))
     say(f"case: 2x2 of 8x6, ranks 6, singular values 1 .. 1e{lo}")
@@ -232,7 +234,9 @@ def test_graded_factors(lo, bound):
     e.step(2)
     got = e.state()
     e.close()
-    assert dd.state_rel_error(got, ref, prob) < bound
+    err = dd.state_rel_error(got, ref, prob)
+    say(f"  state err {err:.3e}")
+    assert err < bound
 
 
 def test_maximum_capacity():
@@ -402,7 +406,8 @@ def test_uneven_adaptive_ranks_at_full_size():
     (sigma_min / sigma_max about 1e-18 in the oracle), so the basis
     completion is arbitrary and the stage result is not unique (the oracle
     differs from itself at the 1e-5 level under a reordering of its
-    augmentation columns); the flux is held to 20 times that spread."""
+    augmentation columns); the flux is held to 3 times that spread (measured
+    1.5 to 1.9 times)."""
     wl = _c4_at_capacity()
     say("case: 512x512 cells, 8x8 subdomains of 64x64, M=1024, adaptive tol 1e-4, ranks 2..21, x stage")
     prob = dd.Problem(wl)
@@ -418,7 +423,7 @@ def test_uneven_adaptive_ranks_at_full_size():
     assert list(r) == [S.shape[0] for _, S, _ in ref]
     err = rho_err(rho, dd.moments(ref, prob))
     say(f"  ranks {min(r)}..{max(r)}, t {min(tmax)}..{max(tmax)}: flux err {err:.3e}, oracle spread {spread:.3e}")
-    assert err <= max(STRICT, 20.0 * spread)
+    assert err <= max(STRICT, 3.0 * spread)
 
 
 @pytest.mark.parametrize("name,nsteps,prec", [("C2", 200, "fp64"), ("C3", 200, "fp64"), ("C3", 200, "fp32"),
@@ -561,6 +566,10 @@ def _oracle_spread(wl, nsteps, advance=None):
 
 @pytest.mark.parametrize("name,nsteps", [("C1", 2), ("C2", 2)])
 def test_raw_workloads_within_oracle_spread(name, nsteps):
+    """The raw lattice (C1) and Gaussian (C2) configurations as specified:
+    their singular values reach the 1e-8 noise level, where the oracle
+    itself moves under an equivalent reordering; the FP64 path stays within
+    3 times that spread (measured 0.6 and 1.0 times)."""
     wl = wk.make_workload(name)
     say(f"case: raw {name}, {nsteps} steps vs oracle spread")
     ref, prob, spread = _oracle_spread(wl, nsteps)
@@ -570,7 +579,7 @@ def test_raw_workloads_within_oracle_spread(name, nsteps):
     e.close()
     err = rho_err(rho, dd.moments(ref, prob))
     say(f"  {name}: gpu-vs-oracle {err:.3e}, oracle spread {spread:.3e}")
-    assert err <= max(STRICT, 20.0 * spread)
+    assert err <= max(STRICT, 3.0 * spread)
 
 
 # ----------------------------------------------------------------------------
@@ -611,40 +620,38 @@ def test_mixed_precision_scalar_flux(name, nsteps, prec):
     assert err < MIXED
 
 
-def _fp32_sensitivity(wl, nsteps, rho_ref):
-    """Scalar-flux distance between the FP64 oracle and the same oracle with
-    the arrays that the mixed modes keep in FP32 rounded to FP32: the K- and
-    L-step results before every QR, and V-hat.  It is the size of change
-    that FP32 storage of the working arrays alone causes."""
-    f_sp, f_ang, f_aug = dd.qr_spatial, dd.qr_angular, dd.augment
-    f32 = lambda x: x.astype(np.float32).astype(np.float64)
-
-    def aug(*a, **k):
-        K, Vh, t, sig, cl = f_aug(*a, **k)
-        return K, f32(Vh), t, sig, cl
-
-    try:
-        dd.qr_spatial = lambda K, prob: f_sp(f32(K), prob)
-        dd.qr_angular = lambda L, prob: f_ang(f32(L), prob)
-        dd.augment = aug
-        st, prob = oracle_steps(wl, nsteps)
-    finally:
-        dd.qr_spatial, dd.qr_angular, dd.augment = f_sp, f_ang, f_aug
-    return rho_err(dd.moments(st, prob), rho_ref)
+# Scalar-flux errors measured for the mixed modes where a raw configuration
+# misses the bar; the bar itself is not widened.
+_MIXED_MISSES = {
+    ("C1", "fp32"): "measured 2.05e-2 after 10 steps",
+    ("C1", "bf16"): "measured 1.57e-2 after 10 steps",
+    ("C2", "bf16"): "measured 1.10e-4 after 2 steps",
+    ("C3", "bf16"): "measured 1.24e-4 after 2 steps",
+}
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
-@pytest.mark.parametrize("name,nsteps", [("C1", 10), ("C2", 2)])
-def test_mixed_precision_raw_within_fp32_sensitivity(name, nsteps, prec):
-    """The raw workloads carry singular values ~1e-8 (C1) of the largest, so
-    the QR of K1 amplifies any FP32 rounding by that condition number; the
-    bar is the oracle's own change under FP32 rounding of K1 and L1."""
+@pytest.mark.parametrize("name,nsteps", [("C1", 10), ("C2", 2), ("C3", 2)])
+def test_mixed_precision_raw_at_the_bar(name, nsteps, prec, request):
+    """Mixed precision on the raw configurations as specified, against the
+    FP64 oracle: the scalar flux within max(1e-4, 1.1 e64), e64 being the FP64
+    GPU path's own distance from the oracle on the same steps (the equal-
+    accuracy rule).  The raw lattice and Gaussian inputs carry singular
+    values near 1e-8 of the largest, which the QR of K1 amplifies; cases
+    known to miss are expected failures with the measured error."""
+    if (name, prec) in _MIXED_MISSES:
+        request.applymarker(pytest.mark.xfail(reason=f"raw {name} {prec}: {_MIXED_MISSES[(name, prec)]}",
+                                              strict=False))
     wl, rho_ref = _oracle_cached(name, nsteps)
-    key = (name, nsteps, "fp32sens")
+    key = (name, nsteps, "gpu64")
     if key not in _ORACLE_CACHE:
-        _ORACLE_CACHE[key] = _fp32_sensitivity(wl, nsteps, rho_ref)
-    sens = _ORACLE_CACHE[key]
+        e = engine(wl)
+        e.step(nsteps)
+        _ORACLE_CACHE[key] = rho_err(e.moments(), rho_ref)
+        e.close()
+    e64 = _ORACLE_CACHE[key]
     say(f"case: raw {name}, {nsteps} steps, mixed {prec}")
     err = rho_err(_mixed_run(wl, nsteps, prec), rho_ref)
-    say(f"  {name} mixed {prec}: scalar-flux err {err:.3e}, oracle FP32 sensitivity {sens:.3e}")
-    assert err <= max(MIXED, 10.0 * sens)
+    bar = max(MIXED, 1.1 * e64)
+    say(f"  {name} mixed {prec}: scalar-flux err {err:.3e}, FP64 path {e64:.3e}, bar {bar:.3e}")
+    assert err <= bar
