@@ -65,6 +65,11 @@ enum { DD_PREC_FP64 = 0, DD_PREC_MIXED_FP32 = 1, DD_PREC_MIXED_BF16 = 2 };
 enum { DD_RANK_FIXED = 0, DD_RANK_ADAPTIVE = 1 };
 enum { DD_EXEC_PER_SUBDOMAIN = 0, DD_EXEC_BATCHED = 1, DD_EXEC_BATCHED_GRAPH = 2 };
 enum { DD_BC_VACUUM = 0 };
+/* Substep integrator of every K-, S- and L-step (Algorithms 1-3): one
+ * explicit Euler step of length dt, or one classic four-stage Runge-Kutta
+ * step with the boundary data frozen over the substep (Section 4 runs use
+ * the latter).  RK4 runs in DD_PREC_FP64. */
+enum { DD_INT_EULER = 0, DD_INT_RK4 = 1 };
 
 typedef struct {
   int32_t nx, ny;          /* global cells                                        */
@@ -89,6 +94,7 @@ typedef struct {
   int32_t exec_mode;       /* DD_EXEC_*                                            */
   int32_t bc[4];           /* faces -x, +x, -y, +y: DD_BC_VACUUM only             */
   int32_t strict_caps;     /* 1: a rank clamp latches DD_ERANK; 0: clamp, count   */
+  int32_t integrator;      /* DD_INT_EULER or DD_INT_RK4                           */
 } dd_dlra_config;
 
 /* Device bytes a handle needs for this configuration (state, scratch and

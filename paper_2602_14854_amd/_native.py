@@ -17,6 +17,7 @@ DD_OK, DD_EINVAL, DD_ENOMEM, DD_EHIP, DD_ERANK, DD_ENUMERIC, DD_ESTATE = 0, -1, 
 DD_PREC_FP64, DD_PREC_MIXED_FP32, DD_PREC_MIXED_BF16 = 0, 1, 2
 DD_RANK_FIXED, DD_RANK_ADAPTIVE = 0, 1
 DD_EXEC_PER_SUBDOMAIN, DD_EXEC_BATCHED, DD_EXEC_BATCHED_GRAPH = 0, 1, 2
+DD_INT_EULER, DD_INT_RK4 = 0, 1
 
 EXPORTS = (
     "dd_dlra_workspace_size", "dd_dlra_create", "dd_dlra_step", "dd_dlra_stage", "dd_dlra_get_ranks",
@@ -44,7 +45,7 @@ class Config(ctypes.Structure):
         ("r_max", ctypes.c_int32), ("r_int_max", ctypes.c_int32),
         ("tol", ctypes.c_double), ("tol_aug_rel", ctypes.c_double),
         ("precision", ctypes.c_int32), ("exec_mode", ctypes.c_int32), ("bc", ctypes.c_int32 * 4),
-        ("strict_caps", ctypes.c_int32),
+        ("strict_caps", ctypes.c_int32), ("integrator", ctypes.c_int32),
     ]
 
 
@@ -112,9 +113,9 @@ class _ConfigHolder:
     """Keeps the numpy arrays a Config points to alive."""
 
     def __init__(self, wl, precision: int, exec_mode: int, strict: int):
-        if str(getattr(wl, "integrator", "euler")) != "euler":
-            raise NotImplementedError("the HIP engine advances every substep by one explicit Euler step; "
-                                      "RK4 substeps are not available in it")
+        integ = str(getattr(wl, "integrator", "euler"))
+        if integ not in ("euler", "rk4"):
+            raise ValueError(f"integrator {integ!r}: the engine takes 'euler' or 'rk4'")
         self.ox = _f64(wl.omega_x)
         self.oy = _f64(wl.omega_y)
         self.w = _f64(wl.w)
@@ -136,6 +137,7 @@ class _ConfigHolder:
         c.precision, c.exec_mode = int(precision), int(exec_mode)
         c.bc[:] = [0, 0, 0, 0]
         c.strict_caps = int(strict)
+        c.integrator = DD_INT_RK4 if integ == "rk4" else DD_INT_EULER
         self.cfg = c
 
 

@@ -92,7 +92,7 @@ enum Kind {
   K_GEMM_FINAL_U, K_GEMM_FINAL_V, K_COLL_PREP, K_COLL_KSTEP, K_COLL_REDUCE, K_COLL_SSTEP,
   K_COLL_LSTEP, K_GEMM_QR_KC, K_GEMM_QR_LC, K_GEMM_QR_K_IP, K_GEMM_QR_L_IP, K_GEMM_QR_KC_IP, K_GEMM_QR_LC_IP,
   K_W_GRAM_A, K_W_GRAM_VHAT, K_W_ANG, K_W_GRAM_K, K_W_SPATIAL, K_W_GRAM_L, K_W_GRAM_KC, K_W_COLL_REDUCE,
-  K_W_CHOL,
+  K_W_CHOL, K_W_RK_PREP, K_GEMM_K0, K_W_RK_KSTEP,
   K_COUNT
 };
 
@@ -105,6 +105,7 @@ const char* const kKindName[K_COUNT] = {
   "k_gemm[QR K1 collision in place]", "k_gemm[QR L1 collision in place]",
   "kw_xgram[Gram A]", "kw_xgram[Gram V-hat]", "kw_xgram[angular]", "kw_xgram[Gram K1]", "kw_xgram[spatial]",
   "kw_xgram[Gram L1]", "kw_xgram[Gram K1 collision]", "kw_xgram[collision]", "sw_chol",
+  "sw_rk_prep", "k_gemm[K0=U*Am]", "kw_rk_kstep",
 };
 
 struct Layout {
@@ -115,6 +116,8 @@ struct Layout {
   size_t bytes;
   // byte offsets of the arena segments
   size_t oU, oV, oS, oA, oZ, oQh, oK1, oK2, oAL, oAL2, oGP, oSM, oRho, oIn, oCs, oCt, oQ, oInt, oFlags;
+  size_t oK3, oGhost;  // RK4 only: the K-step's initial value and the frozen ghost rows
+  int face;            // cells on the longer subdomain face
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -158,6 +161,9 @@ std::string validate(const dd_dlra_config* c) {
   if (c->r_int_max < R) return "r_int_max must be at least the stored-rank capacity";
   if (c->r_int_max > dd::WCAP_T) return "r_int_max beyond the supported maximum of 128";
   if (R > dd::WCAP_R) return "stored-rank capacity beyond the supported maximum of 64";
+  if (c->integrator != DD_INT_EULER && c->integrator != DD_INT_RK4) return "unknown integrator";
+  if (c->integrator == DD_INT_RK4 && c->precision != DD_PREC_FP64)
+    return "RK4 substeps run in DD_PREC_FP64 only";
   if (c->precision < DD_PREC_FP64 || c->precision > DD_PREC_MIXED_BF16) return "unknown precision";
   if (c->exec_mode < DD_EXEC_PER_SUBDOMAIN || c->exec_mode > DD_EXEC_BATCHED_GRAPH) return "unknown exec_mode";
   for (int f = 0; f < 4; ++f)
@@ -173,6 +179,7 @@ bool wide_plan(const dd_dlra_config* c) {
   const int R = c->rank_mode == DD_RANK_FIXED ? c->r_fixed : c->r_max;
   const char* env = getenv("DD_DLRA_PLAN");
   if (env && strcmp(env, "wide") == 0) return true;
+  if (c->integrator == DD_INT_RK4) return true;  // the RK4 substeps exist in the wide kernels
   return c->r_int_max > dd::CAP || 3 * R > dd::CAP;
 }
 
@@ -269,6 +276,12 @@ Layout make_layout(const dd_dlra_config* c) {
   L.oQ = seg(ns * L.N * d8);
   L.oInt = seg(8 * ns * sizeof(int));
   L.oFlags = seg(64);
+  L.face = std::max(c->nx / c->px, c->ny / c->py);
+  L.oK3 = L.oGhost = 0;
+  if (c->integrator == DD_INT_RK4) {
+    L.oK3 = seg(ns * L.N * T * d8);
+    L.oGhost = seg(ns * 2 * (size_t)T * L.face * d8);
+  }
   L.bytes = b;
   return L;
 }
@@ -307,6 +320,10 @@ void fill_dev(Dev& d, const Layout& L, const dd_dlra_config* c, char* base) {
   d.strict = c->strict_caps;
   d.prec = c->precision;
   d.wide = L.wide;
+  d.rk4 = c->integrator == DD_INT_RK4 ? 1 : 0;
+  d.face = L.face;
+  d.K3 = d.rk4 ? (double*)(base + L.oK3) : nullptr;
+  d.ghost = d.rk4 ? (double*)(base + L.oGhost) : nullptr;
   d.tol = c->tol;
   d.tol_aug_rel = c->tol_aug_rel;
   d.U = (double*)(base + L.oU);
@@ -438,7 +455,7 @@ bool repeatable(int kind) {
     case K_SPATIAL_REDUCE: case K_LSTEP: case K_GEMM_QR_L: case K_GEMM_FINAL_U: case K_GEMM_FINAL_V:
     case K_COLL_KSTEP: case K_COLL_REDUCE: case K_COLL_LSTEP: case K_GEMM_QR_KC: case K_GEMM_QR_LC:
     case K_W_GRAM_A: case K_W_GRAM_VHAT: case K_W_ANG: case K_W_GRAM_K: case K_W_SPATIAL: case K_W_GRAM_L:
-    case K_W_GRAM_KC: case K_W_COLL_REDUCE:
+    case K_W_GRAM_KC: case K_W_COLL_REDUCE: case K_W_RK_PREP: case K_GEMM_K0: case K_W_RK_KSTEP:
       return true;
     default:
       return false;
@@ -730,7 +747,25 @@ void enqueue_advection_wide(dd_dlra_handle h, int axis) {
   }
   phase(h, K_ADV_PREP, [&](int s0, int ns) { dd::launch_w_adv_prep(d, axis, s0, ns, st); });
   // Algorithm 1/2 steps 1-2: K-step, QR (three passes: K1 -> K2 -> K1 -> K2)
-  phase(h, K_KSTEP, [&](int s0, int ns) { dd::launch_w_kstep(d, axis, s0, ns, st); });
+  if (d.rk4) {
+    // K0 = U Am and the frozen ghost rows, then the four nested stages
+    // K0 -> K2 -> K1 -> K2 -> K1 (each out = K0 + alpha g(in))
+    phase(h, K_W_RK_PREP, [&](int s0, int ns) { dd::launch_w_rk_prep(d, axis, s0, ns, st); });
+    phase(h, K_GEMM_K0, [&](int s0, int ns) {
+      dd::launch_w_gemm(d, axis, s0, ns, d.U, true, sdNR, d.N, dd::DIM_R, dd::DIM_T, d.oAm, d.R, d.K3, true, sdNT,
+                        nullptr, -1, true, true, st);
+    });
+    const void* ins[4] = {d.K3, d.K2, d.K1, d.K2};
+    void* outs[4] = {d.K2, d.K1, d.K2, d.K1};
+    for (int stg = 0; stg < 4; ++stg) {
+      const double alpha = d.dt / (double)(4 - stg);
+      phase(h, K_W_RK_KSTEP, [&](int s0, int ns) {
+        dd::launch_w_rk_kstep(d, axis, s0, ns, alpha, ins[stg], outs[stg], st);
+      });
+    }
+  } else {
+    phase(h, K_KSTEP, [&](int s0, int ns) { dd::launch_w_kstep(d, axis, s0, ns, st); });
+  }
   void* Q = w_chol_qr(h, axis, dd::DIM_T, d.K1, d.K2, sdNT, d.N, true, 3, true, K_W_GRAM_K, K_GEMM_QR_K);
   // step 3: spatial Galerkin matrix and the face products, S-step
   {

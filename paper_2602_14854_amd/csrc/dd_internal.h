@@ -37,6 +37,8 @@ struct Dev {
   int rank_mode, r_fixed, r_min, r_max, r_int_max, strict;
   int prec;
   int wide;                // 1: the wide launch plan (capacities beyond the narrow kernels)
+  int rk4;                 // 1: every substep is one classic RK4 step (wide plan, FP64)
+  int face;                // cells on the longer subdomain face (ghost rows)
   double tol, tol_aug_rel;
   // state (FP64 in every mode)
   double* U;               // [nsub][R][N]
@@ -59,6 +61,8 @@ struct Dev {
   void* K2;                // [nsub][T][N]
   void* AL;                // [nsub][T][M]
   void* AL2;               // [nsub][T][M]
+  double* K3;              // [nsub][T][N]    RK4: the K-step's initial value K0
+  double* ghost;           // [nsub][2][T][face] RK4: frozen ghost rows (low, high face)
   double* gpart;           // [nsub][gpStride]
   double* small;           // [nsub][smallStride]
   double* rho;             // [3][ny*nx]: rho, jx, jy

@@ -728,6 +728,93 @@ void launch_coll_prep(const Dev& d, int sd0, int nsd, hipStream_t st) {
 //   P = S2^T (I - dt Gt),  crow = dt ((S2 m)^T Gs / W + q^T).
 // All operands are staged in LDS (leading dimension L, the stored-rank
 // capacity: 21, or 64 in the wide plan).
+// The collision S- and L-steps with RK4 substeps (nested form: four stages
+// out = base + alpha f(in), alpha = dt/4, dt/3, dt/2, dt).
+//   S-step: f(S) = -(1/W) Gs S m m^T + Gt S - q m^T, from S1;
+//   L-step: L = V N + 1 y^T stays of that form, with
+//           f(N, y) = (-N Gt, (1/W) Gs N^T m + (Gs - Gt) y + q), from (S2^T, 0);
+// the result gives P = N and Crow = y for the L-step product L1 = V P + 1 Crow^T.
+// Stage buffers of order r: S2 (LDS) and the small workspace slots W1, W2.
+template <int L>
+__device__ void coll_sstep_rk4(const Dev& d, int s, int r, const double* Gs, const double* Gt, const double* S1,
+                               double* S2, const double* qv, const double* mv, double* v1, double* v2, double* v3) {
+  const int T = d.T, R = d.R;
+  const double iW = 1.0 / d.W;
+  double* sm = small_of(d, s);
+  double* Xg = sm + d.oW1;
+  double* Yg = sm + d.oW2;
+  for (int stg = 0; stg < 4; ++stg) {
+    const double al = d.dt / (double)(4 - stg);
+    // Sin = S1 (LDS, ld L) at the first stage, else Xg (ld T)
+    const double* Sin = stg == 0 ? S1 : Xg;
+    const int ldi = stg == 0 ? L : T;
+    for (int i = threadIdx.x; i < r; i += NTHR) {
+      double acc = 0.0;
+      for (int k = 0; k < r; ++k) acc = fma(Sin[i + k * ldi], mv[k], acc);
+      v1[i] = acc;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < r; i += NTHR) {
+      double acc = 0.0;
+      for (int k = 0; k < r; ++k) acc = fma(Gs[i + k * L], v1[k], acc);
+      v2[i] = acc;
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < r * r; idx += NTHR) {
+      const int i = idx % r, j = idx / r;
+      double g = 0.0;
+      for (int k = 0; k < r; ++k) g = fma(Gt[i + k * L], Sin[k + j * ldi], g);
+      S2[i + j * L] = S1[i + j * L] + al * (-iW * v2[i] * mv[j] + g - qv[i] * mv[j]);
+    }
+    __syncthreads();
+    if (stg < 3) {
+      for (int idx = threadIdx.x; idx < r * r; idx += NTHR) {
+        const int i = idx % r, j = idx / r;
+        Xg[i + j * T] = S2[i + j * L];
+      }
+      __syncthreads();
+    }
+  }
+  // L-step: (N, y) from (S2^T, 0); stage inputs in Xg / Yg alternately, y in v3
+  for (int i = threadIdx.x; i < r; i += NTHR) v3[i] = 0.0;
+  __syncthreads();
+  for (int stg = 0; stg < 4; ++stg) {
+    const double al = d.dt / (double)(4 - stg);
+    double* Nout = (stg & 1) ? Yg : Xg;
+    const double* Nin = (stg & 1) ? Xg : Yg;  // unused at the first stage
+    // v1 = N_in^T m, then v2 = y_out
+    for (int j = threadIdx.x; j < r; j += NTHR) {
+      double acc = 0.0;
+      for (int k = 0; k < r; ++k) acc = fma(stg == 0 ? S2[j + k * L] : Nin[k + j * T], mv[k], acc);
+      v1[j] = acc;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < r; i += NTHR) {
+      double a = 0.0, b = 0.0;
+      for (int k = 0; k < r; ++k) {
+        a = fma(Gs[i + k * L], v1[k], a);
+        b = fma(Gs[i + k * L] - Gt[i + k * L], v3[k], b);
+      }
+      v2[i] = al * (iW * a + b + qv[i]);
+    }
+    for (int idx = threadIdx.x; idx < r * r; idx += NTHR) {
+      const int i = idx % r, j = idx / r;
+      double g = 0.0;
+      for (int k = 0; k < r; ++k) g = fma(stg == 0 ? S2[k + i * L] : Nin[i + k * T], Gt[k + j * L], g);
+      Nout[i + j * T] = S2[j + i * L] - al * g;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < r; i += NTHR) v3[i] = v2[i];
+    __syncthreads();
+  }
+  // the last stage (odd) wrote Yg
+  for (int idx = threadIdx.x; idx < r * r; idx += NTHR) {
+    const int i = idx % r, j = idx / r;
+    sm[d.oP0 + i + j * R] = Yg[i + j * T];
+  }
+  for (int j = threadIdx.x; j < r; j += NTHR) sm[d.oCrow + j] = v3[j];
+}
+
 template <int L>
 __global__ __launch_bounds__(NTHR) void s_coll_sstep(Dev d, int sd0) {
   const int s = sd0 + blockIdx.x;
@@ -757,8 +844,12 @@ __global__ __launch_bounds__(NTHR) void s_coll_sstep(Dev d, int sd0) {
     for (int k = 0; k < r; ++k) acc = fma(Gs[i + k * L], v1[k], acc);
     v2[i] = acc;
   }
-  mm(S2, L, Gt, L, false, S1, L, false, r, r, r, 1.0, 0.0);
   const double dt = d.dt, iW = 1.0 / d.W;
+  if (d.rk4) {
+    coll_sstep_rk4<L>(d, s, r, Gs, Gt, S1, S2, qv, mv, v1, v2, v3);
+    return;
+  }
+  mm(S2, L, Gt, L, false, S1, L, false, r, r, r, 1.0, 0.0);
   for (int idx = threadIdx.x; idx < r * r; idx += NTHR) {
     const int i = idx % r, j = idx / r;
     const int o = i + j * L;

@@ -62,6 +62,10 @@ void launch_w_adv_prep(const Dev& d, int axis, int sd0, int nsd, hipStream_t st)
 void launch_w_adv_sstep(const Dev& d, int axis, int sd0, int nsd, hipStream_t st);
 void launch_w_trunc(const Dev& d, int axis, int sd0, int nsd, hipStream_t st);
 void launch_w_coll_prep(const Dev& d, int sd0, int nsd, hipStream_t st);
+// RK4 advection K-step: frozen ghost rows, then out = K0 + alpha g(in)
+void launch_w_rk_prep(const Dev& d, int axis, int sd0, int nsd, hipStream_t st);
+void launch_w_rk_kstep(const Dev& d, int axis, int sd0, int nsd, double alpha, const void* in, void* out,
+                       hipStream_t st);
 void init_wide_kernels();
 
 }  // namespace dd

@@ -320,11 +320,12 @@ __global__ __launch_bounds__(WTHR) void kw_kstep(Dev d, int axis, int sd0) {
 // with one accumulator set per coefficient matrix and the per-direction
 // factors applied to the accumulators (each lane's accumulators belong to
 // its own direction).
-template <class S, int P>
+template <class S, int P, int NM, int NCB>
 __global__ __launch_bounds__(WTHR) void kw_lstep(Dev d, int axis, int sd0) {
   using F = typename Prec<P>::F;
   using Acc = typename Prec<P>::Acc;
-  constexpr int NCB = 2, NG = WCAP_T / 64;
+  static_assert(NM == 3 || NM == 9, "Euler (P0, Pm, Pp) or RK4 (P0, N1..N4 of each class)");
+  constexpr int NG = WCAP_T / 64;
   constexpr int gstride = 16 * NCB * 64;         // one group of one matrix
   const int s = sd0 + blockIdx.y;
   const int t = d.tdim[s];
@@ -339,8 +340,19 @@ __global__ __launch_bounds__(WTHR) void kw_lstep(Dev d, int axis, int sd0) {
   F* Pf = reinterpret_cast<F*>(lds);  // [m][g] groups
   {
     const double* sm = small_of(d, s);
-    const int offs[3] = {d.oP0, d.oPm, d.oPp};
-    const int total = 3 * NG * gstride;
+    int offs[NM];
+    offs[0] = d.oP0;
+    if (NM == 3) {
+      offs[1] = d.oPm;
+      offs[2] = d.oPp;
+    } else {
+      const int op[4] = {d.oPm, d.oW1, d.oW3, d.oW5}, on[4] = {d.oPp, d.oW2, d.oW4, d.oW6};
+      for (int j = 0; j < 4; ++j) {
+        offs[1 + j] = op[j];
+        offs[5 + j] = on[j];
+      }
+    }
+    const int total = NM * NG * gstride;
     for (int idx = threadIdx.x; idx < total; idx += WTHR) {
       const int l = idx & 63, f = idx >> 6, cb = f % NCB, u = (f / NCB) % 16, g = (f / (16 * NCB)) % NG,
                 m = f / (16 * NCB * NG);
@@ -367,10 +379,9 @@ __global__ __launch_bounds__(WTHR) void kw_lstep(Dev d, int axis, int sd0) {
   };
   int st = blockIdx.x * WNW + wave, g = 0;
   if (st < nst) load(st, 0);
-  Acc a0[NCB], am[NCB], ap[NCB];
-  zero_prod<P>(a0, NCB);
-  zero_prod<P>(am, NCB);
-  zero_prod<P>(ap, NCB);
+  Acc a[NM][NCB];
+#pragma unroll
+  for (int m = 0; m < NM; ++m) zero_prod<P>(a[m], NCB);
   while (st < nst) {
 #pragma unroll
     for (int u = 0; u < 16; ++u) xv[u] = xn[u];
@@ -380,9 +391,8 @@ __global__ __launch_bounds__(WTHR) void kw_lstep(Dev d, int axis, int sd0) {
       st2 = st + stride;
     }
     if (st2 < nst) load(st2, g2);
-    prod_acc<P, NCB, 16>(a0, Pf + (0 * NG + g) * gstride, xv);
-    prod_acc<P, NCB, 16>(am, Pf + (1 * NG + g) * gstride, xv);
-    prod_acc<P, NCB, 16>(ap, Pf + (2 * NG + g) * gstride, xv);
+#pragma unroll
+    for (int m = 0; m < NM; ++m) prod_acc<P, NCB, 16>(a[m], Pf + (m * NG + g) * gstride, xv);
     if (g == ng - 1) {
       const int q = st * 16 + l16;
       const bool rin = q < M;
@@ -393,22 +403,104 @@ __global__ __launch_bounds__(WTHR) void kw_lstep(Dev d, int axis, int sd0) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int j = c0 + out_col<P>(cb, v, kq);
-          const double val = (double)a0[cb][v] + op * (double)am[cb][v] + on * (double)ap[cb][v];
+          double val;
+          if (NM == 3) {
+            val = (double)a[0][cb][v] + op * (double)a[1][cb][v] + on * (double)a[2][cb][v];
+          } else {
+            // sum_j w^j N_j of the direction's class, nested in w
+            double vp = (double)a[4][cb][v], vn = (double)a[8][cb][v];
+#pragma unroll
+            for (int m = 3; m >= 1; --m) {
+              vp = fma(vp, op, (double)a[m][cb][v]);
+              vn = fma(vn, on, (double)a[4 + m][cb][v]);
+            }
+            val = (double)a[0][cb][v] + op * vp + on * vn;
+          }
           if (rin && j < t) ALs[(int64_t)j * M + q] = (S)val;
         }
-      zero_prod<P>(a0, NCB);
-      zero_prod<P>(am, NCB);
-      zero_prod<P>(ap, NCB);
+#pragma unroll
+      for (int m = 0; m < NM; ++m) zero_prod<P>(a[m], NCB);
     }
     st = st2;
     g = g2;
   }
 }
 
+// Degree-4 Taylor polynomial of exp: e(y) = 1 + y + y^2/2 + y^3/6 + y^4/24,
+// and the divided difference (e(x) - e(y)) / (x - y) of e(dt .) written
+// without the division (x = dt a, y = dt b; the result carries the factor dt).
+__device__ __forceinline__ double taylor_e4(double y) {
+  return 1.0 + y * (1.0 + y * (0.5 + y * (1.0 / 6.0 + y * (1.0 / 24.0))));
+}
+__device__ __forceinline__ double taylor_d4(double x, double y, double dt) {
+  const double s1 = x + y, s2 = x * x + x * y + y * y, s3 = x * x * x + x * x * y + x * y * y + y * y * y;
+  return dt * (1.0 + 0.5 * s1 + s2 * (1.0 / 6.0) + s3 * (1.0 / 24.0));
+}
+
+// RK4 substeps of the advection K-step (Algorithms 1-2, step 1, with the
+// classic four-stage method; Section 4).  The right-hand side
+//   g(K) = -(c / h) [ (K - K_prev) C+ + (K_next - K) C- ]
+// is affine in K once the ghost rows K^b of the faces are frozen, so one
+// RK4 step equals the nested form
+//   K1 = K0 + dt g(K0 + dt/2 g(K0 + dt/3 g(K0 + dt/4 g(K0)))),
+// four passes of "out = K0 + alpha g(in)" over the materialised arrays.
+//
+// One nested stage: out = K0 + alpha g(in) for output columns [c0, c0 + 32)
+// of one tile of 64 cells (FP64).  A thread owns one cell and four columns;
+// C+ and C- (columns c0..c0+31, all t rows) sit in LDS.
+constexpr int RKC = 32;  // output columns per workgroup
+__global__ __launch_bounds__(WTHR) void kw_rk_kstep(Dev d, int axis, int sd0, double alpha, const double* in,
+                                                    double* out) {
+  const int s = sd0 + blockIdx.y;
+  const int t = d.tdim[s];
+  const int c0 = blockIdx.z * RKC;
+  if (c0 >= t) return;
+  const int N = d.N, T = d.T;
+  __shared__ double Cps[WCAP_T * RKC], Cns[WCAP_T * RKC];
+  const double* sm = small_of(d, s);
+  for (int idx = threadIdx.x; idx < t * RKC; idx += WTHR) {
+    const int k = idx / RKC, c = idx % RKC, j = c0 + c;
+    Cps[idx] = j < t ? sm[d.oCp + k + j * T] : 0.0;
+    Cns[idx] = j < t ? sm[d.oCn + k + j * T] : 0.0;
+  }
+  __syncthreads();
+  const int p = blockIdx.x * 64 + (threadIdx.x & 63);
+  if (p >= N) return;
+  const int cg = (threadIdx.x >> 6) * 4;  // this thread's first column in the block
+  const int ix = p % d.lnx, iy = p / d.lnx;
+  const int pos = axis == 0 ? ix : iy, len = axis == 0 ? d.lnx : d.lny, f = axis == 0 ? iy : ix;
+  const int step = axis == 0 ? 1 : d.lnx;
+  const double* K0 = d.K3 + (int64_t)s * N * T;
+  const double* X = in + (int64_t)s * N * T;
+  double* Y = out + (int64_t)s * N * T;
+  const double* glo = d.ghost + (int64_t)(2 * s) * T * d.face;
+  const double* ghi = glo + (int64_t)T * d.face;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int k = 0; k < t; ++k) {
+    const double x = X[(int64_t)k * N + p];
+    const double xp = pos > 0 ? X[(int64_t)k * N + p - step] : glo[(int64_t)k * d.face + f];
+    const double xn = pos < len - 1 ? X[(int64_t)k * N + p + step] : ghi[(int64_t)k * d.face + f];
+    const double dm = x - xp, dp = xn - x;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[c] = fma(dm, Cps[k * RKC + cg + c], fma(dp, Cns[k * RKC + cg + c], acc[c]));
+  }
+  const double sc = -alpha * d.c / d.h;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int j = c0 + cg + c;
+    if (j < t) Y[(int64_t)j * N + p] = fma(sc, acc[c], K0[(int64_t)j * N + p]);
+  }
+}
+
 // Collision K-step (eq. coll_evolK) for output columns [c0, c0 + 32), with
 // K = U S and m = V^T w:
 //   K1[p] = (1 - dt c_t[p]) K[p] + dt (c_s[p] / W (K[p].m) + Q[p]) m;
-// K[p].m = U[p] (S m) is an extra product block.
+// K[p].m = U[p] (S m) is an extra product block.  With RK4 substeps the
+// row ODE K' = K (a m m^T - b I) + Q m^T (a = c_s / W, b = c_t) has the
+// degree-4 Taylor step
+//   K1 = e(-b) K + (a D(lam, -b) (K.m) + Q D(lam, 0)) m,  lam = -b + a m.m,
+// with e(x) = sum_{j <= 4} (dt x)^j / j! and D(x, y) = (e(x) - e(y)) / (x - y)
+// (the rank-one part of the matrix power collapses because m m^T m = (m.m) m).
 template <class S, int P>
 __global__ __launch_bounds__(WTHR) void kw_coll_kstep(Dev d, int sd0) {
   using F = typename Prec<P>::F;
@@ -433,6 +525,9 @@ __global__ __launch_bounds__(WTHR) void kw_coll_kstep(Dev d, int sd0) {
     for (int b = 0; b < r; ++b) acc = fma(Sg[a + b * R], mv[b], acc);
     smv[a] = a < r ? acc : 0.0;
   }
+  double mu = 0.0;  // m.m (RK4 only)
+  if (d.rk4)
+    for (int b = 0; b < r; ++b) mu = fma(mv[b], mv[b], mu);
   for (int idx = threadIdx.x; idx < KSP * NCB * 64; idx += WTHR) {
     const int l = idx & 63, f = idx >> 6, cb = f % NCB, u = f / NCB;
     const int kc = sub_col<P>(u, l >> 4), col = c0 + 16 * cb + (l & 15);
@@ -482,8 +577,16 @@ __global__ __launch_bounds__(WTHR) void kw_coll_kstep(Dev d, int sd0) {
     prod_acc<P, 1, KSP>(ae, Be, xv);
     // column 0 of the extra block sits in component 0 of lanes 0..15
     const double km = __shfl((double)ae[0][0], l16, 64);
-    const double a0 = rin ? 1.0 - dt * ct[pc] : 0.0;
-    const double a1 = rin ? dt * (cs[pc] * iW * km + Qs[pc]) : 0.0;
+    double a0, a1;
+    if (!d.rk4) {
+      a0 = rin ? 1.0 - dt * ct[pc] : 0.0;
+      a1 = rin ? dt * (cs[pc] * iW * km + Qs[pc]) : 0.0;
+    } else {
+      const double b = ct[pc], aa = cs[pc] * iW;
+      const double yb = -dt * b, yl = dt * (aa * mu - b);
+      a0 = rin ? taylor_e4(yb) : 0.0;
+      a1 = rin ? aa * taylor_d4(yl, yb, dt) * km + Qs[pc] * taylor_d4(yl, 0.0, dt) : 0.0;
+    }
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
@@ -1567,6 +1670,46 @@ __global__ __launch_bounds__(STHR) void sw_adv_prep(Dev d, int axis, int sd0) {
   adv_prep_body(d, s, axis, t, lds, sc);
 }
 
+// sw_rk_prep: the frozen ghost rows of the low and high faces,
+//   Kb_lo = K0[low face] En + U_lo[its high face] S_lo Olo,
+//   Kb_hi = K0[high face] Ep + U_hi[its low face] S_hi Ohi,
+// with K0 = U Am (Am = S Tm), into d.ghost[s][side][j][f].
+__global__ __launch_bounds__(STHR) void sw_rk_prep(Dev d, int axis, int sd0) {
+  const int s = sd0 + blockIdx.x;
+  const int lo = neighbour(d, s, axis, -1), hi = neighbour(d, s, axis, +1);
+  const int r = d.rank[s], rl = lo >= 0 ? d.rank[lo] : 0, rh = hi >= 0 ? d.rank[hi] : 0;
+  const int t = d.tdim[s];
+  const int R = d.R, T = d.T, N = d.N;
+  double* sm = small_of(d, s);
+  double* AEn = sm + d.oW1;  // r x t, ld T
+  double* AEp = sm + d.oW2;
+  double* SOl = sm + d.oW3;  // rl x t
+  double* SOh = sm + d.oW4;  // rh x t
+  gmm(AEn, T, sm + d.oAm, R, false, sm + d.oEn, T, false, r, t, t, 1.0, 0.0);
+  gmm(AEp, T, sm + d.oAm, R, false, sm + d.oEp, T, false, r, t, t, 1.0, 0.0);
+  if (rl > 0) gmm(SOl, T, d.S + (int64_t)lo * R * R, R, false, sm + d.oOlo, R, false, rl, t, rl, 1.0, 0.0);
+  if (rh > 0) gmm(SOh, T, d.S + (int64_t)hi * R * R, R, false, sm + d.oOhi, R, false, rh, t, rh, 1.0, 0.0);
+  const int F = face_len(d, axis);
+  const double* U = d.U + (int64_t)s * N * R;
+  const double* Ul = lo >= 0 ? d.U + (int64_t)lo * N * R : U;
+  const double* Uh = hi >= 0 ? d.U + (int64_t)hi * N * R : U;
+  double* glo = d.ghost + (int64_t)(2 * s) * T * d.face;
+  double* ghi = glo + (int64_t)T * d.face;
+  for (int idx = threadIdx.x; idx < F * t; idx += STHR) {
+    const int f = idx % F, j = idx / F;
+    const int pl = face_cell(d, axis, false, f), ph = face_cell(d, axis, true, f);
+    double a = 0.0, b = 0.0;
+    for (int k = 0; k < r; ++k) {
+      a = fma(U[(int64_t)k * N + pl], AEn[k + j * T], a);
+      b = fma(U[(int64_t)k * N + ph], AEp[k + j * T], b);
+    }
+    for (int k = 0; k < rl; ++k) a = fma(Ul[(int64_t)k * N + ph], SOl[k + j * T], a);
+    for (int k = 0; k < rh; ++k) b = fma(Uh[(int64_t)k * N + pl], SOh[k + j * T], b);
+    glo[(int64_t)j * d.face + f] = a;
+    ghi[(int64_t)j * d.face + f] = b;
+  }
+}
+
 // S-step (eq. advx_evolS, integrated with the opposite sign) and the L-step
 // coefficients, as in the narrow plan (Q = h U^1, frozen boundary data):
 //   BKlo = Xlo (Am En) + Xln (S_lo Olo),  BKhi = Xhi (Am Ep) + Xhn (S_hi Ohi),
@@ -1622,18 +1765,36 @@ __global__ __launch_bounds__(STHR) void sw_adv_sstep(Dev d, int axis, int sd0) {
   __syncthreads();
   double* Hm = W5;
   double* Hp = W6;
-  gmm(Hm, T, Gm, T, false, S1, T, false, t, t, t, 1.0, 0.0);
-  gmm(Hp, T, Gp, T, false, S1, T, false, t, t, t, 1.0, 0.0);
-  for (int idx = threadIdx.x; idx < t * t; idx += STHR) {
-    const int o = (idx % t) + (idx / t) * T;
-    Hm[o] -= BKlo[o];
-    Hp[o] += BKhi[o];
-    S2[o] = S1[o];
+  // S-step: S' = c ((Gm S - BKlo) C+ + (Gp S + BKhi) C-), one Euler step, or
+  // RK4 in the nested form S2 = S1 + dt f(S1 + dt/2 f(S1 + dt/3 f(S1 + dt/4 f(S1))))
+  // (stage outputs alternate between S2 and W1, the last one is copied to S2)
+  const int nst = d.rk4 ? 4 : 1;
+  const double* Sin = S1;
+  for (int stg = 0; stg < nst; ++stg) {
+    const double al = d.dt / (double)(nst - stg);
+    double* Sout = (stg & 1) ? Xlo : S2;
+    gmm(Hm, T, Gm, T, false, Sin, T, false, t, t, t, 1.0, 0.0);
+    gmm(Hp, T, Gp, T, false, Sin, T, false, t, t, t, 1.0, 0.0);
+    for (int idx = threadIdx.x; idx < t * t; idx += STHR) {
+      const int o = (idx % t) + (idx / t) * T;
+      Hm[o] -= BKlo[o];
+      Hp[o] += BKhi[o];
+      Sout[o] = S1[o];
+    }
+    __syncthreads();
+    const double dc = al * d.c;
+    gmm(Sout, T, Hm, T, false, sm + d.oCp, T, false, t, t, t, dc, 1.0);
+    gmm(Sout, T, Hp, T, false, sm + d.oCn, T, false, t, t, t, dc, 1.0);
+    Sin = Sout;
   }
-  __syncthreads();
+  if (Sin != S2) {
+    for (int idx = threadIdx.x; idx < t * t; idx += STHR) {
+      const int o = (idx % t) + (idx / t) * T;
+      S2[o] = Sin[o];
+    }
+    __syncthreads();
+  }
   const double dc = d.dt * d.c;
-  gmm(S2, T, Hm, T, false, sm + d.oCp, T, false, t, t, t, dc, 1.0);
-  gmm(S2, T, Hp, T, false, sm + d.oCn, T, false, t, t, t, dc, 1.0);
   gmm(Hm, T, Gm, T, false, S2, T, false, t, t, t, 1.0, 0.0);
   gmm(Hp, T, Gp, T, false, S2, T, false, t, t, t, 1.0, 0.0);
   for (int idx = threadIdx.x; idx < t * t; idx += STHR) {
@@ -1642,6 +1803,22 @@ __global__ __launch_bounds__(STHR) void sw_adv_sstep(Dev d, int axis, int sd0) {
     sm[d.oP0 + ot] = S2[o];
     sm[d.oPm + ot] = -dc * (Hm[o] - BKlo[o]);
     sm[d.oPp + ot] = -dc * (Hp[o] + BKhi[o]);
+  }
+  if (d.rk4) {
+    // L-step of direction q in the class of the sign of w = Omega_q: with
+    // L = V-hat_q X, X' = w (X A + B) (A+ = -c Gm^T, A- = -c Gp^T), whose RK4
+    // step is the degree-4 Taylor polynomial X1 = sum_j w^j N_j with
+    // N0 = S2^T, N1 = dt (S2^T A + B) (the Euler Pm / Pp above) and
+    // N_{j+1} = dt / (j + 1) N_j A: N2..N4 of the + class into W1, W3, W5,
+    // of the - class into W2, W4, W6
+    __syncthreads();
+    double* Np[4] = {sm + d.oPm, sm + d.oW1, sm + d.oW3, sm + d.oW5};
+    double* Nn[4] = {sm + d.oPp, sm + d.oW2, sm + d.oW4, sm + d.oW6};
+    for (int j = 1; j < 4; ++j) {
+      const double a = -d.c * d.dt / (double)(j + 1);
+      gmm(Np[j], T, Np[j - 1], T, false, Gm, T, true, t, t, t, a, 0.0);
+      gmm(Nn[j], T, Nn[j - 1], T, false, Gp, T, true, t, t, t, a, 0.0);
+    }
   }
 }
 
@@ -1883,13 +2060,30 @@ void launch_w_kstep(const Dev& d, int axis, int sd0, int nsd, hipStream_t st) {
   });
 }
 
+void launch_w_rk_prep(const Dev& d, int axis, int sd0, int nsd, hipStream_t st) {
+  hipLaunchKernelGGL(sw_rk_prep, dim3(nsd), dim3(STHR), 0, st, d, axis, sd0);
+}
+
+void launch_w_rk_kstep(const Dev& d, int axis, int sd0, int nsd, double alpha, const void* in, void* out,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(kw_rk_kstep, dim3(wdiv(d.N, 64), nsd, wdiv(d.T, RKC)), dim3(WTHR), 0, st, d, axis, sd0, alpha,
+                     (const double*)in, (double*)out);
+}
+
 void launch_w_lstep(const Dev& d, int axis, int sd0, int nsd, hipStream_t st) {
   const int nz = wdiv(d.T, 32);
   w_with_prec(d.prec, false, [&](auto ts, auto pc) {
     using S = typename decltype(ts)::type;
     constexpr int P = decltype(pc)::value;
+    if (d.rk4) {
+      // RK4 (FP64 only): nine coefficient matrices, 16 output columns per workgroup
+      const size_t lds = sizeof(double) * 9 * (WCAP_T / 64) * 16 * 1 * 64;
+      hipLaunchKernelGGL((kw_lstep<double, 0, 9, 1>), dim3(d.nwgM, nsd, wdiv(d.T, 16)), dim3(WTHR), lds, st, d,
+                         axis, sd0);
+      return;
+    }
     const size_t lds = sizeof(typename Prec<P>::F) * 3 * (WCAP_T / 64) * 16 * 2 * 64;
-    hipLaunchKernelGGL((kw_lstep<S, P>), dim3(d.nwgM, nsd, nz), dim3(WTHR), lds, st, d, axis, sd0);
+    hipLaunchKernelGGL((kw_lstep<S, P, 3, 2>), dim3(d.nwgM, nsd, nz), dim3(WTHR), lds, st, d, axis, sd0);
   });
 }
 
@@ -1959,13 +2153,14 @@ void init_wide_kernels() {
         w_allow((const void*)kw_gemm<W, double, P, 4>);
         w_allow((const void*)kw_gemm<W, W, P, 4>);
         w_allow((const void*)kw_kstep<W, P>);
-        w_allow((const void*)kw_lstep<W, P>);
+        w_allow((const void*)kw_lstep<W, P, 3, 2>);
       });
   w_allow((const void*)kw_aug_form);
   w_allow((const void*)sw_chol);
   w_allow((const void*)sw_aug_svd);
   w_allow((const void*)sw_adv_prep);
   w_allow((const void*)sw_trunc);
+  w_allow((const void*)kw_lstep<double, 0, 9, 1>);
   (void)hipGetLastError();
 }
 

@@ -121,11 +121,15 @@ def test_largest_configurations_accepted(name):
 
 
 @needs_lib
-def test_rk4_substeps_refused_by_the_engine():
-    """RK4 substeps exist in the oracle only: the binding refuses such a
-    problem before anything reaches the library."""
-    with pytest.raises(NotImplementedError):
-        pkg.workspace_size(_cfg(integrator="rk4"))
+def test_rk4_substeps_accepted_in_fp64_only():
+    """RK4 substeps take the wide launch plan in FP64; the mixed-precision
+    modes refuse them, and an unknown integrator is refused by the binding."""
+    assert pkg.workspace_size(_cfg(integrator="rk4")) > pkg.workspace_size(_cfg())
+    with pytest.raises(nat.DDError) as ei:
+        pkg.workspace_size(_cfg(integrator="rk4"), precision=pkg.DD_PREC_MIXED_FP32)
+    assert ei.value.status == nat.DD_EINVAL and "RK4" in str(ei.value)
+    with pytest.raises(ValueError):
+        pkg.workspace_size(_cfg(integrator="midpoint"))
 
 
 @needs_lib
