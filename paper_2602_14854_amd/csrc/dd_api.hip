@@ -171,8 +171,9 @@ std::string validate(const dd_dlra_config* c) {
   return "";
 }
 
-// The narrow plan's kernels hold up to 64 intermediate and augmentation
-// columns (stored ranks up to 21); larger capacities take the wide plan.
+// The narrow plan's kernels hold up to 48 intermediate and 64 augmentation
+// columns (stored ranks up to 21; its 64-column row reductions would spill
+// registers); larger capacities take the wide plan.
 // DD_DLRA_PLAN=wide in the environment selects the wide plan for any
 // capacity (used to test it on small problems).
 bool wide_plan(const dd_dlra_config* c) {
@@ -180,7 +181,7 @@ bool wide_plan(const dd_dlra_config* c) {
   const char* env = getenv("DD_DLRA_PLAN");
   if (env && strcmp(env, "wide") == 0) return true;
   if (c->integrator == DD_INT_RK4) return true;  // the RK4 substeps exist in the wide kernels
-  return c->r_int_max > dd::CAP || 3 * R > dd::CAP;
+  return c->r_int_max > 48 || 3 * R > dd::CAP;
 }
 
 Layout make_layout(const dd_dlra_config* c) {

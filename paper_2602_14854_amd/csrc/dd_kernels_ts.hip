@@ -917,8 +917,10 @@ __global__ __launch_bounds__(NTHR) void k_coll_reduce(Dev d, int sd0) {
       const double v = Ug[(int64_t)(in ? c : 0) * N + pc];
       xn[ks] = in ? v : 0.0;
     }
-    const double* src = kq == 0 ? cs : (kq == 1 ? ct : Qg);
-    const double w_ = src[pc];
+    // three plain loads and a select: a pointer chosen per lane would be
+    // kept in a private array (scratch) by the compiler
+    const double w0 = cs[pc], w1 = ct[pc], w2 = Qg[pc];
+    const double w_ = kq == 0 ? w0 : (kq == 1 ? w1 : w2);
     wn = (rin_ && kq < 3) ? w_ : 0.0;
   };
   int st = blockIdx.x * NW + wave;
@@ -1222,6 +1224,18 @@ void with_ksp(int rcap, Fn f) {
 
 constexpr size_t D8 = sizeof(double);
 
+// dynamic LDS of the row reductions (one helper for the launch and for the
+// occupancy query)
+template <int NT, int NR>
+constexpr size_t ang_reduce_lds() {
+  constexpr int NACC = std::max(3 * NR * NT, 3 * NT * (NT + 1) / 2);
+  return D8 * std::max<size_t>(NW * (16 * (16 * (NT + 3 * NR) + 1) + 16), (size_t)2 * NACC * 256);
+}
+template <int NT, int NR>
+constexpr size_t spatial_reduce_lds() {
+  return D8 * (size_t)(NT * NT + 4 * NT * NR) * 256;  // the workgroup reduction
+}
+
 // 160 KB of LDS per compute unit, less room for a kernel's static LDS
 void allow_lds(const void* fn) {
   (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 159 * 1024);
@@ -1282,9 +1296,8 @@ void launch_ang_reduce(const Dev& d, int axis, int sd0, int nsd, hipStream_t st)
       constexpr int NT = decltype(ct)::value;
       with_ncb(ncb_of(d.R), [&](auto cr) {
         constexpr int NR = decltype(cr)::value;
-        constexpr int NACC = std::max(3 * NR * NT, 3 * NT * (NT + 1) / 2);
-        const size_t lds = D8 * std::max<size_t>(NW * (16 * (16 * (NT + 3 * NR) + 1) + 16), (size_t)2 * NACC * 256);
-        if constexpr (NR <= 2)  // stored ranks are at most 21
+        const size_t lds = ang_reduce_lds<NT, NR>();
+        if constexpr (NR <= 2 && NT <= 3)  // stored ranks <= 21, intermediate ranks <= 48
           hipLaunchKernelGGL((k_ang_reduce<S, NT, NR>), dim3(d.nwgM, nsd), dim3(NTHR), lds, st, d, axis, sd0);
       });
     });
@@ -1313,9 +1326,8 @@ void launch_spatial_reduce(const Dev& d, int axis, int sd0, int nsd, const void*
       constexpr int NT = decltype(ct)::value;
       with_ncb(ncb_of(d.R), [&](auto cr) {
         constexpr int NR = decltype(cr)::value;
-        constexpr int NACC = NT * NT + 4 * NT * NR;
-        const size_t lds = D8 * (size_t)NACC * 256;  // the workgroup reduction
-        if constexpr (NR <= 2)  // stored ranks are at most 21
+        const size_t lds = spatial_reduce_lds<NT, NR>();
+        if constexpr (NR <= 2 && NT <= 3)  // stored ranks <= 21, intermediate ranks <= 48
           hipLaunchKernelGGL((k_spatial_reduce<S, NT, NR>), dim3(d.nwgN, nsd), dim3(NTHR), lds, st, d, axis, sd0,
                              Q);
       });
@@ -1417,10 +1429,8 @@ int ts_resident_wgs(const Dev& d) {
       take((const void*)k_gemm<S, S, 0, NC, KS>, strip_bytes<0, NC>(KS * NC * 64));
       with_ncb(ncb_of(d.R), [&](auto cr) {
         constexpr int NR = decltype(cr)::value;
-        constexpr int NACC = NC * NC + 2 * NC * NR;
-        if constexpr (NR <= 2)
-          take((const void*)k_spatial_reduce<S, NC, NR>,
-               D8 * std::max<size_t>(NW * 2 * 16 * (strip_ld<NC>() + strip_ld<NR>()), (size_t)2 * NACC * 256));
+        if constexpr (NR <= 2 && NC <= 3)
+          take((const void*)k_spatial_reduce<S, NC, NR>, spatial_reduce_lds<NC, NR>());
       });
     });
   });
@@ -1453,7 +1463,7 @@ void init_kernels() {
             for (int nr = 1; nr <= 2; ++nr) {
               with_ncb(nr, [&](auto r) {
                 constexpr int NR = decltype(r)::value;
-                if constexpr (NR <= 2) {
+                if constexpr (NR <= 2 && NC <= 3) {
                   allow_lds((const void*)k_ang_reduce<W, NC, NR>);
                   allow_lds((const void*)k_spatial_reduce<W, NC, NR>);
                 }

@@ -208,3 +208,20 @@ def test_workloads_are_seeded(name):
     assert np.array_equal(a.sigma_s, b.sigma_s) and np.array_equal(a.Q, b.Q) and np.array_equal(a.w, b.w)
     c = wk.make_workload(name, seed=a.seed + 1)
     assert not all(np.array_equal(x, y) for x, y in zip(a.S0 + a.V0, c.S0 + c.V0))
+
+
+def test_build_flags_tall_skinny_scratch():
+    """The build's resource check: scratch memory of a tall-skinny kernel
+    (k_*, kw_*) fails the build, that of a small per-subdomain kernel is
+    allowed."""
+    from paper_2602_14854_amd import build as b
+    rem = ("a.hip:1:1: remark: Function Name: _ZN2dd12k_ang_reduceIdLi4ELi2EEEvNS_3DevEii [-Rpass]\n"
+           "a.hip:1:1: remark:     ScratchSize [bytes/lane]: 304 [-Rpass]\n"
+           "a.hip:2:1: remark: Function Name: _ZN2dd10sw_aug_svdENS_3DevEii [-Rpass]\n"
+           "a.hip:2:1: remark:     ScratchSize [bytes/lane]: 80 [-Rpass]\n"
+           "a.hip:3:1: remark: Function Name: _ZN2dd7kw_gemmIddLi0ELi4EEEvNS_3DevE [-Rpass]\n"
+           "a.hip:3:1: remark:     ScratchSize [bytes/lane]: 0 [-Rpass]\n")
+    rep = b.scratch_report(rem)
+    assert [v for _, v in rep] == [304, 80, 0]
+    flagged = [k for k, v in rep if v > 0 and b._TS_KERNEL.match(k)]
+    assert flagged == ["_ZN2dd12k_ang_reduceIdLi4ELi2EEEvNS_3DevEii"]

@@ -240,17 +240,17 @@ def test_graded_factors(lo, bound):
 
 
 def test_maximum_capacity():
-    """The largest shapes the engine accepts: stored rank 21 (three times
-    that fills the 64-column capacity) with r_int_max 64, so the middle
-    subdomain of each 3-row gets m0 = t = 63 intermediate columns (the
-    64-column instantiations of every small kernel) on N = 100 cells and
-    M = 80 directions."""
+    """The largest shapes of the narrow plan: stored rank 21 (three times
+    that fills its 64-column augmentation capacity) with r_int_max 48, so the
+    middle subdomain of each 3-row augments to m0 = 63 columns (the 64-column
+    instantiations of the small kernels) and keeps t = 48, on N = 100 cells
+    and M = 80 directions.  (Larger intermediate ranks take the wide plan.)"""
     rng = np.random.default_rng(32)
     n = 30 * 30
     wl = wk.make_custom(30, 30, 3, 3, wk.product_directions(8, 10), [21] * 9, seed=31,
                         sigma_s=rng.uniform(0, 2, n), sigma_a=rng.uniform(0, 1, n), Q=rng.uniform(0, 1, n),
-                        cfl=0.5, r_int_max=64, sig=np.logspace(0, -2, 21))
-    say("case: 3x3 of 10x10, M=80, ranks 21, r_int_max 64 (t = 63 in the middle row)")
+                        cfl=0.5, r_int_max=48, sig=np.logspace(0, -2, 21))
+    say("case: 3x3 of 10x10, M=80, ranks 21, r_int_max 48 (m0 = 63 in the middle row)")
     ref, prob = oracle_steps(wl, 2)
     e = engine(wl)
     e.step(2)
