@@ -28,6 +28,14 @@ eigen-decomposition of C).  Readings used where the paper is silent:
   R14/R15 rank rules (see aug_rank / trunc_rank).
   R16     the collision stage does not truncate.
   R17     a physical vacuum face has zero inflow; the own outflow part stays.
+  R33     a physical inflow face (the prescribed inflow of Section 4's
+          Hohlraum and boundary point-source problems, f_in = A B^T along the
+          face) acts as a neighbour: a layer one cell thick outside the face
+          holding f_in, with the factors U_v = Q_a / h (on its cells next to
+          the face), S_v = h R_a, V_v = B from the thin QR A_s = Q_a R_a of the
+          subdomain's part of A.  It supplies the inflow part of the ghost
+          values, and V_v S_v^T = h B R_a^T joins L0 in the augmentation, as a
+          neighbour's V_n S_n^T does.
 """
 from __future__ import annotations
 
@@ -58,6 +66,7 @@ class Problem:
         self.W = float(np.sum(self.w))
         self.c = float(wl.c_adv)
         self.dt = float(wl.dt)
+        self.inflow = list(getattr(wl, "inflow", None) or [None] * 4)
         self.rank_mode = int(wl.rank_mode)
         self.r_fixed = int(wl.r_fixed)
         self.r_min, self.r_max = int(wl.r_min), int(wl.r_max)
@@ -100,6 +109,30 @@ class Problem:
             if sy < 0 or sy >= self.py:
                 return None
         return sy * self.px + sx
+
+    def virtual_neighbour(self, s, axis, side):
+        """(U_v, S_v, V_v) of the inflow layer outside a physical inflow face
+        of subdomain s (R33), or None (an interior face or a vacuum face).
+        U_v is nonzero only on its face next to s."""
+        sx, sy = s % self.px, s // self.px
+        if axis == 0:
+            if (side < 0 and sx > 0) or (side > 0 and sx < self.px - 1):
+                return None
+            f = 0 if side < 0 else 1
+            pos = sy * self.lny + np.arange(self.lny)
+        else:
+            if (side < 0 and sy > 0) or (side > 0 and sy < self.py - 1):
+                return None
+            f = 2 if side < 0 else 3
+            pos = sx * self.lnx + np.arange(self.lnx)
+        if self.inflow[f] is None:
+            return None
+        A, B = self.inflow[f]
+        As = np.asarray(A, float)[pos]
+        Qa, Ra = np.linalg.qr(As)
+        U = np.zeros((self.N, As.shape[1]))
+        U[self.face(axis, side < 0)] = Qa / self.h   # its cells next to s
+        return U, self.h * Ra, np.asarray(B, float)
 
     def face(self, axis, high):
         """Local cell indices of a subdomain face, ordered along the face:
@@ -277,6 +310,16 @@ def augment(U, S, V, nbrs, prob, U_rand=None):
 # inflow boundary data (eq. generate_Kboundary and its y counterpart)
 # ----------------------------------------------------------------------------
 
+def neighbour_factors(s, axis, side, snapshot, prob):
+    """Factors of the subdomain next to s on that side as they were at the
+    start of the stage (R6), the inflow layer of a physical inflow face
+    (R33), or None (vacuum)."""
+    n = prob.neighbour(s, axis, side)
+    if n is not None:
+        return snapshot[n]
+    return prob.virtual_neighbour(s, axis, side)
+
+
 def boundary_K(s, axis, K, V_hat, snapshot, prob):
     """K^b on the low and high faces of subdomain s for one advection stage.
 
@@ -284,7 +327,8 @@ def boundary_K(s, axis, K, V_hat, snapshot, prob):
     high face, projected with <1_{omega>=0} V^n_l, V-hat_j>; the outflow part
     (omega < 0) is this subdomain's own K at its low face projected with
     <1_{omega<0} V-hat_l, V-hat_j>.  The high face mirrors it.  A physical
-    vacuum face contributes no inflow (R17)."""
+    vacuum face contributes no inflow (R17); a physical inflow face
+    contributes its prescribed inflow through its layer's factors (R33)."""
     w = prob.w
     om = prob.omega[axis]
     pos = (om >= 0).astype(float)           # R3
@@ -293,13 +337,13 @@ def boundary_K(s, axis, K, V_hat, snapshot, prob):
     hi_face = prob.face(axis, True)
     Kb_lo = K[lo_face] @ (V_hat.T @ ((w * neg)[:, None] * V_hat))
     Kb_hi = K[hi_face] @ (V_hat.T @ ((w * pos)[:, None] * V_hat))
-    n_lo = prob.neighbour(s, axis, -1)
-    n_hi = prob.neighbour(s, axis, +1)
-    if n_lo is not None:
-        Un, Sn, Vn = snapshot[n_lo]
+    f_lo = neighbour_factors(s, axis, -1, snapshot, prob)
+    f_hi = neighbour_factors(s, axis, +1, snapshot, prob)
+    if f_lo is not None:
+        Un, Sn, Vn = f_lo
         Kb_lo = Kb_lo + (Un[hi_face] @ Sn) @ (Vn.T @ ((w * pos)[:, None] * V_hat))
-    if n_hi is not None:
-        Un, Sn, Vn = snapshot[n_hi]
+    if f_hi is not None:
+        Un, Sn, Vn = f_hi
         Kb_hi = Kb_hi + (Un[lo_face] @ Sn) @ (Vn.T @ ((w * neg)[:, None] * V_hat))
     return Kb_lo, Kb_hi
 
@@ -463,9 +507,9 @@ def stage_advect(state, axis, prob, rng=None, records=None, only=None):
             continue
         nbrs = []
         for side in (-1, +1):
-            n = prob.neighbour(s, axis, side)
-            if n is not None:
-                nbrs.append((snapshot[n][2], snapshot[n][1]))
+            fn = neighbour_factors(s, axis, side, snapshot, prob)
+            if fn is not None:
+                nbrs.append((fn[2], fn[1]))
         U_rand = None
         if rng is not None:
             U_rand = rng.standard_normal((prob.N, prob.r_int_max + 1))

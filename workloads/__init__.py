@@ -62,6 +62,10 @@ class Workload:
     seed: int = 0
     note: str = ""
     integrator: str = "euler"    # substep integrator: "euler" or "rk4"
+    # prescribed inflow on the physical faces -x, +x, -y, +y: None (vacuum)
+    # or (A, B) with f_in(position along the face, direction) = A B^T,
+    # A [face cells x rb] (ny cells for an x face, nx for a y face), B [M x rb]
+    inflow: Optional[list] = None
 
     @property
     def lnx(self) -> int:
