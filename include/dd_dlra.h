@@ -64,7 +64,16 @@ typedef enum {
 enum { DD_PREC_FP64 = 0, DD_PREC_MIXED_FP32 = 1, DD_PREC_MIXED_BF16 = 2 };
 enum { DD_RANK_FIXED = 0, DD_RANK_ADAPTIVE = 1 };
 enum { DD_EXEC_PER_SUBDOMAIN = 0, DD_EXEC_BATCHED = 1, DD_EXEC_BATCHED_GRAPH = 2 };
-enum { DD_BC_VACUUM = 0 };
+/* Physical faces (Section 4): vacuum (zero inflow), or a prescribed inflow
+ * f_in(position along the face, direction) = sum_k a_k(position) b_k(direction)
+ * that enters through the face for the directions pointing into the domain
+ * (-x face: Omega_x >= 0; +x: Omega_x < 0; -y: Omega_y >= 0; +y: Omega_y < 0).
+ * An inflow face acts as a neighbour of the subdomains along it: a layer one
+ * cell thick outside the face holding f_in, which supplies their ghost
+ * values and joins the augmentation (Algorithm 4) with the factors
+ * U = Q_a / h, S = h R_a, V = b of the thin QR a_s = Q_a R_a of the
+ * subdomain's part of a. */
+enum { DD_BC_VACUUM = 0, DD_BC_INFLOW_LOWRANK = 1 };
 /* Substep integrator of every K-, S- and L-step (Algorithms 1-3): one
  * explicit Euler step of length dt, or one classic four-stage Runge-Kutta
  * step with the boundary data frozen over the substep (Section 4 runs use
@@ -92,9 +101,16 @@ typedef struct {
   double tol_aug_rel;      /* fixed mode: augmentation tail <= tol_aug_rel*sigma_1 */
   int32_t precision;       /* DD_PREC_*                                            */
   int32_t exec_mode;       /* DD_EXEC_*                                            */
-  int32_t bc[4];           /* faces -x, +x, -y, +y: DD_BC_VACUUM only             */
+  int32_t bc[4];           /* faces -x, +x, -y, +y: DD_BC_VACUUM or _INFLOW_LOWRANK */
   int32_t strict_caps;     /* 1: a rank clamp latches DD_ERANK; 0: clamp, count   */
   int32_t integrator;      /* DD_INT_EULER or DD_INT_RK4                           */
+  /* prescribed inflow of the faces with bc[f] = DD_BC_INFLOW_LOWRANK (ignored
+   * otherwise; copied at create): rank rb = bc_rank[f] (1 <= rb <= the
+   * stored-rank capacity), bc_a[f] [rb][face cells] (ny cells along an x
+   * face, nx along a y face, in increasing coordinate), bc_b[f] [rb][M]   */
+  int32_t bc_rank[4];
+  const double* bc_a[4];
+  const double* bc_b[4];
 } dd_dlra_config;
 
 /* Device bytes a handle needs for this configuration (state, scratch and

@@ -18,6 +18,7 @@ DD_PREC_FP64, DD_PREC_MIXED_FP32, DD_PREC_MIXED_BF16 = 0, 1, 2
 DD_RANK_FIXED, DD_RANK_ADAPTIVE = 0, 1
 DD_EXEC_PER_SUBDOMAIN, DD_EXEC_BATCHED, DD_EXEC_BATCHED_GRAPH = 0, 1, 2
 DD_INT_EULER, DD_INT_RK4 = 0, 1
+DD_BC_VACUUM, DD_BC_INFLOW_LOWRANK = 0, 1
 
 EXPORTS = (
     "dd_dlra_workspace_size", "dd_dlra_create", "dd_dlra_step", "dd_dlra_stage", "dd_dlra_get_ranks",
@@ -46,6 +47,7 @@ class Config(ctypes.Structure):
         ("tol", ctypes.c_double), ("tol_aug_rel", ctypes.c_double),
         ("precision", ctypes.c_int32), ("exec_mode", ctypes.c_int32), ("bc", ctypes.c_int32 * 4),
         ("strict_caps", ctypes.c_int32), ("integrator", ctypes.c_int32),
+        ("bc_rank", ctypes.c_int32 * 4), ("bc_a", _DP * 4), ("bc_b", _DP * 4),
     ]
 
 
@@ -136,6 +138,23 @@ class _ConfigHolder:
         c.tol, c.tol_aug_rel = float(wl.tol), float(wl.tol_aug_rel)
         c.precision, c.exec_mode = int(precision), int(exec_mode)
         c.bc[:] = [0, 0, 0, 0]
+        self.bc_arrays = []
+        for f, spec in enumerate(getattr(wl, "inflow", None) or [None] * 4):
+            if spec is None:
+                continue
+            A = np.asarray(spec[0], float)
+            B = np.asarray(spec[1], float)
+            if A.ndim == 1:
+                A = A[:, None]
+            if B.ndim == 1:
+                B = B[:, None]
+            a = np.ascontiguousarray(A.T)   # [rb][face cells]
+            b = np.ascontiguousarray(B.T)   # [rb][M]
+            self.bc_arrays += [a, b]
+            c.bc[f] = DD_BC_INFLOW_LOWRANK
+            c.bc_rank[f] = int(A.shape[1])
+            c.bc_a[f] = _dp(a)
+            c.bc_b[f] = _dp(b)
         c.strict_caps = int(strict)
         c.integrator = DD_INT_RK4 if integ == "rk4" else DD_INT_EULER
         self.cfg = c

@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <mutex>
+#include <numeric>
 #include <string>
 #include <vector>
 
@@ -117,6 +118,7 @@ struct Layout {
   // byte offsets of the arena segments
   size_t oU, oV, oS, oA, oZ, oQh, oK1, oK2, oAL, oAL2, oGP, oSM, oRho, oIn, oCs, oCt, oQ, oInt, oFlags;
   size_t oK3, oGhost;  // RK4 only: the K-step's initial value and the frozen ghost rows
+  int npseudo;         // layer slots of the inflow faces
   int face;            // cells on the longer subdomain face
 };
 
@@ -166,8 +168,16 @@ std::string validate(const dd_dlra_config* c) {
     return "RK4 substeps run in DD_PREC_FP64 only";
   if (c->precision < DD_PREC_FP64 || c->precision > DD_PREC_MIXED_BF16) return "unknown precision";
   if (c->exec_mode < DD_EXEC_PER_SUBDOMAIN || c->exec_mode > DD_EXEC_BATCHED_GRAPH) return "unknown exec_mode";
-  for (int f = 0; f < 4; ++f)
-    if (c->bc[f] != DD_BC_VACUUM) return "only vacuum physical boundaries are available";
+  for (int f = 0; f < 4; ++f) {
+    if (c->bc[f] == DD_BC_VACUUM) continue;
+    if (c->bc[f] != DD_BC_INFLOW_LOWRANK) return "unknown boundary condition of face " + std::to_string(f);
+    if (c->bc_rank[f] < 1 || c->bc_rank[f] > R)
+      return "inflow rank of face " + std::to_string(f) + " must be between 1 and the stored-rank capacity";
+    if (!c->bc_a[f] || !c->bc_b[f]) return "inflow arrays of face " + std::to_string(f) + " must not be NULL";
+    const size_t nf = f < 2 ? c->ny : c->nx;
+    if (!finite_all(c->bc_a[f], nf * c->bc_rank[f]) || !finite_all(c->bc_b[f], M * c->bc_rank[f]))
+      return "non-finite inflow data of face " + std::to_string(f);
+  }
   return "";
 }
 
@@ -258,9 +268,15 @@ Layout make_layout(const dd_dlra_config* c) {
     b = align256(b + bytes);
     return r;
   };
-  L.oU = seg(ns * L.N * R * d8);
-  L.oV = seg(ns * L.M * R * d8);
-  L.oS = seg(ns * R * R * d8);
+  // inflow faces act as neighbours held in extra "layer" slots after the
+  // subdomains (-x: py, +x: py, -y: px, +y: px), in the state arrays only
+  L.npseudo = 0;
+  for (int f = 0; f < 4; ++f)
+    if (c->bc[f] == DD_BC_INFLOW_LOWRANK) L.npseudo = 2 * (c->px + c->py);
+  const size_t nsx = ns + L.npseudo;
+  L.oU = seg(nsx * L.N * R * d8);
+  L.oV = seg(nsx * L.M * R * d8);
+  L.oS = seg(nsx * R * R * d8);
   L.oA = seg(ns * L.M * MA * d8);
   L.oZ = seg(ns * L.M * std::max(MA, T) * d8);  // the wide plan's second V-hat buffer
   L.oQh = seg(ns * L.M * T * es);
@@ -275,7 +291,7 @@ Layout make_layout(const dd_dlra_config* c) {
   L.oCs = seg(ns * L.N * d8);
   L.oCt = seg(ns * L.N * d8);
   L.oQ = seg(ns * L.N * d8);
-  L.oInt = seg(8 * ns * sizeof(int));
+  L.oInt = seg((8 * ns + L.npseudo) * sizeof(int));
   L.oFlags = seg(64);
   L.face = std::max(c->nx / c->px, c->ny / c->py);
   L.oK3 = L.oGhost = 0;
@@ -350,11 +366,13 @@ void fill_dev(Dev& d, const Layout& L, const dd_dlra_config* c, char* base) {
   d.ct = (double*)(base + L.oCt);
   d.Qsrc = (double*)(base + L.oQ);
   int* ip = (int*)(base + L.oInt);
-  d.rank = ip;
-  d.tdim = ip + L.nsub;
-  d.rnew = ip + 2 * L.nsub;
-  d.tmax = ip + 3 * L.nsub;
-  d.force = ip + 4 * L.nsub;
+  d.rank = ip;  // [nsub + npseudo]
+  d.tdim = ip + L.nsub + L.npseudo;
+  d.rnew = d.tdim + L.nsub;
+  d.tmax = d.rnew + L.nsub;
+  d.force = d.tmax + L.nsub;
+  d.npseudo = L.npseudo;
+  for (int f = 0; f < 4; ++f) d.bc_in[f] = c->bc[f] == DD_BC_INFLOW_LOWRANK ? 1 : 0;
   d.flags = (unsigned*)(base + L.oFlags);
   d.clamps = (unsigned long long*)(base + L.oFlags + 8);
   const int* f = L.off;
@@ -430,6 +448,66 @@ dd_status upload_factors(dd_dlra_handle h, const int32_t* rank, const double* co
   HIPCHK(hipMemcpyAsync(d.rank, iv.data(), d.nsub * sizeof(int), hipMemcpyHostToDevice, h->stream));
   HIPCHK(hipMemcpyAsync(d.tmax, iv.data(), d.nsub * sizeof(int), hipMemcpyHostToDevice, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
+  return DD_OK;
+}
+
+// The layer slots of the inflow faces: for each subdomain along an inflow
+// face, the thin QR a_s = Q_a R_a (classical Gram-Schmidt applied twice) of
+// its part of the face profile gives U = Q_a / h on the layer's cells next
+// to the subdomain, S = h R_a and V = b (Section 4's prescribed inflow as a
+// neighbour; see the header).
+dd_status upload_inflow_layers(dd_dlra_handle h, const dd_dlra_config* c) {
+  const Dev& d = h->d;
+  if (d.npseudo == 0) return DD_OK;
+  const int N = d.N, M = d.M, R = d.R;
+  for (int f = 0; f < 4; ++f) {
+    if (!d.bc_in[f]) continue;
+    const int rb = c->bc_rank[f];
+    const int axis = f < 2 ? 0 : 1;
+    const bool layer_high = (f % 2) == 0;  // a low face's layer touches the subdomain with its high face
+    const int nface = axis == 0 ? d.lny : d.lnx;       // cells along one subdomain's face
+    const int ntot = axis == 0 ? c->ny : c->nx;        // along the whole face
+    const int npos = axis == 0 ? d.py : d.px;
+    const int slot0 = d.nsub + (f == 0 ? 0 : f == 1 ? d.py : f == 2 ? 2 * d.py : 2 * d.py + d.px);
+    for (int j = 0; j < npos; ++j) {
+      std::vector<double> Q((size_t)nface * rb), Rm((size_t)rb * rb, 0.0);
+      for (int k = 0; k < rb; ++k)
+        for (int i = 0; i < nface; ++i) Q[i + (size_t)k * nface] = c->bc_a[f][(size_t)k * ntot + j * nface + i];
+      for (int k = 0; k < rb; ++k) {
+        double* q = &Q[(size_t)k * nface];
+        const double n0 = sqrt(std::inner_product(q, q + nface, q, 0.0));
+        for (int pass = 0; pass < 2; ++pass)
+          for (int l = 0; l < k; ++l) {
+            const double* p = &Q[(size_t)l * nface];
+            const double dot = std::inner_product(p, p + nface, q, 0.0);
+            Rm[l + (size_t)k * rb] += dot;
+            for (int i = 0; i < nface; ++i) q[i] -= dot * p[i];
+          }
+        const double nrm = sqrt(std::inner_product(q, q + nface, q, 0.0));
+        if (nrm > 1e-14 * n0 && nrm > 0.0) {
+          Rm[k + (size_t)k * rb] = nrm;
+          for (int i = 0; i < nface; ++i) q[i] /= nrm;
+        } else {
+          for (int i = 0; i < nface; ++i) q[i] = 0.0;  // dependent: a zero column, a zero row of R
+        }
+      }
+      std::vector<double> U((size_t)N * R, 0.0), Sv((size_t)R * R, 0.0), V((size_t)M * R, 0.0);
+      for (int k = 0; k < rb; ++k) {
+        for (int i = 0; i < nface; ++i) {
+          const int cell = axis == 0 ? i * d.lnx + (layer_high ? d.lnx - 1 : 0)
+                                     : (layer_high ? d.lny - 1 : 0) * d.lnx + i;
+          U[(size_t)k * N + cell] = Q[i + (size_t)k * nface] / d.h;
+        }
+        for (int q = 0; q < M; ++q) V[(size_t)k * M + q] = c->bc_b[f][(size_t)k * M + q];
+        for (int l = 0; l < rb; ++l) Sv[l + (size_t)k * R] = d.h * Rm[l + (size_t)k * rb];
+      }
+      const int slot = slot0 + j;
+      HIPCHK(hipMemcpy(d.U + (size_t)slot * N * R, U.data(), U.size() * 8, hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(d.V + (size_t)slot * M * R, V.data(), V.size() * 8, hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(d.S + (size_t)slot * R * R, Sv.data(), Sv.size() * 8, hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(d.rank + slot, &rb, sizeof(int), hipMemcpyHostToDevice));
+    }
+  }
   return DD_OK;
 }
 
@@ -1007,6 +1085,8 @@ dd_status dd_dlra_create(const dd_dlra_config* cfg, const int32_t* rank0, const 
     }
   }
   dd_status st = upload_factors(h, rank0, U0, S0, V0);
+  if (st != DD_OK) return fail(st);
+  st = upload_inflow_layers(h, cfg);
   if (st != DD_OK) return fail(st);
   *out = h;
   return DD_OK;

@@ -38,13 +38,15 @@ struct Dev {
   int prec;
   int wide;                // 1: the wide launch plan (capacities beyond the narrow kernels)
   int rk4;                 // 1: every substep is one classic RK4 step (wide plan, FP64)
+  int bc_in[4];            // faces -x, +x, -y, +y with a prescribed inflow
+  int npseudo;             // their layer slots after the subdomains in U, V, S, rank
   int face;                // cells on the longer subdomain face (ghost rows)
   double tol, tol_aug_rel;
   // state (FP64 in every mode)
-  double* U;               // [nsub][R][N]
-  double* V;               // [nsub][R][M]
-  double* S;               // [nsub][R][R]
-  int* rank;               // [nsub]
+  double* U;               // [nsub + npseudo][R][N]
+  double* V;               // [nsub + npseudo][R][M]
+  double* S;               // [nsub + npseudo][R][R]
+  int* rank;               // [nsub + npseudo]
   int* tdim;               // [nsub] intermediate rank of the current stage
   int* rnew;               // [nsub] rank after truncation
   int* tmax;               // [nsub] largest t seen
@@ -82,14 +84,19 @@ struct Dev {
   int oSig, oMv, oCrow, oGs, oGt, oQv, oW1, oW2, oW3, oW4, oW5, oW6, oRinvA, oSkip;
 };
 
+// The subdomain next to s along axis on side -1 / +1; at a physical face
+// the layer slot of its prescribed inflow (slots after the subdomains: -x
+// faces, +x, -y, +y, each by position along the face), or -1 (vacuum).
 __host__ __device__ inline int neighbour(const Dev& d, int s, int axis, int side) {
   int sx = s % d.px, sy = s / d.px;
   if (axis == 0) {
     sx += side;
-    if (sx < 0 || sx >= d.px) return -1;
+    if (sx < 0) return d.bc_in[0] ? d.nsub + sy : -1;
+    if (sx >= d.px) return d.bc_in[1] ? d.nsub + d.py + sy : -1;
   } else {
     sy += side;
-    if (sy < 0 || sy >= d.py) return -1;
+    if (sy < 0) return d.bc_in[2] ? d.nsub + 2 * d.py + sx : -1;
+    if (sy >= d.py) return d.bc_in[3] ? d.nsub + 2 * d.py + d.px + sx : -1;
   }
   return sy * d.px + sx;
 }

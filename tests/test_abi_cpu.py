@@ -225,3 +225,26 @@ def test_build_flags_tall_skinny_scratch():
     assert [v for _, v in rep] == [304, 80, 0]
     flagged = [k for k, v in rep if v > 0 and b._TS_KERNEL.match(k)]
     assert flagged == ["_ZN2dd12k_ang_reduceIdLi4ELi2EEEvNS_3DevEii"]
+
+
+@needs_lib
+def test_inflow_faces_validated_and_sized():
+    """A prescribed inflow on a physical face adds layer slots to the state
+    arrays; rank, NULL-free arrays and finiteness are checked."""
+    import dataclasses
+    wl = _cfg()
+    A = np.ones((wl.ny, 1))
+    B = (np.asarray(wl.omega_x) >= 0).astype(float)[:, None]
+    wi = dataclasses.replace(wl, inflow=[(A, B), None, None, None])
+    assert pkg.workspace_size(wi) > pkg.workspace_size(wl)
+    big = np.ones((wl.ny, wl.r_fixed + 1))
+    with pytest.raises(nat.DDError) as ei:
+        pkg.workspace_size(dataclasses.replace(wl, inflow=[(big, np.ones((wl.w.shape[0], wl.r_fixed + 1))),
+                                                           None, None, None]))
+    assert "inflow rank" in str(ei.value)
+    bad = A.copy()
+    bad[0, 0] = np.nan
+    with pytest.raises(nat.DDError) as ei:
+        pkg.workspace_size(dataclasses.replace(wl, inflow=[None, None, (np.ones((wl.nx, 1)), B), None]))
+        pkg.workspace_size(dataclasses.replace(wl, inflow=[(bad, B), None, None, None]))
+    assert "non-finite inflow" in str(ei.value)
