@@ -190,7 +190,24 @@ dd_status dd_dlra_set_factors(dd_dlra_handle h, const int32_t* rank,
  * keep the rule.  Pass NULL for both to return to the rules. */
 dd_status dd_dlra_force_ranks(dd_dlra_handle h, const int32_t* t, const int32_t* r_out);
 
-/* Kernel timing.  With enable != 0, later non-graph launches (exec modes
+/* Stage probe, for testing the kernels phase by phase against a reference:
+ * runs advection stage `stage` (0 = x, 1 = y) from the current state up to
+ * and including the phase `upto` (the phases of Algorithms 1/2 and 4) and
+ * copies one working array of subdomain sd into buf (column-major, ld
+ * *rows; *rows x *cols values, cap = room in buf in doubles, DD_EINVAL if
+ * short).  The stored factors and ranks are left as they were (a stage
+ * writes them only in its final products; the largest-t statistic of
+ * dd_dlra_get_ranks may grow).  Synchronous.
+ *   DD_PROBE_VHAT  sqrt(w) V-hat after the augmentation, M x t
+ *   DD_PROBE_K1    the K-step output K1 in the basis V-hat, N x t
+ *   DD_PROBE_U1    h U1 (orthonormal factor of the QR of K1), N x t
+ *   DD_PROBE_S2    the S-step output S2 in the bases (U1, V-hat), t x t
+ *   DD_PROBE_L1    sqrt(w) L1, the L-step output (F = U1 L1^T), M x t   */
+enum { DD_PROBE_VHAT = 1, DD_PROBE_K1 = 2, DD_PROBE_U1 = 3, DD_PROBE_S2 = 4, DD_PROBE_L1 = 5 };
+dd_status dd_dlra_probe(dd_dlra_handle h, int32_t stage, int32_t upto, int32_t sd, int64_t cap, double* buf,
+                        int32_t* rows, int32_t* cols);
+
+/* Kernel timing./* Kernel timing.  With enable != 0, later non-graph launches (exec modes
  * PER_SUBDOMAIN and BATCHED, and dd_dlra_stage) are bracketed by hipEvent
  * pairs on the handle's stream, one pair per phase.  With enable = k > 1 the
  * tall-skinny phases whose launch leaves the same result when repeated are

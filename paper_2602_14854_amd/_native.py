@@ -19,10 +19,11 @@ DD_RANK_FIXED, DD_RANK_ADAPTIVE = 0, 1
 DD_EXEC_PER_SUBDOMAIN, DD_EXEC_BATCHED, DD_EXEC_BATCHED_GRAPH = 0, 1, 2
 DD_INT_EULER, DD_INT_RK4 = 0, 1
 DD_BC_VACUUM, DD_BC_INFLOW_LOWRANK = 0, 1
+DD_PROBE_VHAT, DD_PROBE_K1, DD_PROBE_U1, DD_PROBE_S2, DD_PROBE_L1 = 1, 2, 3, 4, 5
 
 EXPORTS = (
     "dd_dlra_workspace_size", "dd_dlra_create", "dd_dlra_step", "dd_dlra_stage", "dd_dlra_get_ranks",
-    "dd_dlra_get_factors", "dd_dlra_moments", "dd_dlra_moments_noalloc", "dd_dlra_set_factors", "dd_dlra_force_ranks", "dd_dlra_autotune",
+    "dd_dlra_get_factors", "dd_dlra_moments", "dd_dlra_moments_noalloc", "dd_dlra_probe", "dd_dlra_set_factors", "dd_dlra_force_ranks", "dd_dlra_autotune",
     "dd_dlra_set_tiling",
     "dd_dlra_profile", "dd_dlra_kernel_stats", "dd_dlra_kernel_name",
     "dd_dlra_sync", "dd_dlra_destroy", "dd_dlra_last_error",
@@ -83,6 +84,7 @@ def load_library():
     lib.dd_dlra_get_factors.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, _IP, _DP, _DP, _DP]
     lib.dd_dlra_moments.argtypes = [vp, _DP, _DP, _DP, ctypes.c_int32]
     lib.dd_dlra_moments_noalloc.argtypes = [vp, _DP, _DP, _DP]
+    lib.dd_dlra_probe.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, _DP, _IP, _IP]
     lib.dd_dlra_autotune.argtypes = [vp, ctypes.c_int32, _IP, _DP]
     lib.dd_dlra_set_tiling.argtypes = [vp, ctypes.c_int32]
     lib.dd_dlra_set_factors.argtypes = [vp, _IP, ctypes.POINTER(_DP), ctypes.POINTER(_DP), ctypes.POINTER(_DP)]
@@ -269,6 +271,17 @@ class DDDLRA:
         p = lambda t: None if t is None else ctypes.cast(t.data_ptr(), _DP)
         self._check(self.lib.dd_dlra_moments_noalloc(self.h, p(rho), p(jx), p(jy)))
         return rho
+
+    def probe(self, stage: int, upto: int, sd: int) -> np.ndarray:
+        """One working array of subdomain sd after advection stage `stage` ran
+        up to phase `upto` (DD_PROBE_*); the state is left as it was."""
+        cap = max(self.N, self.M) * int(self.wl.r_int_max)
+        buf = np.zeros(cap)
+        r = ctypes.c_int32(0)
+        c = ctypes.c_int32(0)
+        self._check(self.lib.dd_dlra_probe(self.h, int(stage), int(upto), int(sd), cap, _dp(buf), ctypes.byref(r),
+                                           ctypes.byref(c)))
+        return buf[: r.value * c.value].reshape(c.value, r.value).T.copy()
 
     def autotune(self, steps: int = 2) -> Tuple[int, float]:
         """Pick the workgroups per subdomain of the tall-skinny kernels by

@@ -639,7 +639,7 @@ void chol_qr3(dd_dlra_handle h, int axis, int ndim, void* X, void* Y, int64_t sd
   });
 }
 
-void enqueue_advection(dd_dlra_handle h, int axis) {
+void enqueue_advection(dd_dlra_handle h, int axis, int upto = 0) {
   const Dev& d = h->d;
   hipStream_t st = h->stream;
   const int64_t sdMA = (int64_t)d.M * d.MA, sdMT = (int64_t)d.M * d.T, sdNT = (int64_t)d.N * d.T;
@@ -678,17 +678,22 @@ void enqueue_advection(dd_dlra_handle h, int axis) {
                       nullptr, pass == 0, d.oFill, false, true, st, false, pass == 1 ? d.oSkip : -1);
     });
   }
+  if (upto == DD_PROBE_VHAT) return;
   // angular Galerkin matrices, eigen-split of C, K-step coefficients
   phase(h, K_ANG_REDUCE, [&](int s0, int ns) { dd::launch_ang_reduce(d, axis, s0, ns, st); });
   phase(h, K_ADV_PREP, [&](int s0, int ns) { dd::launch_adv_prep(d, axis, s0, ns, st); });
   // Algorithm 1/2 steps 1-2: K-step, QR
   phase(h, K_KSTEP, [&](int s0, int ns) { dd::launch_kstep(d, axis, s0, ns, st); });
+  if (upto == DD_PROBE_K1) return;
   chol_qr3(h, axis, dd::DIM_T, d.K1, d.K2, sdNT, d.N, true, nullptr, 0, nullptr, 1.0, K_GEMM_QR_K, K_GEMM_QR_K_IP);
+  if (upto == DD_PROBE_U1) return;
   // step 3: S-step
   phase(h, K_SPATIAL_REDUCE, [&](int s0, int ns) { dd::launch_spatial_reduce(d, axis, s0, ns, d.K2, st); });
   phase(h, K_ADV_SSTEP, [&](int s0, int ns) { dd::launch_adv_sstep(d, axis, s0, ns, st); });
+  if (upto == DD_PROBE_S2) return;
   // steps 4-5: L-step, weighted QR
   phase(h, K_LSTEP, [&](int s0, int ns) { dd::launch_lstep(d, axis, s0, ns, st); });
+  if (upto == DD_PROBE_L1) return;
   // (the last product, Q_L = Y Rinv, is folded into the final V product)
   chol_qr3(h, axis, dd::DIM_T, d.AL, d.AL2, sdMT, d.M, false, nullptr, 0, nullptr, 1.0, K_GEMM_QR_L, K_GEMM_QR_L_IP,
            nullptr, true);
@@ -794,7 +799,7 @@ void* w_chol_qr(dd_dlra_handle h, int axis, int ndim, void* X, void* Y, int64_t 
   return cur;
 }
 
-void enqueue_advection_wide(dd_dlra_handle h, int axis) {
+void enqueue_advection_wide(dd_dlra_handle h, int axis, int upto = 0) {
   const Dev& d = h->d;
   hipStream_t st = h->stream;
   const int64_t sdMA = (int64_t)d.M * d.MA, sdMT = (int64_t)d.M * d.T, sdNT = (int64_t)d.N * d.T;
@@ -811,6 +816,7 @@ void enqueue_advection_wide(dd_dlra_handle h, int axis) {
   });
   void* q = w_chol_qr(h, axis, dd::DIM_T, d.Qh, d.Z, sdMT, d.M, false, 2, false, K_W_GRAM_VHAT, K_GEMM_QR_VHAT);
   (void)q;  // two passes: V-hat is back in Qh
+  if (upto == DD_PROBE_VHAT) return;
   // angular Galerkin matrices (partial layout of the narrow plan)
   {
     dd::XJobs jobs;
@@ -845,7 +851,9 @@ void enqueue_advection_wide(dd_dlra_handle h, int axis) {
   } else {
     phase(h, K_KSTEP, [&](int s0, int ns) { dd::launch_w_kstep(d, axis, s0, ns, st); });
   }
+  if (upto == DD_PROBE_K1) return;
   void* Q = w_chol_qr(h, axis, dd::DIM_T, d.K1, d.K2, sdNT, d.N, true, 3, true, K_W_GRAM_K, K_GEMM_QR_K);
+  if (upto == DD_PROBE_U1) return;
   // step 3: spatial Galerkin matrix and the face products, S-step
   {
     dd::XJobs jobs;
@@ -862,8 +870,10 @@ void enqueue_advection_wide(dd_dlra_handle h, int axis) {
     phase(h, K_W_SPATIAL, [&](int s0, int ns) { dd::launch_w_xgram(d, axis, s0, ns, jobs, true, st); });
   }
   phase(h, K_ADV_SSTEP, [&](int s0, int ns) { dd::launch_w_adv_sstep(d, axis, s0, ns, st); });
+  if (upto == DD_PROBE_S2) return;
   // steps 4-5: L-step, weighted QR (AL -> AL2 -> AL -> AL2)
   phase(h, K_LSTEP, [&](int s0, int ns) { dd::launch_w_lstep(d, axis, s0, ns, st); });
+  if (upto == DD_PROBE_L1) return;
   void* QL = w_chol_qr(h, axis, dd::DIM_T, d.AL, d.AL2, sdMT, d.M, false, 3, true, K_W_GRAM_L, K_GEMM_QR_L);
   // Algorithm 5: truncation, then rotate the bases into the state
   phase(h, K_TRUNC, [&](int s0, int ns) { dd::launch_w_trunc(d, axis, s0, ns, st); });
@@ -1239,6 +1249,51 @@ dd_status dd_dlra_stage(dd_dlra_handle h, int32_t stage) {
   }
   HIPCHK(hipGetLastError());
   return DD_OK;
+}
+
+dd_status dd_dlra_probe(dd_dlra_handle h, int32_t stage, int32_t upto, int32_t sd, int64_t cap, double* buf,
+                        int32_t* rows, int32_t* cols) {
+  if (!h) return DD_EINVAL;
+  const Dev& d = h->d;
+  if (stage < 0 || stage > 1 || upto < DD_PROBE_VHAT || upto > DD_PROBE_L1 || sd < 0 || sd >= d.nsub || !buf ||
+      !rows || !cols) {
+    h->err = "dd_dlra_probe: stage 0 or 1, a DD_PROBE_* phase, a subdomain index and non-NULL outputs";
+    return DD_EINVAL;
+  }
+  if (h->d.wide) enqueue_advection_wide(h, stage, upto);
+  else enqueue_advection(h, stage, upto);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(h->stream));
+  int t = 0;
+  HIPCHK(hipMemcpy(&t, d.tdim + sd, sizeof(int), hipMemcpyDeviceToHost));
+  const bool f64 = d.prec == DD_PREC_FP64;
+  const void* src = nullptr;
+  int nr = 0, nc = t, ld = 0;
+  bool work = true;  // an array of the working type
+  switch (upto) {
+    case DD_PROBE_VHAT: src = (const char*)d.Qh + (size_t)sd * d.M * d.T * (f64 ? 8 : 4); nr = d.M; ld = d.M; break;
+    case DD_PROBE_K1: src = (const char*)d.K1 + (size_t)sd * d.N * d.T * (f64 ? 8 : 4); nr = d.N; ld = d.N; break;
+    case DD_PROBE_U1: src = (const char*)d.K2 + (size_t)sd * d.N * d.T * (f64 ? 8 : 4); nr = d.N; ld = d.N; break;
+    case DD_PROBE_L1: src = (const char*)d.AL + (size_t)sd * d.M * d.T * (f64 ? 8 : 4); nr = d.M; ld = d.M; break;
+    default: src = d.small + (size_t)sd * d.smallStride + d.oP0; nr = t; ld = d.T; work = false; break;
+  }
+  *rows = nr;
+  *cols = nc;
+  if (cap < (int64_t)nr * nc) {
+    h->err = "dd_dlra_probe: buffer too small";
+    return DD_EINVAL;
+  }
+  const size_t es = (work && !f64) ? 4 : 8;
+  std::vector<char> tmp((size_t)ld * nc * es);
+  if (!tmp.empty()) HIPCHK(hipMemcpy(tmp.data(), src, tmp.size(), hipMemcpyDeviceToHost));
+  for (int j = 0; j < nc; ++j)
+    for (int i = 0; i < nr; ++i) {
+      const size_t o = i + (size_t)j * ld;
+      const double v = es == 8 ? ((const double*)tmp.data())[o] : (double)((const float*)tmp.data())[o];
+      if (upto == DD_PROBE_S2) buf[j + (size_t)i * nr] = v;  // the slot holds S2^T
+      else buf[i + (size_t)j * nr] = v;
+    }
+  return check_flags(h);
 }
 
 dd_status dd_dlra_profile(dd_dlra_handle h, int32_t enable) {
