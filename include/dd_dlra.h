@@ -207,7 +207,7 @@ enum { DD_PROBE_VHAT = 1, DD_PROBE_K1 = 2, DD_PROBE_U1 = 3, DD_PROBE_S2 = 4, DD_
 dd_status dd_dlra_probe(dd_dlra_handle h, int32_t stage, int32_t upto, int32_t sd, int64_t cap, double* buf,
                         int32_t* rows, int32_t* cols);
 
-/* Kernel timing./* Kernel timing.  With enable != 0, later non-graph launches (exec modes
+/* Kernel timing.  With enable != 0, later non-graph launches (exec modes
  * PER_SUBDOMAIN and BATCHED, and dd_dlra_stage) are bracketed by hipEvent
  * pairs on the handle's stream, one pair per phase.  With enable = k > 1 the
  * tall-skinny phases whose launch leaves the same result when repeated are

@@ -316,32 +316,31 @@ __device__ __forceinline__ void sum_partials(const Dev& d, int s, int ngp, int o
   sum_partials_blocks<1>(d, s, ngp, blk);
 }
 
-// sum over aligned groups of G lanes (G = 1, 2, 4, 8 or 16) with DPP
+// a double moved across lanes by the DPP pattern CTRL (every lane has a
+// source in the patterns used here, so no old value is needed)
+template <int CTRL>
+__device__ __forceinline__ double dpp_double(double v) {
+  union { double d; int i[2]; } a, b;
+  a.d = v;
+  b.i[0] = __builtin_amdgcn_mov_dpp(a.i[0], CTRL, 0xF, 0xF, true);
+  b.i[1] = __builtin_amdgcn_mov_dpp(a.i[1], CTRL, 0xF, 0xF, true);
+  return b.d;
+}
+
+// sum over aligned groups of G lanes (G = 1, 2, 4, 8 or 16) with DPP; each
+// step adds a lane's partner, so every lane of a group ends with the same
+// bits
 template <int G>
 __device__ __forceinline__ double group_sum_dpp(double v) {
   if (G == 1) return v;
-  union { double d; int i[2]; } a, b;
-  a.d = v;
-  // quad_perm [1,0,3,2]: partner lane ^ 1
-  b.i[0] = __builtin_amdgcn_update_dpp(0, a.i[0], 0xB1, 0xF, 0xF, false);
-  b.i[1] = __builtin_amdgcn_update_dpp(0, a.i[1], 0xB1, 0xF, 0xF, false);
-  a.d += b.d;
-  if (G == 2) return a.d;
-  // quad_perm [2,3,0,1]: partner lane ^ 2
-  b.i[0] = __builtin_amdgcn_update_dpp(0, a.i[0], 0x4E, 0xF, 0xF, false);
-  b.i[1] = __builtin_amdgcn_update_dpp(0, a.i[1], 0x4E, 0xF, 0xF, false);
-  a.d += b.d;
-  if (G == 4) return a.d;
-  // row_half_mirror: lane i <-> 7 - i inside each group of 8 (quads are uniform)
-  b.i[0] = __builtin_amdgcn_update_dpp(0, a.i[0], 0x141, 0xF, 0xF, false);
-  b.i[1] = __builtin_amdgcn_update_dpp(0, a.i[1], 0x141, 0xF, 0xF, false);
-  a.d += b.d;
-  if (G == 8) return a.d;
-  // row_mirror: lane i <-> 15 - i inside each row of 16
-  b.i[0] = __builtin_amdgcn_update_dpp(0, a.i[0], 0x140, 0xF, 0xF, false);
-  b.i[1] = __builtin_amdgcn_update_dpp(0, a.i[1], 0x140, 0xF, 0xF, false);
-  a.d += b.d;
-  return a.d;
+  v += dpp_double<0xB1>(v);   // quad_perm [1,0,3,2]: partner lane ^ 1
+  if (G == 2) return v;
+  v += dpp_double<0x4E>(v);   // quad_perm [2,3,0,1]: partner lane ^ 2
+  if (G == 4) return v;
+  v += dpp_double<0x141>(v);  // row_half_mirror: lane i <-> 7 - i in each 8 (quads are uniform)
+  if (G == 8) return v;
+  v += dpp_double<0x140>(v);  // row_mirror: lane i <-> 15 - i in each row of 16
+  return v;
 }
 
 // Plane rotation that orthogonalises two columns with squared norms al, be

@@ -12,14 +12,14 @@
 // operands straight into the matrix-core lane layout and leave one 64 x 64
 // block of one partial per workgroup.
 //
-// Small per-subdomain kernels run one workgroup of 1024 threads per
-// subdomain.  Matrices of order up to 128 sit in LDS; the augmentation Gram
-// (order up to 192) is kept as a packed lower triangle.  The one-sided
-// Jacobi SVD keeps its columns in registers: 16 wavefronts hold the column
-// pairs of a round-robin (caterpillar) ordering, the two columns of a pair
-// spread over the 64 lanes, and after each round only the pairs at the ends
-// of a wavefront's run exchange a column with the neighbouring wavefront
-// through LDS.
+// Small per-subdomain kernels run one workgroup per subdomain (1024
+// threads; the two SVD kernels 512).  Matrices of order up to 128 sit in
+// LDS; the augmentation Gram (order up to 192) is kept as a packed lower
+// triangle.  The one-sided Jacobi SVD keeps its columns in registers: each
+// lane group of 16 holds a few column pairs of a round-robin (caterpillar)
+// ordering, a pair's rows spread over the group's lanes, so a wavefront works
+// on four pairs at once; after each round only the columns at the ends of a
+// group's run move, to the neighbouring group.
 #include <algorithm>
 #include <type_traits>
 
@@ -748,7 +748,7 @@ __device__ __forceinline__ double s_sum(double v, double* red) {
   if (lane == 0) red[wave] = v;
   __syncthreads();
   double r = 0.0;
-  for (int w = 0; w < SNW; ++w) r += red[w];
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r += red[w];
   __syncthreads();
   return r;
 }
@@ -760,7 +760,7 @@ __device__ __forceinline__ double s_max(double v, double* red) {
   if (lane == 0) red[wave] = v;
   __syncthreads();
   double r = red[0];
-  for (int w = 1; w < SNW; ++w) r = fmax(r, red[w]);
+  for (int w = 1; w < (int)(blockDim.x >> 6); ++w) r = fmax(r, red[w]);
   __syncthreads();
   return r;
 }
@@ -1017,242 +1017,382 @@ __device__ void lds_tri_inv(double* L, int n, double* colj) {
 }
 
 // ----------------------------------------------------------------------------
-// One-sided Jacobi with the columns in registers.  Pair slots: processor p
-// (0 <= p < P = n2/2) is slot k = p % PPW of wavefront p / PPW; it holds
-// columns top and bot (rows = lane + 64 i, i < RPL) and, with ACC, the
-// matching columns of the accumulated rotation J (n rows, JRPL per lane).
+// One-sided Jacobi with the columns in registers ("group ring").  The SVD
+// kernels run JTHR threads; lane l of a wavefront belongs to group l % 4, so
+// each wavefront holds four groups of 16 lanes, and group gi = 4 wave + l % 4
+// holds the pair slots p = gi PPG + k (k < PPG): a top and a bottom column,
+// row l / 4 + 16 i in register i of lane l, with ACC the matching columns
+// of the accumulated rotation J, and the squared norms of both columns (the
+// same value in every lane of the group).  A pair's inner product is summed
+// over its 16 lanes by partner exchanges (DPP row rotations by 8 and 4, then
+// swaps of rows and of wavefront halves), each of which adds the same two
+// values on both sides, so every lane of the group gets the same bits and
+// forms the same rotation: four pairs share each instruction and no value
+// has to be read back from a single lane.
+//
 // After each round the columns move by the caterpillar rule
 //   top'[0] = top[0], top'[1] = bot[0], top'[p] = top[p-1] (p >= 2),
 //   bot'[p] = bot[p+1] (p <= P-2), bot'[P-1] = top[P-1],
-// which meets every pair once in n2 - 1 rounds.  Moves inside a wavefront
-// are register copies; the two columns that cross to a neighbouring
-// wavefront go through a double-buffered LDS area (one barrier per round).
-// The squared column norms travel with the columns and are updated with
-// each rotation (|x'|^2 = c^2 |x|^2 - 2 c s x.y + s^2 |y|^2, and likewise),
-// recomputed exactly at the start of every sweep, so a round sums one inner
-// product per pair; the rotation parameters of a wavefront's pairs are
-// formed side by side in its first lanes and read back as scalars.
+// which meets every pair once in n2 - 1 rounds.  Inside a group the moves
+// are renamings: in phase ph of the round counter (mod PPG) logical top k is
+// register (k - ph) mod PPG and logical bottom k is register (k + ph) mod
+// PPG, so only the outgoing top of the last slot and the outgoing bottom of
+// the first slot of each group move: to the neighbouring group of the same
+// wavefront by a DPP rotation inside each quad of lanes, across wavefronts
+// through a double-buffered LDS area (one barrier per round).  Slots p >= P
+// are inactive: they never rotate, and what drifts into them never flows
+// back.  The squared norms are updated with each rotation (|x'|^2 = c^2 |x|^2
+// - 2 c s x.y + s^2 |y|^2, and likewise) and recomputed exactly at the start
+// of every sweep.
 // ----------------------------------------------------------------------------
-template <int PPW, int RPL, bool ACC, int JRPL>
-struct RingCols {
-  double tp[PPW][RPL], bt[PPW][RPL];
-  double jt[PPW][ACC ? JRPL : 1], jb[PPW][ACC ? JRPL : 1];
+constexpr int JTHR = 512;          // threads of the SVD kernels
+constexpr int JNW = JTHR / 64;
+constexpr int JNG = 4 * JNW;       // lane groups of 16
+
+template <int PPG, int RPL, bool ACC, int JRPL>
+struct GRing {
+  static constexpr int JR = ACC ? JRPL : 1;
+  static constexpr int CW = RPL + (ACC ? JRPL : 0) + 1;  // values per lane of one moving column
+  double t[RPL][PPG], b[RPL][PPG];
+  double jt[JR][PPG], jb[JR][PPG];
+  double nt[PPG], nb[PPG];
 };
 
-// LDS doubles needed by ring_jacobi: a moving column carries its rows and
-// the rows of its J column (double-buffered, both directions), and its
-// squared norm, one value per wavefront
-template <int RPL, int JRPL, bool ACC>
-constexpr int ring_lds_doubles() { return 2 * 2 * SNW * 64 * (RPL + (ACC ? JRPL : 0)) + 2 * 2 * SNW; }
+// LDS doubles of the wavefront-boundary exchange: [buffer][direction][wave][CW][16]
+template <int CW>
+constexpr int gring_lds_doubles() { return 2 * 2 * JNW * CW * 16; }
 
-// a wave-uniform double moved to scalar registers (keeps the per-pair
-// norms and inner products out of the vector register budget)
-__device__ __forceinline__ double uni(double x) {
-  union { double d; int i[2]; } a;
-  a.d = x;
-  a.i[0] = __builtin_amdgcn_readfirstlane(a.i[0]);
-  a.i[1] = __builtin_amdgcn_readfirstlane(a.i[1]);
-  return a.d;
+// a double swapped between the two rows of each pair of rows (R = 16) or
+// between the two halves of the wavefront (R = 32): returns both values, in
+// the same order on both sides
+template <int R>
+__device__ __forceinline__ void lane_swap(double v, double& a, double& b) {
+  union { double d; unsigned u[2]; } x, p, q;
+  x.d = v;
+  if (R == 16) {
+    const auto lo = __builtin_amdgcn_permlane16_swap(x.u[0], x.u[0], false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(x.u[1], x.u[1], false, false);
+    p.u[0] = lo[0]; q.u[0] = lo[1]; p.u[1] = hi[0]; q.u[1] = hi[1];
+  } else {
+    const auto lo = __builtin_amdgcn_permlane32_swap(x.u[0], x.u[0], false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(x.u[1], x.u[1], false, false);
+    p.u[0] = lo[0]; q.u[0] = lo[1]; p.u[1] = hi[0]; q.u[1] = hi[1];
+  }
+  a = p.d;
+  b = q.d;
 }
 
-// Returns the sweeps done (negative if not converged within max_sweeps).
-template <int PPW, int RPL, bool ACC, int JRPL>
-__device__ int ring_jacobi(const Dev& d, RingCols<PPW, RPL, ACC, JRPL>& c, int rows, int n, double tol,
-                           double floor_rel, int max_sweeps, double* xbuf, double* red, int* rotflag) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int n2 = n + (n & 1);
-  const int P = n2 / 2;
-  const int p0 = wave * PPW;
-  // squared Frobenius norm for the noise floor
-  double part = 0.0;
+// sum over the 16 lanes of a group (lanes of one residue mod 4), the same
+// bits in every one of them
+__device__ __forceinline__ double class_sum16(double v) {
+  v += dpp_double<0x128>(v);  // row_ror:8, partner lane i + 8 in its row
+  v += dpp_double<0x124>(v);  // row_ror:4 (the values repeat with period 8 now)
+  double a, b;
+  lane_swap<16>(v, a, b);
+  v = a + b;
+  lane_swap<32>(v, a, b);
+  return a + b;
+}
+
+// the value of the previous / next group of the same quad (group 0 gets
+// group 3's, group 3 gets group 0's)
+__device__ __forceinline__ double from_prev_group(double v) { return dpp_double<0x93>(v); }  // quad_perm [3,0,1,2]
+__device__ __forceinline__ double from_next_group(double v) { return dpp_double<0x39>(v); }  // quad_perm [1,2,3,0]
+
+// a lane's place in the group ring
+struct GPos {
+  int l16, g, wave, gi;
+  int P, gP, kP;        // active pair slots, group and slot of the last one
+  bool special;         // the wavefront holds slot 0 or slot P - 1 (uniform)
+  bool rdT, rdB;        // the lane takes its incoming top / bottom from LDS
+};
+
+// The moves of one row inside a wavefront (T[k] / B[k]: the row's values
+// in the top / bottom registers k).  Lanes of groups 0 and 3 receive a value
+// here that is replaced after the barrier.  The special form also applies
+// the rules of the two ends of the ring: slot 0 keeps its top and takes its
+// bottom as top'[1], and the last active slot P - 1 takes its top as its
+// new bottom.
+template <int PPG, int PH>
+__device__ __forceinline__ void gx_plain(double (&T)[PPG], double (&B)[PPG], const GPos& x) {
+  constexpr int OTP = (2 * PPG - 1 - PH) % PPG;  // logical top PPG-1
+  constexpr int OBP = PH % PPG;                   // logical bottom 0
+  T[OTP] = from_prev_group(T[OTP]);
+  B[OBP] = from_next_group(B[OBP]);
+}
+
+template <int PPG, int PH>
+__device__ __forceinline__ void gx_special(double (&T)[PPG], double (&B)[PPG], const GPos& x) {
+  constexpr int OTP = (2 * PPG - 1 - PH) % PPG;
+  constexpr int OBP = PH % PPG;
+  constexpr int T0P = (PPG - PH) % PPG;           // logical top 0
+  const double oldT = T[OTP], oldB = B[OBP], t0 = T[T0P];
+  const double inT = from_prev_group(oldT), inB = from_next_group(oldB);
+  const bool last = x.gi == x.gP;
 #pragma unroll
-  for (int k = 0; k < PPW; ++k)
+  for (int kk = 0; kk + 1 < PPG; ++kk)
+    if (last && x.kP == kk) B[(kk + PH + 1) % PPG] = T[(kk - PH + PPG) % PPG];
+  B[OBP] = (last && x.kP == PPG - 1) ? oldT : inB;
+  T[OTP] = x.gi == 0 ? t0 : inT;
+  if (x.gi == 0) T[T0P] = oldB;
+}
+
+// One round in phase PH: rotate every active pair, then move the columns.
+// Returns true if this lane rotated a pair.
+template <int PH, int PPG, int RPL, bool ACC, int JRPL>
+__device__ __forceinline__ bool gring_round(GRing<PPG, RPL, ACC, JRPL>& c, const GPos& x, double floor2, double tol2,
+                                            bool move, double* xbuf, int buf) {
+  using GR = GRing<PPG, RPL, ACC, JRPL>;
+  bool rot = false;
+  if (__builtin_amdgcn_readfirstlane(x.wave) * 4 * PPG < x.P) {  // a wavefront with active slots
+    double ga[PPG];
 #pragma unroll
-    for (int i = 0; i < RPL; ++i) part = fma(c.tp[k][i], c.tp[k][i], fma(c.bt[k][i], c.bt[k][i], part));
-  const double floor2 = floor_rel * floor_rel * s_sum(part, red);
-  const double tol2 = tol * tol;
-  if (n2 <= 1) return 0;
-  constexpr int CW = RPL + (ACC ? JRPL : 0);  // doubles per lane of one moving column
-  double* nbuf = xbuf + 2 * 2 * SNW * 64 * CW;   // [buf][direction][wave] norms
-  bool converged = false;
-  int sweeps = 0;
-  int buf = 0;
-  double nt[PPW], nb[PPW];
-  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-    sweeps = sweep + 1;
-    bool rot = false;
-    // exact squared norms at the start of the sweep
+    for (int k = 0; k < PPG; ++k) {
+      const int pt = (k - PH + PPG) % PPG, pb = (k + PH) % PPG;
+      double s = 0.0;
 #pragma unroll
-    for (int k = 0; k < PPW; ++k) {
-      double a = 0.0, b = 0.0;
-#pragma unroll
-      for (int i = 0; i < RPL; ++i) {
-        a = fma(c.tp[k][i], c.tp[k][i], a);
-        b = fma(c.bt[k][i], c.bt[k][i], b);
-      }
-      nt[k] = uni(wave_sum(a));
-      nb[k] = uni(wave_sum(b));
+      for (int i = 0; i < RPL; ++i) s = fma(c.t[i][pt], c.b[i][pb], s);
+      ga[k] = class_sum16(s);
     }
-    for (int round = 0; round < n2 - 1; ++round) {
-      double g[PPW];
 #pragma unroll
-      for (int k = 0; k < PPW; ++k) {
-        double ga = 0.0;
-#pragma unroll
-        for (int i = 0; i < RPL; ++i) ga = fma(c.tp[k][i], c.bt[k][i], ga);
-        g[k] = uni(wave_sum(ga));
-      }
-      // lane k < PPW forms the rotation of pair k
-      double al = nt[0], be = nb[0], ga = g[0];
-#pragma unroll
-      for (int k = 1; k < PPW; ++k)
-        if (lane == k) {
-          al = nt[k];
-          be = nb[k];
-          ga = g[k];
-        }
-      const bool mine = lane < PPW && p0 + lane < P;
-      const bool dorot = mine && ga != 0.0 && al > floor2 && be > floor2 && ga * ga > tol2 * al * be;
-      double cs = 1.0, sn = 0.0;
-      if (dorot) jacobi_rotation(al, be, ga, cs, sn);
-      const int flag = dorot ? 1 : 0;
-#pragma unroll
-      for (int k = 0; k < PPW; ++k) {
-        if (__builtin_amdgcn_readlane(flag, k)) {
-          const double ck = lane_value(cs, k), sk = lane_value(sn, k);
-#pragma unroll
-          for (int i = 0; i < RPL; ++i) {
-            const double x = c.tp[k][i], y = c.bt[k][i];
-            c.tp[k][i] = ck * x - sk * y;
-            c.bt[k][i] = fma(sk, x, ck * y);
-          }
-          if (ACC) {
-#pragma unroll
-            for (int i = 0; i < JRPL; ++i) {
-              const double x = c.jt[k][i], y = c.jb[k][i];
-              c.jt[k][i] = ck * x - sk * y;
-              c.jb[k][i] = fma(sk, x, ck * y);
-            }
-          }
-          const double a = nt[k], b = nb[k], cg = 2.0 * ck * sk * g[k];
-          nt[k] = uni(fma(ck * ck, a, fma(sk * sk, b, -cg)));
-          nb[k] = uni(fma(sk * sk, a, fma(ck * ck, b, cg)));
-          rot = true;
-        }
-      }
-      if (P == 1) continue;  // a single pair: nothing moves
-      // columns leaving the wavefront: top of the last slot (to the next
-      // wavefront), bottom of the first slot (to the previous one)
-      double* ob = xbuf + buf * (2 * SNW * 64 * CW);
-      double* outT = ob + (0 * SNW + wave) * 64 * CW;
-      double* outB = ob + (1 * SNW + wave) * 64 * CW;
+    for (int k = 0; k < PPG; ++k) {
+      const int pt = (k - PH + PPG) % PPG, pb = (k + PH) % PPG;
+      const double al = c.nt[pt], be = c.nb[pb], g = ga[k];
+      const bool act = x.gi * PPG + k < x.P;
+      const bool dorot = act && g != 0.0 && al > floor2 && be > floor2 && g * g > tol2 * al * be;
+      // every lane applies a rotation, the identity (c = 1, s = 0: exact)
+      // where the pair is left alone, so no branch splits the groups
+      double cs, sn;
+      jacobi_rotation(al, be, g, cs, sn);
+      cs = dorot ? cs : 1.0;
+      sn = dorot ? sn : 0.0;
 #pragma unroll
       for (int i = 0; i < RPL; ++i) {
-        outT[i * 64 + lane] = c.tp[PPW - 1][i];
-        outB[i * 64 + lane] = c.bt[0][i];
+        const double u = c.t[i][pt], v = c.b[i][pb];
+        c.t[i][pt] = cs * u - sn * v;
+        c.b[i][pb] = fma(sn, u, cs * v);
       }
       if (ACC) {
 #pragma unroll
-        for (int i = 0; i < JRPL; ++i) {
-          outT[(RPL + i) * 64 + lane] = c.jt[PPW - 1][i];
-          outB[(RPL + i) * 64 + lane] = c.jb[0][i];
+        for (int i = 0; i < GR::JR; ++i) {
+          const double u = c.jt[i][pt], v = c.jb[i][pb];
+          c.jt[i][pt] = cs * u - sn * v;
+          c.jb[i][pb] = fma(sn, u, cs * v);
         }
       }
-      if (lane == 0) {
-        nbuf[(buf * 2 + 0) * SNW + wave] = nt[PPW - 1];
-        nbuf[(buf * 2 + 1) * SNW + wave] = nb[0];
-      }
-      __syncthreads();
-      const double* inT = ob + (0 * SNW + (wave > 0 ? wave - 1 : 0)) * 64 * CW;
-      const double* inB = ob + (1 * SNW + (wave < SNW - 1 ? wave + 1 : wave)) * 64 * CW;
-      // in place: bottoms first in ascending slot order (each reads the old
-      // value of the next slot), then tops in descending order (each reads
-      // the old value of the previous slot); bot[0] is kept for top'[1]
-      double b0[RPL], jb0[ACC ? JRPL : 1];
-#pragma unroll
-      for (int i = 0; i < RPL; ++i) b0[i] = c.bt[0][i];
-      if (ACC)
-#pragma unroll
-        for (int i = 0; i < JRPL; ++i) jb0[i] = c.jb[0][i];
-      const double nb0 = nb[0];
-#pragma unroll
-      for (int k = 0; k < PPW; ++k) {
-        const int p = p0 + k;
-        if (p == P - 1) {
-#pragma unroll
-          for (int i = 0; i < RPL; ++i) c.bt[k][i] = c.tp[k][i];
-          if (ACC)
-#pragma unroll
-            for (int i = 0; i < JRPL; ++i) c.jb[k][i] = c.jt[k][i];
-          nb[k] = nt[k];
-        } else if (k == PPW - 1) {
-#pragma unroll
-          for (int i = 0; i < RPL; ++i) c.bt[k][i] = inB[i * 64 + lane];
-          if (ACC)
-#pragma unroll
-            for (int i = 0; i < JRPL; ++i) c.jb[k][i] = inB[(RPL + i) * 64 + lane];
-          nb[k] = uni(nbuf[(buf * 2 + 1) * SNW + (wave < SNW - 1 ? wave + 1 : wave)]);
-        } else {
-#pragma unroll
-          for (int i = 0; i < RPL; ++i) c.bt[k][i] = c.bt[k + 1][i];
-          if (ACC)
-#pragma unroll
-            for (int i = 0; i < JRPL; ++i) c.jb[k][i] = c.jb[k + 1][i];
-          nb[k] = nb[k + 1];
-        }
-      }
-#pragma unroll
-      for (int k = PPW - 1; k >= 0; --k) {
-        const int p = p0 + k;
-        if (k == 0) {
-          if (p != 0) {
-#pragma unroll
-            for (int i = 0; i < RPL; ++i) c.tp[0][i] = inT[i * 64 + lane];
-            if (ACC)
-#pragma unroll
-              for (int i = 0; i < JRPL; ++i) c.jt[0][i] = inT[(RPL + i) * 64 + lane];
-            nt[0] = uni(nbuf[(buf * 2 + 0) * SNW + (wave > 0 ? wave - 1 : 0)]);
-          }
-        } else if (p == 1) {
-#pragma unroll
-          for (int i = 0; i < RPL; ++i) c.tp[k][i] = b0[i];
-          if (ACC)
-#pragma unroll
-            for (int i = 0; i < JRPL; ++i) c.jt[k][i] = jb0[i];
-          nt[k] = nb0;
-        } else {
-#pragma unroll
-          for (int i = 0; i < RPL; ++i) c.tp[k][i] = c.tp[k - 1][i];
-          if (ACC)
-#pragma unroll
-            for (int i = 0; i < JRPL; ++i) c.jt[k][i] = c.jt[k - 1][i];
-          nt[k] = nt[k - 1];
-        }
-      }
-      buf ^= 1;
-    }
-    // after n2 - 1 rounds every column is back in its starting slot
-    __syncthreads();
-    if (lane == 0) rotflag[wave] = rot ? 1 : 0;
-    __syncthreads();
-    int any = 0;
-    for (int w = 0; w < SNW; ++w) any |= rotflag[w];
-    __syncthreads();
-    if (!any) {
-      converged = true;
-      break;
+      const double cg = 2.0 * cs * sn * g;
+      c.nt[pt] = fma(cs * cs, al, fma(sn * sn, be, -cg));
+      c.nb[pb] = fma(sn * sn, al, fma(cs * cs, be, cg));
+      rot = rot || dorot;
     }
   }
-  if (!converged && threadIdx.x == 0) atomicOr(d.flags, FLAG_JACOBI_NOCONV);
-  return converged ? sweeps : -sweeps;
+  if (!move) return rot;
+  constexpr int CW = GR::CW;
+  constexpr int OTP = (2 * PPG - 1 - PH) % PPG, OBP = PH % PPG;
+  double* ob = xbuf + buf * (2 * JNW * CW * 16);
+  // outgoing columns of the wavefront's end groups, [buffer][direction]
+  // [wave][value][16]: the top of group 3 (direction 0), the bottom of
+  // group 0 (direction 1); one store per value and lane, the value selected
+  // (a store from either column would take the columns out of registers)
+  if (x.g == 0 || x.g == 3) {
+    const bool up = x.g == 3;
+    double* o = ob + ((up ? 0 : JNW) + x.wave) * CW * 16 + x.l16;
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) o[i * 16] = up ? c.t[i][OTP] : c.b[i][OBP];
+    if (ACC) {
+#pragma unroll
+      for (int i = 0; i < GR::JR; ++i) o[(RPL + i) * 16] = up ? c.jt[i][OTP] : c.jb[i][OBP];
+    }
+    o[(CW - 1) * 16] = up ? c.nt[OTP] : c.nb[OBP];
+  }
+  if (x.special) {
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) gx_special<PPG, PH>(c.t[i], c.b[i], x);
+    if (ACC) {
+#pragma unroll
+      for (int i = 0; i < GR::JR; ++i) gx_special<PPG, PH>(c.jt[i], c.jb[i], x);
+    }
+    gx_special<PPG, PH>(c.nt, c.nb, x);
+  } else {
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) gx_plain<PPG, PH>(c.t[i], c.b[i], x);
+    if (ACC) {
+#pragma unroll
+      for (int i = 0; i < GR::JR; ++i) gx_plain<PPG, PH>(c.jt[i], c.jb[i], x);
+    }
+    gx_plain<PPG, PH>(c.nt, c.nb, x);
+  }
+  __syncthreads();
+  // incoming columns across wavefronts: group 0 takes the previous
+  // wavefront's top, group 3 the next wavefront's bottom
+  if (x.rdT) {
+    const double* q = ob + (x.wave - 1) * CW * 16 + x.l16;
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) c.t[i][OTP] = q[i * 16];
+    if (ACC) {
+#pragma unroll
+      for (int i = 0; i < GR::JR; ++i) c.jt[i][OTP] = q[(RPL + i) * 16];
+    }
+    c.nt[OTP] = q[(CW - 1) * 16];
+  }
+  if (x.rdB) {
+    const double* q = ob + (JNW + x.wave + 1) * CW * 16 + x.l16;
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) c.b[i][OBP] = q[i * 16];
+    if (ACC) {
+#pragma unroll
+      for (int i = 0; i < GR::JR; ++i) c.jb[i][OBP] = q[(RPL + i) * 16];
+    }
+    c.nb[OBP] = q[(CW - 1) * 16];
+  }
+  return rot;
 }
 
-// column c of the ring layout: processor c / 2, top if c is even
-__device__ __forceinline__ void ring_slot(int c, int ppw, int& wave, int& k, bool& top) {
-  const int p = c >> 1;
-  wave = p / ppw;
-  k = p % ppw;
-  top = (c & 1) == 0;
+// registers of phase ph back to phase 0 (logical slot k in register k)
+template <int PPG>
+__device__ __forceinline__ void gring_unphase(double (&T)[PPG], double (&B)[PPG], int ph) {
+  double t2[PPG], b2[PPG];
+#pragma unroll
+  for (int q = 1; q < PPG; ++q) {
+    if (ph != q) continue;
+#pragma unroll
+    for (int k = 0; k < PPG; ++k) {
+      t2[k] = T[(k - q + PPG) % PPG];
+      b2[k] = B[(k + q) % PPG];
+    }
+#pragma unroll
+    for (int k = 0; k < PPG; ++k) {
+      T[k] = t2[k];
+      B[k] = b2[k];
+    }
+  }
+}
+
+// exact squared norms of every register's columns
+template <int PPG, int RPL, bool ACC, int JRPL>
+__device__ __forceinline__ void gring_norms(GRing<PPG, RPL, ACC, JRPL>& c) {
+#pragma unroll
+  for (int k = 0; k < PPG; ++k) {
+    double a = 0.0, b = 0.0;
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+      a = fma(c.t[i][k], c.t[i][k], a);
+      b = fma(c.b[i][k], c.b[i][k], b);
+    }
+    c.nt[k] = class_sum16(a);
+    c.nb[k] = class_sum16(b);
+  }
+}
+
+// sweep bookkeeping of the group ring
+struct GSweep {
+  int rr;         // rounds done in the current sweep
+  int sweeps;     // current sweep (1-based)
+  int buf;        // exchange buffer of the next round
+  bool rot;       // this lane rotated a pair in the current sweep
+  bool converged;
+};
+
+// One round in phase PH and, after the last round of a sweep, the sweep's
+// end: the block stops when no wavefront rotated (converged) or after
+// max_sweeps, else the next sweep starts from exact norms.  Returns true
+// when the block stops.
+template <int PH, int PPG, int RPL, bool ACC, int JRPL>
+__device__ __forceinline__ bool gring_step(GRing<PPG, RPL, ACC, JRPL>& c, const GPos& x, double floor2, double tol2,
+                                           bool move, double* xbuf, int* rotflag, int n2, int max_sweeps,
+                                           GSweep& w) {
+  const bool r = gring_round<PH>(c, x, floor2, tol2, move, xbuf, w.buf);
+  w.rot = w.rot || r;
+  w.buf ^= 1;
+  if (++w.rr < n2 - 1) return false;
+  // after n2 - 1 rounds every column is back in its starting slot
+  w.rr = 0;
+  const bool any = __any(w.rot ? 1 : 0);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) rotflag[x.wave] = any ? 1 : 0;
+  __syncthreads();
+  int anyb = 0;
+  for (int q = 0; q < JNW; ++q) anyb |= rotflag[q];
+  __syncthreads();
+  if (!anyb) {
+    w.converged = true;
+    return true;
+  }
+  if (w.sweeps == max_sweeps) return true;
+  ++w.sweeps;
+  w.rot = false;
+  gring_norms(c);
+  return false;
+}
+
+// Runs the sweeps on the n columns held in c (rows <= 16 RPL each); on
+// return logical slot k is in register k again.  Returns the sweeps done
+// (negative if not converged within max_sweeps).
+template <int PPG, int RPL, bool ACC, int JRPL>
+__device__ __forceinline__ int gring_jacobi(const Dev& d, GRing<PPG, RPL, ACC, JRPL>& c, int n, double tol, double floor_rel,
+                            int max_sweeps, double* xbuf, double* red, int* rotflag) {
+  static_assert(PPG >= 2, "two pair slots per group at least");
+  using GR = GRing<PPG, RPL, ACC, JRPL>;
+  GPos x;
+  const int lane = threadIdx.x & 63;
+  x.l16 = lane >> 2;
+  x.g = lane & 3;
+  x.wave = threadIdx.x >> 6;
+  x.gi = 4 * x.wave + x.g;
+  const int n2 = n + (n & 1);
+  x.P = n2 / 2;
+  x.gP = x.P > 0 ? (x.P - 1) / PPG : 0;
+  x.kP = x.P > 0 ? (x.P - 1) % PPG : 0;
+  const int uw = __builtin_amdgcn_readfirstlane(x.wave);
+  x.special = uw == 0 || uw == x.gP / 4;
+  x.rdT = x.g == 0 && x.gi != 0;
+  x.rdB = x.g == 3 && x.wave + 1 < JNW && !(x.gi == x.gP && x.kP == PPG - 1);
+  double part = 0.0;
+#pragma unroll
+  for (int i = 0; i < RPL; ++i)
+#pragma unroll
+    for (int k = 0; k < PPG; ++k) part = fma(c.t[i][k], c.t[i][k], fma(c.b[i][k], c.b[i][k], part));
+  const double floor2 = floor_rel * floor_rel * s_sum(part, red);
+  const double tol2 = tol * tol;
+  if (n2 <= 1) return 0;
+  GSweep w{0, 1, 0, false, false};
+  gring_norms(c);
+  int ph = 0;
+  if (x.P == 1) {
+    // a single pair: nothing moves
+    while (!gring_step<0>(c, x, floor2, tol2, false, xbuf, rotflag, n2, max_sweeps, w)) {
+    }
+  } else {
+    // the round loop unrolled over the phases, so that every register keeps
+    // its role from one round to the next
+    for (;;) {
+      if (gring_step<0>(c, x, floor2, tol2, true, xbuf, rotflag, n2, max_sweeps, w)) {
+        ph = 1 % PPG;
+        break;
+      }
+      if (gring_step<1 % PPG>(c, x, floor2, tol2, true, xbuf, rotflag, n2, max_sweeps, w)) {
+        ph = 2 % PPG;
+        break;
+      }
+      if constexpr (PPG > 2) {
+        if (gring_step<2 % PPG>(c, x, floor2, tol2, true, xbuf, rotflag, n2, max_sweeps, w)) {
+          ph = 3 % PPG;
+          break;
+        }
+      }
+    }
+  }
+  const bool converged = w.converged;
+  const int sweeps = w.sweeps;
+#pragma unroll
+  for (int i = 0; i < RPL; ++i) gring_unphase<PPG>(c.t[i], c.b[i], ph);
+  if (ACC) {
+#pragma unroll
+    for (int i = 0; i < GR::JR; ++i) gring_unphase<PPG>(c.jt[i], c.jb[i], ph);
+  }
+  gring_unphase<PPG>(c.nt, c.nb, ph);
+  if (!converged && threadIdx.x == 0) atomicOr(d.flags, FLAG_JACOBI_NOCONV);
+  return converged ? sweeps : -sweeps;
 }
 
 // rank of the value of column c among n values (descending, ties by index)
@@ -1409,91 +1549,104 @@ __global__ __launch_bounds__(STHR) void sw_chol(Dev d, int axis, int sd0, int nd
 // (packed lower triangle in LDS) that stops when the largest remaining pivot
 // is at most 1e-20 of the largest initial diagonal; the columns of the
 // factor L (G[perm, perm] = L L^T, rows in the original order) are then
-// orthogonalised by the ring Jacobi, L J = B, so that A B Sigma^-2 has
+// orthogonalised by the group ring Jacobi, L J = B, so that A B Sigma^-2 has
 // orthonormal columns: the left singular vectors of A, with sigma the
 // column norms of B.  Then the rank rule of step 3 and the coefficients of
 // sqrt(w) V-hat = A B[:, :t] Sigma^-2.  Singular values come from the Gram:
 // they are accurate to about u sigma_1^2 / sigma, which resolves the
 // absolute tolerances of the adaptive mode.
-template <int PPW, int RPL>
-__device__ void aug_svd_body(const Dev& d, int s, int axis, int m0, double* lds, SmallScratch& sc) {
+template <int PPG, int RPL>
+__device__ __forceinline__ void aug_svd_body(const Dev& d, int s, int axis, int m0, double* lds, SmallScratch& sc) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l16 = lane >> 2, gi = 4 * wave + (lane & 3);
   double* sm = small_of(d, s);
   const int r = d.rank[s];
   double* Gp = lds;            // packed lower triangle, m0 (m0 + 1) / 2
   double* dg = sc.v0;          // current diagonal
   double* d0s = sc.v1;
   int* estep = sc.i0;          // elimination step of each column (NOT_ELIM: never)
-  double* lcol = sc.v2;
+  double* lcol = sc.v2;        // the step's factor column, 0 outside the remaining rows
   double* sigs = sc.v3;
   double* sorted = sc.v4;
   int* rk = sc.i1;
   constexpr int NOT_ELIM = 1 << 20;
   auto pk = [](int i, int j) { return i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i; };
-  // Gram from the partials (symmetric, ld m0), lower triangle packed
+  // Gram from the partials (symmetric, ld m0), lower triangle packed:
+  // columns j over the wavefronts, rows i >= j over the lanes
   {
     const double* gp = gpart_of(d, s);
     const int ngp = d.nwgM;
-    for (int idx = threadIdx.x; idx < m0 * m0; idx += STHR) {
-      const int i = idx % m0, j = idx / m0;
-      if (i < j) continue;
-      const int64_t src = i + (int64_t)j * m0;
-      double acc = 0.0;
-      for (int w = 0; w < ngp; ++w) acc += gp[(int64_t)w * d.gpTile + src];
-      Gp[pk(i, j)] = acc;
-    }
+    for (int j = wave; j < m0; j += JNW)
+      for (int i = j + lane; i < m0; i += 64) {
+        const int64_t src = i + (int64_t)j * m0;
+        double acc = 0.0;
+        for (int w = 0; w < ngp; ++w) acc += gp[(int64_t)w * d.gpTile + src];
+        Gp[i * (i + 1) / 2 + j] = acc;
+      }
     __syncthreads();
-    for (int i = threadIdx.x; i < m0; i += STHR) {
-      dg[i] = Gp[pk(i, i)];
+    for (int i = threadIdx.x; i < m0; i += JTHR) {
+      dg[i] = Gp[i * (i + 1) / 2 + i];
       d0s[i] = dg[i];
       estep[i] = NOT_ELIM;
     }
     __syncthreads();
   }
   double dmax = 0.0;
-  for (int i = threadIdx.x; i < m0; i += STHR) dmax = fmax(dmax, d0s[i]);
+  for (int i = threadIdx.x; i < m0; i += JTHR) dmax = fmax(dmax, d0s[i]);
   dmax = s_max(dmax, sc.red);
   // pivoted right-looking Cholesky: pivot = the largest remaining diagonal,
-  // the smallest index among equal ones
+  // the smallest index among equal ones (every wavefront finds it itself)
   for (int k = 0; k < m0; ++k) {
     double key = 0.0;
-    for (int i = threadIdx.x; i < m0; i += STHR)
+    for (int i = lane; i < m0; i += 64)
       if (estep[i] > k) key = fmax(key, dg[i]);
-    const double best = s_max(key, sc.red);
-    if (threadIdx.x == 0) sc.ival[1] = m0;
-    __syncthreads();
-    for (int i = threadIdx.x; i < m0; i += STHR)
-      if (estep[i] > k && dg[i] == best) atomicMin(&sc.ival[1], i);
-    __syncthreads();
-    const int p = sc.ival[1];
+    const double best = wave_max(key);
+    int p = m0;
+    for (int q = 0; q * 64 < m0; ++q) {
+      const int i = lane + 64 * q;
+      const unsigned long long m = __ballot(i < m0 && estep[i] > k && dg[i] == best);
+      if (m) {
+        p = 64 * q + __builtin_ctzll(m);
+        break;
+      }
+    }
     if (p >= m0 || !(best > 1e-20 * dmax) || !isfinite(best)) break;  // the rest is numerically dependent
     const double lpp = sqrt(best), il = 1.0 / lpp;
-    for (int i = threadIdx.x; i < m0; i += STHR)
-      lcol[i] = (i == p) ? lpp : ((estep[i] > k) ? Gp[pk(i, p)] * il : 0.0);
+    for (int i = threadIdx.x; i < m0; i += JTHR) lcol[i] = (i != p && estep[i] > k) ? Gp[pk(i, p)] * il : 0.0;
     __syncthreads();
-    if (threadIdx.x == 0) estep[p] = k;
-    for (int i = threadIdx.x; i < m0; i += STHR)
-      if (i != p && estep[i] > k) Gp[pk(i, p)] = lcol[i];
-    if (threadIdx.x == 0) Gp[pk(p, p)] = lpp;
-    // trailing update of the active block (p itself is no longer active)
-    for (int idx = threadIdx.x; idx < m0 * m0; idx += STHR) {
-      const int i = idx % m0, j = idx / m0;
-      if (i >= j && i != p && j != p && estep[i] > k && estep[j] > k)
-        Gp[pk(i, j)] = fma(-lcol[i], lcol[j], Gp[pk(i, j)]);
+    // the factor column over column p of the packed Gram, then the update
+    // of the remaining block (entries with a zero factor value are left
+    // alone, so the two writes never meet)
+    for (int i = threadIdx.x; i < m0; i += JTHR)
+      if (lcol[i] != 0.0) Gp[pk(i, p)] = lcol[i];
+    if (threadIdx.x == 0) {
+      Gp[pk(p, p)] = lpp;
+      estep[p] = k;
     }
-    for (int i = threadIdx.x; i < m0; i += STHR)
-      if (i != p && estep[i] > k) dg[i] = fma(-lcol[i], lcol[i], dg[i]);
+    for (int j = wave; j < m0; j += JNW) {
+      const double lj = lcol[j];
+      if (lj == 0.0) continue;
+      for (int i = j + lane; i < m0; i += 64) {
+        const double li = lcol[i];
+        if (li != 0.0) {
+          const int o = i * (i + 1) / 2 + j;
+          Gp[o] = fma(-li, lj, Gp[o]);
+        }
+      }
+    }
+    for (int i = threadIdx.x; i < m0; i += JTHR)
+      if (lcol[i] != 0.0) dg[i] = fma(-lcol[i], lcol[i], dg[i]);
     __syncthreads();
   }
   // columns of the factor into the ring registers: column c (original
   // index) holds L(:, estep[c]), nonzero in rows eliminated at or after it
-  RingCols<PPW, RPL, false, 1> c;
+  GRing<PPG, RPL, false, 1> c;
 #pragma unroll
-  for (int k = 0; k < PPW; ++k)
+  for (int i = 0; i < RPL; ++i)
 #pragma unroll
-    for (int i = 0; i < RPL; ++i) {
-      const int row = lane + 64 * i;
-      const int p = wave * PPW + k;
+    for (int k = 0; k < PPG; ++k) {
+      const int row = l16 + 16 * i;
+      const int p = gi * PPG + k;
       const int ct = 2 * p, cb = 2 * p + 1;
       double vt = 0.0, vb = 0.0;
       if (row < m0 && ct < m0 && estep[ct] < NOT_ELIM) {
@@ -1504,30 +1657,32 @@ __device__ void aug_svd_body(const Dev& d, int s, int axis, int m0, double* lds,
         if (row == cb) vb = Gp[pk(cb, cb)];
         else if (estep[row] > estep[cb]) vb = Gp[pk(row, cb)];
       }
-      c.tp[k][i] = vt;
-      c.bt[k][i] = vb;
+      c.t[i][k] = vt;
+      c.b[i][k] = vb;
     }
+#pragma unroll
+  for (int k = 0; k < PPG; ++k) c.nt[k] = c.nb[k] = 0.0;
   __syncthreads();  // LDS now free for the exchange buffers
-  ring_jacobi<PPW, RPL, false, 1>(d, c, m0, m0, 1e-14, 1e-15, 40, lds, sc.red, sc.rotflag);
+  gring_jacobi<PPG, RPL, false, 1>(d, c, m0, 1e-14, 1e-15, 40, lds, sc.red, sc.rotflag);
   // singular values: column norms
 #pragma unroll
-  for (int k = 0; k < PPW; ++k) {
+  for (int k = 0; k < PPG; ++k) {
     double nt = 0.0, nb = 0.0;
 #pragma unroll
     for (int i = 0; i < RPL; ++i) {
-      nt = fma(c.tp[k][i], c.tp[k][i], nt);
-      nb = fma(c.bt[k][i], c.bt[k][i], nb);
+      nt = fma(c.t[i][k], c.t[i][k], nt);
+      nb = fma(c.b[i][k], c.b[i][k], nb);
     }
-    nt = wave_sum(nt);
-    nb = wave_sum(nb);
-    const int p = wave * PPW + k;
-    if (lane == 0) {
+    nt = class_sum16(nt);
+    nb = class_sum16(nb);
+    const int p = gi * PPG + k;
+    if (l16 == 0) {
       if (2 * p < m0) sigs[2 * p] = sqrt(nt);
       if (2 * p + 1 < m0) sigs[2 * p + 1] = sqrt(nb);
     }
   }
   __syncthreads();
-  for (int j = threadIdx.x; j < m0; j += STHR) {
+  for (int j = threadIdx.x; j < m0; j += JTHR) {
     const int q = desc_rank(sigs, m0, j);
     rk[j] = q;
     sorted[q] = sigs[j];
@@ -1555,13 +1710,13 @@ __device__ void aug_svd_body(const Dev& d, int s, int axis, int m0, double* lds,
   __syncthreads();
   const int t = sc.ival[0];
   const double s0 = sorted[0];
-  for (int j = threadIdx.x; j < m0; j += STHR) sm[d.oSig + j] = sorted[j];
-  for (int j = threadIdx.x; j < t; j += STHR)
+  for (int j = threadIdx.x; j < m0; j += JTHR) sm[d.oSig + j] = sorted[j];
+  for (int j = threadIdx.x; j < t; j += JTHR)
     sm[d.oFill + j] = (s0 > 0.0 && sorted[j] > 1e-13 * s0) ? 0.0 : 1.0;
   // Coef[:, rank(c)] = b_c / sigma_c^2 for the kept columns
 #pragma unroll
-  for (int k = 0; k < PPW; ++k) {
-    const int p = wave * PPW + k;
+  for (int k = 0; k < PPG; ++k) {
+    const int p = gi * PPG + k;
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
       const int col = 2 * p + half;
@@ -1573,21 +1728,21 @@ __device__ void aug_svd_body(const Dev& d, int s, int axis, int m0, double* lds,
       const double isg2 = ok ? 1.0 / (sg * sg) : 0.0;
 #pragma unroll
       for (int i = 0; i < RPL; ++i) {
-        const int row = lane + 64 * i;
-        if (row < m0) sm[d.oCoef + row + q * d.MA] = (half ? c.bt[k][i] : c.tp[k][i]) * isg2;
+        const int row = l16 + 16 * i;
+        if (row < m0) sm[d.oCoef + row + q * d.MA] = (half ? c.b[i][k] : c.t[i][k]) * isg2;
       }
     }
   }
 }
 
-__global__ __launch_bounds__(STHR) void sw_aug_svd(Dev d, int axis, int sd0) {
+__global__ __launch_bounds__(JTHR) void sw_aug_svd(Dev d, int axis, int sd0) {
   const int s = sd0 + blockIdx.x;
   const int m0 = m0_of(d, s, axis);
   extern __shared__ double lds[];
   __shared__ SmallScratch sc;
-  if (m0 <= 64) aug_svd_body<2, 1>(d, s, axis, m0, lds, sc);
-  else if (m0 <= 128) aug_svd_body<4, 2>(d, s, axis, m0, lds, sc);
-  else aug_svd_body<6, 3>(d, s, axis, m0, lds, sc);
+  if (m0 <= 64) aug_svd_body<2, 4>(d, s, axis, m0, lds, sc);
+  else if (m0 <= 128) aug_svd_body<2, 8>(d, s, axis, m0, lds, sc);
+  else aug_svd_body<3, 12>(d, s, axis, m0, lds, sc);
 }
 
 // Upwind split of the angular Galerkin matrix C (Appendix A: C = P diag(lambda)
@@ -1826,46 +1981,49 @@ __global__ __launch_bounds__(STHR) void sw_adv_sstep(Dev d, int axis, int sd0) {
 // rotations accumulated (S3 J = U~ Sigma, V~ = J), the rank rule, and the
 // rotations Bu = U~[:, :r'] / h, Bv = V~[:, :r'] of the final products;
 // S = diag(sigma[:r']) goes into the state and r' into rnew.
-template <int PPW, int RPL>
-__device__ void trunc_body(const Dev& d, int s, int axis, int t, double* lds, SmallScratch& sc) {
+template <int PPG, int RPL>
+__device__ __forceinline__ void trunc_body(const Dev& d, int s, int axis, int t, double* lds, SmallScratch& sc) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l16 = lane >> 2, gi = 4 * wave + (lane & 3);
   const int R = d.R, T = d.T;
   double* sm = small_of(d, s);
   double* sigs = sc.v0;
   double* sorted = sc.v1;
   int* rk = sc.i0;
   const double* RL = sm + d.oRacc;
-  RingCols<PPW, RPL, true, RPL> c;
+  GRing<PPG, RPL, true, RPL> c;
 #pragma unroll
-  for (int k = 0; k < PPW; ++k)
+  for (int i = 0; i < RPL; ++i)
 #pragma unroll
-    for (int i = 0; i < RPL; ++i) {
-      const int row = lane + 64 * i, p = wave * PPW + k;
+    for (int k = 0; k < PPG; ++k) {
+      const int row = l16 + 16 * i, p = gi * PPG + k;
       const int ct = 2 * p, cb = 2 * p + 1;
-      c.tp[k][i] = (row < t && ct < t) ? RL[ct + row * T] : 0.0;   // S3[row][col] = RL[col][row]
-      c.bt[k][i] = (row < t && cb < t) ? RL[cb + row * T] : 0.0;
-      c.jt[k][i] = (row == ct && ct < t) ? 1.0 : 0.0;
-      c.jb[k][i] = (row == cb && cb < t) ? 1.0 : 0.0;
+      c.t[i][k] = (row < t && ct < t) ? RL[ct + row * T] : 0.0;   // S3[row][col] = RL[col][row]
+      c.b[i][k] = (row < t && cb < t) ? RL[cb + row * T] : 0.0;
+      c.jt[i][k] = (row == ct && ct < t) ? 1.0 : 0.0;
+      c.jb[i][k] = (row == cb && cb < t) ? 1.0 : 0.0;
     }
-  ring_jacobi<PPW, RPL, true, RPL>(d, c, t, t, 1e-14, 1e-15, 40, lds, sc.red, sc.rotflag);
 #pragma unroll
-  for (int k = 0; k < PPW; ++k) {
+  for (int k = 0; k < PPG; ++k) c.nt[k] = c.nb[k] = 0.0;
+  gring_jacobi<PPG, RPL, true, RPL>(d, c, t, 1e-14, 1e-15, 40, lds, sc.red, sc.rotflag);
+#pragma unroll
+  for (int k = 0; k < PPG; ++k) {
     double nt = 0.0, nb = 0.0;
 #pragma unroll
     for (int i = 0; i < RPL; ++i) {
-      nt = fma(c.tp[k][i], c.tp[k][i], nt);
-      nb = fma(c.bt[k][i], c.bt[k][i], nb);
+      nt = fma(c.t[i][k], c.t[i][k], nt);
+      nb = fma(c.b[i][k], c.b[i][k], nb);
     }
-    nt = wave_sum(nt);
-    nb = wave_sum(nb);
-    const int p = wave * PPW + k;
-    if (lane == 0) {
+    nt = class_sum16(nt);
+    nb = class_sum16(nb);
+    const int p = gi * PPG + k;
+    if (l16 == 0) {
       if (2 * p < t) sigs[2 * p] = sqrt(nt);
       if (2 * p + 1 < t) sigs[2 * p + 1] = sqrt(nb);
     }
   }
   __syncthreads();
-  for (int j = threadIdx.x; j < t; j += STHR) {
+  for (int j = threadIdx.x; j < t; j += JTHR) {
     const int q = desc_rank(sigs, t, j);
     rk[j] = q;
     sorted[q] = sigs[j];
@@ -1898,8 +2056,8 @@ __device__ void trunc_body(const Dev& d, int s, int axis, int t, double* lds, Sm
   double* Ut = sm + d.oBu;
   double* Bv = sm + d.oBv;
 #pragma unroll
-  for (int k = 0; k < PPW; ++k) {
-    const int p = wave * PPW + k;
+  for (int k = 0; k < PPG; ++k) {
+    const int p = gi * PPG + k;
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
       const int col = 2 * p + half;
@@ -1908,14 +2066,14 @@ __device__ void trunc_body(const Dev& d, int s, int axis, int t, double* lds, Sm
       if (q >= rp) continue;
       const double sg = sigs[col];
       const bool ok = s0 > 0.0 && sg > 1e-13 * s0;
-      if (!ok && lane == 0) sc.ival[1] = 1;
+      if (!ok && l16 == 0) sc.ival[1] = 1;
       const double isg = ok ? 1.0 / sg : 0.0;
 #pragma unroll
       for (int i = 0; i < RPL; ++i) {
-        const int row = lane + 64 * i;
+        const int row = l16 + 16 * i;
         if (row < t) {
-          const double b = half ? c.bt[k][i] : c.tp[k][i];
-          const double v = half ? c.jb[k][i] : c.jt[k][i];
+          const double b = half ? c.b[i][k] : c.t[i][k];
+          const double v = half ? c.jb[i][k] : c.jt[i][k];
           Ut[row + q * T] =
               ok ? b * isg : hash_unit(((uint64_t)s << 40) ^ ((uint64_t)(q + 1000) << 24) ^ (uint64_t)row);
           Bv[row + q * T] = v;
@@ -1931,38 +2089,38 @@ __device__ void trunc_body(const Dev& d, int s, int axis, int t, double* lds, Sm
       for (int j = 0; j < rp; ++j) {
         for (int k = 0; k < j; ++k) {
           double part = 0.0;
-          for (int i = threadIdx.x; i < t; i += STHR) part = fma(Ut[i + k * T], Ut[i + j * T], part);
+          for (int i = threadIdx.x; i < t; i += JTHR) part = fma(Ut[i + k * T], Ut[i + j * T], part);
           const double dot = s_sum(part, sc.red);
-          for (int i = threadIdx.x; i < t; i += STHR) Ut[i + j * T] -= dot * Ut[i + k * T];
+          for (int i = threadIdx.x; i < t; i += JTHR) Ut[i + j * T] -= dot * Ut[i + k * T];
           __syncthreads();
         }
         double part = 0.0;
-        for (int i = threadIdx.x; i < t; i += STHR) part = fma(Ut[i + j * T], Ut[i + j * T], part);
+        for (int i = threadIdx.x; i < t; i += JTHR) part = fma(Ut[i + j * T], Ut[i + j * T], part);
         const double nrm = sqrt(s_sum(part, sc.red));
         const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
-        for (int i = threadIdx.x; i < t; i += STHR) Ut[i + j * T] *= inv;
+        for (int i = threadIdx.x; i < t; i += JTHR) Ut[i + j * T] *= inv;
         __syncthreads();
       }
   }
-  for (int idx = threadIdx.x; idx < t * rp; idx += STHR) {
+  for (int idx = threadIdx.x; idx < t * rp; idx += JTHR) {
     const int i = idx % t, j = idx / t;
     Ut[i + j * T] *= ih;
   }
   double* Sg = d.S + (int64_t)s * R * R;
-  for (int idx = threadIdx.x; idx < R * R; idx += STHR) {
+  for (int idx = threadIdx.x; idx < R * R; idx += JTHR) {
     const int i = idx % R, j = idx / R;
     Sg[idx] = (i == j && i < rp) ? sorted[i] : 0.0;
   }
   if (threadIdx.x < rp && !isfinite(sorted[threadIdx.x])) atomicOr(d.flags, FLAG_NONFINITE);
 }
 
-__global__ __launch_bounds__(STHR) void sw_trunc(Dev d, int axis, int sd0) {
+__global__ __launch_bounds__(JTHR) void sw_trunc(Dev d, int axis, int sd0) {
   const int s = sd0 + blockIdx.x;
   const int t = d.tdim[s];
   extern __shared__ double lds[];
   __shared__ SmallScratch sc;
-  if (t <= 64) trunc_body<2, 1>(d, s, axis, t, lds, sc);
-  else trunc_body<4, 2>(d, s, axis, t, lds, sc);
+  if (t <= 64) trunc_body<2, 4>(d, s, axis, t, lds, sc);
+  else trunc_body<2, 8>(d, s, axis, t, lds, sc);
 }
 
 // m = V^T w (eq. coll_evolK) for stored ranks up to 64: one wavefront per
@@ -2009,15 +2167,16 @@ void w_allow(const void* fn) {
 
 int w_dim_cap(const Dev& d, int which) { return which == DIM_M0 ? d.MA : (which == DIM_T ? d.T : d.R); }
 
-size_t ring_bytes_max() { return sizeof(double) * ring_lds_doubles<3, 0, false>(); }
+constexpr size_t AUG_RING_LDS = sizeof(double) * gring_lds_doubles<GRing<3, 12, false, 1>::CW>();
+constexpr size_t TRUNC_RING_LDS = sizeof(double) * gring_lds_doubles<GRing<2, 8, true, 8>::CW>();
 
 // every small kernel's dynamic LDS plus its static scratch fits the 160 KB
 // of a compute unit
 constexpr size_t LDS_CU = 160 * 1024;
 constexpr size_t AUG_LDS = sizeof(double) * (size_t)WCAP_A * (WCAP_A + 1) / 2;
-static_assert(sizeof(double) * ring_lds_doubles<3, 0, false>() <= AUG_LDS, "ring buffer of the augmentation SVD");
+static_assert(AUG_RING_LDS <= AUG_LDS, "ring buffer of the augmentation SVD");
 static_assert(AUG_LDS + sizeof(SmallScratch) <= LDS_CU, "LDS of sw_aug_svd");
-static_assert(sizeof(double) * ring_lds_doubles<2, 2, true>() + sizeof(SmallScratch) <= LDS_CU, "LDS of sw_trunc");
+static_assert(TRUNC_RING_LDS + sizeof(SmallScratch) <= LDS_CU, "LDS of sw_trunc");
 static_assert(sizeof(double) * (size_t)WLD * WCAP_T + sizeof(SmallScratch) <= LDS_CU, "LDS of sw_chol/adv_prep");
 }  // namespace
 
@@ -2120,8 +2279,8 @@ void launch_w_chol(const Dev& d, int axis, int sd0, int nsd, int ndim, int rows,
 }
 
 void launch_w_aug_svd(const Dev& d, int axis, int sd0, int nsd, hipStream_t st) {
-  const size_t lds = std::max(sizeof(double) * (size_t)WCAP_A * (WCAP_A + 1) / 2, ring_bytes_max());
-  hipLaunchKernelGGL(sw_aug_svd, dim3(nsd), dim3(STHR), lds, st, d, axis, sd0);
+  const size_t lds = std::max(AUG_LDS, AUG_RING_LDS);
+  hipLaunchKernelGGL(sw_aug_svd, dim3(nsd), dim3(JTHR), lds, st, d, axis, sd0);
 }
 
 void launch_w_adv_prep(const Dev& d, int axis, int sd0, int nsd, hipStream_t st) {
@@ -2134,8 +2293,8 @@ void launch_w_adv_sstep(const Dev& d, int axis, int sd0, int nsd, hipStream_t st
 }
 
 void launch_w_trunc(const Dev& d, int axis, int sd0, int nsd, hipStream_t st) {
-  const size_t lds = sizeof(double) * ring_lds_doubles<2, 2, true>();
-  hipLaunchKernelGGL(sw_trunc, dim3(nsd), dim3(STHR), lds, st, d, axis, sd0);
+  const size_t lds = TRUNC_RING_LDS;
+  hipLaunchKernelGGL(sw_trunc, dim3(nsd), dim3(JTHR), lds, st, d, axis, sd0);
 }
 
 void launch_w_coll_prep(const Dev& d, int sd0, int nsd, hipStream_t st) {
