@@ -795,31 +795,46 @@ __device__ void s_sum_partials(const Dev& d, int s, int ngp, int off, int ldp, i
 // loads of a step issued first.  Ends with a barrier.
 __device__ void gmm(double* C, int ldc, const double* A, int lda, bool ta, const double* B, int ldb, bool tb, int m,
                     int n, int k, double alpha, double beta, const double* D, int ldd) {
+  constexpr int KC = 16, NL = KC / 4;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nw = blockDim.x >> 6;
   const int l16 = lane & 15, kq = lane >> 4;
   const int tm = wdiv(m, 16), tn = wdiv(n, 16);
+  const int nch = wdiv(k, KC);
   for (int tile = wave; tile < tm * tn; tile += nw) {
     const int ti = tile % tm, tj = tile / tm;
     const int i0 = 16 * ti, j0 = 16 * tj;
     const int i = i0 + l16, j = j0 + l16;
     const int ic = i < m ? i : 0, jc = j < n ? j : 0;
-    dbl4 e = zero4(), o = zero4();
-    for (int k0 = 0; k0 < k; k0 += 64) {
-      double av[16], bv[16];
+    // operands of the next 16 values of k are loaded while the MFMAs of
+    // the current ones run
+    auto load = [&](int c, double (&av)[NL], double (&bv)[NL]) {
 #pragma unroll
-      for (int s4 = 0; s4 < 16; ++s4) {
-        const int l = k0 + 4 * s4 + kq;
+      for (int u = 0; u < NL; ++u) {
+        const int l = c * KC + 4 * u + kq;
         const int lc = l < k ? l : 0;
         const double a_ = ta ? A[lc + (int64_t)ic * lda] : A[ic + (int64_t)lc * lda];
         const double b_ = tb ? B[jc + (int64_t)lc * ldb] : B[lc + (int64_t)jc * ldb];
-        av[s4] = (i < m && l < k) ? a_ : 0.0;
-        bv[s4] = (j < n && l < k) ? b_ : 0.0;
+        av[u] = (i < m && l < k) ? a_ : 0.0;
+        bv[u] = (j < n && l < k) ? b_ : 0.0;
       }
+    };
+    dbl4 e = zero4(), o = zero4();
+    double a0[NL], b0[NL], a1[NL], b1[NL];
+    if (nch > 0) load(0, a0, b0);
+    for (int c = 0; c < nch; c += 2) {
+      if (c + 1 < nch) load(c + 1, a1, b1);
 #pragma unroll
-      for (int s4 = 0; s4 < 16; s4 += 2) {
-        e = mfma64(av[s4], bv[s4], e);
-        o = mfma64(av[s4 + 1], bv[s4 + 1], o);
+      for (int u = 0; u < NL; u += 2) {
+        e = mfma64(a0[u], b0[u], e);
+        o = mfma64(a0[u + 1], b0[u + 1], o);
+      }
+      if (c + 1 >= nch) break;
+      if (c + 2 < nch) load(c + 2, a0, b0);
+#pragma unroll
+      for (int u = 0; u < NL; u += 2) {
+        e = mfma64(a1[u], b1[u], e);
+        o = mfma64(a1[u + 1], b1[u + 1], o);
       }
     }
 #pragma unroll
@@ -844,15 +859,19 @@ __device__ __forceinline__ void gmm(double* C, int ldc, const double* A, int lda
 // matrix): only the 16 x 16 tiles on and above the diagonal are formed and
 // each value is stored at (i, j) and (j, i) (in a diagonal tile only i <= j
 // writes), so C comes out exactly symmetric and iterations built on it keep
-// exact symmetry.  C differs from A, B and D unless beta = 0.  Ends with a
-// barrier.
+// exact symmetry.  B is read by rows (B[l][j] = B[j][l]), so both operands
+// load 16 consecutive rows per instruction, and the operands of the next
+// 16 values of k are loaded while the MFMAs of the current ones run.  C
+// differs from A, B and D unless beta = 0.  Ends with a barrier.
 __device__ void gmm_sym(double* C, int ldc, const double* A, int lda, const double* B, int ldb, int n, double alpha,
                         double beta, const double* D, int ldd) {
+  constexpr int KC = 16, NL = KC / 4;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nw = blockDim.x >> 6;
   const int l16 = lane & 15, kq = lane >> 4;
   const int tn = wdiv(n, 16);
   const int ntiles = tn * (tn + 1) / 2;
+  const int nch = wdiv(n, KC);
   for (int tile = wave; tile < ntiles; tile += nw) {
     int tj = 0, ti = tile;
     while (ti > tj) {
@@ -861,23 +880,34 @@ __device__ void gmm_sym(double* C, int ldc, const double* A, int lda, const doub
     }
     const int i0 = 16 * ti, j0 = 16 * tj;
     const int i = i0 + l16, j = j0 + l16;
-    const int ic = i < n ? i : 0, jc = j < n ? j : 0;
-    dbl4 e = zero4(), o = zero4();
-    for (int k0 = 0; k0 < n; k0 += 64) {
-      double av[16], bv[16];
+    const double* pa = A + (i < n ? i : 0);
+    const double* pb = B + (j < n ? j : 0);
+    auto load = [&](int c, double (&av)[NL], double (&bv)[NL]) {
 #pragma unroll
-      for (int s4 = 0; s4 < 16; ++s4) {
-        const int l = k0 + 4 * s4 + kq;
+      for (int u = 0; u < NL; ++u) {
+        const int l = c * KC + 4 * u + kq;
         const int lc = l < n ? l : 0;
-        const double a_ = A[ic + (int64_t)lc * lda];
-        const double b_ = B[lc + (int64_t)jc * ldb];
-        av[s4] = (i < n && l < n) ? a_ : 0.0;
-        bv[s4] = (j < n && l < n) ? b_ : 0.0;
+        const double a_ = pa[(int64_t)lc * lda], b_ = pb[(int64_t)lc * ldb];
+        av[u] = (i < n && l < n) ? a_ : 0.0;
+        bv[u] = (j < n && l < n) ? b_ : 0.0;
       }
+    };
+    dbl4 e = zero4(), o = zero4();
+    double a0[NL], b0[NL], a1[NL], b1[NL];
+    load(0, a0, b0);
+    for (int c = 0; c < nch; c += 2) {
+      if (c + 1 < nch) load(c + 1, a1, b1);
 #pragma unroll
-      for (int s4 = 0; s4 < 16; s4 += 2) {
-        e = mfma64(av[s4], bv[s4], e);
-        o = mfma64(av[s4 + 1], bv[s4 + 1], o);
+      for (int u = 0; u < NL; u += 2) {
+        e = mfma64(a0[u], b0[u], e);
+        o = mfma64(a0[u + 1], b0[u + 1], o);
+      }
+      if (c + 1 >= nch) break;
+      if (c + 2 < nch) load(c + 2, a0, b0);
+#pragma unroll
+      for (int u = 0; u < NL; u += 2) {
+        e = mfma64(a1[u], b1[u], e);
+        o = mfma64(a1[u + 1], b1[u + 1], o);
       }
     }
 #pragma unroll
@@ -1594,6 +1624,22 @@ __device__ __forceinline__ void aug_svd_body(const Dev& d, int s, int axis, int 
   double dmax = 0.0;
   for (int i = threadIdx.x; i < m0; i += JTHR) dmax = fmax(dmax, d0s[i]);
   dmax = s_max(dmax, sc.red);
+  // the active Gram in registers: thread (ri, ci) = (tid / 32, tid % 32)
+  // holds rows [12 ri, 12 ri + 12) and columns [6 ci, 6 ci + 6) of the full
+  // square (both triangles get the same updates, so it stays symmetric);
+  // the packed triangle in LDS then receives the factor columns
+  constexpr int GR_ = 12, GC_ = 6;
+  static_assert(GR_ * (JTHR / 32) >= WCAP_A && GC_ * 32 >= WCAP_A, "register tiles of the Gram");
+  const int ri = threadIdx.x >> 5, ci = threadIdx.x & 31;
+  double gt[GR_][GC_];
+#pragma unroll
+  for (int a = 0; a < GR_; ++a)
+#pragma unroll
+    for (int b = 0; b < GC_; ++b) {
+      const int i = GR_ * ri + a, j = GC_ * ci + b;
+      gt[a][b] = (i < m0 && j < m0) ? Gp[pk(i, j)] : 0.0;
+    }
+  __syncthreads();
   // pivoted right-looking Cholesky: pivot = the largest remaining diagonal,
   // the smallest index among equal ones (every wavefront finds it itself)
   for (int k = 0; k < m0; ++k) {
@@ -1612,30 +1658,40 @@ __device__ __forceinline__ void aug_svd_body(const Dev& d, int s, int axis, int 
     }
     if (p >= m0 || !(best > 1e-20 * dmax) || !isfinite(best)) break;  // the rest is numerically dependent
     const double lpp = sqrt(best), il = 1.0 / lpp;
-    for (int i = threadIdx.x; i < m0; i += JTHR) lcol[i] = (i != p && estep[i] > k) ? Gp[pk(i, p)] * il : 0.0;
+    // the step's factor column from the holders of Gram column p
+    if (ci == p / GC_) {
+      const int cc = p - GC_ * ci;
+#pragma unroll
+      for (int a = 0; a < GR_; ++a) {
+        const int i = GR_ * ri + a;
+        double v = 0.0;
+#pragma unroll
+        for (int b = 0; b < GC_; ++b)
+          if (b == cc) v = gt[a][b];
+        if (i < m0) lcol[i] = (i != p && estep[i] > k) ? v * il : 0.0;
+      }
+    }
     __syncthreads();
-    // the factor column over column p of the packed Gram, then the update
-    // of the remaining block (entries with a zero factor value are left
-    // alone, so the two writes never meet)
-    for (int i = threadIdx.x; i < m0; i += JTHR)
-      if (lcol[i] != 0.0) Gp[pk(i, p)] = lcol[i];
+    for (int i = threadIdx.x; i < m0; i += JTHR) {
+      if (i != p && estep[i] > k) {   // the remaining rows (the rest of the column holds earlier factors)
+        const double l = lcol[i];
+        Gp[pk(i, p)] = l;
+        dg[i] = fma(-l, l, dg[i]);
+      }
+    }
     if (threadIdx.x == 0) {
       Gp[pk(p, p)] = lpp;
       estep[p] = k;
     }
-    for (int j = wave; j < m0; j += JNW) {
-      const double lj = lcol[j];
-      if (lj == 0.0) continue;
-      for (int i = j + lane; i < m0; i += 64) {
-        const double li = lcol[i];
-        if (li != 0.0) {
-          const int o = i * (i + 1) / 2 + j;
-          Gp[o] = fma(-li, lj, Gp[o]);
-        }
-      }
-    }
-    for (int i = threadIdx.x; i < m0; i += JTHR)
-      if (lcol[i] != 0.0) dg[i] = fma(-lcol[i], lcol[i], dg[i]);
+    double li[GR_], lj[GC_];
+#pragma unroll
+    for (int a = 0; a < GR_; ++a) li[a] = GR_ * ri + a < m0 ? lcol[GR_ * ri + a] : 0.0;
+#pragma unroll
+    for (int b = 0; b < GC_; ++b) lj[b] = GC_ * ci + b < m0 ? lcol[GC_ * ci + b] : 0.0;
+#pragma unroll
+    for (int a = 0; a < GR_; ++a)
+#pragma unroll
+      for (int b = 0; b < GC_; ++b) gt[a][b] = fma(-li[a], lj[b], gt[a][b]);
     __syncthreads();
   }
   // columns of the factor into the ring registers: column c (original
