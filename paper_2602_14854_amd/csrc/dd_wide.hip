@@ -663,77 +663,128 @@ __global__ __launch_bounds__(XTHR) void kw_xgram(Dev d, int axis, int sd0, XJobs
     b = pz / J.pa;
   }
   const int nx = src_cols(d, s, axis, J.x), ny = src_cols(d, s, axis, J.y);
+  const bool live = 64 * a < nx && 64 * b < ny;
+  if (!live) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int l16 = lane & 15, kq = lane >> 4;
-  __shared__ double red[16 * 256];
-  const bool live = 64 * a < nx && 64 * b < ny;
+  // a chunk of XR rows of the 64 X columns and 64 Y columns of the block,
+  // column-major in LDS (odd leading dimension); the loads put consecutive
+  // lanes on consecutive rows of one column
+  constexpr int XR = 32, XLD = XR + 1;
+  __shared__ double xs[64 * XLD], ys[64 * XLD];
   const int rows = J.rows_cells ? (J.x.face ? face_len(d, axis) : d.N) : d.M;
   const double* om = axis == 0 ? d.omx : d.omy;
   const double* wcell = J.wmode == 4 ? d.cs + (int64_t)s * d.N : d.ct + (int64_t)s * d.N;
   const int e = axis == 0 ? 1 : d.lnx;
   const int na = axis == 0 ? d.lnx : d.lny;
-  dbl4 acc[16];
-  zero_acc<16>(acc);
-  if (live) {
-    const int nst = wdiv(rows, 16);
-    for (int st = blockIdx.x * 4 + wave; st < nst; st += gridDim.x * 4) {
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        const int row = st * 16 + 4 * kk + kq;
-        const bool rin = row < rows;
-        const int rc = rin ? row : 0;
-        double wt = rin ? 1.0 : 0.0;
-        if (J.wmode == 1) wt *= om[rc];
-        else if (J.wmode == 2) wt *= om[rc] >= 0.0 ? 1.0 : 0.0;
-        else if (J.wmode == 3) wt *= om[rc] < 0.0 ? 1.0 : 0.0;
-        else if (J.wmode >= 4) wt *= wcell[rc];
-        bool hs = false;
-        if (J.shift) {
-          const int ia = axis == 0 ? rc % d.lnx : rc / d.lnx;
-          hs = ia < na - 1;
-        }
-        double xa[4], yb[4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const int ci = 64 * a + 16 * c + l16, cj = 64 * b + 16 * c + l16;
-          const bool xin = ci < nx, yin = cj < ny;
-          const double xv = src_load<W>(d, s, axis, J.x, rc, xin ? ci : 0);
-          double yv = src_load<W>(d, s, axis, J.y, rc, yin ? cj : 0);
-          if (J.shift) {
-            const double y1 = src_load<W>(d, s, axis, J.y, hs ? rc + e : rc, yin ? cj : 0);
-            yv = (hs ? y1 : 0.0) - yv;
-          }
-          xa[c] = xin ? xv * wt : 0.0;
-          yb[c] = (yin && rin) ? yv : 0.0;
-        }
-#pragma unroll
-        for (int ci = 0; ci < 4; ++ci)
-#pragma unroll
-          for (int cj = 0; cj < 4; ++cj) acc[ci * 4 + cj] = mfma64(xa[ci], yb[cj], acc[ci * 4 + cj]);
-      }
+  // per-source constants
+  const int sdx = src_subdomain(d, s, axis, J.x.side), sdy = src_subdomain(d, s, axis, J.y.side);
+  const int64_t bx = (int64_t)(sdx < 0 ? 0 : sdx) * J.x.sd, by = (int64_t)(sdy < 0 ? 0 : sdy) * J.y.sd;
+  const int cx0 = 64 * a, cy0 = 64 * b;
+  // thread (wave, lane) loads row lane % 32 of the columns 2 (8 wave + q) +
+  // lane / 32 (q < 8) of the chunk, for X and for Y
+  constexpr int NQ = 64 * XR / XTHR;
+  const int lr = lane % XR, lc = lane / XR;  // XR = 32: two columns per load instruction
+  auto fetch = [&](int ch, double (&xv)[NQ], double (&yv)[NQ]) {
+    const int row = ch * XR + lr;
+    const bool rin = row < rows;
+    const int rc = rin ? row : 0;
+    double wt = rin ? 1.0 : 0.0;
+    if (J.wmode == 1) wt *= om[rc];
+    else if (J.wmode == 2) wt *= om[rc] >= 0.0 ? 1.0 : 0.0;
+    else if (J.wmode == 3) wt *= om[rc] < 0.0 ? 1.0 : 0.0;
+    else if (J.wmode >= 4) wt *= wcell[rc];
+    const int px = src_row(d, axis, J.x, rc), py = src_row(d, axis, J.y, rc);
+    bool hs = false;
+    if (J.shift) {
+      const int ia = axis == 0 ? rc % d.lnx : rc / d.lnx;
+      hs = ia < na - 1;
     }
+    const double sx = J.x.rowscale ? d.sw[px] : 1.0, sy = J.y.rowscale ? d.sw[py] : 1.0;
+    const double sy1 = (J.shift && J.y.rowscale) ? d.sw[hs ? py + e : py] : sy;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int cl = 2 * (NQ * wave + q) + lc;  // column of the block, 0..63
+      const int ci = cx0 + cl, cj = cy0 + cl;
+      const bool xin = ci < nx, yin = cj < ny;
+      double v = 0.0, u = 0.0;
+      if (xin && wt != 0.0) {
+        if (J.x.vec) v = ((const double*)J.x.p)[bx + px];
+        else if (J.x.is64) v = ((const double*)J.x.p)[bx + (int64_t)ci * J.x.ld + px];
+        else v = (double)((const W*)J.x.p)[bx + (int64_t)ci * J.x.ld + px];
+        v = v * sx * wt;
+      }
+      if (yin && rin) {
+        const int64_t o = J.y.vec ? by + py : by + (int64_t)cj * J.y.ld + py;
+        const bool w64 = J.y.vec || J.y.is64;
+        u = w64 ? ((const double*)J.y.p)[o] : (double)((const W*)J.y.p)[o];
+        u *= sy;
+        if (J.shift) {
+          double u1 = 0.0;
+          if (hs) {
+            const int64_t o1 = o + e;
+            u1 = (w64 ? ((const double*)J.y.p)[o1] : (double)((const W*)J.y.p)[o1]) * sy1;
+          }
+          u = u1 - u;
+        }
+      }
+      xv[q] = v;
+      yv[q] = u;
+    }
+  };
+  auto stash = [&](const double (&xv)[NQ], const double (&yv)[NQ]) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int cl = 2 * (NQ * wave + q) + lc;
+      xs[cl * XLD + lr] = xv[q];
+      ys[cl * XLD + lr] = yv[q];
+    }
+  };
+  // wavefront w accumulates the output rows 16 w .. 16 w + 15 of the block
+  dbl4 acc[4];
+  zero_acc<4>(acc);
+  const int nch = wdiv(rows, XR);
+  double xv[NQ], yv[NQ];
+  int ch = blockIdx.x;
+  if (ch < nch) fetch(ch, xv, yv);
+  for (; ch < nch; ch += gridDim.x) {
+    __syncthreads();
+    stash(xv, yv);
+    __syncthreads();
+    if (ch + (int)gridDim.x < nch) fetch(ch + gridDim.x, xv, yv);  // the next chunk's loads overlap the MFMAs
+    const double* xa = xs + (16 * wave + l16) * XLD + kq;
+    const double* yb = ys + l16 * XLD + kq;
+    // each chunk is summed on its own and then added to the running total,
+    // so no chain of roundings runs over more than one chunk (the angular
+    // sums cancel strongly near sources)
+    dbl4 cacc[4];
+    zero_acc<4>(cacc);
+#pragma unroll
+    for (int ks = 0; ks < XR / 4; ++ks) {
+      const double av = xa[4 * ks];
+#pragma unroll
+      for (int cj = 0; cj < 4; ++cj) cacc[cj] = mfma64(av, yb[16 * cj * XLD + 4 * ks], cacc[cj]);
+    }
+#pragma unroll
+    for (int cj = 0; cj < 4; ++cj) acc[cj] += cacc[cj];
   }
-  wg_reduce_acc<16>(acc, red);
-  if (wave != 0 || !live) return;
   double* out = gpart_of(d, s) + (int64_t)blockIdx.x * d.gpTile + J.out_off;
   const int ld = J.out_ld > 0 ? J.out_ld : nx;
 #pragma unroll
-  for (int ci = 0; ci < 4; ++ci)
+  for (int cj = 0; cj < 4; ++cj)
 #pragma unroll
-    for (int cj = 0; cj < 4; ++cj)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = 64 * a + 16 * ci + 4 * v + kq, j = 64 * b + 16 * cj + l16;
-        if (i >= nx || j >= ny) continue;
-        const double val = J.scale * acc[ci * 4 + cj][v];
-        if (J.sym) {
-          if (a == b && i > j) continue;
-          out[i + (int64_t)j * ld] = val;
-          out[j + (int64_t)i * ld] = val;
-        } else {
-          out[i + (int64_t)j * ld] = val;
-        }
+    for (int v = 0; v < 4; ++v) {
+      const int i = 64 * a + 16 * wave + 4 * v + kq, j = 64 * b + 16 * cj + l16;
+      if (i >= nx || j >= ny) continue;
+      const double val = J.scale * acc[cj][v];
+      if (J.sym) {
+        if (a == b && i > j) continue;
+        out[i + (int64_t)j * ld] = val;
+        out[j + (int64_t)i * ld] = val;
+      } else {
+        out[i + (int64_t)j * ld] = val;
       }
+    }
 }
 
 // ============================================================================
