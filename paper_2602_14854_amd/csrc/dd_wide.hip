@@ -1032,36 +1032,72 @@ __device__ void ns_abs(const double* C, double* X, double* Y, double* W, double*
   gmm_sym(out, ld, X, ld, C, ld, t, 1.0, 0.0, out, ld);  // sign(C) C
 }
 
-// Right-looking Cholesky G = L L^T of the n x n matrix in LDS (lower
-// triangle, ld WLD; n <= 128) in place.  dep[k] = 1 marks a pivot at most
+// Right-looking Cholesky G = L L^T of the n x n matrix in LDS (ld WLD,
+// n <= 128), L written over its lower triangle; the matrix being reduced
+// is held in registers, so each column costs two barriers and no LDS
+// traffic beyond the column itself.  dep[k] = 1 marks a pivot at most
 // 1e-20 of its initial diagonal d0[k] (or not finite): its column is set to
 // the unit vector, so the factorisation goes on.  Returns the smallest ratio
 // pivot / d0 met (for the unshifted first try).  The strict upper triangle
-// is zeroed on exit.
-__device__ double lds_chol(const Dev& d, double* L, int n, const double* d0, int* dep, double* red) {
+// is zeroed on exit.  col: n doubles of LDS scratch.
+__device__ double lds_chol(const Dev& d, double* L, int n, const double* d0, int* dep, double* red, double* col) {
+  // the active matrix in registers: thread (ri, ci) = (tid / 32, tid % 32)
+  // holds rows 4 ri .. 4 ri + 3 and columns 4 ci .. 4 ci + 3 of the full
+  // square (both triangles get the same updates); each step's column goes
+  // through LDS (col) and its scaled values into L
+  static_assert(4 * 32 >= WCAP_T && STHR == 1024, "register tiles of the Gram");
   double& minratio = red[SNW];
+  const int ri = threadIdx.x >> 5, ci = threadIdx.x & 31;
+  double g[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int i = 4 * ri + a, j = 4 * ci + b;
+      g[a][b] = (i < n && j < n) ? L[i + j * WLD] : 0.0;
+    }
   if (threadIdx.x == 0) minratio = 1e300;
   __syncthreads();
   for (int k = 0; k < n; ++k) {
-    const double pv = L[k + k * WLD];
+    // the holders of column k publish it
+    if (ci == (k >> 2)) {
+      const int cc = k & 3;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        double v = 0.0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          if (b == cc) v = g[a][b];
+        if (4 * ri + a < n) col[4 * ri + a] = v;
+      }
+    }
+    __syncthreads();
+    const double pv = col[k];
     const bool isdep = !isfinite(pv) || !(pv > 1e-20 * d0[k]);
     const double lkk = isdep ? 1.0 : sqrt(pv);
     const double il = 1.0 / lkk;
-    __syncthreads();
     if (threadIdx.x == 0) {
       dep[k] = isdep ? 1 : 0;
       minratio = fmin(minratio, isdep ? 0.0 : pv / d0[k]);
       L[k + k * WLD] = lkk;
       if (!isfinite(pv)) atomicOr(d.flags, FLAG_NONFINITE);
     }
-    for (int i = k + 1 + (int)threadIdx.x; i < n; i += blockDim.x)
-      L[i + k * WLD] = isdep ? 0.0 : L[i + k * WLD] * il;
-    __syncthreads();
-    const int m = n - k - 1;
-    for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
-      const int i = k + 1 + idx % m, j = k + 1 + idx / m;
-      if (i >= j) L[i + j * WLD] = fma(-L[i + k * WLD], L[j + k * WLD], L[i + j * WLD]);
+    for (int i = k + 1 + (int)threadIdx.x; i < n; i += blockDim.x) L[i + k * WLD] = isdep ? 0.0 : col[i] * il;
+    double li[4], lj[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int i = 4 * ri + a;
+      li[a] = (i > k && i < n && !isdep) ? col[i] * il : 0.0;
     }
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int j = 4 * ci + b;
+      lj[b] = (j > k && j < n && !isdep) ? col[j] * il : 0.0;
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) g[a][b] = fma(-li[a], lj[b], g[a][b]);
     __syncthreads();
   }
   for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
@@ -1597,7 +1633,7 @@ __global__ __launch_bounds__(STHR) void sw_chol(Dev d, int axis, int sd0, int nd
     }
     for (int i = threadIdx.x; i < n; i += STHR) d0[i] = L[i * (WLD + 1)];
     __syncthreads();
-    const double mr = lds_chol(d, L, n, d0, dep, sc.red);
+    const double mr = lds_chol(d, L, n, d0, dep, sc.red, sc.v1);
     if (shifted || mr >= 1e-12) break;
     shifted = true;
   }
