@@ -303,6 +303,17 @@ Layout make_layout(const dd_dlra_config* c) {
   return L;
 }
 
+// The wide plan's reductions read by wide kernels use twice the workgroups
+// per subdomain of the other tall-skinny kernels (up to the room for
+// partial sums): their launch length is set by the few high-rank
+// subdomains, which then spread over more compute units.
+void set_wide_partials(Dev& d) {
+  const int capN = std::max(1, (int)(d.gpStride / d.gpTile));
+  d.xpN = std::min(2 * d.nwgN, capN);
+  d.xpM = std::min(2 * d.nwgM, capN);
+}
+
+
 void fill_dev(Dev& d, const Layout& L, const dd_dlra_config* c, char* base) {
   memset(&d, 0, sizeof(d));
   d.px = c->px;
@@ -328,6 +339,7 @@ void fill_dev(Dev& d, const Layout& L, const dd_dlra_config* c, char* base) {
   d.nwgM = L.nwgM;
   d.gpTile = L.gpTile;
   d.gpStride = L.gpStride;
+  set_wide_partials(d);
   d.smallStride = L.smallStride;
   d.rank_mode = c->rank_mode;
   d.r_fixed = c->r_fixed;
@@ -764,14 +776,17 @@ dd::XJob xjob(const dd::XSrc& x, const dd::XSrc& y, int capx, int capy, int wmod
 }
 
 // partial Grams X^T X of a working array (ld rows), live ld
+// Gram of X into the partial sums; wide: read by a wide kernel (d.xpN /
+// d.xpM partials), else by a narrow one (d.nwgN / d.nwgM)
 void w_gram(dd_dlra_handle h, int kind, int axis, const void* X, bool is64, int64_t sd, int rows, int ndim, int cap,
-            bool cells) {
+            bool cells, bool wide) {
   const Dev& d = h->d;
   dd::XJobs jobs;
   jobs.n = 1;
   const dd::XSrc x = xsrc(X, sd, rows, ndim, is64);
   jobs.j[0] = xjob(x, x, cap, cap, 0, true, 0, -1);
-  phase(h, kind, [&](int s0, int ns) { dd::launch_w_xgram(d, axis, s0, ns, jobs, cells, h->stream); });
+  const int np = wide ? (cells ? d.xpN : d.xpM) : (cells ? d.nwgN : d.nwgM);
+  phase(h, kind, [&](int s0, int ns) { dd::launch_w_xgram(d, axis, s0, ns, jobs, cells, np, h->stream); });
 }
 
 // passes of Cholesky QR of X (rows x n, n = dim ndim <= 128) for the wide
@@ -780,12 +795,12 @@ void w_gram(dd_dlra_handle h, int kind, int axis, const void* X, bool is64, int6
 void* w_chol_qr(dd_dlra_handle h, int axis, int ndim, void* X, void* Y, int64_t sd, int rows, bool cells, int passes,
                 bool acc, int gram_kind, int gemm_kind) {
   const Dev& d = h->d;
-  const int ngp = cells ? d.nwgN : d.nwgM;
+  const int ngp = cells ? d.xpN : d.xpM;
   const int cap = ndim == dd::DIM_T ? d.T : d.R;
   void* cur = X;
   void* oth = Y;
   for (int pass = 0; pass < passes; ++pass) {
-    w_gram(h, gram_kind, axis, cur, false, sd, rows, ndim, cap, cells);
+    w_gram(h, gram_kind, axis, cur, false, sd, rows, ndim, cap, cells, true);
     phase(h, K_W_CHOL, [&](int s0, int ns) {
       dd::launch_w_chol(d, axis, s0, ns, ndim, rows, ngp, acc ? (pass == 0 ? 1 : 2) : 0, 1.0, d.oRinv, d.oRacc, d.T,
                         pass > 0, h->stream);
@@ -808,7 +823,7 @@ void enqueue_advection_wide(dd_dlra_handle h, int axis, int upto = 0) {
   // Algorithm 4: A = sqrt(w) L0, its Gram, the SVD through the pivoted
   // Cholesky factor, V-hat = A B Sigma^-2, two Cholesky-QR passes
   phase(h, K_AUG_FORM, [&](int s0, int ns) { dd::launch_w_aug_form(d, axis, s0, ns, st); });
-  w_gram(h, K_W_GRAM_A, axis, d.A, true, sdMA, d.M, dd::DIM_M0, d.MA, false);
+  w_gram(h, K_W_GRAM_A, axis, d.A, true, sdMA, d.M, dd::DIM_M0, d.MA, false, true);
   phase(h, K_AUG_SVD, [&](int s0, int ns) { dd::launch_w_aug_svd(d, axis, s0, ns, st); });
   phase(h, K_GEMM_VHAT, [&](int s0, int ns) {
     dd::launch_w_gemm(d, axis, s0, ns, d.A, true, sdMA, d.M, dd::DIM_M0, dd::DIM_T, d.oCoef, d.MA, d.Qh, false, sdMT,
@@ -828,7 +843,7 @@ void enqueue_advection_wide(dd_dlra_handle h, int axis, int upto = 0) {
     jobs.j[3] = xjob(qh, qh, T, T, 3, true, R * T + 2 * T * T, -1);
     jobs.j[4] = xjob(xsrc(d.V, sdMR, d.M, dd::DIM_R, true, -1, true), qh, R, T, 2, false, R * T + 3 * T * T, R);
     jobs.j[5] = xjob(xsrc(d.V, sdMR, d.M, dd::DIM_R, true, +1, true), qh, R, T, 3, false, 2 * R * T + 3 * T * T, R);
-    phase(h, K_W_ANG, [&](int s0, int ns) { dd::launch_w_xgram(d, axis, s0, ns, jobs, false, st); });
+    phase(h, K_W_ANG, [&](int s0, int ns) { dd::launch_w_xgram(d, axis, s0, ns, jobs, false, d.xpM, st); });
   }
   phase(h, K_ADV_PREP, [&](int s0, int ns) { dd::launch_w_adv_prep(d, axis, s0, ns, st); });
   // Algorithm 1/2 steps 1-2: K-step, QR (three passes: K1 -> K2 -> K1 -> K2)
@@ -867,7 +882,7 @@ void enqueue_advection_wide(dd_dlra_handle h, int axis, int upto = 0) {
     jobs.j[2] = xjob(qhf, xsrc(d.U, sdNR, d.N, dd::DIM_R, true, 0, false, 2), T, R, 0, false, oX + T * R, T);
     jobs.j[3] = xjob(ql, xsrc(d.U, sdNR, d.N, dd::DIM_R, true, -1, false, 2), T, R, 0, false, oX + 2 * T * R, T);
     jobs.j[4] = xjob(qhf, xsrc(d.U, sdNR, d.N, dd::DIM_R, true, +1, false, 1), T, R, 0, false, oX + 3 * T * R, T);
-    phase(h, K_W_SPATIAL, [&](int s0, int ns) { dd::launch_w_xgram(d, axis, s0, ns, jobs, true, st); });
+    phase(h, K_W_SPATIAL, [&](int s0, int ns) { dd::launch_w_xgram(d, axis, s0, ns, jobs, true, d.xpN, st); });
   }
   phase(h, K_ADV_SSTEP, [&](int s0, int ns) { dd::launch_w_adv_sstep(d, axis, s0, ns, st); });
   if (upto == DD_PROBE_S2) return;
@@ -894,7 +909,7 @@ void enqueue_collision_wide(dd_dlra_handle h) {
   const int R = d.R;
   phase(h, K_COLL_PREP, [&](int s0, int ns) { dd::launch_w_coll_prep(d, s0, ns, st); });
   phase(h, K_COLL_KSTEP, [&](int s0, int ns) { dd::launch_w_coll_kstep(d, s0, ns, st); });
-  w_gram(h, K_W_GRAM_KC, 0, d.K1, false, sdNT, d.N, dd::DIM_R, R, true);
+  w_gram(h, K_W_GRAM_KC, 0, d.K1, false, sdNT, d.N, dd::DIM_R, R, true, false);  // read by the narrow Cholesky QR
   // QR of K1 (stored ranks <= 64: the narrow Cholesky-QR kernels); the last
   // product writes U^1 = Q / h into the state
   chol_qr3(h, 0, dd::DIM_R, d.K1, d.K2, sdNT, d.N, true, d.U, (int64_t)d.N * d.R, nullptr, 1.0 / d.h, K_GEMM_QR_KC,
@@ -909,7 +924,7 @@ void enqueue_collision_wide(dd_dlra_handle h) {
     jobs.j[0] = xjob(u, u, R, R, 4, true, 0, R, h2);
     jobs.j[1] = xjob(u, u, R, R, 5, true, R * R, R, h2);
     jobs.j[2] = xjob(u, qv, R, 1, 0, false, 2 * R * R, R, h2);
-    phase(h, K_W_COLL_REDUCE, [&](int s0, int ns) { dd::launch_w_xgram(d, 0, s0, ns, jobs, true, st); });
+    phase(h, K_W_COLL_REDUCE, [&](int s0, int ns) { dd::launch_w_xgram(d, 0, s0, ns, jobs, true, d.nwgN, st); });
   }
   phase(h, K_COLL_SSTEP, [&](int s0, int ns) { dd::launch_coll_sstep(d, s0, ns, st); });
   phase(h, K_COLL_LSTEP, [&](int s0, int ns) { dd::launch_coll_lstep(d, s0, ns, st); });
@@ -1051,6 +1066,7 @@ dd_status dd_dlra_create(const dd_dlra_config* cfg, const int32_t* rank0, const 
     const int per_sd = std::max(1, ncu * occ / d.nsub);
     d.nwgN = std::min(per_sd, L.nwgN);
     d.nwgM = std::min(per_sd, L.nwgM);
+    set_wide_partials(d);
   }
   if (hipMemsetAsync(h->ws, 0, L.bytes, h->stream) != hipSuccess) {
     h->err = "hipMemsetAsync failed";
@@ -1156,6 +1172,7 @@ dd_status dd_dlra_set_tiling(dd_dlra_handle h, int32_t wg_per_subdomain) {
   const int w = std::min((int)wg_per_subdomain, capN);
   d.nwgN = std::min(w, d.ntN);
   d.nwgM = std::min(w, d.ntM);
+  set_wide_partials(d);
   drop_graph(h);
   return DD_OK;
 }
@@ -1200,6 +1217,7 @@ dd_status dd_dlra_autotune(dd_dlra_handle h, int32_t steps, int32_t* wg_per_subd
   for (size_t i = 0; i < cands.size() && e == hipSuccess; ++i) {
     d.nwgN = std::min(cands[i], ntN);
     d.nwgM = std::min(cands[i], ntM);
+    set_wide_partials(d);
     drop_graph(h);
     dd_status st = dd_dlra_step(h, 1);  // warm-up (captures the graph in graph mode)
     if (st != DD_OK) {
@@ -1229,6 +1247,7 @@ dd_status dd_dlra_autotune(dd_dlra_handle h, int32_t steps, int32_t* wg_per_subd
   }
   d.nwgN = std::min(best, ntN);
   d.nwgM = std::min(best, ntM);
+  set_wide_partials(d);
   if (wg_per_subdomain) *wg_per_subdomain = best;
   if (ms_per_step) *ms_per_step = best_ms / steps;
   return DD_OK;

@@ -52,7 +52,7 @@ void launch_w_aug_form(const Dev& d, int axis, int sd0, int nsd, hipStream_t st)
 void launch_w_kstep(const Dev& d, int axis, int sd0, int nsd, hipStream_t st);
 void launch_w_lstep(const Dev& d, int axis, int sd0, int nsd, hipStream_t st);
 void launch_w_coll_kstep(const Dev& d, int sd0, int nsd, hipStream_t st);
-void launch_w_xgram(const Dev& d, int axis, int sd0, int nsd, XJobs jobs, bool cells, hipStream_t st);
+void launch_w_xgram(const Dev& d, int axis, int sd0, int nsd, XJobs jobs, bool cells, int np, hipStream_t st);
 // near: a Gram within 1e-3 of the identity takes the symmetric factor from
 // the binomial series instead of the Cholesky factorisation
 void launch_w_chol(const Dev& d, int axis, int sd0, int nsd, int ndim, int rows, int ngp, int acc_mode,

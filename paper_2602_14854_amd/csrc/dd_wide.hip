@@ -1692,7 +1692,7 @@ __device__ __forceinline__ void aug_svd_body(const Dev& d, int s, int axis, int 
   // columns j over the wavefronts, rows i >= j over the lanes
   {
     const double* gp = gpart_of(d, s);
-    const int ngp = d.nwgM;
+    const int ngp = d.xpM;
     for (int j = wave; j < m0; j += JNW)
       for (int i = j + lane; i < m0; i += 64) {
         const int64_t src = i + (int64_t)j * m0;
@@ -1901,7 +1901,7 @@ __device__ void adv_prep_body(const Dev& d, int s, int axis, int t, double* lds,
   double* sm = small_of(d, s);
   double* Cl = lds;  // t x t, ld WLD
   const int pT = 0, pC = R * T, pEp = pC + T * T, pEn = pEp + T * T, pOlo = pEn + T * T, pOhi = pOlo + R * T;
-  const int ngp = d.nwgM;
+  const int ngp = d.xpM;
   s_sum_partials(d, s, ngp, pT, R, r, t, sm + d.oTm, R, 1.0);
   s_sum_partials(d, s, ngp, pEp, t, t, t, sm + d.oEp, T, 1.0);
   s_sum_partials(d, s, ngp, pEn, t, t, t, sm + d.oEn, T, 1.0);
@@ -2028,7 +2028,7 @@ __global__ __launch_bounds__(STHR) void sw_adv_sstep(Dev d, int axis, int sd0) {
   double* Xhi = sm + d.oW2;
   double* Xln = sm + d.oW3;
   double* Xhn = sm + d.oW4;
-  const int oX = 2 * T * T, ngp = d.nwgN;
+  const int oX = 2 * T * T, ngp = d.xpN;
   s_sum_partials(d, s, ngp, 0, t, t, t, Gp, T, ih);
   s_sum_partials(d, s, ngp, oX, T, t, r, Xlo, T, 1.0);
   s_sum_partials(d, s, ngp, oX + T * R, T, t, r, Xhi, T, 1.0);
@@ -2398,7 +2398,7 @@ void launch_w_coll_kstep(const Dev& d, int sd0, int nsd, hipStream_t st) {
   });
 }
 
-void launch_w_xgram(const Dev& d, int axis, int sd0, int nsd, XJobs jobs, bool cells, hipStream_t st) {
+void launch_w_xgram(const Dev& d, int axis, int sd0, int nsd, XJobs jobs, bool cells, int np, hipStream_t st) {
   int z = 0;
   for (int q = 0; q < jobs.n; ++q) {
     XJob& J = jobs.j[q];
@@ -2407,10 +2407,10 @@ void launch_w_xgram(const Dev& d, int axis, int sd0, int nsd, XJobs jobs, bool c
     J.rows_cells = cells ? 1 : 0;
   }
   if (d.prec == DD_PREC_FP64)
-    hipLaunchKernelGGL(kw_xgram<double>, dim3(cells ? d.nwgN : d.nwgM, nsd, z), dim3(XTHR), 0, st, d, axis, sd0,
+    hipLaunchKernelGGL(kw_xgram<double>, dim3(np, nsd, z), dim3(XTHR), 0, st, d, axis, sd0,
                        jobs);
   else
-    hipLaunchKernelGGL(kw_xgram<float>, dim3(cells ? d.nwgN : d.nwgM, nsd, z), dim3(XTHR), 0, st, d, axis, sd0,
+    hipLaunchKernelGGL(kw_xgram<float>, dim3(np, nsd, z), dim3(XTHR), 0, st, d, axis, sd0,
                        jobs);
 }
 
