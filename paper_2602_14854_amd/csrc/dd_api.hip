@@ -207,7 +207,7 @@ Layout make_layout(const dd_dlra_config* c) {
   L.ntM = (L.M + dd::TILE - 1) / dd::TILE;
   // room for partial sums of up to this many workgroups per subdomain (the
   // grid actually used is chosen at creation from the kernels' occupancy)
-  const int cap = std::min(64, std::max(1, (2048 + L.nsub - 1) / L.nsub));
+  const int cap = std::min(64, std::max(1, (4096 + L.nsub - 1) / L.nsub));
   L.nwgN = std::min(L.ntN, cap);
   L.nwgM = std::min(L.ntM, cap);
   const int R = L.R, T = L.T, MA = L.MA;
@@ -1204,7 +1204,7 @@ dd_status dd_dlra_autotune(dd_dlra_handle h, int32_t steps, int32_t* wg_per_subd
   const int capN = std::max(1, (int)(d.gpStride / d.gpTile));
   const int base = std::max(1, ncu * dd::ts_resident_wgs(d) / d.nsub);
   std::vector<int> cands;
-  for (int c : {base / 4, base / 2, base, 2 * base, 4 * base}) {
+  for (int c : {base / 4, base / 2, base, 2 * base, 4 * base, 8 * base, 16 * base}) {
     const int v = std::max(1, std::min(c, capN));
     if (std::find(cands.begin(), cands.end(), v) == cands.end()) cands.push_back(v);
   }

@@ -99,15 +99,17 @@ __device__ __forceinline__ void bf16_split(float x, __bf16& hi, __bf16& lo) {
   lo = (__bf16)(x - (float)hi);
 }
 
-// acc[cb] += sum over the NSUB sub-steps u of (fragment u, block cb) x xv[u].
-// frag[(u * NCB + cb) * 64 + lane] is the coefficient operand B[sub_col(u,
-// kq)][16 cb + l16]; xv[u] the row's value in column sub_col(u, kq).  All
-// NSUB sub-steps are issued (operands beyond the live columns are zero): a
-// branch between matrix-core instructions would make the compiler copy the
-// accumulators between register files around it.
-template <int P, int NCB, int NSUB>
+// acc[cb] += sum over the NSUB sub-steps u of (fragment u, block cb) x xv[u],
+// cb < NCB.  frag[(u * NCL + cb) * 64 + lane] is the coefficient operand
+// B[sub_col(u, kq)][16 cb + l16] (NCL column blocks per sub-step in the
+// array, of which the first NCB are used); xv[u] the row's value in column
+// sub_col(u, kq).  All NSUB sub-steps are issued (operands beyond the live
+// columns are zero): a branch between matrix-core instructions would make
+// the compiler copy the accumulators between register files around it.
+template <int P, int NCB, int NSUB, int NCL = NCB>
 __device__ __forceinline__ void prod_acc(typename Prec<P>::Acc* acc, const typename Prec<P>::F* frag,
                                          const typename Prec<P>::F* xv) {
+  static_assert(NCB <= NCL, "column blocks beyond the fragment layout");
   const int lane = threadIdx.x & 63;
   if constexpr (P == 2) {
     static_assert(NSUB % 8 == 0, "split-BF16 operands come in whole 32-column instructions");
@@ -127,7 +129,7 @@ __device__ __forceinline__ void prod_acc(typename Prec<P>::Acc* acc, const typen
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
           __bf16 h, l;
-          bf16_split(frag[((8 * g + i) * NCB + cb) * 64 + lane], h, l);
+          bf16_split(frag[((8 * g + i) * NCL + cb) * 64 + lane], h, l);
           ah[i] = h;
           al[i] = l;
         }
@@ -142,9 +144,9 @@ __device__ __forceinline__ void prod_acc(typename Prec<P>::Acc* acc, const typen
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb) {
         if constexpr (P == 0)
-          acc[cb] = mfma64(frag[(u * NCB + cb) * 64 + lane], xv[u], acc[cb]);
+          acc[cb] = mfma64(frag[(u * NCL + cb) * 64 + lane], xv[u], acc[cb]);
         else
-          acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(frag[(u * NCB + cb) * 64 + lane], xv[u], acc[cb], 0, 0, 0);
+          acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(frag[(u * NCL + cb) * 64 + lane], xv[u], acc[cb], 0, 0, 0);
       }
     }
   }

@@ -35,6 +35,8 @@ constexpr int XTHR = 256;          // threads of a wide reduction (kw_xgram)
 constexpr int STHR = 1024;         // threads of a wide small kernel
 constexpr int SNW = STHR / 64;
 constexpr int WLD = WCAP_T + 1;    // leading dimension of LDS matrices of order <= 128
+template <int V>
+using wint = std::integral_constant<int, V>;
 
 __host__ __device__ constexpr int wdiv(int a, int b) { return (a + b - 1) / b; }
 
@@ -88,51 +90,62 @@ __global__ __launch_bounds__(WTHR) void kw_gemm(Dev d, int axis, int sd0, const 
   SO* Ys = (SO*)Y + (int64_t)s * ysd;
   const int nst = wdiv(rows, 16);
   const int stride = gridDim.x * WNW;
-  F xv[16], xn[16];
-  auto load = [&](int st_, int g_) {
-    const int row_ = st_ * 16 + l16;
-    const int rc = row_ < rows ? row_ : rows - 1;
+  // NS sub-steps of each 64-column group of X and NC column blocks of the
+  // output are issued; a subdomain of low rank (one group with few live
+  // columns, few output columns) takes a shorter instance
+  auto run = [&](auto ns_c, auto nc_c) {
+    constexpr int NS = decltype(ns_c)::value, NC = decltype(nc_c)::value;
+    F xv[NS], xn[NS];
+    auto load = [&](int st_, int g_) {
+      const int row_ = st_ * 16 + l16;
+      const int rc = row_ < rows ? row_ : rows - 1;
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int kc = 64 * g_ + sub_col<P>(u, kq);
-      const bool in = row_ < rows && kc < k;
-      const SI v = Xs[(int64_t)(in ? kc : 0) * rows + rc];
-      xn[u] = in ? (F)v : (F)0;
+      for (int u = 0; u < NS; ++u) {
+        const int kc = 64 * g_ + sub_col<P>(u, kq);
+        const bool in = row_ < rows && kc < k;
+        const SI v = Xs[(int64_t)(in ? kc : 0) * rows + rc];
+        xn[u] = in ? (F)v : (F)0;
+      }
+    };
+    int st = blockIdx.x * WNW + wave, g = 0;
+    if (st < nst) load(st, 0);
+    Acc acc[NC];
+    zero_prod<P>(acc, NC);
+    while (st < nst) {
+#pragma unroll
+      for (int u = 0; u < NS; ++u) xv[u] = xn[u];
+      int st2 = st, g2 = g + 1;
+      if (g2 >= ng) {
+        g2 = 0;
+        st2 = st + stride;
+      }
+      if (st2 < nst) load(st2, g2);
+      prod_acc<P, NC, NS, NCB>(acc, frag + g * 16 * NCB * 64, xv);
+      if (g == ng - 1) {
+        const int row = st * 16 + l16;
+        const bool rin = row < rows;
+        const double rs = (rowscale != nullptr && rin) ? rowscale[row] : 1.0;
+#pragma unroll
+        for (int cb = 0; cb < NC; ++cb) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int j = out_col<P>(cb, v, kq);
+            double val = (double)acc[cb][v] * rs;
+            if (fillm[j]) val = hash_unit(((uint64_t)s << 40) ^ ((uint64_t)(c0 + j) << 24) ^ (uint64_t)row);
+            if (rin && c0 + j < n) Ys[(int64_t)(c0 + j) * rows + row] = (SO)val;
+          }
+        }
+        zero_prod<P>(acc, NC);
+      }
+      st = st2;
+      g = g2;
     }
   };
-  int st = blockIdx.x * WNW + wave, g = 0;
-  if (st < nst) load(st, 0);
-  Acc acc[NCB];
-  zero_prod<P>(acc, NCB);
-  while (st < nst) {
-#pragma unroll
-    for (int u = 0; u < 16; ++u) xv[u] = xn[u];
-    int st2 = st, g2 = g + 1;
-    if (g2 >= ng) {
-      g2 = 0;
-      st2 = st + stride;
-    }
-    if (st2 < nst) load(st2, g2);
-    prod_acc<P, NCB, 16>(acc, frag + g * 16 * NCB * 64, xv);
-    if (g == ng - 1) {
-      const int row = st * 16 + l16;
-      const bool rin = row < rows;
-      const double rs = (rowscale != nullptr && rin) ? rowscale[row] : 1.0;
-#pragma unroll
-      for (int cb = 0; cb < NCB; ++cb) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int j = out_col<P>(cb, v, kq);
-          double val = (double)acc[cb][v] * rs;
-          if (fillm[j]) val = hash_unit(((uint64_t)s << 40) ^ ((uint64_t)(c0 + j) << 24) ^ (uint64_t)row);
-          if (rin && c0 + j < n) Ys[(int64_t)(c0 + j) * rows + row] = (SO)val;
-        }
-      }
-      zero_prod<P>(acc, NCB);
-    }
-    st = st2;
-    g = g2;
-  }
+  constexpr int NS1 = P == 2 ? 8 : 4;  // one matrix-core instruction (P = 2: one 32-column one)
+  const int ls = live_sub<P>(k), nl = n - c0;
+  if (ng == 1 && ls <= NS1 && nl <= 16) run(wint<NS1>{}, wint<1>{});
+  else if (ng == 1 && ls <= 8 && nl <= 32 && NCB >= 2) run(wint<8>{}, wint<(NCB >= 2 ? 2 : 1)>{});
+  else run(wint<16>{}, wint<NCB>{});
 }
 
 // Augmentation matrix (Algorithm 4, step 1), one source block per blockIdx.z
@@ -638,7 +651,7 @@ __device__ __forceinline__ double src_load(const Dev& d, int s, int axis, const 
 }
 
 template <class W>
-__global__ __launch_bounds__(XTHR) void kw_xgram(Dev d, int axis, int sd0, XJobs jobs) {
+__global__ __launch_bounds__(XTHR, 4) void kw_xgram(Dev d, int axis, int sd0, XJobs jobs) {
   const int s = sd0 + blockIdx.y;
   int jb = 0;
 #pragma unroll
@@ -685,6 +698,10 @@ __global__ __launch_bounds__(XTHR) void kw_xgram(Dev d, int axis, int sd0, XJobs
   // lane / 32 (q < 8) of the chunk, for X and for Y
   constexpr int NQ = 64 * XR / XTHR;
   const int lr = lane % XR, lc = lane / XR;  // XR = 32: two columns per load instruction
+  const double* xd = (const double*)J.x.p + bx;
+  const W* xw = (const W*)J.x.p + bx;
+  const double* yd = (const double*)J.y.p + by;
+  const W* yw = (const W*)J.y.p + by;
   auto fetch = [&](int ch, double (&xv)[NQ], double (&yv)[NQ]) {
     const int row = ch * XR + lr;
     const bool rin = row < rows;
@@ -708,23 +725,21 @@ __global__ __launch_bounds__(XTHR) void kw_xgram(Dev d, int axis, int sd0, XJobs
       const int ci = cx0 + cl, cj = cy0 + cl;
       const bool xin = ci < nx, yin = cj < ny;
       double v = 0.0, u = 0.0;
+      // offsets within a subdomain's slab fit in 32 bits: the loads take the
+      // slab base as a scalar and a 32-bit offset per lane
       if (xin && wt != 0.0) {
-        if (J.x.vec) v = ((const double*)J.x.p)[bx + px];
-        else if (J.x.is64) v = ((const double*)J.x.p)[bx + (int64_t)ci * J.x.ld + px];
-        else v = (double)((const W*)J.x.p)[bx + (int64_t)ci * J.x.ld + px];
+        const unsigned ox = J.x.vec ? (unsigned)px : (unsigned)(ci * J.x.ld + px);
+        v = (J.x.vec || J.x.is64) ? xd[ox] : (double)xw[ox];
         v = v * sx * wt;
       }
       if (yin && rin) {
-        const int64_t o = J.y.vec ? by + py : by + (int64_t)cj * J.y.ld + py;
+        const unsigned oy = J.y.vec ? (unsigned)py : (unsigned)(cj * J.y.ld + py);
         const bool w64 = J.y.vec || J.y.is64;
-        u = w64 ? ((const double*)J.y.p)[o] : (double)((const W*)J.y.p)[o];
+        u = w64 ? yd[oy] : (double)yw[oy];
         u *= sy;
         if (J.shift) {
           double u1 = 0.0;
-          if (hs) {
-            const int64_t o1 = o + e;
-            u1 = (w64 ? ((const double*)J.y.p)[o1] : (double)((const W*)J.y.p)[o1]) * sy1;
-          }
+          if (hs) u1 = (w64 ? yd[oy + e] : (double)yw[oy + e]) * sy1;
           u = u1 - u;
         }
       }
@@ -740,51 +755,64 @@ __global__ __launch_bounds__(XTHR) void kw_xgram(Dev d, int axis, int sd0, XJobs
       ys[cl * XLD + lr] = yv[q];
     }
   };
-  // wavefront w accumulates the output rows 16 w .. 16 w + 15 of the block
-  dbl4 acc[4];
-  zero_acc<4>(acc);
+  // wavefront w accumulates the output rows 16 w .. 16 w + 15 of the block,
+  // in NCJ column blocks of 16 (only as many as the block has live columns);
+  // a wavefront whose rows are all beyond the live ones only stages data
   const int nch = wdiv(rows, XR);
-  double xv[NQ], yv[NQ];
-  int ch = blockIdx.x;
-  if (ch < nch) fetch(ch, xv, yv);
-  for (; ch < nch; ch += gridDim.x) {
-    __syncthreads();
-    stash(xv, yv);
-    __syncthreads();
-    if (ch + (int)gridDim.x < nch) fetch(ch + gridDim.x, xv, yv);  // the next chunk's loads overlap the MFMAs
-    const double* xa = xs + (16 * wave + l16) * XLD + kq;
-    const double* yb = ys + l16 * XLD + kq;
-    // each chunk is summed on its own and then added to the running total,
-    // so no chain of roundings runs over more than one chunk (the angular
-    // sums cancel strongly near sources)
-    dbl4 cacc[4];
-    zero_acc<4>(cacc);
+  const bool wlive = cx0 + 16 * wave < nx;
+  auto run = [&](auto ncj_c) {
+    constexpr int NCJ = decltype(ncj_c)::value;
+    dbl4 acc[NCJ];
+    zero_acc<NCJ>(acc);
+    for (int ch = blockIdx.x; ch < nch; ch += gridDim.x) {
+      {
+        double xv[NQ], yv[NQ];
+        fetch(ch, xv, yv);
+        __syncthreads();
+        stash(xv, yv);
+      }
+      __syncthreads();
+      if (wlive) {
+        const double* xa = xs + (16 * wave + l16) * XLD + kq;
+        const double* yb = ys + l16 * XLD + kq;
+        // each chunk is summed on its own and then added to the running
+        // total, so no chain of roundings runs over more than one chunk (the
+        // angular sums cancel strongly near sources)
+        dbl4 cacc[NCJ];
+        zero_acc<NCJ>(cacc);
 #pragma unroll
-    for (int ks = 0; ks < XR / 4; ++ks) {
-      const double av = xa[4 * ks];
+        for (int ks = 0; ks < XR / 4; ++ks) {
+          const double av = xa[4 * ks];
 #pragma unroll
-      for (int cj = 0; cj < 4; ++cj) cacc[cj] = mfma64(av, yb[16 * cj * XLD + 4 * ks], cacc[cj]);
-    }
+          for (int cj = 0; cj < NCJ; ++cj) cacc[cj] = mfma64(av, yb[16 * cj * XLD + 4 * ks], cacc[cj]);
+        }
 #pragma unroll
-    for (int cj = 0; cj < 4; ++cj) acc[cj] += cacc[cj];
-  }
-  double* out = gpart_of(d, s) + (int64_t)blockIdx.x * d.gpTile + J.out_off;
-  const int ld = J.out_ld > 0 ? J.out_ld : nx;
-#pragma unroll
-  for (int cj = 0; cj < 4; ++cj)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int i = 64 * a + 16 * wave + 4 * v + kq, j = 64 * b + 16 * cj + l16;
-      if (i >= nx || j >= ny) continue;
-      const double val = J.scale * acc[cj][v];
-      if (J.sym) {
-        if (a == b && i > j) continue;
-        out[i + (int64_t)j * ld] = val;
-        out[j + (int64_t)i * ld] = val;
-      } else {
-        out[i + (int64_t)j * ld] = val;
+        for (int cj = 0; cj < NCJ; ++cj) acc[cj] += cacc[cj];
       }
     }
+    if (!wlive) return;
+    double* out = gpart_of(d, s) + (int64_t)blockIdx.x * d.gpTile + J.out_off;
+    const int ld = J.out_ld > 0 ? J.out_ld : nx;
+#pragma unroll
+    for (int cj = 0; cj < NCJ; ++cj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 64 * a + 16 * wave + 4 * v + kq, j = 64 * b + 16 * cj + l16;
+        if (i >= nx || j >= ny) continue;
+        const double val = J.scale * acc[cj][v];
+        if (J.sym) {
+          if (a == b && i > j) continue;
+          out[i + (int64_t)j * ld] = val;
+          out[j + (int64_t)i * ld] = val;
+        } else {
+          out[i + (int64_t)j * ld] = val;
+        }
+      }
+  };
+  const int ncj = ny - cy0;
+  if (ncj <= 16) run(wint<1>{});
+  else if (ncj <= 32) run(wint<2>{});
+  else run(wint<4>{});
 }
 
 // ============================================================================
