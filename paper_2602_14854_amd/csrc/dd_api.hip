@@ -779,10 +779,11 @@ dd::XJob xjob(const dd::XSrc& x, const dd::XSrc& y, int capx, int capy, int wmod
 // Gram of X into the partial sums; wide: read by a wide kernel (d.xpN /
 // d.xpM partials), else by a narrow one (d.nwgN / d.nwgM)
 void w_gram(dd_dlra_handle h, int kind, int axis, const void* X, bool is64, int64_t sd, int rows, int ndim, int cap,
-            bool cells, bool wide) {
+            bool cells, bool wide, int skip_off = -1) {
   const Dev& d = h->d;
   dd::XJobs jobs;
   jobs.n = 1;
+  jobs.skip_off = skip_off;
   const dd::XSrc x = xsrc(X, sd, rows, ndim, is64);
   jobs.j[0] = xjob(x, x, cap, cap, 0, true, 0, -1);
   const int np = wide ? (cells ? d.xpN : d.xpM) : (cells ? d.nwgN : d.nwgM);
@@ -791,23 +792,29 @@ void w_gram(dd_dlra_handle h, int kind, int axis, const void* X, bool is64, int6
 
 // passes of Cholesky QR of X (rows x n, n = dim ndim <= 128) for the wide
 // plan, out of place, alternating between X and Y; acc: accumulate the R
-// factors in the small workspace.  Returns the buffer holding Q.
+// factors in the small workspace; near0: the first pass may take the
+// near-identity factor too (an input orthonormal in exact arithmetic).  The
+// last pass is skipped, per subdomain, after a next-to-last one that took
+// the near-identity factor (its product then copies).  Returns the buffer
+// holding Q.
 void* w_chol_qr(dd_dlra_handle h, int axis, int ndim, void* X, void* Y, int64_t sd, int rows, bool cells, int passes,
-                bool acc, int gram_kind, int gemm_kind) {
+                bool acc, int gram_kind, int gemm_kind, bool near0 = false) {
   const Dev& d = h->d;
   const int ngp = cells ? d.xpN : d.xpM;
   const int cap = ndim == dd::DIM_T ? d.T : d.R;
   void* cur = X;
   void* oth = Y;
   for (int pass = 0; pass < passes; ++pass) {
-    w_gram(h, gram_kind, axis, cur, false, sd, rows, ndim, cap, cells, true);
+    const int skip_mode = passes < 2 ? 0 : (pass == passes - 2 ? 1 : (pass == passes - 1 ? 2 : 0));
+    const int skip_off = skip_mode == 2 ? d.oSkip : -1;
+    w_gram(h, gram_kind, axis, cur, false, sd, rows, ndim, cap, cells, true, skip_off);
     phase(h, K_W_CHOL, [&](int s0, int ns) {
       dd::launch_w_chol(d, axis, s0, ns, ndim, rows, ngp, acc ? (pass == 0 ? 1 : 2) : 0, 1.0, d.oRinv, d.oRacc, d.T,
-                        pass > 0, h->stream);
+                        pass > 0 || near0, h->stream, skip_mode);
     });
     phase(h, gemm_kind, [&](int s0, int ns) {
       dd::launch_w_gemm(d, axis, s0, ns, cur, false, sd, rows, ndim, ndim, d.oRinv, d.T, oth, false, sd, nullptr,
-                        d.oFill, cells, true, h->stream);
+                        d.oFill, cells, true, h->stream, false, skip_off);
     });
     std::swap(cur, oth);
   }
@@ -829,7 +836,7 @@ void enqueue_advection_wide(dd_dlra_handle h, int axis, int upto = 0) {
     dd::launch_w_gemm(d, axis, s0, ns, d.A, true, sdMA, d.M, dd::DIM_M0, dd::DIM_T, d.oCoef, d.MA, d.Qh, false, sdMT,
                       nullptr, d.oFill, false, true, st);
   });
-  void* q = w_chol_qr(h, axis, dd::DIM_T, d.Qh, d.Z, sdMT, d.M, false, 2, false, K_W_GRAM_VHAT, K_GEMM_QR_VHAT);
+  void* q = w_chol_qr(h, axis, dd::DIM_T, d.Qh, d.Z, sdMT, d.M, false, 2, false, K_W_GRAM_VHAT, K_GEMM_QR_VHAT, true);
   (void)q;  // two passes: V-hat is back in Qh
   if (upto == DD_PROBE_VHAT) return;
   // angular Galerkin matrices (partial layout of the narrow plan)

@@ -43,11 +43,13 @@ constexpr int XJOBS_MAX = 8;
 struct XJobs {
   XJob j[XJOBS_MAX];
   int n;
+  int skip_off = -1;  // >= 0: a subdomain whose small-workspace slot here is set writes nothing
 };
 
 void launch_w_gemm(const Dev& d, int axis, int sd0, int nsd, const void* X, bool x64, int64_t xsd, int rows,
                    int kdim, int ndim, int boff, int bld, void* Y, bool y64, int64_t ysd, const double* rowscale,
-                   int fill_off, bool rows_are_cells, bool exact, hipStream_t st, bool set_rank = false);
+                   int fill_off, bool rows_are_cells, bool exact, hipStream_t st, bool set_rank = false,
+                   int skip_off = -1);
 void launch_w_aug_form(const Dev& d, int axis, int sd0, int nsd, hipStream_t st);
 void launch_w_kstep(const Dev& d, int axis, int sd0, int nsd, hipStream_t st);
 void launch_w_lstep(const Dev& d, int axis, int sd0, int nsd, hipStream_t st);
@@ -55,8 +57,11 @@ void launch_w_coll_kstep(const Dev& d, int sd0, int nsd, hipStream_t st);
 void launch_w_xgram(const Dev& d, int axis, int sd0, int nsd, XJobs jobs, bool cells, int np, hipStream_t st);
 // near: a Gram within 1e-3 of the identity takes the symmetric factor from
 // the binomial series instead of the Cholesky factorisation
+// skip_mode 1 records in the skip slot whether the pass took the
+// near-identity factor (its output is then orthonormal to rounding); a pass
+// with skip_mode 2 does nothing for a subdomain whose slot is set
 void launch_w_chol(const Dev& d, int axis, int sd0, int nsd, int ndim, int rows, int ngp, int acc_mode,
-                   double bscale, int oRinv, int oRacc, int ld, bool near, hipStream_t st);
+                   double bscale, int oRinv, int oRacc, int ld, bool near, hipStream_t st, int skip_mode = 0);
 void launch_w_aug_svd(const Dev& d, int axis, int sd0, int nsd, hipStream_t st);
 void launch_w_adv_prep(const Dev& d, int axis, int sd0, int nsd, hipStream_t st);
 void launch_w_adv_sstep(const Dev& d, int axis, int sd0, int nsd, hipStream_t st);

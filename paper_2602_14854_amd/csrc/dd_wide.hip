@@ -66,7 +66,7 @@ __device__ __forceinline__ void stage_frags(typename Prec<P>::F* frag, const dou
 template <class SI, class SO, int P, int NCB>
 __global__ __launch_bounds__(WTHR) void kw_gemm(Dev d, int axis, int sd0, const void* X, int64_t xsd, int rows,
                                                 int kdim, int ndim, int boff, int bld, void* Y, int64_t ysd,
-                                                const double* rowscale, int fill_off, int set_rank) {
+                                                const double* rowscale, int fill_off, int set_rank, int skip_off) {
   using F = typename Prec<P>::F;
   using Acc = typename Prec<P>::Acc;
   const int s = sd0 + blockIdx.y;
@@ -75,6 +75,17 @@ __global__ __launch_bounds__(WTHR) void kw_gemm(Dev d, int axis, int sd0, const 
   const int c0 = blockIdx.z * 16 * NCB;
   if (set_rank && blockIdx.x == 0 && blockIdx.z == 0 && threadIdx.x == 0) d.rank[s] = d.rnew[s];
   if (c0 >= n || k <= 0) return;
+  if (skip_off >= 0 && small_of(d, s)[skip_off] != 0.0) {
+    // a skipped Cholesky-QR pass (B = I): Y = X on this block of columns
+    const SI* Xc = (const SI*)X + (int64_t)s * xsd;
+    SO* Yc = (SO*)Y + (int64_t)s * ysd;
+    const int64_t tot = (int64_t)min(16 * NCB, n - c0) * rows;
+    for (int64_t idx = (int64_t)blockIdx.x * WTHR + threadIdx.x; idx < tot; idx += (int64_t)gridDim.x * WTHR) {
+      const int64_t o = (int64_t)c0 * rows + idx;
+      Yc[o] = (SO)Xc[o];
+    }
+    return;
+  }
   const int ng = wdiv(k, 64);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int l16 = lane & 15, kq = lane >> 4;
@@ -103,7 +114,7 @@ __global__ __launch_bounds__(WTHR) void kw_gemm(Dev d, int axis, int sd0, const 
       for (int u = 0; u < NS; ++u) {
         const int kc = 64 * g_ + sub_col<P>(u, kq);
         const bool in = row_ < rows && kc < k;
-        const SI v = Xs[(int64_t)(in ? kc : 0) * rows + rc];
+        const SI v = Xs[(unsigned)((in ? kc : 0) * rows + rc)];  // offsets within a slab fit in 32 bits
         xn[u] = in ? (F)v : (F)0;
       }
     };
@@ -653,6 +664,7 @@ __device__ __forceinline__ double src_load(const Dev& d, int s, int axis, const 
 template <class W>
 __global__ __launch_bounds__(XTHR, 4) void kw_xgram(Dev d, int axis, int sd0, XJobs jobs) {
   const int s = sd0 + blockIdx.y;
+  if (jobs.skip_off >= 0 && small_of(d, s)[jobs.skip_off] != 0.0) return;
   int jb = 0;
 #pragma unroll
   for (int q = 1; q < XJOBS_MAX; ++q)
@@ -844,27 +856,54 @@ __device__ __forceinline__ double s_max(double v, double* red) {
   return r;
 }
 
+// acc[u] = sum over the ngp partials, added in order w = 0, 1, ..., of
+// gp[w tile + src[u]], for UI entries at once: each group of four partials
+// issues all 4 UI loads before the first addition, so one workgroup keeps
+// enough loads in flight to cover the memory latency
+template <int UI>
+__device__ __forceinline__ void sum_partials_multi(const double* gp, int64_t tile, int ngp, const int64_t (&src)[UI],
+                                                   double (&acc)[UI]) {
+#pragma unroll
+  for (int u = 0; u < UI; ++u) acc[u] = 0.0;
+  int w = 0;
+  for (; w + 4 <= ngp; w += 4) {
+    double v[4][UI];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int u = 0; u < UI; ++u) v[a][u] = gp[(int64_t)(w + a) * tile + src[u]];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int u = 0; u < UI; ++u) acc[u] += v[a][u];
+  }
+  for (; w < ngp; ++w)
+#pragma unroll
+    for (int u = 0; u < UI; ++u) acc[u] += gp[(int64_t)w * tile + src[u]];
+}
+
 // dst (rows x cols, ldd) = scale * sum over ngp partials of the block at off
 // (leading dimension ldp), partials added in a fixed order
 __device__ void s_sum_partials(const Dev& d, int s, int ngp, int off, int ldp, int rows, int cols, double* dst,
                                int ldd, double scale) {
+  constexpr int UI = 4;
   const double* gp = gpart_of(d, s);
   const int total = rows * cols;
-  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-    const int i = idx % rows, j = idx / rows;
-    const int64_t src = off + i + (int64_t)j * ldp;
-    double acc = 0.0;
-    int w = 0;
-    for (; w + 4 <= ngp; w += 4) {
-      const double v0 = gp[(int64_t)w * d.gpTile + src], v1 = gp[(int64_t)(w + 1) * d.gpTile + src];
-      const double v2 = gp[(int64_t)(w + 2) * d.gpTile + src], v3 = gp[(int64_t)(w + 3) * d.gpTile + src];
-      acc += v0;
-      acc += v1;
-      acc += v2;
-      acc += v3;
+  for (int base = threadIdx.x; base < total; base += UI * blockDim.x) {
+    int64_t src[UI];
+#pragma unroll
+    for (int u = 0; u < UI; ++u) {
+      const int idx = base + u * blockDim.x;
+      const int i = idx % rows, j = idx / rows;
+      src[u] = idx < total ? off + i + (int64_t)j * ldp : off;
     }
-    for (; w < ngp; ++w) acc += gp[(int64_t)w * d.gpTile + src];
-    dst[i + (int64_t)j * ldd] = scale * acc;
+    double acc[UI];
+    sum_partials_multi<UI>(gp, d.gpTile, ngp, src, acc);
+#pragma unroll
+    for (int u = 0; u < UI; ++u) {
+      const int idx = base + u * blockDim.x;
+      if (idx < total) dst[idx % rows + (int64_t)(idx / rows) * ldd] = scale * acc[u];
+    }
   }
 }
 
@@ -1571,7 +1610,7 @@ struct SmallScratch {
 //   Racc slot: R (acc_mode 1) or R Racc (acc_mode 2), rows of dependent
 //              columns zeroed.
 __global__ __launch_bounds__(STHR) void sw_chol(Dev d, int axis, int sd0, int ndim, int rows, int ngp, int acc_mode,
-                                               double bscale, int oRinv, int oRacc, int ld, int near) {
+                                               double bscale, int oRinv, int oRacc, int ld, int near, int skip_mode) {
   const int s = sd0 + blockIdx.x;
   const int n = dim_of(d, s, axis, ndim);
   double* sm = small_of(d, s);
@@ -1580,6 +1619,10 @@ __global__ __launch_bounds__(STHR) void sw_chol(Dev d, int axis, int sd0, int nd
   double* d0 = sc.v0;
   int* dep = sc.i0;
   if (n <= 0) return;
+  // a pass after one that took the near-identity factor is skipped: that
+  // output is orthonormal to rounding, R = I (Racc unchanged), and the Gram
+  // and the product of this pass are skipped with it
+  if (skip_mode == 2 && sm[d.oSkip] != 0.0) return;
   if (near) {
     // A Gram within 1e-3 (Frobenius) of the identity (a pass over an input
     // that is already orthonormal up to rounding) takes the symmetric factor
@@ -1644,9 +1687,11 @@ __global__ __launch_bounds__(STHR) void sw_chol(Dev d, int axis, int sd0, int nd
           sm[oRacc + i + j * ld] = Wt[i + j * T];
         }
       }
+      if (skip_mode == 1 && threadIdx.x == 0) sm[d.oSkip] = 1.0;
       return;
     }
   }
+  if (skip_mode == 1 && threadIdx.x == 0) sm[d.oSkip] = 0.0;
   bool shifted = false;
   for (int attempt = 0; attempt < 2; ++attempt) {
     s_sum_partials(d, s, ngp, 0, n, n, n, L, WLD, 1.0);
@@ -1721,12 +1766,22 @@ __device__ __forceinline__ void aug_svd_body(const Dev& d, int s, int axis, int 
   {
     const double* gp = gpart_of(d, s);
     const int ngp = d.xpM;
+    constexpr int UI = 2;
     for (int j = wave; j < m0; j += JNW)
-      for (int i = j + lane; i < m0; i += 64) {
-        const int64_t src = i + (int64_t)j * m0;
-        double acc = 0.0;
-        for (int w = 0; w < ngp; ++w) acc += gp[(int64_t)w * d.gpTile + src];
-        Gp[i * (i + 1) / 2 + j] = acc;
+      for (int i0 = j + lane; i0 < m0; i0 += 64 * UI) {
+        int64_t src[UI];
+#pragma unroll
+        for (int u = 0; u < UI; ++u) {
+          const int i = i0 + 64 * u;
+          src[u] = i < m0 ? i + (int64_t)j * m0 : 0;
+        }
+        double acc[UI];
+        sum_partials_multi<UI>(gp, d.gpTile, ngp, src, acc);
+#pragma unroll
+        for (int u = 0; u < UI; ++u) {
+          const int i = i0 + 64 * u;
+          if (i < m0) Gp[i * (i + 1) / 2 + j] = acc[u];
+        }
       }
     __syncthreads();
     for (int i = threadIdx.x; i < m0; i += JTHR) {
@@ -2353,7 +2408,7 @@ static_assert(sizeof(double) * (size_t)WLD * WCAP_T + sizeof(SmallScratch) <= LD
 
 void launch_w_gemm(const Dev& d, int axis, int sd0, int nsd, const void* X, bool x64, int64_t xsd, int rows,
                    int kdim, int ndim, int boff, int bld, void* Y, bool y64, int64_t ysd, const double* rowscale,
-                   int fill_off, bool rows_are_cells, bool exact, hipStream_t st, bool set_rank) {
+                   int fill_off, bool rows_are_cells, bool exact, hipStream_t st, bool set_rank, int skip_off) {
   const int nwg = rows_are_cells ? d.nwgN : d.nwgM;
   constexpr int NCB = 4;
   const int nz = wdiv(w_dim_cap(d, ndim), 16 * NCB);
@@ -2364,7 +2419,7 @@ void launch_w_gemm(const Dev& d, int axis, int sd0, int nsd, const void* X, bool
     constexpr int P = decltype(pc)::value;
     const size_t lds = sizeof(typename Prec<P>::F) * (size_t)ng * 16 * NCB * 64;
     hipLaunchKernelGGL((kw_gemm<SI, SO, P, NCB>), dim3(nwg, nsd, nz), dim3(WTHR), lds, st, d, axis, sd0, X, xsd,
-                       rows, kdim, ndim, boff, bld, Y, ysd, rowscale, fill_off, set_rank ? 1 : 0);
+                       rows, kdim, ndim, boff, bld, Y, ysd, rowscale, fill_off, set_rank ? 1 : 0, skip_off);
   };
   w_with_prec(d.prec, exact, [&](auto ts, auto pc) {
     using W = typename decltype(ts)::type;
@@ -2443,10 +2498,10 @@ void launch_w_xgram(const Dev& d, int axis, int sd0, int nsd, XJobs jobs, bool c
 }
 
 void launch_w_chol(const Dev& d, int axis, int sd0, int nsd, int ndim, int rows, int ngp, int acc_mode,
-                   double bscale, int oRinv, int oRacc, int ld, bool near, hipStream_t st) {
+                   double bscale, int oRinv, int oRacc, int ld, bool near, hipStream_t st, int skip_mode) {
   const size_t lds = sizeof(double) * (size_t)WLD * WCAP_T;
   hipLaunchKernelGGL(sw_chol, dim3(nsd), dim3(STHR), lds, st, d, axis, sd0, ndim, rows, ngp, acc_mode, bscale,
-                     oRinv, oRacc, ld, near ? 1 : 0);
+                     oRinv, oRacc, ld, near ? 1 : 0, skip_mode);
 }
 
 void launch_w_aug_svd(const Dev& d, int axis, int sd0, int nsd, hipStream_t st) {
