@@ -311,6 +311,10 @@ void set_wide_partials(Dev& d) {
   const int capN = std::max(1, (int)(d.gpStride / d.gpTile));
   d.xpN = std::min(2 * d.nwgN, capN);
   d.xpM = std::min(2 * d.nwgM, capN);
+  // the Galerkin job sets write several blocks per subdomain and their
+  // partials are summed by one workgroup: at most 8 row splits
+  d.xgN = std::min(d.xpN, 8);
+  d.xgM = std::min(d.xpM, 8);
 }
 
 
@@ -850,7 +854,7 @@ void enqueue_advection_wide(dd_dlra_handle h, int axis, int upto = 0) {
     jobs.j[3] = xjob(qh, qh, T, T, 3, true, R * T + 2 * T * T, -1);
     jobs.j[4] = xjob(xsrc(d.V, sdMR, d.M, dd::DIM_R, true, -1, true), qh, R, T, 2, false, R * T + 3 * T * T, R);
     jobs.j[5] = xjob(xsrc(d.V, sdMR, d.M, dd::DIM_R, true, +1, true), qh, R, T, 3, false, 2 * R * T + 3 * T * T, R);
-    phase(h, K_W_ANG, [&](int s0, int ns) { dd::launch_w_xgram(d, axis, s0, ns, jobs, false, d.xpM, st); });
+    phase(h, K_W_ANG, [&](int s0, int ns) { dd::launch_w_xgram(d, axis, s0, ns, jobs, false, d.xgM, st); });
   }
   phase(h, K_ADV_PREP, [&](int s0, int ns) { dd::launch_w_adv_prep(d, axis, s0, ns, st); });
   // Algorithm 1/2 steps 1-2: K-step, QR (three passes: K1 -> K2 -> K1 -> K2)
@@ -889,7 +893,7 @@ void enqueue_advection_wide(dd_dlra_handle h, int axis, int upto = 0) {
     jobs.j[2] = xjob(qhf, xsrc(d.U, sdNR, d.N, dd::DIM_R, true, 0, false, 2), T, R, 0, false, oX + T * R, T);
     jobs.j[3] = xjob(ql, xsrc(d.U, sdNR, d.N, dd::DIM_R, true, -1, false, 2), T, R, 0, false, oX + 2 * T * R, T);
     jobs.j[4] = xjob(qhf, xsrc(d.U, sdNR, d.N, dd::DIM_R, true, +1, false, 1), T, R, 0, false, oX + 3 * T * R, T);
-    phase(h, K_W_SPATIAL, [&](int s0, int ns) { dd::launch_w_xgram(d, axis, s0, ns, jobs, true, d.xpN, st); });
+    phase(h, K_W_SPATIAL, [&](int s0, int ns) { dd::launch_w_xgram(d, axis, s0, ns, jobs, true, d.xgN, st); });
   }
   phase(h, K_ADV_SSTEP, [&](int s0, int ns) { dd::launch_w_adv_sstep(d, axis, s0, ns, st); });
   if (upto == DD_PROBE_S2) return;

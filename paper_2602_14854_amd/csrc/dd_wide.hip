@@ -1984,7 +1984,7 @@ __device__ void adv_prep_body(const Dev& d, int s, int axis, int t, double* lds,
   double* sm = small_of(d, s);
   double* Cl = lds;  // t x t, ld WLD
   const int pT = 0, pC = R * T, pEp = pC + T * T, pEn = pEp + T * T, pOlo = pEn + T * T, pOhi = pOlo + R * T;
-  const int ngp = d.xpM;
+  const int ngp = d.xgM;
   s_sum_partials(d, s, ngp, pT, R, r, t, sm + d.oTm, R, 1.0);
   s_sum_partials(d, s, ngp, pEp, t, t, t, sm + d.oEp, T, 1.0);
   s_sum_partials(d, s, ngp, pEn, t, t, t, sm + d.oEn, T, 1.0);
@@ -2111,7 +2111,7 @@ __global__ __launch_bounds__(STHR) void sw_adv_sstep(Dev d, int axis, int sd0) {
   double* Xhi = sm + d.oW2;
   double* Xln = sm + d.oW3;
   double* Xhn = sm + d.oW4;
-  const int oX = 2 * T * T, ngp = d.xpN;
+  const int oX = 2 * T * T, ngp = d.xgN;
   s_sum_partials(d, s, ngp, 0, t, t, t, Gp, T, ih);
   s_sum_partials(d, s, ngp, oX, T, t, r, Xlo, T, 1.0);
   s_sum_partials(d, s, ngp, oX + T * R, T, t, r, Xhi, T, 1.0);
