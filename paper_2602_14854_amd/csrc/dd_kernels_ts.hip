@@ -144,7 +144,6 @@ __global__ __launch_bounds__(NTHR) void k_gemm(Dev d, int axis, int sd0, const v
   using F = typename Prec<P>::F;
   using Acc = typename Prec<P>::Acc;
   constexpr int LD = strip_ld<NCB>();
-  constexpr int NB = NCB * (NCB + 1) / 2;
   const int s = sd0 + blockIdx.y;
   const int k = dim_of(d, s, axis, kdim);
   const int n = dim_of(d, s, axis, ndim);
@@ -168,58 +167,70 @@ __global__ __launch_bounds__(NTHR) void k_gemm(Dev d, int axis, int sd0, const v
 
   const SI* Xsd = (const SI*)X + (int64_t)s * xsd;
   S* Ysd = (S*)Y + (int64_t)s * ysd;
-  dbl4 g[NB];
-  zero_acc<NB>(g);
   const int nst = ceil_div(rows, 16);
   const int stride = gridDim.x * NW;
-  F xn[KS];
-  auto load = [&](int st_) {
-    const int row_ = st_ * 16 + l16;
-    const int rc = row_ < rows ? row_ : rows - 1;
+  // NC output column blocks and KSR sub-steps are issued: a subdomain whose
+  // operands have at most one instruction's live columns and 16 output
+  // columns takes the short instance
+  auto run = [&](auto nc_c, auto ks_c) {
+    constexpr int NC = decltype(nc_c)::value, KSR = decltype(ks_c)::value;
+    constexpr int NBR = NC * (NC + 1) / 2;
+    dbl4 g[NBR];
+    zero_acc<NBR>(g);
+    F xn[KSR];
+    auto load = [&](int st_) {
+      const int row_ = st_ * 16 + l16;
+      const int rc = row_ < rows ? row_ : rows - 1;
 #pragma unroll
-    for (int u = 0; u < KS; ++u) {
-      const int kc = sub_col<P>(u, kq);
-      const bool in = row_ < rows && kc < k;
-      const SI v = Xsd[(int64_t)(in ? kc : 0) * rows + rc];
-      xn[u] = in ? (F)v : (F)0;
-    }
-  };
-  int st = blockIdx.x * NW + wave;
-  if (st < nst) load(st);
-  for (; st < nst; st += stride) {
-    const int row = st * 16 + l16;
-    const bool rin = row < rows;
-    F xv[KS];
+      for (int u = 0; u < KSR; ++u) {
+        const int kc = sub_col<P>(u, kq);
+        const bool in = row_ < rows && kc < k;
+        const SI v = Xsd[(int64_t)(in ? kc : 0) * rows + rc];
+        xn[u] = in ? (F)v : (F)0;
+      }
+    };
+    int st = blockIdx.x * NW + wave;
+    if (st < nst) load(st);
+    for (; st < nst; st += stride) {
+      const int row = st * 16 + l16;
+      const bool rin = row < rows;
+      F xv[KSR];
 #pragma unroll
-    for (int u = 0; u < KS; ++u) xv[u] = xn[u];
-    if (st + stride < nst) load(st + stride);
-    Acc acc[NCB];
-    zero_prod<P>(acc, NCB);
-    prod_acc<P, NCB, KS>(acc, Bf, xv);
-    const double rs = (rowscale != nullptr && rin) ? rowscale[row] : 1.0;
+      for (int u = 0; u < KSR; ++u) xv[u] = xn[u];
+      if (st + stride < nst) load(st + stride);
+      Acc acc[NC];
+      zero_prod<P>(acc, NC);
+      prod_acc<P, NC, KSR, NCB>(acc, Bf, xv);
+      const double rs = (rowscale != nullptr && rin) ? rowscale[row] : 1.0;
 #pragma unroll
-    for (int cb = 0; cb < NCB; ++cb) {
+      for (int cb = 0; cb < NC; ++cb) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int j = out_col<P>(cb, v, kq);
-        double val = (double)acc[cb][v] * rs;
-        if (fillm[j]) val = hash_unit(((uint64_t)s << 40) ^ ((uint64_t)j << 24) ^ (uint64_t)row);
-        if (!rin) val = 0.0;
-        const S sv = (S)val;
-        if (rin && j < n) Ysd[(int64_t)j * rows + row] = sv;
-        if (gram) Ys[l16 * LD + j] = (double)sv;
+        for (int v = 0; v < 4; ++v) {
+          const int j = out_col<P>(cb, v, kq);
+          double val = (double)acc[cb][v] * rs;
+          if (fillm[j]) val = hash_unit(((uint64_t)s << 40) ^ ((uint64_t)j << 24) ^ (uint64_t)row);
+          if (!rin) val = 0.0;
+          const S sv = (S)val;
+          if (rin && j < n) Ysd[(int64_t)j * rows + row] = sv;
+          if (gram) Ys[l16 * LD + j] = (double)sv;
+        }
+      }
+      if (gram) {
+        wave_sync();
+        strip_gram<NC, LD>(g, Ys);
+        wave_sync();
       }
     }
     if (gram) {
-      wave_sync();
-      strip_gram<NCB, LD>(g, Ys);
-      wave_sync();
+      wg_reduce_acc<NBR>(g, lds);
+      if (wave == 0) store_gram<NC>(g, gpart_of(d, s) + (int64_t)blockIdx.x * d.gpTile, n, 1.0);
     }
-  }
-  if (gram) {
-    wg_reduce_acc<NB>(g, lds);
-    if (wave == 0) store_gram<NCB>(g, gpart_of(d, s) + (int64_t)blockIdx.x * d.gpTile, n, 1.0);
-  }
+  };
+  constexpr int KS1 = P == 2 ? 8 : 4;  // one instruction's sub-steps
+  if (NCB > 1 && KS > KS1 && live_sub<P>(k) <= KS1 && n <= 16)
+    run(std::integral_constant<int, 1>{}, std::integral_constant<int, (KS > KS1 ? KS1 : KS)>{});
+  else
+    run(std::integral_constant<int, NCB>{}, std::integral_constant<int, KS>{});
 }
 
 // ----------------------------------------------------------------------------
