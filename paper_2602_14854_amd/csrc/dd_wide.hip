@@ -188,30 +188,37 @@ __global__ __launch_bounds__(WTHR) void kw_aug_form(Dev d, int axis, int sd0) {
   double* As = d.A + (int64_t)s * M * d.MA + (int64_t)off * M;
   const int nst = wdiv(M, 16);
   const int stride = gridDim.x * WNW;
-  for (int st = blockIdx.x * WNW + wave; st < nst; st += stride) {
-    const int q = st * 16 + l16;
-    const bool rin = q < M;
-    const int qc = rin ? q : M - 1;
-    double xv[16];
+  // a source block of rank <= 16 takes the short instance (one column
+  // block, four sub-steps)
+  auto run = [&](auto ns_c, auto nc_c) {
+    constexpr int NS = decltype(ns_c)::value, NC = decltype(nc_c)::value;
+    for (int st = blockIdx.x * WNW + wave; st < nst; st += stride) {
+      const int q = st * 16 + l16;
+      const bool rin = q < M;
+      const int qc = rin ? q : M - 1;
+      double xv[NS];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int kc = sub_col<0>(u, kq);
-      const bool in = rin && kc < rb;
-      const double v = Vn[(int64_t)(in ? kc : 0) * M + qc];
-      xv[u] = in ? v : 0.0;
-    }
-    dbl4 acc[NCB];
-    zero_acc<NCB>(acc);
-    prod_acc<0, NCB, 16>(acc, frag, xv);
-    const double swq = d.sw[qc];
-#pragma unroll
-    for (int cb = 0; cb < NCB; ++cb)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int j = out_col<0>(cb, v, kq);
-        if (rin && j < rb) As[(int64_t)j * M + q] = acc[cb][v] * swq;
+      for (int u = 0; u < NS; ++u) {
+        const int kc = sub_col<0>(u, kq);
+        const bool in = rin && kc < rb;
+        const double v = Vn[(int64_t)(in ? kc : 0) * M + qc];
+        xv[u] = in ? v : 0.0;
       }
-  }
+      dbl4 acc[NC];
+      zero_acc<NC>(acc);
+      prod_acc<0, NC, NS, NCB>(acc, frag, xv);
+      const double swq = d.sw[qc];
+#pragma unroll
+      for (int cb = 0; cb < NC; ++cb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int j = out_col<0>(cb, v, kq);
+          if (rin && j < rb) As[(int64_t)j * M + q] = acc[cb][v] * swq;
+        }
+    }
+  };
+  if (rb <= 16) run(wint<4>{}, wint<1>{});
+  else run(wint<16>{}, wint<NCB>{});
 }
 
 // K-step of an advection stage (eq. advx_evolK / advy_evolK, Appendix A),
@@ -262,80 +269,90 @@ __global__ __launch_bounds__(WTHR) void kw_kstep(Dev d, int axis, int sd0) {
   const int na = axis == 0 ? d.lnx : d.lny;
   const int nst = wdiv(N, 16);
   const int stride = gridDim.x * WNW;
-  for (int st = blockIdx.x * WNW + wave; st < nst; st += stride) {
-    const int p = st * 16 + l16;
-    const bool rin = p < N;
-    const int pc = rin ? p : N - 1;
-    const int ia = axis == 0 ? pc % d.lnx : pc / d.lnx;
-    const int f = axis == 0 ? pc / d.lnx : pc % d.lnx;
-    const bool hm = rin && ia > 0, hp = rin && ia < na - 1;
-    const bool flo = rin && ia == 0, fhi = rin && ia == na - 1;
-    const int pm = hm ? pc - e : pc, pp = hp ? pc + e : pc;
-    Acc acc[NCB];
-    zero_prod<P>(acc, NCB);
-    for (int kg = 0; kg < kgr; ++kg) {
-      F u0[KG], um[KG], up[KG];
+  // KGR sub-steps of each 32-column group and NC output column blocks are
+  // issued: a subdomain whose own and neighbouring ranks fit one short group
+  // and whose block has at most 16 live columns takes the short instance
+  auto run = [&](auto kg_c, auto nc_c) {
+    constexpr int KGR = decltype(kg_c)::value, NC = decltype(nc_c)::value;
+    for (int st = blockIdx.x * WNW + wave; st < nst; st += stride) {
+      const int p = st * 16 + l16;
+      const bool rin = p < N;
+      const int pc = rin ? p : N - 1;
+      const int ia = axis == 0 ? pc % d.lnx : pc / d.lnx;
+      const int f = axis == 0 ? pc / d.lnx : pc % d.lnx;
+      const bool hm = rin && ia > 0, hp = rin && ia < na - 1;
+      const bool flo = rin && ia == 0, fhi = rin && ia == na - 1;
+      const int pm = hm ? pc - e : pc, pp = hp ? pc + e : pc;
+      Acc acc[NC];
+      zero_prod<P>(acc, NC);
+      for (int kg = 0; kg < kgr; ++kg) {
+        F u0[KGR], um[KGR], up[KGR];
 #pragma unroll
-      for (int u = 0; u < KG; ++u) {
-        const int kc = 32 * kg + sub_col<P>(u, kq);
-        const bool kin = kc < r;
-        const int64_t col = (int64_t)(kin ? kc : 0) * N;
-        const double v0 = Us[col + pc], vm = Us[col + pm], vp = Us[col + pp];
-        u0[u] = (rin && kin) ? (F)v0 : (F)0;
-        um[u] = (hm && kin) ? (F)vm : (F)0;
-        up[u] = (hp && kin) ? (F)vp : (F)0;
-      }
-      prod_acc<P, NCB, KG>(acc, Cf + kg * gstride, u0);
-      prod_acc<P, NCB, KG>(acc, Cf + bstride + kg * gstride, um);
-      prod_acc<P, NCB, KG>(acc, Cf + 2 * bstride + kg * gstride, up);
-      // own face row: U[p] GLo at the low face, U[p] GHi at the high face
-      if (__any(flo || fhi)) {
-#pragma unroll
-        for (int u = 0; u < KG; ++u) {
-          um[u] = flo ? u0[u] : (F)0;
-          up[u] = fhi ? u0[u] : (F)0;
-        }
-        prod_acc<P, NCB, KG>(acc, Cf + 3 * bstride + kg * gstride, um);
-        prod_acc<P, NCB, KG>(acc, Cf + 4 * bstride + kg * gstride, up);
-      }
-    }
-    // the neighbours' face rows
-    if (__any(flo)) {
-      const int pn = face_cell(d, axis, true, f);
-      for (int kg = 0; kg < kgl; ++kg) {
-        F gn[KG];
-#pragma unroll
-        for (int u = 0; u < KG; ++u) {
+        for (int u = 0; u < KGR; ++u) {
           const int kc = 32 * kg + sub_col<P>(u, kq);
-          const bool in = flo && lo >= 0 && kc < rl;
-          const double v = Ul[(int64_t)(in ? kc : 0) * N + pn];
-          gn[u] = in ? (F)v : (F)0;
+          const bool kin = kc < r;
+          const int64_t col = (int64_t)(kin ? kc : 0) * N;
+          const double v0 = Us[col + pc], vm = Us[col + pm], vp = Us[col + pp];
+          u0[u] = (rin && kin) ? (F)v0 : (F)0;
+          um[u] = (hm && kin) ? (F)vm : (F)0;
+          up[u] = (hp && kin) ? (F)vp : (F)0;
         }
-        prod_acc<P, NCB, KG>(acc, Cf + 5 * bstride + kg * gstride, gn);
-      }
-    }
-    if (__any(fhi)) {
-      const int pn = face_cell(d, axis, false, f);
-      for (int kg = 0; kg < kgh; ++kg) {
-        F gn[KG];
+        prod_acc<P, NC, KGR, NCB>(acc, Cf + kg * gstride, u0);
+        prod_acc<P, NC, KGR, NCB>(acc, Cf + bstride + kg * gstride, um);
+        prod_acc<P, NC, KGR, NCB>(acc, Cf + 2 * bstride + kg * gstride, up);
+        // own face row: U[p] GLo at the low face, U[p] GHi at the high face
+        if (__any(flo || fhi)) {
 #pragma unroll
-        for (int u = 0; u < KG; ++u) {
-          const int kc = 32 * kg + sub_col<P>(u, kq);
-          const bool in = fhi && hi >= 0 && kc < rh;
-          const double v = Uh[(int64_t)(in ? kc : 0) * N + pn];
-          gn[u] = in ? (F)v : (F)0;
+          for (int u = 0; u < KGR; ++u) {
+            um[u] = flo ? u0[u] : (F)0;
+            up[u] = fhi ? u0[u] : (F)0;
+          }
+          prod_acc<P, NC, KGR, NCB>(acc, Cf + 3 * bstride + kg * gstride, um);
+          prod_acc<P, NC, KGR, NCB>(acc, Cf + 4 * bstride + kg * gstride, up);
         }
-        prod_acc<P, NCB, KG>(acc, Cf + 6 * bstride + kg * gstride, gn);
       }
+      // the neighbours' face rows
+      if (__any(flo)) {
+        const int pn = face_cell(d, axis, true, f);
+        for (int kg = 0; kg < kgl; ++kg) {
+          F gn[KGR];
+#pragma unroll
+          for (int u = 0; u < KGR; ++u) {
+            const int kc = 32 * kg + sub_col<P>(u, kq);
+            const bool in = flo && lo >= 0 && kc < rl;
+            const double v = Ul[(int64_t)(in ? kc : 0) * N + pn];
+            gn[u] = in ? (F)v : (F)0;
+          }
+          prod_acc<P, NC, KGR, NCB>(acc, Cf + 5 * bstride + kg * gstride, gn);
+        }
+      }
+      if (__any(fhi)) {
+        const int pn = face_cell(d, axis, false, f);
+        for (int kg = 0; kg < kgh; ++kg) {
+          F gn[KGR];
+#pragma unroll
+          for (int u = 0; u < KGR; ++u) {
+            const int kc = 32 * kg + sub_col<P>(u, kq);
+            const bool in = fhi && hi >= 0 && kc < rh;
+            const double v = Uh[(int64_t)(in ? kc : 0) * N + pn];
+            gn[u] = in ? (F)v : (F)0;
+          }
+          prod_acc<P, NC, KGR, NCB>(acc, Cf + 6 * bstride + kg * gstride, gn);
+        }
+      }
+#pragma unroll
+      for (int cb = 0; cb < NC; ++cb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int j = c0 + out_col<P>(cb, v, kq);
+          if (rin && j < t) K1[(int64_t)j * N + p] = (S)acc[cb][v];
+        }
     }
-#pragma unroll
-    for (int cb = 0; cb < NCB; ++cb)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int j = c0 + out_col<P>(cb, v, kq);
-        if (rin && j < t) K1[(int64_t)j * N + p] = (S)acc[cb][v];
-      }
-  }
+  };
+  constexpr int KG1 = P == 2 ? 8 : 4;
+  const int rmax = max(r, max(rl, rh));
+  if (live_sub<P>(rmax) <= KG1 && t - c0 <= 16) run(wint<KG1>{}, wint<1>{});
+  else run(wint<KG>{}, wint<NCB>{});
 }
 
 // L-step of an advection stage (eq. advx_evolL), weighted by sqrt(w), for
@@ -389,65 +406,74 @@ __global__ __launch_bounds__(WTHR) void kw_lstep(Dev d, int axis, int sd0) {
   S* ALs = (S*)d.AL + (int64_t)s * M * T;
   const int nst = wdiv(M, 16);
   const int stride = gridDim.x * WNW;
-  F xv[16], xn[16];
-  auto load = [&](int st_, int g_) {
-    const int q_ = st_ * 16 + l16;
-    const int qc = q_ < M ? q_ : M - 1;
+  // NS sub-steps of each 64-column group and NC output column blocks are
+  // issued: a subdomain with one short group and at most 16 live columns in
+  // the block takes the short instance
+  auto run = [&](auto ns_c, auto nc_c) {
+    constexpr int NS = decltype(ns_c)::value, NC = decltype(nc_c)::value;
+    F xv[NS], xn[NS];
+    auto load = [&](int st_, int g_) {
+      const int q_ = st_ * 16 + l16;
+      const int qc = q_ < M ? q_ : M - 1;
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int kc = 64 * g_ + sub_col<P>(u, kq);
-      const bool in = q_ < M && kc < t;
-      const S v = Qsd[(int64_t)(in ? kc : 0) * M + qc];
-      xn[u] = in ? (F)v : (F)0;
+      for (int u = 0; u < NS; ++u) {
+        const int kc = 64 * g_ + sub_col<P>(u, kq);
+        const bool in = q_ < M && kc < t;
+        const S v = Qsd[(int64_t)(in ? kc : 0) * M + qc];
+        xn[u] = in ? (F)v : (F)0;
+      }
+    };
+    int st = blockIdx.x * WNW + wave, g = 0;
+    if (st < nst) load(st, 0);
+    Acc a[NM][NC];
+#pragma unroll
+    for (int m = 0; m < NM; ++m) zero_prod<P>(a[m], NC);
+    while (st < nst) {
+#pragma unroll
+      for (int u = 0; u < NS; ++u) xv[u] = xn[u];
+      int st2 = st, g2 = g + 1;
+      if (g2 >= ng) {
+        g2 = 0;
+        st2 = st + stride;
+      }
+      if (st2 < nst) load(st2, g2);
+#pragma unroll
+      for (int m = 0; m < NM; ++m) prod_acc<P, NC, NS, NCB>(a[m], Pf + (m * NG + g) * gstride, xv);
+      if (g == ng - 1) {
+        const int q = st * 16 + l16;
+        const bool rin = q < M;
+        const double o = rin ? om[q] : 0.0;
+        const double op = o >= 0.0 ? o : 0.0, on = o < 0.0 ? o : 0.0;
+#pragma unroll
+        for (int cb = 0; cb < NC; ++cb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int j = c0 + out_col<P>(cb, v, kq);
+            double val;
+            if (NM == 3) {
+              val = (double)a[0][cb][v] + op * (double)a[1][cb][v] + on * (double)a[2][cb][v];
+            } else {
+              // sum_j w^j N_j of the direction's class, nested in w
+              double vp = (double)a[4][cb][v], vn = (double)a[8][cb][v];
+#pragma unroll
+              for (int m = 3; m >= 1; --m) {
+                vp = fma(vp, op, (double)a[m][cb][v]);
+                vn = fma(vn, on, (double)a[4 + m][cb][v]);
+              }
+              val = (double)a[0][cb][v] + op * vp + on * vn;
+            }
+            if (rin && j < t) ALs[(int64_t)j * M + q] = (S)val;
+          }
+#pragma unroll
+        for (int m = 0; m < NM; ++m) zero_prod<P>(a[m], NC);
+      }
+      st = st2;
+      g = g2;
     }
   };
-  int st = blockIdx.x * WNW + wave, g = 0;
-  if (st < nst) load(st, 0);
-  Acc a[NM][NCB];
-#pragma unroll
-  for (int m = 0; m < NM; ++m) zero_prod<P>(a[m], NCB);
-  while (st < nst) {
-#pragma unroll
-    for (int u = 0; u < 16; ++u) xv[u] = xn[u];
-    int st2 = st, g2 = g + 1;
-    if (g2 >= ng) {
-      g2 = 0;
-      st2 = st + stride;
-    }
-    if (st2 < nst) load(st2, g2);
-#pragma unroll
-    for (int m = 0; m < NM; ++m) prod_acc<P, NCB, 16>(a[m], Pf + (m * NG + g) * gstride, xv);
-    if (g == ng - 1) {
-      const int q = st * 16 + l16;
-      const bool rin = q < M;
-      const double o = rin ? om[q] : 0.0;
-      const double op = o >= 0.0 ? o : 0.0, on = o < 0.0 ? o : 0.0;
-#pragma unroll
-      for (int cb = 0; cb < NCB; ++cb)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int j = c0 + out_col<P>(cb, v, kq);
-          double val;
-          if (NM == 3) {
-            val = (double)a[0][cb][v] + op * (double)a[1][cb][v] + on * (double)a[2][cb][v];
-          } else {
-            // sum_j w^j N_j of the direction's class, nested in w
-            double vp = (double)a[4][cb][v], vn = (double)a[8][cb][v];
-#pragma unroll
-            for (int m = 3; m >= 1; --m) {
-              vp = fma(vp, op, (double)a[m][cb][v]);
-              vn = fma(vn, on, (double)a[4 + m][cb][v]);
-            }
-            val = (double)a[0][cb][v] + op * vp + on * vn;
-          }
-          if (rin && j < t) ALs[(int64_t)j * M + q] = (S)val;
-        }
-#pragma unroll
-      for (int m = 0; m < NM; ++m) zero_prod<P>(a[m], NCB);
-    }
-    st = st2;
-    g = g2;
-  }
+  constexpr int NS1 = P == 2 ? 8 : 4;
+  if (ng == 1 && live_sub<P>(t) <= NS1 && t - c0 <= 16) run(wint<NS1>{}, wint<1>{});
+  else run(wint<16>{}, wint<NCB>{});
 }
 
 // Degree-4 Taylor polynomial of exp: e(y) = 1 + y + y^2/2 + y^3/6 + y^4/24,
@@ -572,53 +598,61 @@ __global__ __launch_bounds__(WTHR) void kw_coll_kstep(Dev d, int sd0) {
   const double dt = d.dt, iW = 1.0 / d.W;
   const int nst = wdiv(N, 16);
   const int stride = gridDim.x * WNW;
-  F xn[KSP];
-  auto load = [&](int st_) {
-    const int p_ = st_ * 16 + l16;
-    const int pc = p_ < N ? p_ : N - 1;
+  // a subdomain of rank <= 16 (one short group, one column block) takes the
+  // short instance
+  auto run = [&](auto ns_c, auto nc_c) {
+    constexpr int NS = decltype(ns_c)::value, NC = decltype(nc_c)::value;
+    F xn[NS];
+    auto load = [&](int st_) {
+      const int p_ = st_ * 16 + l16;
+      const int pc = p_ < N ? p_ : N - 1;
 #pragma unroll
-    for (int u = 0; u < KSP; ++u) {
-      const int kc = sub_col<P>(u, kq);
-      const bool in = p_ < N && kc < r;
-      const double v = Us[(int64_t)(in ? kc : 0) * N + pc];
-      xn[u] = in ? (F)v : (F)0;
+      for (int u = 0; u < NS; ++u) {
+        const int kc = sub_col<P>(u, kq);
+        const bool in = p_ < N && kc < r;
+        const double v = Us[(int64_t)(in ? kc : 0) * N + pc];
+        xn[u] = in ? (F)v : (F)0;
+      }
+    };
+    int st = blockIdx.x * WNW + wave;
+    if (st < nst) load(st);
+    for (; st < nst; st += stride) {
+      F xv[NS];
+#pragma unroll
+      for (int u = 0; u < NS; ++u) xv[u] = xn[u];
+      if (st + stride < nst) load(st + stride);
+      const int p = st * 16 + l16;
+      const bool rin = p < N;
+      const int pc = rin ? p : N - 1;
+      Acc acc[NC], ae[1];
+      zero_prod<P>(acc, NC);
+      zero_prod<P>(ae, 1);
+      prod_acc<P, NC, NS, NCB>(acc, Bf, xv);
+      prod_acc<P, 1, NS>(ae, Be, xv);
+      // column 0 of the extra block sits in component 0 of lanes 0..15
+      const double km = __shfl((double)ae[0][0], l16, 64);
+      double a0, a1;
+      if (!d.rk4) {
+        a0 = rin ? 1.0 - dt * ct[pc] : 0.0;
+        a1 = rin ? dt * (cs[pc] * iW * km + Qs[pc]) : 0.0;
+      } else {
+        const double b = ct[pc], aa = cs[pc] * iW;
+        const double yb = -dt * b, yl = dt * (aa * mu - b);
+        a0 = rin ? taylor_e4(yb) : 0.0;
+        a1 = rin ? aa * taylor_d4(yl, yb, dt) * km + Qs[pc] * taylor_d4(yl, 0.0, dt) : 0.0;
+      }
+#pragma unroll
+      for (int cb = 0; cb < NC; ++cb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int j = c0 + out_col<P>(cb, v, kq);
+          if (rin && j < r) K1[(int64_t)j * N + p] = (S)fma(a0, (double)acc[cb][v], a1 * mv[j]);
+        }
     }
   };
-  int st = blockIdx.x * WNW + wave;
-  if (st < nst) load(st);
-  for (; st < nst; st += stride) {
-    F xv[KSP];
-#pragma unroll
-    for (int u = 0; u < KSP; ++u) xv[u] = xn[u];
-    if (st + stride < nst) load(st + stride);
-    const int p = st * 16 + l16;
-    const bool rin = p < N;
-    const int pc = rin ? p : N - 1;
-    Acc acc[NCB], ae[1];
-    zero_prod<P>(acc, NCB);
-    zero_prod<P>(ae, 1);
-    prod_acc<P, NCB, KSP>(acc, Bf, xv);
-    prod_acc<P, 1, KSP>(ae, Be, xv);
-    // column 0 of the extra block sits in component 0 of lanes 0..15
-    const double km = __shfl((double)ae[0][0], l16, 64);
-    double a0, a1;
-    if (!d.rk4) {
-      a0 = rin ? 1.0 - dt * ct[pc] : 0.0;
-      a1 = rin ? dt * (cs[pc] * iW * km + Qs[pc]) : 0.0;
-    } else {
-      const double b = ct[pc], aa = cs[pc] * iW;
-      const double yb = -dt * b, yl = dt * (aa * mu - b);
-      a0 = rin ? taylor_e4(yb) : 0.0;
-      a1 = rin ? aa * taylor_d4(yl, yb, dt) * km + Qs[pc] * taylor_d4(yl, 0.0, dt) : 0.0;
-    }
-#pragma unroll
-    for (int cb = 0; cb < NCB; ++cb)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int j = c0 + out_col<P>(cb, v, kq);
-        if (rin && j < r) K1[(int64_t)j * N + p] = (S)fma(a0, (double)acc[cb][v], a1 * mv[j]);
-      }
-  }
+  constexpr int NS1 = P == 2 ? 8 : 4;
+  if (live_sub<P>(r) <= NS1 && r - c0 <= 16) run(wint<NS1>{}, wint<1>{});
+  else run(wint<KSP>{}, wint<NCB>{});
 }
 
 // ----------------------------------------------------------------------------
