@@ -923,11 +923,11 @@ __device__ void s_sum_partials(const Dev& d, int s, int ngp, int off, int ldp, i
   constexpr int UI = 4;
   const double* gp = gpart_of(d, s);
   const int total = rows * cols;
-  for (int base = threadIdx.x; base < total; base += UI * blockDim.x) {
+  for (int base = threadIdx.x; base < total; base += UI * STHR) {  // STHR-thread kernels only
     int64_t src[UI];
 #pragma unroll
     for (int u = 0; u < UI; ++u) {
-      const int idx = base + u * blockDim.x;
+      const int idx = base + u * STHR;
       const int i = idx % rows, j = idx / rows;
       src[u] = idx < total ? off + i + (int64_t)j * ldp : off;
     }
@@ -935,7 +935,7 @@ __device__ void s_sum_partials(const Dev& d, int s, int ngp, int off, int ldp, i
     sum_partials_multi<UI>(gp, d.gpTile, ngp, src, acc);
 #pragma unroll
     for (int u = 0; u < UI; ++u) {
-      const int idx = base + u * blockDim.x;
+      const int idx = base + u * STHR;
       if (idx < total) dst[idx % rows + (int64_t)(idx / rows) * ldd] = scale * acc[u];
     }
   }
@@ -949,7 +949,7 @@ __device__ void gmm(double* C, int ldc, const double* A, int lda, bool ta, const
                     int n, int k, double alpha, double beta, const double* D, int ldd) {
   constexpr int KC = 16, NL = KC / 4;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int nw = blockDim.x >> 6;
+  constexpr int nw = SNW;  // called by STHR-thread kernels only
   const int l16 = lane & 15, kq = lane >> 4;
   const int tm = wdiv(m, 16), tn = wdiv(n, 16);
   const int nch = wdiv(k, KC);
@@ -1019,7 +1019,7 @@ __device__ void gmm_sym(double* C, int ldc, const double* A, int lda, const doub
                         double beta, const double* D, int ldd) {
   constexpr int KC = 16, NL = KC / 4;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int nw = blockDim.x >> 6;
+  constexpr int nw = SNW;  // called by STHR-thread kernels only
   const int l16 = lane & 15, kq = lane >> 4;
   const int tn = wdiv(n, 16);
   const int ntiles = tn * (tn + 1) / 2;
@@ -1085,21 +1085,21 @@ __device__ void gmm_sym(double* C, int ldc, const double* A, int lda, const doub
 // (Frobenius, at most 48 steps).  Eigenvalues below the scaled phase's bound
 // keep their sign; exactly zero ones stay zero.  X, Y and W are t x t work
 // buffers (ld ld).  Then C+ = (C + |C|) / 2 = P diag(max(lambda, 0)) P^T and
-// C- = (C - |C|) / 2 without the eigenvectors.
+// C- = (C - |C|) / 2 without the eigenvectors.  STHR threads.
 __device__ void ns_abs(const double* C, double* X, double* Y, double* W, double* out, int t, int ld, double* red) {
   double part = 0.0;
-  for (int idx = threadIdx.x; idx < t * t; idx += blockDim.x) {
+  for (int idx = threadIdx.x; idx < t * t; idx += STHR) {
     const double c = C[(idx % t) + (int64_t)(idx / t) * ld];
     part = fma(c, c, part);
   }
   const double fro = sqrt(s_sum(part, red));
   if (!(fro > 0.0)) {
-    for (int idx = threadIdx.x; idx < t * t; idx += blockDim.x) out[(idx % t) + (int64_t)(idx / t) * ld] = 0.0;
+    for (int idx = threadIdx.x; idx < t * t; idx += STHR) out[(idx % t) + (int64_t)(idx / t) * ld] = 0.0;
     __syncthreads();
     return;
   }
   const double ifro = 1.0 / fro;
-  for (int idx = threadIdx.x; idx < t * t; idx += blockDim.x) {
+  for (int idx = threadIdx.x; idx < t * t; idx += STHR) {
     const int o = (idx % t) + (idx / t) * ld;
     X[o] = C[o] * ifro;
   }
@@ -1119,7 +1119,7 @@ __device__ void ns_abs(const double* C, double* X, double* Y, double* W, double*
     gmm_sym(Y, ld, X, ld, X, ld, t, 1.0, 0.0, Y, ld);
     gmm_sym(W, ld, X, ld, Y, ld, t, -0.5, 1.5, X, ld);
     double ch = 0.0;
-    for (int idx = threadIdx.x; idx < t * t; idx += blockDim.x) {
+    for (int idx = threadIdx.x; idx < t * t; idx += STHR) {
       const int o = (idx % t) + (idx / t) * ld;
       const double dl = W[o] - X[o];
       ch = fma(dl, dl, ch);
@@ -1140,68 +1140,76 @@ __device__ void ns_abs(const double* C, double* X, double* Y, double* W, double*
 // 1e-20 of its initial diagonal d0[k] (or not finite): its column is set to
 // the unit vector, so the factorisation goes on.  Returns the smallest ratio
 // pivot / d0 met (for the unshifted first try).  The strict upper triangle
-// is zeroed on exit.  col: n doubles of LDS scratch.
+// is zeroed on exit.  col: n doubles of LDS scratch.  STHR threads.
 __device__ double lds_chol(const Dev& d, double* L, int n, const double* d0, int* dep, double* red, double* col) {
-  // the active matrix in registers: thread (ri, ci) = (tid / 32, tid % 32)
-  // holds rows 4 ri .. 4 ri + 3 and columns 4 ci .. 4 ci + 3 of the full
-  // square (both triangles get the same updates); each step's column goes
-  // through LDS (col) and its scaled values into L
-  static_assert(4 * 32 >= WCAP_T && STHR == 1024, "register tiles of the Gram");
+  // the active matrix in registers: thread t < CTHR, (ri, ci) = (t % 16,
+  // t / 16), holds rows 8 ri .. 8 ri + 7 and columns 4 ci .. 4 ci + 3 of the
+  // full square (both triangles get the same updates), so the holders of a
+  // column are 16 lanes of one wavefront; each step's column goes through
+  // LDS (col) and its scaled values into L.  The other wavefronts only keep
+  // the barriers: the per-step work that every wavefront repeats (the
+  // pivot's square root and reciprocal, the column reads) is issued by half
+  // as many.
+  constexpr int CTHR = 512;
+  static_assert(8 * 16 >= WCAP_T && 4 * (CTHR / 16) >= WCAP_T && STHR >= CTHR, "register tiles of the Gram");
   double& minratio = red[SNW];
-  const int ri = threadIdx.x >> 5, ci = threadIdx.x & 31;
-  double g[4][4];
+  const bool act = threadIdx.x < CTHR;
+  const int ri = threadIdx.x & 15, ci = (threadIdx.x >> 4) & (CTHR / 16 - 1);
+  double g[8][4];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < 8; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-      const int i = 4 * ri + a, j = 4 * ci + b;
-      g[a][b] = (i < n && j < n) ? L[i + j * WLD] : 0.0;
+      const int i = 8 * ri + a, j = 4 * ci + b;
+      g[a][b] = (act && i < n && j < n) ? L[i + j * WLD] : 0.0;
     }
   if (threadIdx.x == 0) minratio = 1e300;
   __syncthreads();
   for (int k = 0; k < n; ++k) {
     // the holders of column k publish it
-    if (ci == (k >> 2)) {
+    if (act && ci == (k >> 2)) {
       const int cc = k & 3;
 #pragma unroll
-      for (int a = 0; a < 4; ++a) {
+      for (int a = 0; a < 8; ++a) {
         double v = 0.0;
 #pragma unroll
         for (int b = 0; b < 4; ++b)
           if (b == cc) v = g[a][b];
-        if (4 * ri + a < n) col[4 * ri + a] = v;
+        if (8 * ri + a < n) col[8 * ri + a] = v;
       }
     }
     __syncthreads();
-    const double pv = col[k];
-    const bool isdep = !isfinite(pv) || !(pv > 1e-20 * d0[k]);
-    const double lkk = isdep ? 1.0 : sqrt(pv);
-    const double il = 1.0 / lkk;
-    if (threadIdx.x == 0) {
-      dep[k] = isdep ? 1 : 0;
-      minratio = fmin(minratio, isdep ? 0.0 : pv / d0[k]);
-      L[k + k * WLD] = lkk;
-      if (!isfinite(pv)) atomicOr(d.flags, FLAG_NONFINITE);
+    if (act) {
+      const double pv = col[k];
+      const bool isdep = !isfinite(pv) || !(pv > 1e-20 * d0[k]);
+      const double lkk = isdep ? 1.0 : sqrt(pv);
+      const double il = 1.0 / lkk;
+      if (threadIdx.x == 0) {
+        dep[k] = isdep ? 1 : 0;
+        minratio = fmin(minratio, isdep ? 0.0 : pv / d0[k]);
+        L[k + k * WLD] = lkk;
+        if (!isfinite(pv)) atomicOr(d.flags, FLAG_NONFINITE);
+      }
+      for (int i = k + 1 + (int)threadIdx.x; i < n; i += CTHR) L[i + k * WLD] = isdep ? 0.0 : col[i] * il;
+      double li[8], lj[4];
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        const int i = 8 * ri + a;
+        li[a] = (i > k && i < n && !isdep) ? col[i] * il : 0.0;
+      }
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int j = 4 * ci + b;
+        lj[b] = (j > k && j < n && !isdep) ? col[j] * il : 0.0;
+      }
+#pragma unroll
+      for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) g[a][b] = fma(-li[a], lj[b], g[a][b]);
     }
-    for (int i = k + 1 + (int)threadIdx.x; i < n; i += blockDim.x) L[i + k * WLD] = isdep ? 0.0 : col[i] * il;
-    double li[4], lj[4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const int i = 4 * ri + a;
-      li[a] = (i > k && i < n && !isdep) ? col[i] * il : 0.0;
-    }
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int j = 4 * ci + b;
-      lj[b] = (j > k && j < n && !isdep) ? col[j] * il : 0.0;
-    }
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int b = 0; b < 4; ++b) g[a][b] = fma(-li[a], lj[b], g[a][b]);
     __syncthreads();
   }
-  for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+  for (int idx = threadIdx.x; idx < n * n; idx += STHR) {
     const int i = idx % n, j = idx / n;
     if (i < j) L[i + j * WLD] = 0.0;
   }
@@ -1214,10 +1222,10 @@ __device__ double lds_chol(const Dev& d, double* L, int n, const double* d0, int
 // In-place inverse of the lower triangular L (n x n, LDS, ld WLD, unit
 // vectors in dependent columns keep it regular), column by column from the
 // last: X[j][j] = 1/L[j][j], X[i][j] = -X[j][j] sum_{j<l<=i} X[i][l] L[l][j].
-// Each row's sum is split over 8 lanes and added with DPP.
+// Each row's sum is split over 8 lanes and added with DPP (STHR threads).
 __device__ void lds_tri_inv(double* L, int n, double* colj) {
   for (int j = n - 1; j >= 0; --j) {
-    for (int i = threadIdx.x; i < n; i += blockDim.x) colj[i] = L[i + j * WLD];
+    for (int i = threadIdx.x; i < n; i += STHR) colj[i] = L[i + j * WLD];
     __syncthreads();
     const double xjj = 1.0 / colj[j];
     const int grp = threadIdx.x >> 3, sub = threadIdx.x & 7;
