@@ -945,8 +945,9 @@ __device__ void s_sum_partials(const Dev& d, int s, int ngp, int off, int ldp, i
 // pointers (LDS or global), C aliasing neither A nor B; the 16 x 16 output
 // tiles are dealt to the wavefronts, k walked in steps of 64 with all operand
 // loads of a step issued first.  Ends with a barrier.
-__device__ void gmm(double* C, int ldc, const double* A, int lda, bool ta, const double* B, int ldb, bool tb, int m,
-                    int n, int k, double alpha, double beta, const double* D, int ldd) {
+__device__ __forceinline__ void gmm_t1(double* C, int ldc, const double* A, int lda, bool ta, const double* B,
+                                       int ldb, bool tb, int m, int n, int k, double alpha, double beta,
+                                       const double* D, int ldd) {
   constexpr int KC = 16, NL = KC / 4;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   constexpr int nw = SNW;  // called by STHR-thread kernels only
@@ -999,6 +1000,94 @@ __device__ void gmm(double* C, int ldc, const double* A, int lda, bool ta, const
     }
   }
   __syncthreads();
+}
+
+// The same product with 2 x 2 output tiles per wavefront and step: the
+// operands of two row blocks and two column blocks are loaded once for four
+// tiles (half the loads per matrix-core instruction), k walked in steps of 4
+// with the next step's operands loaded while the current MFMAs run.
+template <bool ta, bool tb>
+__device__ __forceinline__ void gmm_t2(double* C, int ldc, const double* A, int lda, const double* B, int ldb, int m,
+                                       int n, int k, double alpha, double beta, const double* D, int ldd) {
+  constexpr int KC = 4, NL = KC / 4;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int nw = SNW;  // called by STHR-thread kernels only
+  const int l16 = lane & 15, kq = lane >> 4;
+  const int bm = wdiv(m, 32), bn = wdiv(n, 32);
+  const int nch = wdiv(k, KC);
+  for (int blk = wave; blk < bm * bn; blk += nw) {
+    const int i0 = 32 * (blk % bm), j0 = 32 * (blk / bm);
+    int ic[2], jc[2];
+    bool iv[2], jv[2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x) {
+      const int i = i0 + 16 * x + l16, j = j0 + 16 * x + l16;
+      iv[x] = i < m;
+      jv[x] = j < n;
+      ic[x] = iv[x] ? i : 0;
+      jc[x] = jv[x] ? j : 0;
+    }
+    auto load = [&](int c, double (&av)[2][NL], double (&bv)[2][NL]) {
+#pragma unroll
+      for (int u = 0; u < NL; ++u) {
+        const int l = c * KC + 4 * u + kq;
+        const bool lin = l < k;
+        const int lc = lin ? l : 0;
+#pragma unroll
+        for (int x = 0; x < 2; ++x) {
+          const double a_ = ta ? A[lc + (int64_t)ic[x] * lda] : A[ic[x] + (int64_t)lc * lda];
+          const double b_ = tb ? B[jc[x] + (int64_t)lc * ldb] : B[lc + (int64_t)jc[x] * ldb];
+          av[x][u] = (iv[x] && lin) ? a_ : 0.0;
+          bv[x][u] = (jv[x] && lin) ? b_ : 0.0;
+        }
+      }
+    };
+    dbl4 acc[2][2] = {{zero4(), zero4()}, {zero4(), zero4()}};
+    double a0[2][NL], b0[2][NL], a1[2][NL], b1[2][NL];
+    if (nch > 0) load(0, a0, b0);
+    for (int c = 0; c < nch; c += 2) {
+      if (c + 1 < nch) load(c + 1, a1, b1);
+#pragma unroll
+      for (int u = 0; u < NL; ++u)
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y) acc[x][y] = mfma64(a0[x][u], b0[y][u], acc[x][y]);
+      if (c + 1 >= nch) break;
+      if (c + 2 < nch) load(c + 2, a0, b0);
+#pragma unroll
+      for (int u = 0; u < NL; ++u)
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y) acc[x][y] = mfma64(a1[x][u], b1[y][u], acc[x][y]);
+    }
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int ci = i0 + 16 * x + 4 * v + kq, cj = j0 + 16 * y + l16;
+          if (ci < m && cj < n) {
+            const double a = acc[x][y][v];
+            C[ci + (int64_t)cj * ldc] = beta == 0.0 ? alpha * a : fma(alpha, a, beta * D[ci + (int64_t)cj * ldd]);
+          }
+        }
+  }
+  __syncthreads();
+}
+
+// products of at least 2 SNW tiles take the 2 x 2 tiling
+__device__ void gmm(double* C, int ldc, const double* A, int lda, bool ta, const double* B, int ldb, bool tb, int m,
+                    int n, int k, double alpha, double beta, const double* D, int ldd) {
+  if (wdiv(m, 16) * wdiv(n, 16) >= 2 * SNW) {
+    if (ta && tb) gmm_t2<true, true>(C, ldc, A, lda, B, ldb, m, n, k, alpha, beta, D, ldd);
+    else if (ta) gmm_t2<true, false>(C, ldc, A, lda, B, ldb, m, n, k, alpha, beta, D, ldd);
+    else if (tb) gmm_t2<false, true>(C, ldc, A, lda, B, ldb, m, n, k, alpha, beta, D, ldd);
+    else gmm_t2<false, false>(C, ldc, A, lda, B, ldb, m, n, k, alpha, beta, D, ldd);
+  } else
+    gmm_t1(C, ldc, A, lda, ta, B, ldb, tb, m, n, k, alpha, beta, D, ldd);
 }
 
 __device__ __forceinline__ void gmm(double* C, int ldc, const double* A, int lda, bool ta, const double* B, int ldb,
@@ -1075,6 +1164,7 @@ __device__ void gmm_sym(double* C, int ldc, const double* A, int lda, const doub
   }
   __syncthreads();
 }
+
 
 // |C| = sign(C) C for a symmetric t x t matrix C (ld ld) into out, by the
 // scaled Newton-Schulz iteration of Chen and Chow (2014) on X0 = C / |C|_F:
