@@ -748,7 +748,8 @@ __global__ __launch_bounds__(XTHR, 4) void kw_xgram(Dev d, int axis, int sd0, XJ
   const W* xw = (const W*)J.x.p + bx;
   const double* yd = (const double*)J.y.p + by;
   const W* yw = (const W*)J.y.p + by;
-  auto fetch = [&](int ch, double (&xv)[NQ], double (&yv)[NQ]) {
+  // columns cb0 + 2 q + lane / 32 (q < NQ) of rows ch XR + lane % 32
+  auto fetch = [&](int ch, int cb0, double (&xv)[NQ], double (&yv)[NQ]) {
     const int row = ch * XR + lr;
     const bool rin = row < rows;
     const int rc = rin ? row : 0;
@@ -767,7 +768,7 @@ __global__ __launch_bounds__(XTHR, 4) void kw_xgram(Dev d, int axis, int sd0, XJ
     const double sy1 = (J.shift && J.y.rowscale) ? d.sw[hs ? py + e : py] : sy;
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-      const int cl = 2 * (NQ * wave + q) + lc;  // column of the block, 0..63
+      const int cl = cb0 + 2 * q + lc;  // column of the block, 0..63
       const int ci = cx0 + cl, cj = cy0 + cl;
       const bool xin = ci < nx, yin = cj < ny;
       double v = 0.0, u = 0.0;
@@ -793,18 +794,71 @@ __global__ __launch_bounds__(XTHR, 4) void kw_xgram(Dev d, int axis, int sd0, XJ
       yv[q] = u;
     }
   };
-  auto stash = [&](const double (&xv)[NQ], const double (&yv)[NQ]) {
+  auto stash = [&](double* xb, double* yb, int cb0, const double (&xv)[NQ], const double (&yv)[NQ]) {
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-      const int cl = 2 * (NQ * wave + q) + lc;
-      xs[cl * XLD + lr] = xv[q];
-      ys[cl * XLD + lr] = yv[q];
+      const int cl = cb0 + 2 * q + lc;
+      xb[cl * XLD + lr] = xv[q];
+      yb[cl * XLD + lr] = yv[q];
     }
   };
+  const int nch = wdiv(rows, XR);
+  if (nx - cx0 <= 16 && ny - cy0 <= 16) {
+    // a block with at most 16 live rows and columns: each wavefront stages
+    // and reduces chunks of its own (32 rows of 16 columns, no workgroup
+    // barrier), then the four sums are added in a fixed order
+    constexpr int XNW = XTHR / 64;
+    double* xw = xs + wave * 16 * XLD;
+    double* yw = ys + wave * 16 * XLD;
+    dbl4 acc = zero4();
+    for (int ch = blockIdx.x * XNW + wave; ch < nch; ch += gridDim.x * XNW) {
+      {
+        double xv[NQ], yv[NQ];
+        fetch(ch, 0, xv, yv);
+        stash(xw, yw, 0, xv, yv);
+      }
+      wave_sync();
+      const double* xa = xw + l16 * XLD + kq;
+      const double* yb = yw + l16 * XLD + kq;
+      dbl4 cacc = zero4();
+#pragma unroll
+      for (int ks = 0; ks < XR / 4; ++ks) cacc = mfma64(xa[4 * ks], yb[4 * ks], cacc);
+      acc += cacc;
+      wave_sync();
+    }
+    __syncthreads();
+    double* red = xs;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) red[(wave * 4 + v) * 64 + lane] = acc[v];
+    __syncthreads();
+    if (wave != 0) return;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      double tot = red[v * 64 + lane];
+#pragma unroll
+      for (int w = 1; w < XNW; ++w) tot += red[(w * 4 + v) * 64 + lane];
+      acc[v] = tot;
+    }
+    double* out = gpart_of(d, s) + (int64_t)blockIdx.x * d.gpTile + J.out_off;
+    const int ld = J.out_ld > 0 ? J.out_ld : nx;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = 64 * a + 4 * v + kq, j = 64 * b + l16;
+      if (i >= nx || j >= ny) continue;
+      const double val = J.scale * acc[v];
+      if (J.sym) {
+        if (a == b && i > j) continue;
+        out[i + (int64_t)j * ld] = val;
+        out[j + (int64_t)i * ld] = val;
+      } else {
+        out[i + (int64_t)j * ld] = val;
+      }
+    }
+    return;
+  }
   // wavefront w accumulates the output rows 16 w .. 16 w + 15 of the block,
   // in NCJ column blocks of 16 (only as many as the block has live columns);
   // a wavefront whose rows are all beyond the live ones only stages data
-  const int nch = wdiv(rows, XR);
   const bool wlive = cx0 + 16 * wave < nx;
   auto run = [&](auto ncj_c) {
     constexpr int NCJ = decltype(ncj_c)::value;
@@ -813,9 +867,9 @@ __global__ __launch_bounds__(XTHR, 4) void kw_xgram(Dev d, int axis, int sd0, XJ
     for (int ch = blockIdx.x; ch < nch; ch += gridDim.x) {
       {
         double xv[NQ], yv[NQ];
-        fetch(ch, xv, yv);
+        fetch(ch, 2 * NQ * wave, xv, yv);
         __syncthreads();
-        stash(xv, yv);
+        stash(xs, ys, 2 * NQ * wave, xv, yv);
       }
       __syncthreads();
       if (wlive) {
