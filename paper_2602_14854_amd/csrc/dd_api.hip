@@ -311,8 +311,9 @@ void set_wide_partials(Dev& d) {
   const int capN = std::max(1, (int)(d.gpStride / d.gpTile));
   d.xpN = std::min(2 * d.nwgN, capN);
   d.xpM = std::min(2 * d.nwgM, capN);
-  // the Galerkin job sets write several blocks per subdomain and their
-  // partials are summed by one workgroup: at most 8 row splits
+  // the Galerkin job sets (several blocks per subdomain) and the Gram of
+  // the augmentation matrix are summed by one workgroup of the preparation
+  // and SVD kernels: at most 8 row splits
   d.xgN = std::min(d.xpN, 8);
   d.xgM = std::min(d.xpM, 8);
 }
@@ -783,14 +784,14 @@ dd::XJob xjob(const dd::XSrc& x, const dd::XSrc& y, int capx, int capy, int wmod
 // Gram of X into the partial sums; wide: read by a wide kernel (d.xpN /
 // d.xpM partials), else by a narrow one (d.nwgN / d.nwgM)
 void w_gram(dd_dlra_handle h, int kind, int axis, const void* X, bool is64, int64_t sd, int rows, int ndim, int cap,
-            bool cells, bool wide, int skip_off = -1) {
+            bool cells, bool wide, int skip_off = -1, int np_set = 0) {
   const Dev& d = h->d;
   dd::XJobs jobs;
   jobs.n = 1;
   jobs.skip_off = skip_off;
   const dd::XSrc x = xsrc(X, sd, rows, ndim, is64);
   jobs.j[0] = xjob(x, x, cap, cap, 0, true, 0, -1);
-  const int np = wide ? (cells ? d.xpN : d.xpM) : (cells ? d.nwgN : d.nwgM);
+  const int np = np_set > 0 ? np_set : (wide ? (cells ? d.xpN : d.xpM) : (cells ? d.nwgN : d.nwgM));
   phase(h, kind, [&](int s0, int ns) { dd::launch_w_xgram(d, axis, s0, ns, jobs, cells, np, h->stream); });
 }
 
@@ -834,7 +835,9 @@ void enqueue_advection_wide(dd_dlra_handle h, int axis, int upto = 0) {
   // Algorithm 4: A = sqrt(w) L0, its Gram, the SVD through the pivoted
   // Cholesky factor, V-hat = A B Sigma^-2, two Cholesky-QR passes
   phase(h, K_AUG_FORM, [&](int s0, int ns) { dd::launch_w_aug_form(d, axis, s0, ns, st); });
-  w_gram(h, K_W_GRAM_A, axis, d.A, true, sdMA, d.M, dd::DIM_M0, d.MA, false, true);
+  // the augmentation SVD sums the Gram's partials in its one workgroup: at
+  // most 8 of them
+  w_gram(h, K_W_GRAM_A, axis, d.A, true, sdMA, d.M, dd::DIM_M0, d.MA, false, true, -1, d.xgM);
   phase(h, K_AUG_SVD, [&](int s0, int ns) { dd::launch_w_aug_svd(d, axis, s0, ns, st); });
   phase(h, K_GEMM_VHAT, [&](int s0, int ns) {
     dd::launch_w_gemm(d, axis, s0, ns, d.A, true, sdMA, d.M, dd::DIM_M0, dd::DIM_T, d.oCoef, d.MA, d.Qh, false, sdMT,

@@ -31,7 +31,7 @@ struct Dev {
   int ntN, ntM;            // tiles over cells / over directions
   int nwgN, nwgM;          // workgroups per subdomain for cell / direction kernels
   int xpN, xpM;            // partial sums (row splits) of the wide plan's reductions read by wide kernels
-  int xgN, xgM;            // the same for the wide Galerkin job sets (angular, spatial)
+  int xgN, xgM;            // the same for the Galerkin job sets and the Gram of A (at most 8)
   int gpTile;              // doubles per workgroup partial
   int64_t gpStride;        // doubles of partials per subdomain (room for the largest grid)
   int64_t smallStride;     // doubles of small workspace per subdomain

@@ -1951,7 +1951,7 @@ __device__ __forceinline__ void aug_svd_body(const Dev& d, int s, int axis, int 
   // columns j over the wavefronts, rows i >= j over the lanes
   {
     const double* gp = gpart_of(d, s);
-    const int ngp = d.xpM;
+    const int ngp = d.xgM;  // the Gram of A is reduced into at most 8 partials
     constexpr int UI = 2;
     for (int j = wave; j < m0; j += JNW)
       for (int i0 = j + lane; i0 < m0; i0 += 64 * UI) {
