@@ -115,6 +115,42 @@ def test_wide_medium_ranks(stage):
     stage_check(wl, stage, 1e-11)
 
 
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("stage,ranks", [(0, [1, 2, 24, 40]), (1, [1, 24, 2, 40]), (2, [1, 2, 24, 40]),
+                                         (0, [8, 12, 24, 40])])
+def test_wide_low_and_high_ranks_together(stage, ranks):
+    """Ranks 1, 2, 24 and 40 in one launch: the short instances of the
+    tall-skinny kernels and the per-wavefront reduction of small blocks (ranks
+    up to 16; intermediate ranks 17 to 32 take the middle instance of the
+    products) run beside the full instances.  Along the stage axis a low rank
+    meets a low one and a high rank a high one: a rank-1 subdomain next to a
+    rank-24 one makes K1 exactly rank deficient, and the completion of its
+    basis (arbitrary, the result depends on it) is compared by the oracle's
+    own spread elsewhere, not at this bar."""
+    wl = graded_case(ranks)
+    say(f"case: 2x2 of 16x16, M=256, ranks {ranks}, stage {stage}")
+    stage_check(wl, stage, 1e-11)
+
+
+def test_wide_low_and_high_ranks_exec_modes_bitwise_equal():
+    """With low and high ranks together, per-subdomain launches, batched
+    launches and the captured graph give bitwise identical factors after two
+    steps."""
+    import paper_2602_14854_amd as pkg
+    wl = graded_case([1, 2, 24, 40])
+    say("case: wide plan, ranks 1/2/24/40, exec modes")
+    out = []
+    for mode in (pkg.DD_EXEC_PER_SUBDOMAIN, pkg.DD_EXEC_BATCHED, pkg.DD_EXEC_BATCHED_GRAPH):
+        e = engine(wl, exec_mode=mode)
+        e.step(2)
+        out.append(e.state())
+        e.close()
+    for other in out[1:]:
+        for a, b in zip(out[0], other):
+            for x, y in zip(a, b):
+                assert np.array_equal(x, y)
+
+
 def test_wide_exec_modes_bitwise_equal():
     """Per-subdomain launches, batched launches and the captured graph give
     bitwise identical factors in the wide plan."""
