@@ -64,9 +64,9 @@ __device__ __forceinline__ void stage_frags(typename Prec<P>::F* frag, const dou
 // fill mask get deterministic pseudo-random values; with set_rank, one
 // workgroup of each subdomain commits the truncated rank.
 template <class SI, class SO, int P, int NCB>
-__global__ __launch_bounds__(WTHR) void kw_gemm(Dev d, int axis, int sd0, const void* X, int64_t xsd, int rows,
-                                                int kdim, int ndim, int boff, int bld, void* Y, int64_t ysd,
-                                                const double* rowscale, int fill_off, int set_rank, int skip_off) {
+__global__ __launch_bounds__(WTHR, P == 2 ? 2 : 4)  // four wavefronts per SIMD (two for split BF16)
+void kw_gemm(Dev d, int axis, int sd0, const void* X, int64_t xsd, int rows, int kdim, int ndim, int boff, int bld,
+             void* Y, int64_t ysd, const double* rowscale, int fill_off, int set_rank, int skip_off) {
   using F = typename Prec<P>::F;
   using Acc = typename Prec<P>::Acc;
   const int s = sd0 + blockIdx.y;
@@ -106,33 +106,43 @@ __global__ __launch_bounds__(WTHR) void kw_gemm(Dev d, int axis, int sd0, const 
   // columns, few output columns) takes a shorter instance
   auto run = [&](auto ns_c, auto nc_c) {
     constexpr int NS = decltype(ns_c)::value, NC = decltype(nc_c)::value;
-    F xv[NS], xn[NS];
-    auto load = [&](int st_, int g_) {
+    // a group's NS sub-steps go in chunks of SUB (one instruction's worth:
+    // 4 sub-steps, or 8 for the split-BF16 32-column instruction), the next
+    // chunk's operands loaded while the current one's MFMAs run; so few
+    // values in flight per lane keep the kernel at four wavefronts per SIMD
+    constexpr int SUBI = P == 2 ? 8 : 4;
+    constexpr int SUB = NS < SUBI ? NS : SUBI, NH = NS / SUB;
+    F xv[SUB], xn[SUB];
+    auto load = [&](int st_, int g_, int h_) {
       const int row_ = st_ * 16 + l16;
       const int rc = row_ < rows ? row_ : rows - 1;
 #pragma unroll
-      for (int u = 0; u < NS; ++u) {
-        const int kc = 64 * g_ + sub_col<P>(u, kq);
+      for (int u = 0; u < SUB; ++u) {
+        const int kc = 64 * g_ + sub_col<P>(SUB * h_ + u, kq);
         const bool in = row_ < rows && kc < k;
         const SI v = Xs[(unsigned)((in ? kc : 0) * rows + rc)];  // offsets within a slab fit in 32 bits
         xn[u] = in ? (F)v : (F)0;
       }
     };
-    int st = blockIdx.x * WNW + wave, g = 0;
-    if (st < nst) load(st, 0);
+    int st = blockIdx.x * WNW + wave, g = 0, h = 0;
+    if (st < nst) load(st, 0, 0);
     Acc acc[NC];
     zero_prod<P>(acc, NC);
     while (st < nst) {
 #pragma unroll
-      for (int u = 0; u < NS; ++u) xv[u] = xn[u];
-      int st2 = st, g2 = g + 1;
-      if (g2 >= ng) {
-        g2 = 0;
-        st2 = st + stride;
+      for (int u = 0; u < SUB; ++u) xv[u] = xn[u];
+      int st2 = st, g2 = g, h2 = h + 1;
+      if (h2 >= NH) {
+        h2 = 0;
+        g2 = g + 1;
+        if (g2 >= ng) {
+          g2 = 0;
+          st2 = st + stride;
+        }
       }
-      if (st2 < nst) load(st2, g2);
-      prod_acc<P, NC, NS, NCB>(acc, frag + g * 16 * NCB * 64, xv);
-      if (g == ng - 1) {
+      if (st2 < nst) load(st2, g2, h2);
+      prod_acc<P, NC, SUB, NCB>(acc, frag + (g * 16 + SUB * h) * NCB * 64, xv);
+      if (g == ng - 1 && h == NH - 1) {
         const int row = st * 16 + l16;
         const bool rin = row < rows;
         const double rs = (rowscale != nullptr && rin) ? rowscale[row] : 1.0;
@@ -150,6 +160,7 @@ __global__ __launch_bounds__(WTHR) void kw_gemm(Dev d, int axis, int sd0, const 
       }
       st = st2;
       g = g2;
+      h = h2;
     }
   };
   constexpr int NS1 = P == 2 ? 8 : 4;  // one matrix-core instruction (P = 2: one 32-column one)
