@@ -998,7 +998,6 @@ __global__ __launch_bounds__(NTHR) void k_coll_lstep(Dev d, int sd0) {
   using F = typename Prec<P>::F;
   using Acc = typename Prec<P>::Acc;
   constexpr int LD = strip_ld<NCB>();
-  constexpr int NB = NCB * (NCB + 1) / 2;
   const int s = sd0 + blockIdx.y;
   const int r = d.rank[s];
   const int M = d.M, R = d.R;
@@ -1018,54 +1017,65 @@ __global__ __launch_bounds__(NTHR) void k_coll_lstep(Dev d, int sd0) {
   __syncthreads();
   const double* Vs = d.V + (int64_t)s * M * R;
   S* ALs = (S*)d.AL + (int64_t)s * M * d.T;
-  dbl4 g[NB];
-  zero_acc<NB>(g);
   const int nst = ceil_div(M, 16);
   const int stride = gridDim.x * NW;
-  F xn[KSP];
-  double swn = 0.0;
-  auto load = [&](int st_) {
-    const int q_ = st_ * 16 + l16;
-    const int qc = q_ < M ? q_ : M - 1;
+  // NC output column blocks and KSR sub-steps are issued: a subdomain of
+  // rank at most one instruction's columns (and 16) takes the short instance
+  auto run = [&](auto nc_c, auto ks_c) {
+    constexpr int NC = decltype(nc_c)::value, KSR = decltype(ks_c)::value;
+    constexpr int NBR = NC * (NC + 1) / 2;
+    dbl4 g[NBR];
+    zero_acc<NBR>(g);
+    F xn[KSR];
+    double swn = 0.0;
+    auto load = [&](int st_) {
+      const int q_ = st_ * 16 + l16;
+      const int qc = q_ < M ? q_ : M - 1;
 #pragma unroll
-    for (int u = 0; u < KSP; ++u) {
-      const int kc = sub_col<P>(u, kq);
-      const bool in = q_ < M && kc < r;
-      const double v = Vs[(int64_t)(in ? kc : 0) * M + qc];
-      xn[u] = in ? (F)v : (F)0;
-    }
-    const double w_ = d.sw[qc];
-    swn = q_ < M ? w_ : 0.0;
-  };
-  int st = blockIdx.x * NW + wave;
-  if (st < nst) load(st);
-  for (; st < nst; st += stride) {
-    const int q = st * 16 + l16;
-    const bool rin = q < M;
-    F xv[KSP];
-#pragma unroll
-    for (int u = 0; u < KSP; ++u) xv[u] = xn[u];
-    const double swq = swn;
-    if (st + stride < nst) load(st + stride);
-    Acc acc[NCB];
-    zero_prod<P>(acc, NCB);
-    prod_acc<P, NCB, KSP>(acc, Bf, xv);
-#pragma unroll
-    for (int cb = 0; cb < NCB; ++cb) {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int j = out_col<P>(cb, v, kq);
-        const S val = (rin && j < r) ? (S)(swq * ((double)acc[cb][v] + cr[j])) : (S)0;
-        if (rin && j < r) ALs[(int64_t)j * M + q] = val;
-        Ys[l16 * LD + j] = (double)val;
+      for (int u = 0; u < KSR; ++u) {
+        const int kc = sub_col<P>(u, kq);
+        const bool in = q_ < M && kc < r;
+        const double v = Vs[(int64_t)(in ? kc : 0) * M + qc];
+        xn[u] = in ? (F)v : (F)0;
       }
+      const double w_ = d.sw[qc];
+      swn = q_ < M ? w_ : 0.0;
+    };
+    int st = blockIdx.x * NW + wave;
+    if (st < nst) load(st);
+    for (; st < nst; st += stride) {
+      const int q = st * 16 + l16;
+      const bool rin = q < M;
+      F xv[KSR];
+#pragma unroll
+      for (int u = 0; u < KSR; ++u) xv[u] = xn[u];
+      const double swq = swn;
+      if (st + stride < nst) load(st + stride);
+      Acc acc[NC];
+      zero_prod<P>(acc, NC);
+      prod_acc<P, NC, KSR, NCB>(acc, Bf, xv);
+#pragma unroll
+      for (int cb = 0; cb < NC; ++cb) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int j = out_col<P>(cb, v, kq);
+          const S val = (rin && j < r) ? (S)(swq * ((double)acc[cb][v] + cr[j])) : (S)0;
+          if (rin && j < r) ALs[(int64_t)j * M + q] = val;
+          Ys[l16 * LD + j] = (double)val;
+        }
+      }
+      wave_sync();
+      strip_gram<NC, LD>(g, Ys);
+      wave_sync();
     }
-    wave_sync();
-    strip_gram<NCB, LD>(g, Ys);
-    wave_sync();
-  }
-  wg_reduce_acc<NB>(g, Ysh);
-  if (wave == 0) store_gram<NCB>(g, gpart_of(d, s) + (int64_t)blockIdx.x * d.gpTile, r, 1.0);
+    wg_reduce_acc<NBR>(g, Ysh);
+    if (wave == 0) store_gram<NC>(g, gpart_of(d, s) + (int64_t)blockIdx.x * d.gpTile, r, 1.0);
+  };
+  constexpr int KS1 = P == 2 ? 8 : 4;  // one instruction's sub-steps
+  if (NCB > 1 && KSP > KS1 && live_sub<P>(r) <= KS1 && r <= 16)
+    run(std::integral_constant<int, 1>{}, std::integral_constant<int, (KSP > KS1 ? KS1 : KSP)>{});
+  else
+    run(std::integral_constant<int, NCB>{}, std::integral_constant<int, KSP>{});
 }
 
 // ----------------------------------------------------------------------------
